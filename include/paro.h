@@ -1,0 +1,267 @@
+/*
+ * paro.h -- C ABI of libparo, the MI355X (gfx950) hot path of the parallel
+ * orbital-updating (ParO) plane-wave eigensolver.
+ *
+ * Paper: Y. Pan, X. Dai, S. de Gironcoli, X.-G. Gong, G.-M. Rignanese,
+ * A. Zhou, "A parallel orbital-updating based plane-wave basis method for
+ * electronic structure calculations", arXiv 1702.04045.
+ *
+ * The library solves the fixed-potential, Gamma-point, norm-conserving
+ * (S = I) discrete eigenproblem H Psi = eps Psi of Section 2.3, eq. (e5),
+ * with H = kinetic (1/2)|G|^2 + local potential + Kleinman-Bylander (KB)
+ * nonlocal part, on the plane-wave basis of eq. (e2) cut off by eq. (e3).
+ * The solver is Algorithm 1 of Section 3 (and Algorithm 2 of Section 4)
+ * with the cutoff held fixed, as in all runs of Section 5.
+ *
+ * Conventions (all entry points)
+ *  - Every function returns int32_t: PARO_OK (0) or a negative PARO_E* code.
+ *    No exception crosses the ABI.  paro_last_error() returns a message for
+ *    the last failure on the calling thread.
+ *  - Complex numbers are interleaved (re, im) IEEE doubles, the layout of
+ *    C99 double complex and of torch.complex128.
+ *  - Orbital blocks are band-major: coefficient g of band b is element
+ *    [b * ld + g], ld >= n_g.  The G order is the plan's Miller list order.
+ *  - Small dense matrices are column-major.
+ *  - "dev" pointers are device memory (hipMalloc'd, e.g. owned by torch);
+ *    "host" pointers are host memory.  The library allocates no device
+ *    memory: the caller passes the plan buffer and a workspace whose sizes
+ *    it queries first, and owns them.  The library keeps no caller pointer
+ *    beyond a call except the plan buffer, which must live until
+ *    paro_plan_destroy.
+ *  - All device work is enqueued on the plan's stream and is asynchronous
+ *    to the host, except where stated.  A plan is not thread-safe.
+ *  - Numerical failures inside enqueued work cannot be returned
+ *    synchronously; they set sticky bits in the plan's device status word,
+ *    read with paro_get_status().
+ */
+#ifndef PARO_H
+#define PARO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PARO_ABI_VERSION 1
+
+/* return codes */
+#define PARO_OK 0
+#define PARO_EINVAL (-1)   /* bad argument: NULL, size <= 0, ld < n_g, non-finite input,
+                              Miller list not the cutoff sphere in canonical order */
+#define PARO_EALIAS (-2)   /* FFT grid smaller than 4 * n_max + 1 along some axis */
+#define PARO_ESIZE (-3)    /* plan buffer or workspace smaller than queried */
+#define PARO_EHIP (-4)     /* HIP runtime error (text in paro_last_error) */
+#define PARO_EUNSUP (-5)   /* valid input outside what this build supports
+                              (FFT length not in the supported set) */
+
+/* sticky device status bits (paro_get_status) */
+#define PARO_F_NEGCURV 1   /* PCG met p^H (H - sigma) p <= 0: sigma not below the spectrum */
+#define PARO_F_CHOL 2      /* Rayleigh-Ritz overlap matrix not positive definite */
+#define PARO_F_NAN 4       /* a NaN reached a PCG scalar */
+
+/* shift modes of paro_iterate */
+#define PARO_SHIFT_FIXED 0     /* sigma = sigma_lb every outer iteration */
+#define PARO_SHIFT_ADAPTIVE 1  /* sigma = max(sigma_lb, eps_1 - 0.05 - |r_1|) once |r_1| < 0.1 */
+
+/* solver variants of paro_iterate */
+#define PARO_VARIANT_PARO 0    /* Algorithm 1: Rayleigh-Ritz on span{u_i} (m = nb) */
+#define PARO_VARIANT_MPARO1 1  /* Algorithm 2: Rayleigh-Ritz on span{psi_i, e_i} (m = 2 nb) */
+
+typedef void *paro_stream_t; /* a hipStream_t; NULL is the default stream */
+typedef struct paro_plan_s *paro_plan;
+
+/* One Kleinman-Bylander projector beta_p (nonlocal part of the
+ * pseudopotential, Section 2.2).  Gaussian form in the plane-wave basis:
+ *   s   (l = 0):          beta(G) = c exp(-w^2 |G|^2 / 2) exp(-i G.R)
+ *   p_a (l = 1, m = a):   beta(G) = c (-i w G_a) exp(-w^2 |G|^2 / 2) exp(-i G.R)
+ * a = 0, 1, 2 for x, y, z; c normalises sum_G |beta(G)|^2 = 1 over the
+ * sphere.  The nonlocal operator is sum_p d_p beta_p beta_p^H. */
+typedef struct {
+    double center[3]; /* R, Cartesian bohr */
+    int32_t l, m;
+    double width;     /* w, bohr, > 0 */
+    double d;         /* KB energy d_p, Ha */
+} paro_projector;
+
+/* The problem statement (all host memory; copied by paro_plan_create). */
+typedef struct {
+    double cell[9];          /* lattice vectors a1, a2, a3 as rows, bohr */
+    double ecut;             /* plane-wave cutoff, Ha: (1/2)|G|^2 <= ecut, eq. (e3) */
+    int32_t grid[3];         /* FFT grid N1, N2, N3 of vloc */
+    int64_t n_g;             /* size of the G-sphere */
+    const int32_t *miller;   /* host, n_g x 3 Miller indices (n1, n2, n3), G = sum n_d b_d;
+                                must be the cutoff sphere in canonical (lexicographic) order,
+                                as produced by paro_sphere_enumerate */
+    const double *vloc;      /* host, N1*N2*N3 local potential values (Ha), C order
+                                [i1][i2][i3], at r = sum_d (i_d / N_d) a_d */
+    int32_t n_proj;          /* number of KB projectors, >= 0 */
+    const paro_projector *proj; /* host, n_proj entries (may be NULL when n_proj = 0) */
+} paro_problem;
+
+typedef struct {
+    int64_t n_g;
+    int32_t nmax[3];         /* max |n_d| over the sphere */
+    int32_t grid[3];
+    int32_t n_sticks;        /* (n1, n2) columns holding sphere points */
+    int32_t n_proj;
+    double omega;            /* cell volume, bohr^3 */
+} paro_plan_info;
+
+/* Options of paro_iterate. */
+typedef struct {
+    int32_t n_outer;         /* outer iterations (Algorithm 1 steps 3-5) to run */
+    int32_t n_cg;            /* PCG steps per source problem */
+    int32_t n_conv;          /* lowest bands whose convergence counts (<= nb) */
+    int32_t shift_mode;      /* PARO_SHIFT_* */
+    int32_t variant;         /* PARO_VARIANT_* */
+    int32_t initial_rr;      /* 1: first run Rayleigh-Ritz on the trial block (Algorithm 1 step 1) */
+    double sigma_lb;         /* lower bound of the spectrum (paro_shift_lower_bound) */
+    double tol_res;          /* stop once max_{b < n_conv} |H psi_b - eps_b psi_b| <= tol_res
+                                (checked on the device after each outer iteration; 0 = never) */
+} paro_iter_opts;
+
+/* ---------------------------------------------------------------- ABI */
+
+int32_t paro_abi_version(void);
+const char *paro_last_error(void);
+
+/* ---------------------------------------------------------------- setup (host) */
+
+/* The cutoff sphere of eq. (e3) at k = 0, in canonical order: lexicographic
+ * in (n1, n2, n3).  A point is included iff (1/2)|G|^2 <= ecut (1 + 1e-12).
+ * cell: host double[9]; miller: host int32[capacity * 3] or NULL (count
+ * only); n_g_out: number of points; nmax_out: host int32[3] or NULL.
+ * Returns PARO_ESIZE if capacity < n_g (n_g_out still set). */
+int32_t paro_sphere_enumerate(const double *cell, double ecut, int64_t capacity,
+                              int32_t *miller, int64_t *n_g_out, int32_t *nmax_out);
+
+/* Smallest FFT grid 2^a * {1, 3, 5} >= 4 nmax_d + 1 along each axis, the
+ * size at which the FFT apply of the local potential has no alias on the
+ * sphere.  nmax, grid_out: host int32[3]. */
+int32_t paro_grid_size(const int32_t *nmax, int32_t *grid_out);
+
+/* Device bytes the plan needs for this problem. */
+int32_t paro_plan_bytes(const paro_problem *prob, size_t *bytes);
+
+/* Validate the problem and build the plan in dev_buf (device, >= plan
+ * bytes, 256-byte aligned): stick maps, kinetic table, plane-major V,
+ * FFT twiddles and the KB projector matrix B (n_g x n_proj), computed by
+ * a device kernel.  Synchronises the stream before returning.
+ * Errors: PARO_EINVAL, PARO_EALIAS, PARO_ESIZE, PARO_EUNSUP, PARO_EHIP. */
+int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes,
+                         paro_stream_t stream, paro_plan *plan_out);
+int32_t paro_plan_destroy(paro_plan plan);
+int32_t paro_plan_set_stream(paro_plan plan, paro_stream_t stream);
+int32_t paro_plan_get_info(paro_plan plan, paro_plan_info *info);
+
+/* Device bytes of the workspace for calls on up to nb bands.
+ * Valid for paro_apply_h, paro_source_solve, paro_rayleigh_ritz (m <= 2 nb)
+ * and paro_iterate with either variant. */
+int32_t paro_workspace_bytes(paro_plan plan, int32_t nb, size_t *bytes);
+
+/* Copy the plan's kinetic table (1/2)|G|^2 (dev double[n_g]) or projector
+ * matrix B (dev complex[n_proj][n_g], projector-major) to dev memory;
+ * for tests. */
+int32_t paro_get_kinetic(paro_plan plan, double *kin_dev);
+int32_t paro_get_projectors(paro_plan plan, double *beta_dev);
+
+/* ---------------------------------------------------------------- hot path */
+
+/* hpsi_b = (H - shift_b) psi_b for b < nb.  The matrix elements are
+ * h_mn = (1/2)|G_m|^2 delta_mn + Vt(n_m - n_n) + sum_p d_p beta_p(G_m)
+ * conj(beta_p(G_n)) with Vt the grid DFT of vloc (eq. (e5), read with
+ * G_m - G_n), applied through sphere -> stick -> plane FFTs.
+ * psi, hpsi: dev complex, band-major, leading dimension ld; may not alias.
+ * shift: dev double[nb] or NULL (zero).  ws: dev workspace of at least
+ * paro_workspace_bytes(nb) bytes. */
+int32_t paro_apply_h(paro_plan plan, int32_t nb, const double *psi, int64_t ld,
+                     const double *shift, double *hpsi, void *ws, size_t ws_bytes);
+
+/* The N independent source problems of Algorithm 1, step 3, read with a
+ * shift sigma_b below the spectrum:
+ *   (H - sigma_b) u_b = (eps_b - sigma_b) psi_b,
+ * each by n_cg steps of Teter-preconditioned CG from u_b = psi_b, with the
+ * recurrence residual (r_0 = eps_b psi_b - hpsi_b from the carried H psi).
+ * Teter preconditioner K(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4),
+ * x = (1/2)|G|^2 / tau_b, tau_b = <psi_b|T|psi_b>/<psi_b|psi_b>.
+ * A band stops early when p^H (H - sigma) p <= 0 (sets PARO_F_NEGCURV) or
+ * when r^H z <= 1e-26 r_0^H z_0.
+ * psi, hpsi, u: dev complex band-major (ld); eps, shift: dev double[nb];
+ * band_flags: dev int32[nb] or NULL, receives the per-band status bits. */
+int32_t paro_source_solve(paro_plan plan, int32_t nb, const double *psi, const double *hpsi,
+                          int64_t ld, const double *eps, const double *shift, int32_t n_cg,
+                          double *u, int32_t *band_flags, void *ws, size_t ws_bytes);
+
+/* Rayleigh-Ritz on span{U} (Algorithm 1, step 4): with W = H U given,
+ * S = U^H U, Hs = U^H W, S = L L^H, Hhat = L^-1 Hs L^-H = Y diag(eps) Y^H
+ * (ascending), C = L^-H Y; writes the lowest n_keep pairs:
+ * eps (dev double[n_keep]), psi = U C, hpsi = W C (dev complex band-major,
+ * leading dimension ld, n_keep bands).  U and W: m bands each, ld.
+ * Sets PARO_F_CHOL if S is not positive definite (outputs then undefined).
+ * m <= 2 * (the nb the workspace was sized for), n_keep <= m. */
+int32_t paro_rayleigh_ritz(paro_plan plan, int32_t m, int32_t n_keep, const double *U,
+                           const double *W, int64_t ld, double *eps, double *psi, double *hpsi,
+                           void *ws, size_t ws_bytes);
+
+/* |hpsi_b - eps_b psi_b| for b < nb into res (dev double[nb]). */
+int32_t paro_residual_norms(paro_plan plan, int32_t nb, const double *psi, const double *hpsi,
+                            int64_t ld, const double *eps, double *res, void *ws, size_t ws_bytes);
+
+/* Lower bound of the spectrum, written to sigma_dev (dev double[1]):
+ * sigma_lb = min_j vloc_j + min(0, lambda_min(V_NL)) - 0.1 (Weyl: kinetic
+ * >= 0, the local part is a compression of multiplication by V, and
+ * V_NL = B D B^H has the nonzero eigenvalues of L^H D L, B^H B = L L^H).
+ * ws sized for at least max(1, ceil(n_proj / 2)) bands. */
+int32_t paro_shift_lower_bound(paro_plan plan, double *sigma_dev, void *ws, size_t ws_bytes);
+
+/* ParO at fixed cutoff (Algorithm 1 steps 1, 3, 4, 5; Algorithm 2 for
+ * variant MPARO1): up to opts->n_outer outer iterations of nb source
+ * problems followed by Rayleigh-Ritz (m = nb, or 2 nb for MPARO1).
+ * psi: in the trial block (initial_rr = 1) or orthonormal Ritz vectors with
+ * hpsi = H psi and eps (initial_rr = 0); out the Ritz vectors.  hpsi, eps:
+ * out (in when initial_rr = 0).  sigma: dev double[1], out: the shift the
+ * next outer iteration would use.  stats: dev double[(n_outer + 1) *
+ * (2 nb + 2)] or NULL; row i (row 0: before the first outer iteration)
+ * holds eps (nb), residual norms |H psi_b - eps_b psi_b| (nb), the next
+ * shift, and 1.0 when max_{b < n_conv} residual <= tol_res.  When tol_res >
+ * 0 the loop stops before an outer iteration once that test passed (one
+ * host synchronisation per outer iteration).  In adaptive shift mode a
+ * source solve that meets negative curvature is redone with sigma_lb (one
+ * host synchronisation per outer iteration).  n_done: host int32 or NULL,
+ * the outer iterations run.  ws: paro_workspace_bytes(nb).  nb <= 512. */
+int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi, double *hpsi, int64_t ld,
+                     double *eps, double *sigma, const paro_iter_opts *opts, double *stats,
+                     void *ws, size_t ws_bytes, int32_t *n_done);
+
+/* Read and clear the sticky status bits (synchronises the plan's stream). */
+int32_t paro_get_status(paro_plan plan, int32_t *flags);
+
+/* ---------------------------------------------------------------- building blocks */
+
+/* Complex double GEMMs on the FP64 matrix cores, the products the hot
+ * path is made of (all matrices column-major, dev memory, on stream s).
+ * paro_zgemm_hn: C (M x N, ldc) = A^H B, A: K x M (lda), B: K x N (ldb);
+ *   the K sum is split over work-groups into partial tiles held in ws
+ *   (at least M * N * 16 bytes; more allows more splits) and reduced in a
+ *   fixed order.
+ * paro_zgemm_nn: C (M x N, ldc) = A B (+ C when accumulate), A: M x K,
+ *   B: K x N. */
+int32_t paro_zgemm_hn(paro_stream_t s, int32_t M, int32_t N, int64_t K, const double *A, int64_t lda,
+                      const double *B, int64_t ldb, double *C, int64_t ldc, void *ws, size_t ws_bytes);
+int32_t paro_zgemm_nn(paro_stream_t s, int64_t M, int32_t N, int32_t K, const double *A, int64_t lda,
+                      const double *B, int64_t ldb, double *C, int64_t ldc, int32_t accumulate);
+
+/* The device Hermitian eigensolver of the Rayleigh-Ritz step: A (m x m,
+ * column-major, dev, read only) = V diag(w) V^H, w ascending (dev
+ * double[m]), V (dev complex m x m).  Householder tridiagonalisation,
+ * bisection, inverse iteration, back-transformation.  m <= 1024.
+ * ws: paro_heev_workspace_bytes(m). */
+int32_t paro_heev_workspace_bytes(int32_t m, size_t *bytes);
+int32_t paro_heev(paro_stream_t s, int32_t m, const double *A, double *w, double *V, void *ws, size_t ws_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PARO_H */

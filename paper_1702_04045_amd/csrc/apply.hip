@@ -1,0 +1,248 @@
+// Local part of H psi through sphere -> stick -> plane FFTs (gfx950).
+//
+// The orbital psi(r) = sum_G c_G exp(iG.r) of eq. (e2) lives on the sphere
+// of eq. (e3).  Its coefficients are scattered into sticks (the (n1, n2)
+// columns holding sphere points) and transformed along n3; each z-plane is
+// transformed along n2 for the populated n1 columns only and along n1 for
+// every row; the row is multiplied by the local potential and sent back the
+// same way; the forward stick transform gathers the sphere, scales by
+// 1/(N1 N2 N3) and adds the kinetic diagonal.  This is the stiffness matrix
+// element of eq. (e5), h_mn = (1/2)|G_m|^2 delta_mn + Vt(n_m - n_n), read
+// with the difference G_m - G_n and the grid quadrature of the integral.
+//
+// Stick buffer layout: [band][n3 mod N3][stick], so a z-plane of one band
+// is contiguous for the plane kernel and the stick kernels write rows of
+// consecutive sticks.
+#include "fft_device.h"
+#include "paro_internal.h"
+#include "reduce_device.h"
+
+namespace paro {
+
+namespace {
+
+template <int N> constexpr bool cfg_ok()
+{
+    using C = FftCfg<N>;
+    return C::T * C::E == N && ListInfo<typename C::Inv>::last == ListInfo<typename C::Fwd>::first;
+}
+
+constexpr int kStickThreads = 256;
+
+// Sphere -> sticks, inverse transform along n3.
+// pbuf != null: PCG prologue, p <- z + beta p (first step: p <- z), the new p
+// is written back and transformed.  Otherwise src is transformed as is.
+template <int N3>
+__global__ void __launch_bounds__(kStickThreads)
+k_stick_inv(const double2 *__restrict__ src, int64_t ld, double2 *__restrict__ pbuf,
+            const double *__restrict__ beta, int first, double2 *__restrict__ sticks, int nst,
+            const int32_t *__restrict__ st_start, const int32_t *__restrict__ pt_sz,
+            const double2 *__restrict__ tw)
+{
+    using C = FftCfg<N3>;
+    static_assert(cfg_ok<N3>(), "bad FFT config");
+    constexpr int T = C::T, E = C::E, S = kStickThreads / T, LD = N3 + 1;
+    __shared__ double2 tile[S * LD];
+    const int tid = threadIdx.x, sl = tid % S, t = tid / S;
+    const int s0 = blockIdx.x * S, band = blockIdx.y;
+    const int s = s0 + sl;
+    const bool act = s < nst;
+    for (int i = tid; i < S * LD; i += kStickThreads) tile[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const int p0 = st_start[s0], p1 = st_start[min(s0 + S, nst)];
+    const double2 *x = src + band * ld;
+    double2 *pb = pbuf ? pbuf + band * ld : nullptr;
+    const double bt = (pbuf && !first) ? beta[band] : 0.0;
+    for (int idx = p0 + tid; idx < p1; idx += kStickThreads) {
+        double2 val = x[idx];
+        if (pb) {
+            if (!first) {
+                const double2 po = pb[idx];
+                val = make_double2(val.x + bt * po.x, val.y + bt * po.y);
+            }
+            pb[idx] = val;
+        }
+        const int sz = pt_sz[idx];
+        tile[((sz >> 8) - s0) * LD + (sz & 255)] = val;
+    }
+    __syncthreads();
+    double2 v[E];
+    double2 *line = tile + sl * LD;
+    if (act) pass_load<N3, T, E, ListInfo<typename C::Inv>::first>(v, t, [&](int i) { return line[i]; });
+    stockham<N3, +1>(typename C::Inv{}, v, t, act, line, 1, tw);
+    double2 *out = sticks + (size_t)band * N3 * nst;
+    if (act)
+        final_foreach<N3, T, E, ListInfo<typename C::Inv>::last>(
+            v, t, [&](int i, int e) { out[(size_t)i * nst + s] = v[e]; });
+}
+
+// One z-plane of one band: inverse along n2 (populated n1 columns), along n1
+// (all rows), times V, forward along n1, forward along n2; in place in the
+// stick buffer.
+template <int N>
+__global__ void __launch_bounds__(N * FftCfg<N>::T)
+k_plane(double2 *__restrict__ sticks, int nst, int N3, const int32_t *__restrict__ st_xy,
+        const double *__restrict__ vplane, int nmax1, const double2 *__restrict__ tw)
+{
+    using C = FftCfg<N>;
+    static_assert(cfg_ok<N>(), "bad FFT config");
+    using Inv = typename C::Inv;
+    using Fwd = typename C::Fwd;
+    constexpr int T = C::T, E = C::E, LDX = N + 1, NT = N * T;
+    __shared__ double2 plane[N * LDX];
+    const int tid = threadIdx.x;
+    const int z = blockIdx.x, band = blockIdx.y;
+    double2 *tz = sticks + ((size_t)band * N3 + z) * nst;
+    const int ncol = 2 * nmax1 + 1;
+    for (int e = tid; e < ncol * N; e += NT) {
+        const int c = e / N, y = e - c * N;
+        int x = c - nmax1;
+        x += x < 0 ? N : 0;
+        plane[y * LDX + x] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int s = tid; s < nst; s += NT) {
+        const int xy = st_xy[s];
+        plane[(xy >> 16) * LDX + (xy & 0xffff)] = tz[s];
+    }
+    __syncthreads();
+    const int slot = tid / T, t = tid % T;
+    int xcol = slot - nmax1;
+    xcol += xcol < 0 ? N : 0;
+    const bool colact = slot < ncol;
+    double2 *col = plane + (colact ? xcol : 0);
+    double2 v[E];
+    // n2, inverse
+    if (colact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) { return col[i * LDX]; });
+    stockham<N, +1>(Inv{}, v, t, colact, col, LDX, tw);
+    __syncthreads();
+    if (colact) final_foreach<N, T, E, ListInfo<Inv>::last>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
+    __syncthreads();
+    // n1 rows: inverse, multiply by V, forward
+    {
+        const int y = slot;
+        double2 *row = plane + y * LDX;
+        pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
+            return (i <= nmax1 || i >= N - nmax1) ? row[i] : make_double2(0.0, 0.0);
+        });
+        stockham<N, +1>(Inv{}, v, t, true, row, 1, tw);
+        const double *vrow = vplane + ((size_t)z * N + y) * N;
+        final_foreach<N, T, E, ListInfo<Inv>::last>(v, t, [&](int i, int e) { v[e] = cscale(v[e], vrow[i]); });
+        stockham<N, -1>(Fwd{}, v, t, true, row, 1, tw);
+        __syncthreads();
+        final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
+            if (i <= nmax1 || i >= N - nmax1) row[i] = v[e];
+        });
+        __syncthreads();
+    }
+    // n2, forward
+    if (colact) pass_load<N, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return col[i * LDX]; });
+    stockham<N, -1>(Fwd{}, v, t, colact, col, LDX, tw);
+    __syncthreads();
+    if (colact) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
+    __syncthreads();
+    for (int s = tid; s < nst; s += NT) {
+        const int xy = st_xy[s];
+        tz[s] = plane[(xy >> 16) * LDX + (xy & 0xffff)];
+    }
+}
+
+// Sticks -> sphere, forward transform along n3, then
+// out = scale * local + (kin - shift_b) x; dot_part gets sum Re(conj(x) out).
+template <int N3>
+__global__ void __launch_bounds__(kStickThreads)
+k_stick_fwd(const double2 *__restrict__ sticks, int nst, const int32_t *__restrict__ st_start,
+            const int32_t *__restrict__ pt_sz, const double2 *__restrict__ tw,
+            const double2 *__restrict__ xin, int64_t ld, double2 *__restrict__ out,
+            const double *__restrict__ kin, const double *__restrict__ shift, double scale,
+            double *__restrict__ dot_part, int part_stride)
+{
+    using C = FftCfg<N3>;
+    using Fwd = typename C::Fwd;
+    constexpr int T = C::T, E = C::E, S = kStickThreads / T, LD = N3 + 1;
+    __shared__ double2 tile[S * LD];
+    __shared__ double red[kStickThreads / 64];
+    const int tid = threadIdx.x, sl = tid % S, t = tid / S;
+    const int s0 = blockIdx.x * S, band = blockIdx.y;
+    const int s = s0 + sl;
+    const bool act = s < nst;
+    const double2 *in = sticks + (size_t)band * N3 * nst;
+    double2 v[E];
+    double2 *line = tile + sl * LD;
+    if (act) pass_load<N3, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return in[(size_t)i * nst + s]; });
+    stockham<N3, -1>(Fwd{}, v, t, act, line, 1, tw);
+    __syncthreads();
+    if (act) final_foreach<N3, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) { line[i] = v[e]; });
+    __syncthreads();
+    const int p0 = st_start[s0], p1 = st_start[min(s0 + S, nst)];
+    const double sig = shift ? shift[band] : 0.0;
+    const double2 *x = xin + band * ld;
+    double2 *o = out + band * ld;
+    double dot = 0.0;
+    for (int idx = p0 + tid; idx < p1; idx += kStickThreads) {
+        const int sz = pt_sz[idx];
+        const double2 loc = tile[((sz >> 8) - s0) * LD + (sz & 255)];
+        const double2 xv = x[idx];
+        const double k = kin[idx] - sig;
+        const double2 r = make_double2(loc.x * scale + k * xv.x, loc.y * scale + k * xv.y);
+        o[idx] = r;
+        dot += xv.x * r.x + xv.y * r.y;
+    }
+    if (dot_part) {
+        dot = block_sum<kStickThreads>(dot, red);
+        if (tid == 0) dot_part[(size_t)band * part_stride + blockIdx.x] = dot;
+    }
+}
+
+template <int N>
+hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const double2 *src, int64_t ld, double2 *out,
+                     const double *shift, double2 *pbuf, const double *beta, bool first, double *dot_part,
+                     int *nparts_out)
+{
+    constexpr int S = kStickThreads / FftCfg<N>::T;
+    const int N3 = pl.grid[2];
+    const int ntiles = (pl.nst + S - 1) / S;
+    if (nparts_out) *nparts_out = ntiles;
+    const double scale = 1.0 / ((double)pl.grid[0] * pl.grid[1] * pl.grid[2]);
+    for (int c0 = 0; c0 < nb; c0 += kMaxBandsPerChunk) {
+        const int cb = min(kMaxBandsPerChunk, nb - c0);
+        hipLaunchKernelGGL(k_stick_inv<N>, dim3(ntiles, cb), dim3(kStickThreads), 0, pl.stream,
+                           src + c0 * ld, ld, pbuf ? pbuf + c0 * ld : nullptr, beta ? beta + c0 : nullptr,
+                           first ? 1 : 0, w.sticks, pl.nst, pl.st_start, pl.pt_sz, pl.tw[2]);
+        hipLaunchKernelGGL(k_plane<N>, dim3(N3, cb), dim3(N * FftCfg<N>::T), 0, pl.stream, w.sticks, pl.nst, N3,
+                           pl.st_xy, pl.vplane, pl.nmax[0], pl.tw[0]);
+        const double2 *x = pbuf ? pbuf : src;
+        hipLaunchKernelGGL(k_stick_fwd<N>, dim3(ntiles, cb), dim3(kStickThreads), 0, pl.stream, w.sticks, pl.nst,
+                           pl.st_start, pl.pt_sz, pl.tw[2], x + c0 * ld, ld, out + c0 * ld, pl.kin,
+                           shift ? shift + c0 : nullptr, scale, dot_part ? dot_part + (size_t)c0 * kMaxParts : nullptr,
+                           kMaxParts);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool fft_supported(int n)
+{
+    switch (n) {
+    case 8: case 16: case 24: case 32: case 40: case 48: case 64: case 80: case 96: return true;
+    default: return false;
+    }
+}
+
+hipError_t launch_local_apply(const Plan &pl, const Workspace &w, int nb, const double2 *src, int64_t ld,
+                              double2 *out, const double *shift, double2 *pbuf, const double *beta, bool first,
+                              double *dot_part, int *nparts_out)
+{
+    // the kernels are instantiated for cubic grids N1 = N2 = N3
+    switch (pl.grid[0]) {
+#define PARO_CASE(n) \
+    case n: return run_local<n>(pl, w, nb, src, ld, out, shift, pbuf, beta, first, dot_part, nparts_out);
+    PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
+    PARO_CASE(80) PARO_CASE(96)
+#undef PARO_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace paro

@@ -1,0 +1,603 @@
+// Small dense FP64 linear algebra of the Rayleigh-Ritz step (Algorithm 1,
+// step 4) on the GPU:  S = L L^H,  Hhat = L^-1 Hs L^-H,  Hhat = Q T Q^H
+// (Householder, T real tridiagonal),  T = Z diag(lambda) Z^T (bisection on
+// Sturm counts, then inverse iteration with Gram-Schmidt inside clusters),
+// Y = Q Z,  C = L^-H Y.  Matrices are m x m column-major with ld = m.
+// Everything runs in a few launches: one work-group for the factorisations
+// that need the whole matrix, one wave per column for the triangular
+// solves and the back-transformation.
+#include <cfloat>
+#include <cmath>
+
+#include "paro_internal.h"
+#include "reduce_device.h"
+
+namespace paro {
+
+namespace {
+
+constexpr int kBig = 1024;
+
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cmul_(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ double2 cjmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// Hermitise S (first m columns of gram) into L and, when hs, Hs (next m
+// columns) into X; then Cholesky of L in place (lower; upper zeroed).
+// A pivot <= 1e-14 max_i S_ii sets fail[0] = 1 and the CHOL status bit.
+__global__ void __launch_bounds__(kBig)
+k_rr_chol(int m, const double2 *__restrict__ gram, int hs, double2 *__restrict__ L, double2 *__restrict__ X,
+          int32_t *__restrict__ fail, int32_t *__restrict__ status)
+{
+    __shared__ double red[kBig / 64];
+    __shared__ double s_ljj;
+    __shared__ int s_fail;
+    const int tid = threadIdx.x;
+    const int64_t mm = (int64_t)m * m;
+    double dmax = 0.0;
+    for (int64_t e = tid; e < mm; e += kBig) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        const double2 a = gram[e], b = gram[(int64_t)i * m + j];
+        L[e] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+        if (i == j) dmax = fmax(dmax, a.x);
+        if (hs) {
+            const double2 c = gram[mm + e], d = gram[mm + (int64_t)i * m + j];
+            X[e] = make_double2(0.5 * (c.x + d.x), 0.5 * (c.y - d.y));
+        }
+    }
+    dmax = block_max<kBig>(dmax, red);
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
+    for (int j = 0; j < m; ++j) {
+        if (tid == 0) {
+            const double d = L[(int64_t)j * m + j].x;
+            if (!(d > 1e-14 * dmax)) {
+                s_fail = 1;
+                s_ljj = 1.0;
+            } else {
+                s_ljj = sqrt(d);
+            }
+        }
+        __syncthreads();
+        if (s_fail) break;
+        const double ljj = s_ljj, inv = 1.0 / ljj;
+        for (int i = j + 1 + tid; i < m; i += kBig) {
+            double2 v = L[(int64_t)j * m + i];
+            L[(int64_t)j * m + i] = make_double2(v.x * inv, v.y * inv);
+        }
+        if (tid == 0) L[(int64_t)j * m + j] = make_double2(ljj, 0.0);
+        __syncthreads();
+        const int n = m - j - 1;
+        for (int64_t e = tid; e < (int64_t)n * n; e += kBig) {
+            const int il = (int)(e % n), ll = (int)(e / n);
+            if (il < ll) continue;
+            const int i = j + 1 + il, l = j + 1 + ll;
+            const double2 a = L[(int64_t)j * m + i], b = L[(int64_t)j * m + l];
+            double2 c = L[(int64_t)l * m + i];
+            // c -= a conj(b)
+            c.x -= a.x * b.x + a.y * b.y;
+            c.y -= a.y * b.x - a.x * b.y;
+            L[(int64_t)l * m + i] = c;
+        }
+        __syncthreads();
+    }
+    for (int64_t e = tid; e < mm; e += kBig) {
+        const int i = (int)(e % m), j = (int)(e / m);
+        if (i < j) L[e] = make_double2(0.0, 0.0);
+    }
+    if (tid == 0) {
+        fail[0] = s_fail;
+        if (s_fail) atomicOr(status, PARO_F_CHOL);
+    }
+}
+
+// One column per single-wave work-group.
+// mode 0: out = L^-1 b;  mode 1: out = L^-H b.
+// b = column j of src, or (transb) the conjugate of row j of src.
+__global__ void __launch_bounds__(64)
+k_trsm_col(int m, const double2 *__restrict__ L, const double2 *__restrict__ src, int transb, int mode,
+           double2 *__restrict__ out)
+{
+    extern __shared__ double2 x[];
+    const int j = blockIdx.x, lane = threadIdx.x;
+    for (int i = lane; i < m; i += 64)
+        x[i] = transb ? cconj(src[(int64_t)i * m + j]) : src[(int64_t)j * m + i];
+    __syncthreads();
+    if (mode == 0) {
+        for (int k = 0; k < m; ++k) {
+            const double lkk = L[(int64_t)k * m + k].x;
+            const double2 xk = make_double2(x[k].x / lkk, x[k].y / lkk);
+            __syncthreads();
+            if (lane == 0) x[k] = xk;
+            for (int i = k + 1 + lane; i < m; i += 64) {
+                const double2 l = L[(int64_t)k * m + i];
+                const double2 t = cmul_(l, xk);
+                x[i] = make_double2(x[i].x - t.x, x[i].y - t.y);
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int k = m - 1; k >= 0; --k) {
+            const double lkk = L[(int64_t)k * m + k].x;
+            const double2 xk = make_double2(x[k].x / lkk, x[k].y / lkk);
+            __syncthreads();
+            if (lane == 0) x[k] = xk;
+            // x_i -= conj(L_ki) x_k for i < k; L_ki is row k of L: L[i*m + k]
+            for (int i = lane; i < k; i += 64) {
+                const double2 l = L[(int64_t)i * m + k];
+                const double2 t = cjmul(l, xk);
+                x[i] = make_double2(x[i].x - t.x, x[i].y - t.y);
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = lane; i < m; i += 64) out[(int64_t)j * m + i] = x[i];
+}
+
+// Householder reduction of the Hermitian matrix A (hermitised first) to a
+// real symmetric tridiagonal T = Q^H A Q, Q = H_0 ... H_{m-2},
+// H_k = I - tau_k v_k v_k^H acting on rows k+1.., v_k[0] = 1, chosen so
+// that H_k^H maps column k below the diagonal to (beta_k, 0, ...), beta_k
+// real.  On exit: d (diagonal), e (off-diagonal, e_k = beta_k), tau, and
+// v_k stored in column k of A below the diagonal.
+__global__ void __launch_bounds__(kBig)
+k_tridiag(int m, double2 *__restrict__ A, double *__restrict__ d, double *__restrict__ e, double2 *__restrict__ tau)
+{
+    __shared__ double red[kBig / 64];
+    __shared__ double2 sv[kBig], sy[kBig], sw[kBig];
+    __shared__ double2 partial[kBig];
+    __shared__ double2 s_tau, s_scale;
+    __shared__ double s_beta;
+    const int tid = threadIdx.x;
+    const int64_t mm = (int64_t)m * m;
+    // hermitise in place (upper from lower average)
+    for (int64_t q = tid; q < mm; q += kBig) {
+        const int i = (int)(q % m), j = (int)(q / m);
+        if (i > j) {
+            const double2 a = A[q], b = A[(int64_t)i * m + j];
+            const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+            A[q] = h;
+            A[(int64_t)i * m + j] = cconj(h);
+        } else if (i == j) {
+            A[q].y = 0.0;
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k + 1 < m; ++k) {
+        const int n = m - k - 1;
+        double2 *col = A + (int64_t)k * m + k + 1;  // x = A[k+1:, k]
+        double xn = 0.0;
+        for (int i = 1 + tid; i < n; i += kBig) xn += col[i].x * col[i].x + col[i].y * col[i].y;
+        xn = block_sum<kBig>(xn, red);
+        if (tid == 0) {
+            const double2 alpha = col[0];
+            d[k] = A[(int64_t)k * m + k].x;
+            if (xn == 0.0 && alpha.y == 0.0) {
+                s_tau = make_double2(0.0, 0.0);
+                s_beta = alpha.x;
+                s_scale = make_double2(0.0, 0.0);
+            } else {
+                const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn);
+                const double beta = alpha.x >= 0.0 ? -nrm : nrm;
+                s_tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                // scale = 1 / (alpha - beta)
+                const double ar = alpha.x - beta, ai = alpha.y, den = ar * ar + ai * ai;
+                s_scale = make_double2(ar / den, -ai / den);
+                s_beta = beta;
+            }
+            e[k] = s_beta;
+            tau[k] = s_tau;
+        }
+        __syncthreads();
+        const double2 tk = s_tau, sc = s_scale;
+        for (int i = tid; i < n; i += kBig) {
+            const double2 v = i == 0 ? make_double2(1.0, 0.0) : cmul_(col[i], sc);
+            sv[i] = v;
+            col[i] = v;
+        }
+        __syncthreads();
+        if (tk.x == 0.0 && tk.y == 0.0) continue;
+        // y = A_trail v, A_trail = A[k+1:, k+1:]
+        double2 *At = A + (int64_t)(k + 1) * m + k + 1;
+        const int parts = kBig / n;
+        const int i = tid % n, part = tid / n;
+        if (part < parts) {
+            const int jb = (int)((int64_t)n * part / parts), je = (int)((int64_t)n * (part + 1) / parts);
+            double2 acc = make_double2(0.0, 0.0);
+            for (int j = jb; j < je; ++j) {
+                const double2 t = cmul_(At[(int64_t)j * m + i], sv[j]);
+                acc.x += t.x;
+                acc.y += t.y;
+            }
+            partial[part * n + i] = acc;
+        }
+        __syncthreads();
+        double cr = 0.0;
+        for (int r = tid; r < n; r += kBig) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int p = 0; p < parts; ++p) {
+                acc.x += partial[p * n + r].x;
+                acc.y += partial[p * n + r].y;
+            }
+            sy[r] = acc;
+            const double2 c = cjmul(sv[r], acc);
+            cr += c.x;
+        }
+        cr = block_sum<kBig>(cr, red);  // c = Re(v^H y)
+        const double t2 = 0.5 * (tk.x * tk.x + tk.y * tk.y) * cr;
+        for (int r = tid; r < n; r += kBig) {
+            const double2 ty = cmul_(tk, sy[r]);
+            sw[r] = make_double2(ty.x - t2 * sv[r].x, ty.y - t2 * sv[r].y);
+        }
+        __syncthreads();
+        for (int64_t q = tid; q < (int64_t)n * n; q += kBig) {
+            const int ii = (int)(q % n), jj = (int)(q / n);
+            const double2 a = cjmul(sv[jj], sw[ii]);  // w_i conj(v_j)
+            const double2 b = cjmul(sw[jj], sv[ii]);  // v_i conj(w_j)
+            double2 c = At[(int64_t)jj * m + ii];
+            c.x -= a.x + b.x;
+            c.y -= a.y + b.y;
+            At[(int64_t)jj * m + ii] = c;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        d[m - 1] = A[(int64_t)(m - 1) * m + m - 1].x;
+        e[m - 1] = 0.0;
+        tau[m - 1] = make_double2(0.0, 0.0);
+    }
+}
+
+// number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots)
+__device__ int sturm_count(int m, const double *d, const double *e2, double x, double pivmin)
+{
+    int c = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+    for (int i = 1; i < m; ++i) {
+        q = d[i] - x - e2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        c += q < 0.0;
+    }
+    return c;
+}
+
+// Eigenvalues of the real symmetric tridiagonal T (d, e) by bisection, one
+// thread per eigenvalue (ascending).  When Z != null, eigenvectors by
+// inverse iteration: for each eigenvalue, LU with partial pivoting of
+// T - lambda I, three solves from a fixed start vector; members of a
+// cluster (gap below 1e-5 |T|) are orthogonalised against the earlier
+// members (modified Gram-Schmidt) after every solve and get shifts at
+// least 10 eps |T| apart.  scr: 4 m * m doubles of per-thread workspace.
+__global__ void __launch_bounds__(kBig)
+k_tridiag_eig(int m, const double *__restrict__ d_in, const double *__restrict__ e_in, double *__restrict__ lam,
+              double *__restrict__ lam2, int nout, double *__restrict__ Z, double *__restrict__ scr)
+{
+    __shared__ double sd[kBig], se[kBig], se2[kBig], sl[kBig];
+    __shared__ double red[kBig / 64];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < m; i += kBig) {
+        sd[i] = d_in[i];
+        se[i] = i + 1 < m ? e_in[i] : 0.0;
+        se2[i] = se[i] * se[i];
+    }
+    __syncthreads();
+    double lo = INFINITY, hi = -INFINITY, emax2 = 0.0;
+    for (int i = tid; i < m; i += kBig) {
+        const double r = fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0);
+        lo = fmin(lo, sd[i] - r);
+        hi = fmax(hi, sd[i] + r);
+        emax2 = fmax(emax2, se2[i]);
+    }
+    lo = -block_max<kBig>(-lo, red);
+    hi = block_max<kBig>(hi, red);
+    emax2 = block_max<kBig>(emax2, red);
+    const double tnorm = fmax(fabs(lo), fabs(hi));
+    const double pivmin = DBL_MIN * fmax(1.0, emax2);
+    lo -= 2.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
+    hi += 2.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
+    if (tid < m) {
+        double a = lo, b = hi;
+        for (int it = 0; it < 128; ++it) {
+            const double mid = 0.5 * (a + b);
+            if (mid <= a || mid >= b) break;
+            if (b - a <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + pivmin) break;
+            if (sturm_count(m, sd, se2, mid, pivmin) > tid) b = mid;
+            else a = mid;
+        }
+        sl[tid] = 0.5 * (a + b);
+        lam[tid] = sl[tid];
+        if (lam2 && tid < nout) lam2[tid] = sl[tid];
+    }
+    __syncthreads();
+    if (!Z) return;
+    const double ortol = 1e-5 * tnorm, pert = 10.0 * DBL_EPSILON * tnorm;
+    if (tid >= m) return;
+    if (tid > 0 && sl[tid] - sl[tid - 1] <= ortol) return;  // not a cluster start
+    int cend = tid + 1;
+    while (cend < m && sl[cend] - sl[cend - 1] <= ortol) ++cend;
+    // per-thread LU arrays, interleaved by thread: scr[(a * m + k) * m + tid]
+    auto S = [&](int a, int k) -> double & { return scr[((int64_t)a * m + k) * m + tid]; };
+    double prev_shift = 0.0;
+    for (int j = tid; j < cend; ++j) {
+        double s = sl[j];
+        if (j > tid && s - prev_shift < pert) s = prev_shift + pert;
+        prev_shift = s;
+        // LU of T - s I: 0: dl (multipliers), 1: d, 2: du, 3: du2; pivots packed in the sign of a flag array
+        for (int k = 0; k < m; ++k) {
+            S(0, k) = se[k];
+            S(1, k) = sd[k] - s;
+            S(2, k) = se[k];
+            S(3, k) = 0.0;
+        }
+        const double tiny = DBL_EPSILON * tnorm + DBL_MIN;
+        unsigned long long pivbits[16] = {0};  // m <= 1024
+        for (int k = 0; k + 1 < m; ++k) {
+            const double dk = S(1, k), lk = S(0, k);
+            if (fabs(dk) >= fabs(lk)) {
+                const double dd = dk == 0.0 ? tiny : dk;
+                S(1, k) = dd;
+                const double f = lk / dd;
+                S(0, k) = f;
+                S(1, k + 1) -= f * S(2, k);
+            } else {
+                pivbits[k >> 6] |= 1ull << (k & 63);
+                const double f = dk / lk;
+                S(1, k) = lk;
+                S(0, k) = f;
+                const double t = S(2, k);
+                S(2, k) = S(1, k + 1);
+                S(1, k + 1) = t - f * S(1, k + 1);
+                if (k + 2 < m) {
+                    S(3, k) = S(2, k + 1);
+                    S(2, k + 1) = -f * S(2, k + 1);
+                }
+            }
+        }
+        if (S(1, m - 1) == 0.0) S(1, m - 1) = tiny;
+        double *z = Z + (int64_t)j * m;
+        // start vector: fixed pseudo-random entries in [0.5, 1.5)
+        for (int k = 0; k < m; ++k) {
+            unsigned h = (unsigned)(k + 1) * 2654435761u ^ (unsigned)(j + 7) * 40503u;
+            h ^= h >> 13;
+            h *= 0x5bd1e995u;
+            h ^= h >> 15;
+            z[k] = 0.5 + (double)(h & 0xffffff) / 16777216.0;
+        }
+        for (int it = 0; it < 3; ++it) {
+            for (int k = 0; k + 1 < m; ++k) {
+                if (pivbits[k >> 6] >> (k & 63) & 1ull) {
+                    const double t = z[k];
+                    z[k] = z[k + 1];
+                    z[k + 1] = t - S(0, k) * z[k];
+                } else {
+                    z[k + 1] -= S(0, k) * z[k];
+                }
+            }
+            z[m - 1] /= S(1, m - 1);
+            if (m > 1) z[m - 2] = (z[m - 2] - S(2, m - 2) * z[m - 1]) / S(1, m - 2);
+            for (int k = m - 3; k >= 0; --k)
+                z[k] = (z[k] - S(2, k) * z[k + 1] - S(3, k) * z[k + 2]) / S(1, k);
+            double nrm = 0.0;
+            for (int k = 0; k < m; ++k) nrm = fmax(nrm, fabs(z[k]));
+            double inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
+            for (int k = 0; k < m; ++k) z[k] *= inv;
+            for (int p = tid; p < j; ++p) {
+                const double *zp = Z + (int64_t)p * m;
+                double dot = 0.0;
+                for (int k = 0; k < m; ++k) dot += zp[k] * z[k];
+                for (int k = 0; k < m; ++k) z[k] -= dot * zp[k];
+            }
+            double n2 = 0.0;
+            for (int k = 0; k < m; ++k) n2 += z[k] * z[k];
+            inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 1.0;
+            for (int k = 0; k < m; ++k) z[k] *= inv;
+        }
+    }
+}
+
+// Y = Q Z (complex m x m from real Z), one column per single-wave block:
+// y <- H_k y = y - tau_k v_k (v_k^H y), k = m-2 .. 0.
+__global__ void __launch_bounds__(64)
+k_backtransform(int m, const double2 *__restrict__ A, const double2 *__restrict__ tau, const double *__restrict__ Z,
+                double2 *__restrict__ Y)
+{
+    extern __shared__ double2 y[];
+    const int j = blockIdx.x, lane = threadIdx.x;
+    for (int i = lane; i < m; i += 64) y[i] = make_double2(Z[(int64_t)j * m + i], 0.0);
+    __syncthreads();
+    for (int k = m - 2; k >= 0; --k) {
+        const double2 tk = tau[k];
+        if (tk.x == 0.0 && tk.y == 0.0) continue;
+        const int n = m - k - 1;
+        const double2 *v = A + (int64_t)k * m + k + 1;
+        double sr = 0.0, si = 0.0;
+        for (int i = lane; i < n; i += 64) {
+            const double2 t = cjmul(v[i], y[k + 1 + i]);
+            sr += t.x;
+            si += t.y;
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        sr = __shfl(sr, 0, 64);
+        si = __shfl(si, 0, 64);
+        const double2 f = cmul_(tk, make_double2(sr, si));
+        __syncthreads();
+        for (int i = lane; i < n; i += 64) {
+            const double2 t = cmul_(v[i], f);
+            y[k + 1 + i] = make_double2(y[k + 1 + i].x - t.x, y[k + 1 + i].y - t.y);
+        }
+        __syncthreads();
+    }
+    for (int i = lane; i < m; i += 64) Y[(int64_t)j * m + i] = y[i];
+}
+
+// M = L^H diag(dk) L (projector part of the shift bound)
+__global__ void k_lhdl(int m, const double2 *__restrict__ L, const double *__restrict__ dk, double2 *__restrict__ M)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= m) return;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int k = 0; k < m; ++k) {
+        const double2 t = cjmul(L[(int64_t)i * m + k], L[(int64_t)j * m + k]);
+        acc.x += dk[k] * t.x;
+        acc.y += dk[k] * t.y;
+    }
+    M[(int64_t)j * m + i] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_vmin(int64_t n, const double *__restrict__ v, double *__restrict__ out)
+{
+    __shared__ double red[4];
+    double mn = INFINITY;
+    for (int64_t i = threadIdx.x; i < n; i += 256) mn = fmin(mn, v[i]);
+    mn = -block_max<256>(-mn, red);
+    if (threadIdx.x == 0) out[0] = mn;
+}
+
+__global__ void k_shift_final(const double *__restrict__ vmin, const double *__restrict__ lam, int has_nl,
+                              const int32_t *__restrict__ fail, double *__restrict__ sigma)
+{
+    double l = has_nl ? lam[0] : 0.0;
+    if (has_nl && fail[0]) l = NAN;
+    sigma[0] = vmin[0] + (l < 0.0 ? l : 0.0) - 0.1;
+    if (l != l) sigma[0] = NAN;
+}
+
+// After an outer iteration: stats row, next shift, convergence flag.
+__global__ void k_bookkeep(int nb, int n_conv, int shift_mode, double sigma_lb, double tol_res,
+                           const double *__restrict__ eps, const double *__restrict__ res, double *__restrict__ sig_all,
+                           double *__restrict__ sig_out, double *__restrict__ stats_row, int32_t *__restrict__ conv)
+{
+    double sigma = sigma_lb;
+    if (shift_mode == PARO_SHIFT_ADAPTIVE && res[0] < 0.1) {
+        const double s = eps[0] - 0.05 - res[0];
+        if (s > sigma) sigma = s;
+    }
+    double rmax = 0.0;
+    for (int b = 0; b < n_conv; ++b) rmax = fmax(rmax, res[b]);
+    const int ok = tol_res > 0.0 && rmax <= tol_res;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) sig_all[b] = sigma;
+    if (threadIdx.x == 0) {
+        sig_out[0] = sigma;
+        conv[0] = ok;
+    }
+    if (stats_row) {
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+            stats_row[b] = eps[b];
+            stats_row[nb + b] = res[b];
+        }
+        if (threadIdx.x == 0) {
+            stats_row[2 * nb] = sigma;
+            stats_row[2 * nb + 1] = ok ? 1.0 : 0.0;
+        }
+    }
+}
+
+}  // namespace
+
+// dreal layout: d[m] e[m] tau[2m] lam[m] vmin[1] fail(int)[2] | Z[m*m] | scr[4*m*m]
+struct DenseScratch {
+    double *d, *e, *lam, *vmin;
+    double2 *tau;
+    int32_t *fail;
+    double *Z, *scr;
+};
+
+static DenseScratch dense_scratch(const Workspace &w, int m)
+{
+    DenseScratch s;
+    double *p = w.dreal;
+    s.d = p;
+    s.e = p + m;
+    s.tau = reinterpret_cast<double2 *>(p + 2 * m);
+    s.lam = p + 4 * m;
+    s.vmin = p + 5 * m;
+    s.fail = reinterpret_cast<int32_t *>(p + 5 * m + 1);
+    s.Z = p + 5 * m + 2;
+    s.scr = s.Z + (size_t)m * m;
+    return s;
+}
+
+size_t dense_real_elems(int mmax) { return 5 * (size_t)mmax + 2 + 5 * (size_t)mmax * mmax; }
+
+static hipError_t eig_pipeline(hipStream_t st, int m, double2 *Hh, const DenseScratch &s, double *eps_out,
+                               int nout, double2 *Yout, bool vectors)
+{
+    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kBig), 0, st, m, Hh, s.d, s.e, s.tau);
+    hipLaunchKernelGGL(k_tridiag_eig, dim3(1), dim3(kBig), 0, st, m, s.d, s.e, s.lam, eps_out, nout,
+                       vectors ? s.Z : nullptr, s.scr);
+    if (vectors)
+        hipLaunchKernelGGL(k_backtransform, dim3(m), dim3(64), (size_t)m * sizeof(double2), st, m, Hh, s.tau, s.Z,
+                           Yout);
+    return hipGetLastError();
+}
+
+hipError_t launch_rr_dense(const Plan &pl, const Workspace &w, int m, int n_keep, double *eps_out, double2 *C)
+{
+    if (m > kBig) return hipErrorInvalidValue;
+    hipStream_t st = pl.stream;
+    DenseScratch s = dense_scratch(w, m);
+    double2 *L = w.dense[0], *X = w.dense[1], *Hh = w.dense[2], *Y = w.dense[3];
+    const size_t colshm = (size_t)m * sizeof(double2);
+    hipLaunchKernelGGL(k_rr_chol, dim3(1), dim3(kBig), 0, st, m, w.gram, 1, L, X, s.fail, pl.status);
+    // X <- L^-1 Hs;  Hh <- L^-1 X^H = L^-1 Hs L^-H
+    hipLaunchKernelGGL(k_trsm_col, dim3(m), dim3(64), colshm, st, m, L, X, 0, 0, X);
+    hipLaunchKernelGGL(k_trsm_col, dim3(m), dim3(64), colshm, st, m, L, X, 1, 0, Hh);
+    eig_pipeline(st, m, Hh, s, eps_out, n_keep, Y, true);
+    // C = L^-H Y
+    hipLaunchKernelGGL(k_trsm_col, dim3(m), dim3(64), colshm, st, m, L, Y, 0, 1, C);
+    return hipGetLastError();
+}
+
+// Standalone Hermitian eigensolver on the device (the Rayleigh-Ritz
+// eigensolve without the overlap): A (m x m, column-major) is copied to
+// dense[2]; eigenvalues to w (ascending), eigenvectors to V.
+hipError_t launch_heev(hipStream_t st, const Workspace &w, int m, const double2 *A, double *wout, double2 *V)
+{
+    if (m > kBig) return hipErrorInvalidValue;
+    DenseScratch s = dense_scratch(w, m);
+    hipError_t e = hipMemcpyAsync(w.dense[2], A, sizeof(double2) * m * m, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    return eig_pipeline(st, m, w.dense[2], s, wout, m, V, true);
+}
+
+hipError_t launch_shift_bound(const Plan &pl, const Workspace &w, double *sigma)
+{
+    hipStream_t st = pl.stream;
+    const int np = pl.nproj;
+    DenseScratch s = dense_scratch(w, np > 0 ? np : 1);
+    const int64_t nv = (int64_t)pl.grid[0] * pl.grid[1] * pl.grid[2];
+    hipLaunchKernelGGL(k_vmin, dim3(1), dim3(256), 0, st, nv, pl.vplane, s.vmin);
+    if (np > 0) {
+        // G = B^H B, Cholesky, M = L^H D L, lowest eigenvalue
+        hipError_t err = gemm_hn(st, np, np, pl.ng, pl.beta, pl.ldv, pl.beta, pl.ldv, w.gram, np, w.part,
+                                 w.part_elems, nullptr, nullptr);
+        if (err != hipSuccess) return err;
+        hipLaunchKernelGGL(k_rr_chol, dim3(1), dim3(kBig), 0, st, np, w.gram, 0, w.dense[0], w.dense[1], s.fail,
+                           pl.status);
+        hipLaunchKernelGGL(k_lhdl, dim3((np + 63) / 64, np), dim3(64), 0, st, np, w.dense[0], pl.dkb, w.dense[2]);
+        eig_pipeline(st, np, w.dense[2], s, nullptr, 0, nullptr, false);
+    }
+    hipLaunchKernelGGL(k_shift_final, dim3(1), dim3(1), 0, st, s.vmin, s.lam, np > 0 ? 1 : 0, s.fail, sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_bookkeeping(const Plan &pl, int nb, const paro_iter_opts &o, const double *eps, const double *res,
+                              double *sig_all, double *sig_out, double *stats_row, int32_t *conv)
+{
+    const int nconv = o.n_conv > 0 && o.n_conv <= nb ? o.n_conv : nb;
+    hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(256), 0, pl.stream, nb, nconv, o.shift_mode, o.sigma_lb, o.tol_res,
+                       eps, res, sig_all, sig_out, stats_row, conv);
+    return hipGetLastError();
+}
+
+}  // namespace paro

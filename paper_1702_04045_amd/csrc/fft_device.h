@@ -1,0 +1,311 @@
+// Batched mixed-radix FFT lines for gfx950, double precision complex.
+//
+// A line of length N is owned by T consecutive "line threads"; each holds
+// E = N / T elements in registers.  The transform is a Stockham autosort
+// sequence of radix passes R0, R1, ... (product N).  Inside a pass thread t
+// runs E / R radix-R butterflies on tasks j = t + T q; between passes the
+// line goes through LDS once (store, barrier, load).  After the last pass
+// of radix RL the thread holds output index j + r (N / RL) in v[q RL + r],
+// which are exactly the input positions of a pass of radix RL: a forward
+// transform that starts with RL can run on the registers an inverse
+// transform that ended with RL left behind.
+//
+// X_k = sum_j x_j exp(SIGN 2 pi i j k / N), unnormalised.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace paro {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// SIGN * i * a
+template <int SIGN> __device__ __forceinline__ double2 mul_si(double2 a)
+{
+    return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+// cos / sin (2 pi j / R), j < R, correctly rounded literals.
+template <int R> struct TwC;
+template <> struct TwC<4> {
+    static constexpr double c[4] = {1.0, 0.0, -1.0, 0.0};
+    static constexpr double s[4] = {0.0, 1.0, 0.0, -1.0};
+};
+template <> struct TwC<6> {
+    static constexpr double c[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+    static constexpr double s[6] = {0.0, 0.8660254037844386467637, 0.8660254037844386467637, 0.0,
+                                    -0.8660254037844386467637, -0.8660254037844386467637};
+};
+template <> struct TwC<8> {
+    static constexpr double c[8] = {1.0, 0.7071067811865475244008, 0.0, -0.7071067811865475244008,
+                                    -1.0, -0.7071067811865475244008, 0.0, 0.7071067811865475244008};
+    static constexpr double s[8] = {0.0, 0.7071067811865475244008, 1.0, 0.7071067811865475244008,
+                                    0.0, -0.7071067811865475244008, -1.0, -0.7071067811865475244008};
+};
+template <> struct TwC<10> {
+    static constexpr double c[10] = {1.0, 0.8090169943749474241023, 0.3090169943749474241023,
+                                     -0.3090169943749474241023, -0.8090169943749474241023, -1.0,
+                                     -0.8090169943749474241023, -0.3090169943749474241023,
+                                     0.3090169943749474241023, 0.8090169943749474241023};
+    static constexpr double s[10] = {0.0, 0.5877852522924731291687, 0.9510565162951535721164,
+                                     0.9510565162951535721164, 0.5877852522924731291687, 0.0,
+                                     -0.5877852522924731291687, -0.9510565162951535721164,
+                                     -0.9510565162951535721164, -0.5877852522924731291687};
+};
+template <> struct TwC<12> {
+    static constexpr double c[12] = {1.0, 0.8660254037844386467637, 0.5, 0.0, -0.5,
+                                     -0.8660254037844386467637, -1.0, -0.8660254037844386467637,
+                                     -0.5, 0.0, 0.5, 0.8660254037844386467637};
+    static constexpr double s[12] = {0.0, 0.5, 0.8660254037844386467637, 1.0, 0.8660254037844386467637,
+                                     0.5, 0.0, -0.5, -0.8660254037844386467637, -1.0,
+                                     -0.8660254037844386467637, -0.5};
+};
+template <> struct TwC<16> {
+    static constexpr double c[16] = {1.0, 0.9238795325112867561282, 0.7071067811865475244008,
+                                     0.3826834323650897717285, 0.0, -0.3826834323650897717285,
+                                     -0.7071067811865475244008, -0.9238795325112867561282, -1.0,
+                                     -0.9238795325112867561282, -0.7071067811865475244008,
+                                     -0.3826834323650897717285, 0.0, 0.3826834323650897717285,
+                                     0.7071067811865475244008, 0.9238795325112867561282};
+    static constexpr double s[16] = {0.0, 0.3826834323650897717285, 0.7071067811865475244008,
+                                     0.9238795325112867561282, 1.0, 0.9238795325112867561282,
+                                     0.7071067811865475244008, 0.3826834323650897717285, 0.0,
+                                     -0.3826834323650897717285, -0.7071067811865475244008,
+                                     -0.9238795325112867561282, -1.0, -0.9238795325112867561282,
+                                     -0.7071067811865475244008, -0.3826834323650897717285};
+};
+template <> struct TwC<20> {
+    static constexpr double c[20] = {1.0, 0.9510565162951535721164, 0.8090169943749474241023,
+                                     0.5877852522924731291687, 0.3090169943749474241023, 0.0,
+                                     -0.3090169943749474241023, -0.5877852522924731291687,
+                                     -0.8090169943749474241023, -0.9510565162951535721164, -1.0,
+                                     -0.9510565162951535721164, -0.8090169943749474241023,
+                                     -0.5877852522924731291687, -0.3090169943749474241023, 0.0,
+                                     0.3090169943749474241023, 0.5877852522924731291687,
+                                     0.8090169943749474241023, 0.9510565162951535721164};
+    static constexpr double s[20] = {0.0, 0.3090169943749474241023, 0.5877852522924731291687,
+                                     0.8090169943749474241023, 0.9510565162951535721164, 1.0,
+                                     0.9510565162951535721164, 0.8090169943749474241023,
+                                     0.5877852522924731291687, 0.3090169943749474241023, 0.0,
+                                     -0.3090169943749474241023, -0.5877852522924731291687,
+                                     -0.8090169943749474241023, -0.9510565162951535721164, -1.0,
+                                     -0.9510565162951535721164, -0.8090169943749474241023,
+                                     -0.5877852522924731291687, -0.3090169943749474241023};
+};
+
+// ---------------------------------------------------------------- radix-R DFTs
+template <int R, int SIGN> struct Dft;
+
+template <int SIGN> struct Dft<1, SIGN> {
+    static __device__ __forceinline__ void run(double2 *) {}
+};
+
+template <int SIGN> struct Dft<2, SIGN> {
+    static __device__ __forceinline__ void run(double2 *v)
+    {
+        double2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <int SIGN> struct Dft<3, SIGN> {
+    static __device__ __forceinline__ void run(double2 *v)
+    {
+        const double h = 0.8660254037844386467637;  // sin(2 pi / 3)
+        double2 t1 = cadd(v[1], v[2]);
+        double2 t2 = make_double2(v[0].x - 0.5 * t1.x, v[0].y - 0.5 * t1.y);
+        double2 t3 = cscale(csub(v[1], v[2]), h);
+        double2 it3 = mul_si<SIGN>(t3);
+        v[0] = cadd(v[0], t1);
+        v[1] = cadd(t2, it3);
+        v[2] = csub(t2, it3);
+    }
+};
+
+template <int SIGN> struct Dft<4, SIGN> {
+    static __device__ __forceinline__ void run(double2 *v)
+    {
+        double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+        double2 c = cadd(v[1], v[3]), d = mul_si<SIGN>(csub(v[1], v[3]));
+        v[0] = cadd(a, c);
+        v[2] = csub(a, c);
+        v[1] = cadd(b, d);
+        v[3] = csub(b, d);
+    }
+};
+
+template <int SIGN> struct Dft<5, SIGN> {
+    static __device__ __forceinline__ void run(double2 *v)
+    {
+        const double c1 = 0.3090169943749474241023, c2 = -0.8090169943749474241023;
+        const double s1 = 0.9510565162951535721164, s2 = 0.5877852522924731291687;
+        double2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+        double2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+        double2 x0 = v[0];
+        double2 p1 = make_double2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+        double2 p2 = make_double2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+        double2 q1 = mul_si<SIGN>(make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
+        double2 q2 = mul_si<SIGN>(make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+        v[0] = cadd(x0, cadd(a1, a2));
+        v[1] = cadd(p1, q1);
+        v[4] = csub(p1, q1);
+        v[2] = cadd(p2, q2);
+        v[3] = csub(p2, q2);
+    }
+};
+
+// R = A B: A-point DFTs over s_a of x[B s_a + s_b], twiddle by w_R^(s_b k_a),
+// then B-point DFTs over s_b; output index k_a + A k_b.
+template <int A, int B, int SIGN> struct DftComp {
+    static __device__ __forceinline__ void run(double2 *v)
+    {
+        constexpr int R = A * B;
+        double2 y[R];
+#pragma unroll
+        for (int sb = 0; sb < B; ++sb) {
+            double2 a[A];
+#pragma unroll
+            for (int sa = 0; sa < A; ++sa) a[sa] = v[B * sa + sb];
+            Dft<A, SIGN>::run(a);
+#pragma unroll
+            for (int ka = 0; ka < A; ++ka) y[sb * A + ka] = a[ka];
+        }
+#pragma unroll
+        for (int ka = 0; ka < A; ++ka) {
+            double2 b[B];
+#pragma unroll
+            for (int sb = 0; sb < B; ++sb) {
+                const int j = sb * ka;
+                double2 x = y[sb * A + ka];
+                if (j != 0) {
+                    const double c = TwC<R>::c[j], s = SIGN * TwC<R>::s[j];
+                    x = make_double2(x.x * c - x.y * s, x.x * s + x.y * c);
+                }
+                b[sb] = x;
+            }
+            Dft<B, SIGN>::run(b);
+#pragma unroll
+            for (int kb = 0; kb < B; ++kb) v[ka + A * kb] = b[kb];
+        }
+    }
+};
+
+template <int SIGN> struct Dft<6, SIGN> : DftComp<2, 3, SIGN> {};
+template <int SIGN> struct Dft<8, SIGN> : DftComp<2, 4, SIGN> {};
+template <int SIGN> struct Dft<10, SIGN> : DftComp<2, 5, SIGN> {};
+template <int SIGN> struct Dft<12, SIGN> : DftComp<4, 3, SIGN> {};
+template <int SIGN> struct Dft<16, SIGN> : DftComp<4, 4, SIGN> {};
+template <int SIGN> struct Dft<20, SIGN> : DftComp<4, 5, SIGN> {};
+
+// ---------------------------------------------------------------- line schedules
+template <int... Rs> struct RList {};
+
+template <int First, int... Rest> struct FirstOf { static constexpr int value = First; };
+template <int... Rs> struct LastOf;
+template <int R> struct LastOf<R> { static constexpr int value = R; };
+template <int R, int... Rs> struct LastOf<R, Rs...> { static constexpr int value = LastOf<Rs...>::value; };
+
+// FftCfg<N>: T threads per line, E = N / T elements each, radix list Inv
+// (used for SIGN = +1) and its reverse Fwd (SIGN = -1).
+template <int N> struct FftCfg;
+template <> struct FftCfg<8> { static constexpr int T = 2, E = 4; using Inv = RList<4, 2>; using Fwd = RList<2, 4>; };
+template <> struct FftCfg<16> { static constexpr int T = 4, E = 4; using Inv = RList<4, 4>; using Fwd = RList<4, 4>; };
+template <> struct FftCfg<24> { static constexpr int T = 2, E = 12; using Inv = RList<6, 4>; using Fwd = RList<4, 6>; };
+template <> struct FftCfg<32> { static constexpr int T = 4, E = 8; using Inv = RList<8, 4>; using Fwd = RList<4, 8>; };
+template <> struct FftCfg<40> { static constexpr int T = 2, E = 20; using Inv = RList<10, 4>; using Fwd = RList<4, 10>; };
+template <> struct FftCfg<48> { static constexpr int T = 4, E = 12; using Inv = RList<12, 4>; using Fwd = RList<4, 12>; };
+template <> struct FftCfg<64> { static constexpr int T = 8, E = 8; using Inv = RList<8, 8>; using Fwd = RList<8, 8>; };
+template <> struct FftCfg<80> { static constexpr int T = 4, E = 20; using Inv = RList<5, 4, 4>; using Fwd = RList<4, 4, 5>; };
+template <> struct FftCfg<96> { static constexpr int T = 8, E = 12; using Inv = RList<6, 4, 4>; using Fwd = RList<4, 4, 6>; };
+
+template <class L> struct ListInfo;
+template <int... Rs> struct ListInfo<RList<Rs...>> {
+    static constexpr int first = FirstOf<Rs...>::value;
+    static constexpr int last = LastOf<Rs...>::value;
+};
+
+// Inputs of a radix-R pass: v[q R + r] <- x[t + T q + r N/R].
+template <int N, int T, int E, int R, class F>
+__device__ __forceinline__ void pass_load(double2 (&v)[E], int t, F &&f)
+{
+#pragma unroll
+    for (int q = 0; q < E / R; ++q)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q * R + r] = f(t + T * q + r * (N / R));
+}
+
+// Outputs of a radix-R pass at stride NS: v[q R + r] -> y[(j/NS) NS R + j%NS + r NS].
+template <int N, int T, int E, int R, int NS, class F>
+__device__ __forceinline__ void pass_store(const double2 (&v)[E], int t, F &&f)
+{
+#pragma unroll
+    for (int q = 0; q < E / R; ++q) {
+        const int j = t + T * q;
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) f(base + r * NS, v[q * R + r]);
+    }
+}
+
+// Final outputs (after a last pass of radix RL): v[q RL + r] is element t + T q + r N/RL.
+template <int N, int T, int E, int RL, class F>
+__device__ __forceinline__ void final_foreach(const double2 (&v)[E], int t, F &&f)
+{
+#pragma unroll
+    for (int q = 0; q < E / RL; ++q)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) f(t + T * q + r * (N / RL), q * RL + r);
+}
+
+// tw[m] = exp(-2 pi i m / N); SIGN = +1 uses the conjugate.
+template <int N, int T, int E, int R, int NS, int SIGN>
+__device__ __forceinline__ void pass_compute(double2 (&v)[E], int t, const double2 *__restrict__ tw)
+{
+#pragma unroll
+    for (int q = 0; q < E / R; ++q) {
+        if constexpr (NS > 1) {
+            const int j = t + T * q;
+            const int k = j % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                double2 w = tw[r * k * (N / (NS * R))];
+                if (SIGN > 0) w.y = -w.y;
+                v[q * R + r] = cmul(v[q * R + r], w);
+            }
+        }
+        Dft<R, SIGN>::run(&v[q * R]);
+    }
+}
+
+template <int N, int T, int E, int SIGN, int NS, int R, int... Rest>
+__device__ __forceinline__ void stockham_rec(double2 (&v)[E], int t, bool act, double2 *line, int es,
+                                             const double2 *__restrict__ tw)
+{
+    if (act) pass_compute<N, T, E, R, NS, SIGN>(v, t, tw);
+    if constexpr (sizeof...(Rest) > 0) {
+        constexpr int R2 = FirstOf<Rest...>::value;
+        __syncthreads();
+        if (act) pass_store<N, T, E, R, NS>(v, t, [&](int i, double2 x) { line[i * es] = x; });
+        __syncthreads();
+        if (act) pass_load<N, T, E, R2>(v, t, [&](int i) { return line[i * es]; });
+        stockham_rec<N, T, E, SIGN, NS * R, Rest...>(v, t, act, line, es, tw);
+    }
+}
+
+// Run all passes of list L on registers v that hold the inputs of its first
+// pass.  Every thread of the block must call this (it contains barriers);
+// act = false threads only take part in the barriers.  line/es: this
+// thread's line in LDS, used for the exchanges between passes.
+template <int N, int SIGN, int... Rs>
+__device__ __forceinline__ void stockham(RList<Rs...>, double2 (&v)[FftCfg<N>::E], int t, bool act,
+                                         double2 *line, int es, const double2 *__restrict__ tw)
+{
+    stockham_rec<N, FftCfg<N>::T, FftCfg<N>::E, SIGN, 1, Rs...>(v, t, act, line, es, tw);
+}
+
+}  // namespace paro

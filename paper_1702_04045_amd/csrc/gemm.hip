@@ -1,0 +1,264 @@
+// Complex double GEMMs on the FP64 matrix cores of gfx950, and the device
+// construction of the Kleinman-Bylander projector matrix.
+//
+// Every complex product is four real v_mfma_f64_16x16x4f64 products.  For
+// that instruction lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// (a 16 x 4 by 4 x 16 step) and holds D[4 (l / 16) + v][l % 16], v < 4.
+//
+// gemm_hn: C = A^H B with a long contraction (projector coefficients
+// P = B^H psi, Gram matrices U^H U and U^H W of Rayleigh-Ritz).  The
+// contraction is split over work-groups; partial tiles are summed in a
+// fixed order by a second kernel, so results are bitwise reproducible.
+// gemm_nn: C (+)= A B with a tall A and a short contraction (the nonlocal
+// add q += B (D P) and the Ritz rotations U C, W C).  The matrix-core tile
+// is laid out as (column of C) x (row of C) so that a lane group writes 16
+// consecutive rows of C: stores are coalesced along the sphere.
+#include <cmath>
+
+#include "paro_internal.h"
+#include "reduce_device.h"
+
+namespace paro {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+namespace {
+
+constexpr int kTile = 64;  // work-group tile (4 waves of 32 x 32)
+
+// partial[s][j][i] = sum over k in split s of conj(A[k][i]) B[k][j]
+__global__ void __launch_bounds__(256)
+k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, const double2 *__restrict__ A, int64_t lda,
+               const double2 *__restrict__ B, int64_t ldb, double2 *__restrict__ part)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i0 = blockIdx.x * kTile + (wave & 1) * 32;
+    const int j0 = blockIdx.y * kTile + (wave >> 1) * 32;
+    const int64_t kb = (int64_t)blockIdx.z * kchunk;
+    const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
+    const int l16 = lane & 15, lk = lane >> 4;
+    d4 re[2][2], im[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            re[a][b] = d4{0, 0, 0, 0};
+            im[a][b] = d4{0, 0, 0, 0};
+        }
+    const int ia[2] = {i0 + l16, i0 + 16 + l16};
+    const int jb[2] = {j0 + l16, j0 + 16 + l16};
+    for (int64_t k0 = kb; k0 < ke; k0 += 4) {
+        const int64_t kk = k0 + lk;
+        const bool kv = kk < ke;
+        double2 a[2], b[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            a[u] = (kv && ia[u] < M) ? A[(int64_t)ia[u] * lda + kk] : make_double2(0.0, 0.0);
+            b[u] = (kv && jb[u] < N) ? B[(int64_t)jb[u] * ldb + kk] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
+                re[u][w] = mfma(a[u].x, b[w].x, re[u][w]);
+                re[u][w] = mfma(a[u].y, b[w].y, re[u][w]);
+                im[u][w] = mfma(a[u].x, b[w].y, im[u][w]);
+                im[u][w] = mfma(-a[u].y, b[w].x, im[u][w]);
+            }
+    }
+    double2 *P = part + (size_t)blockIdx.z * M * N;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + u * 16 + 4 * lk + v;
+                const int j = j0 + w * 16 + l16;
+                if (i < M && j < N) P[(size_t)j * M + i] = make_double2(re[u][w][v], im[u][w][v]);
+            }
+}
+
+// C[i][j] = dscale_i * sum_s part[s][j][i]; quad_j = sum_i dscale_i |sum_s part|^2
+__global__ void __launch_bounds__(256)
+k_gemm_hn_reduce(int M, int N, int nsplit, const double2 *__restrict__ part, double2 *__restrict__ C, int64_t ldc,
+                 const double *__restrict__ dscale, double *__restrict__ quad)
+{
+    __shared__ double red[4];
+    const int j = blockIdx.x;
+    double q = 0.0;
+    for (int i = threadIdx.x; i < M; i += 256) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int p = 0; p < nsplit; ++p) {
+            const double2 x = part[((size_t)p * N + j) * M + i];
+            s.x += x.x;
+            s.y += x.y;
+        }
+        if (dscale) {
+            const double d = dscale[i];
+            q += d * (s.x * s.x + s.y * s.y);
+            s.x *= d;
+            s.y *= d;
+        }
+        C[(int64_t)j * ldc + i] = s;
+    }
+    if (quad) {
+        q = block_sum<256>(q, red);
+        if (threadIdx.x == 0) quad[j] = q;
+    }
+}
+
+// C[g][n] (+)= sum_k A[g][k] B[k][n]; matrix-core rows = n, columns = g.
+__global__ void __launch_bounds__(256)
+k_gemm_nn(int64_t M, int N, int K, const double2 *__restrict__ A, int64_t lda, const double2 *__restrict__ B,
+          int64_t ldb, double2 *__restrict__ C, int64_t ldc, int accumulate)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t g0 = (int64_t)blockIdx.x * kTile + (wave & 1) * 32;
+    const int n0 = blockIdx.y * kTile + (wave >> 1) * 32;
+    const int l16 = lane & 15, lk = lane >> 4;
+    d4 re[2][2], im[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            re[a][b] = d4{0, 0, 0, 0};
+            im[a][b] = d4{0, 0, 0, 0};
+        }
+    const int nb_[2] = {n0 + l16, n0 + 16 + l16};
+    const int64_t gg[2] = {g0 + l16, g0 + 16 + l16};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int kk = k0 + lk;
+        const bool kv = kk < K;
+        double2 x[2], y[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            x[u] = (kv && nb_[u] < N) ? B[(int64_t)nb_[u] * ldb + kk] : make_double2(0.0, 0.0);
+            y[u] = (kv && gg[u] < M) ? A[(int64_t)kk * lda + gg[u]] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                // (x y): re = xr yr - xi yi, im = xr yi + xi yr
+                re[u][w] = mfma(x[u].x, y[w].x, re[u][w]);
+                re[u][w] = mfma(-x[u].y, y[w].y, re[u][w]);
+                im[u][w] = mfma(x[u].x, y[w].y, im[u][w]);
+                im[u][w] = mfma(x[u].y, y[w].x, im[u][w]);
+            }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int n = n0 + u * 16 + 4 * lk + v;
+                const int64_t g = g0 + w * 16 + l16;
+                if (n < N && g < M) {
+                    double2 *c = C + (int64_t)n * ldc + g;
+                    double2 r = make_double2(re[u][w][v], im[u][w][v]);
+                    if (accumulate) {
+                        const double2 o = *c;
+                        r.x += o.x;
+                        r.y += o.y;
+                    }
+                    *c = r;
+                }
+            }
+}
+
+// One work-group per projector: beta_p(G) for every sphere point, then the
+// normalisation sum_G |beta_p(G)|^2 = 1 (two passes over the sphere).
+__global__ void __launch_bounds__(256)
+k_build_projectors(int64_t ng, const int32_t *__restrict__ miller, double b00, double b01, double b02,
+                   double b10, double b11, double b12, double b20, double b21, double b22,
+                   const double *__restrict__ centers, const int32_t *__restrict__ lm,
+                   const double *__restrict__ widths, double2 *__restrict__ beta, int64_t ldb)
+{
+    __shared__ double red[4];
+    const int p = blockIdx.x;
+    const double R0 = centers[3 * p], R1 = centers[3 * p + 1], R2 = centers[3 * p + 2];
+    const int l = lm[2 * p], m = lm[2 * p + 1];
+    const double w = widths[p];
+    double2 *out = beta + (int64_t)p * ldb;
+    double nrm = 0.0;
+    for (int64_t g = threadIdx.x; g < ng; g += 256) {
+        const double n1 = miller[3 * g], n2 = miller[3 * g + 1], n3 = miller[3 * g + 2];
+        const double G0 = n1 * b00 + n2 * b10 + n3 * b20;
+        const double G1 = n1 * b01 + n2 * b11 + n3 * b21;
+        const double G2 = n1 * b02 + n2 * b12 + n3 * b22;
+        const double g2 = G0 * G0 + G1 * G1 + G2 * G2;
+        const double gr = G0 * R0 + G1 * R1 + G2 * R2;
+        const double env = exp(-0.5 * w * w * g2);
+        double sn, cs;
+        sincos(gr, &sn, &cs);
+        double2 val = make_double2(env * cs, -env * sn);  // exp(-0.5 w^2 G^2) exp(-i G.R)
+        if (l == 1) {
+            const double ga = m == 0 ? G0 : (m == 1 ? G1 : G2);
+            // times (-i w G_a)
+            val = make_double2(w * ga * val.y, -w * ga * val.x);
+        }
+        out[g] = val;
+        nrm += val.x * val.x + val.y * val.y;
+    }
+    nrm = block_sum<256>(nrm, red);
+    const double sc = nrm > 0 ? 1.0 / sqrt(nrm) : 0.0;
+    for (int64_t g = threadIdx.x; g < ng; g += 256) {
+        double2 v = out[g];
+        out[g] = make_double2(v.x * sc, v.y * sc);
+    }
+    for (int64_t g = ng + threadIdx.x; g < ldb; g += 256) out[g] = make_double2(0.0, 0.0);
+}
+
+}  // namespace
+
+hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const double2 *A, int64_t lda, const double2 *B,
+                   int64_t ldb, double2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale,
+                   double *quad)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int tm = (M + kTile - 1) / kTile, tn = (N + kTile - 1) / kTile;
+    int64_t nsplit = (kSplitTarget + tm * tn - 1) / (tm * tn);
+    const int64_t kmax = (K + 255) / 256;  // at least 256 per split
+    if (nsplit > kmax) nsplit = kmax;
+    if (nsplit < 1) nsplit = 1;
+    const int64_t cap = (int64_t)(part_elems / ((size_t)M * N));
+    if (nsplit > cap) nsplit = cap;
+    if (nsplit < 1) return hipErrorInvalidValue;
+    int64_t kchunk = (K + nsplit - 1) / nsplit;
+    kchunk = (kchunk + 3) / 4 * 4;
+    nsplit = (K + kchunk - 1) / kchunk;
+    if (nsplit < 1) nsplit = 1;
+    hipLaunchKernelGGL(k_gemm_hn_part, dim3(tm, tn, nsplit), dim3(256), 0, s, M, N, K, kchunk, A, lda, B, ldb,
+                       part);
+    hipLaunchKernelGGL(k_gemm_hn_reduce, dim3(N), dim3(256), 0, s, M, N, (int)nsplit, part, C, ldc, dscale, quad);
+    return hipGetLastError();
+}
+
+hipError_t gemm_nn(hipStream_t s, int64_t M, int N, int K, const double2 *A, int64_t lda, const double2 *B,
+                   int64_t ldb, double2 *C, int64_t ldc, bool accumulate)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((M + kTile - 1) / kTile), (N + kTile - 1) / kTile);
+    hipLaunchKernelGGL(k_gemm_nn, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_projectors(const Plan &pl, const int32_t *miller_dev, const double *centers,
+                                   const int32_t *lm, const double *widths)
+{
+    if (pl.nproj == 0) return hipSuccess;
+    const double *b = pl.bvec;
+    hipLaunchKernelGGL(k_build_projectors, dim3(pl.nproj), dim3(256), 0, pl.stream, pl.ng, miller_dev, b[0], b[1],
+                       b[2], b[3], b[4], b[5], b[6], b[7], b[8], centers, lm, widths, pl.beta, pl.ldv);
+    return hipGetLastError();
+}
+
+}  // namespace paro

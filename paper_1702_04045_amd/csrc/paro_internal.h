@@ -1,0 +1,112 @@
+// Internal declarations of libparo (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "paro.h"
+
+namespace paro {
+
+constexpr int kMaxBandsPerChunk = 64;  // bands per sphere->stick->plane pass (stick buffer size)
+constexpr int kSplitTarget = 512;      // aim for about this many split-K work-groups
+constexpr int kMaxParts = 512;         // partial sums per band per reduction
+
+// per-band scalar slots (Workspace::sc, each nb long)
+enum { SC_GAMMA = 0, SC_GAMMA0, SC_TAU, SC_BETA, SC_NLQ, kScalars };
+// partial-sum slots (Workspace::dots, each nb x kMaxParts)
+enum { DOT_PQ = 0, DOT_RZ, DOT_TKIN, DOT_NRM, DOT_RES, kDotSlots };
+
+struct Plan {
+    hipStream_t stream = nullptr;
+    double cell[9], bvec[9], omega, ecut, vmin;
+    int32_t grid[3], nmax[3];
+    int64_t ng = 0, ldv = 0;  // sphere size; padded length of workspace vectors
+    int32_t nst = 0, nproj = 0, ncol = 0;
+    // device arrays inside the caller's plan buffer
+    double *kin = nullptr;        // (1/2)|G|^2, ng
+    int32_t *pt_sz = nullptr;     // per sphere point: (stick << 8) | (n3 mod N3)
+    int32_t *st_start = nullptr;  // per stick: first sphere point, nst + 1
+    int32_t *st_xy = nullptr;     // per stick: (n1 mod N1) | (n2 mod N2) << 16
+    double *vplane = nullptr;     // local potential, plane-major [i3][i2][i1]
+    double2 *tw[3] = {nullptr, nullptr, nullptr};  // exp(-2 pi i m / N_d)
+    double2 *beta = nullptr;      // KB projectors, nproj x ldv (projector-major)
+    double *dkb = nullptr;        // KB energies
+    int32_t *status = nullptr;    // sticky status bits
+};
+
+// Workspace carve-up for calls on up to nb bands (m <= 2 nb for Rayleigh-Ritz).
+struct Workspace {
+    double2 *sticks;          // min(64, 2 nb) x N3 x nst
+    double2 *r, *z, *p, *q;   // PCG vectors, nb x ldv each
+    double2 *U, *W;           // 2 nb x ldv each: Rayleigh-Ritz basis and its H image
+    double2 *gram;            // [S Hs], m x 2m
+    double2 *part;            // split-K partial tiles
+    size_t part_elems;
+    double2 *P;               // projector coefficients, nproj x 2 nb
+    double2 *dense[5];        // max(2 nb, nproj)^2 each: L, X, Hhat, Y, C
+    double *dreal;            // real scratch of the tridiagonal eigensolver
+    size_t dreal_elems;
+    double *sc;               // per-band scalars, kScalars x nb
+    double *dots;             // per-band partial sums, kDotSlots x nb x kMaxParts
+    int32_t *iflags;          // per band: active (nb) and status bits (nb)
+    double *sig_all, *res, *eps_all;  // 2 nb each
+    double *scal;             // 8 doubles of device scalars
+};
+
+size_t workspace_bytes(const Plan &pl, int nb);
+Workspace carve_workspace(const Plan &pl, int nb, void *ws);
+size_t dense_real_elems(int mmax);
+
+void set_error(const std::string &msg);
+#define PARO_HIP_TRY(expr)                                                      \
+    do {                                                                        \
+        hipError_t _e = (expr);                                                 \
+        if (_e != hipSuccess) {                                                 \
+            ::paro::set_error(std::string(#expr ": ") + hipGetErrorString(_e)); \
+            return PARO_EHIP;                                                   \
+        }                                                                       \
+    } while (0)
+
+// ---- launchers (return the hipError_t of the launches) ----
+// apply.hip
+bool fft_supported(int n);
+// Local part on nb bands: out_b = FFT^-1 (V FFT(x_b)) / N + (kin - shift_b) x_b,
+// x = src, or in PCG mode (pbuf != null) x = p with p <- z + beta_b p first
+// (first: p <- z) and src = z; dot_part then gets partial Re(x^H out).
+hipError_t launch_local_apply(const Plan &pl, const Workspace &w, int nb, const double2 *src, int64_t ld,
+                              double2 *out, const double *shift, double2 *pbuf, const double *beta, bool first,
+                              double *dot_part, int *nparts_out);
+// gemm.hip
+hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const double2 *A, int64_t lda, const double2 *B,
+                   int64_t ldb, double2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale,
+                   double *quad);
+hipError_t gemm_nn(hipStream_t s, int64_t M, int N, int K, const double2 *A, int64_t lda, const double2 *B,
+                   int64_t ldb, double2 *C, int64_t ldc, bool accumulate);
+hipError_t launch_build_projectors(const Plan &pl, const int32_t *miller_dev, const double *centers,
+                                   const int32_t *lm, const double *widths);
+// vec.hip
+hipError_t launch_pcg_init(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
+                           int64_t ld, const double *eps, double2 *u, int64_t ldu, int32_t *band_flags);
+hipError_t launch_pcg_update(const Plan &pl, const Workspace &w, int nb, double2 *u, int64_t ldu, int npq,
+                             int32_t *band_flags);
+hipError_t launch_residuals(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
+                            int64_t ld, const double *eps, double *res);
+hipError_t launch_mparo_correction(const Plan &pl, const Workspace &w, int nb, const double2 *psi, int64_t ld,
+                                   double2 *e, int64_t lde);
+hipError_t launch_copy_bands(hipStream_t s, int nb, int64_t ng, const double2 *src, int64_t lds, double2 *dst,
+                             int64_t ldd);
+// dense.hip
+hipError_t launch_rr_dense(const Plan &pl, const Workspace &w, int m, int n_keep, double *eps_out, double2 *C);
+hipError_t launch_heev(hipStream_t st, const Workspace &w, int m, const double2 *A, double *wout, double2 *V);
+hipError_t launch_shift_bound(const Plan &pl, const Workspace &w, double *sigma);
+hipError_t launch_bookkeeping(const Plan &pl, int nb, const paro_iter_opts &o, const double *eps, const double *res,
+                              double *sig_all, double *sig_out, double *stats_row, int32_t *conv);
+
+}  // namespace paro
+
+struct paro_plan_s {
+    paro::Plan pl;
+};

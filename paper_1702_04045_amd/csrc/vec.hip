@@ -1,0 +1,300 @@
+// Band-wise vector kernels: the preconditioned CG of the source problems
+// (Algorithm 1, step 3), residual norms (step 5) and the correction vectors
+// of Algorithm 2.  Every reduction goes through per-work-group partial sums
+// that the consumer adds in a fixed order, so runs are bitwise reproducible.
+#include "paro_internal.h"
+#include "reduce_device.h"
+
+namespace paro {
+
+namespace {
+
+constexpr int kVecThreads = 256;
+constexpr int kVecChunk = 2048;  // sphere points per work-group
+
+__device__ __forceinline__ double sum_parts(const double *p, int n)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += p[i];
+    return s;
+}
+
+// Teter-Payne-Allan preconditioner K(x), x = (1/2)|G|^2 / tau.
+__device__ __forceinline__ double teter(double x)
+{
+    const double num = 27.0 + 18.0 * x + 12.0 * x * x + 8.0 * x * x * x;
+    return num / (num + 16.0 * x * x * x * x);
+}
+
+// partial sums of <psi|T|psi> and <psi|psi>
+__global__ void __launch_bounds__(kVecThreads)
+k_pcg_init_parts(int64_t ng, const double2 *__restrict__ psi, int64_t ld, const double *__restrict__ kin,
+                 double *__restrict__ dots, int nb)
+{
+    __shared__ double red[kVecThreads / 64];
+    const int band = blockIdx.y;
+    const double2 *x = psi + band * ld;
+    double tk = 0.0, nr = 0.0;
+    const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
+        const double2 v = x[g];
+        const double a2 = v.x * v.x + v.y * v.y;
+        tk += kin[g] * a2;
+        nr += a2;
+    }
+    tk = block_sum<kVecThreads>(tk, red);
+    nr = block_sum<kVecThreads>(nr, red);
+    if (threadIdx.x == 0) {
+        dots[((size_t)DOT_TKIN * nb + band) * kMaxParts + blockIdx.x] = tk;
+        dots[((size_t)DOT_NRM * nb + band) * kMaxParts + blockIdx.x] = nr;
+    }
+}
+
+// u = psi; r = eps psi - H psi; z = K r; partial r^H z.
+__global__ void __launch_bounds__(kVecThreads)
+k_pcg_init(int64_t ng, int nparts, const double2 *__restrict__ psi, const double2 *__restrict__ hpsi, int64_t ld,
+           const double *__restrict__ eps, const double *__restrict__ kin, double2 *__restrict__ u, int64_t ldu,
+           double2 *__restrict__ r, double2 *__restrict__ z, int64_t ldv, double *__restrict__ dots,
+           double *__restrict__ sc, int nb)
+{
+    __shared__ double red[kVecThreads / 64];
+    const int band = blockIdx.y;
+    const double tk = sum_parts(dots + ((size_t)DOT_TKIN * nb + band) * kMaxParts, nparts);
+    const double nr = sum_parts(dots + ((size_t)DOT_NRM * nb + band) * kMaxParts, nparts);
+    const double tau = tk / nr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc[SC_TAU * nb + band] = tau;
+    const double e = eps[band];
+    const double2 *x = psi + band * ld, *hx = hpsi + band * ld;
+    double2 *uu = u + band * ldu, *rr = r + band * ldv, *zz = z + band * ldv;
+    double rz = 0.0;
+    const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
+        const double2 v = x[g], hv = hx[g];
+        const double2 rv = make_double2(e * v.x - hv.x, e * v.y - hv.y);
+        const double k = teter(kin[g] / tau);
+        const double2 zv = make_double2(k * rv.x, k * rv.y);
+        uu[g] = v;
+        rr[g] = rv;
+        zz[g] = zv;
+        rz += rv.x * zv.x + rv.y * zv.y;
+    }
+    rz = block_sum<kVecThreads>(rz, red);
+    if (threadIdx.x == 0) dots[((size_t)DOT_RZ * nb + band) * kMaxParts + blockIdx.x] = rz;
+}
+
+// alpha = gamma / p^H q; u += alpha p; r -= alpha q; z = K r; partial r^H z.
+__global__ void __launch_bounds__(kVecThreads)
+k_pcg_update(int64_t ng, int npq, const double2 *__restrict__ p, const double2 *__restrict__ q, int64_t ldv,
+             double2 *__restrict__ u, int64_t ldu, double2 *__restrict__ r, double2 *__restrict__ z,
+             const double *__restrict__ kin, const double *__restrict__ dots_pq, double *__restrict__ dots_rz,
+             const double *__restrict__ sc, const int32_t *__restrict__ active, int nb)
+{
+    __shared__ double red[kVecThreads / 64];
+    const int band = blockIdx.y;
+    const double pq = sum_parts(dots_pq + (size_t)band * kMaxParts, npq) + sc[SC_NLQ * nb + band];
+    const bool go = active[band] && pq > 0.0;
+    double rz = 0.0;
+    if (go) {
+        const double alpha = sc[SC_GAMMA * nb + band] / pq;
+        const double tau = sc[SC_TAU * nb + band];
+        const double2 *pp = p + band * ldv, *qq = q + band * ldv;
+        double2 *uu = u + band * ldu, *rr = r + band * ldv, *zz = z + band * ldv;
+        const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+        const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
+        for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
+            const double2 pv = pp[g], qv = qq[g];
+            double2 uv = uu[g], rv = rr[g];
+            uv.x += alpha * pv.x;
+            uv.y += alpha * pv.y;
+            rv.x -= alpha * qv.x;
+            rv.y -= alpha * qv.y;
+            const double k = teter(kin[g] / tau);
+            const double2 zv = make_double2(k * rv.x, k * rv.y);
+            uu[g] = uv;
+            rr[g] = rv;
+            zz[g] = zv;
+            rz += rv.x * zv.x + rv.y * zv.y;
+        }
+    }
+    rz = block_sum<kVecThreads>(rz, red);
+    if (threadIdx.x == 0) dots_rz[(size_t)band * kMaxParts + blockIdx.x] = rz;
+}
+
+// Per-band PCG scalars.
+// stage 0 (after init): gamma = gamma0 = r^H z; active = gamma0 > 0.
+// stage 1 (after an update): stop on p^H q <= 0 (flag NEGCURV, or NAN), else
+//   gamma' = r^H z; stop when gamma' <= 1e-26 gamma0, else beta = gamma'/gamma.
+__global__ void __launch_bounds__(kVecThreads)
+k_pcg_scalars(int nb, int stage, int nparts_rz, int npq, const double *__restrict__ dots_pq,
+              const double *__restrict__ dots_rz, double *__restrict__ sc, int32_t *__restrict__ active,
+              int32_t *__restrict__ bflags, int32_t *__restrict__ band_flags_out, int32_t *__restrict__ status)
+{
+    for (int b = threadIdx.x; b < nb; b += kVecThreads) {
+        const double rz = sum_parts(dots_rz + (size_t)b * kMaxParts, nparts_rz);
+        if (stage == 0) {
+            sc[SC_GAMMA * nb + b] = rz;
+            sc[SC_GAMMA0 * nb + b] = rz;
+            sc[SC_BETA * nb + b] = 0.0;
+            sc[SC_NLQ * nb + b] = 0.0;
+            const bool ok = rz > 0.0;
+            active[b] = ok ? 1 : 0;
+            const int32_t f = (rz != rz) ? PARO_F_NAN : 0;
+            bflags[b] = f;
+            if (f) atomicOr(status, f);
+        } else if (active[b]) {
+            const double pq = sum_parts(dots_pq + (size_t)b * kMaxParts, npq) + sc[SC_NLQ * nb + b];
+            if (!(pq > 0.0)) {
+                const int32_t f = (pq != pq) ? PARO_F_NAN : PARO_F_NEGCURV;
+                active[b] = 0;
+                bflags[b] |= f;
+                atomicOr(status, f);
+            } else if (rz != rz) {
+                active[b] = 0;
+                bflags[b] |= PARO_F_NAN;
+                atomicOr(status, PARO_F_NAN);
+            } else if (rz <= 1e-26 * sc[SC_GAMMA0 * nb + b]) {
+                active[b] = 0;
+            } else {
+                sc[SC_BETA * nb + b] = rz / sc[SC_GAMMA * nb + b];
+                sc[SC_GAMMA * nb + b] = rz;
+            }
+        }
+        if (band_flags_out) band_flags_out[b] = bflags[b];
+    }
+}
+
+// partial sums of |hpsi - eps psi|^2
+__global__ void __launch_bounds__(kVecThreads)
+k_res_parts(int64_t ng, const double2 *__restrict__ psi, const double2 *__restrict__ hpsi, int64_t ld,
+            const double *__restrict__ eps, double *__restrict__ dots)
+{
+    __shared__ double red[kVecThreads / 64];
+    const int band = blockIdx.y;
+    const double e = eps[band];
+    const double2 *x = psi + band * ld, *hx = hpsi + band * ld;
+    double s = 0.0;
+    const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
+        const double2 v = x[g], hv = hx[g];
+        const double dx = hv.x - e * v.x, dy = hv.y - e * v.y;
+        s += dx * dx + dy * dy;
+    }
+    s = block_sum<kVecThreads>(s, red);
+    if (threadIdx.x == 0) dots[(size_t)band * kMaxParts + blockIdx.x] = s;
+}
+
+__global__ void k_res_final(int nb, int nparts, const double *__restrict__ dots, double *__restrict__ res)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nb) res[b] = sqrt(sum_parts(dots + (size_t)b * kMaxParts, nparts));
+}
+
+// d = u - psi and its squared norm (partials)
+__global__ void __launch_bounds__(kVecThreads)
+k_corr_parts(int64_t ng, const double2 *__restrict__ psi, int64_t ld, double2 *__restrict__ e, int64_t lde,
+             double *__restrict__ dots)
+{
+    __shared__ double red[kVecThreads / 64];
+    const int band = blockIdx.y;
+    const double2 *x = psi + band * ld;
+    double2 *ee = e + band * lde;
+    double s = 0.0;
+    const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
+        const double2 v = x[g], u = ee[g];
+        const double2 d = make_double2(u.x - v.x, u.y - v.y);
+        ee[g] = d;
+        s += d.x * d.x + d.y * d.y;
+    }
+    s = block_sum<kVecThreads>(s, red);
+    if (threadIdx.x == 0) dots[(size_t)band * kMaxParts + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kVecThreads)
+k_corr_scale(int64_t ng, int nparts, double2 *__restrict__ e, int64_t lde, const double *__restrict__ dots)
+{
+    const int band = blockIdx.y;
+    const double n2 = sum_parts(dots + (size_t)band * kMaxParts, nparts);
+    const double s = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+    double2 *ee = e + band * lde;
+    const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
+        const double2 d = ee[g];
+        ee[g] = make_double2(d.x * s, d.y * s);
+    }
+}
+
+__global__ void __launch_bounds__(kVecThreads)
+k_copy_bands(int64_t ng, const double2 *__restrict__ src, int64_t lds, double2 *__restrict__ dst, int64_t ldd)
+{
+    const int band = blockIdx.y;
+    const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) dst[band * ldd + g] = src[band * lds + g];
+}
+
+inline unsigned nchunks(int64_t ng) { return (unsigned)((ng + kVecChunk - 1) / kVecChunk); }
+
+}  // namespace
+
+hipError_t launch_pcg_init(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
+                           int64_t ld, const double *eps, double2 *u, int64_t ldu, int32_t *band_flags)
+{
+    const unsigned nc = nchunks(pl.ng);
+    hipLaunchKernelGGL(k_pcg_init_parts, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, psi, ld, pl.kin,
+                       w.dots, nb);
+    hipLaunchKernelGGL(k_pcg_init, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, (int)nc, psi, hpsi, ld, eps,
+                       pl.kin, u, ldu, w.r, w.z, pl.ldv, w.dots, w.sc, nb);
+    hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kVecThreads), 0, pl.stream, nb, 0, (int)nc, 0,
+                       (const double *)nullptr, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags,
+                       w.iflags + nb, band_flags, pl.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_update(const Plan &pl, const Workspace &w, int nb, double2 *u, int64_t ldu, int npq,
+                             int32_t *band_flags)
+{
+    const unsigned nc = nchunks(pl.ng);
+    hipLaunchKernelGGL(k_pcg_update, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, npq, w.p, w.q, pl.ldv, u,
+                       ldu, w.r, w.z, pl.kin, w.dots + (size_t)DOT_PQ * nb * kMaxParts,
+                       w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags, nb);
+    hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kVecThreads), 0, pl.stream, nb, 1, (int)nc, npq,
+                       w.dots + (size_t)DOT_PQ * nb * kMaxParts, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc,
+                       w.iflags, w.iflags + nb, band_flags, pl.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_residuals(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
+                            int64_t ld, const double *eps, double *res)
+{
+    const unsigned nc = nchunks(pl.ng);
+    double *dots = w.dots + (size_t)DOT_RES * nb * kMaxParts;
+    hipLaunchKernelGGL(k_res_parts, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, psi, hpsi, ld, eps, dots);
+    hipLaunchKernelGGL(k_res_final, dim3((nb + 255) / 256), dim3(256), 0, pl.stream, nb, (int)nc, dots, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_mparo_correction(const Plan &pl, const Workspace &w, int nb, const double2 *psi, int64_t ld,
+                                   double2 *e, int64_t lde)
+{
+    const unsigned nc = nchunks(pl.ng);
+    double *dots = w.dots + (size_t)DOT_RES * nb * kMaxParts;
+    hipLaunchKernelGGL(k_corr_parts, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, psi, ld, e, lde, dots);
+    hipLaunchKernelGGL(k_corr_scale, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, (int)nc, e, lde, dots);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_bands(hipStream_t s, int nb, int64_t ng, const double2 *src, int64_t lds, double2 *dst,
+                             int64_t ldd)
+{
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_bands, dim3(nchunks(ng), nb), dim3(kVecThreads), 0, s, ng, src, lds, dst, ldd);
+    return hipGetLastError();
+}
+
+}  // namespace paro

@@ -1,0 +1,158 @@
+"""Host-side checks of libparo that need no GPU: the library loads, exports
+every function include/paro.h declares, and its host logic (sphere
+enumeration, grid rule, problem validation and error codes) is right."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "paro.h")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1702_04045_amd as P
+    P.load()
+    return P
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(paro_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol(P):
+    lib = P.load()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_1702_04045_amd import _lib
+    assert set(names) == set(_lib.SIGNATURES), "ctypes table and header disagree"
+    assert lib.paro_abi_version() == 1
+
+
+@pytest.mark.parametrize("cell,ecut", [
+    (np.eye(3) * 10.0, 10.0),
+    (np.eye(3) * 20.0, 20.0),
+    (np.diag([5.0, 6.5, 7.0]), 5.0),
+    (np.array([[5.0, 0, 0], [1.2, 5.5, 0], [0.3, -0.7, 6.0]]), 3.5),
+])
+def test_sphere_enumeration_matches_oracle(P, cell, ecut):
+    m, nm = P.sphere_enumerate(cell, ecut)
+    mo, nmo = oracle.sphere(cell, ecut)
+    assert np.array_equal(m, mo)
+    assert np.array_equal(nm, nmo)
+
+
+def test_grid_rule():
+    import paper_1702_04045_amd as P
+
+    def rule(n):
+        k = 4 * n + 1
+        while True:
+            r = k
+            while r % 2 == 0:
+                r //= 2
+            if r in (1, 3, 5):
+                return k
+            k += 1
+    for nmax in range(0, 45):
+        g = P.grid_size([nmax, nmax, nmax])
+        assert g[0] == rule(nmax) and g[0] >= 4 * nmax + 1
+    # the workloads' grids: 32 for n_max 7 and 96 for n_max 20
+    assert P.grid_size([7, 7, 7])[0] == 32 and P.grid_size([20, 20, 20])[0] == 96
+
+
+def _problem(P, cell, ecut, grid, miller=None, vloc=None, projs=()):
+    from paper_1702_04045_amd import _lib as L
+    from paper_1702_04045_amd.paro import _projectors
+    cell = np.ascontiguousarray(cell, np.float64).reshape(9)
+    if miller is None:
+        miller, _ = P.sphere_enumerate(cell, ecut)
+    miller = np.ascontiguousarray(miller, np.int32)
+    v = np.zeros((grid,) * 3) if vloc is None else np.ascontiguousarray(vloc, np.float64)
+    pa = _projectors(projs)
+    prob = L.Problem()
+    prob.cell[:] = list(cell)
+    prob.ecut = ecut
+    prob.grid[:] = list(v.shape)
+    prob.n_g = len(miller)
+    prob.miller = miller.ctypes.data_as(C.POINTER(C.c_int32))
+    prob.vloc = v.ctypes.data_as(C.POINTER(C.c_double))
+    prob.n_proj = len(projs)
+    prob.proj = pa if projs else None
+    keep = (cell, miller, v, pa)
+    return prob, keep
+
+
+def _plan_bytes(P, prob):
+    n = C.c_size_t()
+    rc = P.load().paro_plan_bytes(C.byref(prob), C.byref(n))
+    return rc, n.value
+
+
+def test_plan_validation_error_codes(P):
+    from paper_1702_04045_amd import _lib as L
+    cell = np.eye(3) * 10.0
+    prob, keep = _problem(P, cell, 10.0, 32)
+    rc, n = _plan_bytes(P, prob)
+    assert rc == L.PARO_OK and n > 0
+    # grid too small for the sphere (n_max = 7 needs >= 29 points)
+    prob2, keep2 = _problem(P, cell, 10.0, 24)
+    assert _plan_bytes(P, prob2)[0] == L.PARO_EALIAS
+    # Miller list out of canonical order
+    m, _ = P.sphere_enumerate(cell, 10.0)
+    prob3, keep3 = _problem(P, cell, 10.0, 32, miller=m[::-1].copy())
+    assert _plan_bytes(P, prob3)[0] == L.PARO_EINVAL
+    # Miller list of another cutoff
+    m4, _ = P.sphere_enumerate(cell, 9.0)
+    prob4, keep4 = _problem(P, cell, 10.0, 32, miller=m4)
+    assert _plan_bytes(P, prob4)[0] == L.PARO_EINVAL
+    # non-finite potential
+    v = np.zeros((32, 32, 32))
+    v[3, 4, 5] = np.nan
+    prob5, keep5 = _problem(P, cell, 10.0, 32, vloc=v)
+    assert _plan_bytes(P, prob5)[0] == L.PARO_EINVAL
+    # unsupported FFT length (36 = 4 * 9 is not 2^a {1,3,5})
+    prob6, keep6 = _problem(P, cell, 10.0, 36)
+    assert _plan_bytes(P, prob6)[0] == L.PARO_EUNSUP
+    # bad projector channel
+    prob7, keep7 = _problem(P, cell, 10.0, 32, projs=[dict(center=[0, 0, 0], l=2, m=0, width=1.0, d=0.1)])
+    assert _plan_bytes(P, prob7)[0] == L.PARO_EINVAL
+    prob8, keep8 = _problem(P, cell, 10.0, 32, projs=[dict(center=[0, 0, 0], l=0, m=0, width=0.0, d=0.1)])
+    assert _plan_bytes(P, prob8)[0] == L.PARO_EINVAL
+    # messages are set
+    assert P.load().paro_last_error()
+
+
+def test_sphere_enumerate_capacity_and_bad_input(P):
+    from paper_1702_04045_amd import _lib as L
+    lib = P.load()
+    cell = np.ascontiguousarray(np.eye(3) * 6.0).reshape(9)
+    ng = C.c_int64()
+    buf = np.zeros((4, 3), np.int32)
+    rc = lib.paro_sphere_enumerate(cell.ctypes.data_as(C.POINTER(C.c_double)), 4.0, 4,
+                                   buf.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(ng), None)
+    assert rc == L.PARO_ESIZE and ng.value > 4
+    rc = lib.paro_sphere_enumerate(cell.ctypes.data_as(C.POINTER(C.c_double)), -1.0, 0, None, C.byref(ng), None)
+    assert rc == L.PARO_EINVAL
+    sing = np.zeros(9)
+    rc = lib.paro_sphere_enumerate(sing.ctypes.data_as(C.POINTER(C.c_double)), 4.0, 0, None, C.byref(ng), None)
+    assert rc == L.PARO_EINVAL
+
+
+def test_workload_inputs_are_reproducible():
+    s = synth.WORKLOADS["c1"]
+    a = synth.make_cell(s, 3)
+    b = synth.make_cell(s, 3)
+    assert np.array_equal(a["positions"], b["positions"])
+    assert len(a["projectors"]) == 128
+    assert np.array_equal(synth.trial_block(100, 4, 3), synth.trial_block(100, 4, 3))

@@ -1,0 +1,331 @@
+"""GPU parity: libparo (HIP, gfx950) against the CPU oracle on the same seeded
+inputs.  Tolerances (FP64 everywhere):
+  H psi, projectors, kinetic table   max |diff| <= 1e-12 max |ref|
+  GEMMs on the matrix cores          max |diff| <= 1e-13 max |ref| (x sqrt K)
+  PCG iterates after n_cg steps      |du| <= 1e-9 |u| per band
+  Rayleigh-Ritz / ParO eigenvalues   |d eps| <= 1e-10 max(|eps|, 1 Ha)
+  Ritz subspaces (gapped clusters)   sin(angle) <= 1e-8
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+EIG_TOL = 1e-10
+SIN_TOL = 1e-8
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def make_case(spec, seed=0):
+    import paper_1702_04045_amd as P
+    c = synth.make_cell(spec, seed)
+    v = synth.vloc_on_grid(c["cell"], c["grid"], c["positions"], c["depths"], c["widths"])
+    h = oracle.Hamiltonian(c["cell"], c["ecut"], v, c["projectors"])
+    pl = P.Plan(c["cell"], c["ecut"], v, c["projectors"])
+    assert pl.ng == h.ng
+    return c, v, h, pl
+
+
+def to_dev(x):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def rel_err(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def subspace_sin(A, B):
+    """sin of the largest principal angle between the row spaces of A and B."""
+    Qa, _ = np.linalg.qr(A.T)
+    Qb, _ = np.linalg.qr(B.T)
+    return np.linalg.norm(Qa - Qb @ (Qb.conj().T @ Qa), 2)
+
+
+def gapped_clusters(eps, n, gap=1e-6):
+    """Index ranges [i, j) of the first n eigenvalues separated from the rest by > gap."""
+    out, i = [], 0
+    while i < n:
+        j = i + 1
+        while j < len(eps) and eps[j] - eps[j - 1] <= gap:
+            j += 1
+        if j <= n and (j == len(eps) or eps[j] - eps[j - 1] > gap):
+            out.append((i, j))
+        i = j
+    return out
+
+
+TINY = synth.small_cell(a=6.0, ecut=4.0, grid=16, n_atoms=2)
+C0 = synth.WORKLOADS["c0"]
+C1 = synth.WORKLOADS["c1"]
+
+
+# ---------------------------------------------------------------- building blocks
+
+@pytest.mark.parametrize("M,N,K", [(16, 16, 4), (37, 21, 1000), (128, 160, 34265), (1, 1, 3)])
+def test_zgemm_hn_vs_numpy(M, N, K):
+    import paper_1702_04045_amd as P
+    rng = np.random.default_rng(M + N + K)
+    A = rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))
+    B = rng.standard_normal((N, K)) + 1j * rng.standard_normal((N, K))
+    C = to_np(P.zgemm_hn(to_dev(A), to_dev(B)))
+    ref = (A.conj() @ B.T).T  # C[j][i] = sum_k conj(A_ik) B_jk
+    assert rel_err(C, ref) < 1e-13 * np.sqrt(K)
+
+
+@pytest.mark.parametrize("M,N,K", [(16, 16, 4), (1000, 33, 7), (34265, 160, 128), (5, 1, 1)])
+def test_zgemm_nn_vs_numpy(M, N, K):
+    import paper_1702_04045_amd as P
+    rng = np.random.default_rng(M + 7 * N + K)
+    A = rng.standard_normal((K, M)) + 1j * rng.standard_normal((K, M))  # rows = columns of A
+    B = rng.standard_normal((N, K)) + 1j * rng.standard_normal((N, K))
+    C0_ = rng.standard_normal((N, M)) + 1j * rng.standard_normal((N, M))
+    ref = (A.T @ B.T).T
+    C = to_np(P.zgemm_nn(to_dev(A), to_dev(B)))
+    assert rel_err(C, ref) < 1e-13 * np.sqrt(K)
+    C2 = to_np(P.zgemm_nn(to_dev(A), to_dev(B), to_dev(C0_), accumulate=True))
+    assert rel_err(C2, ref + C0_) < 1e-13 * np.sqrt(K)
+
+
+@pytest.mark.parametrize("m", [1, 2, 7, 64, 160, 333])
+def test_device_heev_vs_lapack(m):
+    import paper_1702_04045_amd as P
+    rng = np.random.default_rng(m)
+    A = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    A = A + A.conj().T
+    w, V = P.heev(to_dev(A))
+    w, V = to_np(w), to_np(V)
+    wr = np.linalg.eigvalsh(A)
+    nrm = np.abs(wr).max()
+    assert np.abs(w - wr).max() < 1e-13 * nrm * max(1, np.sqrt(m) / 4)
+    assert np.abs(A @ V - V * w).max() < 1e-11 * nrm
+    assert np.abs(V.conj().T @ V - np.eye(m)).max() < 1e-10
+
+
+def test_device_heev_degenerate():
+    import paper_1702_04045_amd as P
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.standard_normal((40, 40)) + 1j * rng.standard_normal((40, 40)))
+    d = np.repeat(np.arange(10, dtype=float), 4)
+    A = (Q * d) @ Q.conj().T
+    w, V = P.heev(to_dev(A))
+    w, V = to_np(w), to_np(V)
+    assert np.abs(w - d).max() < 1e-12
+    assert np.abs(A @ V - V * w).max() < 1e-11
+    assert np.abs(V.conj().T @ V - np.eye(40)).max() < 1e-10
+
+
+# ---------------------------------------------------------------- Hamiltonian
+
+@pytest.mark.parametrize("spec", [TINY, C0], ids=["tiny", "c0"])
+def test_plan_tables_match_oracle(spec):
+    c, v, h, pl = make_case(spec, 1)
+    assert np.array_equal(pl.miller, h.miller)
+    assert rel_err(to_np(pl.kinetic()), h.kin) < 1e-15
+    if pl.n_proj:
+        assert rel_err(to_np(pl.projectors()), h.beta) < 1e-12
+
+
+@pytest.mark.parametrize("spec,nb", [(TINY, 3), (C0, 8), (C0, 65), (C0, 1)], ids=["tiny", "c0", "c0_ragged65", "c0_1"])
+def test_apply_h_matches_oracle(spec, nb):
+    c, v, h, pl = make_case(spec, 2)
+    x = synth.trial_block(h.ng, nb, 5)
+    shift = np.linspace(-0.3, 0.2, nb)
+    ref = h.apply(x, shift)
+    got = to_np(pl.apply_h(to_dev(x), shift=to_dev(shift)))
+    assert rel_err(got, ref) < 1e-12
+    ref0 = h.apply(x)
+    got0 = to_np(pl.apply_h(to_dev(x)))
+    assert rel_err(got0, ref0) < 1e-12
+
+
+def test_apply_h_padded_leading_dimension():
+    torch = _torch()
+    c, v, h, pl = make_case(TINY, 3)
+    x = synth.trial_block(h.ng, 4, 1)
+    xd = torch.zeros((4, h.ng + 37), dtype=torch.complex128, device="cuda:0")
+    xd[:, :h.ng] = to_dev(x)
+    out = torch.full_like(xd, 7.0)
+    pl.apply_h(xd, out=out)
+    o = to_np(out)
+    assert rel_err(o[:, :h.ng], h.apply(x)) < 1e-12
+    assert np.all(o[:, h.ng:] == 7.0)  # padding untouched
+
+
+def test_apply_h_full_size_sampled_bands():
+    """The 34k-plane-wave cell with 128 projectors, 160 bands in one call (the
+    benchmark's launch shape); four bands compared with the oracle."""
+    c, v, h, pl = make_case(C1, 0)
+    nb = C1.n_carried
+    x = synth.trial_block(h.ng, nb, 0)
+    got = to_np(pl.apply_h(to_dev(x)))
+    idx = [0, 63, 64, nb - 1]
+    ref = h.apply(x[idx])
+    assert rel_err(got[idx], ref) < 1e-12
+    # Hermiticity of the device operator on two bands: <x0, H x1> = conj <x1, H x0>
+    a = np.vdot(x[0], got[1])
+    b = np.vdot(x[1], got[0])
+    assert abs(a - np.conj(b)) < 1e-11 * abs(a)
+
+
+def test_shift_lower_bound_matches_oracle():
+    for spec in (TINY, C0):
+        c, v, h, pl = make_case(spec, 4)
+        s = pl.shift_lower_bound()
+        assert abs(s - h.shift_bound()) < 1e-12 * max(1.0, abs(s))
+
+
+# ---------------------------------------------------------------- source problems
+
+@pytest.mark.parametrize("spec,nb,ncg", [(TINY, 4, 12), (C0, 8, 20)], ids=["tiny", "c0"])
+def test_source_solve_matches_oracle(spec, nb, ncg):
+    c, v, h, pl = make_case(spec, 5)
+    x = synth.trial_block(h.ng, nb, 2)
+    x /= np.linalg.norm(x, axis=1)[:, None]
+    hx = h.apply(x)
+    eps = np.einsum("bg,bg->b", x.conj(), hx).real
+    sigma = h.shift_bound()
+    sh = np.full(nb, sigma)
+    u_ref, f_ref = h.pcg(x, hx, eps, sh, ncg)
+    u, flags = pl.source_solve(to_dev(x), to_dev(hx), to_dev(eps), to_dev(sh), ncg)
+    u = to_np(u)
+    for b in range(nb):
+        assert np.linalg.norm(u[b] - u_ref[b]) <= 1e-9 * np.linalg.norm(u_ref[b])
+    assert np.array_equal(to_np(flags), f_ref)
+
+
+def test_source_solve_negative_curvature_flag():
+    import paper_1702_04045_amd as P
+    c, v, h, pl = make_case(TINY, 6)
+    x = synth.trial_block(h.ng, 2, 3)
+    hx = h.apply(x)
+    eps = np.zeros(2)
+    sh = np.full(2, 1e3)  # far above the spectrum: H - sigma is negative definite
+    u_ref, f_ref = h.pcg(x, hx, eps, sh, 4)
+    u, flags = pl.source_solve(to_dev(x), to_dev(hx), to_dev(eps), to_dev(sh), 4)
+    assert np.all(to_np(flags) & P.F_NEGCURV)
+    assert np.array_equal(to_np(flags), f_ref)
+    assert rel_err(to_np(u), u_ref) < 1e-12
+    assert pl.status() & P.F_NEGCURV
+    assert pl.status() == 0  # cleared by the read
+
+
+# ---------------------------------------------------------------- Rayleigh-Ritz
+
+@pytest.mark.parametrize("spec,m,nkeep", [(TINY, 6, 6), (C0, 16, 12)], ids=["tiny", "c0"])
+def test_rayleigh_ritz_matches_oracle(spec, m, nkeep):
+    c, v, h, pl = make_case(spec, 7)
+    U = synth.trial_block(h.ng, m, 4)
+    W = h.apply(U)
+    e_ref, p_ref, hp_ref, f = oracle.rayleigh_ritz(U, W, nkeep)
+    eps, psi, hpsi = pl.rayleigh_ritz(to_dev(U), to_dev(W), nkeep)
+    eps, psi, hpsi = to_np(eps), to_np(psi)[:, :h.ng], to_np(hpsi)[:, :h.ng]
+    assert np.abs(eps - e_ref).max() <= EIG_TOL * max(1.0, np.abs(e_ref).max())
+    assert np.abs(psi.conj() @ psi.T - np.eye(nkeep)).max() < 1e-10
+    for i, j in gapped_clusters(e_ref, nkeep):
+        assert subspace_sin(psi[i:j], p_ref[i:j]) < SIN_TOL
+    assert rel_err(hpsi, h.apply(psi)) < 1e-9
+
+
+# ---------------------------------------------------------------- ParO loop
+
+def test_paro_fixed_work_config_matches_oracle():
+    """The 1503-plane-wave cell: N = 8, 10 outer iterations x 20 PCG steps, fixed shift."""
+    c, v, h, pl = make_case(C0, 0)
+    nb = C0.n_carried
+    x = synth.trial_block(h.ng, nb, 0)
+    sigma = h.shift_bound()
+    ref = h.paro(x, C0.n_outer, C0.n_cg, sigma)
+    out = pl.iterate(to_dev(x), C0.n_outer, C0.n_cg, sigma)
+    st = to_np(out["stats"])
+    eh = st[:, :nb]
+    scale = np.maximum(np.abs(ref["eps_hist"]), 1.0)
+    assert np.all(np.abs(eh - ref["eps_hist"]) <= EIG_TOL * scale)
+    assert np.allclose(st[:, nb:2 * nb], ref["res_hist"], rtol=1e-6, atol=1e-10)
+    psi = to_np(out["psi"])[:, :h.ng]
+    for i, j in gapped_clusters(ref["eps"], nb):
+        assert subspace_sin(psi[i:j], ref["psi"][i:j]) < SIN_TOL
+    assert out["n_done"] == C0.n_outer
+    assert pl.status() == 0
+
+
+@pytest.mark.parametrize("variant,shift_mode", [(1, 1), (0, 1)], ids=["mparo_adaptive", "paro_adaptive"])
+def test_paro_variants_match_oracle(variant, shift_mode):
+    c, v, h, pl = make_case(C0, 1)
+    nb = 12
+    x = synth.trial_block(h.ng, nb, 1)
+    sigma = h.shift_bound()
+    ref = h.paro(x, 12, 10, sigma, variant=variant, shift_mode=shift_mode)
+    out = pl.iterate(to_dev(x), 12, 10, sigma, variant=variant, shift_mode=shift_mode)
+    st = to_np(out["stats"])
+    scale = np.maximum(np.abs(ref["eps_hist"]), 1.0)
+    assert np.all(np.abs(st[:, :nb] - ref["eps_hist"]) <= EIG_TOL * scale)
+    # row i holds the shift of outer iteration i
+    assert np.allclose(st[:-1, 2 * nb], ref["sigma_hist"], rtol=0, atol=1e-9)
+    psi = to_np(out["psi"])[:, :h.ng]
+    for i, j in gapped_clusters(ref["eps"], nb):
+        assert subspace_sin(psi[i:j], ref["psi"][i:j]) < SIN_TOL
+
+
+def test_paro_converges_to_dense_eigenvalues():
+    """MParO I with buffer bands reaches the dense-diagonalisation eigenvalues (1e-8 Ha)."""
+    c, v, h, pl = make_case(C0, 0)
+    lam = np.linalg.eigvalsh(h.dense())
+    nb = 16
+    x = synth.trial_block(h.ng, nb, 0)
+    out = pl.iterate(to_dev(x), 40, 10, h.shift_bound(), variant=1, shift_mode=1, n_conv=8, tol_res=1e-6)
+    eps = to_np(out["eps"])
+    assert np.abs(eps[:8] - lam[:8]).max() < 1e-8
+    assert out["n_done"] < 40
+
+
+def test_paro_full_size_properties():
+    """The 34k-plane-wave, 128-projector cell at the benchmark's launch shape
+    (160 bands, 20 PCG steps): two outer iterations; checks that hold at any
+    size: orthonormal Ritz vectors, H psi consistent with a fresh apply,
+    Ritz values above the Weyl bound and ascending,
+    residuals consistent with psi, no status flags."""
+    torch = _torch()
+    c, v, h, pl = make_case(C1, 0)
+    nb = C1.n_carried
+    x = synth.trial_block(h.ng, nb, 0)
+    sigma = pl.shift_lower_bound()
+    assert abs(sigma - h.shift_bound()) < 1e-12 * abs(sigma)
+    out = pl.iterate(to_dev(x), 2, C1.n_cg, sigma, variant=0, shift_mode=1)
+    psi, hpsi = out["psi"], out["hpsi"]
+    G = (psi.conj() @ psi.T).cpu().numpy()
+    assert np.abs(G - np.eye(nb)).max() < 1e-10
+    h2 = pl.apply_h(psi)
+    assert (h2 - hpsi).abs().max().item() < 1e-9 * hpsi.abs().max().item()
+    st = to_np(out["stats"])
+    eps_hist = st[:, :nb]
+    assert np.all(np.diff(eps_hist, axis=1) >= -1e-12)       # ascending
+    assert np.all(eps_hist[:, 0] > sigma)
+    res = to_np(pl.residual_norms(psi, hpsi, out["eps"]))
+    assert np.allclose(res, st[2, nb:2 * nb], rtol=1e-12, atol=0)
+    # two sampled bands against the oracle's own apply
+    p = to_np(psi)[[0, nb - 1], :h.ng]
+    assert rel_err(to_np(hpsi)[[0, nb - 1], :h.ng], h.apply(p)) < 1e-11
+    assert pl.status() == 0
+    torch.cuda.synchronize()
+
+
+def test_repeat_runs_are_bitwise_identical():
+    c, v, h, pl = make_case(C0, 2)
+    x = synth.trial_block(h.ng, 8, 2)
+    s = h.shift_bound()
+    a = pl.iterate(to_dev(x), 3, 8, s)
+    b = pl.iterate(to_dev(x), 3, 8, s)
+    assert (a["psi"] == b["psi"]).all().item()
+    assert (a["eps"] == b["eps"]).all().item()
