@@ -238,6 +238,24 @@ int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi, double *hpsi, int6
 /* Read and clear the sticky status bits (synchronises the plan's stream). */
 int32_t paro_get_status(paro_plan plan, int32_t *flags);
 
+/* ---------------------------------------------------------------- profiling */
+
+/* Kernel classes that can be timed with HIP events. */
+#define PARO_K_STICK_INV 1   /* sphere -> sticks, inverse transform along n3 */
+#define PARO_K_PLANE 2       /* z-plane stage: n2/n1 transforms and the V multiply */
+#define PARO_K_STICK_FWD 3   /* sticks -> sphere, forward transform along n3, kinetic term */
+#define PARO_K_GEMM_HN 4     /* split-K A^H B partial tiles */
+#define PARO_K_GEMM_NN 5     /* A B (+ C) */
+#define PARO_K_PCG_UPDATE 6  /* PCG vector update and preconditioner */
+
+/* Record a HIP event pair around every launch of one kernel class, on the
+ * stream it is launched on, for up to max_launches launches, until
+ * paro_profile_stop.  Process-wide (one class at a time); not thread-safe.
+ * paro_profile_stop synchronises the recorded events and returns the number
+ * of timed launches and their summed duration in milliseconds. */
+int32_t paro_profile_start(int32_t kernel, int32_t max_launches);
+int32_t paro_profile_stop(int32_t *launches, double *total_ms);
+
 /* ---------------------------------------------------------------- building blocks */
 
 /* Complex double GEMMs on the FP64 matrix cores, the products the hot

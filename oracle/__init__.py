@@ -68,7 +68,7 @@ def _load():
         "orc_cholesky": (C.c_int32, [C.c_int32, _vp]),
         "orc_rayleigh_ritz": (C.c_int32, [C.c_int64, C.c_int32, C.c_int32, _vp, _vp, _dp, _vp, _vp]),
         "orc_teter": (C.c_double, [C.c_double]),
-        "orc_pcg": (C.c_int32, [_vp, C.c_int32, _vp, _vp, _dp, _dp, C.c_int32, _vp, _ip, _dp]),
+        "orc_pcg": (C.c_int32, [_vp, C.c_int32, _vp, _vp, _dp, _dp, C.c_int32, C.c_int32, _vp, _ip, _dp]),
         "orc_nl_min_eig": (C.c_double, [_vp]),
         "orc_shift_bound": (C.c_double, [_vp]),
         "orc_paro": (C.c_int32, [_vp, C.c_int32, _vp, _vp, _dp, C.c_int32, C.c_int32, C.c_int32,
@@ -257,7 +257,7 @@ class Hamiltonian:
     def shift_bound(self):
         return float(self._lib.orc_shift_bound(self._h))
 
-    def pcg(self, psi, hpsi, eps, shift, ncg, gamma_hist=False):
+    def pcg(self, psi, hpsi, eps, shift, ncg, gamma_hist=False, correction=False):
         psi, hpsi = _cc(psi), _cc(hpsi)
         nb = psi.shape[0]
         eps = _cd(eps)
@@ -265,7 +265,7 @@ class Hamiltonian:
         u = np.zeros_like(psi)
         flags = np.zeros(nb, np.int32)
         gh = np.zeros((nb, ncg + 1)) if gamma_hist else None
-        self._lib.orc_pcg(self._h, nb, _v(psi), _v(hpsi), _d(eps), _d(sh), ncg, _v(u), _i(flags),
+        self._lib.orc_pcg(self._h, nb, _v(psi), _v(hpsi), _d(eps), _d(sh), ncg, int(correction), _v(u), _i(flags),
                           None if gh is None else _d(gh))
         return (u, flags, gh) if gamma_hist else (u, flags)
 

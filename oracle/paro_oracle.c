@@ -696,9 +696,13 @@ double orc_teter(double x)
 /* r0 = eps psi - H psi uses the carried H psi.                          */
 /* A band stops on p^H (H - sigma) p <= 0 (flag NEGCURV) or when         */
 /* r^H z <= 1e-26 r0^H z0.                                               */
+/* correction = 1: the correction equation of Algorithm 2, step 3,       */
+/*   (H - sigma_b) e_b = -(H psi_b - eps_b psi_b), from e = 0: the same   */
+/*   Krylov iteration (r0 is identical), the iterate is e = u - psi       */
+/*   accumulated directly instead of formed by a difference.             */
 /* ------------------------------------------------------------------ */
 static int32_t pcg_band(const orc_ham *h, const cplx *psi, const cplx *hpsi, double eps, double sigma,
-                        int ncg, cplx *u, cplx *r, cplx *z, cplx *p, cplx *q, cplx *work,
+                        int ncg, int correction, cplx *u, cplx *r, cplx *z, cplx *p, cplx *q, cplx *work,
                         double *gamma_hist)
 {
     int64_t ng = h->ng;
@@ -711,7 +715,7 @@ static int32_t pcg_band(const orc_ham *h, const cplx *psi, const cplx *hpsi, dou
     double tau = tkin / nrm;
     double gamma = 0;
     for (int64_t g = 0; g < ng; ++g) {
-        u[g] = psi[g];
+        u[g] = correction ? 0 : psi[g];
         r[g] = eps * psi[g] - hpsi[g];
         z[g] = orc_teter(h->kin[g] / tau) * r[g];
         p[g] = z[g];
@@ -744,7 +748,8 @@ static int32_t pcg_band(const orc_ham *h, const cplx *psi, const cplx *hpsi, dou
 }
 
 int32_t orc_pcg(const orc_ham *h, int32_t nb, const cplx *psi, const cplx *hpsi, const double *eps,
-                const double *shift, int32_t ncg, cplx *u, int32_t *flags, double *gamma_hist)
+                const double *shift, int32_t ncg, int32_t correction, cplx *u, int32_t *flags,
+                double *gamma_hist)
 {
     int64_t ng = h->ng, mtot = (int64_t)h->M[0] * h->M[1] * h->M[2];
     int32_t all = 0;
@@ -756,7 +761,7 @@ int32_t orc_pcg(const orc_ham *h, int32_t nb, const cplx *psi, const cplx *hpsi,
 #pragma omp for schedule(dynamic, 1)
         for (int b = 0; b < nb; ++b) {
             int32_t f = pcg_band(h, psi + (int64_t)b * ng, hpsi + (int64_t)b * ng, eps[b], shift[b], ncg,
-                                 u + (int64_t)b * ng, r, z, p, q, work,
+                                 correction, u + (int64_t)b * ng, r, z, p, q, work,
                                  gamma_hist ? gamma_hist + (int64_t)b * (ncg + 1) : NULL);
             if (flags) flags[b] = f;
             all |= f;
@@ -820,8 +825,8 @@ static void residual_norms(int64_t ng, int nb, const cplx *psi, const cplx *hpsi
 /* ParO at fixed cutoff and potential (Algorithm 1 with steps 1, 3, 4,  */
 /* 5; the cutoff is not raised).  variant 0: Algorithm 1, RR on the      */
 /* source solutions u; variant 1: Algorithm 2 (MParO I), RR on           */
-/* span{psi, e} with e = u - psi the solution of the correction          */
-/* equation (H - sigma) e = -(H psi - eps psi), normalised.              */
+/* span{psi, e} with e the solution of the correction equation         */
+/* (H - sigma) e = -(H psi - eps psi) (e = u - psi), normalised.          */
 /*                                                                       */
 /* psi: in the trial block, out the Ritz vectors (nb bands).             */
 /* shift_mode 0: sigma = sigma_lb for every step.                        */
@@ -858,22 +863,23 @@ int32_t orc_paro(const orc_ham *h, int32_t nb, cplx *psi, cplx *hpsi, double *ep
             double s = eps[0] - 0.05 - res[0];
             if (s > sigma) sigma = s;
         }
+        /* Algorithm 1: u into U[0:nb]; Algorithm 2: e into U[nb:2nb] */
+        cplx *sol = variant == 1 ? U + ng * nb : U;
         for (int attempt = 0; attempt < 2; ++attempt) {
             for (int b = 0; b < nb; ++b) sig[b] = sigma;
-            int32_t pf = orc_pcg(h, nb, psi, hpsi, eps, sig, ncg, U, fl, NULL);
+            int32_t pf = orc_pcg(h, nb, psi, hpsi, eps, sig, ncg, variant == 1, sol, fl, NULL);
             if ((pf & ORC_F_NEGCURV) && sigma != sigma_lb) { sigma = sigma_lb; all |= ORC_F_NEGCURV; continue; }
             all |= pf;
             break;
         }
         if (sigma_hist) sigma_hist[it] = sigma;
         if (variant == 1) {
-            /* U = [psi, e/|e|] with e = u - psi; W = [H psi, H e] */
+            /* U = [psi, e/|e|]; W = [H psi, H e] */
             cplx *E = U + ng * nb;
             for (int b = 0; b < nb; ++b) {
                 double s = 0;
                 for (int64_t g = 0; g < ng; ++g) {
-                    cplx d = U[(int64_t)b * ng + g] - psi[(int64_t)b * ng + g];
-                    E[(int64_t)b * ng + g] = d;
+                    cplx d = E[(int64_t)b * ng + g];
                     s += creal(d) * creal(d) + cimag(d) * cimag(d);
                 }
                 s = s > 0 ? 1.0 / sqrt(s) : 0.0;

@@ -15,6 +15,7 @@ PARO_OK, PARO_EINVAL, PARO_EALIAS, PARO_ESIZE, PARO_EHIP, PARO_EUNSUP = 0, -1, -
 F_NEGCURV, F_CHOL, F_NAN = 1, 2, 4
 SHIFT_FIXED, SHIFT_ADAPTIVE = 0, 1
 VARIANT_PARO, VARIANT_MPARO1 = 0, 1
+K_STICK_INV, K_PLANE, K_STICK_FWD, K_GEMM_HN, K_GEMM_NN, K_PCG_UPDATE = 1, 2, 3, 4, 5, 6
 
 ERRORS = {PARO_EINVAL: "EINVAL", PARO_EALIAS: "EALIAS", PARO_ESIZE: "ESIZE", PARO_EHIP: "EHIP",
           PARO_EUNSUP: "EUNSUP"}
@@ -77,6 +78,8 @@ SIGNATURES = {
                                   C.c_int64, _vp, _sz]),
     "paro_zgemm_nn": (C.c_int32, [_vp, C.c_int64, C.c_int32, C.c_int32, _vp, C.c_int64, _vp, C.c_int64, _vp,
                                   C.c_int64, C.c_int32]),
+    "paro_profile_start": (C.c_int32, [C.c_int32, C.c_int32]),
+    "paro_profile_stop": (C.c_int32, [_ip, C.POINTER(C.c_double)]),
     "paro_heev_workspace_bytes": (C.c_int32, [C.c_int32, C.POINTER(_sz)]),
     "paro_heev": (C.c_int32, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _sz]),
 }

@@ -29,7 +29,24 @@ template <int N> constexpr bool cfg_ok()
 
 constexpr int kStickThreads = 256;
 
-// Sphere -> sticks, inverse transform along n3.
+// Thread -> (line, thread-in-line) map: the T threads of a line are in one
+// wavefront, spaced 64/T lanes apart, so that 8 consecutive lanes work on 8
+// consecutive lines at the same element index.  Line strides are odd (N+1
+// elements) or 1, so those 8 lanes hit 8 different LDS bank groups in every
+// load and exchange, and stores of consecutive sticks are contiguous.
+template <int T> __device__ __forceinline__ int line_of(int tid)
+{
+    return (tid >> 6) * (64 / T) + (tid & 63) % (64 / T);
+}
+template <int T> __device__ __forceinline__ int thread_in_line(int tid) { return (tid & 63) / (64 / T); }
+
+// threads of the plane kernel: one line slot per row, rounded up to whole wavefronts
+template <int N> constexpr int plane_threads() { return (N * PlaneCfg<N>::T + 63) / 64 * 64; }
+constexpr int kPlanesPerBlock = 4;  // z-planes handled by one work-group of the plane kernel
+constexpr int kSticksPerThread = 4;  // stick values per thread staged in registers per plane
+
+// Sphere -> sticks, inverse transform along n3.  Line (stick) threads are
+// consecutive lanes, so the exchanges between passes are wavefront-local.
 // pbuf != null: PCG prologue, p <- z + beta p (first step: p <- z), the new p
 // is written back and transformed.  Otherwise src is transformed as is.
 template <int N3>
@@ -43,7 +60,7 @@ k_stick_inv(const double2 *__restrict__ src, int64_t ld, double2 *__restrict__ p
     static_assert(cfg_ok<N3>(), "bad FFT config");
     constexpr int T = C::T, E = C::E, S = kStickThreads / T, LD = N3 + 1;
     __shared__ double2 tile[S * LD];
-    const int tid = threadIdx.x, sl = tid % S, t = tid / S;
+    const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
     const int s0 = blockIdx.x * S, band = blockIdx.y;
     const int s = s0 + sl;
     const bool act = s < nst;
@@ -69,82 +86,138 @@ k_stick_inv(const double2 *__restrict__ src, int64_t ld, double2 *__restrict__ p
     double2 v[E];
     double2 *line = tile + sl * LD;
     if (act) pass_load<N3, T, E, ListInfo<typename C::Inv>::first>(v, t, [&](int i) { return line[i]; });
-    stockham<N3, +1>(typename C::Inv{}, v, t, act, line, 1, tw);
+    stockham<N3, +1, true>(typename C::Inv{}, v, t, act, line, 1, tw);
     double2 *out = sticks + (size_t)band * N3 * nst;
     if (act)
         final_foreach<N3, T, E, ListInfo<typename C::Inv>::last>(
             v, t, [&](int i, int e) { out[(size_t)i * nst + s] = v[e]; });
 }
 
-// One z-plane of one band: inverse along n2 (populated n1 columns), along n1
-// (all rows), times V, forward along n1, forward along n2; in place in the
-// stick buffer.
+// z-planes z0 .. z0 + kPlanesPerBlock - 1 of one band, one after the other:
+// inverse along n2 (populated n1 columns), along n1 (all rows), times V,
+// forward along n1, forward along n2; in place in the stick buffer.  Every
+// transform line is wavefront-local; work-group barriers separate only the
+// column, row and column stages.  The plane's stick values are loaded into
+// registers before the LDS is cleared, so their latency overlaps the clear;
+// the potential is stored in the order the row threads hold their values
+// (vperm[z][y][t][e]), so each thread reads E consecutive doubles.
 template <int N>
-__global__ void __launch_bounds__(N * FftCfg<N>::T)
+__global__ void __launch_bounds__(plane_threads<N>())
 k_plane(double2 *__restrict__ sticks, int nst, int N3, const int32_t *__restrict__ st_xy,
-        const double *__restrict__ vplane, int nmax1, const double2 *__restrict__ tw)
+        const double *__restrict__ vperm, int nmax1, const double2 *__restrict__ tw)
 {
-    using C = FftCfg<N>;
-    static_assert(cfg_ok<N>(), "bad FFT config");
+    using C = PlaneCfg<N>;
+    static_assert(C::T * C::E == N && ListInfo<typename C::Inv>::last == ListInfo<typename C::Fwd>::first,
+                  "bad plane FFT config");
     using Inv = typename C::Inv;
     using Fwd = typename C::Fwd;
-    constexpr int T = C::T, E = C::E, LDX = N + 1, NT = N * T;
+    constexpr int T = C::T, E = C::E, LDX = N + 1, NT = plane_threads<N>();
+    constexpr int RL = ListInfo<Inv>::last;
+    constexpr int SPT = kSticksPerThread;
     __shared__ double2 plane[N * LDX];
     const int tid = threadIdx.x;
-    const int z = blockIdx.x, band = blockIdx.y;
-    double2 *tz = sticks + ((size_t)band * N3 + z) * nst;
+    const int band = blockIdx.y;
+    const int z0 = blockIdx.x * kPlanesPerBlock;
+    const int z1 = min(z0 + kPlanesPerBlock, N3);
     const int ncol = 2 * nmax1 + 1;
-    for (int e = tid; e < ncol * N; e += NT) {
-        const int c = e / N, y = e - c * N;
-        int x = c - nmax1;
-        x += x < 0 ? N : 0;
-        plane[y * LDX + x] = make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    for (int s = tid; s < nst; s += NT) {
-        const int xy = st_xy[s];
-        plane[(xy >> 16) * LDX + (xy & 0xffff)] = tz[s];
-    }
-    __syncthreads();
-    const int slot = tid / T, t = tid % T;
+    const int slot = line_of<T>(tid), t = thread_in_line<T>(tid);
     int xcol = slot - nmax1;
     xcol += xcol < 0 ? N : 0;
     const bool colact = slot < ncol;
     double2 *col = plane + (colact ? xcol : 0);
-    double2 v[E];
-    // n2, inverse
-    if (colact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) { return col[i * LDX]; });
-    stockham<N, +1>(Inv{}, v, t, colact, col, LDX, tw);
-    __syncthreads();
-    if (colact) final_foreach<N, T, E, ListInfo<Inv>::last>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
-    __syncthreads();
-    // n1 rows: inverse, multiply by V, forward
-    {
-        const int y = slot;
-        double2 *row = plane + y * LDX;
-        pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
+    const bool rowact = slot < N;
+    double2 *row = plane + (rowact ? slot : 0) * LDX;
+    const bool inreg = nst <= SPT * NT;  // all sticks of a plane fit in SPT registers per thread
+    int xy[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) xy[k] = (inreg && tid + k * NT < nst) ? st_xy[tid + k * NT] : 0;
+    for (int z = z0; z < z1; ++z) {
+        double2 *tz = sticks + ((size_t)band * N3 + z) * nst;
+        double2 sv[SPT];
+        if (inreg) {
+#pragma unroll
+            for (int k = 0; k < SPT; ++k) sv[k] = tid + k * NT < nst ? tz[tid + k * NT] : make_double2(0.0, 0.0);
+        }
+        for (int e = tid; e < ncol * N; e += NT) {
+            const int c = e / N, y = e - c * N;
+            int x = c - nmax1;
+            x += x < 0 ? N : 0;
+            plane[y * LDX + x] = make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        if (inreg) {
+#pragma unroll
+            for (int k = 0; k < SPT; ++k)
+                if (tid + k * NT < nst) plane[(xy[k] >> 16) * LDX + (xy[k] & 0xffff)] = sv[k];
+        } else {
+            for (int s = tid; s < nst; s += NT) {
+                const int q = st_xy[s];
+                plane[(q >> 16) * LDX + (q & 0xffff)] = tz[s];
+            }
+        }
+        __syncthreads();
+        double2 v[E];
+        // n2, inverse
+        if (colact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) { return col[i * LDX]; });
+        stockham_c<C, +1, true>(Inv{}, v, t, colact, col, LDX, tw);
+        wave_lds_sync();
+        if (colact) final_foreach<N, T, E, RL>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
+        __syncthreads();
+        // n1 rows: inverse, multiply by V, forward.  The potential values at
+        // the positions this thread holds after the inverse pass are loaded
+        // first so that their latency overlaps the inverse transform.
+        double vr[E];
+        const double *vp = vperm + (((size_t)z * N + (rowact ? slot : 0)) * T + t) * E;
+#pragma unroll
+        for (int e = 0; e < E; ++e) vr[e] = vp[e];
+        if (rowact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
             return (i <= nmax1 || i >= N - nmax1) ? row[i] : make_double2(0.0, 0.0);
         });
-        stockham<N, +1>(Inv{}, v, t, true, row, 1, tw);
-        const double *vrow = vplane + ((size_t)z * N + y) * N;
-        final_foreach<N, T, E, ListInfo<Inv>::last>(v, t, [&](int i, int e) { v[e] = cscale(v[e], vrow[i]); });
-        stockham<N, -1>(Fwd{}, v, t, true, row, 1, tw);
-        __syncthreads();
-        final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
+        stockham_c<C, +1, true>(Inv{}, v, t, rowact, row, 1, tw);
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vr[e]);
+        stockham_c<C, -1, true>(Fwd{}, v, t, rowact, row, 1, tw);
+        wave_lds_sync();
+        if (rowact) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
             if (i <= nmax1 || i >= N - nmax1) row[i] = v[e];
         });
         __syncthreads();
+        // n2, forward
+        if (colact) pass_load<N, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return col[i * LDX]; });
+        stockham_c<C, -1, true>(Fwd{}, v, t, colact, col, LDX, tw);
+        wave_lds_sync();
+        if (colact) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
+        __syncthreads();
+        if (inreg) {
+#pragma unroll
+            for (int k = 0; k < SPT; ++k)
+                if (tid + k * NT < nst) tz[tid + k * NT] = plane[(xy[k] >> 16) * LDX + (xy[k] & 0xffff)];
+        } else {
+            for (int s = tid; s < nst; s += NT) {
+                const int q = st_xy[s];
+                tz[s] = plane[(q >> 16) * LDX + (q & 0xffff)];
+            }
+        }
+        __syncthreads();
     }
-    // n2, forward
-    if (colact) pass_load<N, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return col[i * LDX]; });
-    stockham<N, -1>(Fwd{}, v, t, colact, col, LDX, tw);
-    __syncthreads();
-    if (colact) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
-    __syncthreads();
-    for (int s = tid; s < nst; s += NT) {
-        const int xy = st_xy[s];
-        tz[s] = plane[(xy >> 16) * LDX + (xy & 0xffff)];
-    }
+}
+
+// Potential in the row-thread order of k_plane<N>: out[((z N + y) T + t) E + e]
+// = V(i1 = x(t, e), i2 = y, i3 = z), x(t, e) = t + T (e / RL) + (e % RL)(N / RL),
+// from vloc in C order [i1][i2][i3].
+template <int N>
+void plane_potential(const int32_t *grid, const double *vloc, double *out)
+{
+    using C = PlaneCfg<N>;
+    constexpr int T = C::T, E = C::E, RL = ListInfo<typename C::Inv>::last;
+    const int N2 = grid[1], N3 = grid[2];
+    for (int z = 0; z < N3; ++z)
+        for (int y = 0; y < N2; ++y)
+            for (int t = 0; t < T; ++t)
+                for (int e = 0; e < E; ++e) {
+                    const int x = t + T * (e / RL) + (e % RL) * (N / RL);
+                    out[(((size_t)z * N + y) * T + t) * E + e] = vloc[((size_t)x * N2 + y) * N3 + z];
+                }
 }
 
 // Sticks -> sphere, forward transform along n3, then
@@ -162,7 +235,7 @@ k_stick_fwd(const double2 *__restrict__ sticks, int nst, const int32_t *__restri
     constexpr int T = C::T, E = C::E, S = kStickThreads / T, LD = N3 + 1;
     __shared__ double2 tile[S * LD];
     __shared__ double red[kStickThreads / 64];
-    const int tid = threadIdx.x, sl = tid % S, t = tid / S;
+    const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
     const int s0 = blockIdx.x * S, band = blockIdx.y;
     const int s = s0 + sl;
     const bool act = s < nst;
@@ -170,8 +243,8 @@ k_stick_fwd(const double2 *__restrict__ sticks, int nst, const int32_t *__restri
     double2 v[E];
     double2 *line = tile + sl * LD;
     if (act) pass_load<N3, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return in[(size_t)i * nst + s]; });
-    stockham<N3, -1>(Fwd{}, v, t, act, line, 1, tw);
-    __syncthreads();
+    stockham<N3, -1, true>(Fwd{}, v, t, act, line, 1, tw);
+    wave_lds_sync();
     if (act) final_foreach<N3, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) { line[i] = v[e]; });
     __syncthreads();
     const int p0 = st_start[s0], p1 = st_start[min(s0 + S, nst)];
@@ -206,16 +279,23 @@ hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const double2 *
     const double scale = 1.0 / ((double)pl.grid[0] * pl.grid[1] * pl.grid[2]);
     for (int c0 = 0; c0 < nb; c0 += kMaxBandsPerChunk) {
         const int cb = min(kMaxBandsPerChunk, nb - c0);
+        prof_mark(PARO_K_STICK_INV, pl.stream, true);
         hipLaunchKernelGGL(k_stick_inv<N>, dim3(ntiles, cb), dim3(kStickThreads), 0, pl.stream,
                            src + c0 * ld, ld, pbuf ? pbuf + c0 * ld : nullptr, beta ? beta + c0 : nullptr,
                            first ? 1 : 0, w.sticks, pl.nst, pl.st_start, pl.pt_sz, pl.tw[2]);
-        hipLaunchKernelGGL(k_plane<N>, dim3(N3, cb), dim3(N * FftCfg<N>::T), 0, pl.stream, w.sticks, pl.nst, N3,
-                           pl.st_xy, pl.vplane, pl.nmax[0], pl.tw[0]);
+        prof_mark(PARO_K_STICK_INV, pl.stream, false);
+        prof_mark(PARO_K_PLANE, pl.stream, true);
+        hipLaunchKernelGGL(k_plane<N>, dim3((N3 + kPlanesPerBlock - 1) / kPlanesPerBlock, cb),
+                           dim3(plane_threads<N>()), 0, pl.stream, w.sticks, pl.nst, N3, pl.st_xy, pl.vplane,
+                           pl.nmax[0], pl.tw[0]);
+        prof_mark(PARO_K_PLANE, pl.stream, false);
         const double2 *x = pbuf ? pbuf : src;
+        prof_mark(PARO_K_STICK_FWD, pl.stream, true);
         hipLaunchKernelGGL(k_stick_fwd<N>, dim3(ntiles, cb), dim3(kStickThreads), 0, pl.stream, w.sticks, pl.nst,
                            pl.st_start, pl.pt_sz, pl.tw[2], x + c0 * ld, ld, out + c0 * ld, pl.kin,
                            shift ? shift + c0 : nullptr, scale, dot_part ? dot_part + (size_t)c0 * kMaxParts : nullptr,
                            kMaxParts);
+        prof_mark(PARO_K_STICK_FWD, pl.stream, false);
     }
     return hipGetLastError();
 }
@@ -227,6 +307,18 @@ bool fft_supported(int n)
     switch (n) {
     case 8: case 16: case 24: case 32: case 40: case 48: case 64: case 80: case 96: return true;
     default: return false;
+    }
+}
+
+void build_plane_potential(int n, const int32_t *grid, const double *vloc, double *out)
+{
+    switch (n) {
+#define PARO_CASE(k) \
+    case k: plane_potential<k>(grid, vloc, out); break;
+    PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
+    PARO_CASE(80) PARO_CASE(96)
+#undef PARO_CASE
+    default: break;
     }
 }
 

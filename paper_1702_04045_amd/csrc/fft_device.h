@@ -213,15 +213,15 @@ template <int R, int... Rs> struct LastOf<R, Rs...> { static constexpr int value
 // FftCfg<N>: T threads per line, E = N / T elements each, radix list Inv
 // (used for SIGN = +1) and its reverse Fwd (SIGN = -1).
 template <int N> struct FftCfg;
-template <> struct FftCfg<8> { static constexpr int T = 2, E = 4; using Inv = RList<4, 2>; using Fwd = RList<2, 4>; };
-template <> struct FftCfg<16> { static constexpr int T = 4, E = 4; using Inv = RList<4, 4>; using Fwd = RList<4, 4>; };
-template <> struct FftCfg<24> { static constexpr int T = 2, E = 12; using Inv = RList<6, 4>; using Fwd = RList<4, 6>; };
-template <> struct FftCfg<32> { static constexpr int T = 4, E = 8; using Inv = RList<8, 4>; using Fwd = RList<4, 8>; };
-template <> struct FftCfg<40> { static constexpr int T = 2, E = 20; using Inv = RList<10, 4>; using Fwd = RList<4, 10>; };
-template <> struct FftCfg<48> { static constexpr int T = 4, E = 12; using Inv = RList<12, 4>; using Fwd = RList<4, 12>; };
-template <> struct FftCfg<64> { static constexpr int T = 8, E = 8; using Inv = RList<8, 8>; using Fwd = RList<8, 8>; };
-template <> struct FftCfg<80> { static constexpr int T = 4, E = 20; using Inv = RList<5, 4, 4>; using Fwd = RList<4, 4, 5>; };
-template <> struct FftCfg<96> { static constexpr int T = 8, E = 12; using Inv = RList<6, 4, 4>; using Fwd = RList<4, 4, 6>; };
+template <> struct FftCfg<8> { static constexpr int N = 8, T = 2, E = 4; using Inv = RList<4, 2>; using Fwd = RList<2, 4>; };
+template <> struct FftCfg<16> { static constexpr int N = 16, T = 4, E = 4; using Inv = RList<4, 4>; using Fwd = RList<4, 4>; };
+template <> struct FftCfg<24> { static constexpr int N = 24, T = 2, E = 12; using Inv = RList<6, 4>; using Fwd = RList<4, 6>; };
+template <> struct FftCfg<32> { static constexpr int N = 32, T = 4, E = 8; using Inv = RList<8, 4>; using Fwd = RList<4, 8>; };
+template <> struct FftCfg<40> { static constexpr int N = 40, T = 2, E = 20; using Inv = RList<10, 4>; using Fwd = RList<4, 10>; };
+template <> struct FftCfg<48> { static constexpr int N = 48, T = 4, E = 12; using Inv = RList<12, 4>; using Fwd = RList<4, 12>; };
+template <> struct FftCfg<64> { static constexpr int N = 64, T = 8, E = 8; using Inv = RList<8, 8>; using Fwd = RList<8, 8>; };
+template <> struct FftCfg<80> { static constexpr int N = 80, T = 4, E = 20; using Inv = RList<5, 4, 4>; using Fwd = RList<4, 4, 5>; };
+template <> struct FftCfg<96> { static constexpr int N = 96, T = 8, E = 12; using Inv = RList<6, 4, 4>; using Fwd = RList<4, 4, 6>; };
 
 template <class L> struct ListInfo;
 template <int... Rs> struct ListInfo<RList<Rs...>> {
@@ -282,30 +282,77 @@ __device__ __forceinline__ void pass_compute(double2 (&v)[E], int t, const doubl
     }
 }
 
-template <int N, int T, int E, int SIGN, int NS, int R, int... Rest>
-__device__ __forceinline__ void stockham_rec(double2 (&v)[E], int t, bool act, double2 *line, int es,
-                                             const double2 *__restrict__ tw)
+// Order LDS accesses between the lanes of one wavefront: every line of a
+// transform lives inside one wavefront (T divides 64 and line threads are
+// consecutive lanes), so exchanges between passes need no work-group
+// barrier.  LDS operations of a wavefront complete in order; the wait and
+// the fences keep the compiler from moving loads above the stores.
+__device__ __forceinline__ void wave_lds_sync()
 {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool WL> __device__ __forceinline__ void line_sync()
+{
+    if constexpr (WL) wave_lds_sync();
+    else __syncthreads();
+}
+
+template <int N, int T, int E, int SIGN, bool WL, int NS, int R, int... Rest>
+__device__ __forceinline__ void stockham_rec(double2 (&v)[E], int t, bool act, double2 *line, int es,
+                                             const double2 *tw)
+{
+    // A fresh copy of the table pointer per pass keeps the compiler from
+    // loading the twiddles of later passes (or other transforms) up front,
+    // which costs registers; without work-group barriers nothing else
+    // bounds that code motion.
+    if constexpr (NS > 1) asm volatile("" : "+s"(tw));
     if (act) pass_compute<N, T, E, R, NS, SIGN>(v, t, tw);
     if constexpr (sizeof...(Rest) > 0) {
         constexpr int R2 = FirstOf<Rest...>::value;
-        __syncthreads();
+        line_sync<WL>();
         if (act) pass_store<N, T, E, R, NS>(v, t, [&](int i, double2 x) { line[i * es] = x; });
-        __syncthreads();
+        line_sync<WL>();
         if (act) pass_load<N, T, E, R2>(v, t, [&](int i) { return line[i * es]; });
-        stockham_rec<N, T, E, SIGN, NS * R, Rest...>(v, t, act, line, es, tw);
+        stockham_rec<N, T, E, SIGN, WL, NS * R, Rest...>(v, t, act, line, es, tw);
     }
 }
 
 // Run all passes of list L on registers v that hold the inputs of its first
-// pass.  Every thread of the block must call this (it contains barriers);
-// act = false threads only take part in the barriers.  line/es: this
-// thread's line in LDS, used for the exchanges between passes.
-template <int N, int SIGN, int... Rs>
-__device__ __forceinline__ void stockham(RList<Rs...>, double2 (&v)[FftCfg<N>::E], int t, bool act,
+// pass, for a line schedule Cfg (N, T threads per line, E elements each).
+// line/es: this thread's line in LDS, used for the exchanges between
+// passes.  WL = false: every thread of the block must call this (it
+// contains work-group barriers; act = false threads only take part in
+// them).  WL = true: the T threads of each line are consecutive lanes of one
+// wavefront and only wavefront-level ordering is used.
+template <class Cfg, int SIGN, bool WL = false, int... Rs>
+__device__ __forceinline__ void stockham_c(RList<Rs...>, double2 (&v)[Cfg::E], int t, bool act, double2 *line,
+                                           int es, const double2 *__restrict__ tw)
+{
+    static_assert(!WL || 64 % Cfg::T == 0, "wave-local lines need T | 64");
+    const double2 *twl = tw;
+    asm volatile("" : "+s"(twl));
+    stockham_rec<Cfg::N, Cfg::T, Cfg::E, SIGN, WL, 1, Rs...>(v, t, act, line, es, twl);
+}
+
+template <int N, int SIGN, bool WL = false, int... Rs>
+__device__ __forceinline__ void stockham(RList<Rs...> l, double2 (&v)[FftCfg<N>::E], int t, bool act,
                                          double2 *line, int es, const double2 *__restrict__ tw)
 {
-    stockham_rec<N, FftCfg<N>::T, FftCfg<N>::E, SIGN, 1, Rs...>(v, t, act, line, es, tw);
+    stockham_c<FftCfg<N>, SIGN, WL>(l, v, t, act, line, es, tw);
 }
+
+// Line schedule of the z-plane kernel (defaults to FftCfg).  For 96 points
+// two passes (12 x 8, one LDS exchange) on 4 threads per line measured
+// faster than three passes on 8 threads.
+template <int N> struct PlaneCfg : FftCfg<N> {};
+template <> struct PlaneCfg<96> {
+    static constexpr int N = 96, T = 4, E = 24;
+    using Inv = RList<12, 8>;
+    using Fwd = RList<8, 12>;
+};
 
 }  // namespace paro

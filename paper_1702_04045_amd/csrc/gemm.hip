@@ -3,7 +3,7 @@
 //
 // Every complex product is four real v_mfma_f64_16x16x4f64 products.  For
 // that instruction lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
-// (a 16 x 4 by 4 x 16 step) and holds D[4 (l / 16) + v][l % 16], v < 4.
+// (a 16 x 4 by 4 x 16 step) and holds D[l / 16 + 4 v][l % 16], v < 4.
 //
 // gemm_hn: C = A^H B with a long contraction (projector coefficients
 // P = B^H psi, Gram matrices U^H U and U^H W of Rayleigh-Ritz).  The
@@ -79,7 +79,7 @@ k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, const double2 *__restric
         for (int w = 0; w < 2; ++w)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = i0 + u * 16 + 4 * lk + v;
+                const int i = i0 + u * 16 + lk + 4 * v;
                 const int j = j0 + w * 16 + l16;
                 if (i < M && j < N) P[(size_t)j * M + i] = make_double2(re[u][w][v], im[u][w][v]);
             }
@@ -159,7 +159,7 @@ k_gemm_nn(int64_t M, int N, int K, const double2 *__restrict__ A, int64_t lda, c
         for (int w = 0; w < 2; ++w)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int n = n0 + u * 16 + 4 * lk + v;
+                const int n = n0 + u * 16 + lk + 4 * v;
                 const int64_t g = g0 + w * 16 + l16;
                 if (n < N && g < M) {
                     double2 *c = C + (int64_t)n * ldc + g;
@@ -236,8 +236,10 @@ hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const double2 *A, int
     kchunk = (kchunk + 3) / 4 * 4;
     nsplit = (K + kchunk - 1) / kchunk;
     if (nsplit < 1) nsplit = 1;
+    prof_mark(PARO_K_GEMM_HN, s, true);
     hipLaunchKernelGGL(k_gemm_hn_part, dim3(tm, tn, nsplit), dim3(256), 0, s, M, N, K, kchunk, A, lda, B, ldb,
                        part);
+    prof_mark(PARO_K_GEMM_HN, s, false);
     hipLaunchKernelGGL(k_gemm_hn_reduce, dim3(N), dim3(256), 0, s, M, N, (int)nsplit, part, C, ldc, dscale, quad);
     return hipGetLastError();
 }
@@ -247,7 +249,9 @@ hipError_t gemm_nn(hipStream_t s, int64_t M, int N, int K, const double2 *A, int
 {
     if (M <= 0 || N <= 0) return hipSuccess;
     dim3 grid((unsigned)((M + kTile - 1) / kTile), (N + kTile - 1) / kTile);
+    prof_mark(PARO_K_GEMM_NN, s, true);
     hipLaunchKernelGGL(k_gemm_nn, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, accumulate ? 1 : 0);
+    prof_mark(PARO_K_GEMM_NN, s, false);
     return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ struct Plan {
     int32_t *pt_sz = nullptr;     // per sphere point: (stick << 8) | (n3 mod N3)
     int32_t *st_start = nullptr;  // per stick: first sphere point, nst + 1
     int32_t *st_xy = nullptr;     // per stick: (n1 mod N1) | (n2 mod N2) << 16
-    double *vplane = nullptr;     // local potential, plane-major [i3][i2][i1]
+    double *vplane = nullptr;     // local potential in the plane kernel's row-thread order
     double2 *tw[3] = {nullptr, nullptr, nullptr};  // exp(-2 pi i m / N_d)
     double2 *beta = nullptr;      // KB projectors, nproj x ldv (projector-major)
     double *dkb = nullptr;        // KB energies
@@ -61,6 +61,8 @@ Workspace carve_workspace(const Plan &pl, int nb, void *ws);
 size_t dense_real_elems(int mmax);
 
 void set_error(const std::string &msg);
+// HIP event pair around launches of the kernel class being profiled (no-op otherwise)
+void prof_mark(int kernel, hipStream_t s, bool begin);
 #define PARO_HIP_TRY(expr)                                                      \
     do {                                                                        \
         hipError_t _e = (expr);                                                 \
@@ -73,6 +75,8 @@ void set_error(const std::string &msg);
 // ---- launchers (return the hipError_t of the launches) ----
 // apply.hip
 bool fft_supported(int n);
+// the local potential re-laid in the order the plane kernel's row threads use it
+void build_plane_potential(int n, const int32_t *grid, const double *vloc, double *out);
 // Local part on nb bands: out_b = FFT^-1 (V FFT(x_b)) / N + (kin - shift_b) x_b,
 // x = src, or in PCG mode (pbuf != null) x = p with p <- z + beta_b p first
 // (first: p <- z) and src = z; dot_part then gets partial Re(x^H out).
@@ -89,13 +93,13 @@ hipError_t launch_build_projectors(const Plan &pl, const int32_t *miller_dev, co
                                    const int32_t *lm, const double *widths);
 // vec.hip
 hipError_t launch_pcg_init(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
-                           int64_t ld, const double *eps, double2 *u, int64_t ldu, int32_t *band_flags);
+                           int64_t ld, const double *eps, double2 *u, int64_t ldu, int32_t *band_flags,
+                           bool correction);
 hipError_t launch_pcg_update(const Plan &pl, const Workspace &w, int nb, double2 *u, int64_t ldu, int npq,
                              int32_t *band_flags);
 hipError_t launch_residuals(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
                             int64_t ld, const double *eps, double *res);
-hipError_t launch_mparo_correction(const Plan &pl, const Workspace &w, int nb, const double2 *psi, int64_t ld,
-                                   double2 *e, int64_t lde);
+hipError_t launch_normalize_bands(const Plan &pl, const Workspace &w, int nb, double2 *e, int64_t lde);
 hipError_t launch_copy_bands(hipStream_t s, int nb, int64_t ng, const double2 *src, int64_t lds, double2 *dst,
                              int64_t ldd);
 // dense.hip

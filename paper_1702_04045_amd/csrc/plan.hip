@@ -13,6 +13,26 @@ namespace paro {
 static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
+struct Profiler {
+    int kernel = 0, cap = 0, used = 0;
+    bool skip = false;
+    std::vector<hipEvent_t> ev;
+};
+static Profiler *g_prof = nullptr;
+
+void prof_mark(int kernel, hipStream_t s, bool begin)
+{
+    Profiler *p = g_prof;
+    if (!p || p->kernel != kernel) return;
+    if (begin) {
+        p->skip = p->used >= p->cap;
+        if (!p->skip) (void)hipEventRecord(p->ev[2 * p->used], s);
+    } else if (!p->skip) {
+        (void)hipEventRecord(p->ev[2 * p->used + 1], s);
+        ++p->used;
+    }
+}
+
 static int32_t fail(int32_t code, const std::string &msg)
 {
     set_error(msg);
@@ -347,13 +367,8 @@ int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes, 
     const size_t nv = (size_t)N1 * N2 * N3;
     std::vector<double> vpl(nv);
     double vmin = prob->vloc[0];
-    for (int i1 = 0; i1 < N1; ++i1)
-        for (int i2 = 0; i2 < N2; ++i2)
-            for (int i3 = 0; i3 < N3; ++i3) {
-                const double v = prob->vloc[((size_t)i1 * N2 + i2) * N3 + i3];
-                vpl[((size_t)i3 * N2 + i2) * N1 + i1] = v;
-                vmin = std::min(vmin, v);
-            }
+    for (size_t i = 0; i < nv; ++i) vmin = std::min(vmin, prob->vloc[i]);
+    build_plane_potential(N1, pl.grid, prob->vloc, vpl.data());
     pl.vmin = vmin;
     std::vector<double2> tw[3];
     for (int d = 0; d < 3; ++d) {
@@ -451,6 +466,51 @@ int32_t paro_get_projectors(paro_plan plan, double *beta_dev)
     PARO_HIP_TRY(hipMemcpy2DAsync(beta_dev, sizeof(double2) * pl.ng, pl.beta, sizeof(double2) * pl.ldv,
                                   sizeof(double2) * pl.ng, pl.nproj, hipMemcpyDeviceToDevice, pl.stream));
     return PARO_OK;
+}
+
+int32_t paro_profile_start(int32_t kernel, int32_t max_launches)
+{
+    if (kernel < PARO_K_STICK_INV || kernel > PARO_K_PCG_UPDATE || max_launches <= 0 || max_launches > (1 << 20))
+        return fail(PARO_EINVAL, "paro_profile_start: bad kernel class or launch count");
+    if (g_prof) return fail(PARO_EINVAL, "paro_profile_start: a profile is already running");
+    Profiler *p = new (std::nothrow) Profiler();
+    if (!p) return fail(PARO_EINVAL, "out of host memory");
+    p->kernel = kernel;
+    p->cap = max_launches;
+    p->ev.resize(2 * (size_t)max_launches);
+    for (auto &e : p->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &f : p->ev)
+                if (f) (void)hipEventDestroy(f);
+            delete p;
+            return fail(PARO_EHIP, "paro_profile_start: hipEventCreate failed");
+        }
+    }
+    g_prof = p;
+    return PARO_OK;
+}
+
+int32_t paro_profile_stop(int32_t *launches, double *total_ms)
+{
+    Profiler *p = g_prof;
+    if (!p) return fail(PARO_EINVAL, "paro_profile_stop: no profile running");
+    g_prof = nullptr;
+    double tot = 0.0;
+    int32_t rc = PARO_OK;
+    for (int i = 0; i < p->used; ++i) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p->ev[2 * i + 1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, p->ev[2 * i], p->ev[2 * i + 1]) != hipSuccess) {
+            rc = fail(PARO_EHIP, "paro_profile_stop: event query failed");
+            break;
+        }
+        tot += ms;
+    }
+    if (launches) *launches = p->used;
+    if (total_ms) *total_ms = tot;
+    for (auto &e : p->ev) (void)hipEventDestroy(e);
+    delete p;
+    return rc;
 }
 
 int32_t paro_get_status(paro_plan plan, int32_t *flags)

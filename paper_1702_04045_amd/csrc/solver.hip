@@ -22,9 +22,9 @@ static hipError_t apply_full(const Plan &pl, const Workspace &w, int nb, const d
 
 static hipError_t source_solve(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
                                int64_t ld, const double *eps, const double *shift, int ncg, double2 *u, int64_t ldu,
-                               int32_t *band_flags)
+                               int32_t *band_flags, bool correction = false)
 {
-    hipError_t e = launch_pcg_init(pl, w, nb, psi, hpsi, ld, eps, u, ldu, band_flags);
+    hipError_t e = launch_pcg_init(pl, w, nb, psi, hpsi, ld, eps, u, ldu, band_flags, correction);
     double *pq_parts = w.dots + (size_t)DOT_PQ * nb * kMaxParts;
     for (int k = 1; k <= ncg && e == hipSuccess; ++k) {
         int npq = 0;
@@ -221,10 +221,10 @@ int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi_, double *hpsi_, in
             if (c) break;
         }
         const bool mparo = opts->variant == PARO_VARIANT_MPARO1;
-        double2 *Ut = mparo ? w.U + (size_t)nb * lv : w.U;  // where the source solutions go
+        double2 *Ut = mparo ? w.U + (size_t)nb * lv : w.U;  // u (Algorithm 1) or e (Algorithm 2)
         for (int attempt = 0; attempt < 2; ++attempt) {
             PARO_CHECK_LAUNCH(source_solve(pl, w, nb, psi, hpsi, ld, eps, w.sig_all, opts->n_cg, Ut, lv,
-                                           w.iflags + nb));
+                                           w.iflags + nb, mparo));
             if (opts->shift_mode != PARO_SHIFT_ADAPTIVE) break;
             // on negative curvature redo the source problems with sigma_lb
             double scur = 0.0;
@@ -240,8 +240,8 @@ int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi_, double *hpsi_, in
             PARO_CHECK_LAUNCH(launch_bookkeeping(pl, nb, fixed, eps, w.res, w.sig_all, sigma, nullptr, conv));
         }
         if (mparo) {
-            // span{psi, e}, e = (u - psi)/|u - psi| (Algorithm 2)
-            PARO_CHECK_LAUNCH(launch_mparo_correction(pl, w, nb, psi, ld, Ut, lv));
+            // span{psi, e/|e|}, e from the correction equation (Algorithm 2)
+            PARO_CHECK_LAUNCH(launch_normalize_bands(pl, w, nb, Ut, lv));
             PARO_CHECK_LAUNCH(launch_copy_bands(st, nb, pl.ng, psi, ld, w.U, lv));
             PARO_CHECK_LAUNCH(launch_copy_bands(st, nb, pl.ng, hpsi, ld, w.W, lv));
             PARO_CHECK_LAUNCH(apply_full(pl, w, nb, Ut, lv, w.W + (size_t)nb * lv, nullptr));

