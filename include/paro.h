@@ -104,7 +104,8 @@ typedef struct {
     int64_t n_g;
     int32_t nmax[3];         /* max |n_d| over the sphere */
     int32_t grid[3];
-    int32_t n_sticks;        /* (n1, n2) columns holding sphere points */
+    int32_t n_sticks;        /* (n1, n2) lines transformed along n3: for each n1, every n2
+                                between the lowest and highest that hold sphere points */
     int32_t n_proj;
     double omega;            /* cell volume, bohr^3 */
 } paro_plan_info;

@@ -42,8 +42,7 @@ template <int T> __device__ __forceinline__ int thread_in_line(int tid) { return
 
 // threads of the plane kernel: one line slot per row, rounded up to whole wavefronts
 template <int N> constexpr int plane_threads() { return (N * PlaneCfg<N>::T + 63) / 64 * 64; }
-constexpr int kPlanesPerBlock = 4;  // z-planes handled by one work-group of the plane kernel
-constexpr int kSticksPerThread = 4;  // stick values per thread staged in registers per plane
+constexpr int kBandsPerBlock = 4;  // bands one work-group of the plane kernel takes through its z-plane
 
 // Sphere -> sticks, inverse transform along n3.  Line (stick) threads are
 // consecutive lanes, so the exchanges between passes are wavefront-local.
@@ -93,17 +92,19 @@ k_stick_inv(const double2 *__restrict__ src, int64_t ld, double2 *__restrict__ p
             v, t, [&](int i, int e) { out[(size_t)i * nst + s] = v[e]; });
 }
 
-// z-planes z0 .. z0 + kPlanesPerBlock - 1 of one band, one after the other:
-// inverse along n2 (populated n1 columns), along n1 (all rows), times V,
-// forward along n1, forward along n2; in place in the stick buffer.  Every
-// transform line is wavefront-local; work-group barriers separate only the
-// column, row and column stages.  The plane's stick values are loaded into
-// registers before the LDS is cleared, so their latency overlaps the clear;
-// the potential is stored in the order the row threads hold their values
-// (vperm[z][y][t][e]), so each thread reads E consecutive doubles.
+// One z-plane of bands b0 .. b1-1, one band after the other: inverse along
+// n2 (populated n1 columns), along n1 (all rows), times V, forward along n1,
+// forward along n2; in place in the stick buffer.  A column's sticks are one
+// contiguous range (n2 ascending), so the column transforms read their input
+// from and write their output to the stick buffer directly; the plane in
+// LDS only carries the data between the column and row stages, and two
+// work-group barriers per band separate them.  Every transform line is
+// wavefront-local.  The potential is stored in the order the row threads
+// hold their values, so each thread reads E consecutive doubles, which the
+// bands of the work-group share through the cache.
 template <int N>
 __global__ void __launch_bounds__(plane_threads<N>())
-k_plane(double2 *__restrict__ sticks, int nst, int N3, const int32_t *__restrict__ st_xy,
+k_plane(double2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restrict__ cols,
         const double *__restrict__ vperm, int nmax1, const double2 *__restrict__ tw)
 {
     using C = PlaneCfg<N>;
@@ -111,14 +112,12 @@ k_plane(double2 *__restrict__ sticks, int nst, int N3, const int32_t *__restrict
                   "bad plane FFT config");
     using Inv = typename C::Inv;
     using Fwd = typename C::Fwd;
-    constexpr int T = C::T, E = C::E, LDX = N + 1, NT = plane_threads<N>();
+    constexpr int T = C::T, E = C::E, LDX = N + 1;
     constexpr int RL = ListInfo<Inv>::last;
-    constexpr int SPT = kSticksPerThread;
     __shared__ double2 plane[N * LDX];
     const int tid = threadIdx.x;
-    const int band = blockIdx.y;
-    const int z0 = blockIdx.x * kPlanesPerBlock;
-    const int z1 = min(z0 + kPlanesPerBlock, N3);
+    const int z = blockIdx.x;
+    const int b0 = blockIdx.y * kBandsPerBlock, b1 = min(b0 + kBandsPerBlock, nb);
     const int ncol = 2 * nmax1 + 1;
     const int slot = line_of<T>(tid), t = thread_in_line<T>(tid);
     int xcol = slot - nmax1;
@@ -127,47 +126,38 @@ k_plane(double2 *__restrict__ sticks, int nst, int N3, const int32_t *__restrict
     double2 *col = plane + (colact ? xcol : 0);
     const bool rowact = slot < N;
     double2 *row = plane + (rowact ? slot : 0) * LDX;
-    const bool inreg = nst <= SPT * NT;  // all sticks of a plane fit in SPT registers per thread
-    int xy[SPT];
-#pragma unroll
-    for (int k = 0; k < SPT; ++k) xy[k] = (inreg && tid + k * NT < nst) ? st_xy[tid + k * NT] : 0;
-    for (int z = z0; z < z1; ++z) {
-        double2 *tz = sticks + ((size_t)band * N3 + z) * nst;
-        double2 sv[SPT];
-        if (inreg) {
-#pragma unroll
-            for (int k = 0; k < SPT; ++k) sv[k] = tid + k * NT < nst ? tz[tid + k * NT] : make_double2(0.0, 0.0);
-        }
-        for (int e = tid; e < ncol * N; e += NT) {
-            const int c = e / N, y = e - c * N;
-            int x = c - nmax1;
-            x += x < 0 ? N : 0;
-            plane[y * LDX + x] = make_double2(0.0, 0.0);
-        }
-        __syncthreads();
-        if (inreg) {
-#pragma unroll
-            for (int k = 0; k < SPT; ++k)
-                if (tid + k * NT < nst) plane[(xy[k] >> 16) * LDX + (xy[k] & 0xffff)] = sv[k];
-        } else {
-            for (int s = tid; s < nst; s += NT) {
-                const int q = st_xy[s];
-                plane[(q >> 16) * LDX + (q & 0xffff)] = tz[s];
-            }
-        }
-        __syncthreads();
+    int cst = 0, ylo = 0, cnt = 0;
+    if (colact) {
+        cst = cols[3 * slot];
+        ylo = cols[3 * slot + 1];
+        cnt = cols[3 * slot + 2];
+    }
+    // offset of grid row i (n2 = i or i - N) in this column's stick range, or -1
+    auto stick_of = [&](int i) {
+        const int k = (i > N / 2 ? i - N : i) - ylo;
+        return (unsigned)k < (unsigned)cnt ? k : -1;
+    };
+    const double *vp = vperm + (((size_t)z * N + (rowact ? slot : 0)) * T + t) * E;
+    for (int band = b0; band < b1; ++band) {
+        // Opaque per band: keeps the compiler from hoisting the potential
+        // loads and the per-element stick offsets out of the band loop,
+        // which would hold them in registers across all stages.
+        asm volatile("" : "+v"(ylo), "+v"(cnt), "+v"(vp));
+        double2 *tz = sticks + ((size_t)band * N3 + z) * nst + cst;
         double2 v[E];
-        // n2, inverse
-        if (colact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) { return col[i * LDX]; });
+        // n2, inverse: sticks -> plane columns
+        if (colact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
+            const int k = stick_of(i);
+            return k >= 0 ? tz[k] : make_double2(0.0, 0.0);
+        });
         stockham_c<C, +1, true>(Inv{}, v, t, colact, col, LDX, tw);
         wave_lds_sync();
         if (colact) final_foreach<N, T, E, RL>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
         __syncthreads();
-        // n1 rows: inverse, multiply by V, forward.  The potential values at
-        // the positions this thread holds after the inverse pass are loaded
-        // first so that their latency overlaps the inverse transform.
+        // n1 rows: inverse, multiply by V, forward; only the populated n1
+        // columns are read and written back.  The potential is loaded first
+        // so that its latency overlaps the inverse transform.
         double vr[E];
-        const double *vp = vperm + (((size_t)z * N + (rowact ? slot : 0)) * T + t) * E;
 #pragma unroll
         for (int e = 0; e < E; ++e) vr[e] = vp[e];
         if (rowact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
@@ -182,23 +172,15 @@ k_plane(double2 *__restrict__ sticks, int nst, int N3, const int32_t *__restrict
             if (i <= nmax1 || i >= N - nmax1) row[i] = v[e];
         });
         __syncthreads();
-        // n2, forward
+        // n2, forward: plane columns -> sticks
         if (colact) pass_load<N, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return col[i * LDX]; });
         stockham_c<C, -1, true>(Fwd{}, v, t, colact, col, LDX, tw);
+        if (colact) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
+            const int k = stick_of(i);
+            if (k >= 0) tz[k] = v[e];
+        });
+        // the next band's column stage reuses this column's LDS from the same wavefront
         wave_lds_sync();
-        if (colact) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
-        __syncthreads();
-        if (inreg) {
-#pragma unroll
-            for (int k = 0; k < SPT; ++k)
-                if (tid + k * NT < nst) tz[tid + k * NT] = plane[(xy[k] >> 16) * LDX + (xy[k] & 0xffff)];
-        } else {
-            for (int s = tid; s < nst; s += NT) {
-                const int q = st_xy[s];
-                tz[s] = plane[(q >> 16) * LDX + (q & 0xffff)];
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -285,8 +267,8 @@ hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const double2 *
                            first ? 1 : 0, w.sticks, pl.nst, pl.st_start, pl.pt_sz, pl.tw[2]);
         prof_mark(PARO_K_STICK_INV, pl.stream, false);
         prof_mark(PARO_K_PLANE, pl.stream, true);
-        hipLaunchKernelGGL(k_plane<N>, dim3((N3 + kPlanesPerBlock - 1) / kPlanesPerBlock, cb),
-                           dim3(plane_threads<N>()), 0, pl.stream, w.sticks, pl.nst, N3, pl.st_xy, pl.vplane,
+        hipLaunchKernelGGL(k_plane<N>, dim3(N3, (cb + kBandsPerBlock - 1) / kBandsPerBlock),
+                           dim3(plane_threads<N>()), 0, pl.stream, w.sticks, pl.nst, N3, cb, pl.cols, pl.vplane,
                            pl.nmax[0], pl.tw[0]);
         prof_mark(PARO_K_PLANE, pl.stream, false);
         const double2 *x = pbuf ? pbuf : src;

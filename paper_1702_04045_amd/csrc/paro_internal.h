@@ -29,7 +29,7 @@ struct Plan {
     double *kin = nullptr;        // (1/2)|G|^2, ng
     int32_t *pt_sz = nullptr;     // per sphere point: (stick << 8) | (n3 mod N3)
     int32_t *st_start = nullptr;  // per stick: first sphere point, nst + 1
-    int32_t *st_xy = nullptr;     // per stick: (n1 mod N1) | (n2 mod N2) << 16
+    int32_t *cols = nullptr;      // per n1 column (n1 = -nmax1 ..): first stick, lowest n2, stick count
     double *vplane = nullptr;     // local potential in the plane kernel's row-thread order
     double2 *tw[3] = {nullptr, nullptr, nullptr};  // exp(-2 pi i m / N_d)
     double2 *beta = nullptr;      // KB projectors, nproj x ldv (projector-major)

@@ -1,6 +1,7 @@
 // Host side of libparo: problem validation, plan construction, workspace
 // layout and the C ABI entry points declared in paro.h.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -103,14 +104,15 @@ static bool good_size(int n)
 
 // Layout of the device plan buffer.
 struct PlanLayout {
-    size_t kin, pt_sz, st_start, st_xy, vplane, tw[3], beta, dkb, miller, pcen, plm, pwid, status, total;
+    size_t kin, pt_sz, st_start, cols, vplane, tw[3], beta, dkb, miller, pcen, plm, pwid, status, total;
 };
 
 struct HostGeom {
     int64_t ng;
     int32_t nmax[3];
-    int32_t nst;
+    int32_t nst;                  // sticks, fillers included
     int64_t ldv;
+    std::vector<int32_t> cols;    // per n1 column: first stick, lowest n2, stick count
 };
 
 static PlanLayout layout(const paro_problem &p, const HostGeom &g)
@@ -126,7 +128,7 @@ static PlanLayout layout(const paro_problem &p, const HostGeom &g)
     L.kin = take(sizeof(double) * g.ng);
     L.pt_sz = take(sizeof(int32_t) * g.ng);
     L.st_start = take(sizeof(int32_t) * (g.nst + 1));
-    L.st_xy = take(sizeof(int32_t) * g.nst);
+    L.cols = take(sizeof(int32_t) * g.cols.size());
     L.vplane = take(sizeof(double) * nv);
     for (int d = 0; d < 3; ++d) L.tw[d] = take(sizeof(double2) * p.grid[d]);
     L.beta = take(sizeof(double2) * (size_t)p.n_proj * g.ldv);
@@ -178,11 +180,29 @@ static int32_t validate(const paro_problem *p, HostGeom *g)
         !good_size(p->grid[0]))
         return fail(PARO_EUNSUP, "this build supports cubic FFT grids of 8, 16, 24, 32, 40, 48, 64, 80 or 96 points");
     g->ng = n;
-    int32_t nst = 0;
-    for (int64_t i = 0; i < n; ++i)
-        if (i == 0 || p->miller[3 * i] != p->miller[3 * i - 3] || p->miller[3 * i + 1] != p->miller[3 * i - 2]) ++nst;
-    g->nst = nst;
+    // Sticks are numbered column by column (n1 ascending), n2 ascending
+    // within a column, and every n2 between a column's lowest and highest
+    // populated value gets a stick: the plane kernel addresses a column's
+    // sticks as one contiguous range.  Fillers hold no sphere point and stay
+    // zero through the transforms.
+    const int ncol = 2 * g->nmax[0] + 1;
+    std::vector<int32_t> lo(ncol, INT32_MAX), hi(ncol, INT32_MIN);
+    for (int64_t i = 0; i < n; ++i) {
+        const int c = p->miller[3 * i] + g->nmax[0];
+        lo[c] = std::min(lo[c], p->miller[3 * i + 1]);
+        hi[c] = std::max(hi[c], p->miller[3 * i + 1]);
+    }
+    g->cols.assign(3 * ncol, 0);
+    int64_t nst = 0;
+    for (int c = 0; c < ncol; ++c) {
+        const int64_t cnt = hi[c] >= lo[c] ? (int64_t)hi[c] - lo[c] + 1 : 0;
+        g->cols[3 * c] = (int32_t)std::min<int64_t>(nst, INT32_MAX);
+        g->cols[3 * c + 1] = cnt ? lo[c] : 0;
+        g->cols[3 * c + 2] = (int32_t)cnt;
+        nst += cnt;
+    }
     if (nst >= (1 << 23)) return fail(PARO_EUNSUP, "too many sticks");
+    g->nst = (int32_t)nst;
     g->ldv = (n + 31) / 32 * 32;
     return PARO_OK;
 }
@@ -334,7 +354,7 @@ int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes, 
     pl.kin = (double *)(base + L.kin);
     pl.pt_sz = (int32_t *)(base + L.pt_sz);
     pl.st_start = (int32_t *)(base + L.st_start);
-    pl.st_xy = (int32_t *)(base + L.st_xy);
+    pl.cols = (int32_t *)(base + L.cols);
     pl.vplane = (double *)(base + L.vplane);
     for (int d = 0; d < 3; ++d) pl.tw[d] = (double2 *)(base + L.tw[d]);
     pl.beta = (double2 *)(base + L.beta);
@@ -349,21 +369,19 @@ int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes, 
     const int64_t ng = g.ng;
     const int N1 = pl.grid[0], N2 = pl.grid[1], N3 = pl.grid[2];
     std::vector<double> kin(ng);
-    std::vector<int32_t> pt_sz(ng), st_start(g.nst + 1), st_xy(g.nst);
-    int32_t s = -1;
+    std::vector<int32_t> pt_sz(ng), st_start(g.nst + 1, -1);
     for (int64_t i = 0; i < ng; ++i) {
         const int32_t *n = prob->miller + 3 * i;
-        if (i == 0 || n[0] != n[-3] || n[1] != n[-2]) {
-            ++s;
-            st_start[s] = (int32_t)i;
-            const int x = ((n[0] % N1) + N1) % N1, y = ((n[1] % N2) + N2) % N2;
-            st_xy[s] = x | (y << 16);
-        }
+        const int32_t *col = g.cols.data() + 3 * (n[0] + g.nmax[0]);
+        const int32_t s = col[0] + (n[1] - col[1]);
+        if (st_start[s] < 0) st_start[s] = (int32_t)i;
         const int z = ((n[2] % N3) + N3) % N3;
         pt_sz[i] = (s << 8) | z;
         kin[i] = half_g2(pl.bvec, n[0], n[1], n[2]);
     }
     st_start[g.nst] = (int32_t)ng;
+    for (int s = g.nst - 1; s >= 0; --s)
+        if (st_start[s] < 0) st_start[s] = st_start[s + 1];  // filler: empty point range
     const size_t nv = (size_t)N1 * N2 * N3;
     std::vector<double> vpl(nv);
     double vmin = prob->vloc[0];
@@ -396,7 +414,7 @@ int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes, 
     if (e == hipSuccess) e = up(pl.kin, kin.data(), sizeof(double) * ng);
     if (e == hipSuccess) e = up(pl.pt_sz, pt_sz.data(), sizeof(int32_t) * ng);
     if (e == hipSuccess) e = up(pl.st_start, st_start.data(), sizeof(int32_t) * (g.nst + 1));
-    if (e == hipSuccess) e = up(pl.st_xy, st_xy.data(), sizeof(int32_t) * g.nst);
+    if (e == hipSuccess) e = up(pl.cols, g.cols.data(), sizeof(int32_t) * g.cols.size());
     if (e == hipSuccess) e = up(pl.vplane, vpl.data(), sizeof(double) * nv);
     for (int d = 0; d < 3 && e == hipSuccess; ++d) e = up(pl.tw[d], tw[d].data(), sizeof(double2) * pl.grid[d]);
     if (e == hipSuccess) e = up(miller_dev, prob->miller, sizeof(int32_t) * 3 * ng);
