@@ -32,6 +32,12 @@ if ROOT not in sys.path:
 import synth  # noqa: E402
 
 METRIC = "ParO iters/s & Hψ applies/s, plain FP64 vs batched mixed, at 1e-8 Ha eig err"
+# HBM bytes per plane-kernel launch from the committed counter summary; it
+# counts only while the kernel sources hash to the value recorded there.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_plane_96_c1_hbm_traffic.txt")
+PLANE_SOURCES = ["paper_1702_04045_amd/csrc/apply.hip", "paper_1702_04045_amd/csrc/fft_device.h",
+                 "paper_1702_04045_amd/csrc/paro_internal.h"]
+COPY_BYTES = 1 << 30         # bytes read (and written) by the calibration copy
 PEAK_FP64_VALU = 78.6e12     # MI355X FP64 vector, flop/s
 PEAK_HBM = 8.0e12            # bytes/s
 
@@ -59,7 +65,48 @@ def quad_bound(eps, res, n):
     return out
 
 
-def cpu_baseline(spec, cell, v, x_trial, sample_bands=16):
+def plane_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in PLANE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per plane launch from the counter summary, or None when the
+    summary is missing or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("plane_sources_sha256") != plane_sources_sha256():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device copy of COPY_BYTES, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters to bytes."""
+    import torch
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "launches": 3}))
+
+
+def cpu_baseline(spec, cell, v, x_trial, sample_bands=64):
     """The CPU oracle's outer-iteration time, extrapolated from a bounded sample."""
     import oracle
     h = oracle.Hamiltonian(cell["cell"], cell["ecut"], v, cell["projectors"])
@@ -96,7 +143,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-1e-8 run")
     ap.add_argument("--tta-seconds", type=float, default=60.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the band-sharded multi-GPU "
               "layout is a design note, not part of this build", file=sys.stderr)
@@ -154,9 +206,14 @@ def main():
     flops_launch = plane_flops(N, ncol) * planes_per_launch
     avg_ms = tot.value / max(nl.value, 1)
     achieved = flops_launch / (avg_ms * 1e-3)
+    # algorithmic bytes: every stick of the launch's band-planes read and
+    # written once, the potential read once
+    bytes_launch = 2 * 16.0 * pl.n_sticks * pl.grid[2] * (nb / launches_per_apply) + 8.0 * N ** 3
     roofline = {"kernel": "k_plane<96> (z-plane stage: n2/n1 FFTs, V multiply)", "bound": "alu",
                 "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_VALU, "traffic": None,
+                "frac": achieved / PEAK_FP64_VALU, "traffic": measured_traffic(),
+                "algorithmic_bytes_per_launch": bytes_launch,
+                "hbm_frac_algorithmic": bytes_launch / (avg_ms * 1e-3) / PEAK_HBM,
                 "launches_timed": int(nl.value), "avg_launch_ms": avg_ms, "flops_per_launch": flops_launch,
                 "share_of_step": (tot.value / max(args.steps, 1)) / ms_step}
 

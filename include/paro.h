@@ -147,7 +147,8 @@ int32_t paro_grid_size(const int32_t *nmax, int32_t *grid_out);
 int32_t paro_plan_bytes(const paro_problem *prob, size_t *bytes);
 
 /* Validate the problem and build the plan in dev_buf (device, >= plan
- * bytes, 256-byte aligned): stick maps, kinetic table, plane-major V,
+ * bytes, 256-byte aligned): stick maps, kinetic table, V re-laid for the
+ * plane transforms,
  * FFT twiddles and the KB projector matrix B (n_g x n_proj), computed by
  * a device kernel.  Synchronises the stream before returning.
  * Errors: PARO_EINVAL, PARO_EALIAS, PARO_ESIZE, PARO_EUNSUP, PARO_EHIP. */
