@@ -92,16 +92,23 @@ k_stick_inv(const double2 *__restrict__ src, int64_t ld, double2 *__restrict__ p
             v, t, [&](int i, int e) { out[(size_t)i * nst + s] = v[e]; });
 }
 
-// One z-plane of bands b0 .. b1-1, one band after the other: inverse along
-// n2 (populated n1 columns), along n1 (all rows), times V, forward along n1,
-// forward along n2; in place in the stick buffer.  A column's sticks are one
-// contiguous range (n2 ascending), so the column transforms read their input
-// from and write their output to the stick buffer directly; the plane in
-// LDS only carries the data between the column and row stages, and two
-// work-group barriers per band separate them.  Every transform line is
-// wavefront-local.  The potential is stored in the order the row threads
-// hold their values, so each thread reads E consecutive doubles, which the
-// bands of the work-group share through the cache.
+// One z-plane of bands b0 .. b1-1: inverse along n2 (populated n1 columns),
+// along n1 (all rows), times V, forward along n1, forward along n2; in place
+// in the stick buffer.  A column's sticks are one contiguous range (n2
+// ascending), so the column transforms read their input from and write
+// their output to the stick buffer directly; the plane in LDS only carries
+// the data between the column and row stages.
+//
+// The populated n1 columns are |n1| <= nmax1, at most N/2 of the N, so the
+// plane holds the columns of two bands at once: even bands (counted from
+// b0) at x = n1 mod N, odd bands shifted by N/2.  The line slots split in
+// two halves: while the lower half runs the forward column transforms of
+// band k-1, the upper half runs the inverse column transforms of band k;
+// then all slots run the row transforms of band k.  Two work-group barriers
+// per band.  Every transform line is wavefront-local.  The potential is
+// stored in the order the row threads hold their values, so each thread
+// reads E consecutive doubles, which the bands of the work-group share
+// through the cache.
 template <int N>
 __global__ void __launch_bounds__(plane_threads<N>())
 k_plane(double2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restrict__ cols,
@@ -112,25 +119,28 @@ k_plane(double2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__
                   "bad plane FFT config");
     using Inv = typename C::Inv;
     using Fwd = typename C::Fwd;
-    constexpr int T = C::T, E = C::E, LDX = N + 1;
+    constexpr int T = C::T, E = C::E, LDX = N + 1, HALF = N / 2;
     constexpr int RL = ListInfo<Inv>::last;
     __shared__ double2 plane[N * LDX];
     const int tid = threadIdx.x;
     const int z = blockIdx.x;
     const int b0 = blockIdx.y * kBandsPerBlock, b1 = min(b0 + kBandsPerBlock, nb);
+    const int nbk = b1 - b0;
     const int ncol = 2 * nmax1 + 1;
     const int slot = line_of<T>(tid), t = thread_in_line<T>(tid);
-    int xcol = slot - nmax1;
+    // column role of this line slot: lower half forward, upper half inverse
+    const bool lower = slot < HALF;
+    const int c = lower ? slot : slot - HALF;
+    const bool colact = c < ncol && slot < N;
+    int xcol = c - nmax1;
     xcol += xcol < 0 ? N : 0;
-    const bool colact = slot < ncol;
-    double2 *col = plane + (colact ? xcol : 0);
     const bool rowact = slot < N;
     double2 *row = plane + (rowact ? slot : 0) * LDX;
     int cst = 0, ylo = 0, cnt = 0;
     if (colact) {
-        cst = cols[3 * slot];
-        ylo = cols[3 * slot + 1];
-        cnt = cols[3 * slot + 2];
+        cst = cols[3 * c];
+        ylo = cols[3 * c + 1];
+        cnt = cols[3 * c + 2];
     }
     // offset of grid row i (n2 = i or i - N) in this column's stick range, or -1
     auto stick_of = [&](int i) {
@@ -138,49 +148,64 @@ k_plane(double2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__
         return (unsigned)k < (unsigned)cnt ? k : -1;
     };
     const double *vp = vperm + (((size_t)z * N + (rowact ? slot : 0)) * T + t) * E;
-    for (int band = b0; band < b1; ++band) {
+    for (int k = 0; k <= nbk; ++k) {
         // Opaque per band: keeps the compiler from hoisting the potential
         // loads and the per-element stick offsets out of the band loop,
         // which would hold them in registers across all stages.
         asm volatile("" : "+v"(ylo), "+v"(cnt), "+v"(vp));
-        double2 *tz = sticks + ((size_t)band * N3 + z) * nst + cst;
         double2 v[E];
-        // n2, inverse: sticks -> plane columns
-        if (colact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
-            const int k = stick_of(i);
-            return k >= 0 ? tz[k] : make_double2(0.0, 0.0);
-        });
-        stockham_c<C, +1, true>(Inv{}, v, t, colact, col, LDX, tw);
-        wave_lds_sync();
-        if (colact) final_foreach<N, T, E, RL>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
+        {
+            // column phase: forward of band k-1 (lower), inverse of band k (upper)
+            const int kb = lower ? k - 1 : k;
+            const bool act = colact && kb >= 0 && kb < nbk;
+            int xs = xcol + ((kb & 1) ? HALF : 0);
+            xs -= xs >= N ? N : 0;
+            double2 *col = plane + (act ? xs : 0);
+            double2 *tz = sticks + ((size_t)(b0 + (act ? kb : 0)) * N3 + z) * nst + cst;
+            if (lower) {
+                if (act) pass_load<N, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return col[i * LDX]; });
+                stockham_c<C, -1, true>(Fwd{}, v, t, act, col, LDX, tw);
+                if (act) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
+                    const int q = stick_of(i);
+                    if (q >= 0) tz[q] = v[e];
+                });
+            } else {
+                if (act) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
+                    const int q = stick_of(i);
+                    return q >= 0 ? tz[q] : make_double2(0.0, 0.0);
+                });
+                stockham_c<C, +1, true>(Inv{}, v, t, act, col, LDX, tw);
+                wave_lds_sync();
+                if (act) final_foreach<N, T, E, RL>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
+            }
+        }
         __syncthreads();
-        // n1 rows: inverse, multiply by V, forward; only the populated n1
-        // columns are read and written back.  The potential is loaded first
-        // so that its latency overlaps the inverse transform.
-        double vr[E];
+        if (k == nbk) break;
+        // n1 rows of band k: inverse, multiply by V, forward; only the
+        // populated n1 columns are read and written back.  The potential is
+        // loaded first so that its latency overlaps the inverse transform.
+        {
+            const int sh = (k & 1) ? HALF : 0;
+            auto at = [&](int i) {  // plane slot of n1 index i (populated only)
+                int x = i + sh;
+                return x - (x >= N ? N : 0);
+            };
+            double vr[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) vr[e] = vp[e];
-        if (rowact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
-            return (i <= nmax1 || i >= N - nmax1) ? row[i] : make_double2(0.0, 0.0);
-        });
-        stockham_c<C, +1, true>(Inv{}, v, t, rowact, row, 1, tw);
+            for (int e = 0; e < E; ++e) vr[e] = vp[e];
+            if (rowact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
+                return (i <= nmax1 || i >= N - nmax1) ? row[at(i)] : make_double2(0.0, 0.0);
+            });
+            stockham_c<C, +1, true>(Inv{}, v, t, rowact, row, 1, tw);
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vr[e]);
-        stockham_c<C, -1, true>(Fwd{}, v, t, rowact, row, 1, tw);
-        wave_lds_sync();
-        if (rowact) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
-            if (i <= nmax1 || i >= N - nmax1) row[i] = v[e];
-        });
+            for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vr[e]);
+            stockham_c<C, -1, true>(Fwd{}, v, t, rowact, row, 1, tw);
+            wave_lds_sync();
+            if (rowact) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
+                if (i <= nmax1 || i >= N - nmax1) row[at(i)] = v[e];
+            });
+        }
         __syncthreads();
-        // n2, forward: plane columns -> sticks
-        if (colact) pass_load<N, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return col[i * LDX]; });
-        stockham_c<C, -1, true>(Fwd{}, v, t, colact, col, LDX, tw);
-        if (colact) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
-            const int k = stick_of(i);
-            if (k >= 0) tz[k] = v[e];
-        });
-        // the next band's column stage reuses this column's LDS from the same wavefront
-        wave_lds_sync();
     }
 }
 

@@ -346,13 +346,13 @@ __device__ __forceinline__ void stockham(RList<Rs...> l, double2 (&v)[FftCfg<N>:
 }
 
 // Line schedule of the z-plane kernel (defaults to FftCfg).  For 96 points
-// two passes (12 x 8, one LDS exchange) on 4 threads per line measured
-// faster than three passes on 8 threads.
+// 8 threads per line (12 work-group waves) with passes 4 x 6 x 4 measured
+// fastest among 4 x 24 and 8 x 12 splits of the lines.
 template <int N> struct PlaneCfg : FftCfg<N> {};
 template <> struct PlaneCfg<96> {
-    static constexpr int N = 96, T = 4, E = 24;
-    using Inv = RList<12, 8>;
-    using Fwd = RList<8, 12>;
+    static constexpr int N = 96, T = 8, E = 12;
+    using Inv = RList<4, 6, 4>;
+    using Fwd = RList<4, 6, 4>;
 };
 
 }  // namespace paro
