@@ -255,6 +255,14 @@ k_tridiag(int m, double2 *__restrict__ A, double *__restrict__ d, double *__rest
     }
 }
 
+// 1 / x: hardware reciprocal refined by one Newton step (about 1 ulp);
+// used where the result feeds a sign test or an iterative refinement.
+__device__ __forceinline__ double rcp1(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots)
 __device__ int sturm_count(int m, const double *d, const double *e2, double x, double pivmin)
 {
@@ -263,144 +271,205 @@ __device__ int sturm_count(int m, const double *d, const double *e2, double x, d
     if (fabs(q) < pivmin) q = -pivmin;
     c += q < 0.0;
     for (int i = 1; i < m; ++i) {
-        q = d[i] - x - e2[i - 1] / q;
+        q = (d[i] - x) - e2[i - 1] * rcp1(q);
         if (fabs(q) < pivmin) q = -pivmin;
         c += q < 0.0;
     }
     return c;
 }
 
-// Eigenvalues of the real symmetric tridiagonal T (d, e) by bisection, one
-// thread per eigenvalue (ascending).  When Z != null, eigenvectors by
-// inverse iteration: for each eigenvalue, LU with partial pivoting of
-// T - lambda I, three solves from a fixed start vector; members of a
-// cluster (gap below 1e-5 |T|) are orthogonalised against the earlier
-// members (modified Gram-Schmidt) after every solve and get shifts at
-// least 10 eps |T| apart.  scr: 4 m * m doubles of per-thread workspace.
-__global__ void __launch_bounds__(kBig)
-k_tridiag_eig(int m, const double *__restrict__ d_in, const double *__restrict__ e_in, double *__restrict__ lam,
-              double *__restrict__ lam2, int nout, double *__restrict__ Z, double *__restrict__ scr)
+// Gershgorin interval of T, |T| and the pivot floor, from d and e in LDS
+// (one wavefront).
+struct TriBounds {
+    double lo, hi, tnorm, pivmin;
+};
+__device__ TriBounds tri_bounds(int m, const double *sd, const double *se)
 {
-    __shared__ double sd[kBig], se[kBig], se2[kBig], sl[kBig];
-    __shared__ double red[kBig / 64];
-    const int tid = threadIdx.x;
-    for (int i = tid; i < m; i += kBig) {
+    double lo = INFINITY, hi = -INFINITY, emax2 = 0.0;
+    for (int i = threadIdx.x; i < m; i += 64) {
+        const double r = fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0);
+        lo = fmin(lo, sd[i] - r);
+        hi = fmax(hi, sd[i] + r);
+        emax2 = fmax(emax2, se[i] * se[i]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o));
+        hi = fmax(hi, __shfl_xor(hi, o));
+        emax2 = fmax(emax2, __shfl_xor(emax2, o));
+    }
+    TriBounds b;
+    b.tnorm = fmax(fabs(lo), fabs(hi));
+    b.pivmin = DBL_MIN * fmax(1.0, emax2);
+    b.lo = lo - (2.0 * DBL_EPSILON * b.tnorm + 2.0 * b.pivmin);
+    b.hi = hi + (2.0 * DBL_EPSILON * b.tnorm + 2.0 * b.pivmin);
+    return b;
+}
+
+constexpr int kTriMax = 1024;  // largest tridiagonal order of the eigen kernels
+
+// Eigenvalue j of the real symmetric tridiagonal T (d, e), ascending, one
+// single-wave work-group per eigenvalue: 64-point multisection of Sturm
+// counts, each round shrinking the interval 65-fold, down to an absolute
+// width of 2 eps |T| (the accuracy of the eigenvalues of T).
+__global__ void __launch_bounds__(64)
+k_tri_eigvals(int m, const double *__restrict__ d_in, const double *__restrict__ e_in, double *__restrict__ lam,
+              double *__restrict__ lam2, int nout)
+{
+    __shared__ double sd[kTriMax], se[kTriMax], se2[kTriMax];
+    const int lane = threadIdx.x, j = blockIdx.x;
+    for (int i = lane; i < m; i += 64) {
         sd[i] = d_in[i];
         se[i] = i + 1 < m ? e_in[i] : 0.0;
         se2[i] = se[i] * se[i];
     }
     __syncthreads();
-    double lo = INFINITY, hi = -INFINITY, emax2 = 0.0;
-    for (int i = tid; i < m; i += kBig) {
-        const double r = fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0);
-        lo = fmin(lo, sd[i] - r);
-        hi = fmax(hi, sd[i] + r);
-        emax2 = fmax(emax2, se2[i]);
+    const TriBounds b = tri_bounds(m, sd, se);
+    double a = b.lo, c = b.hi;
+    const double target = 2.0 * DBL_EPSILON * b.tnorm + 2.0 * b.pivmin;
+    const int rounds = (int)ceil(log(fmax((c - a) / target, 2.0)) / log(65.0)) + 1;
+    for (int r = 0; r < rounds; ++r) {
+        const double x = a + (c - a) * (double)(lane + 1) / 65.0;
+        const unsigned long long above = __ballot(sturm_count(m, sd, se2, x, b.pivmin) > j);
+        // eigenvalue j lies in (x_{p-1}, x_p], p = first point above it
+        const int p = above ? __builtin_ctzll(above) : 64;
+        const double na = p > 0 ? a + (c - a) * (double)p / 65.0 : a;
+        const double nc = p < 64 ? a + (c - a) * (double)(p + 1) / 65.0 : c;
+        a = na;
+        c = nc;
     }
-    lo = -block_max<kBig>(-lo, red);
-    hi = block_max<kBig>(hi, red);
-    emax2 = block_max<kBig>(emax2, red);
-    const double tnorm = fmax(fabs(lo), fabs(hi));
-    const double pivmin = DBL_MIN * fmax(1.0, emax2);
-    lo -= 2.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
-    hi += 2.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
-    if (tid < m) {
-        double a = lo, b = hi;
-        for (int it = 0; it < 128; ++it) {
-            const double mid = 0.5 * (a + b);
-            if (mid <= a || mid >= b) break;
-            if (b - a <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + pivmin) break;
-            if (sturm_count(m, sd, se2, mid, pivmin) > tid) b = mid;
-            else a = mid;
-        }
-        sl[tid] = 0.5 * (a + b);
-        lam[tid] = sl[tid];
-        if (lam2 && tid < nout) lam2[tid] = sl[tid];
+    if (lane == 0) {
+        const double v = 0.5 * (a + c);
+        lam[j] = v;
+        if (lam2 && j < nout) lam2[j] = v;
+    }
+}
+
+// Eigenvectors of T by inverse iteration, one single-wave work-group per
+// cluster of eigenvalues (gaps below 1e-5 |T|; most clusters have one
+// member), started by the work-group of its first member.  Per member: LU
+// with partial pivoting of T - s I (s at least 10 eps |T| above the
+// previous member's), three solves from a fixed start vector, members after
+// the first orthogonalised against the earlier ones (modified Gram-Schmidt)
+// after every solve.  The LU factors and the iterate live in LDS; lane 0
+// runs the serial recurrences, the wavefront the vector operations.
+// Z: column j (m doubles) of eigenvector j.
+__global__ void __launch_bounds__(64)
+k_tri_eigvecs(int m, const double *__restrict__ d_in, const double *__restrict__ e_in, const double *__restrict__ lam,
+              double *__restrict__ Z)
+{
+    extern __shared__ double lds[];
+    double *sd = lds, *se = lds + m;
+    double *S0 = lds + 2 * m, *S1 = lds + 3 * m, *S2 = lds + 4 * m, *S3 = lds + 5 * m, *PV = lds + 6 * m;
+    double *zw = lds + 7 * m;
+    __shared__ double s_scale;
+    const int lane = threadIdx.x, j0 = blockIdx.x;
+    for (int i = lane; i < m; i += 64) {
+        sd[i] = d_in[i];
+        se[i] = i + 1 < m ? e_in[i] : 0.0;
     }
     __syncthreads();
-    if (!Z) return;
-    const double ortol = 1e-5 * tnorm, pert = 10.0 * DBL_EPSILON * tnorm;
-    if (tid >= m) return;
-    if (tid > 0 && sl[tid] - sl[tid - 1] <= ortol) return;  // not a cluster start
-    int cend = tid + 1;
-    while (cend < m && sl[cend] - sl[cend - 1] <= ortol) ++cend;
-    // per-thread LU arrays, interleaved by thread: scr[(a * m + k) * m + tid]
-    auto S = [&](int a, int k) -> double & { return scr[((int64_t)a * m + k) * m + tid]; };
+    const TriBounds b = tri_bounds(m, sd, se);
+    const double ortol = 1e-5 * b.tnorm, pert = 10.0 * DBL_EPSILON * b.tnorm;
+    if (j0 > 0 && lam[j0] - lam[j0 - 1] <= ortol) return;  // not a cluster start
+    int cend = j0 + 1;
+    while (cend < m && lam[cend] - lam[cend - 1] <= ortol) ++cend;
+    const double tiny = DBL_EPSILON * b.tnorm + DBL_MIN;
     double prev_shift = 0.0;
-    for (int j = tid; j < cend; ++j) {
-        double s = sl[j];
-        if (j > tid && s - prev_shift < pert) s = prev_shift + pert;
+    for (int j = j0; j < cend; ++j) {
+        double s = lam[j];
+        if (j > j0 && s - prev_shift < pert) s = prev_shift + pert;
         prev_shift = s;
-        // LU of T - s I: 0: dl (multipliers), 1: d, 2: du, 3: du2; pivots packed in the sign of a flag array
-        for (int k = 0; k < m; ++k) {
-            S(0, k) = se[k];
-            S(1, k) = sd[k] - s;
-            S(2, k) = se[k];
-            S(3, k) = 0.0;
-        }
-        const double tiny = DBL_EPSILON * tnorm + DBL_MIN;
-        unsigned long long pivbits[16] = {0};  // m <= 1024
-        for (int k = 0; k + 1 < m; ++k) {
-            const double dk = S(1, k), lk = S(0, k);
-            if (fabs(dk) >= fabs(lk)) {
-                const double dd = dk == 0.0 ? tiny : dk;
-                S(1, k) = dd;
-                const double f = lk / dd;
-                S(0, k) = f;
-                S(1, k + 1) -= f * S(2, k);
-            } else {
-                pivbits[k >> 6] |= 1ull << (k & 63);
-                const double f = dk / lk;
-                S(1, k) = lk;
-                S(0, k) = f;
-                const double t = S(2, k);
-                S(2, k) = S(1, k + 1);
-                S(1, k + 1) = t - f * S(1, k + 1);
-                if (k + 2 < m) {
-                    S(3, k) = S(2, k + 1);
-                    S(2, k + 1) = -f * S(2, k + 1);
+        if (lane == 0) {
+            // S0 multipliers, S1 reciprocal pivots, S2 / S3 first / second
+            // superdiagonal of U, PV = 1 where rows k and k+1 were swapped
+            double dk = sd[0] - s, uk = se[0];
+            for (int k = 0; k + 1 < m; ++k) {
+                const double lk = se[k];
+                const double dn = sd[k + 1] - s, un = se[k + 1];
+                if (fabs(dk) >= fabs(lk)) {
+                    const double r = rcp1(dk == 0.0 ? tiny : dk);
+                    const double f = lk * r;
+                    S0[k] = f;
+                    S1[k] = r;
+                    S2[k] = uk;
+                    S3[k] = 0.0;
+                    PV[k] = 0.0;
+                    dk = fma(-f, uk, dn);
+                    uk = un;
+                } else {
+                    const double f = dk * rcp1(lk);
+                    S0[k] = f;
+                    S1[k] = rcp1(lk);
+                    S2[k] = dn;
+                    S3[k] = un;
+                    PV[k] = 1.0;
+                    dk = fma(-f, dn, uk);
+                    uk = -f * un;
                 }
             }
+            S1[m - 1] = rcp1(dk == 0.0 ? tiny : dk);
+            S2[m - 1] = 0.0;
+            S3[m - 1] = 0.0;
         }
-        if (S(1, m - 1) == 0.0) S(1, m - 1) = tiny;
-        double *z = Z + (int64_t)j * m;
         // start vector: fixed pseudo-random entries in [0.5, 1.5)
-        for (int k = 0; k < m; ++k) {
+        for (int k = lane; k < m; k += 64) {
             unsigned h = (unsigned)(k + 1) * 2654435761u ^ (unsigned)(j + 7) * 40503u;
             h ^= h >> 13;
             h *= 0x5bd1e995u;
             h ^= h >> 15;
-            z[k] = 0.5 + (double)(h & 0xffffff) / 16777216.0;
+            zw[k] = 0.5 + (double)(h & 0xffffff) / 16777216.0;
         }
+        __syncthreads();
         for (int it = 0; it < 3; ++it) {
-            for (int k = 0; k + 1 < m; ++k) {
-                if (pivbits[k >> 6] >> (k & 63) & 1ull) {
-                    const double t = z[k];
-                    z[k] = z[k + 1];
-                    z[k + 1] = t - S(0, k) * z[k];
-                } else {
-                    z[k + 1] -= S(0, k) * z[k];
+            if (lane == 0) {
+                // forward: row swaps and multipliers; zc = running z[k]
+                double zc = zw[0];
+                for (int k = 0; k + 1 < m; ++k) {
+                    const double zn = zw[k + 1], f = S0[k];
+                    if (PV[k] != 0.0) {
+                        zw[k] = zn;
+                        zc = fma(-f, zn, zc);
+                    } else {
+                        zw[k] = zc;
+                        zc = fma(-f, zc, zn);
+                    }
                 }
+                // back substitution with U
+                double z1 = zc * S1[m - 1], z2 = 0.0, n2 = z1 * z1;
+                zw[m - 1] = z1;
+                for (int k = m - 2; k >= 0; --k) {
+                    const double v = (zw[k] - S2[k] * z1 - S3[k] * z2) * S1[k];
+                    zw[k] = v;
+                    n2 = fma(v, v, n2);
+                    z2 = z1;
+                    z1 = v;
+                }
+                s_scale = n2 > 0.0 ? 1.0 / sqrt(n2) : 1.0;
             }
-            z[m - 1] /= S(1, m - 1);
-            if (m > 1) z[m - 2] = (z[m - 2] - S(2, m - 2) * z[m - 1]) / S(1, m - 2);
-            for (int k = m - 3; k >= 0; --k)
-                z[k] = (z[k] - S(2, k) * z[k + 1] - S(3, k) * z[k + 2]) / S(1, k);
-            double nrm = 0.0;
-            for (int k = 0; k < m; ++k) nrm = fmax(nrm, fabs(z[k]));
-            double inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
-            for (int k = 0; k < m; ++k) z[k] *= inv;
-            for (int p = tid; p < j; ++p) {
-                const double *zp = Z + (int64_t)p * m;
-                double dot = 0.0;
-                for (int k = 0; k < m; ++k) dot += zp[k] * z[k];
-                for (int k = 0; k < m; ++k) z[k] -= dot * zp[k];
+            __syncthreads();
+            const double sc = s_scale;
+            for (int k = lane; k < m; k += 64) zw[k] *= sc;
+            if (j > j0) {
+                __syncthreads();
+                for (int p = j0; p < j; ++p) {
+                    const double *__restrict__ zp = Z + (int64_t)p * m;
+                    double dot = 0.0;
+                    for (int k = lane; k < m; k += 64) dot += zp[k] * zw[k];
+                    for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
+                    for (int k = lane; k < m; k += 64) zw[k] -= dot * zp[k];
+                }
+                double q2 = 0.0;
+                for (int k = lane; k < m; k += 64) q2 += zw[k] * zw[k];
+                for (int o = 32; o > 0; o >>= 1) q2 += __shfl_xor(q2, o);
+                const double sq = q2 > 0.0 ? 1.0 / sqrt(q2) : 1.0;
+                for (int k = lane; k < m; k += 64) zw[k] *= sq;
             }
-            double n2 = 0.0;
-            for (int k = 0; k < m; ++k) n2 += z[k] * z[k];
-            inv = n2 > 0.0 ? 1.0 / sqrt(n2) : 1.0;
-            for (int k = 0; k < m; ++k) z[k] *= inv;
+            __syncthreads();
         }
+        double *__restrict__ z = Z + (int64_t)j * m;
+        for (int k = lane; k < m; k += 64) z[k] = zw[k];
+        __threadfence_block();
+        __syncthreads();
     }
 }
 
@@ -504,12 +573,12 @@ __global__ void k_bookkeep(int nb, int n_conv, int shift_mode, double sigma_lb, 
 
 }  // namespace
 
-// dreal layout: d[m] e[m] tau[2m] lam[m] vmin[1] fail(int)[2] | Z[m*m] | scr[4*m*m]
+// dreal layout: d[m] e[m] tau[2m] lam[m] vmin[1] fail(int)[2] | Z[m*m]
 struct DenseScratch {
     double *d, *e, *lam, *vmin;
     double2 *tau;
     int32_t *fail;
-    double *Z, *scr;
+    double *Z;
 };
 
 static DenseScratch dense_scratch(const Workspace &w, int m)
@@ -523,18 +592,19 @@ static DenseScratch dense_scratch(const Workspace &w, int m)
     s.vmin = p + 5 * m;
     s.fail = reinterpret_cast<int32_t *>(p + 5 * m + 1);
     s.Z = p + 5 * m + 2;
-    s.scr = s.Z + (size_t)m * m;
     return s;
 }
 
-size_t dense_real_elems(int mmax) { return 5 * (size_t)mmax + 2 + 5 * (size_t)mmax * mmax; }
+size_t dense_real_elems(int mmax) { return 5 * (size_t)mmax + 2 + (size_t)mmax * mmax; }
 
 static hipError_t eig_pipeline(hipStream_t st, int m, double2 *Hh, const DenseScratch &s, double *eps_out,
                                int nout, double2 *Yout, bool vectors)
 {
     hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kBig), 0, st, m, Hh, s.d, s.e, s.tau);
-    hipLaunchKernelGGL(k_tridiag_eig, dim3(1), dim3(kBig), 0, st, m, s.d, s.e, s.lam, eps_out, nout,
-                       vectors ? s.Z : nullptr, s.scr);
+    hipLaunchKernelGGL(k_tri_eigvals, dim3(m), dim3(64), 0, st, m, s.d, s.e, s.lam, eps_out, nout);
+    if (vectors)
+        hipLaunchKernelGGL(k_tri_eigvecs, dim3(m), dim3(64), 8 * (size_t)m * sizeof(double), st, m, s.d, s.e, s.lam,
+                           s.Z);
     if (vectors)
         hipLaunchKernelGGL(k_backtransform, dim3(m), dim3(64), (size_t)m * sizeof(double2), st, m, Hh, s.tau, s.Z,
                            Yout);

@@ -29,7 +29,11 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
 
 namespace {
 
-constexpr int kTile = 64;  // work-group tile (4 waves of 32 x 32)
+constexpr int kTile = 64;   // work-group tile (4 waves of 32 x 32)
+// k-steps of 4 in flight per wave (register prefetch ring), measured best
+// for the long split contraction of gemm_hn and the short one of gemm_nn
+constexpr int kDepthHN = 8;
+constexpr int kDepthNN = 4;
 
 // partial[s][j][i] = sum over k in split s of conj(A[k][i]) B[k][j]
 __global__ void __launch_bounds__(256)
@@ -52,25 +56,39 @@ k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, const double2 *__restric
         }
     const int ia[2] = {i0 + l16, i0 + 16 + l16};
     const int jb[2] = {j0 + l16, j0 + 16 + l16};
-    for (int64_t k0 = kb; k0 < ke; k0 += 4) {
+    // Register prefetch ring: the operands of k-step s + kDepthHN - 1 are
+    // requested before the products of step s, so that their latency
+    // overlaps kDepthHN - 1 steps of matrix-core work.
+    double2 a[kDepthHN][2], b[kDepthHN][2];
+    auto load = [&](int slot, int64_t k0) {
         const int64_t kk = k0 + lk;
         const bool kv = kk < ke;
-        double2 a[2], b[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            a[u] = (kv && ia[u] < M) ? A[(int64_t)ia[u] * lda + kk] : make_double2(0.0, 0.0);
-            b[u] = (kv && jb[u] < N) ? B[(int64_t)jb[u] * ldb + kk] : make_double2(0.0, 0.0);
+            a[slot][u] = (kv && ia[u] < M) ? A[(int64_t)ia[u] * lda + kk] : make_double2(0.0, 0.0);
+            b[slot][u] = (kv && jb[u] < N) ? B[(int64_t)jb[u] * ldb + kk] : make_double2(0.0, 0.0);
         }
+    };
+    auto step = [&](int slot) {
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int w = 0; w < 2; ++w) {
                 // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
-                re[u][w] = mfma(a[u].x, b[w].x, re[u][w]);
-                re[u][w] = mfma(a[u].y, b[w].y, re[u][w]);
-                im[u][w] = mfma(a[u].x, b[w].y, im[u][w]);
-                im[u][w] = mfma(-a[u].y, b[w].x, im[u][w]);
+                re[u][w] = mfma(a[slot][u].x, b[slot][w].x, re[u][w]);
+                re[u][w] = mfma(a[slot][u].y, b[slot][w].y, re[u][w]);
+                im[u][w] = mfma(a[slot][u].x, b[slot][w].y, im[u][w]);
+                im[u][w] = mfma(-a[slot][u].y, b[slot][w].x, im[u][w]);
             }
+    };
+#pragma unroll
+    for (int d = 0; d < kDepthHN - 1; ++d) load(d, kb + 4 * d);
+    for (int64_t k0 = kb; k0 < ke; k0 += 4 * kDepthHN) {
+#pragma unroll
+        for (int d = 0; d < kDepthHN; ++d) {
+            load((d + kDepthHN - 1) % kDepthHN, k0 + 4 * (d + kDepthHN - 1));
+            step(d);
+        }
     }
     double2 *P = part + (size_t)blockIdx.z * M * N;
 #pragma unroll
@@ -133,25 +151,37 @@ k_gemm_nn(int64_t M, int N, int K, const double2 *__restrict__ A, int64_t lda, c
         }
     const int nb_[2] = {n0 + l16, n0 + 16 + l16};
     const int64_t gg[2] = {g0 + l16, g0 + 16 + l16};
-    for (int k0 = 0; k0 < K; k0 += 4) {
+    // register prefetch ring, as in k_gemm_hn_part
+    double2 x[kDepthNN][2], y[kDepthNN][2];
+    auto load = [&](int slot, int k0) {
         const int kk = k0 + lk;
         const bool kv = kk < K;
-        double2 x[2], y[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            x[u] = (kv && nb_[u] < N) ? B[(int64_t)nb_[u] * ldb + kk] : make_double2(0.0, 0.0);
-            y[u] = (kv && gg[u] < M) ? A[(int64_t)kk * lda + gg[u]] : make_double2(0.0, 0.0);
+            x[slot][u] = (kv && nb_[u] < N) ? B[(int64_t)nb_[u] * ldb + kk] : make_double2(0.0, 0.0);
+            y[slot][u] = (kv && gg[u] < M) ? A[(int64_t)kk * lda + gg[u]] : make_double2(0.0, 0.0);
         }
+    };
+    auto step = [&](int slot) {
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int w = 0; w < 2; ++w) {
                 // (x y): re = xr yr - xi yi, im = xr yi + xi yr
-                re[u][w] = mfma(x[u].x, y[w].x, re[u][w]);
-                re[u][w] = mfma(-x[u].y, y[w].y, re[u][w]);
-                im[u][w] = mfma(x[u].x, y[w].y, im[u][w]);
-                im[u][w] = mfma(x[u].y, y[w].x, im[u][w]);
+                re[u][w] = mfma(x[slot][u].x, y[slot][w].x, re[u][w]);
+                re[u][w] = mfma(-x[slot][u].y, y[slot][w].y, re[u][w]);
+                im[u][w] = mfma(x[slot][u].x, y[slot][w].y, im[u][w]);
+                im[u][w] = mfma(x[slot][u].y, y[slot][w].x, im[u][w]);
             }
+    };
+#pragma unroll
+    for (int d = 0; d < kDepthNN - 1; ++d) load(d, 4 * d);
+    for (int k0 = 0; k0 < K; k0 += 4 * kDepthNN) {
+#pragma unroll
+        for (int d = 0; d < kDepthNN; ++d) {
+            load((d + kDepthNN - 1) % kDepthNN, k0 + 4 * (d + kDepthNN - 1));
+            step(d);
+        }
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
