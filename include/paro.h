@@ -65,6 +65,12 @@ extern "C" {
 #define PARO_SHIFT_FIXED 0     /* sigma = sigma_lb every outer iteration */
 #define PARO_SHIFT_ADAPTIVE 1  /* sigma = max(sigma_lb, eps_1 - 0.05 - |r_1|) once |r_1| < 0.1 */
 
+/* arithmetic of the source problems in paro_iterate */
+#define PARO_PREC_FP64 0   /* everything in FP64 */
+#define PARO_PREC_MIXED 1  /* source problems in FP32 (correction form, see
+                              paro_source_solve_mixed); H U, Rayleigh-Ritz,
+                              residuals and shifts in FP64 */
+
 /* solver variants of paro_iterate */
 #define PARO_VARIANT_PARO 0    /* Algorithm 1: Rayleigh-Ritz on span{u_i} (m = nb) */
 #define PARO_VARIANT_MPARO1 1  /* Algorithm 2: Rayleigh-Ritz on span{psi_i, e_i} (m = 2 nb) */
@@ -121,6 +127,7 @@ typedef struct {
     double sigma_lb;         /* lower bound of the spectrum (paro_shift_lower_bound) */
     double tol_res;          /* stop once max_{b < n_conv} |H psi_b - eps_b psi_b| <= tol_res
                                 (checked on the device after each outer iteration; 0 = never) */
+    int32_t precision;       /* PARO_PREC_FP64 or PARO_PREC_MIXED */
 } paro_iter_opts;
 
 /* ---------------------------------------------------------------- ABI */
@@ -181,6 +188,14 @@ int32_t paro_get_projectors(paro_plan plan, double *beta_dev);
 int32_t paro_apply_h(paro_plan plan, int32_t nb, const double *psi, int64_t ld,
                      const double *shift, double *hpsi, void *ws, size_t ws_bytes);
 
+/* H psi in single precision: hpsi_b = (H - shift_b) psi_b with psi, hpsi
+ * dev complex64 (interleaved float re, im), band-major, leading dimension
+ * ld; FP32 FFTs with an FP32 copy of the potential and FP32 matrix-core
+ * projector products (split partial sums added in FP64).  The building
+ * block of the mixed-precision source solve; shift and ws as paro_apply_h. */
+int32_t paro_apply_h_f32(paro_plan plan, int32_t nb, const float *psi, int64_t ld,
+                         const double *shift, float *hpsi, void *ws, size_t ws_bytes);
+
 /* The N independent source problems of Algorithm 1, step 3, read with a
  * shift sigma_b below the spectrum:
  *   (H - sigma_b) u_b = (eps_b - sigma_b) psi_b,
@@ -195,6 +210,18 @@ int32_t paro_apply_h(paro_plan plan, int32_t nb, const double *psi, int64_t ld,
 int32_t paro_source_solve(paro_plan plan, int32_t nb, const double *psi, const double *hpsi,
                           int64_t ld, const double *eps, const double *shift, int32_t n_cg,
                           double *u, int32_t *band_flags, void *ws, size_t ws_bytes);
+
+/* The same source problems with FP32 vectors (the "batched mixed" solve):
+ * u_b = psi_b + d_b where d_b, from d_b = 0, takes n_cg Teter-preconditioned
+ * CG steps on (H - sigma_b) d_b = eps_b psi_b - hpsi_b, the right-hand side
+ * formed in FP64 and stored in FP32, H applied as in paro_apply_h_f32, the
+ * CG scalars in FP64.  In exact arithmetic this is the iterate of
+ * paro_source_solve (its CG run from u = psi); in floating point the error is
+ * about 1e-7 |d_b|.  Arguments, layout and flags as paro_source_solve (FP64
+ * psi, hpsi, u). */
+int32_t paro_source_solve_mixed(paro_plan plan, int32_t nb, const double *psi, const double *hpsi,
+                                int64_t ld, const double *eps, const double *shift, int32_t n_cg,
+                                double *u, int32_t *band_flags, void *ws, size_t ws_bytes);
 
 /* Rayleigh-Ritz on span{U} (Algorithm 1, step 4): with W = H U given,
  * S = U^H U, Hs = U^H W, S = L L^H, Hhat = L^-1 Hs L^-H = Y diag(eps) Y^H

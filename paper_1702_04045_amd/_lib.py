@@ -15,6 +15,7 @@ PARO_OK, PARO_EINVAL, PARO_EALIAS, PARO_ESIZE, PARO_EHIP, PARO_EUNSUP = 0, -1, -
 F_NEGCURV, F_CHOL, F_NAN = 1, 2, 4
 SHIFT_FIXED, SHIFT_ADAPTIVE = 0, 1
 VARIANT_PARO, VARIANT_MPARO1 = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
 K_STICK_INV, K_PLANE, K_STICK_FWD, K_GEMM_HN, K_GEMM_NN, K_PCG_UPDATE = 1, 2, 3, 4, 5, 6
 
 ERRORS = {PARO_EINVAL: "EINVAL", PARO_EALIAS: "EALIAS", PARO_ESIZE: "ESIZE", PARO_EHIP: "EHIP",
@@ -46,7 +47,7 @@ class PlanInfo(C.Structure):
 class IterOpts(C.Structure):
     _fields_ = [("n_outer", C.c_int32), ("n_cg", C.c_int32), ("n_conv", C.c_int32), ("shift_mode", C.c_int32),
                 ("variant", C.c_int32), ("initial_rr", C.c_int32), ("sigma_lb", C.c_double),
-                ("tol_res", C.c_double)]
+                ("tol_res", C.c_double), ("precision", C.c_int32)]
 
 
 _vp, _dp, _ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
@@ -66,7 +67,10 @@ SIGNATURES = {
     "paro_get_kinetic": (C.c_int32, [_vp, _vp]),
     "paro_get_projectors": (C.c_int32, [_vp, _vp]),
     "paro_apply_h": (C.c_int32, [_vp, C.c_int32, _vp, C.c_int64, _vp, _vp, _vp, _sz]),
+    "paro_apply_h_f32": (C.c_int32, [_vp, C.c_int32, _vp, C.c_int64, _vp, _vp, _vp, _sz]),
     "paro_source_solve": (C.c_int32, [_vp, C.c_int32, _vp, _vp, C.c_int64, _vp, _vp, C.c_int32, _vp, _vp, _vp,
+                                      _sz]),
+    "paro_source_solve_mixed": (C.c_int32, [_vp, C.c_int32, _vp, _vp, C.c_int64, _vp, _vp, C.c_int32, _vp, _vp, _vp,
                                       _sz]),
     "paro_rayleigh_ritz": (C.c_int32, [_vp, C.c_int32, C.c_int32, _vp, _vp, C.c_int64, _vp, _vp, _vp, _vp, _sz]),
     "paro_residual_norms": (C.c_int32, [_vp, C.c_int32, _vp, _vp, C.c_int64, _vp, _vp, _vp, _sz]),

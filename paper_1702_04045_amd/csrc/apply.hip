@@ -13,6 +13,8 @@
 // Stick buffer layout: [band][n3 mod N3][stick], so a z-plane of one band
 // is contiguous for the plane kernel and the stick kernels write rows of
 // consecutive sticks.
+#include <type_traits>
+
 #include "fft_device.h"
 #include "paro_internal.h"
 #include "reduce_device.h"
@@ -41,40 +43,41 @@ template <int T> __device__ __forceinline__ int line_of(int tid)
 template <int T> __device__ __forceinline__ int thread_in_line(int tid) { return (tid & 63) / (64 / T); }
 
 // threads of the plane kernel: one line slot per row, rounded up to whole wavefronts
-template <int N> constexpr int plane_threads() { return (N * PlaneCfg<N>::T + 63) / 64 * 64; }
+template <int N, class C2> constexpr int plane_threads() { return (N * PlaneCfgP<N, C2>::T + 63) / 64 * 64; }
 constexpr int kBandsPerBlock = 4;  // bands one work-group of the plane kernel takes through its z-plane
 
 // Sphere -> sticks, inverse transform along n3.  Line (stick) threads are
 // consecutive lanes, so the exchanges between passes are wavefront-local.
 // pbuf != null: PCG prologue, p <- z + beta p (first step: p <- z), the new p
 // is written back and transformed.  Otherwise src is transformed as is.
-template <int N3>
+template <int N3, class C2>
 __global__ void __launch_bounds__(kStickThreads)
-k_stick_inv(const double2 *__restrict__ src, int64_t ld, double2 *__restrict__ pbuf,
-            const double *__restrict__ beta, int first, double2 *__restrict__ sticks, int nst,
-            const int32_t *__restrict__ st_start, const int32_t *__restrict__ pt_sz,
-            const double2 *__restrict__ tw)
+k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const double *__restrict__ beta, int first,
+            C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ st_start, const int32_t *__restrict__ pt_sz,
+            const C2 *__restrict__ tw)
 {
     using C = FftCfg<N3>;
+    using S2 = RealOf<C2>;
     static_assert(cfg_ok<N3>(), "bad FFT config");
     constexpr int T = C::T, E = C::E, S = kStickThreads / T, LD = N3 + 1;
-    __shared__ double2 tile[S * LD];
+    __shared__ C2 tile[S * LD];
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
     const int s0 = blockIdx.x * S, band = blockIdx.y;
     const int s = s0 + sl;
     const bool act = s < nst;
-    for (int i = tid; i < S * LD; i += kStickThreads) tile[i] = make_double2(0.0, 0.0);
+    for (int i = tid; i < S * LD; i += kStickThreads) tile[i] = cmk<C2>(0.0, 0.0);
     __syncthreads();
     const int p0 = st_start[s0], p1 = st_start[min(s0 + S, nst)];
-    const double2 *x = src + band * ld;
-    double2 *pb = pbuf ? pbuf + band * ld : nullptr;
-    const double bt = (pbuf && !first) ? beta[band] : 0.0;
+    const C2 *x = src + band * ld;
+    C2 *pb = pbuf ? pbuf + band * ld : nullptr;
+    const S2 bt = (pbuf && !first) ? (S2)beta[band] : (S2)0;
     for (int idx = p0 + tid; idx < p1; idx += kStickThreads) {
-        double2 val = x[idx];
+        C2 val = x[idx];
         if (pb) {
             if (!first) {
-                const double2 po = pb[idx];
-                val = make_double2(val.x + bt * po.x, val.y + bt * po.y);
+                const C2 po = pb[idx];
+                val.x += bt * po.x;
+                val.y += bt * po.y;
             }
             pb[idx] = val;
         }
@@ -82,11 +85,11 @@ k_stick_inv(const double2 *__restrict__ src, int64_t ld, double2 *__restrict__ p
         tile[((sz >> 8) - s0) * LD + (sz & 255)] = val;
     }
     __syncthreads();
-    double2 v[E];
-    double2 *line = tile + sl * LD;
+    C2 v[E];
+    C2 *line = tile + sl * LD;
     if (act) pass_load<N3, T, E, ListInfo<typename C::Inv>::first>(v, t, [&](int i) { return line[i]; });
     stockham<N3, +1, true>(typename C::Inv{}, v, t, act, line, 1, tw);
-    double2 *out = sticks + (size_t)band * N3 * nst;
+    C2 *out = sticks + (size_t)band * N3 * nst;
     if (act)
         final_foreach<N3, T, E, ListInfo<typename C::Inv>::last>(
             v, t, [&](int i, int e) { out[(size_t)i * nst + s] = v[e]; });
@@ -109,19 +112,21 @@ k_stick_inv(const double2 *__restrict__ src, int64_t ld, double2 *__restrict__ p
 // stored in the order the row threads hold their values, so each thread
 // reads E consecutive doubles, which the bands of the work-group share
 // through the cache.
-template <int N>
-__global__ void __launch_bounds__(plane_threads<N>())
-k_plane(double2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restrict__ cols,
-        const double *__restrict__ vperm, int nmax1, const double2 *__restrict__ tw)
+template <int N, class C2>
+__global__ void __launch_bounds__((plane_threads<N, C2>()))
+__attribute__((amdgpu_waves_per_eu(PlaneCfgP<N, C2>::min_waves)))
+k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restrict__ cols,
+        const RealOf<C2> *__restrict__ vperm, int nmax1, const C2 *__restrict__ tw)
 {
-    using C = PlaneCfg<N>;
+    using VR = RealOf<C2>;
+    using C = PlaneCfgP<N, C2>;
     static_assert(C::T * C::E == N && ListInfo<typename C::Inv>::last == ListInfo<typename C::Fwd>::first,
                   "bad plane FFT config");
     using Inv = typename C::Inv;
     using Fwd = typename C::Fwd;
     constexpr int T = C::T, E = C::E, LDX = N + 1, HALF = N / 2;
     constexpr int RL = ListInfo<Inv>::last;
-    __shared__ double2 plane[N * LDX];
+    __shared__ C2 plane[N * LDX];
     const int tid = threadIdx.x;
     const int z = blockIdx.x;
     const int b0 = blockIdx.y * kBandsPerBlock, b1 = min(b0 + kBandsPerBlock, nb);
@@ -135,7 +140,7 @@ k_plane(double2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__
     int xcol = c - nmax1;
     xcol += xcol < 0 ? N : 0;
     const bool rowact = slot < N;
-    double2 *row = plane + (rowact ? slot : 0) * LDX;
+    C2 *row = plane + (rowact ? slot : 0) * LDX;
     int cst = 0, ylo = 0, cnt = 0;
     if (colact) {
         cst = cols[3 * c];
@@ -147,21 +152,21 @@ k_plane(double2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__
         const int k = (i > N / 2 ? i - N : i) - ylo;
         return (unsigned)k < (unsigned)cnt ? k : -1;
     };
-    const double *vp = vperm + (((size_t)z * N + (rowact ? slot : 0)) * T + t) * E;
+    const VR *vp = vperm + (((size_t)z * N + (rowact ? slot : 0)) * T + t) * E;
     for (int k = 0; k <= nbk; ++k) {
         // Opaque per band: keeps the compiler from hoisting the potential
         // loads and the per-element stick offsets out of the band loop,
         // which would hold them in registers across all stages.
         asm volatile("" : "+v"(ylo), "+v"(cnt), "+v"(vp));
-        double2 v[E];
+        C2 v[E];
         {
             // column phase: forward of band k-1 (lower), inverse of band k (upper)
             const int kb = lower ? k - 1 : k;
             const bool act = colact && kb >= 0 && kb < nbk;
             int xs = xcol + ((kb & 1) ? HALF : 0);
             xs -= xs >= N ? N : 0;
-            double2 *col = plane + (act ? xs : 0);
-            double2 *tz = sticks + ((size_t)(b0 + (act ? kb : 0)) * N3 + z) * nst + cst;
+            C2 *col = plane + (act ? xs : 0);
+            C2 *tz = sticks + ((size_t)(b0 + (act ? kb : 0)) * N3 + z) * nst + cst;
             if (lower) {
                 if (act) pass_load<N, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return col[i * LDX]; });
                 stockham_c<C, -1, true>(Fwd{}, v, t, act, col, LDX, tw);
@@ -172,7 +177,7 @@ k_plane(double2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__
             } else {
                 if (act) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
                     const int q = stick_of(i);
-                    return q >= 0 ? tz[q] : make_double2(0.0, 0.0);
+                    return q >= 0 ? tz[q] : cmk<C2>(0.0, 0.0);
                 });
                 stockham_c<C, +1, true>(Inv{}, v, t, act, col, LDX, tw);
                 wave_lds_sync();
@@ -190,11 +195,11 @@ k_plane(double2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__
                 int x = i + sh;
                 return x - (x >= N ? N : 0);
             };
-            double vr[E];
+            VR vr[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) vr[e] = vp[e];
             if (rowact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
-                return (i <= nmax1 || i >= N - nmax1) ? row[at(i)] : make_double2(0.0, 0.0);
+                return (i <= nmax1 || i >= N - nmax1) ? row[at(i)] : cmk<C2>(0.0, 0.0);
             });
             stockham_c<C, +1, true>(Inv{}, v, t, rowact, row, 1, tw);
 #pragma unroll
@@ -212,10 +217,10 @@ k_plane(double2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__
 // Potential in the row-thread order of k_plane<N>: out[((z N + y) T + t) E + e]
 // = V(i1 = x(t, e), i2 = y, i3 = z), x(t, e) = t + T (e / RL) + (e % RL)(N / RL),
 // from vloc in C order [i1][i2][i3].
-template <int N>
-void plane_potential(const int32_t *grid, const double *vloc, double *out)
+template <int N, class VT>
+void plane_potential(const int32_t *grid, const double *vloc, VT *out)
 {
-    using C = PlaneCfg<N>;
+    using C = PlaneCfgP<N, typename std::conditional<std::is_same<VT, float>::value, float2, double2>::type>;
     constexpr int T = C::T, E = C::E, RL = ListInfo<typename C::Inv>::last;
     const int N2 = grid[1], N3 = grid[2];
     for (int z = 0; z < N3; ++z)
@@ -223,32 +228,32 @@ void plane_potential(const int32_t *grid, const double *vloc, double *out)
             for (int t = 0; t < T; ++t)
                 for (int e = 0; e < E; ++e) {
                     const int x = t + T * (e / RL) + (e % RL) * (N / RL);
-                    out[(((size_t)z * N + y) * T + t) * E + e] = vloc[((size_t)x * N2 + y) * N3 + z];
+                    out[(((size_t)z * N + y) * T + t) * E + e] = (VT)vloc[((size_t)x * N2 + y) * N3 + z];
                 }
 }
 
 // Sticks -> sphere, forward transform along n3, then
 // out = scale * local + (kin - shift_b) x; dot_part gets sum Re(conj(x) out).
-template <int N3>
+template <int N3, class C2>
 __global__ void __launch_bounds__(kStickThreads)
-k_stick_fwd(const double2 *__restrict__ sticks, int nst, const int32_t *__restrict__ st_start,
-            const int32_t *__restrict__ pt_sz, const double2 *__restrict__ tw,
-            const double2 *__restrict__ xin, int64_t ld, double2 *__restrict__ out,
-            const double *__restrict__ kin, const double *__restrict__ shift, double scale,
+k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ st_start,
+            const int32_t *__restrict__ pt_sz, const C2 *__restrict__ tw, const C2 *__restrict__ xin, int64_t ld,
+            C2 *__restrict__ out, const double *__restrict__ kin, const double *__restrict__ shift, double scale,
             double *__restrict__ dot_part, int part_stride)
 {
     using C = FftCfg<N3>;
     using Fwd = typename C::Fwd;
+    using S2 = RealOf<C2>;
     constexpr int T = C::T, E = C::E, S = kStickThreads / T, LD = N3 + 1;
-    __shared__ double2 tile[S * LD];
+    __shared__ C2 tile[S * LD];
     __shared__ double red[kStickThreads / 64];
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
     const int s0 = blockIdx.x * S, band = blockIdx.y;
     const int s = s0 + sl;
     const bool act = s < nst;
-    const double2 *in = sticks + (size_t)band * N3 * nst;
-    double2 v[E];
-    double2 *line = tile + sl * LD;
+    const C2 *in = sticks + (size_t)band * N3 * nst;
+    C2 v[E];
+    C2 *line = tile + sl * LD;
     if (act) pass_load<N3, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return in[(size_t)i * nst + s]; });
     stockham<N3, -1, true>(Fwd{}, v, t, act, line, 1, tw);
     wave_lds_sync();
@@ -256,17 +261,20 @@ k_stick_fwd(const double2 *__restrict__ sticks, int nst, const int32_t *__restri
     __syncthreads();
     const int p0 = st_start[s0], p1 = st_start[min(s0 + S, nst)];
     const double sig = shift ? shift[band] : 0.0;
-    const double2 *x = xin + band * ld;
-    double2 *o = out + band * ld;
+    const C2 *x = xin + band * ld;
+    C2 *o = out + band * ld;
+    const S2 sc = (S2)scale;
     double dot = 0.0;
     for (int idx = p0 + tid; idx < p1; idx += kStickThreads) {
         const int sz = pt_sz[idx];
-        const double2 loc = tile[((sz >> 8) - s0) * LD + (sz & 255)];
-        const double2 xv = x[idx];
-        const double k = kin[idx] - sig;
-        const double2 r = make_double2(loc.x * scale + k * xv.x, loc.y * scale + k * xv.y);
+        const C2 loc = tile[((sz >> 8) - s0) * LD + (sz & 255)];
+        const C2 xv = x[idx];
+        const S2 k = (S2)(kin[idx] - sig);
+        C2 r;
+        r.x = loc.x * sc + k * xv.x;
+        r.y = loc.y * sc + k * xv.y;
         o[idx] = r;
-        dot += xv.x * r.x + xv.y * r.y;
+        dot += (double)xv.x * (double)r.x + (double)xv.y * (double)r.y;
     }
     if (dot_part) {
         dot = block_sum<kStickThreads>(dot, red);
@@ -274,9 +282,20 @@ k_stick_fwd(const double2 *__restrict__ sticks, int nst, const int32_t *__restri
     }
 }
 
-template <int N>
-hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const double2 *src, int64_t ld, double2 *out,
-                     const double *shift, double2 *pbuf, const double *beta, bool first, double *dot_part,
+// Precision-specific plan tables.
+template <class C2> struct PlanTabs;
+template <> struct PlanTabs<double2> {
+    static const double2 *tw(const Plan &pl, int d) { return pl.tw[d]; }
+    static const double *v(const Plan &pl) { return pl.vplane; }
+};
+template <> struct PlanTabs<float2> {
+    static const float2 *tw(const Plan &pl, int d) { return pl.tw32[d]; }
+    static const float *v(const Plan &pl) { return pl.vplane32; }
+};
+
+template <int N, class C2>
+hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const C2 *src, int64_t ld, C2 *out,
+                     const double *shift, C2 *pbuf, const double *beta, bool first, double *dot_part,
                      int *nparts_out)
 {
     constexpr int S = kStickThreads / FftCfg<N>::T;
@@ -284,27 +303,44 @@ hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const double2 *
     const int ntiles = (pl.nst + S - 1) / S;
     if (nparts_out) *nparts_out = ntiles;
     const double scale = 1.0 / ((double)pl.grid[0] * pl.grid[1] * pl.grid[2]);
+    C2 *sticks = reinterpret_cast<C2 *>(w.sticks);
     for (int c0 = 0; c0 < nb; c0 += kMaxBandsPerChunk) {
         const int cb = min(kMaxBandsPerChunk, nb - c0);
         prof_mark(PARO_K_STICK_INV, pl.stream, true);
-        hipLaunchKernelGGL(k_stick_inv<N>, dim3(ntiles, cb), dim3(kStickThreads), 0, pl.stream,
+        hipLaunchKernelGGL((k_stick_inv<N, C2>), dim3(ntiles, cb), dim3(kStickThreads), 0, pl.stream,
                            src + c0 * ld, ld, pbuf ? pbuf + c0 * ld : nullptr, beta ? beta + c0 : nullptr,
-                           first ? 1 : 0, w.sticks, pl.nst, pl.st_start, pl.pt_sz, pl.tw[2]);
+                           first ? 1 : 0, sticks, pl.nst, pl.st_start, pl.pt_sz, PlanTabs<C2>::tw(pl, 2));
         prof_mark(PARO_K_STICK_INV, pl.stream, false);
         prof_mark(PARO_K_PLANE, pl.stream, true);
-        hipLaunchKernelGGL(k_plane<N>, dim3(N3, (cb + kBandsPerBlock - 1) / kBandsPerBlock),
-                           dim3(plane_threads<N>()), 0, pl.stream, w.sticks, pl.nst, N3, cb, pl.cols, pl.vplane,
-                           pl.nmax[0], pl.tw[0]);
+        hipLaunchKernelGGL((k_plane<N, C2>), dim3(N3, (cb + kBandsPerBlock - 1) / kBandsPerBlock),
+                           dim3(plane_threads<N, C2>()), 0, pl.stream, sticks, pl.nst, N3, cb, pl.cols,
+                           PlanTabs<C2>::v(pl), pl.nmax[0], PlanTabs<C2>::tw(pl, 0));
         prof_mark(PARO_K_PLANE, pl.stream, false);
-        const double2 *x = pbuf ? pbuf : src;
+        const C2 *x = pbuf ? pbuf : src;
         prof_mark(PARO_K_STICK_FWD, pl.stream, true);
-        hipLaunchKernelGGL(k_stick_fwd<N>, dim3(ntiles, cb), dim3(kStickThreads), 0, pl.stream, w.sticks, pl.nst,
-                           pl.st_start, pl.pt_sz, pl.tw[2], x + c0 * ld, ld, out + c0 * ld, pl.kin,
-                           shift ? shift + c0 : nullptr, scale, dot_part ? dot_part + (size_t)c0 * kMaxParts : nullptr,
-                           kMaxParts);
+        hipLaunchKernelGGL((k_stick_fwd<N, C2>), dim3(ntiles, cb), dim3(kStickThreads), 0, pl.stream, sticks,
+                           pl.nst, pl.st_start, pl.pt_sz, PlanTabs<C2>::tw(pl, 2), x + c0 * ld, ld, out + c0 * ld,
+                           pl.kin, shift ? shift + c0 : nullptr, scale,
+                           dot_part ? dot_part + (size_t)c0 * kMaxParts : nullptr, kMaxParts);
         prof_mark(PARO_K_STICK_FWD, pl.stream, false);
     }
     return hipGetLastError();
+}
+
+template <class C2>
+hipError_t local_apply(const Plan &pl, const Workspace &w, int nb, const C2 *src, int64_t ld, C2 *out,
+                       const double *shift, C2 *pbuf, const double *beta, bool first, double *dot_part,
+                       int *nparts_out)
+{
+    // the kernels are instantiated for cubic grids N1 = N2 = N3
+    switch (pl.grid[0]) {
+#define PARO_CASE(n) \
+    case n: return run_local<n, C2>(pl, w, nb, src, ld, out, shift, pbuf, beta, first, dot_part, nparts_out);
+    PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
+    PARO_CASE(80) PARO_CASE(96)
+#undef PARO_CASE
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -317,11 +353,11 @@ bool fft_supported(int n)
     }
 }
 
-void build_plane_potential(int n, const int32_t *grid, const double *vloc, double *out)
+template <class VT> static void build_plane_potential_t(int n, const int32_t *grid, const double *vloc, VT *out)
 {
     switch (n) {
 #define PARO_CASE(k) \
-    case k: plane_potential<k>(grid, vloc, out); break;
+    case k: plane_potential<k, VT>(grid, vloc, out); break;
     PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
     PARO_CASE(80) PARO_CASE(96)
 #undef PARO_CASE
@@ -329,19 +365,28 @@ void build_plane_potential(int n, const int32_t *grid, const double *vloc, doubl
     }
 }
 
+void build_plane_potential(int n, const int32_t *grid, const double *vloc, double *out)
+{
+    build_plane_potential_t(n, grid, vloc, out);
+}
+
+void build_plane_potential(int n, const int32_t *grid, const double *vloc, float *out)
+{
+    build_plane_potential_t(n, grid, vloc, out);
+}
+
 hipError_t launch_local_apply(const Plan &pl, const Workspace &w, int nb, const double2 *src, int64_t ld,
                               double2 *out, const double *shift, double2 *pbuf, const double *beta, bool first,
                               double *dot_part, int *nparts_out)
 {
-    // the kernels are instantiated for cubic grids N1 = N2 = N3
-    switch (pl.grid[0]) {
-#define PARO_CASE(n) \
-    case n: return run_local<n>(pl, w, nb, src, ld, out, shift, pbuf, beta, first, dot_part, nparts_out);
-    PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
-    PARO_CASE(80) PARO_CASE(96)
-#undef PARO_CASE
-    default: return hipErrorInvalidValue;
-    }
+    return local_apply<double2>(pl, w, nb, src, ld, out, shift, pbuf, beta, first, dot_part, nparts_out);
+}
+
+hipError_t launch_local_apply(const Plan &pl, const Workspace &w, int nb, const float2 *src, int64_t ld, float2 *out,
+                              const double *shift, float2 *pbuf, const double *beta, bool first, double *dot_part,
+                              int *nparts_out)
+{
+    return local_apply<float2>(pl, w, nb, src, ld, out, shift, pbuf, beta, first, dot_part, nparts_out);
 }
 
 }  // namespace paro

@@ -1,4 +1,5 @@
-// Batched mixed-radix FFT lines for gfx950, double precision complex.
+// Batched mixed-radix FFT lines for gfx950, double (double2) or single
+// (float2) precision complex.
 //
 // A line of length N is owned by T consecutive "line threads"; each holds
 // E = N / T elements in registers.  The transform is a Stockham autosort
@@ -23,10 +24,30 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-// SIGN * i * a
-template <int SIGN> __device__ __forceinline__ double2 mul_si(double2 a)
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
-    return SIGN > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// complex value of type C2 (double2 or float2) from two doubles
+template <class C2> __device__ __forceinline__ C2 cmk(double x, double y);
+template <> __device__ __forceinline__ double2 cmk<double2>(double x, double y) { return make_double2(x, y); }
+template <> __device__ __forceinline__ float2 cmk<float2>(double x, double y) { return make_float2((float)x, (float)y); }
+template <class C2> using RealOf = decltype(C2{}.x);
+// SIGN * i * a
+template <int SIGN, class C2> __device__ __forceinline__ C2 mul_si(C2 a)
+{
+    C2 r;
+    if (SIGN > 0) {
+        r.x = -a.y;
+        r.y = a.x;
+    } else {
+        r.x = a.y;
+        r.y = -a.x;
+    }
+    return r;
 }
 
 // cos / sin (2 pi j / R), j < R, correctly rounded literals.
@@ -98,29 +119,33 @@ template <> struct TwC<20> {
 };
 
 // ---------------------------------------------------------------- radix-R DFTs
+// Dft<R, SIGN>::run(v): in-place R-point DFT of v[0..R) (double2 or float2).
 template <int R, int SIGN> struct Dft;
 
 template <int SIGN> struct Dft<1, SIGN> {
-    static __device__ __forceinline__ void run(double2 *) {}
+    template <class C2> static __device__ __forceinline__ void run(C2 *) {}
 };
 
 template <int SIGN> struct Dft<2, SIGN> {
-    static __device__ __forceinline__ void run(double2 *v)
+    template <class C2> static __device__ __forceinline__ void run(C2 *v)
     {
-        double2 a = v[0], b = v[1];
+        C2 a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
     }
 };
 
 template <int SIGN> struct Dft<3, SIGN> {
-    static __device__ __forceinline__ void run(double2 *v)
+    template <class C2> static __device__ __forceinline__ void run(C2 *v)
     {
-        const double h = 0.8660254037844386467637;  // sin(2 pi / 3)
-        double2 t1 = cadd(v[1], v[2]);
-        double2 t2 = make_double2(v[0].x - 0.5 * t1.x, v[0].y - 0.5 * t1.y);
-        double2 t3 = cscale(csub(v[1], v[2]), h);
-        double2 it3 = mul_si<SIGN>(t3);
+        using S = RealOf<C2>;
+        const S h = (S)0.8660254037844386467637;  // sin(2 pi / 3)
+        C2 t1 = cadd(v[1], v[2]);
+        C2 t2;
+        t2.x = v[0].x - (S)0.5 * t1.x;
+        t2.y = v[0].y - (S)0.5 * t1.y;
+        C2 t3 = cscale(csub(v[1], v[2]), h);
+        C2 it3 = mul_si<SIGN>(t3);
         v[0] = cadd(v[0], t1);
         v[1] = cadd(t2, it3);
         v[2] = csub(t2, it3);
@@ -128,10 +153,10 @@ template <int SIGN> struct Dft<3, SIGN> {
 };
 
 template <int SIGN> struct Dft<4, SIGN> {
-    static __device__ __forceinline__ void run(double2 *v)
+    template <class C2> static __device__ __forceinline__ void run(C2 *v)
     {
-        double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
-        double2 c = cadd(v[1], v[3]), d = mul_si<SIGN>(csub(v[1], v[3]));
+        C2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+        C2 c = cadd(v[1], v[3]), d = mul_si<SIGN>(csub(v[1], v[3]));
         v[0] = cadd(a, c);
         v[2] = csub(a, c);
         v[1] = cadd(b, d);
@@ -140,17 +165,25 @@ template <int SIGN> struct Dft<4, SIGN> {
 };
 
 template <int SIGN> struct Dft<5, SIGN> {
-    static __device__ __forceinline__ void run(double2 *v)
+    template <class C2> static __device__ __forceinline__ void run(C2 *v)
     {
-        const double c1 = 0.3090169943749474241023, c2 = -0.8090169943749474241023;
-        const double s1 = 0.9510565162951535721164, s2 = 0.5877852522924731291687;
-        double2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
-        double2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
-        double2 x0 = v[0];
-        double2 p1 = make_double2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
-        double2 p2 = make_double2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
-        double2 q1 = mul_si<SIGN>(make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y));
-        double2 q2 = mul_si<SIGN>(make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y));
+        using S = RealOf<C2>;
+        const S c1 = (S)0.3090169943749474241023, c2 = (S)-0.8090169943749474241023;
+        const S s1 = (S)0.9510565162951535721164, s2 = (S)0.5877852522924731291687;
+        C2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+        C2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+        C2 x0 = v[0];
+        C2 p1, p2, q1, q2;
+        p1.x = x0.x + c1 * a1.x + c2 * a2.x;
+        p1.y = x0.y + c1 * a1.y + c2 * a2.y;
+        p2.x = x0.x + c2 * a1.x + c1 * a2.x;
+        p2.y = x0.y + c2 * a1.y + c1 * a2.y;
+        q1.x = s1 * b1.x + s2 * b2.x;
+        q1.y = s1 * b1.y + s2 * b2.y;
+        q2.x = s2 * b1.x - s1 * b2.x;
+        q2.y = s2 * b1.y - s1 * b2.y;
+        q1 = mul_si<SIGN>(q1);
+        q2 = mul_si<SIGN>(q2);
         v[0] = cadd(x0, cadd(a1, a2));
         v[1] = cadd(p1, q1);
         v[4] = csub(p1, q1);
@@ -162,13 +195,14 @@ template <int SIGN> struct Dft<5, SIGN> {
 // R = A B: A-point DFTs over s_a of x[B s_a + s_b], twiddle by w_R^(s_b k_a),
 // then B-point DFTs over s_b; output index k_a + A k_b.
 template <int A, int B, int SIGN> struct DftComp {
-    static __device__ __forceinline__ void run(double2 *v)
+    template <class C2> static __device__ __forceinline__ void run(C2 *v)
     {
+        using S = RealOf<C2>;
         constexpr int R = A * B;
-        double2 y[R];
+        C2 y[R];
 #pragma unroll
         for (int sb = 0; sb < B; ++sb) {
-            double2 a[A];
+            C2 a[A];
 #pragma unroll
             for (int sa = 0; sa < A; ++sa) a[sa] = v[B * sa + sb];
             Dft<A, SIGN>::run(a);
@@ -177,14 +211,17 @@ template <int A, int B, int SIGN> struct DftComp {
         }
 #pragma unroll
         for (int ka = 0; ka < A; ++ka) {
-            double2 b[B];
+            C2 b[B];
 #pragma unroll
             for (int sb = 0; sb < B; ++sb) {
                 const int j = sb * ka;
-                double2 x = y[sb * A + ka];
+                C2 x = y[sb * A + ka];
                 if (j != 0) {
-                    const double c = TwC<R>::c[j], s = SIGN * TwC<R>::s[j];
-                    x = make_double2(x.x * c - x.y * s, x.x * s + x.y * c);
+                    const S c = (S)TwC<R>::c[j], s = (S)(SIGN * TwC<R>::s[j]);
+                    C2 t;
+                    t.x = x.x * c - x.y * s;
+                    t.y = x.x * s + x.y * c;
+                    x = t;
                 }
                 b[sb] = x;
             }
@@ -230,8 +267,8 @@ template <int... Rs> struct ListInfo<RList<Rs...>> {
 };
 
 // Inputs of a radix-R pass: v[q R + r] <- x[t + T q + r N/R].
-template <int N, int T, int E, int R, class F>
-__device__ __forceinline__ void pass_load(double2 (&v)[E], int t, F &&f)
+template <int N, int T, int E, int R, class C2, class F>
+__device__ __forceinline__ void pass_load(C2 (&v)[E], int t, F &&f)
 {
 #pragma unroll
     for (int q = 0; q < E / R; ++q)
@@ -240,8 +277,8 @@ __device__ __forceinline__ void pass_load(double2 (&v)[E], int t, F &&f)
 }
 
 // Outputs of a radix-R pass at stride NS: v[q R + r] -> y[(j/NS) NS R + j%NS + r NS].
-template <int N, int T, int E, int R, int NS, class F>
-__device__ __forceinline__ void pass_store(const double2 (&v)[E], int t, F &&f)
+template <int N, int T, int E, int R, int NS, class C2, class F>
+__device__ __forceinline__ void pass_store(const C2 (&v)[E], int t, F &&f)
 {
 #pragma unroll
     for (int q = 0; q < E / R; ++q) {
@@ -253,8 +290,8 @@ __device__ __forceinline__ void pass_store(const double2 (&v)[E], int t, F &&f)
 }
 
 // Final outputs (after a last pass of radix RL): v[q RL + r] is element t + T q + r N/RL.
-template <int N, int T, int E, int RL, class F>
-__device__ __forceinline__ void final_foreach(const double2 (&v)[E], int t, F &&f)
+template <int N, int T, int E, int RL, class C2, class F>
+__device__ __forceinline__ void final_foreach(const C2 (&v)[E], int t, F &&f)
 {
 #pragma unroll
     for (int q = 0; q < E / RL; ++q)
@@ -262,9 +299,9 @@ __device__ __forceinline__ void final_foreach(const double2 (&v)[E], int t, F &&
         for (int r = 0; r < RL; ++r) f(t + T * q + r * (N / RL), q * RL + r);
 }
 
-// tw[m] = exp(-2 pi i m / N); SIGN = +1 uses the conjugate.
-template <int N, int T, int E, int R, int NS, int SIGN>
-__device__ __forceinline__ void pass_compute(double2 (&v)[E], int t, const double2 *__restrict__ tw)
+// tw[m] = exp(-2 pi i m / N) (same precision as v); SIGN = +1 uses the conjugate.
+template <int N, int T, int E, int R, int NS, int SIGN, class C2>
+__device__ __forceinline__ void pass_compute(C2 (&v)[E], int t, const C2 *__restrict__ tw)
 {
 #pragma unroll
     for (int q = 0; q < E / R; ++q) {
@@ -273,7 +310,7 @@ __device__ __forceinline__ void pass_compute(double2 (&v)[E], int t, const doubl
             const int k = j % NS;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                double2 w = tw[r * k * (N / (NS * R))];
+                C2 w = tw[r * k * (N / (NS * R))];
                 if (SIGN > 0) w.y = -w.y;
                 v[q * R + r] = cmul(v[q * R + r], w);
             }
@@ -301,9 +338,8 @@ template <bool WL> __device__ __forceinline__ void line_sync()
     else __syncthreads();
 }
 
-template <int N, int T, int E, int SIGN, bool WL, int NS, int R, int... Rest>
-__device__ __forceinline__ void stockham_rec(double2 (&v)[E], int t, bool act, double2 *line, int es,
-                                             const double2 *tw)
+template <int N, int T, int E, int SIGN, bool WL, int NS, int R, int... Rest, class C2>
+__device__ __forceinline__ void stockham_rec(C2 (&v)[E], int t, bool act, C2 *line, int es, const C2 *tw)
 {
     // A fresh copy of the table pointer per pass keeps the compiler from
     // loading the twiddles of later passes (or other transforms) up front,
@@ -314,7 +350,7 @@ __device__ __forceinline__ void stockham_rec(double2 (&v)[E], int t, bool act, d
     if constexpr (sizeof...(Rest) > 0) {
         constexpr int R2 = FirstOf<Rest...>::value;
         line_sync<WL>();
-        if (act) pass_store<N, T, E, R, NS>(v, t, [&](int i, double2 x) { line[i * es] = x; });
+        if (act) pass_store<N, T, E, R, NS>(v, t, [&](int i, C2 x) { line[i * es] = x; });
         line_sync<WL>();
         if (act) pass_load<N, T, E, R2>(v, t, [&](int i) { return line[i * es]; });
         stockham_rec<N, T, E, SIGN, WL, NS * R, Rest...>(v, t, act, line, es, tw);
@@ -328,19 +364,19 @@ __device__ __forceinline__ void stockham_rec(double2 (&v)[E], int t, bool act, d
 // contains work-group barriers; act = false threads only take part in
 // them).  WL = true: the T threads of each line are consecutive lanes of one
 // wavefront and only wavefront-level ordering is used.
-template <class Cfg, int SIGN, bool WL = false, int... Rs>
-__device__ __forceinline__ void stockham_c(RList<Rs...>, double2 (&v)[Cfg::E], int t, bool act, double2 *line,
-                                           int es, const double2 *__restrict__ tw)
+template <class Cfg, int SIGN, bool WL = false, int... Rs, class C2>
+__device__ __forceinline__ void stockham_c(RList<Rs...>, C2 (&v)[Cfg::E], int t, bool act, C2 *line, int es,
+                                           const C2 *__restrict__ tw)
 {
     static_assert(!WL || 64 % Cfg::T == 0, "wave-local lines need T | 64");
-    const double2 *twl = tw;
+    const C2 *twl = tw;
     asm volatile("" : "+s"(twl));
     stockham_rec<Cfg::N, Cfg::T, Cfg::E, SIGN, WL, 1, Rs...>(v, t, act, line, es, twl);
 }
 
-template <int N, int SIGN, bool WL = false, int... Rs>
-__device__ __forceinline__ void stockham(RList<Rs...> l, double2 (&v)[FftCfg<N>::E], int t, bool act,
-                                         double2 *line, int es, const double2 *__restrict__ tw)
+template <int N, int SIGN, bool WL = false, int... Rs, class C2>
+__device__ __forceinline__ void stockham(RList<Rs...> l, C2 (&v)[FftCfg<N>::E], int t, bool act, C2 *line, int es,
+                                         const C2 *__restrict__ tw)
 {
     stockham_c<FftCfg<N>, SIGN, WL>(l, v, t, act, line, es, tw);
 }
@@ -348,11 +384,23 @@ __device__ __forceinline__ void stockham(RList<Rs...> l, double2 (&v)[FftCfg<N>:
 // Line schedule of the z-plane kernel (defaults to FftCfg).  For 96 points
 // 8 threads per line (12 work-group waves) with passes 4 x 6 x 4 measured
 // fastest among 4 x 24 and 8 x 12 splits of the lines.
-template <int N> struct PlaneCfg : FftCfg<N> {};
+template <int N> struct PlaneCfg : FftCfg<N> {
+    static constexpr int min_waves = 1;  // waves per SIMD the register budget must allow
+};
 template <> struct PlaneCfg<96> {
-    static constexpr int N = 96, T = 8, E = 12;
+    static constexpr int N = 96, T = 8, E = 12, min_waves = 1;
     using Inv = RList<4, 6, 4>;
     using Fwd = RList<4, 6, 4>;
+};
+// Per precision: in single precision the 96-point plane uses 4 threads per
+// line and two passes (12 x 8, one LDS exchange); measured faster than 8
+// threads per line, and than capping registers so that two 75 KB
+// work-groups share a compute unit.
+template <int N, class C2> struct PlaneCfgP : PlaneCfg<N> {};
+template <> struct PlaneCfgP<96, float2> {
+    static constexpr int N = 96, T = 4, E = 24, min_waves = 1;
+    using Inv = RList<12, 8>;
+    using Fwd = RList<8, 12>;
 };
 
 }  // namespace paro

@@ -1,9 +1,11 @@
 // Complex double GEMMs on the FP64 matrix cores of gfx950, and the device
 // construction of the Kleinman-Bylander projector matrix.
 //
-// Every complex product is four real v_mfma_f64_16x16x4f64 products.  For
-// that instruction lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
-// (a 16 x 4 by 4 x 16 step) and holds D[l / 16 + 4 v][l % 16], v < 4.
+// Every complex product is four real matrix-core products: 16 x 4 by 4 x 16
+// steps of v_mfma_f64_16x16x4f64 (double2 operands) or
+// v_mfma_f32_16x16x4f32 (float2 operands).  Lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; it holds D[l / 16 + 4 v][l % 16], v < 4, for the
+// FP64 instruction and D[4 (l / 16) + v][l % 16] for the FP32 one.
 //
 // gemm_hn: C = A^H B with a long contraction (projector coefficients
 // P = B^H psi, Gram matrices U^H U and U^H W of Rayleigh-Ritz).  The
@@ -15,17 +17,34 @@
 // consecutive rows of C: stores are coalesced along the sphere.
 #include <cmath>
 
+#include "fft_device.h"
 #include "paro_internal.h"
 #include "reduce_device.h"
 
 namespace paro {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// accumulator type and output row of lane group lk, element v
+template <class C2> struct Mma;
+template <> struct Mma<double2> {
+    using Acc = d4;
+    static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <> struct Mma<float2> {
+    using Acc = f4;
+    static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
 
 namespace {
 
@@ -36,37 +55,40 @@ constexpr int kDepthHN = 8;
 constexpr int kDepthNN = 4;
 
 // partial[s][j][i] = sum over k in split s of conj(A[k][i]) B[k][j]
+// (accumulated in the operands' precision, stored in FP64)
+template <class C2>
 __global__ void __launch_bounds__(256)
-k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, const double2 *__restrict__ A, int64_t lda,
-               const double2 *__restrict__ B, int64_t ldb, double2 *__restrict__ part)
+k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, const C2 *__restrict__ A, int64_t lda,
+               const C2 *__restrict__ B, int64_t ldb, double2 *__restrict__ part)
 {
+    using Acc = typename Mma<C2>::Acc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i0 = blockIdx.x * kTile + (wave & 1) * 32;
     const int j0 = blockIdx.y * kTile + (wave >> 1) * 32;
     const int64_t kb = (int64_t)blockIdx.z * kchunk;
     const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
     const int l16 = lane & 15, lk = lane >> 4;
-    d4 re[2][2], im[2][2];
+    Acc re[2][2], im[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            re[a][b] = d4{0, 0, 0, 0};
-            im[a][b] = d4{0, 0, 0, 0};
+            re[a][b] = Acc{0, 0, 0, 0};
+            im[a][b] = Acc{0, 0, 0, 0};
         }
     const int ia[2] = {i0 + l16, i0 + 16 + l16};
     const int jb[2] = {j0 + l16, j0 + 16 + l16};
     // Register prefetch ring: the operands of k-step s + kDepthHN - 1 are
     // requested before the products of step s, so that their latency
     // overlaps kDepthHN - 1 steps of matrix-core work.
-    double2 a[kDepthHN][2], b[kDepthHN][2];
+    C2 a[kDepthHN][2], b[kDepthHN][2];
     auto load = [&](int slot, int64_t k0) {
         const int64_t kk = k0 + lk;
         const bool kv = kk < ke;
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            a[slot][u] = (kv && ia[u] < M) ? A[(int64_t)ia[u] * lda + kk] : make_double2(0.0, 0.0);
-            b[slot][u] = (kv && jb[u] < N) ? B[(int64_t)jb[u] * ldb + kk] : make_double2(0.0, 0.0);
+            a[slot][u] = (kv && ia[u] < M) ? A[(int64_t)ia[u] * lda + kk] : C2{0, 0};
+            b[slot][u] = (kv && jb[u] < N) ? B[(int64_t)jb[u] * ldb + kk] : C2{0, 0};
         }
     };
     auto step = [&](int slot) {
@@ -97,15 +119,16 @@ k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, const double2 *__restric
         for (int w = 0; w < 2; ++w)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = i0 + u * 16 + lk + 4 * v;
+                const int i = i0 + u * 16 + Mma<C2>::row(lk, v);
                 const int j = j0 + w * 16 + l16;
                 if (i < M && j < N) P[(size_t)j * M + i] = make_double2(re[u][w][v], im[u][w][v]);
             }
 }
 
 // C[i][j] = dscale_i * sum_s part[s][j][i]; quad_j = sum_i dscale_i |sum_s part|^2
+template <class CO>
 __global__ void __launch_bounds__(256)
-k_gemm_hn_reduce(int M, int N, int nsplit, const double2 *__restrict__ part, double2 *__restrict__ C, int64_t ldc,
+k_gemm_hn_reduce(int M, int N, int nsplit, const double2 *__restrict__ part, CO *__restrict__ C, int64_t ldc,
                  const double *__restrict__ dscale, double *__restrict__ quad)
 {
     __shared__ double red[4];
@@ -124,7 +147,7 @@ k_gemm_hn_reduce(int M, int N, int nsplit, const double2 *__restrict__ part, dou
             s.x *= d;
             s.y *= d;
         }
-        C[(int64_t)j * ldc + i] = s;
+        C[(int64_t)j * ldc + i] = cmk<CO>(s.x, s.y);
     }
     if (quad) {
         q = block_sum<256>(q, red);
@@ -133,33 +156,35 @@ k_gemm_hn_reduce(int M, int N, int nsplit, const double2 *__restrict__ part, dou
 }
 
 // C[g][n] (+)= sum_k A[g][k] B[k][n]; matrix-core rows = n, columns = g.
+template <class C2>
 __global__ void __launch_bounds__(256)
-k_gemm_nn(int64_t M, int N, int K, const double2 *__restrict__ A, int64_t lda, const double2 *__restrict__ B,
-          int64_t ldb, double2 *__restrict__ C, int64_t ldc, int accumulate)
+k_gemm_nn(int64_t M, int N, int K, const C2 *__restrict__ A, int64_t lda, const C2 *__restrict__ B, int64_t ldb,
+          C2 *__restrict__ C, int64_t ldc, int accumulate)
 {
+    using Acc = typename Mma<C2>::Acc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t g0 = (int64_t)blockIdx.x * kTile + (wave & 1) * 32;
     const int n0 = blockIdx.y * kTile + (wave >> 1) * 32;
     const int l16 = lane & 15, lk = lane >> 4;
-    d4 re[2][2], im[2][2];
+    Acc re[2][2], im[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            re[a][b] = d4{0, 0, 0, 0};
-            im[a][b] = d4{0, 0, 0, 0};
+            re[a][b] = Acc{0, 0, 0, 0};
+            im[a][b] = Acc{0, 0, 0, 0};
         }
     const int nb_[2] = {n0 + l16, n0 + 16 + l16};
     const int64_t gg[2] = {g0 + l16, g0 + 16 + l16};
     // register prefetch ring, as in k_gemm_hn_part
-    double2 x[kDepthNN][2], y[kDepthNN][2];
+    C2 x[kDepthNN][2], y[kDepthNN][2];
     auto load = [&](int slot, int k0) {
         const int kk = k0 + lk;
         const bool kv = kk < K;
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            x[slot][u] = (kv && nb_[u] < N) ? B[(int64_t)nb_[u] * ldb + kk] : make_double2(0.0, 0.0);
-            y[slot][u] = (kv && gg[u] < M) ? A[(int64_t)kk * lda + gg[u]] : make_double2(0.0, 0.0);
+            x[slot][u] = (kv && nb_[u] < N) ? B[(int64_t)nb_[u] * ldb + kk] : C2{0, 0};
+            y[slot][u] = (kv && gg[u] < M) ? A[(int64_t)kk * lda + gg[u]] : C2{0, 0};
         }
     };
     auto step = [&](int slot) {
@@ -189,13 +214,15 @@ k_gemm_nn(int64_t M, int N, int K, const double2 *__restrict__ A, int64_t lda, c
         for (int w = 0; w < 2; ++w)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int n = n0 + u * 16 + lk + 4 * v;
+                const int n = n0 + u * 16 + Mma<C2>::row(lk, v);
                 const int64_t g = g0 + w * 16 + l16;
                 if (n < N && g < M) {
-                    double2 *c = C + (int64_t)n * ldc + g;
-                    double2 r = make_double2(re[u][w][v], im[u][w][v]);
+                    C2 *c = C + (int64_t)n * ldc + g;
+                    C2 r;
+                    r.x = re[u][w][v];
+                    r.y = im[u][w][v];
                     if (accumulate) {
-                        const double2 o = *c;
+                        const C2 o = *c;
                         r.x += o.x;
                         r.y += o.y;
                     }
@@ -247,11 +274,17 @@ k_build_projectors(int64_t ng, const int32_t *__restrict__ miller, double b00, d
     for (int64_t g = ng + threadIdx.x; g < ldb; g += 256) out[g] = make_double2(0.0, 0.0);
 }
 
-}  // namespace
+__global__ void __launch_bounds__(256) k_to_single(int64_t n, const double2 *__restrict__ src, float2 *__restrict__ dst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double2 v = src[i];
+        dst[i] = make_float2((float)v.x, (float)v.y);
+    }
+}
 
-hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const double2 *A, int64_t lda, const double2 *B,
-                   int64_t ldb, double2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale,
-                   double *quad)
+template <class C2>
+hipError_t gemm_hn_t(hipStream_t s, int M, int N, int64_t K, const C2 *A, int64_t lda, const C2 *B, int64_t ldb,
+                     C2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale, double *quad)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
     const int tm = (M + kTile - 1) / kTile, tn = (N + kTile - 1) / kTile;
@@ -267,21 +300,59 @@ hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const double2 *A, int
     nsplit = (K + kchunk - 1) / kchunk;
     if (nsplit < 1) nsplit = 1;
     prof_mark(PARO_K_GEMM_HN, s, true);
-    hipLaunchKernelGGL(k_gemm_hn_part, dim3(tm, tn, nsplit), dim3(256), 0, s, M, N, K, kchunk, A, lda, B, ldb,
+    hipLaunchKernelGGL((k_gemm_hn_part<C2>), dim3(tm, tn, nsplit), dim3(256), 0, s, M, N, K, kchunk, A, lda, B, ldb,
                        part);
     prof_mark(PARO_K_GEMM_HN, s, false);
-    hipLaunchKernelGGL(k_gemm_hn_reduce, dim3(N), dim3(256), 0, s, M, N, (int)nsplit, part, C, ldc, dscale, quad);
+    hipLaunchKernelGGL((k_gemm_hn_reduce<C2>), dim3(N), dim3(256), 0, s, M, N, (int)nsplit, part, C, ldc, dscale,
+                       quad);
     return hipGetLastError();
+}
+
+template <class C2>
+hipError_t gemm_nn_t(hipStream_t s, int64_t M, int N, int K, const C2 *A, int64_t lda, const C2 *B, int64_t ldb,
+                     C2 *C, int64_t ldc, bool accumulate)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((M + kTile - 1) / kTile), (N + kTile - 1) / kTile);
+    prof_mark(PARO_K_GEMM_NN, s, true);
+    hipLaunchKernelGGL((k_gemm_nn<C2>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, accumulate ? 1 : 0);
+    prof_mark(PARO_K_GEMM_NN, s, false);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const double2 *A, int64_t lda, const double2 *B,
+                   int64_t ldb, double2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale,
+                   double *quad)
+{
+    return gemm_hn_t(s, M, N, K, A, lda, B, ldb, C, ldc, part, part_elems, dscale, quad);
+}
+
+hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const float2 *A, int64_t lda, const float2 *B,
+                   int64_t ldb, float2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale,
+                   double *quad)
+{
+    return gemm_hn_t(s, M, N, K, A, lda, B, ldb, C, ldc, part, part_elems, dscale, quad);
 }
 
 hipError_t gemm_nn(hipStream_t s, int64_t M, int N, int K, const double2 *A, int64_t lda, const double2 *B,
                    int64_t ldb, double2 *C, int64_t ldc, bool accumulate)
 {
-    if (M <= 0 || N <= 0) return hipSuccess;
-    dim3 grid((unsigned)((M + kTile - 1) / kTile), (N + kTile - 1) / kTile);
-    prof_mark(PARO_K_GEMM_NN, s, true);
-    hipLaunchKernelGGL(k_gemm_nn, grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, accumulate ? 1 : 0);
-    prof_mark(PARO_K_GEMM_NN, s, false);
+    return gemm_nn_t(s, M, N, K, A, lda, B, ldb, C, ldc, accumulate);
+}
+
+hipError_t gemm_nn(hipStream_t s, int64_t M, int N, int K, const float2 *A, int64_t lda, const float2 *B,
+                   int64_t ldb, float2 *C, int64_t ldc, bool accumulate)
+{
+    return gemm_nn_t(s, M, N, K, A, lda, B, ldb, C, ldc, accumulate);
+}
+
+hipError_t launch_to_single(hipStream_t s, int64_t n, const double2 *src, float2 *dst)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_to_single, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, s, n, src, dst);
     return hipGetLastError();
 }
 

@@ -33,6 +33,10 @@ struct Plan {
     double *vplane = nullptr;     // local potential in the plane kernel's row-thread order
     double2 *tw[3] = {nullptr, nullptr, nullptr};  // exp(-2 pi i m / N_d)
     double2 *beta = nullptr;      // KB projectors, nproj x ldv (projector-major)
+    // single-precision copies for the mixed-precision source solves
+    float *vplane32 = nullptr;
+    float2 *tw32[3] = {nullptr, nullptr, nullptr};
+    float2 *beta32 = nullptr;
     double *dkb = nullptr;        // KB energies
     int32_t *status = nullptr;    // sticky status bits
 };
@@ -54,6 +58,9 @@ struct Workspace {
     int32_t *iflags;          // per band: active (nb) and status bits (nb)
     double *sig_all, *res, *eps_all;  // 2 nb each
     double *scal;             // 8 doubles of device scalars
+    // single-precision PCG vectors of the mixed-precision source solve,
+    // aliased onto r, z, p, q and W (unused while it runs): nb x ldv each
+    float2 *r32, *z32, *p32, *q32, *d32;
 };
 
 size_t workspace_bytes(const Plan &pl, int nb);
@@ -77,18 +84,31 @@ void prof_mark(int kernel, hipStream_t s, bool begin);
 bool fft_supported(int n);
 // the local potential re-laid in the order the plane kernel's row threads use it
 void build_plane_potential(int n, const int32_t *grid, const double *vloc, double *out);
+void build_plane_potential(int n, const int32_t *grid, const double *vloc, float *out);
 // Local part on nb bands: out_b = FFT^-1 (V FFT(x_b)) / N + (kin - shift_b) x_b,
 // x = src, or in PCG mode (pbuf != null) x = p with p <- z + beta_b p first
 // (first: p <- z) and src = z; dot_part then gets partial Re(x^H out).
 hipError_t launch_local_apply(const Plan &pl, const Workspace &w, int nb, const double2 *src, int64_t ld,
                               double2 *out, const double *shift, double2 *pbuf, const double *beta, bool first,
                               double *dot_part, int *nparts_out);
+// the same in single precision (FP32 tables of the plan, FP32 sticks)
+hipError_t launch_local_apply(const Plan &pl, const Workspace &w, int nb, const float2 *src, int64_t ld, float2 *out,
+                              const double *shift, float2 *pbuf, const double *beta, bool first, double *dot_part,
+                              int *nparts_out);
 // gemm.hip
 hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const double2 *A, int64_t lda, const double2 *B,
                    int64_t ldb, double2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale,
                    double *quad);
 hipError_t gemm_nn(hipStream_t s, int64_t M, int N, int K, const double2 *A, int64_t lda, const double2 *B,
                    int64_t ldb, double2 *C, int64_t ldc, bool accumulate);
+// single-precision operands on the FP32 matrix cores; split partials are
+// summed in FP64
+hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const float2 *A, int64_t lda, const float2 *B,
+                   int64_t ldb, float2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale,
+                   double *quad);
+hipError_t gemm_nn(hipStream_t s, int64_t M, int N, int K, const float2 *A, int64_t lda, const float2 *B,
+                   int64_t ldb, float2 *C, int64_t ldc, bool accumulate);
+hipError_t launch_to_single(hipStream_t s, int64_t n, const double2 *src, float2 *dst);
 hipError_t launch_build_projectors(const Plan &pl, const int32_t *miller_dev, const double *centers,
                                    const int32_t *lm, const double *widths);
 // vec.hip
@@ -97,6 +117,14 @@ hipError_t launch_pcg_init(const Plan &pl, const Workspace &w, int nb, const dou
                            bool correction);
 hipError_t launch_pcg_update(const Plan &pl, const Workspace &w, int nb, double2 *u, int64_t ldu, int npq,
                              int32_t *band_flags);
+// Mixed precision: the correction d = u - psi from d = 0 with FP32 vectors
+// (r32, z32, p32, q32, d32); r = eps psi - H psi is formed in FP64.
+hipError_t launch_pcg_init_mixed(const Plan &pl, const Workspace &w, int nb, const double2 *psi,
+                                 const double2 *hpsi, int64_t ld, const double *eps, int32_t *band_flags);
+hipError_t launch_pcg_update_mixed(const Plan &pl, const Workspace &w, int nb, int npq, int32_t *band_flags);
+// u_b = base_b + d32_b (base = psi), or u_b = d32_b (base = null), in FP64
+hipError_t launch_finish_correction(const Plan &pl, const Workspace &w, int nb, const double2 *base, int64_t ld,
+                                    double2 *u, int64_t ldu);
 hipError_t launch_residuals(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
                             int64_t ld, const double *eps, double *res);
 hipError_t launch_normalize_bands(const Plan &pl, const Workspace &w, int nb, double2 *e, int64_t lde);

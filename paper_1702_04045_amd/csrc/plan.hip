@@ -104,7 +104,8 @@ static bool good_size(int n)
 
 // Layout of the device plan buffer.
 struct PlanLayout {
-    size_t kin, pt_sz, st_start, cols, vplane, tw[3], beta, dkb, miller, pcen, plm, pwid, status, total;
+    size_t kin, pt_sz, st_start, cols, vplane, tw[3], beta, dkb, miller, pcen, plm, pwid, status;
+    size_t vplane32, tw32[3], beta32, total;
 };
 
 struct HostGeom {
@@ -138,6 +139,9 @@ static PlanLayout layout(const paro_problem &p, const HostGeom &g)
     L.plm = take(sizeof(int32_t) * 2 * std::max(1, p.n_proj));
     L.pwid = take(sizeof(double) * std::max(1, p.n_proj));
     L.status = take(sizeof(int32_t) * 64);
+    L.vplane32 = take(sizeof(float) * nv);
+    for (int d = 0; d < 3; ++d) L.tw32[d] = take(sizeof(float2) * p.grid[d]);
+    L.beta32 = take(sizeof(float2) * (size_t)p.n_proj * g.ldv);
     L.total = off;
     return L;
 }
@@ -253,6 +257,11 @@ Workspace carve_workspace(const Plan &pl, int nb, void *ws)
     w.q = (double2 *)take(sizeof(double2) * nb * pl.ldv);
     w.U = (double2 *)take(sizeof(double2) * m * pl.ldv);
     w.W = (double2 *)take(sizeof(double2) * m * pl.ldv);
+    w.r32 = reinterpret_cast<float2 *>(w.r);
+    w.z32 = reinterpret_cast<float2 *>(w.z);
+    w.p32 = reinterpret_cast<float2 *>(w.p);
+    w.q32 = reinterpret_cast<float2 *>(w.q);
+    w.d32 = reinterpret_cast<float2 *>(w.W);
     w.gram = (double2 *)take(sizeof(double2) * std::max(2 * m * m, np * np));
     w.part_elems = 32 * std::max(std::max(m * m, np * m), np * np);
     w.part = (double2 *)take(sizeof(double2) * w.part_elems);
@@ -359,6 +368,9 @@ int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes, 
     for (int d = 0; d < 3; ++d) pl.tw[d] = (double2 *)(base + L.tw[d]);
     pl.beta = (double2 *)(base + L.beta);
     pl.dkb = (double *)(base + L.dkb);
+    pl.vplane32 = (float *)(base + L.vplane32);
+    for (int d = 0; d < 3; ++d) pl.tw32[d] = (float2 *)(base + L.tw32[d]);
+    pl.beta32 = (float2 *)(base + L.beta32);
     pl.status = (int32_t *)(base + L.status);
     int32_t *miller_dev = (int32_t *)(base + L.miller);
     double *pcen = (double *)(base + L.pcen);
@@ -387,14 +399,19 @@ int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes, 
     double vmin = prob->vloc[0];
     for (size_t i = 0; i < nv; ++i) vmin = std::min(vmin, prob->vloc[i]);
     build_plane_potential(N1, pl.grid, prob->vloc, vpl.data());
+    std::vector<float> vpl32(nv);
+    build_plane_potential(N1, pl.grid, prob->vloc, vpl32.data());
     pl.vmin = vmin;
     std::vector<double2> tw[3];
+    std::vector<float2> tw32[3];
     for (int d = 0; d < 3; ++d) {
         const int n = pl.grid[d];
         tw[d].resize(n);
+        tw32[d].resize(n);
         for (int k = 0; k < n; ++k) {
             const long double ang = 6.283185307179586476925286766559L * (long double)k / (long double)n;
             tw[d][k] = make_double2((double)cosl(ang), (double)-sinl(ang));
+            tw32[d][k] = make_float2((float)cosl(ang), (float)-sinl(ang));
         }
     }
     const int np = prob->n_proj;
@@ -417,6 +434,8 @@ int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes, 
     if (e == hipSuccess) e = up(pl.cols, g.cols.data(), sizeof(int32_t) * g.cols.size());
     if (e == hipSuccess) e = up(pl.vplane, vpl.data(), sizeof(double) * nv);
     for (int d = 0; d < 3 && e == hipSuccess; ++d) e = up(pl.tw[d], tw[d].data(), sizeof(double2) * pl.grid[d]);
+    if (e == hipSuccess) e = up(pl.vplane32, vpl32.data(), sizeof(float) * nv);
+    for (int d = 0; d < 3 && e == hipSuccess; ++d) e = up(pl.tw32[d], tw32[d].data(), sizeof(float2) * pl.grid[d]);
     if (e == hipSuccess) e = up(miller_dev, prob->miller, sizeof(int32_t) * 3 * ng);
     if (e == hipSuccess) e = up(pcen, cen.data(), sizeof(double) * cen.size());
     if (e == hipSuccess) e = up(plm, lm.data(), sizeof(int32_t) * lm.size());
@@ -424,6 +443,7 @@ int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes, 
     if (e == hipSuccess) e = up(pl.dkb, dk.data(), sizeof(double) * dk.size());
     if (e == hipSuccess) e = hipMemsetAsync(pl.status, 0, sizeof(int32_t) * 64, pl.stream);
     if (e == hipSuccess) e = launch_build_projectors(pl, miller_dev, pcen, plm, pwid);
+    if (e == hipSuccess) e = launch_to_single(pl.stream, (int64_t)pl.nproj * pl.ldv, pl.beta, pl.beta32);
     if (e == hipSuccess) e = hipStreamSynchronize(pl.stream);
     if (e != hipSuccess) {
         delete h;

@@ -41,6 +41,50 @@ static hipError_t source_solve(const Plan &pl, const Workspace &w, int nb, const
     return e;
 }
 
+// H x in single precision (FP32 plan tables, FP32 matrix cores).
+static hipError_t apply_full(const Plan &pl, const Workspace &w, int nb, const float2 *x, int64_t ld, float2 *out,
+                             const double *shift)
+{
+    hipError_t e = launch_local_apply(pl, w, nb, x, ld, out, shift, nullptr, nullptr, false, nullptr, nullptr);
+    if (e != hipSuccess || pl.nproj == 0) return e;
+    float2 *P = reinterpret_cast<float2 *>(w.P);
+    e = gemm_hn(pl.stream, pl.nproj, nb, pl.ng, pl.beta32, pl.ldv, x, ld, P, pl.nproj, w.part, w.part_elems, pl.dkb,
+                nullptr);
+    if (e != hipSuccess) return e;
+    return gemm_nn(pl.stream, pl.ng, nb, pl.nproj, pl.beta32, pl.ldv, P, pl.nproj, out, ld, true);
+}
+
+// Mixed-precision source problems: the correction d = u - psi solves
+// (H - sigma) d = eps psi - H psi (the same problem as source_solve, moved
+// by the FP64 psi), by n_cg PCG steps from d = 0 with FP32 vectors, FP32
+// applies of H and FP64 scalars; the right-hand side is formed in FP64 from
+// the carried FP64 H psi, and u = psi + d (or u = d when correction) is
+// written in FP64.  The FP64 Rayleigh-Ritz that follows acts as the
+// refinement: the FP32 error is relative to d, which vanishes as the bands
+// converge.
+static hipError_t source_solve_mixed(const Plan &pl, const Workspace &w, int nb, const double2 *psi,
+                                     const double2 *hpsi, int64_t ld, const double *eps, const double *shift, int ncg,
+                                     double2 *u, int64_t ldu, int32_t *band_flags, bool correction)
+{
+    hipError_t e = launch_pcg_init_mixed(pl, w, nb, psi, hpsi, ld, eps, band_flags);
+    double *pq_parts = w.dots + (size_t)DOT_PQ * nb * kMaxParts;
+    float2 *P = reinterpret_cast<float2 *>(w.P);
+    for (int k = 1; k <= ncg && e == hipSuccess; ++k) {
+        int npq = 0;
+        e = launch_local_apply(pl, w, nb, w.z32, pl.ldv, w.q32, shift, w.p32, w.sc + SC_BETA * nb, k == 1, pq_parts,
+                               &npq);
+        if (e == hipSuccess && pl.nproj > 0) {
+            e = gemm_hn(pl.stream, pl.nproj, nb, pl.ng, pl.beta32, pl.ldv, w.p32, pl.ldv, P, pl.nproj, w.part,
+                        w.part_elems, pl.dkb, w.sc + SC_NLQ * nb);
+            if (e == hipSuccess)
+                e = gemm_nn(pl.stream, pl.ng, nb, pl.nproj, pl.beta32, pl.ldv, P, pl.nproj, w.q32, pl.ldv, true);
+        }
+        if (e == hipSuccess) e = launch_pcg_update_mixed(pl, w, nb, npq, band_flags);
+    }
+    if (e == hipSuccess) e = launch_finish_correction(pl, w, nb, correction ? nullptr : psi, ld, u, ldu);
+    return e;
+}
+
 static hipError_t rayleigh_ritz(const Plan &pl, const Workspace &w, int m, int nkeep, const double2 *U,
                                 const double2 *W, int64_t ld, double *eps, double2 *psi, double2 *hpsi, int64_t ldo)
 {
@@ -103,6 +147,47 @@ int32_t paro_apply_h(paro_plan plan, int32_t nb, const double *psi, int64_t ld, 
     if (rc) return rc;
     Workspace w = carve_workspace(pl, nbw, ws);
     PARO_CHECK_LAUNCH(apply_full(pl, w, nb, (const double2 *)psi, ld, (double2 *)hpsi, shift));
+    return PARO_OK;
+}
+
+int32_t paro_apply_h_f32(paro_plan plan, int32_t nb, const float *psi, int64_t ld, const double *shift, float *hpsi,
+                         void *ws, size_t ws_bytes)
+{
+    if (!plan || nb <= 0 || !psi || !hpsi) {
+        set_error("paro_apply_h_f32: bad argument");
+        return PARO_EINVAL;
+    }
+    const Plan &pl = plan->pl;
+    if (ld < pl.ng) {
+        set_error("paro_apply_h_f32: ld < n_g");
+        return PARO_EINVAL;
+    }
+    const int nbw = (nb + 1) / 2;
+    int32_t rc = check_ws(pl, nbw, ws, ws_bytes);
+    if (rc) return rc;
+    Workspace w = carve_workspace(pl, nbw, ws);
+    PARO_CHECK_LAUNCH(apply_full(pl, w, nb, (const float2 *)psi, ld, (float2 *)hpsi, shift));
+    return PARO_OK;
+}
+
+int32_t paro_source_solve_mixed(paro_plan plan, int32_t nb, const double *psi, const double *hpsi, int64_t ld,
+                                const double *eps, const double *shift, int32_t n_cg, double *u,
+                                int32_t *band_flags, void *ws, size_t ws_bytes)
+{
+    if (!plan || nb <= 0 || !psi || !hpsi || !eps || !shift || !u || n_cg < 0) {
+        set_error("paro_source_solve_mixed: bad argument");
+        return PARO_EINVAL;
+    }
+    const Plan &pl = plan->pl;
+    if (ld < pl.ng) {
+        set_error("paro_source_solve_mixed: ld < n_g");
+        return PARO_EINVAL;
+    }
+    int32_t rc = check_ws(pl, nb, ws, ws_bytes);
+    if (rc) return rc;
+    Workspace w = carve_workspace(pl, nb, ws);
+    PARO_CHECK_LAUNCH(source_solve_mixed(pl, w, nb, (const double2 *)psi, (const double2 *)hpsi, ld, eps, shift,
+                                         n_cg, (double2 *)u, ld, band_flags, false));
     return PARO_OK;
 }
 
@@ -187,7 +272,8 @@ int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi_, double *hpsi_, in
 {
     if (!plan || nb <= 0 || !psi_ || !hpsi_ || !eps || !sigma || !opts || opts->n_outer < 0 || opts->n_cg < 0 ||
         nb > 512 || (opts->variant != PARO_VARIANT_PARO && opts->variant != PARO_VARIANT_MPARO1) ||
-        (opts->shift_mode != PARO_SHIFT_FIXED && opts->shift_mode != PARO_SHIFT_ADAPTIVE)) {
+        (opts->shift_mode != PARO_SHIFT_FIXED && opts->shift_mode != PARO_SHIFT_ADAPTIVE) ||
+        (opts->precision != PARO_PREC_FP64 && opts->precision != PARO_PREC_MIXED)) {
         set_error("paro_iterate: bad argument");
         return PARO_EINVAL;
     }
@@ -223,8 +309,12 @@ int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi_, double *hpsi_, in
         const bool mparo = opts->variant == PARO_VARIANT_MPARO1;
         double2 *Ut = mparo ? w.U + (size_t)nb * lv : w.U;  // u (Algorithm 1) or e (Algorithm 2)
         for (int attempt = 0; attempt < 2; ++attempt) {
-            PARO_CHECK_LAUNCH(source_solve(pl, w, nb, psi, hpsi, ld, eps, w.sig_all, opts->n_cg, Ut, lv,
-                                           w.iflags + nb, mparo));
+            if (opts->precision == PARO_PREC_MIXED)
+                PARO_CHECK_LAUNCH(source_solve_mixed(pl, w, nb, psi, hpsi, ld, eps, w.sig_all, opts->n_cg, Ut, lv,
+                                                     w.iflags + nb, mparo));
+            else
+                PARO_CHECK_LAUNCH(source_solve(pl, w, nb, psi, hpsi, ld, eps, w.sig_all, opts->n_cg, Ut, lv,
+                                               w.iflags + nb, mparo));
             if (opts->shift_mode != PARO_SHIFT_ADAPTIVE) break;
             // on negative curvature redo the source problems with sigma_lb
             double scur = 0.0;

@@ -2,6 +2,7 @@
 // (Algorithm 1, step 3), residual norms (step 5) and the correction vectors
 // of Algorithm 2.  Every reduction goes through per-work-group partial sums
 // that the consumer adds in a fixed order, so runs are bitwise reproducible.
+#include "fft_device.h"
 #include "paro_internal.h"
 #include "reduce_device.h"
 
@@ -53,11 +54,14 @@ k_pcg_init_parts(int64_t ng, const double2 *__restrict__ psi, int64_t ld, const 
 
 // u = psi (correction: u = 0, the iterate is then e = u - psi of the
 // correction equation of Algorithm 2); r = eps psi - H psi; z = K r;
-// partial r^H z.
+// partial r^H z.  r is formed in FP64 from the FP64 psi and H psi; the
+// vectors are stored as CV (double2, or float2 in the mixed-precision
+// solve) and u as CU.
+template <class CV, class CU>
 __global__ void __launch_bounds__(kVecThreads)
 k_pcg_init(int64_t ng, int nparts, const double2 *__restrict__ psi, const double2 *__restrict__ hpsi, int64_t ld,
-           const double *__restrict__ eps, const double *__restrict__ kin, double2 *__restrict__ u, int64_t ldu,
-           double2 *__restrict__ r, double2 *__restrict__ z, int64_t ldv, double *__restrict__ dots,
+           const double *__restrict__ eps, const double *__restrict__ kin, CU *__restrict__ u, int64_t ldu,
+           CV *__restrict__ r, CV *__restrict__ z, int64_t ldv, double *__restrict__ dots,
            double *__restrict__ sc, int nb, int correction)
 {
     __shared__ double red[kVecThreads / 64];
@@ -68,28 +72,31 @@ k_pcg_init(int64_t ng, int nparts, const double2 *__restrict__ psi, const double
     if (blockIdx.x == 0 && threadIdx.x == 0) sc[SC_TAU * nb + band] = tau;
     const double e = eps[band];
     const double2 *x = psi + band * ld, *hx = hpsi + band * ld;
-    double2 *uu = u + band * ldu, *rr = r + band * ldv, *zz = z + band * ldv;
+    CU *uu = u + band * ldu;
+    CV *rr = r + band * ldv, *zz = z + band * ldv;
     double rz = 0.0;
     const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
     const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
     for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
         const double2 v = x[g], hv = hx[g];
-        const double2 rv = make_double2(e * v.x - hv.x, e * v.y - hv.y);
+        const CV rv = cmk<CV>(e * v.x - hv.x, e * v.y - hv.y);
         const double k = teter(kin[g] / tau);
-        const double2 zv = make_double2(k * rv.x, k * rv.y);
-        uu[g] = correction ? make_double2(0.0, 0.0) : v;
+        const CV zv = cmk<CV>(k * rv.x, k * rv.y);
+        uu[g] = correction ? cmk<CU>(0.0, 0.0) : cmk<CU>(v.x, v.y);
         rr[g] = rv;
         zz[g] = zv;
-        rz += rv.x * zv.x + rv.y * zv.y;
+        rz += (double)rv.x * (double)zv.x + (double)rv.y * (double)zv.y;
     }
     rz = block_sum<kVecThreads>(rz, red);
     if (threadIdx.x == 0) dots[((size_t)DOT_RZ * nb + band) * kMaxParts + blockIdx.x] = rz;
 }
 
-// alpha = gamma / p^H q; u += alpha p; r -= alpha q; z = K r; partial r^H z.
+// alpha = gamma / p^H q; u += alpha p; r -= alpha q; z = K r; partial r^H z
+// (FP64 arithmetic on CV / CU storage).
+template <class CV, class CU>
 __global__ void __launch_bounds__(kVecThreads)
-k_pcg_update(int64_t ng, int npq, const double2 *__restrict__ p, const double2 *__restrict__ q, int64_t ldv,
-             double2 *__restrict__ u, int64_t ldu, double2 *__restrict__ r, double2 *__restrict__ z,
+k_pcg_update(int64_t ng, int npq, const CV *__restrict__ p, const CV *__restrict__ q, int64_t ldv,
+             CU *__restrict__ u, int64_t ldu, CV *__restrict__ r, CV *__restrict__ z,
              const double *__restrict__ kin, const double *__restrict__ dots_pq, double *__restrict__ dots_rz,
              const double *__restrict__ sc, const int32_t *__restrict__ active, int nb)
 {
@@ -101,27 +108,49 @@ k_pcg_update(int64_t ng, int npq, const double2 *__restrict__ p, const double2 *
     if (go) {
         const double alpha = sc[SC_GAMMA * nb + band] / pq;
         const double tau = sc[SC_TAU * nb + band];
-        const double2 *pp = p + band * ldv, *qq = q + band * ldv;
-        double2 *uu = u + band * ldu, *rr = r + band * ldv, *zz = z + band * ldv;
+        const CV *pp = p + band * ldv, *qq = q + band * ldv;
+        CU *uu = u + band * ldu;
+        CV *rr = r + band * ldv, *zz = z + band * ldv;
         const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
         const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
         for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
-            const double2 pv = pp[g], qv = qq[g];
-            double2 uv = uu[g], rv = rr[g];
-            uv.x += alpha * pv.x;
-            uv.y += alpha * pv.y;
-            rv.x -= alpha * qv.x;
-            rv.y -= alpha * qv.y;
+            const CV pv = pp[g], qv = qq[g];
+            const CU uv = uu[g];
+            const CV rv0 = rr[g];
+            const double rx = rv0.x - alpha * qv.x, ry = rv0.y - alpha * qv.y;
+            const CV rv = cmk<CV>(rx, ry);
             const double k = teter(kin[g] / tau);
-            const double2 zv = make_double2(k * rv.x, k * rv.y);
-            uu[g] = uv;
+            const CV zv = cmk<CV>(k * rv.x, k * rv.y);
+            uu[g] = cmk<CU>(uv.x + alpha * pv.x, uv.y + alpha * pv.y);
             rr[g] = rv;
             zz[g] = zv;
-            rz += rv.x * zv.x + rv.y * zv.y;
+            rz += (double)rv.x * (double)zv.x + (double)rv.y * (double)zv.y;
         }
     }
     rz = block_sum<kVecThreads>(rz, red);
     if (threadIdx.x == 0) dots_rz[(size_t)band * kMaxParts + blockIdx.x] = rz;
+}
+
+// u_b = base_b + d_b (base != null) or u_b = d_b, in FP64
+__global__ void __launch_bounds__(kVecThreads)
+k_finish_correction(int64_t ng, const double2 *__restrict__ base, int64_t ld, const float2 *__restrict__ d,
+                    int64_t ldv, double2 *__restrict__ u, int64_t ldu)
+{
+    const int band = blockIdx.y;
+    const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
+    const float2 *dd = d + band * ldv;
+    double2 *uu = u + band * ldu;
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
+        const float2 dv = dd[g];
+        double2 o = make_double2(dv.x, dv.y);
+        if (base) {
+            const double2 b = base[band * ld + g];
+            o.x += b.x;
+            o.y += b.y;
+        }
+        uu[g] = o;
+    }
 }
 
 // Per-band PCG scalars.
@@ -247,8 +276,8 @@ hipError_t launch_pcg_init(const Plan &pl, const Workspace &w, int nb, const dou
     const unsigned nc = nchunks(pl.ng);
     hipLaunchKernelGGL(k_pcg_init_parts, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, psi, ld, pl.kin,
                        w.dots, nb);
-    hipLaunchKernelGGL(k_pcg_init, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, (int)nc, psi, hpsi, ld, eps,
-                       pl.kin, u, ldu, w.r, w.z, pl.ldv, w.dots, w.sc, nb, correction ? 1 : 0);
+    hipLaunchKernelGGL((k_pcg_init<double2, double2>), dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, (int)nc,
+                       psi, hpsi, ld, eps, pl.kin, u, ldu, w.r, w.z, pl.ldv, w.dots, w.sc, nb, correction ? 1 : 0);
     hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kVecThreads), 0, pl.stream, nb, 0, (int)nc, 0,
                        (const double *)nullptr, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags,
                        w.iflags + nb, band_flags, pl.status);
@@ -260,13 +289,50 @@ hipError_t launch_pcg_update(const Plan &pl, const Workspace &w, int nb, double2
 {
     const unsigned nc = nchunks(pl.ng);
     prof_mark(PARO_K_PCG_UPDATE, pl.stream, true);
-    hipLaunchKernelGGL(k_pcg_update, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, npq, w.p, w.q, pl.ldv, u,
-                       ldu, w.r, w.z, pl.kin, w.dots + (size_t)DOT_PQ * nb * kMaxParts,
+    hipLaunchKernelGGL((k_pcg_update<double2, double2>), dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, npq,
+                       w.p, w.q, pl.ldv, u, ldu, w.r, w.z, pl.kin, w.dots + (size_t)DOT_PQ * nb * kMaxParts,
                        w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags, nb);
     prof_mark(PARO_K_PCG_UPDATE, pl.stream, false);
     hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kVecThreads), 0, pl.stream, nb, 1, (int)nc, npq,
                        w.dots + (size_t)DOT_PQ * nb * kMaxParts, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc,
                        w.iflags, w.iflags + nb, band_flags, pl.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_init_mixed(const Plan &pl, const Workspace &w, int nb, const double2 *psi,
+                                 const double2 *hpsi, int64_t ld, const double *eps, int32_t *band_flags)
+{
+    const unsigned nc = nchunks(pl.ng);
+    hipLaunchKernelGGL(k_pcg_init_parts, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, psi, ld, pl.kin,
+                       w.dots, nb);
+    hipLaunchKernelGGL((k_pcg_init<float2, float2>), dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, (int)nc,
+                       psi, hpsi, ld, eps, pl.kin, w.d32, pl.ldv, w.r32, w.z32, pl.ldv, w.dots, w.sc, nb, 1);
+    hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kVecThreads), 0, pl.stream, nb, 0, (int)nc, 0,
+                       (const double *)nullptr, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags,
+                       w.iflags + nb, band_flags, pl.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_update_mixed(const Plan &pl, const Workspace &w, int nb, int npq, int32_t *band_flags)
+{
+    const unsigned nc = nchunks(pl.ng);
+    prof_mark(PARO_K_PCG_UPDATE, pl.stream, true);
+    hipLaunchKernelGGL((k_pcg_update<float2, float2>), dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, npq,
+                       w.p32, w.q32, pl.ldv, w.d32, pl.ldv, w.r32, w.z32, pl.kin,
+                       w.dots + (size_t)DOT_PQ * nb * kMaxParts, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc,
+                       w.iflags, nb);
+    prof_mark(PARO_K_PCG_UPDATE, pl.stream, false);
+    hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kVecThreads), 0, pl.stream, nb, 1, (int)nc, npq,
+                       w.dots + (size_t)DOT_PQ * nb * kMaxParts, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc,
+                       w.iflags, w.iflags + nb, band_flags, pl.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_correction(const Plan &pl, const Workspace &w, int nb, const double2 *base, int64_t ld,
+                                    double2 *u, int64_t ldu)
+{
+    hipLaunchKernelGGL(k_finish_correction, dim3(nchunks(pl.ng), nb), dim3(kVecThreads), 0, pl.stream, pl.ng, base,
+                       ld, w.d32, pl.ldv, u, ldu);
     return hipGetLastError();
 }
 

@@ -171,6 +171,33 @@ class Plan:
                 "paro_apply_h")
         return out
 
+    def apply_h_f32(self, psi, shift=None, out=None):
+        """(H - shift_b) psi_b in single precision; psi: band-major complex64 block."""
+        torch = _torch()
+        assert psi.dtype == torch.complex64 and psi.device == self.device and psi.dim() == 2
+        assert psi.stride(1) == 1 and psi.stride(0) >= self.ng
+        nb = psi.shape[0]
+        out = out if out is not None else torch.empty_like(psi)
+        ws, n = self.workspace((nb + 1) // 2)
+        self._sync_stream()
+        L.check(self.lib.paro_apply_h_f32(self.h, nb, _ptr(psi), psi.stride(0), _ptr(shift), _ptr(out), ws, n),
+                "paro_apply_h_f32")
+        return out
+
+    def source_solve_mixed(self, psi, hpsi, eps, shift, n_cg, u=None):
+        """As source_solve, with FP32 PCG vectors on the correction u - psi; returns (u, band_flags)."""
+        torch = _torch()
+        self._check_block(psi)
+        nb = psi.shape[0]
+        u = u if u is not None else torch.empty_like(psi)
+        flags = torch.zeros(nb, dtype=torch.int32, device=self.device)
+        ws, n = self.workspace(nb)
+        self._sync_stream()
+        L.check(self.lib.paro_source_solve_mixed(self.h, nb, _ptr(psi), _ptr(hpsi), psi.stride(0), _ptr(eps),
+                                                 _ptr(shift), int(n_cg), _ptr(u), _ptr(flags), ws, n),
+                "paro_source_solve_mixed")
+        return u, flags
+
     def source_solve(self, psi, hpsi, eps, shift, n_cg, u=None):
         """u_b from n_cg PCG steps on (H - shift_b) u_b = (eps_b - shift_b) psi_b; returns (u, band_flags)."""
         torch = _torch()
@@ -219,8 +246,10 @@ class Plan:
         return float(out.item())
 
     def iterate(self, psi, n_outer, n_cg, sigma_lb, hpsi=None, eps=None, variant=L.VARIANT_PARO,
-                shift_mode=L.SHIFT_FIXED, initial_rr=True, n_conv=None, tol_res=0.0, stats=True):
-        """ParO / MParO I outer iterations; psi is updated in place.
+                shift_mode=L.SHIFT_FIXED, initial_rr=True, n_conv=None, tol_res=0.0, stats=True,
+                precision=L.PREC_FP64):
+        """ParO / MParO I outer iterations; psi is updated in place.  precision:
+        PREC_FP64, or PREC_MIXED (FP32 source problems, FP64 Rayleigh-Ritz).
 
         Returns dict(psi, hpsi, eps, sigma, stats (rows x (2 nb + 2)) or None, n_done)."""
         torch = _torch()
@@ -233,7 +262,7 @@ class Plan:
                         device=self.device) if stats else None
         o = L.IterOpts(n_outer=int(n_outer), n_cg=int(n_cg), n_conv=int(n_conv or nb), shift_mode=int(shift_mode),
                        variant=int(variant), initial_rr=1 if initial_rr else 0, sigma_lb=float(sigma_lb),
-                       tol_res=float(tol_res))
+                       tol_res=float(tol_res), precision=int(precision))
         ws, n = self.workspace(nb)
         done = C.c_int32()
         self._sync_stream()

@@ -1,10 +1,22 @@
 """GPU parity: libparo (HIP, gfx950) against the CPU oracle on the same seeded
-inputs.  Tolerances (FP64 everywhere):
+inputs.  Tolerances (FP64 path):
   H psi, projectors, kinetic table   max |diff| <= 1e-12 max |ref|
   GEMMs on the matrix cores          max |diff| <= 1e-13 max |ref| (x sqrt K)
   PCG iterates after n_cg steps      |du| <= 1e-9 |u| per band
   Rayleigh-Ritz / ParO eigenvalues   |d eps| <= 1e-10 max(|eps|, 1 Ha)
   Ritz subspaces (gapped clusters)   sin(angle) <= 1e-8
+Mixed precision (FP32 source problems, FP64 Rayleigh-Ritz):
+  FP32 H psi                         max |diff| <= 2e-6 max |ref|: unit roundoff
+                                     2^-24 times the 6 log2 N + 2 rounding
+                                     steps of the three transform pairs and the
+                                     V multiply (linear worst case)
+  FP32 PCG correction d = u - psi    |du| <= 2e-5 |d| per band: 2^-24 grown by
+                                     at most 20 steps x a factor 10 of CG
+                                     round-off amplification
+  converged eigenvalues              the FP64 bars above (dense reference or the
+                                     FP64 run): the FP32 error is relative to
+                                     the correction, which vanishes at
+                                     convergence
 """
 import numpy as np
 import pytest
@@ -230,6 +242,83 @@ def test_source_solve_negative_curvature_flag():
     assert rel_err(to_np(u), u_ref) < 1e-12
     assert pl.status() & P.F_NEGCURV
     assert pl.status() == 0  # cleared by the read
+
+
+# ---------------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("spec,nb", [(TINY, 3), (C0, 9)], ids=["tiny", "c0"])
+def test_apply_h_f32_matches_oracle(spec, nb):
+    c, v, h, pl = make_case(spec, 1)
+    x = synth.trial_block(h.ng, nb, 3).astype(np.complex64)
+    ref = h.apply(x.astype(np.complex128))
+    got = to_np(pl.apply_h_f32(to_dev(x)))
+    assert rel_err(got, ref) < 2e-6
+
+
+def test_apply_h_f32_full_size_sampled_bands():
+    """160 bands of the 34k-plane-wave cell (FP32 matrix-core projector
+    products included), three sampled against the oracle."""
+    c, v, h, pl = make_case(C1, 0)
+    x = synth.trial_block(h.ng, 160, 0).astype(np.complex64)
+    got = to_np(pl.apply_h_f32(to_dev(x)))
+    idx = [0, 77, 159]
+    assert rel_err(got[idx], h.apply(x[idx].astype(np.complex128))) < 2e-6
+
+
+@pytest.mark.parametrize("spec,nb,ncg", [(TINY, 4, 12), (C0, 8, 20)], ids=["tiny", "c0"])
+def test_source_solve_mixed_matches_oracle(spec, nb, ncg):
+    c, v, h, pl = make_case(spec, 5)
+    x = synth.trial_block(h.ng, nb, 2)
+    x /= np.linalg.norm(x, axis=1)[:, None]
+    hx = h.apply(x)
+    eps = np.einsum("bg,bg->b", x.conj(), hx).real
+    sh = np.full(nb, h.shift_bound())
+    u_ref, f_ref = h.pcg(x, hx, eps, sh, ncg)
+    u, flags = pl.source_solve_mixed(to_dev(x), to_dev(hx), to_dev(eps), to_dev(sh), ncg)
+    u = to_np(u)
+    for b in range(nb):
+        assert np.linalg.norm(u[b] - u_ref[b]) <= 2e-5 * np.linalg.norm(u_ref[b] - x[b])
+    assert np.array_equal(to_np(flags), f_ref)
+
+
+@pytest.mark.parametrize("variant", [0, 1], ids=["paro", "mparo"])
+def test_mixed_paro_reaches_dense_eigenvalues(variant):
+    """ParO / MParO I with FP32 source problems reach the dense-diagonalisation
+    eigenvalues as the FP64 run does, in the same number of outer iterations."""
+    import paper_1702_04045_amd as P
+    c, v, h, pl = make_case(C0, 0)
+    lam = np.linalg.eigvalsh(h.dense())
+    runs = {}
+    for prec in (P.PREC_FP64, P.PREC_MIXED):
+        x = synth.trial_block(h.ng, 16, 0)
+        runs[prec] = pl.iterate(to_dev(x), 60, 10, h.shift_bound(), variant=variant, shift_mode=1, n_conv=8,
+                                tol_res=1e-7, precision=prec)
+    eps = to_np(runs[P.PREC_MIXED]["eps"])
+    assert np.abs(eps[:8] - lam[:8]).max() < 1e-8
+    assert runs[P.PREC_MIXED]["n_done"] == runs[P.PREC_FP64]["n_done"]
+    assert pl.status() == 0
+
+
+def test_mixed_full_size_converges_to_fp64_eigenvalues():
+    """The 34k-plane-wave cell at the benchmark shape (160 bands, 20 PCG
+    steps, adaptive shift): FP64 and mixed runs from the same trial block
+    reach the 1e-8 Ha eigenvalue-error bound for the 128 lowest bands, and
+    their eigenvalues agree to the FP64 bar."""
+    import paper_1702_04045_amd as P
+    c, v, h, pl = make_case(C1, 0)
+    nb, nconv = C1.n_carried, C1.n_bands
+    sig = pl.shift_lower_bound()
+    final = {}
+    for prec in (P.PREC_FP64, P.PREC_MIXED):
+        out = pl.iterate(to_dev(synth.trial_block(h.ng, nb, 0)), 400, C1.n_cg, sig, shift_mode=1, n_conv=nconv,
+                         tol_res=2e-6, precision=prec)
+        st = to_np(out["stats"])[out["n_done"]]
+        res, eps = st[nb:nb + nconv], st[:nb]
+        gaps = np.array([np.min(np.abs(np.delete(eps, i) - eps[i])) for i in range(nconv)])
+        assert np.max(np.minimum(res, res ** 2 / gaps)) <= 1e-8
+        final[prec] = to_np(out["eps"])[:nconv]
+    assert np.abs(final[P.PREC_FP64] - final[P.PREC_MIXED]).max() <= EIG_TOL * max(1.0, np.abs(final[0]).max())
+    assert pl.status() == 0
 
 
 # ---------------------------------------------------------------- Rayleigh-Ritz
