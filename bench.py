@@ -10,10 +10,12 @@ N = 128 orbitals plus 32 buffer orbitals, FP64 (complex128) throughout.
 Inputs are seeded synthetic cells (see synth/), resident in HBM before
 the timed region.
 
-Prints one JSON line.  value = ParO outer iterations per second; also
-H-psi band-applies per second, the live HIP-event timing of the dominant
-kernel against its roofline, the time to a 1e-8 Ha eigenvalue error from
-the random trial block, and the CPU oracle's rate on the host cores.
+Prints one JSON line.  value = ParO outer iterations per second in plain
+FP64; also H-psi band-applies per second, the live HIP-event timing of the
+dominant kernel against its roofline, the time to a 1e-8 Ha eigenvalue error
+from the random trial block, and the CPU oracle's rate on the host cores.
+"mixed" holds the same measurements for the batched mixed-precision path
+(FP32 source problems, FP64 H U and Rayleigh-Ritz).
 """
 from __future__ import annotations
 
@@ -39,6 +41,7 @@ PLANE_SOURCES = ["paper_1702_04045_amd/csrc/apply.hip", "paper_1702_04045_amd/cs
                  "paper_1702_04045_amd/csrc/paro_internal.h"]
 COPY_BYTES = 1 << 30         # bytes read (and written) by the calibration copy
 PEAK_FP64_VALU = 78.6e12     # MI355X FP64 vector, flop/s
+PEAK_FP32_VALU = 157.3e12    # MI355X FP32 vector, flop/s
 PEAK_HBM = 8.0e12            # bytes/s
 
 
@@ -176,66 +179,105 @@ def main():
     if args.warmup:
         pl.iterate(psi, args.warmup, ncg, sigma_lb, hpsi=hpsi, eps=eps, initial_rr=False, stats=False, **kw)
     torch.cuda.synchronize()
-
-    # timed region: K outer iterations; HIP events around every plane-stage launch
+    start = (psi.clone(), hpsi.clone(), eps.clone())
     lib = P.load()
-    L.check(lib.paro_profile_start(L.K_PLANE, 1 << 16), "paro_profile_start")
-    stream = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    out = pl.iterate(psi, args.steps, ncg, sigma_lb, hpsi=hpsi, eps=eps, initial_rr=False, stats=True, **kw)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    import ctypes as C
-    nl, tot = C.c_int32(), C.c_double()
-    L.check(lib.paro_profile_stop(C.byref(nl), C.byref(tot)), "paro_profile_stop")
-    gpu_ms = e0.elapsed_time(e1)
-    ms_step = gpu_ms / max(args.steps, 1)
-    iters_s = 1000.0 / ms_step
-    applies_s = iters_s * nb * (ncg + 1)
-    status = pl.status()
-
-    # roofline of the plane-stage kernel (one launch = up to 64 bands x N3 planes)
     N = pl.grid[0]
     ncol = 2 * pl.nmax[0] + 1
     launches_per_apply = (nb + 63) // 64
     planes_per_launch = (nb * pl.grid[2]) / launches_per_apply
     flops_launch = plane_flops(N, ncol) * planes_per_launch
-    avg_ms = tot.value / max(nl.value, 1)
-    achieved = flops_launch / (avg_ms * 1e-3)
-    # algorithmic bytes: every stick of the launch's band-planes read and
-    # written once, the potential read once
-    bytes_launch = 2 * 16.0 * pl.n_sticks * pl.grid[2] * (nb / launches_per_apply) + 8.0 * N ** 3
-    roofline = {"kernel": "k_plane<96> (z-plane stage: n2/n1 FFTs, V multiply)", "bound": "alu",
-                "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_VALU, "traffic": measured_traffic(),
-                "algorithmic_bytes_per_launch": bytes_launch,
-                "hbm_frac_algorithmic": bytes_launch / (avg_ms * 1e-3) / PEAK_HBM,
-                "launches_timed": int(nl.value), "avg_launch_ms": avg_ms, "flops_per_launch": flops_launch,
-                "share_of_step": (tot.value / max(args.steps, 1)) / ms_step}
 
-    # time to a 1e-8 Ha eigenvalue error from the trial block (separate run)
-    tta = None
-    if not args.no_tta:
+    def timed(precision):
+        """K outer iterations from the warmed-up state; HIP events around every plane-stage launch."""
+        import ctypes as C
+        p, h, e = (t.clone() for t in start)
+        if precision == P.PREC_MIXED and args.warmup:
+            pl.iterate(p.clone(), 1, ncg, sigma_lb, hpsi=h.clone(), eps=e.clone(), initial_rr=False, stats=False,
+                       precision=precision, **kw)
+        torch.cuda.synchronize()
+        L.check(lib.paro_profile_start(L.K_PLANE, 1 << 16), "paro_profile_start")
+        stream = torch.cuda.current_stream(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        pl.iterate(p, args.steps, ncg, sigma_lb, hpsi=h, eps=e, initial_rr=False, stats=True, precision=precision,
+                   **kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        nl, tot = C.c_int32(), C.c_double()
+        L.check(lib.paro_profile_stop(C.byref(nl), C.byref(tot)), "paro_profile_stop")
+        ms_step = e0.elapsed_time(e1) / max(args.steps, 1)
+        # plane launches per step: n_cg + 1 applies in FP64, or n_cg in FP32 and one in FP64
+        n_prec = launches_per_apply * (ncg if precision == P.PREC_MIXED else ncg + 1) * args.steps
+        return ms_step, wall, nl.value, tot.value, n_prec
+
+    def tta(precision):
+        """Time to a 1e-8 Ha eigenvalue error from the trial block (separate run)."""
+        if args.no_tta:
+            return None
         psi2 = x0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = pl.iterate(psi2, 0, ncg, sigma_lb, initial_rr=True, stats=True, **kw)
+        r = pl.iterate(psi2, 0, ncg, sigma_lb, initial_rr=True, stats=True, precision=precision, **kw)
         h2, e2 = r["hpsi"], r["eps"]
         its, bound, chunk = 0, np.inf, 10
         while time.perf_counter() - t0 < args.tta_seconds and its < 2000:
-            r = pl.iterate(psi2, chunk, ncg, sigma_lb, hpsi=h2, eps=e2, initial_rr=False, stats=True, **kw)
+            r = pl.iterate(psi2, chunk, ncg, sigma_lb, hpsi=h2, eps=e2, initial_rr=False, stats=True,
+                           precision=precision, **kw)
             its += r["n_done"]
             row = r["stats"][-1].cpu().numpy()
             bound = quad_bound(row[:nb], row[nb:2 * nb], nconv)
             if bound <= 1e-8:
                 break
         torch.cuda.synchronize()
-        tta = {"outer_iterations": its, "seconds": time.perf_counter() - t0, "eig_err_bound": bound,
-               "reached": bool(bound <= 1e-8), "variant": "ParO (Algorithm 1), adaptive shift"}
+        return {"outer_iterations": its, "seconds": time.perf_counter() - t0, "eig_err_bound": bound,
+                "reached": bool(bound <= 1e-8), "checked_every": chunk,
+                "variant": "ParO (Algorithm 1), adaptive shift"}
+
+    def roofline_of(ms_step, nl, tot, precision):
+        avg_ms = tot / max(nl, 1)
+        peak = PEAK_FP32_VALU if precision == P.PREC_MIXED else PEAK_FP64_VALU
+        achieved = flops_launch / (avg_ms * 1e-3)
+        esize = 8 if precision == P.PREC_MIXED else 16
+        bytes_launch = 2 * float(esize) * pl.n_sticks * pl.grid[2] * (nb / launches_per_apply) + esize / 2 * N ** 3
+        name = "k_plane<96, float2>" if precision == P.PREC_MIXED else "k_plane<96, double2>"
+        return {"kernel": name + " (z-plane stage: n2/n1 FFTs, V multiply)", "bound": "alu",
+                "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": measured_traffic() if precision == P.PREC_FP64 else None,
+                "algorithmic_bytes_per_launch": bytes_launch,
+                "hbm_frac_algorithmic": bytes_launch / (avg_ms * 1e-3) / PEAK_HBM,
+                "launches_timed": int(nl), "avg_launch_ms": avg_ms, "flops_per_launch": flops_launch,
+                "share_of_step": (tot / max(args.steps, 1)) / ms_step}
+
+    # FP64: every plane launch is the FP64 kernel
+    ms_step, wall, nl, tot, _ = timed(P.PREC_FP64)
+    iters_s = 1000.0 / ms_step
+    applies_s = iters_s * nb * (ncg + 1)
+    status = pl.status()
+    roofline = roofline_of(ms_step, nl, tot, P.PREC_FP64)
+    tta64 = tta(P.PREC_FP64)
+
+    # mixed: the whole step is timed; its FP32 plane kernel is timed alone below
+    ms_m, wall_m, _, _, n32 = timed(P.PREC_MIXED)
+    iters_m = 1000.0 / ms_m
+    mixed = {"value": iters_m, "unit": "ParO outer iterations/s", "ms_per_step": ms_m, "wall_s_timed": wall_m,
+             "hpsi_applies_per_s": iters_m * nb * (ncg + 1), "dtype": "f32 source problems, f64 H U and RR",
+             "speedup_vs_fp64": ms_step / ms_m, "status_flags": pl.status(),
+             "time_to_1e-8": tta(P.PREC_MIXED)}
+    # FP32 plane kernel alone (the mixed step's dominant kernel), HIP events over 10 FP32 applies
+    import ctypes as C
+    x32 = x0.to(torch.complex64)
+    pl.apply_h_f32(x32)
+    torch.cuda.synchronize()
+    L.check(lib.paro_profile_start(L.K_PLANE, 1 << 12), "paro_profile_start")
+    for _ in range(10):
+        pl.apply_h_f32(x32)
+    nlf, totf = C.c_int32(), C.c_double()
+    L.check(lib.paro_profile_stop(C.byref(nlf), C.byref(totf)), "paro_profile_stop")
+    mixed["roofline"] = roofline_of(ms_m, nlf.value, totf.value, P.PREC_MIXED)
+    mixed["roofline"]["share_of_step"] = (totf.value / nlf.value) * n32 / max(args.steps, 1) / ms_m
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -248,7 +290,7 @@ def main():
                       "bands_converged": nconv, "projectors": pl.n_proj, "pcg_steps": ncg,
                       "variant": "ParO (Algorithm 1)", "shift": "adaptive", "parallelism": "single GPU"},
            "hpsi_applies_per_s": applies_s, "wall_s_timed": wall, "status_flags": status,
-           "roofline": roofline, "time_to_1e-8": tta, "cpu_baseline": cpu}
+           "roofline": roofline, "time_to_1e-8": tta64, "mixed": mixed, "cpu_baseline": cpu}
     print(json.dumps(rec))
 
 
