@@ -257,7 +257,10 @@ class Hamiltonian:
     def shift_bound(self):
         return float(self._lib.orc_shift_bound(self._h))
 
-    def pcg(self, psi, hpsi, eps, shift, ncg, gamma_hist=False, correction=False):
+    def pcg(self, psi, hpsi, eps, shift, ncg, gamma_hist=False, correction=False, projected=False):
+        """n_cg PCG steps per band: the source problem of Algorithm 1 (from u = psi), the
+        correction equation of Algorithm 2 (correction=True, from e = 0) or the projected
+        correction equation of Algorithm 3 (projected=True).  Returns (u or e, flags)."""
         psi, hpsi = _cc(psi), _cc(hpsi)
         nb = psi.shape[0]
         eps = _cd(eps)
@@ -265,12 +268,13 @@ class Hamiltonian:
         u = np.zeros_like(psi)
         flags = np.zeros(nb, np.int32)
         gh = np.zeros((nb, ncg + 1)) if gamma_hist else None
-        self._lib.orc_pcg(self._h, nb, _v(psi), _v(hpsi), _d(eps), _d(sh), ncg, int(correction), _v(u), _i(flags),
+        mode = 2 if projected else int(bool(correction))
+        self._lib.orc_pcg(self._h, nb, _v(psi), _v(hpsi), _d(eps), _d(sh), ncg, mode, _v(u), _i(flags),
                           None if gh is None else _d(gh))
         return (u, flags, gh) if gamma_hist else (u, flags)
 
     def paro(self, trial, n_outer, ncg, sigma_lb, variant=0, shift_mode=0):
-        """ParO (variant 0) or MParO I (variant 1) from a trial block.
+        """ParO (variant 0), MParO I (variant 1) or MParO II (variant 2) from a trial block.
 
         Returns dict(eps, psi, hpsi, eps_hist, res_hist, sigma_hist, flags)."""
         psi = _cc(trial).copy()

@@ -696,13 +696,34 @@ double orc_teter(double x)
 /* r0 = eps psi - H psi uses the carried H psi.                          */
 /* A band stops on p^H (H - sigma) p <= 0 (flag NEGCURV) or when         */
 /* r^H z <= 1e-26 r0^H z0.                                               */
-/* correction = 1: the correction equation of Algorithm 2, step 3,       */
+/* mode 1: the correction equation of Algorithm 2, step 3,               */
 /*   (H - sigma_b) e_b = -(H psi_b - eps_b psi_b), from e = 0: the same   */
 /*   Krylov iteration (r0 is identical), the iterate is e = u - psi       */
 /*   accumulated directly instead of formed by a difference.             */
+/* mode 2: the projected correction equation of Algorithm 3, step 3,     */
+/*   (I - P)(H - sigma_b)(I - P) e_b = (eps_b - H) psi_b, P = psi psi^H /  */
+/*   |psi|^2 (the projector onto psi), the shift sigma_b in place of the  */
+/*   printed lambda so that the operator is positive definite on the     */
+/*   complement of psi: CG from e = 0 in that complement, with the       */
+/*   residual, the preconditioned residual and (H - sigma) p projected.   */
 /* ------------------------------------------------------------------ */
+/* x <- x - psi (psi^H x) / (psi^H psi) */
+static void project_out(int64_t ng, const cplx *psi, cplx *x)
+{
+    cplx c = 0;
+    double n = 0;
+    for (int64_t g = 0; g < ng; ++g) {
+        c += conj(psi[g]) * x[g];
+        n += creal(psi[g]) * creal(psi[g]) + cimag(psi[g]) * cimag(psi[g]);
+    }
+    if (n > 0) {
+        c /= n;
+        for (int64_t g = 0; g < ng; ++g) x[g] -= c * psi[g];
+    }
+}
+
 static int32_t pcg_band(const orc_ham *h, const cplx *psi, const cplx *hpsi, double eps, double sigma,
-                        int ncg, int correction, cplx *u, cplx *r, cplx *z, cplx *p, cplx *q, cplx *work,
+                        int ncg, int mode, cplx *u, cplx *r, cplx *z, cplx *p, cplx *q, cplx *work,
                         double *gamma_hist)
 {
     int64_t ng = h->ng;
@@ -713,11 +734,15 @@ static int32_t pcg_band(const orc_ham *h, const cplx *psi, const cplx *hpsi, dou
         nrm += a2;
     }
     double tau = tkin / nrm;
+    for (int64_t g = 0; g < ng; ++g) {
+        u[g] = mode ? 0 : psi[g];
+        r[g] = eps * psi[g] - hpsi[g];
+    }
+    if (mode == 2) project_out(ng, psi, r);
+    for (int64_t g = 0; g < ng; ++g) z[g] = orc_teter(h->kin[g] / tau) * r[g];
+    if (mode == 2) project_out(ng, psi, z);
     double gamma = 0;
     for (int64_t g = 0; g < ng; ++g) {
-        u[g] = correction ? 0 : psi[g];
-        r[g] = eps * psi[g] - hpsi[g];
-        z[g] = orc_teter(h->kin[g] / tau) * r[g];
         p[g] = z[g];
         gamma += creal(conj(r[g]) * z[g]);
     }
@@ -727,17 +752,19 @@ static int32_t pcg_band(const orc_ham *h, const cplx *psi, const cplx *hpsi, dou
     if (!(gamma0 > 0)) return isnan(gamma0) ? ORC_F_NAN : 0;
     for (int k = 1; k <= ncg; ++k) {
         apply_one(h, p, sigma, q, work);
+        if (mode == 2) project_out(ng, psi, q);
         double pq = 0;
         for (int64_t g = 0; g < ng; ++g) pq += creal(conj(p[g]) * q[g]);
         if (!(pq > 0)) { flags |= isnan(pq) ? ORC_F_NAN : ORC_F_NEGCURV; break; }
         double alpha = gamma / pq;
-        double gnew = 0;
         for (int64_t g = 0; g < ng; ++g) {
             u[g] += alpha * p[g];
             r[g] -= alpha * q[g];
             z[g] = orc_teter(h->kin[g] / tau) * r[g];
-            gnew += creal(conj(r[g]) * z[g]);
         }
+        if (mode == 2) project_out(ng, psi, z);
+        double gnew = 0;
+        for (int64_t g = 0; g < ng; ++g) gnew += creal(conj(r[g]) * z[g]);
         if (gamma_hist) gamma_hist[k] = gnew;
         if (gnew <= 1e-26 * gamma0) break;
         double beta = gnew / gamma;
@@ -748,7 +775,7 @@ static int32_t pcg_band(const orc_ham *h, const cplx *psi, const cplx *hpsi, dou
 }
 
 int32_t orc_pcg(const orc_ham *h, int32_t nb, const cplx *psi, const cplx *hpsi, const double *eps,
-                const double *shift, int32_t ncg, int32_t correction, cplx *u, int32_t *flags,
+                const double *shift, int32_t ncg, int32_t mode, cplx *u, int32_t *flags,
                 double *gamma_hist)
 {
     int64_t ng = h->ng, mtot = (int64_t)h->M[0] * h->M[1] * h->M[2];
@@ -761,7 +788,7 @@ int32_t orc_pcg(const orc_ham *h, int32_t nb, const cplx *psi, const cplx *hpsi,
 #pragma omp for schedule(dynamic, 1)
         for (int b = 0; b < nb; ++b) {
             int32_t f = pcg_band(h, psi + (int64_t)b * ng, hpsi + (int64_t)b * ng, eps[b], shift[b], ncg,
-                                 correction, u + (int64_t)b * ng, r, z, p, q, work,
+                                 mode, u + (int64_t)b * ng, r, z, p, q, work,
                                  gamma_hist ? gamma_hist + (int64_t)b * (ncg + 1) : NULL);
             if (flags) flags[b] = f;
             all |= f;
@@ -826,7 +853,9 @@ static void residual_norms(int64_t ng, int nb, const cplx *psi, const cplx *hpsi
 /* 5; the cutoff is not raised).  variant 0: Algorithm 1, RR on the      */
 /* source solutions u; variant 1: Algorithm 2 (MParO I), RR on           */
 /* span{psi, e} with e the solution of the correction equation         */
-/* (H - sigma) e = -(H psi - eps psi) (e = u - psi), normalised.          */
+/* (H - sigma) e = -(H psi - eps psi) (e = u - psi), normalised;          */
+/* variant 2: Algorithm 3 (MParO II), the same with e from the           */
+/* projected correction equation (pcg_band mode 2).                       */
 /*                                                                       */
 /* psi: in the trial block, out the Ritz vectors (nb bands).             */
 /* shift_mode 0: sigma = sigma_lb for every step.                        */
@@ -842,7 +871,7 @@ int32_t orc_paro(const orc_ham *h, int32_t nb, cplx *psi, cplx *hpsi, double *ep
 {
     int64_t ng = h->ng;
     int32_t all = 0;
-    int m = variant == 1 ? 2 * nb : nb;
+    int m = variant >= 1 ? 2 * nb : nb;
     cplx *U = (cplx *)malloc(sizeof(cplx) * ng * m);
     cplx *W = (cplx *)malloc(sizeof(cplx) * ng * m);
     double *sig = (double *)malloc(sizeof(double) * nb);
@@ -863,17 +892,17 @@ int32_t orc_paro(const orc_ham *h, int32_t nb, cplx *psi, cplx *hpsi, double *ep
             double s = eps[0] - 0.05 - res[0];
             if (s > sigma) sigma = s;
         }
-        /* Algorithm 1: u into U[0:nb]; Algorithm 2: e into U[nb:2nb] */
-        cplx *sol = variant == 1 ? U + ng * nb : U;
+        /* Algorithm 1: u into U[0:nb]; Algorithms 2 and 3: e into U[nb:2nb] */
+        cplx *sol = variant >= 1 ? U + ng * nb : U;
         for (int attempt = 0; attempt < 2; ++attempt) {
             for (int b = 0; b < nb; ++b) sig[b] = sigma;
-            int32_t pf = orc_pcg(h, nb, psi, hpsi, eps, sig, ncg, variant == 1, sol, fl, NULL);
+            int32_t pf = orc_pcg(h, nb, psi, hpsi, eps, sig, ncg, variant, sol, fl, NULL);
             if ((pf & ORC_F_NEGCURV) && sigma != sigma_lb) { sigma = sigma_lb; all |= ORC_F_NEGCURV; continue; }
             all |= pf;
             break;
         }
         if (sigma_hist) sigma_hist[it] = sigma;
-        if (variant == 1) {
+        if (variant >= 1) {
             /* U = [psi, e/|e|]; W = [H psi, H e] */
             cplx *E = U + ng * nb;
             for (int b = 0; b < nb; ++b) {

@@ -319,6 +319,45 @@ def test_pcg_exact_eigenvector_is_fixed_point():
     assert np.abs(u - psi).max() < 1e-11
 
 
+def test_projected_correction_solves_the_projected_system():
+    """Algorithm 3, step 3: with n_cg = n_g the projected PCG gives the solution
+    of (I - P)(H - sigma)(I - P) e = (eps - H) psi on the complement of psi,
+    computed independently in an orthonormal basis Q of that complement:
+    e = Q (Q^H (H - sigma) Q)^-1 Q^H (eps psi - H psi)."""
+    spec, c, v, h = tiny(seed=3, a=5.0, ecut=2.5, grid=16)
+    H = h.dense()
+    sigma = h.shift_bound()
+    rng = np.random.default_rng(11)
+    nb = 3
+    psi = rng.standard_normal((nb, h.ng)) + 1j * rng.standard_normal((nb, h.ng))
+    psi /= np.linalg.norm(psi, axis=1)[:, None]
+    hpsi = psi @ H.T
+    eps = np.einsum("bg,bg->b", psi.conj(), hpsi).real
+    e, flags = h.pcg(psi, hpsi, eps, sigma, h.ng, projected=True)
+    assert not flags.any()
+    A = H - sigma * np.eye(h.ng)
+    for b in range(nb):
+        # orthonormal basis of the complement of psi_b: trailing columns of a full QR
+        Q, _ = np.linalg.qr(np.column_stack([psi[b], rng.standard_normal((h.ng, h.ng - 1))]), mode="complete")
+        Q = Q[:, 1:]
+        rhs = eps[b] * psi[b] - hpsi[b]
+        ref = Q @ np.linalg.solve(Q.conj().T @ A @ Q, Q.conj().T @ rhs)
+        assert np.linalg.norm(e[b] - ref) < 1e-9 * np.linalg.norm(ref)
+        assert abs(np.vdot(psi[b], e[b])) < 1e-12 * np.linalg.norm(e[b])
+        # not the unprojected correction of Algorithm 2
+        e2 = np.linalg.solve(A, rhs)
+        assert np.linalg.norm(e2 - ref) > 1e-3 * np.linalg.norm(ref)
+
+
+def test_projected_correction_vanishes_at_an_eigenvector():
+    spec, c, v, h = tiny(seed=3, a=5.0, ecut=2.5, grid=16)
+    H = h.dense()
+    lam, Vec = np.linalg.eigh(H)
+    psi = Vec[:, :2].T.copy()
+    e, flags = h.pcg(psi, psi @ H.T, lam[:2], h.shift_bound(), 10, projected=True)
+    assert np.abs(e).max() < 1e-12
+
+
 def test_pcg_negative_curvature_flag():
     spec, c, v, h = tiny(seed=3, a=5.0, ecut=2.5, grid=16)
     H = h.dense()
@@ -402,6 +441,19 @@ def test_paro_converges_tiny_cell():
     assert np.abs(r["eps"][:4] - lam[:4]).max() < 1e-9
     # eigenvalue errors never go negative (Ritz values are upper bounds)
     assert np.all(r["eps_hist"][:, :4] - lam[:4] > -1e-12)
+
+
+def test_mparo2_converges_on_the_1503_plane_wave_cell():
+    """Algorithm 3 (MParO II) reaches the dense eigenvalues like Algorithm 2."""
+    spec = synth.WORKLOADS["c0"]
+    c, v = cell_data(spec, 0)
+    h = oracle.Hamiltonian(c["cell"], c["ecut"], v, c["projectors"])
+    lam = np.linalg.eigvalsh(h.dense())
+    x = synth.trial_block(h.ng, 16, 0)
+    r = h.paro(x, 30, 10, h.shift_bound(), variant=2, shift_mode=1)
+    err = np.abs(r["eps_hist"][:, :8] - lam[:8]).max(axis=1)
+    assert err[-1] < 1e-8
+    assert r["flags"] == 0
 
 
 def test_mparo_converges_on_the_1503_plane_wave_cell():
