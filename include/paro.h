@@ -74,6 +74,10 @@ extern "C" {
 /* solver variants of paro_iterate */
 #define PARO_VARIANT_PARO 0    /* Algorithm 1: Rayleigh-Ritz on span{u_i} (m = nb) */
 #define PARO_VARIANT_MPARO1 1  /* Algorithm 2: Rayleigh-Ritz on span{psi_i, e_i} (m = 2 nb) */
+#define PARO_VARIANT_MPARO2 2  /* Algorithm 3: as Algorithm 2 with e_i from the projected
+                                  correction equation (I - P_i)(H - sigma_i)(I - P_i) e_i =
+                                  (eps_i - H) psi_i, P_i the projector onto psi_i (the shift
+                                  sigma_i read for the printed lambda); FP64 only */
 
 typedef void *paro_stream_t; /* a hipStream_t; NULL is the default stream */
 typedef struct paro_plan_s *paro_plan;
@@ -246,8 +250,9 @@ int32_t paro_residual_norms(paro_plan plan, int32_t nb, const double *psi, const
 int32_t paro_shift_lower_bound(paro_plan plan, double *sigma_dev, void *ws, size_t ws_bytes);
 
 /* ParO at fixed cutoff (Algorithm 1 steps 1, 3, 4, 5; Algorithm 2 for
- * variant MPARO1): up to opts->n_outer outer iterations of nb source
- * problems followed by Rayleigh-Ritz (m = nb, or 2 nb for MPARO1).
+ * variant MPARO1, Algorithm 3 for MPARO2): up to opts->n_outer outer
+ * iterations of nb source problems followed by Rayleigh-Ritz (m = nb, or
+ * 2 nb for MPARO1 and MPARO2).  PARO_EUNSUP for MPARO2 in mixed precision.
  * psi: in the trial block (initial_rr = 1) or orthonormal Ritz vectors with
  * hpsi = H psi and eps (initial_rr = 0); out the Ritz vectors.  hpsi, eps:
  * out (in when initial_rr = 0).  sigma: dev double[1], out: the shift the

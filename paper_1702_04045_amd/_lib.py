@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libparo.so")
 PARO_OK, PARO_EINVAL, PARO_EALIAS, PARO_ESIZE, PARO_EHIP, PARO_EUNSUP = 0, -1, -2, -3, -4, -5
 F_NEGCURV, F_CHOL, F_NAN = 1, 2, 4
 SHIFT_FIXED, SHIFT_ADAPTIVE = 0, 1
-VARIANT_PARO, VARIANT_MPARO1 = 0, 1
+VARIANT_PARO, VARIANT_MPARO1, VARIANT_MPARO2 = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 K_STICK_INV, K_PLANE, K_STICK_FWD, K_GEMM_HN, K_GEMM_NN, K_PCG_UPDATE = 1, 2, 3, 4, 5, 6
 

@@ -17,7 +17,7 @@ constexpr int kMaxParts = 512;         // partial sums per band per reduction
 // per-band scalar slots (Workspace::sc, each nb long)
 enum { SC_GAMMA = 0, SC_GAMMA0, SC_TAU, SC_BETA, SC_NLQ, kScalars };
 // partial-sum slots (Workspace::dots, each nb x kMaxParts)
-enum { DOT_PQ = 0, DOT_RZ, DOT_TKIN, DOT_NRM, DOT_RES, kDotSlots };
+enum { DOT_PQ = 0, DOT_RZ, DOT_TKIN, DOT_NRM, DOT_RES, DOT_PJR, DOT_PJI, DOT_PJN, kDotSlots };
 
 struct Plan {
     hipStream_t stream = nullptr;
@@ -112,11 +112,16 @@ hipError_t launch_to_single(hipStream_t s, int64_t n, const double2 *src, float2
 hipError_t launch_build_projectors(const Plan &pl, const int32_t *miller_dev, const double *centers,
                                    const int32_t *lm, const double *widths);
 // vec.hip
+// proj_psi != null: the projected correction equation of Algorithm 3 (r0
+// and every z projected onto the complement of psi; implies correction)
 hipError_t launch_pcg_init(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
                            int64_t ld, const double *eps, double2 *u, int64_t ldu, int32_t *band_flags,
-                           bool correction);
+                           bool correction, const double2 *proj_psi = nullptr);
 hipError_t launch_pcg_update(const Plan &pl, const Workspace &w, int nb, double2 *u, int64_t ldu, int npq,
-                             int32_t *band_flags);
+                             int32_t *band_flags, const double2 *proj_psi = nullptr, int64_t ldpsi = 0);
+// x_b <- x_b - psi_b (psi_b^H x_b) / |psi_b|^2 (PCG vectors, leading dimension ldv)
+hipError_t launch_project_out(const Plan &pl, const Workspace &w, int nb, const double2 *psi, int64_t ld,
+                              double2 *x);
 // Mixed precision: the correction d = u - psi from d = 0 with FP32 vectors
 // (r32, z32, p32, q32, d32); r = eps psi - H psi is formed in FP64.
 hipError_t launch_pcg_init_mixed(const Plan &pl, const Workspace &w, int nb, const double2 *psi,

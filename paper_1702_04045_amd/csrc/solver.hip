@@ -20,11 +20,16 @@ static hipError_t apply_full(const Plan &pl, const Workspace &w, int nb, const d
     return gemm_nn(pl.stream, pl.ng, nb, pl.nproj, pl.beta, pl.ldv, w.P, pl.nproj, out, ld, true);
 }
 
+// mode 0: the source problem of Algorithm 1 (from u = psi); 1: the
+// correction equation of Algorithm 2 (from e = 0); 2: the projected
+// correction equation of Algorithm 3 (from e = 0 in the complement of psi;
+// r0, every z and every (H - sigma) p projected).
 static hipError_t source_solve(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
                                int64_t ld, const double *eps, const double *shift, int ncg, double2 *u, int64_t ldu,
-                               int32_t *band_flags, bool correction = false)
+                               int32_t *band_flags, int mode = 0)
 {
-    hipError_t e = launch_pcg_init(pl, w, nb, psi, hpsi, ld, eps, u, ldu, band_flags, correction);
+    const double2 *proj = mode == 2 ? psi : nullptr;
+    hipError_t e = launch_pcg_init(pl, w, nb, psi, hpsi, ld, eps, u, ldu, band_flags, mode >= 1, proj);
     double *pq_parts = w.dots + (size_t)DOT_PQ * nb * kMaxParts;
     for (int k = 1; k <= ncg && e == hipSuccess; ++k) {
         int npq = 0;
@@ -36,7 +41,9 @@ static hipError_t source_solve(const Plan &pl, const Workspace &w, int nb, const
             if (e == hipSuccess) e = gemm_nn(pl.stream, pl.ng, nb, pl.nproj, pl.beta, pl.ldv, w.P, pl.nproj, w.q,
                                              pl.ldv, true);
         }
-        if (e == hipSuccess) e = launch_pcg_update(pl, w, nb, u, ldu, npq, band_flags);
+        // p lies in the complement of psi, so p^H q is unchanged by the projection
+        if (e == hipSuccess && proj) e = launch_project_out(pl, w, nb, psi, ld, w.q);
+        if (e == hipSuccess) e = launch_pcg_update(pl, w, nb, u, ldu, npq, band_flags, proj, ld);
     }
     return e;
 }
@@ -271,7 +278,9 @@ int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi_, double *hpsi_, in
                      const paro_iter_opts *opts, double *stats, void *ws, size_t ws_bytes, int32_t *n_done)
 {
     if (!plan || nb <= 0 || !psi_ || !hpsi_ || !eps || !sigma || !opts || opts->n_outer < 0 || opts->n_cg < 0 ||
-        nb > 512 || (opts->variant != PARO_VARIANT_PARO && opts->variant != PARO_VARIANT_MPARO1) ||
+        nb > 512 ||
+        (opts->variant != PARO_VARIANT_PARO && opts->variant != PARO_VARIANT_MPARO1 &&
+         opts->variant != PARO_VARIANT_MPARO2) ||
         (opts->shift_mode != PARO_SHIFT_FIXED && opts->shift_mode != PARO_SHIFT_ADAPTIVE) ||
         (opts->precision != PARO_PREC_FP64 && opts->precision != PARO_PREC_MIXED)) {
         set_error("paro_iterate: bad argument");
@@ -281,6 +290,10 @@ int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi_, double *hpsi_, in
     if (ld < pl.ng) {
         set_error("paro_iterate: ld < n_g");
         return PARO_EINVAL;
+    }
+    if (opts->variant == PARO_VARIANT_MPARO2 && opts->precision != PARO_PREC_FP64) {
+        set_error("paro_iterate: MParO II runs in FP64 only");
+        return PARO_EUNSUP;
     }
     int32_t rc = check_ws(pl, nb, ws, ws_bytes);
     if (rc) return rc;
@@ -306,15 +319,15 @@ int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi_, double *hpsi_, in
             PARO_HIP_TRY(hipStreamSynchronize(st));
             if (c) break;
         }
-        const bool mparo = opts->variant == PARO_VARIANT_MPARO1;
-        double2 *Ut = mparo ? w.U + (size_t)nb * lv : w.U;  // u (Algorithm 1) or e (Algorithm 2)
+        const bool mparo = opts->variant != PARO_VARIANT_PARO;
+        double2 *Ut = mparo ? w.U + (size_t)nb * lv : w.U;  // u (Algorithm 1) or e (Algorithms 2, 3)
         for (int attempt = 0; attempt < 2; ++attempt) {
             if (opts->precision == PARO_PREC_MIXED)
                 PARO_CHECK_LAUNCH(source_solve_mixed(pl, w, nb, psi, hpsi, ld, eps, w.sig_all, opts->n_cg, Ut, lv,
                                                      w.iflags + nb, mparo));
             else
                 PARO_CHECK_LAUNCH(source_solve(pl, w, nb, psi, hpsi, ld, eps, w.sig_all, opts->n_cg, Ut, lv,
-                                               w.iflags + nb, mparo));
+                                               w.iflags + nb, opts->variant));
             if (opts->shift_mode != PARO_SHIFT_ADAPTIVE) break;
             // on negative curvature redo the source problems with sigma_lb
             double scur = 0.0;
@@ -330,7 +343,7 @@ int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi_, double *hpsi_, in
             PARO_CHECK_LAUNCH(launch_bookkeeping(pl, nb, fixed, eps, w.res, w.sig_all, sigma, nullptr, conv));
         }
         if (mparo) {
-            // span{psi, e/|e|}, e from the correction equation (Algorithm 2)
+            // span{psi, e/|e|}, e from the correction equation (Algorithms 2, 3)
             PARO_CHECK_LAUNCH(launch_normalize_bands(pl, w, nb, Ut, lv));
             PARO_CHECK_LAUNCH(launch_copy_bands(st, nb, pl.ng, psi, ld, w.U, lv));
             PARO_CHECK_LAUNCH(launch_copy_bands(st, nb, pl.ng, hpsi, ld, w.W, lv));

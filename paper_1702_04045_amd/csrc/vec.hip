@@ -153,6 +153,77 @@ k_finish_correction(int64_t ng, const double2 *__restrict__ base, int64_t ld, co
     }
 }
 
+// Partial sums of psi^H x (re, im) and |psi|^2 (projection onto the
+// complement of psi, Algorithm 3).
+__global__ void __launch_bounds__(kVecThreads)
+k_proj_parts(int64_t ng, const double2 *__restrict__ psi, int64_t ld, const double2 *__restrict__ x, int64_t ldx,
+             double *__restrict__ dots, int nb)
+{
+    __shared__ double red[kVecThreads / 64];
+    const int band = blockIdx.y;
+    const double2 *pp = psi + band * ld, *xx = x + band * ldx;
+    double cr = 0.0, ci = 0.0, nn = 0.0;
+    const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
+        const double2 a = pp[g], b = xx[g];
+        cr += a.x * b.x + a.y * b.y;
+        ci += a.x * b.y - a.y * b.x;
+        nn += a.x * a.x + a.y * a.y;
+    }
+    cr = block_sum<kVecThreads>(cr, red);
+    ci = block_sum<kVecThreads>(ci, red);
+    nn = block_sum<kVecThreads>(nn, red);
+    if (threadIdx.x == 0) {
+        dots[((size_t)DOT_PJR * nb + band) * kMaxParts + blockIdx.x] = cr;
+        dots[((size_t)DOT_PJI * nb + band) * kMaxParts + blockIdx.x] = ci;
+        dots[((size_t)DOT_PJN * nb + band) * kMaxParts + blockIdx.x] = nn;
+    }
+}
+
+// x <- x - c psi, c = psi^H x / |psi|^2 from k_proj_parts.  zout != null:
+// zout = K x (x is a residual); rref != null: partial Re(rref^H x) into
+// dots_rz (x is a preconditioned residual).
+__global__ void __launch_bounds__(kVecThreads)
+k_proj_sub(int64_t ng, int nparts, const double2 *__restrict__ psi, int64_t ld, double2 *__restrict__ x,
+           int64_t ldx, const double *__restrict__ dots, int nb, const double *__restrict__ kin,
+           const double *__restrict__ sc, double2 *__restrict__ zout, const double2 *__restrict__ rref,
+           double *__restrict__ dots_rz)
+{
+    __shared__ double red[kVecThreads / 64];
+    const int band = blockIdx.y;
+    const double cr = sum_parts(dots + ((size_t)DOT_PJR * nb + band) * kMaxParts, nparts);
+    const double ci = sum_parts(dots + ((size_t)DOT_PJI * nb + band) * kMaxParts, nparts);
+    const double nn = sum_parts(dots + ((size_t)DOT_PJN * nb + band) * kMaxParts, nparts);
+    const double s = nn > 0.0 ? 1.0 / nn : 0.0;
+    const double c_r = cr * s, c_i = ci * s;
+    const double tau = zout ? sc[SC_TAU * nb + band] : 1.0;
+    const double2 *pp = psi + band * ld;
+    double2 *xx = x + band * ldx;
+    double rz = 0.0;
+    const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
+        const double2 a = pp[g];
+        double2 v = xx[g];
+        v.x -= c_r * a.x - c_i * a.y;
+        v.y -= c_r * a.y + c_i * a.x;
+        xx[g] = v;
+        if (zout) {
+            const double k = teter(kin[g] / tau);
+            zout[band * ldx + g] = make_double2(k * v.x, k * v.y);
+        }
+        if (rref) {
+            const double2 r = rref[band * ldx + g];
+            rz += r.x * v.x + r.y * v.y;
+        }
+    }
+    if (rref) {
+        rz = block_sum<kVecThreads>(rz, red);
+        if (threadIdx.x == 0) dots_rz[(size_t)band * kMaxParts + blockIdx.x] = rz;
+    }
+}
+
 // Per-band PCG scalars.
 // stage 0 (after init): gamma = gamma0 = r^H z; active = gamma0 > 0.
 // stage 1 (after an update): stop on p^H q <= 0 (flag NEGCURV, or NAN), else
@@ -269,15 +340,45 @@ inline unsigned nchunks(int64_t ng) { return (unsigned)((ng + kVecChunk - 1) / k
 
 }  // namespace
 
+hipError_t launch_project_out(const Plan &pl, const Workspace &w, int nb, const double2 *psi, int64_t ld,
+                              double2 *x)
+{
+    const unsigned nc = nchunks(pl.ng);
+    hipLaunchKernelGGL(k_proj_parts, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, psi, ld, x, pl.ldv, w.dots,
+                       nb);
+    hipLaunchKernelGGL(k_proj_sub, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, (int)nc, psi, ld, x, pl.ldv,
+                       w.dots, nb, pl.kin, w.sc, (double2 *)nullptr, (const double2 *)nullptr, (double *)nullptr);
+    return hipGetLastError();
+}
+
+// z <- z - psi (psi^H z) / |psi|^2 with the partial r^H z of the projected z
+static void project_z(const Plan &pl, const Workspace &w, int nb, const double2 *psi, int64_t ld, unsigned nc)
+{
+    hipLaunchKernelGGL(k_proj_parts, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, psi, ld, w.z, pl.ldv,
+                       w.dots, nb);
+    hipLaunchKernelGGL(k_proj_sub, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, (int)nc, psi, ld, w.z,
+                       pl.ldv, w.dots, nb, pl.kin, w.sc, (double2 *)nullptr, (const double2 *)w.r,
+                       w.dots + (size_t)DOT_RZ * nb * kMaxParts);
+}
+
 hipError_t launch_pcg_init(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
                            int64_t ld, const double *eps, double2 *u, int64_t ldu, int32_t *band_flags,
-                           bool correction)
+                           bool correction, const double2 *proj_psi)
 {
     const unsigned nc = nchunks(pl.ng);
     hipLaunchKernelGGL(k_pcg_init_parts, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, psi, ld, pl.kin,
                        w.dots, nb);
     hipLaunchKernelGGL((k_pcg_init<double2, double2>), dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, (int)nc,
-                       psi, hpsi, ld, eps, pl.kin, u, ldu, w.r, w.z, pl.ldv, w.dots, w.sc, nb, correction ? 1 : 0);
+                       psi, hpsi, ld, eps, pl.kin, u, ldu, w.r, w.z, pl.ldv, w.dots, w.sc, nb,
+                       (correction || proj_psi) ? 1 : 0);
+    if (proj_psi) {
+        // r0 <- (I - P) r0, z0 = K r0, z0 <- (I - P) z0, partial r0^H z0
+        hipLaunchKernelGGL(k_proj_parts, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, proj_psi, ld, w.r,
+                           pl.ldv, w.dots, nb);
+        hipLaunchKernelGGL(k_proj_sub, dim3(nc, nb), dim3(kVecThreads), 0, pl.stream, pl.ng, (int)nc, proj_psi, ld,
+                           w.r, pl.ldv, w.dots, nb, pl.kin, w.sc, w.z, (const double2 *)nullptr, (double *)nullptr);
+        project_z(pl, w, nb, proj_psi, ld, nc);
+    }
     hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kVecThreads), 0, pl.stream, nb, 0, (int)nc, 0,
                        (const double *)nullptr, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags,
                        w.iflags + nb, band_flags, pl.status);
@@ -285,7 +386,7 @@ hipError_t launch_pcg_init(const Plan &pl, const Workspace &w, int nb, const dou
 }
 
 hipError_t launch_pcg_update(const Plan &pl, const Workspace &w, int nb, double2 *u, int64_t ldu, int npq,
-                             int32_t *band_flags)
+                             int32_t *band_flags, const double2 *proj_psi, int64_t ldpsi)
 {
     const unsigned nc = nchunks(pl.ng);
     prof_mark(PARO_K_PCG_UPDATE, pl.stream, true);
@@ -293,6 +394,7 @@ hipError_t launch_pcg_update(const Plan &pl, const Workspace &w, int nb, double2
                        w.p, w.q, pl.ldv, u, ldu, w.r, w.z, pl.kin, w.dots + (size_t)DOT_PQ * nb * kMaxParts,
                        w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags, nb);
     prof_mark(PARO_K_PCG_UPDATE, pl.stream, false);
+    if (proj_psi) project_z(pl, w, nb, proj_psi, ldpsi, nc);
     hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(kVecThreads), 0, pl.stream, nb, 1, (int)nc, npq,
                        w.dots + (size_t)DOT_PQ * nb * kMaxParts, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc,
                        w.iflags, w.iflags + nb, band_flags, pl.status);

@@ -248,7 +248,7 @@ class Plan:
     def iterate(self, psi, n_outer, n_cg, sigma_lb, hpsi=None, eps=None, variant=L.VARIANT_PARO,
                 shift_mode=L.SHIFT_FIXED, initial_rr=True, n_conv=None, tol_res=0.0, stats=True,
                 precision=L.PREC_FP64):
-        """ParO / MParO I outer iterations; psi is updated in place.  precision:
+        """ParO / MParO I / MParO II outer iterations; psi is updated in place.  precision:
         PREC_FP64, or PREC_MIXED (FP32 source problems, FP64 Rayleigh-Ritz).
 
         Returns dict(psi, hpsi, eps, sigma, stats (rows x (2 nb + 2)) or None, n_done)."""

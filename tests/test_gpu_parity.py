@@ -360,7 +360,8 @@ def test_paro_fixed_work_config_matches_oracle():
     assert pl.status() == 0
 
 
-@pytest.mark.parametrize("variant,shift_mode", [(1, 1), (0, 1)], ids=["mparo_adaptive", "paro_adaptive"])
+@pytest.mark.parametrize("variant,shift_mode", [(1, 1), (0, 1), (2, 1)],
+                         ids=["mparo_adaptive", "paro_adaptive", "mparo2_adaptive"])
 def test_paro_variants_match_oracle(variant, shift_mode):
     c, v, h, pl = make_case(C0, 1)
     nb = 12
@@ -374,7 +375,7 @@ def test_paro_variants_match_oracle(variant, shift_mode):
     if variant == 0:
         assert np.all(diff <= EIG_TOL * scale)
     else:
-        # Algorithm 2 adds e = (H - sigma)^-1 r; once band i is converged to
+        # Algorithms 2 and 3 add e = (H - sigma)^-1 r; once band i is converged to
         # round-off its r, hence e_i, is round-off noise, and the Ritz values
         # of the unconverged upper bands depend on that noise: GPU and oracle
         # histories then separate (about 10x per iteration).  Parity holds
@@ -392,13 +393,14 @@ def test_paro_variants_match_oracle(variant, shift_mode):
         assert subspace_sin(psi[i:j], ref["psi"][i:j]) < SIN_TOL
 
 
-def test_paro_converges_to_dense_eigenvalues():
-    """MParO I with buffer bands reaches the dense-diagonalisation eigenvalues (1e-8 Ha)."""
+@pytest.mark.parametrize("variant", [1, 2], ids=["mparo", "mparo2"])
+def test_paro_converges_to_dense_eigenvalues(variant):
+    """MParO I and II with buffer bands reach the dense-diagonalisation eigenvalues (1e-8 Ha)."""
     c, v, h, pl = make_case(C0, 0)
     lam = np.linalg.eigvalsh(h.dense())
     nb = 16
     x = synth.trial_block(h.ng, nb, 0)
-    out = pl.iterate(to_dev(x), 40, 10, h.shift_bound(), variant=1, shift_mode=1, n_conv=8, tol_res=1e-6)
+    out = pl.iterate(to_dev(x), 40, 10, h.shift_bound(), variant=variant, shift_mode=1, n_conv=8, tol_res=1e-6)
     eps = to_np(out["eps"])
     assert np.abs(eps[:8] - lam[:8]).max() < 1e-8
     assert out["n_done"] < 40
@@ -433,6 +435,14 @@ def test_paro_full_size_properties():
     assert rel_err(to_np(hpsi)[[0, nb - 1], :h.ng], h.apply(p)) < 1e-11
     assert pl.status() == 0
     torch.cuda.synchronize()
+
+
+def test_mparo2_rejects_mixed_precision():
+    import paper_1702_04045_amd as P
+    c, v, h, pl = make_case(TINY, 0)
+    x = synth.trial_block(h.ng, 2, 0)
+    with pytest.raises(P.ParoError):
+        pl.iterate(to_dev(x), 1, 2, h.shift_bound(), variant=P.VARIANT_MPARO2, precision=P.PREC_MIXED)
 
 
 def test_repeat_runs_are_bitwise_identical():
