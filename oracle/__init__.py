@@ -74,6 +74,7 @@ def _load():
         "orc_paro": (C.c_int32, [_vp, C.c_int32, _vp, _vp, _dp, C.c_int32, C.c_int32, C.c_int32,
                                  C.c_int32, C.c_double, _dp, _dp, _dp]),
         "orc_num_threads": (C.c_int32, []),
+        "orc_density": (None, [_vp, C.c_int32, _vp, _dp, _dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -272,6 +273,16 @@ class Hamiltonian:
         self._lib.orc_pcg(self._h, nb, _v(psi), _v(hpsi), _d(eps), _d(sh), ncg, mode, _v(u), _i(flags),
                           None if gh is None else _d(gh))
         return (u, flags, gh) if gamma_hist else (u, flags)
+
+    def density(self, psi, weights=None):
+        """rho_j = sum_b w_b |psi_b(r_j)|^2 on the FFT grid (C order [j1][j2][j3]); the
+        Hellmann-Feynman derivative of sum_b w_b eps_b with respect to V_j is rho_j / (N1 N2 N3)."""
+        psi = _cc(psi)
+        nb = psi.shape[0]
+        rho = np.zeros(self.grid)
+        w = None if weights is None else _cd(np.broadcast_to(np.asarray(weights, np.float64), (nb,)))
+        self._lib.orc_density(self._h, nb, _v(psi), None if w is None else _d(w), _d(rho))
+        return rho
 
     def paro(self, trial, n_outer, ncg, sigma_lb, variant=0, shift_mode=0):
         """ParO (variant 0), MParO I (variant 1) or MParO II (variant 2) from a trial block.

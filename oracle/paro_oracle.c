@@ -932,6 +932,75 @@ done:
     return all;
 }
 
+/* ------------------------------------------------------------------ */
+/* Electron density on the FFT grid (the quantity the Hellmann-Feynman    */
+/* derivative of the eigenvalue sum needs):                               */
+/*   rho_j = sum_b w_b |psi_b(r_j)|^2,                                    */
+/*   psi_b(r_j) = sum_G c_bG exp(2 pi i n.j / N)  (eq. (e2) at the grid   */
+/*   point r_j = sum_d (j_d / N_d) a_d, without the 1 / sqrt(Omega)).     */
+/* d(sum_b w_b eps_b) / dV_j = rho_j / (N1 N2 N3) for eigenpairs, since   */
+/* the matrix element of eq. (e5) is the grid sum                         */
+/* (1/N) sum_j V_j exp(-2 pi i (n_m - n_n).j / N).                        */
+/* Direct separable sums over n3, n2, n1 (no FFT).  Output C order        */
+/* [j1][j2][j3]; bands summed in order.                                   */
+/* ------------------------------------------------------------------ */
+void orc_density(const orc_ham *h, int32_t nb, const cplx *psi, const double *w, double *rho)
+{
+    const int N1 = h->grid[0], N2 = h->grid[1], N3 = h->grid[2];
+    const int m1 = h->nmax[0], m2 = h->nmax[1];
+    const int L1 = 2 * m1 + 1, L2 = 2 * m2 + 1;
+    const int64_t nv = (int64_t)N1 * N2 * N3;
+    cplx *t1 = (cplx *)malloc(sizeof(cplx) * N1), *t2 = (cplx *)malloc(sizeof(cplx) * N2);
+    cplx *t3 = (cplx *)malloc(sizeof(cplx) * N3);
+    for (int k = 0; k < N1; ++k) t1[k] = cexp(I * TWO_PI * k / N1);
+    for (int k = 0; k < N2; ++k) t2[k] = cexp(I * TWO_PI * k / N2);
+    for (int k = 0; k < N3; ++k) t3[k] = cexp(I * TWO_PI * k / N3);
+    double *per = (double *)calloc((size_t)nb * nv, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int b = 0; b < nb; ++b) {
+        const cplx *c = psi + (int64_t)b * h->ng;
+        /* A[n1][n2][j3] = sum_n3 c exp(2 pi i n3 j3 / N3) */
+        cplx *A = (cplx *)calloc((size_t)L1 * L2 * N3, sizeof(cplx));
+        for (int64_t g = 0; g < h->ng; ++g) {
+            const int n1 = h->miller[3 * g], n2 = h->miller[3 * g + 1], n3 = h->miller[3 * g + 2];
+            cplx *a = A + ((int64_t)(n1 + m1) * L2 + (n2 + m2)) * N3;
+            for (int j3 = 0; j3 < N3; ++j3) a[j3] += c[g] * t3[(((int64_t)n3 * j3) % N3 + N3) % N3];
+        }
+        /* B[n1][j2][j3] = sum_n2 A exp(2 pi i n2 j2 / N2) */
+        cplx *B = (cplx *)calloc((size_t)L1 * N2 * N3, sizeof(cplx));
+        for (int i1 = 0; i1 < L1; ++i1)
+            for (int i2 = 0; i2 < L2; ++i2) {
+                const cplx *a = A + ((int64_t)i1 * L2 + i2) * N3;
+                const int n2 = i2 - m2;
+                for (int j2 = 0; j2 < N2; ++j2) {
+                    const cplx e = t2[(((int64_t)n2 * j2) % N2 + N2) % N2];
+                    cplx *bb = B + ((int64_t)i1 * N2 + j2) * N3;
+                    for (int j3 = 0; j3 < N3; ++j3) bb[j3] += a[j3] * e;
+                }
+            }
+        /* psi[j1][j2][j3] = sum_n1 B exp(2 pi i n1 j1 / N1); |psi|^2 */
+        double *out = per + (int64_t)b * nv;
+        for (int j1 = 0; j1 < N1; ++j1)
+            for (int j2 = 0; j2 < N2; ++j2)
+                for (int j3 = 0; j3 < N3; ++j3) {
+                    cplx acc = 0;
+                    for (int i1 = 0; i1 < L1; ++i1) {
+                        const int n1 = i1 - m1;
+                        acc += B[((int64_t)i1 * N2 + j2) * N3 + j3] * t1[(((int64_t)n1 * j1) % N1 + N1) % N1];
+                    }
+                    out[((int64_t)j1 * N2 + j2) * N3 + j3] = creal(acc) * creal(acc) + cimag(acc) * cimag(acc);
+                }
+        free(A);
+        free(B);
+    }
+    for (int64_t j = 0; j < nv; ++j) {
+        double s = 0;
+        for (int b = 0; b < nb; ++b) s += (w ? w[b] : 1.0) * per[(int64_t)b * nv + j];
+        rho[j] = s;
+    }
+    free(per); free(t1); free(t2); free(t3);
+}
+
 int32_t orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -466,3 +466,79 @@ def test_mparo_converges_on_the_1503_plane_wave_cell():
     err = np.abs(r["eps_hist"][:, :8] - lam[:8]).max(axis=1)
     assert err[-1] < 1e-8
     assert r["flags"] == 0
+
+
+# ---------------------------------------------------------------- density and the eigenvalue gradient
+
+def _numpy_density(h, psi, w):
+    """|inverse FFT|^2 of the coefficients scattered onto the grid (numpy's FFT)."""
+    N = np.array(h.grid)
+    mil = h.miller
+    rho = np.zeros(h.grid)
+    for b in range(psi.shape[0]):
+        g = np.zeros(h.grid, complex)
+        g[mil[:, 0] % N[0], mil[:, 1] % N[1], mil[:, 2] % N[2]] = psi[b]
+        rho += w[b] * np.abs(np.fft.ifftn(g) * np.prod(N)) ** 2
+    return rho
+
+
+def test_density_vs_numpy_ifft_and_parseval():
+    spec, c, v, h = tiny(seed=9)
+    x = synth.trial_block(h.ng, 3, 9)
+    w = np.array([2.0, 0.5, 1.25])
+    rho = h.density(x, w)
+    ref = _numpy_density(h, x, w)
+    assert np.abs(rho - ref).max() < 1e-12 * ref.max()
+    # Parseval: sum_j |psi(r_j)|^2 = N1 N2 N3 ||c||^2 (grid holds the sphere without aliasing)
+    assert abs(rho.sum() - np.prod(h.grid) * (w * (np.abs(x) ** 2).sum(axis=1)).sum()) < 1e-10 * rho.sum()
+    # default weights are one
+    assert np.allclose(h.density(x), _numpy_density(h, x, np.ones(3)), rtol=0, atol=1e-12 * ref.max())
+
+
+def test_density_of_single_plane_waves_is_uniform():
+    """A plane wave has |psi|^2 = |c|^2 at every grid point, whatever its index."""
+    spec, c, v, h = tiny(seed=10)
+    x = np.zeros((3, h.ng), complex)
+    x[0, 0] = 1.0
+    x[1, h.ng // 2] = 0.6 - 0.8j
+    x[2, h.ng - 1] = 2.0j
+    rho = h.density(x, [1.0, 3.0, 0.25])
+    assert np.abs(rho - (1.0 + 3.0 + 0.25 * 4.0)).max() < 1e-12
+    # two plane waves: |a + b e^{2 pi i (n - n').j/N}|^2 is a cosine on the grid
+    mil = h.miller
+    x = np.zeros((1, h.ng), complex)
+    x[0, 0], x[0, 5] = 1.0, 0.5
+    rho = h.density(x)
+    dn = mil[5] - mil[0]
+    J = np.indices(h.grid).reshape(3, -1).T
+    ph = 2 * np.pi * (J * (dn / np.array(h.grid))).sum(axis=1)
+    ref = (1.25 + np.cos(ph)).reshape(h.grid)
+    assert np.abs(rho - ref).max() < 1e-12
+
+
+def test_density_is_the_hellmann_feynman_gradient_of_the_eigenvalue_sum():
+    """Central differences of the lowest dense eigenvalues (LAPACK) with respect to
+    V at single grid points equal rho_j / (N1 N2 N3) built from the eigenvectors."""
+    spec, c, v, h = tiny(seed=11)
+    lam, vec = np.linalg.eigh(h.dense())
+    # k with a clear gap above it, so the weighted sum is differentiable
+    k = next(k for k in range(4, 9) if lam[k] - lam[k - 1] > 1e-3)
+    w = np.linspace(2.0, 1.0, k)
+    rho = h.density(vec[:, :k].T.copy(), w)
+    nv = np.prod(h.grid)
+    rng = np.random.default_rng(11)
+    pts = [tuple(rng.integers(0, g) for g in h.grid) for _ in range(4)]
+    pts.append(tuple(int(i) for i in np.unravel_index(np.argmax(rho), h.grid)))
+    step = 1e-3
+    for j in pts:
+        vals = []
+        for s in (+step, -step):
+            vp = v.copy()
+            vp[j] += s
+            hp = oracle.Hamiltonian(c["cell"], c["ecut"], vp, c["projectors"])
+            vals.append(w @ np.linalg.eigvalsh(hp.dense())[:k])
+        fd = (vals[0] - vals[1]) / (2 * step)
+        assert abs(fd - rho[j] / nv) < 1e-8 * max(1.0, rho.max() / nv), (j, fd, rho[j] / nv)
+    # and the mirrored point j -> -j does not match where the density is not symmetric
+    jm = tuple((-np.array(pts[-1])) % np.array(h.grid))
+    assert abs(rho[jm] - rho[pts[-1]]) > 1e-3 * rho.max()
