@@ -281,6 +281,7 @@ int32_t paro_get_status(paro_plan plan, int32_t *flags);
 #define PARO_K_GEMM_HN 4     /* split-K A^H B partial tiles */
 #define PARO_K_GEMM_NN 5     /* A B (+ C) */
 #define PARO_K_PCG_UPDATE 6  /* PCG vector update and preconditioner */
+#define PARO_K_DENSITY 7     /* z-plane stage of paro_density: n2/n1 transforms and w |psi|^2 */
 
 /* Record a HIP event pair around every launch of one kernel class, on the
  * stream it is launched on, for up to max_launches launches, until
@@ -289,6 +290,28 @@ int32_t paro_get_status(paro_plan plan, int32_t *flags);
  * of timed launches and their summed duration in milliseconds. */
 int32_t paro_profile_start(int32_t kernel, int32_t max_launches);
 int32_t paro_profile_stop(int32_t *launches, double *total_ms);
+
+/* ---------------------------------------------------------------- density */
+
+/* Electron density of a block of orbitals on the FFT grid (Section 2.3,
+ * eq. (e2) at the grid points r_j = sum_d (j_d / N_d) a_d, without the
+ * 1/sqrt(Omega) normalisation):
+ *   rho[j] = sum_b w_b |psi_b(r_j)|^2,  psi_b(r_j) = sum_G c_bG exp(2 pi i n.j / N).
+ * For eigenpairs of H this is the Hellmann-Feynman gradient of the
+ * weighted band energy with respect to the local potential on the grid:
+ *   d (sum_b w_b eps_b) / d vloc[j] = rho[j] / (N1 N2 N3)
+ * (the matrix elements of eq. (e5) are (1/N) sum_j vloc[j] exp(-2 pi i
+ * (n_m - n_n).j / N)), and the gradient of sum_b w_b <psi_b|V|psi_b> for
+ * any block.
+ * psi: dev complex band-major, leading dimension ld >= n_g; weights: dev
+ * double[nb] or NULL (all 1); rho: dev double[N1 N2 N3], C order
+ * [j1][j2][j3] like paro_problem.vloc, overwritten.  Bands are summed in a
+ * fixed order: the result is bitwise reproducible.  ws: dev workspace of
+ * at least paro_density_workspace_bytes(nb) bytes.  Errors: PARO_EINVAL
+ * (NULL, nb <= 0, ld < n_g), PARO_ESIZE (workspace too small). */
+int32_t paro_density_workspace_bytes(paro_plan plan, int32_t nb, size_t *bytes);
+int32_t paro_density(paro_plan plan, int32_t nb, const double *psi, int64_t ld, const double *weights,
+                     double *rho, void *ws, size_t ws_bytes);
 
 /* ---------------------------------------------------------------- building blocks */
 

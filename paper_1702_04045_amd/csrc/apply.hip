@@ -214,6 +214,169 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
     }
 }
 
+// Density of bands b0 .. b1-1 (b1 - b0 <= bands per group) on one
+// z-plane: inverse along n2 and n1 as in k_plane, then w_b |psi_b(r)|^2
+// summed over the group's bands in registers, in band order.  With PAIR,
+// two bands per step: the lower line slots run the column transforms of
+// band k (at x = n1 mod N), the upper slots those of band k + 1 (shifted
+// by N/2); the row stage then reads both bands' populated entries of a row
+// into registers before the first row transform uses the row as exchange
+// space.  Without PAIR (large N, where the second band's registers would
+// spill) one band per step, its columns on the lower slots, and the
+// running sums wait in LDS between row stages, in the unpopulated n1 range
+// of the thread's own row (N - 2 nmax1 - 1 >= N / 2 complex slots, which
+// the column stage never writes), so that they take no registers during
+// the column transforms.  The group's partial plane is written in the
+// row-thread order of the potential, part[((z N + y) T + t) E + e].
+template <int N> constexpr bool density_pairs() { return N <= 64; }
+
+template <int N>
+__global__ void __launch_bounds__((plane_threads<N, double2>()))
+__attribute__((amdgpu_waves_per_eu(PlaneCfgP<N, double2>::min_waves)))
+k_plane_density(const double2 *__restrict__ sticks, int nst, int N3, int nb, int bpg,
+                const int32_t *__restrict__ cols, int nmax1, const double *__restrict__ weights,
+                const double2 *__restrict__ tw, double *__restrict__ part)
+{
+    using C = PlaneCfgP<N, double2>;
+    using Inv = typename C::Inv;
+    constexpr int T = C::T, E = C::E, LDX = N + 1, HALF = N / 2;
+    constexpr int RL = ListInfo<Inv>::last;
+    __shared__ double2 plane[N * LDX];
+    const int tid = threadIdx.x;
+    const int z = blockIdx.x, g = blockIdx.y;
+    const int b0 = g * bpg, b1 = min(b0 + bpg, nb);
+    const int ncol = 2 * nmax1 + 1;
+    const int slot = line_of<T>(tid);
+    int t = thread_in_line<T>(tid);
+    const bool lower = slot < HALF;
+    const int c = lower ? slot : slot - HALF;
+    const bool colact = c < ncol && slot < N;
+    int xcol = c - nmax1;
+    xcol += xcol < 0 ? N : 0;
+    const bool rowact = slot < N;
+    double2 *row = plane + (rowact ? slot : 0) * LDX;
+    int cst = 0, ylo = 0, cnt = 0;
+    if (colact) {
+        cst = cols[3 * c];
+        ylo = cols[3 * c + 1];
+        cnt = cols[3 * c + 2];
+    }
+    auto stick_of = [&](int i) {
+        const int k = (i > N / 2 ? i - N : i) - ylo;
+        return (unsigned)k < (unsigned)cnt ? k : -1;
+    };
+    constexpr bool PAIR = density_pairs<N>();
+    double acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = 0.0;
+    // this thread's E running sums between row stages (without PAIR)
+    double *stash = reinterpret_cast<double *>(row + nmax1 + 1) + t * E;
+    if (!PAIR && rowact)
+#pragma unroll
+        for (int e = 0; e < E; ++e) stash[e] = 0.0;
+    for (int k = b0; k < b1; k += PAIR ? 2 : 1) {
+        // Opaque per stage: keeps the per-element stick offsets and LDS
+        // addresses of one stage from being hoisted out of the band loop
+        // and held in registers through the other stage.
+        asm volatile("" : "+v"(ylo), "+v"(cnt), "+v"(t), "+v"(xcol));
+        {
+            const int kb = lower ? k : (PAIR ? k + 1 : b1);
+            const bool act = colact && kb < b1;
+            int xs = xcol + (lower ? 0 : HALF);
+            xs -= xs >= N ? N : 0;
+            double2 *col = plane + (act ? xs : 0);
+            const double2 *tz = sticks + ((size_t)(act ? kb : 0) * N3 + z) * nst + cst;
+            double2 v[E];
+            if (act) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
+                const int q = stick_of(i);
+                return q >= 0 ? tz[q] : cmk<double2>(0.0, 0.0);
+            });
+            stockham_c<C, +1, true>(Inv{}, v, t, act, col, LDX, tw);
+            wave_lds_sync();
+            if (act) final_foreach<N, T, E, RL>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
+        }
+        __syncthreads();
+        asm volatile("" : "+v"(t));
+        {
+            const bool two = PAIR && k + 1 < b1;
+            auto populated = [&](int i) { return i <= nmax1 || i >= N - nmax1; };
+            double2 v0[E], v1[E];
+            if (rowact) {
+                pass_load<N, T, E, ListInfo<Inv>::first>(v0, t, [&](int i) {
+                    return populated(i) ? row[i] : cmk<double2>(0.0, 0.0);
+                });
+                if (PAIR)
+                    pass_load<N, T, E, ListInfo<Inv>::first>(v1, t, [&](int i) {
+                        int x = i + HALF;
+                        x -= x >= N ? N : 0;
+                        return (two && populated(i)) ? row[x] : cmk<double2>(0.0, 0.0);
+                    });
+            }
+            if (!PAIR && rowact)
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc[e] = stash[e];
+            wave_lds_sync();
+            stockham_c<C, +1, true>(Inv{}, v0, t, rowact, row, 1, tw);
+            const double w0 = weights ? weights[k] : 1.0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] += w0 * (v0[e].x * v0[e].x + v0[e].y * v0[e].y);
+            if (!PAIR) {
+                wave_lds_sync();
+                if (rowact)
+#pragma unroll
+                    for (int e = 0; e < E; ++e) stash[e] = acc[e];
+            }
+            if (PAIR && two) {
+                wave_lds_sync();
+                stockham_c<C, +1, true>(Inv{}, v1, t, rowact, row, 1, tw);
+                const double w1 = weights ? weights[k + 1] : 1.0;
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc[e] += w1 * (v1[e].x * v1[e].x + v1[e].y * v1[e].y);
+            }
+        }
+        __syncthreads();
+    }
+    if (rowact) {
+        double *o = part + (size_t)g * N * N * N3 + (((size_t)z * N + slot) * T + t) * E;
+#pragma unroll
+        for (int e = 0; e < E; ++e) o[e] = acc[e];
+    }
+}
+
+// rho[x][y][z] (+)= sum_g part[g] over the groups of one chunk, in group
+// order, from the row-thread order of k_plane_density to C order.  One
+// work-group per (y, block of kRedZ planes); the block is transposed
+// through LDS so that both the partial reads and the rho writes are runs
+// of consecutive addresses.
+constexpr int kRedZ = 16;
+template <int N>
+__global__ void __launch_bounds__(256)
+k_density_reduce(const double *__restrict__ part, int ngroups, int N3, int accumulate, double *__restrict__ rho)
+{
+    using C = PlaneCfgP<N, double2>;
+    constexpr int T = C::T, E = C::E, RL = ListInfo<typename C::Inv>::last;
+    __shared__ double tile[N * (kRedZ + 1)];
+    const int y = blockIdx.x, z0 = blockIdx.y * kRedZ;
+    const int nz = min(kRedZ, N3 - z0);
+    const size_t gstride = (size_t)N * N * N3;
+    for (int idx = threadIdx.x; idx < nz * N; idx += 256) {
+        const int zz = idx / N, q = idx - zz * N;
+        const int t = q / E, e = q - t * E;
+        const int x = t + T * (e / RL) + (e % RL) * (N / RL);
+        const double *p = part + ((size_t)(z0 + zz) * N + y) * N + q;
+        double s = 0.0;
+        for (int gi = 0; gi < ngroups; ++gi) s += p[gi * gstride];
+        tile[x * (kRedZ + 1) + zz] = s;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nz * N; idx += 256) {
+        const int x = idx / nz, zz = idx - x * nz;
+        double *o = rho + ((size_t)x * N + y) * N3 + z0 + zz;
+        const double v = tile[x * (kRedZ + 1) + zz];
+        *o = accumulate ? *o + v : v;
+    }
+}
+
 // Potential in the row-thread order of k_plane<N>: out[((z N + y) T + t) E + e]
 // = V(i1 = x(t, e), i2 = y, i3 = z), x(t, e) = t + T (e / RL) + (e % RL)(N / RL),
 // from vloc in C order [i1][i2][i3].
@@ -327,6 +490,29 @@ hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const C2 *src, 
     return hipGetLastError();
 }
 
+template <int N>
+hipError_t run_density(const Plan &pl, double2 *sticks, double *part, int nb, const double2 *psi, int64_t ld,
+                       const double *weights, double *rho)
+{
+    constexpr int S = kStickThreads / FftCfg<N>::T;
+    const int N3 = pl.grid[2];
+    const int ntiles = (pl.nst + S - 1) / S;
+    for (int c0 = 0; c0 < nb; c0 += kMaxBandsPerChunk) {
+        const int cb = min(kMaxBandsPerChunk, nb - c0);
+        const int ng = (cb + kDensityBandsPerGroup - 1) / kDensityBandsPerGroup;
+        hipLaunchKernelGGL((k_stick_inv<N, double2>), dim3(ntiles, cb), dim3(kStickThreads), 0, pl.stream,
+                           psi + c0 * ld, ld, nullptr, nullptr, 0, sticks, pl.nst, pl.st_start, pl.pt_sz, pl.tw[2]);
+        prof_mark(PARO_K_DENSITY, pl.stream, true);
+        hipLaunchKernelGGL((k_plane_density<N>), dim3(N3, ng), dim3(plane_threads<N, double2>()), 0, pl.stream,
+                           sticks, pl.nst, N3, cb, kDensityBandsPerGroup, pl.cols, pl.nmax[0],
+                           weights ? weights + c0 : nullptr, pl.tw[0], part);
+        prof_mark(PARO_K_DENSITY, pl.stream, false);
+        hipLaunchKernelGGL((k_density_reduce<N>), dim3(N, (N3 + kRedZ - 1) / kRedZ), dim3(256), 0, pl.stream, part,
+                           ng, N3, c0 > 0 ? 1 : 0, rho);
+    }
+    return hipGetLastError();
+}
+
 template <class C2>
 hipError_t local_apply(const Plan &pl, const Workspace &w, int nb, const C2 *src, int64_t ld, C2 *out,
                        const double *shift, C2 *pbuf, const double *beta, bool first, double *dot_part,
@@ -350,6 +536,19 @@ bool fft_supported(int n)
     switch (n) {
     case 8: case 16: case 24: case 32: case 40: case 48: case 64: case 80: case 96: return true;
     default: return false;
+    }
+}
+
+hipError_t launch_density(const Plan &pl, double2 *sticks, double *part, int nb, const double2 *psi, int64_t ld,
+                          const double *weights, double *rho)
+{
+    switch (pl.grid[0]) {
+#define PARO_CASE(n) \
+    case n: return run_density<n>(pl, sticks, part, nb, psi, ld, weights, rho);
+    PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
+    PARO_CASE(80) PARO_CASE(96)
+#undef PARO_CASE
+    default: return hipErrorInvalidValue;
     }
 }
 

@@ -13,6 +13,7 @@ namespace paro {
 constexpr int kMaxBandsPerChunk = 64;  // bands per sphere->stick->plane pass (stick buffer size)
 constexpr int kSplitTarget = 512;      // aim for about this many split-K work-groups
 constexpr int kMaxParts = 512;         // partial sums per band per reduction
+constexpr int kDensityBandsPerGroup = 8;  // bands one work-group of the density kernel sums
 
 // per-band scalar slots (Workspace::sc, each nb long)
 enum { SC_GAMMA = 0, SC_GAMMA0, SC_TAU, SC_BETA, SC_NLQ, kScalars };
@@ -65,6 +66,8 @@ struct Workspace {
 
 size_t workspace_bytes(const Plan &pl, int nb);
 Workspace carve_workspace(const Plan &pl, int nb, void *ws);
+// bytes of the paro_density workspace; *part_off: offset of the partial grids
+size_t density_workspace_bytes(const Plan &pl, int nb, size_t *part_off);
 size_t dense_real_elems(int mmax);
 
 void set_error(const std::string &msg);
@@ -95,6 +98,10 @@ hipError_t launch_local_apply(const Plan &pl, const Workspace &w, int nb, const 
 hipError_t launch_local_apply(const Plan &pl, const Workspace &w, int nb, const float2 *src, int64_t ld, float2 *out,
                               const double *shift, float2 *pbuf, const double *beta, bool first, double *dot_part,
                               int *nparts_out);
+// rho (C order [i1][i2][i3]) = sum_b w_b |psi_b(r)|^2 on the FFT grid, weights
+// null = 1; sticks: min(64, nb) x N3 x nst, part: ceil(min(64, nb) / 8) grids
+hipError_t launch_density(const Plan &pl, double2 *sticks, double *part, int nb, const double2 *psi, int64_t ld,
+                          const double *weights, double *rho);
 // gemm.hip
 hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const double2 *A, int64_t lda, const double2 *B,
                    int64_t ldb, double2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale,

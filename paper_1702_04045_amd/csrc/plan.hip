@@ -236,6 +236,18 @@ size_t workspace_bytes(const Plan &pl, int nb)
     return tot;
 }
 
+// Density workspace: the sticks of one chunk, then one partial grid per
+// band group of a chunk.
+size_t density_workspace_bytes(const Plan &pl, int nb, size_t *part_off)
+{
+    const size_t cb = std::min<size_t>(kMaxBandsPerChunk, nb);
+    const size_t ngrp = (cb + kDensityBandsPerGroup - 1) / kDensityBandsPerGroup;
+    const size_t nv = (size_t)pl.grid[0] * pl.grid[1] * pl.grid[2];
+    const size_t off = align256(sizeof(double2) * cb * pl.grid[2] * pl.nst);
+    if (part_off) *part_off = off;
+    return align256(off + sizeof(double) * ngrp * nv);
+}
+
 Workspace carve_workspace(const Plan &pl, int nb, void *ws)
 {
     Workspace w{};
@@ -508,7 +520,7 @@ int32_t paro_get_projectors(paro_plan plan, double *beta_dev)
 
 int32_t paro_profile_start(int32_t kernel, int32_t max_launches)
 {
-    if (kernel < PARO_K_STICK_INV || kernel > PARO_K_PCG_UPDATE || max_launches <= 0 || max_launches > (1 << 20))
+    if (kernel < PARO_K_STICK_INV || kernel > PARO_K_DENSITY || max_launches <= 0 || max_launches > (1 << 20))
         return fail(PARO_EINVAL, "paro_profile_start: bad kernel class or launch count");
     if (g_prof) return fail(PARO_EINVAL, "paro_profile_start: a profile is already running");
     Profiler *p = new (std::nothrow) Profiler();

@@ -157,6 +157,43 @@ int32_t paro_apply_h(paro_plan plan, int32_t nb, const double *psi, int64_t ld, 
     return PARO_OK;
 }
 
+int32_t paro_density_workspace_bytes(paro_plan plan, int32_t nb, size_t *bytes)
+{
+    if (!plan || nb <= 0 || !bytes) {
+        set_error("paro_density_workspace_bytes: bad argument");
+        return PARO_EINVAL;
+    }
+    *bytes = density_workspace_bytes(plan->pl, nb, nullptr);
+    return PARO_OK;
+}
+
+int32_t paro_density(paro_plan plan, int32_t nb, const double *psi, int64_t ld, const double *weights, double *rho,
+                     void *ws, size_t ws_bytes)
+{
+    if (!plan || nb <= 0 || !psi || !rho || !ws) {
+        set_error("paro_density: bad argument");
+        return PARO_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(ws) % 256) {
+        set_error("paro_density: workspace must be 256-byte aligned");
+        return PARO_EINVAL;
+    }
+    const Plan &pl = plan->pl;
+    if (ld < pl.ng) {
+        set_error("paro_density: ld < n_g");
+        return PARO_EINVAL;
+    }
+    size_t off = 0;
+    if (ws_bytes < density_workspace_bytes(pl, nb, &off)) {
+        set_error("paro_density: workspace smaller than paro_density_workspace_bytes");
+        return PARO_ESIZE;
+    }
+    char *base = static_cast<char *>(ws);
+    PARO_CHECK_LAUNCH(launch_density(pl, reinterpret_cast<double2 *>(base), reinterpret_cast<double *>(base + off),
+                                     nb, (const double2 *)psi, ld, weights, rho));
+    return PARO_OK;
+}
+
 int32_t paro_apply_h_f32(paro_plan plan, int32_t nb, const float *psi, int64_t ld, const double *shift, float *hpsi,
                          void *ws, size_t ws_bytes)
 {

@@ -184,6 +184,31 @@ class Plan:
                 "paro_apply_h_f32")
         return out
 
+    def density(self, psi, weights=None, out=None):
+        """rho_j = sum_b w_b |psi_b(r_j)|^2 on the FFT grid (float64, shape grid, C order).
+        For eigenpairs, d(sum_b w_b eps_b)/d vloc_j = rho_j / (N1 N2 N3)."""
+        torch = _torch()
+        self._check_block(psi)
+        nb = psi.shape[0]
+        if weights is not None:
+            assert weights.dtype == torch.float64 and weights.device == self.device and weights.numel() >= nb
+            weights = weights.contiguous()
+        out = out if out is not None else torch.empty(self.grid, dtype=torch.float64, device=self.device)
+        assert out.dtype == torch.float64 and out.is_contiguous() and tuple(out.shape) == self.grid
+        key = ("density", nb)
+        ws = self._ws.get(key)
+        if ws is None:
+            n = C.c_size_t()
+            L.check(self.lib.paro_density_workspace_bytes(self.h, nb, C.byref(n)), "paro_density_workspace_bytes")
+            raw = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+            off = (-raw.data_ptr()) % 256
+            ws = (raw, raw.data_ptr() + off, n.value)
+            self._ws[key] = ws
+        self._sync_stream()
+        L.check(self.lib.paro_density(self.h, nb, _ptr(psi), psi.stride(0), _ptr(weights), _ptr(out),
+                                      C.c_void_p(ws[1]), ws[2]), "paro_density")
+        return out
+
     def source_solve_mixed(self, psi, hpsi, eps, shift, n_cg, u=None):
         """As source_solve, with FP32 PCG vectors on the correction u - psi; returns (u, band_flags)."""
         torch = _torch()
