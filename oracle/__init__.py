@@ -75,6 +75,7 @@ def _load():
                                  C.c_int32, C.c_double, _dp, _dp, _dp]),
         "orc_num_threads": (C.c_int32, []),
         "orc_density": (None, [_vp, C.c_int32, _vp, _dp, _dp]),
+        "orc_projector_gradient": (None, [_vp, C.c_int32, _vp, _dp, _dp, _dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -283,6 +284,18 @@ class Hamiltonian:
         w = None if weights is None else _cd(np.broadcast_to(np.asarray(weights, np.float64), (nb,)))
         self._lib.orc_density(self._h, nb, _v(psi), None if w is None else _d(w), _d(rho))
         return rho
+
+    def projector_gradient(self, psi, weights=None):
+        """Derivatives of sum_b w_b <psi_b|V_NL|psi_b> with respect to the KB energies d_p
+        (shape nproj) and the projector centres R_p (shape nproj x 3)."""
+        psi = _cc(psi)
+        nb = psi.shape[0]
+        dd = np.zeros(self.nproj)
+        dR = np.zeros((self.nproj, 3))
+        w = None if weights is None else _cd(np.broadcast_to(np.asarray(weights, np.float64), (nb,)))
+        if self.nproj:
+            self._lib.orc_projector_gradient(self._h, nb, _v(psi), None if w is None else _d(w), _d(dd), _d(dR))
+        return dd, dR
 
     def paro(self, trial, n_outer, ncg, sigma_lb, variant=0, shift_mode=0):
         """ParO (variant 0), MParO I (variant 1) or MParO II (variant 2) from a trial block.

@@ -1001,6 +1001,41 @@ void orc_density(const orc_ham *h, int32_t nb, const cplx *psi, const double *w,
     free(per); free(t1); free(t2); free(t3);
 }
 
+/* ------------------------------------------------------------------ */
+/* Hellmann-Feynman derivatives of sum_b w_b <psi_b| V_NL |psi_b> with   */
+/* respect to the KB energies d_p and the projector centres R_p, where  */
+/* V_NL = sum_p d_p beta_p beta_p^H (Section 2.2) and beta_p(G) carries  */
+/* the phase exp(-i G.R_p):                                              */
+/*   dd[p]       = sum_b w_b |P_pb|^2,       P_pb = beta_p^H psi_b,     */
+/*   dR[3p + a]  = sum_b w_b d_p 2 Re(conj(P_pb) Q_pb^a),               */
+/*   Q_pb^a      = (d beta_p / d R_a)^H psi_b,  d beta_p / d R_a = -i G_a beta_p. */
+/* For eigenpairs these are the derivatives of sum_b w_b eps_b.         */
+/* ------------------------------------------------------------------ */
+void orc_projector_gradient(const orc_ham *h, int32_t nb, const cplx *psi, const double *w, double *dd,
+                            double *dR)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int p = 0; p < h->nproj; ++p) {
+        const cplx *bp = h->beta + (int64_t)p * h->ng;
+        double sd = 0.0, sr[3] = {0.0, 0.0, 0.0};
+        for (int b = 0; b < nb; ++b) {
+            const cplx *c = psi + (int64_t)b * h->ng;
+            cplx P = 0, Q[3] = {0, 0, 0};
+            for (int64_t g = 0; g < h->ng; ++g) {
+                double G[3];
+                gvec_of(h->bvec, h->miller[3 * g], h->miller[3 * g + 1], h->miller[3 * g + 2], G);
+                P += conj(bp[g]) * c[g];
+                for (int a = 0; a < 3; ++a) Q[a] += conj(-I * G[a] * bp[g]) * c[g];
+            }
+            const double wb = w ? w[b] : 1.0;
+            sd += wb * (creal(P) * creal(P) + cimag(P) * cimag(P));
+            for (int a = 0; a < 3; ++a) sr[a] += wb * h->dkb[p] * 2.0 * creal(conj(P) * Q[a]);
+        }
+        dd[p] = sd;
+        for (int a = 0; a < 3; ++a) dR[3 * p + a] = sr[a];
+    }
+}
+
 int32_t orc_num_threads(void)
 {
 #ifdef _OPENMP

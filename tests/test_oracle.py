@@ -542,3 +542,43 @@ def test_density_is_the_hellmann_feynman_gradient_of_the_eigenvalue_sum():
     # and the mirrored point j -> -j does not match where the density is not symmetric
     jm = tuple((-np.array(pts[-1])) % np.array(h.grid))
     assert abs(rho[jm] - rho[pts[-1]]) > 1e-3 * rho.max()
+
+
+def test_projector_gradient_is_the_hellmann_feynman_derivative():
+    """Central differences of the lowest dense eigenvalues (LAPACK) with respect to
+    every KB energy d_p and every projector centre component R_p equal the
+    oracle's projector gradient built from the eigenvectors."""
+    import copy
+    spec, c, v, h = tiny(seed=12)
+    lam, vec = np.linalg.eigh(h.dense())
+    k = next(k for k in range(4, 9) if lam[k] - lam[k - 1] > 1e-3)
+    w = np.linspace(2.0, 1.0, k)
+    dd, dR = h.projector_gradient(vec[:, :k].T.copy(), w)
+    assert dd.shape == (len(c["projectors"]),) and dR.shape == (len(c["projectors"]), 3)
+
+    def energy(projs):
+        hp = oracle.Hamiltonian(c["cell"], c["ecut"], v, projs)
+        return w @ np.linalg.eigvalsh(hp.dense())[:k]
+
+    # Richardson-extrapolated central differences: O(h^4) truncation
+    def deriv(f, h=1e-4):
+        d1 = (f(h) - f(-h)) / (2 * h)
+        d2 = (f(h / 2) - f(-h / 2)) / h
+        return (4 * d2 - d1) / 3
+
+    def shifted(p, key, a, s):
+        q = copy.deepcopy(c["projectors"])
+        if key == "d":
+            q[p]["d"] += s
+        else:
+            q[p]["center"] = np.array(q[p]["center"], float)
+            q[p]["center"][a] += s
+        return energy(q)
+
+    scale = max(1.0, np.abs(dd).max())
+    for p in range(len(c["projectors"])):
+        assert abs(deriv(lambda s: shifted(p, "d", 0, s)) - dd[p]) < 1e-9 * scale, p
+        for a in range(3):
+            assert abs(deriv(lambda s: shifted(p, "R", a, s)) - dR[p, a]) < 1e-9 * scale, (p, a)
+    # |P|^2 >= 0, and the derivative is not trivially zero
+    assert np.all(dd >= 0) and np.abs(dR).max() > 1e-3
