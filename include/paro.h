@@ -313,6 +313,27 @@ int32_t paro_density_workspace_bytes(paro_plan plan, int32_t nb, size_t *bytes);
 int32_t paro_density(paro_plan plan, int32_t nb, const double *psi, int64_t ld, const double *weights,
                      double *rho, void *ws, size_t ws_bytes);
 
+/* Derivatives of the nonlocal energy sum_b w_b <psi_b| V_NL |psi_b>,
+ * V_NL = sum_p d_p beta_p beta_p^H (Section 2.2, the projectors of
+ * paro_projector), with respect to each KB energy d_p and each projector
+ * centre R_p; with beta_p(G) proportional to exp(-i G.R_p):
+ *   dd[p]      = sum_b w_b |P_pb|^2,  P_pb = beta_p^H psi_b,
+ *   dR[3p + a] = sum_b w_b d_p 2 Re(conj(P_pb) Q_pb^a),
+ *   Q_pb^a = (-i G_a beta_p)^H psi_b.
+ * For eigenpairs these are the Hellmann-Feynman derivatives of the weighted
+ * band energy sum_b w_b eps_b; the force on an atom is minus the sum of dR
+ * over its projectors, plus the local part (paro_density).
+ * psi: dev complex band-major (ld >= n_g); weights: dev double[nb] or NULL
+ * (all 1); dd: dev double[n_proj]; dR: dev double[n_proj x 3]; both
+ * overwritten (nothing is written when n_proj = 0).  The products run on
+ * the FP64 matrix cores with fixed-order split-K sums: the result is
+ * bitwise reproducible.  ws: dev, 256-byte aligned, at least
+ * paro_projector_gradient_workspace_bytes(nb) bytes.  Errors: PARO_EINVAL
+ * (NULL, nb <= 0, ld < n_g, misaligned ws), PARO_ESIZE. */
+int32_t paro_projector_gradient_workspace_bytes(paro_plan plan, int32_t nb, size_t *bytes);
+int32_t paro_projector_gradient(paro_plan plan, int32_t nb, const double *psi, int64_t ld, const double *weights,
+                                double *dd, double *dR, void *ws, size_t ws_bytes);
+
 /* ---------------------------------------------------------------- building blocks */
 
 /* Complex double GEMMs on the FP64 matrix cores, the products the hot

@@ -70,6 +70,8 @@ SIGNATURES = {
     "paro_apply_h_f32": (C.c_int32, [_vp, C.c_int32, _vp, C.c_int64, _vp, _vp, _vp, _sz]),
     "paro_density_workspace_bytes": (C.c_int32, [_vp, C.c_int32, C.POINTER(_sz)]),
     "paro_density": (C.c_int32, [_vp, C.c_int32, _vp, C.c_int64, _vp, _vp, _vp, _sz]),
+    "paro_projector_gradient_workspace_bytes": (C.c_int32, [_vp, C.c_int32, C.POINTER(_sz)]),
+    "paro_projector_gradient": (C.c_int32, [_vp, C.c_int32, _vp, C.c_int64, _vp, _vp, _vp, _vp, _sz]),
     "paro_source_solve": (C.c_int32, [_vp, C.c_int32, _vp, _vp, C.c_int64, _vp, _vp, C.c_int32, _vp, _vp, _vp,
                                       _sz]),
     "paro_source_solve_mixed": (C.c_int32, [_vp, C.c_int32, _vp, _vp, C.c_int64, _vp, _vp, C.c_int32, _vp, _vp, _vp,

@@ -356,6 +356,82 @@ hipError_t launch_to_single(hipStream_t s, int64_t n, const double2 *src, float2
     return hipGetLastError();
 }
 
+namespace {
+
+// out[(a n_proj + p) ldv + g] = G_a(g) beta_p(g), G = n1 b1 + n2 b2 + n3 b3.
+__global__ void __launch_bounds__(256)
+k_gscale_projectors(int64_t ng, int64_t ldv, int np, const int32_t *__restrict__ miller, double b00, double b01,
+                    double b02, double b10, double b11, double b12, double b20, double b21, double b22,
+                    const double2 *__restrict__ beta, double2 *__restrict__ out)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int p = blockIdx.y;
+    if (g >= ng) return;
+    const double n1 = miller[3 * g], n2 = miller[3 * g + 1], n3 = miller[3 * g + 2];
+    const double G[3] = {n1 * b00 + n2 * b10 + n3 * b20, n1 * b01 + n2 * b11 + n3 * b21,
+                         n1 * b02 + n2 * b12 + n3 * b22};
+    const double2 v = beta[(int64_t)p * ldv + g];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[((int64_t)a * np + p) * ldv + g] = make_double2(G[a] * v.x, G[a] * v.y);
+}
+
+// One work-group per projector; bands summed by thread in a fixed stride
+// order, then a fixed-order block reduction.  S^a = (G_a beta)^H psi, so
+// Q^a = i S^a and 2 Re(conj(P) Q^a) = -2 Im(conj(P) S^a).
+__global__ void __launch_bounds__(256)
+k_projector_gradient(int np, int nb, const double2 *__restrict__ P, const double2 *__restrict__ S,
+                     const double *__restrict__ weights, const double *__restrict__ dkb, double *__restrict__ dd,
+                     double *__restrict__ dR)
+{
+    __shared__ double red[4];
+    const int p = blockIdx.x;
+    double sd = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) {
+        const double w = weights ? weights[b] : 1.0;
+        const double2 pv = P[(int64_t)b * np + p];
+        sd += w * (pv.x * pv.x + pv.y * pv.y);
+        const double2 q0 = S[(int64_t)b * 3 * np + p];
+        const double2 q1 = S[(int64_t)b * 3 * np + np + p];
+        const double2 q2 = S[(int64_t)b * 3 * np + 2 * np + p];
+        // Im(conj(P) S) = P.x S.y - P.y S.x
+        s0 += w * (pv.x * q0.y - pv.y * q0.x);
+        s1 += w * (pv.x * q1.y - pv.y * q1.x);
+        s2 += w * (pv.x * q2.y - pv.y * q2.x);
+    }
+    sd = block_sum<256>(sd, red);
+    s0 = block_sum<256>(s0, red);
+    s1 = block_sum<256>(s1, red);
+    s2 = block_sum<256>(s2, red);
+    if (threadIdx.x == 0) {
+        const double f = -2.0 * dkb[p];
+        dd[p] = sd;
+        dR[3 * p] = f * s0;
+        dR[3 * p + 1] = f * s1;
+        dR[3 * p + 2] = f * s2;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_projector_gradient(const Plan &pl, const ProjGradWs &w, int nb, const double2 *psi, int64_t ld,
+                                     const double *weights, double *dd, double *dR)
+{
+    const int np = pl.nproj;
+    if (np == 0) return hipSuccess;
+    const double *b = pl.bvec;
+    hipLaunchKernelGGL(k_gscale_projectors, dim3((unsigned)((pl.ng + 255) / 256), np), dim3(256), 0, pl.stream, pl.ng,
+                       pl.ldv, np, pl.miller, b[0], b[1], b[2], b[3], b[4], b[5], b[6], b[7], b[8], pl.beta, w.gbeta);
+    hipError_t e = gemm_hn(pl.stream, np, nb, pl.ng, pl.beta, pl.ldv, psi, ld, w.P, np, w.part, w.part_elems, nullptr,
+                           nullptr);
+    if (e != hipSuccess) return e;
+    e = gemm_hn(pl.stream, 3 * np, nb, pl.ng, w.gbeta, pl.ldv, psi, ld, w.S, 3 * np, w.part, w.part_elems, nullptr,
+                nullptr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_projector_gradient, dim3(np), dim3(256), 0, pl.stream, np, nb, w.P, w.S, weights, pl.dkb, dd,
+                       dR);
+    return hipGetLastError();
+}
+
 hipError_t launch_build_projectors(const Plan &pl, const int32_t *miller_dev, const double *centers,
                                    const int32_t *lm, const double *widths)
 {

@@ -40,6 +40,7 @@ struct Plan {
     float2 *beta32 = nullptr;
     double *dkb = nullptr;        // KB energies
     int32_t *status = nullptr;    // sticky status bits
+    int32_t *miller = nullptr;    // Miller indices of the sphere, ng x 3
 };
 
 // Workspace carve-up for calls on up to nb bands (m <= 2 nb for Rayleigh-Ritz).
@@ -68,6 +69,14 @@ size_t workspace_bytes(const Plan &pl, int nb);
 Workspace carve_workspace(const Plan &pl, int nb, void *ws);
 // bytes of the paro_density workspace; *part_off: offset of the partial grids
 size_t density_workspace_bytes(const Plan &pl, int nb, size_t *part_off);
+// carve-up of the paro_projector_gradient workspace (ws may be null to size it)
+struct ProjGradWs {
+    double2 *gbeta;           // G_a beta_p, (3 n_proj) x ldv, component-major
+    double2 *P, *S;           // beta^H psi (n_proj x nb), (G beta)^H psi (3 n_proj x nb), column-major
+    double2 *part;            // split-K partials
+    size_t part_elems;
+};
+ProjGradWs proj_grad_workspace(const Plan &pl, int nb, void *ws, size_t *bytes);
 size_t dense_real_elems(int mmax);
 
 void set_error(const std::string &msg);
@@ -116,6 +125,10 @@ hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const float2 *A, int6
 hipError_t gemm_nn(hipStream_t s, int64_t M, int N, int K, const float2 *A, int64_t lda, const float2 *B,
                    int64_t ldb, float2 *C, int64_t ldc, bool accumulate);
 hipError_t launch_to_single(hipStream_t s, int64_t n, const double2 *src, float2 *dst);
+// dd[p] = sum_b w_b |P_pb|^2, dR[3p + a] = sum_b w_b d_p 2 Re(conj(P_pb) Q_pb^a)
+// with P = beta^H psi and Q^a = (-i G_a beta)^H psi (weights null = 1)
+hipError_t launch_projector_gradient(const Plan &pl, const ProjGradWs &w, int nb, const double2 *psi, int64_t ld,
+                                     const double *weights, double *dd, double *dR);
 hipError_t launch_build_projectors(const Plan &pl, const int32_t *miller_dev, const double *centers,
                                    const int32_t *lm, const double *widths);
 // vec.hip

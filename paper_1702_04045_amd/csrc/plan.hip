@@ -248,6 +248,28 @@ size_t density_workspace_bytes(const Plan &pl, int nb, size_t *part_off)
     return align256(off + sizeof(double) * ngrp * nv);
 }
 
+// Projector-gradient workspace: G_a beta_p (3 n_proj x ldv), P = B^H psi
+// (n_proj x nb), S = (G beta)^H psi (3 n_proj x nb), split-K partials.
+ProjGradWs proj_grad_workspace(const Plan &pl, int nb, void *ws, size_t *bytes)
+{
+    const size_t np = pl.nproj;
+    ProjGradWs w{};
+    char *base = static_cast<char *>(ws);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char *q = base + off;
+        off = align256(off + b);
+        return q;
+    };
+    w.gbeta = (double2 *)take(sizeof(double2) * 3 * np * pl.ldv);
+    w.P = (double2 *)take(sizeof(double2) * np * nb);
+    w.S = (double2 *)take(sizeof(double2) * 3 * np * nb);
+    w.part_elems = 32 * 3 * np * (size_t)nb;
+    w.part = (double2 *)take(sizeof(double2) * w.part_elems);
+    if (bytes) *bytes = off;
+    return w;
+}
+
 Workspace carve_workspace(const Plan &pl, int nb, void *ws)
 {
     Workspace w{};
@@ -385,6 +407,7 @@ int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes, 
     pl.beta32 = (float2 *)(base + L.beta32);
     pl.status = (int32_t *)(base + L.status);
     int32_t *miller_dev = (int32_t *)(base + L.miller);
+    pl.miller = miller_dev;
     double *pcen = (double *)(base + L.pcen);
     int32_t *plm = (int32_t *)(base + L.plm);
     double *pwid = (double *)(base + L.pwid);

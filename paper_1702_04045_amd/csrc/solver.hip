@@ -194,6 +194,42 @@ int32_t paro_density(paro_plan plan, int32_t nb, const double *psi, int64_t ld, 
     return PARO_OK;
 }
 
+int32_t paro_projector_gradient_workspace_bytes(paro_plan plan, int32_t nb, size_t *bytes)
+{
+    if (!plan || nb <= 0 || !bytes) {
+        set_error("paro_projector_gradient_workspace_bytes: bad argument");
+        return PARO_EINVAL;
+    }
+    proj_grad_workspace(plan->pl, nb, nullptr, bytes);
+    return PARO_OK;
+}
+
+int32_t paro_projector_gradient(paro_plan plan, int32_t nb, const double *psi, int64_t ld, const double *weights,
+                                double *dd, double *dR, void *ws, size_t ws_bytes)
+{
+    if (!plan || nb <= 0 || !psi || !dd || !dR || !ws) {
+        set_error("paro_projector_gradient: bad argument");
+        return PARO_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(ws) % 256) {
+        set_error("paro_projector_gradient: workspace must be 256-byte aligned");
+        return PARO_EINVAL;
+    }
+    const Plan &pl = plan->pl;
+    if (ld < pl.ng) {
+        set_error("paro_projector_gradient: ld < n_g");
+        return PARO_EINVAL;
+    }
+    size_t need = 0;
+    ProjGradWs w = proj_grad_workspace(pl, nb, ws, &need);
+    if (ws_bytes < need) {
+        set_error("paro_projector_gradient: workspace smaller than paro_projector_gradient_workspace_bytes");
+        return PARO_ESIZE;
+    }
+    PARO_CHECK_LAUNCH(launch_projector_gradient(pl, w, nb, (const double2 *)psi, ld, weights, dd, dR));
+    return PARO_OK;
+}
+
 int32_t paro_apply_h_f32(paro_plan plan, int32_t nb, const float *psi, int64_t ld, const double *shift, float *hpsi,
                          void *ws, size_t ws_bytes)
 {

@@ -1,20 +1,24 @@
-"""Gradient of the band energy with respect to the local potential.
+"""Gradient of the band energy with respect to the local potential and the
+Kleinman-Bylander projectors.
 
-E(V) = sum_{b < n_occ} w_b eps_b(V), the weighted sum of the lowest
-eigenvalues of the Hamiltonian of eq. (e5) for the local potential V given
-on the FFT grid.  The eigenpairs come from the ParO iterations (MParO I,
-Algorithm 2) run to a residual tolerance.  For an eigenpair the derivative
-of eps_b with respect to V_j is the expectation of dH/dV_j (Hellmann-
-Feynman), and since the potential matrix elements are the grid sums
-(1/N) sum_j V_j exp(-2 pi i (n_m - n_n).j / N), N = N1 N2 N3, it is
-|psi_b(r_j)|^2 / N with psi_b(r_j) = sum_G c_bG exp(2 pi i n.j / N).  The
-backward pass is therefore the device density (paro_density) of the
-converged block divided by N.  The error of this gradient is first order in
-the eigenvector error, i.e. of the order of the residual tolerance over the
-gap to the next band.
+E = sum_{b < n_occ} w_b eps_b, the weighted sum of the lowest eigenvalues of
+the Hamiltonian of eq. (e5) for the local potential V given on the FFT grid
+and the projectors of Section 2.2.  The eigenpairs come from the ParO
+iterations (MParO I, Algorithm 2) run to a residual tolerance.  For an
+eigenpair the derivative of eps_b with respect to any parameter of H is the
+expectation of dH/d(parameter) (Hellmann-Feynman):
+  - V_j: the potential matrix elements are the grid sums
+    (1/N) sum_j V_j exp(-2 pi i (n_m - n_n).j / N), N = N1 N2 N3, so
+    d eps_b / dV_j = |psi_b(r_j)|^2 / N, psi_b(r_j) = sum_G c_bG exp(2 pi i n.j / N)
+    (the device density, paro_density, divided by N);
+  - the KB energy d_p and centre R_p of projector p: V_NL = sum_p d_p
+    beta_p beta_p^H with beta_p(G) ~ exp(-i G.R_p)
+    (paro_projector_gradient).
+The error of these gradients is first order in the eigenvector error, i.e.
+of the order of the residual tolerance over the gap to the next band.
 
 Every numerical step runs in libparo's kernels; this module marshals
-arguments and wires the result into torch.autograd.
+arguments and wires the results into torch.autograd.
 """
 from __future__ import annotations
 
@@ -52,10 +56,24 @@ class BandEnergyProblem:
         self.tol_res = float(tol_res)
         self.last = None  # (psi, plan) of the latest solve
 
-    def solve(self, vloc):
-        """Converged (plan, psi, eps, residuals) for the local potential vloc (grid-shaped, float64)."""
+    def projectors_with(self, centers=None, kb=None):
+        """The projector list with centres (n_proj x 3) and KB energies (n_proj) replaced."""
+        out = [dict(p) for p in self.projectors]
+        if centers is not None:
+            c = centers.detach().to("cpu", torch.float64).numpy().reshape(len(out), 3)
+            for p, r in zip(out, c):
+                p["center"] = [float(x) for x in r]
+        if kb is not None:
+            d = kb.detach().to("cpu", torch.float64).numpy().reshape(len(out))
+            for p, x in zip(out, d):
+                p["d"] = float(x)
+        return out
+
+    def solve(self, vloc, centers=None, kb=None):
+        """Converged (plan, psi, eps, residuals) for the local potential vloc (grid-shaped, float64)
+        and, optionally, projector centres and KB energies replacing those of the problem."""
         v = np.ascontiguousarray(vloc.detach().to("cpu", torch.float64).numpy())
-        plan = Plan(self.cell, self.ecut, v, self.projectors, device=self.device)
+        plan = Plan(self.cell, self.ecut, v, self.projectors_with(centers, kb), device=self.device)
         if self.last is not None and self.last[0].shape == (self.n_bands, plan.ng):
             psi = self.last[0].clone()
         elif self.trial is not None:
@@ -76,27 +94,43 @@ class BandEnergyProblem:
 
 class _BandEnergy(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, vloc, problem):
-        plan, psi, eps, _ = problem.solve(vloc)
+    def forward(ctx, vloc, centers, kb, problem):
+        plan, psi, eps, _ = problem.solve(vloc, centers, kb)
         ctx.plan, ctx.psi, ctx.problem = plan, psi, problem
-        ctx.vdevice = vloc.device
+        ctx.devices = (vloc.device, centers.device, kb.device)
         e = (problem.weights * eps[: problem.n_occ]).sum()
         return e.to(vloc.device)
 
     @staticmethod
     def backward(ctx, grad):
         p = ctx.problem
-        rho = ctx.plan.density(ctx.psi[: p.n_occ], p.weights)
-        n = float(np.prod(ctx.plan.grid))
-        g = rho * (grad.to(rho.device) / n)
-        return g.to(ctx.vdevice), None
+        psi = ctx.psi[: p.n_occ]
+        gv = gr = gd = None
+        if ctx.needs_input_grad[0]:
+            rho = ctx.plan.density(psi, p.weights)
+            gv = (rho * (grad.to(rho.device) / float(np.prod(ctx.plan.grid)))).to(ctx.devices[0])
+        if ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
+            dd, dR = ctx.plan.projector_gradient(psi, p.weights)
+            g = grad.to(dd.device)
+            gr = (dR * g).to(ctx.devices[1])
+            gd = (dd * g).to(ctx.devices[2])
+        return gv, gr, gd, None
 
 
-def band_energy(vloc: torch.Tensor, problem: BandEnergyProblem) -> torch.Tensor:
+def band_energy(vloc: torch.Tensor, problem: BandEnergyProblem, centers: torch.Tensor = None,
+                kb: torch.Tensor = None) -> torch.Tensor:
     """sum_{b < n_occ} w_b eps_b of the Hamiltonian with local potential vloc (N1 x N2 x N3,
-    float64, C order); differentiable with respect to vloc (Hellmann-Feynman)."""
+    float64, C order), projector centres (n_proj x 3, bohr) and KB energies (n_proj, Ha);
+    centers and kb default to the problem's.  Differentiable with respect to all three
+    (Hellmann-Feynman)."""
     assert vloc.dtype == torch.float64 and vloc.dim() == 3
-    return _BandEnergy.apply(vloc, problem)
+    n = len(problem.projectors)
+    if centers is None:
+        centers = torch.tensor([list(p["center"]) for p in problem.projectors], dtype=torch.float64).reshape(n, 3)
+    if kb is None:
+        kb = torch.tensor([p["d"] for p in problem.projectors], dtype=torch.float64).reshape(n)
+    assert centers.shape == (n, 3) and kb.shape == (n,)
+    return _BandEnergy.apply(vloc, centers, kb, problem)
 
 
 def potential_gradient(problem: BandEnergyProblem, psi: torch.Tensor, plan: Plan) -> torch.Tensor:

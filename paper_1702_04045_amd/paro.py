@@ -195,19 +195,42 @@ class Plan:
             weights = weights.contiguous()
         out = out if out is not None else torch.empty(self.grid, dtype=torch.float64, device=self.device)
         assert out.dtype == torch.float64 and out.is_contiguous() and tuple(out.shape) == self.grid
-        key = ("density", nb)
+        ws, n = self._aux_workspace("density", nb, self.lib.paro_density_workspace_bytes)
+        self._sync_stream()
+        L.check(self.lib.paro_density(self.h, nb, _ptr(psi), psi.stride(0), _ptr(weights), _ptr(out), ws, n),
+                "paro_density")
+        return out
+
+    def projector_gradient(self, psi, weights=None):
+        """Derivatives of sum_b w_b <psi_b|V_NL|psi_b> with respect to the KB energies (n_proj)
+        and the projector centres (n_proj x 3); for eigenpairs, of sum_b w_b eps_b."""
+        torch = _torch()
+        self._check_block(psi)
+        nb = psi.shape[0]
+        if weights is not None:
+            assert weights.dtype == torch.float64 and weights.device == self.device and weights.numel() >= nb
+            weights = weights.contiguous()
+        dd = torch.zeros(self.n_proj, dtype=torch.float64, device=self.device)
+        dR = torch.zeros((self.n_proj, 3), dtype=torch.float64, device=self.device)
+        ws, n = self._aux_workspace("projgrad", nb, self.lib.paro_projector_gradient_workspace_bytes)
+        self._sync_stream()
+        L.check(self.lib.paro_projector_gradient(self.h, nb, _ptr(psi), psi.stride(0), _ptr(weights), _ptr(dd),
+                                                 _ptr(dR), ws, n), "paro_projector_gradient")
+        return dd, dR
+
+    def _aux_workspace(self, kind, nb, query):
+        """A cached 256-byte aligned device workspace sized by query(plan, nb)."""
+        torch = _torch()
+        key = (kind, int(nb))
         ws = self._ws.get(key)
         if ws is None:
             n = C.c_size_t()
-            L.check(self.lib.paro_density_workspace_bytes(self.h, nb, C.byref(n)), "paro_density_workspace_bytes")
+            L.check(query(self.h, int(nb), C.byref(n)), kind + " workspace query")
             raw = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
             off = (-raw.data_ptr()) % 256
             ws = (raw, raw.data_ptr() + off, n.value)
             self._ws[key] = ws
-        self._sync_stream()
-        L.check(self.lib.paro_density(self.h, nb, _ptr(psi), psi.stride(0), _ptr(weights), _ptr(out),
-                                      C.c_void_p(ws[1]), ws[2]), "paro_density")
-        return out
+        return C.c_void_p(ws[1]), ws[2]
 
     def source_solve_mixed(self, psi, hpsi, eps, shift, n_cg, u=None):
         """As source_solve, with FP32 PCG vectors on the correction u - psi; returns (u, band_flags)."""

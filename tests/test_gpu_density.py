@@ -1,10 +1,12 @@
-"""GPU density (paro_density) against the oracle, and the Hellmann-Feynman
-gradient of the band energy against central finite differences of the
-device eigensolver.
+"""GPU density (paro_density) and projector gradient (paro_projector_gradient)
+against the oracle, and the Hellmann-Feynman gradients of the band energy
+against central finite differences of the device eigensolver.
 
 Tolerances:
   density                      max |diff| <= 1e-12 max |ref| (two FP64 FFT stages
                                and a square; sums in a fixed band order)
+  projector gradient           max |diff| <= 1e-12 max |ref| (FP64 products of
+                               length n_g; the oracle sums directly)
   gradient vs finite diff.     |g.d - FD| <= 1e-6 max(|FD|, |g| |d|): the
                                Hellmann-Feynman error is first order in the
                                eigenvector error (residual 1e-10 over a gap of
@@ -191,3 +193,75 @@ def test_band_energy_gradient_matches_finite_differences():
         fd = (ep - em) / (2 * hstep)
         an = float((g * d).sum())
         assert abs(an - fd) <= 1e-6 * max(abs(fd), np.abs(g).sum()), (k, an, fd)
+
+
+# ---------------------------------------------------------------- projector gradient
+
+MED = synth.small_cell(a=8.0, ecut=6.0, grid=24, n_atoms=3)
+
+
+@pytest.mark.parametrize("spec,nb,weighted", [(TINY, 3, False), (MED, 9, True), (MED, 1, True)],
+                         ids=["tiny", "med9", "med1"])
+def test_projector_gradient_matches_oracle(spec, nb, weighted):
+    c, v, h, pl = make_case(spec, 7)
+    x = synth.trial_block(h.ng, nb, 7)
+    w = np.linspace(0.5, 2.0, nb) if weighted else None
+    dd_ref, dR_ref = h.projector_gradient(x, w)
+    dd, dR = pl.projector_gradient(to_dev(x), None if w is None else to_dev(w))
+    assert rel_err(to_np(dd), dd_ref) < 1e-12
+    assert rel_err(to_np(dR), dR_ref) < 1e-12
+
+
+def test_projector_gradient_full_size_sampled_bands():
+    """128 projectors, all 160 bands of the benchmark cell in one call;
+    weights zero except on four bands, which the oracle sums directly."""
+    c, v, h, pl = make_case(C1, 0)
+    nb = C1.n_carried
+    x = synth.trial_block(h.ng, nb, 1)
+    w = np.zeros(nb)
+    idx = [0, 63, 64, nb - 1]
+    w[idx] = [1.0, 0.5, 2.0, 1.5]
+    dd, dR = pl.projector_gradient(to_dev(x), to_dev(w))
+    dd_ref, dR_ref = h.projector_gradient(x[idx], w[idx])
+    assert rel_err(to_np(dd), dd_ref) < 1e-12
+    assert rel_err(to_np(dR), dR_ref) < 1e-12
+    dd2, dR2 = pl.projector_gradient(to_dev(x), to_dev(w))
+    assert (dd2 == dd).all().item() and (dR2 == dR).all().item()
+
+
+def test_band_energy_projector_gradients_match_finite_differences():
+    """d E / d R_p and d E / d d_p from the backward pass against
+    Richardson-extrapolated central differences of the converged device
+    eigenvalue sum, on a cell with 12 projectors."""
+    torch = _torch()
+    from paper_1702_04045_amd.grad import band_energy
+    c, v, prob = _problem(MED, 3, 4)
+    V = torch.tensor(v, dtype=torch.float64)
+    R = torch.tensor([list(p["center"]) for p in c["projectors"]], dtype=torch.float64, requires_grad=True)
+    D = torch.tensor([p["d"] for p in c["projectors"]], dtype=torch.float64, requires_grad=True)
+    E = band_energy(V, prob, R, D)
+    gR, gD = torch.autograd.grad(E, (R, D))
+    gR, gD = gR.numpy(), gD.numpy()
+    scale = max(np.abs(gR).max(), np.abs(gD).max())
+
+    def energy(Rm, Dm):
+        return band_energy(V, prob, torch.tensor(Rm), torch.tensor(Dm)).item()
+
+    def deriv(f, h=1e-4):
+        d1 = (f(h) - f(-h)) / (2 * h)
+        d2 = (f(h / 2) - f(-h / 2)) / h
+        return (4 * d2 - d1) / 3
+
+    R0, D0 = R.detach().numpy(), D.detach().numpy()
+    for p in (0, 1, 5, 11):
+        def fd_d(s, p=p):
+            Dm = D0.copy()
+            Dm[p] += s
+            return energy(R0, Dm)
+        assert abs(deriv(fd_d) - gD[p]) <= 1e-6 * scale, ("d", p)
+        for a in range(3):
+            def fd_r(s, p=p, a=a):
+                Rm = R0.copy()
+                Rm[p, a] += s
+                return energy(Rm, D0)
+            assert abs(deriv(fd_r) - gR[p, a]) <= 1e-6 * scale, ("R", p, a)
