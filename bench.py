@@ -37,6 +37,7 @@ METRIC = "ParO iters/s & Hψ applies/s, plain FP64 vs batched mixed, at 1e-8 Ha 
 # HBM bytes per plane-kernel launch from the committed counter summary; it
 # counts only while the kernel sources hash to the value recorded there.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_plane_96_c1_hbm_traffic.txt")
+DENSITY_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_plane_density_96_c1_hbm_traffic.txt")
 PLANE_SOURCES = ["paper_1702_04045_amd/csrc/apply.hip", "paper_1702_04045_amd/csrc/fft_device.h",
                  "paper_1702_04045_amd/csrc/paro_internal.h"]
 COPY_BYTES = 1 << 30         # bytes read (and written) by the calibration copy
@@ -55,6 +56,13 @@ def plane_flops(N, ncol):
     all N rows (5 N log2 N each), plus the real potential multiply (2 per
     complex point)."""
     return (2 * ncol + 2 * N) * fft_flops(N) + 2.0 * N * N
+
+
+def density_plane_flops(N, ncol):
+    """Algorithmic flops of one z-plane of one band in the density: inverse
+    transforms along n2 for the ncol populated columns and along n1 for all
+    N rows, then w |psi|^2 accumulated (4 per point)."""
+    return (ncol + N) * fft_flops(N) + 4.0 * N * N
 
 
 def quad_bound(eps, res, n):
@@ -77,13 +85,13 @@ def plane_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per plane launch from the counter summary, or None when the
-    summary is missing or was taken on other kernel sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per launch from a counter summary, or None when the summary
+    is missing or was taken on other kernel sources."""
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith((" ", "#")):
                 k, v = line.split(":", 1)
@@ -279,6 +287,39 @@ def main():
     mixed["roofline"] = roofline_of(ms_m, nlf.value, totf.value, P.PREC_MIXED)
     mixed["roofline"]["share_of_step"] = (totf.value / nlf.value) * n32 / max(args.steps, 1) / ms_m
 
+    # density of the whole block (the Hellmann-Feynman gradient of the band
+    # energy): the full call timed with events on the plan's stream, its
+    # plane kernel with the library's per-launch events
+    rho = pl.density(psi)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    L.check(lib.paro_profile_start(L.K_DENSITY, 1 << 12), "paro_profile_start")
+    e0.record()
+    for _ in range(10):
+        pl.density(psi, out=rho)
+    e1.record()
+    torch.cuda.synchronize()
+    nld, totd = C.c_int32(), C.c_double()
+    L.check(lib.paro_profile_stop(C.byref(nld), C.byref(totd)), "paro_profile_stop")
+    ms_dens = e0.elapsed_time(e1) / 10
+    avg_d = totd.value / max(nld.value, 1)
+    # per-launch means over the 64-band chunks of one call: sticks read once,
+    # one partial grid written per group of 8 bands
+    chunks = [min(64, nb - c0) for c0 in range(0, nb, 64)]
+    fl_d = density_plane_flops(N, ncol) * pl.grid[2] * np.mean(chunks)
+    bytes_d = float(np.mean([16.0 * pl.n_sticks * pl.grid[2] * cb + 8.0 * (-(-cb // 8)) * N ** 3
+                             for cb in chunks]))
+    density = {"bands": nb, "ms_per_call": ms_dens, "calls_per_s": 1000.0 / ms_dens,
+               "roofline": {"kernel": "k_plane_density<96> (z-plane stage: inverse n2/n1 FFTs, w |psi|^2)",
+                            "bound": "alu", "achieved": fl_d / (avg_d * 1e-3) / 1e12,
+                            "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                            "frac": fl_d / (avg_d * 1e-3) / PEAK_FP64_VALU,
+                            "traffic": measured_traffic(DENSITY_TRAFFIC_FILE),
+                            "algorithmic_bytes_per_launch": bytes_d,
+                            "hbm_frac_algorithmic": bytes_d / (avg_d * 1e-3) / PEAK_HBM,
+                            "launches_timed": int(nld.value), "avg_launch_ms": avg_d,
+                            "flops_per_launch": fl_d, "share_of_call": totd.value / 10 / ms_dens}}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(spec, cell, v, x_np)
@@ -290,7 +331,8 @@ def main():
                       "bands_converged": nconv, "projectors": pl.n_proj, "pcg_steps": ncg,
                       "variant": "ParO (Algorithm 1)", "shift": "adaptive", "parallelism": "single GPU"},
            "hpsi_applies_per_s": applies_s, "wall_s_timed": wall, "status_flags": status,
-           "roofline": roofline, "time_to_1e-8": tta64, "mixed": mixed, "cpu_baseline": cpu}
+           "roofline": roofline, "time_to_1e-8": tta64, "mixed": mixed, "density": density,
+           "cpu_baseline": cpu}
     print(json.dumps(rec))
 
 
