@@ -269,6 +269,25 @@ int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi, double *hpsi, int6
                      double *eps, double *sigma, const paro_iter_opts *opts, double *stats,
                      void *ws, size_t ws_bytes, int32_t *n_done);
 
+/* Many independent problems (cells of different grids, sphere sizes and
+ * band counts) iterated together: for cell i the same computation as
+ * paro_iterate(plans[i], nb[i], psi[i], hpsi[i], ld[i], eps[i], sigma[i],
+ * &opts[i], stats ? stats[i] : NULL, ws[i], ws_bytes[i], n_done + i), with
+ * bitwise the same results.  Each cell's kernels are enqueued on its plan's
+ * stream: plans on different streams run concurrently on the GPU.  Every
+ * outer iteration first enqueues the work of all cells and then waits for
+ * them once (convergence test, negative-curvature retry) instead of once
+ * per cell.  A cell stops at its own n_outer or tolerance.  Each cell needs
+ * its own workspace (paro_workspace_bytes(nb[i]) of its plan); cells that
+ * share a plan share its stream and run one after the other.  stats may be
+ * NULL, or hold NULL entries; n_done may be NULL.  Errors: as
+ * paro_iterate, with the failing cell named in paro_last_error;
+ * PARO_EINVAL when two cells share a workspace. */
+int32_t paro_iterate_batch(int32_t n_cells, const paro_plan *plans, const int32_t *nb, double *const *psi,
+                           double *const *hpsi, const int64_t *ld, double *const *eps, double *const *sigma,
+                           const paro_iter_opts *opts, double *const *stats, void *const *ws,
+                           const size_t *ws_bytes, int32_t *n_done);
+
 /* Read and clear the sticky status bits (synchronises the plan's stream). */
 int32_t paro_get_status(paro_plan plan, int32_t *flags);
 

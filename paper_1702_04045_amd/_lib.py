@@ -68,6 +68,10 @@ SIGNATURES = {
     "paro_get_projectors": (C.c_int32, [_vp, _vp]),
     "paro_apply_h": (C.c_int32, [_vp, C.c_int32, _vp, C.c_int64, _vp, _vp, _vp, _sz]),
     "paro_apply_h_f32": (C.c_int32, [_vp, C.c_int32, _vp, C.c_int64, _vp, _vp, _vp, _sz]),
+    "paro_iterate_batch": (C.c_int32, [C.c_int32, C.POINTER(_vp), C.POINTER(C.c_int32), C.POINTER(_vp),
+                                       C.POINTER(_vp), C.POINTER(C.c_int64), C.POINTER(_vp), C.POINTER(_vp),
+                                       C.POINTER(IterOpts), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_sz),
+                                       C.POINTER(C.c_int32)]),
     "paro_density_workspace_bytes": (C.c_int32, [_vp, C.c_int32, C.POINTER(_sz)]),
     "paro_density": (C.c_int32, [_vp, C.c_int32, _vp, C.c_int64, _vp, _vp, _vp, _sz]),
     "paro_projector_gradient_workspace_bytes": (C.c_int32, [_vp, C.c_int32, C.POINTER(_sz)]),

@@ -347,10 +347,31 @@ int32_t paro_shift_lower_bound(paro_plan plan, double *sigma_dev, void *ws, size
     return PARO_OK;
 }
 
-int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi_, double *hpsi_, int64_t ld, double *eps, double *sigma,
-                     const paro_iter_opts *opts, double *stats, void *ws, size_t ws_bytes, int32_t *n_done)
+namespace {
+
+// One problem of paro_iterate / paro_iterate_batch: its plan, block,
+// workspace and options, and the host-side state of its outer loop.
+struct CellRun {
+    const Plan *pl = nullptr;
+    Workspace w{};
+    int nb = 0;
+    double2 *psi = nullptr, *hpsi = nullptr;
+    int64_t ld = 0;
+    double *eps = nullptr, *sigma = nullptr, *stats = nullptr;
+    paro_iter_opts o{};
+    int32_t *conv = nullptr;  // device flag: converged to tol_res
+    int32_t *n_done = nullptr;
+    bool active = true, solve = false;
+    int32_t hconv = 0;
+    double scur = 0.0;
+    std::vector<int32_t> hflags;
+};
+
+int32_t prepare_cell(paro_plan plan, int32_t nb, double *psi, double *hpsi, int64_t ld, double *eps, double *sigma,
+                     const paro_iter_opts *opts, double *stats, void *ws, size_t ws_bytes, int32_t *n_done,
+                     CellRun &c)
 {
-    if (!plan || nb <= 0 || !psi_ || !hpsi_ || !eps || !sigma || !opts || opts->n_outer < 0 || opts->n_cg < 0 ||
+    if (!plan || nb <= 0 || !psi || !hpsi || !eps || !sigma || !opts || opts->n_outer < 0 || opts->n_cg < 0 ||
         nb > 512 ||
         (opts->variant != PARO_VARIANT_PARO && opts->variant != PARO_VARIANT_MPARO1 &&
          opts->variant != PARO_VARIANT_MPARO2) ||
@@ -370,68 +391,170 @@ int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi_, double *hpsi_, in
     }
     int32_t rc = check_ws(pl, nb, ws, ws_bytes);
     if (rc) return rc;
-    Workspace w = carve_workspace(pl, nb, ws);
-    double2 *psi = (double2 *)psi_, *hpsi = (double2 *)hpsi_;
-    const int64_t lv = pl.ldv;
-    hipStream_t st = pl.stream;
-    const int row = 2 * nb + 2;
-    int32_t *conv = reinterpret_cast<int32_t *>(w.scal + 1);
+    c.pl = &pl;
+    c.w = carve_workspace(pl, nb, ws);
+    c.nb = nb;
+    c.psi = (double2 *)psi;
+    c.hpsi = (double2 *)hpsi;
+    c.ld = ld;
+    c.eps = eps;
+    c.sigma = sigma;
+    c.stats = stats;
+    c.o = *opts;
+    c.conv = reinterpret_cast<int32_t *>(c.w.scal + 1);
+    c.n_done = n_done;
+    c.hflags.assign(nb, 0);
     if (n_done) *n_done = 0;
-    if (opts->initial_rr) {
-        PARO_CHECK_LAUNCH(launch_copy_bands(st, nb, pl.ng, psi, ld, w.U, lv));
-        PARO_CHECK_LAUNCH(apply_full(pl, w, nb, w.U, lv, w.W, nullptr));
-        PARO_CHECK_LAUNCH(rayleigh_ritz(pl, w, nb, nb, w.U, w.W, lv, eps, psi, hpsi, ld));
+    return PARO_OK;
+}
+
+// The outer loop of Algorithm 1 (or 2, 3) for every cell.  Each cell's
+// kernels go to its plan's stream; the host decisions of an iteration (the
+// convergence test, the negative-curvature retry of the adaptive shift)
+// first enqueue every cell's work and its small device-to-host copies, then
+// wait for each cell in turn, so that cells on different streams overlap.
+int32_t run_cells(std::vector<CellRun> &cells)
+{
+    for (CellRun &c : cells) {
+        const Plan &pl = *c.pl;
+        Workspace &w = c.w;
+        const int64_t lv = pl.ldv;
+        if (c.o.initial_rr) {
+            PARO_CHECK_LAUNCH(launch_copy_bands(pl.stream, c.nb, pl.ng, c.psi, c.ld, w.U, lv));
+            PARO_CHECK_LAUNCH(apply_full(pl, w, c.nb, w.U, lv, w.W, nullptr));
+            PARO_CHECK_LAUNCH(rayleigh_ritz(pl, w, c.nb, c.nb, w.U, w.W, lv, c.eps, c.psi, c.hpsi, c.ld));
+        }
+        PARO_CHECK_LAUNCH(launch_residuals(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.res));
+        PARO_CHECK_LAUNCH(launch_bookkeeping(pl, c.nb, c.o, c.eps, w.res, w.sig_all, c.sigma, c.stats, c.conv));
     }
-    PARO_CHECK_LAUNCH(launch_residuals(pl, w, nb, psi, hpsi, ld, eps, w.res));
-    PARO_CHECK_LAUNCH(launch_bookkeeping(pl, nb, *opts, eps, w.res, w.sig_all, sigma, stats, conv));
-    std::vector<int32_t> hflags(nb);
-    for (int it = 0; it < opts->n_outer; ++it) {
-        if (opts->tol_res > 0.0) {
-            int32_t c = 0;
-            PARO_HIP_TRY(hipMemcpyAsync(&c, conv, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            PARO_HIP_TRY(hipStreamSynchronize(st));
-            if (c) break;
+    int max_outer = 0;
+    for (const CellRun &c : cells) max_outer = std::max(max_outer, c.o.n_outer);
+    for (int it = 0; it < max_outer; ++it) {
+        // convergence test (tol_res > 0) on the device flag of the last bookkeeping
+        for (CellRun &c : cells) {
+            if (c.active && it >= c.o.n_outer) c.active = false;
+            if (c.active && c.o.tol_res > 0.0)
+                PARO_HIP_TRY(hipMemcpyAsync(&c.hconv, c.conv, sizeof(int32_t), hipMemcpyDeviceToHost, c.pl->stream));
         }
-        const bool mparo = opts->variant != PARO_VARIANT_PARO;
-        double2 *Ut = mparo ? w.U + (size_t)nb * lv : w.U;  // u (Algorithm 1) or e (Algorithms 2, 3)
+        bool any = false;
+        for (CellRun &c : cells) {
+            if (c.active && c.o.tol_res > 0.0) {
+                PARO_HIP_TRY(hipStreamSynchronize(c.pl->stream));
+                if (c.hconv) c.active = false;
+            }
+            any = any || c.active;
+            c.solve = c.active;
+        }
+        if (!any) break;
+        // source problems; with the adaptive shift, a cell whose PCG met
+        // negative curvature solves again with sigma_lb
         for (int attempt = 0; attempt < 2; ++attempt) {
-            if (opts->precision == PARO_PREC_MIXED)
-                PARO_CHECK_LAUNCH(source_solve_mixed(pl, w, nb, psi, hpsi, ld, eps, w.sig_all, opts->n_cg, Ut, lv,
-                                                     w.iflags + nb, mparo));
-            else
-                PARO_CHECK_LAUNCH(source_solve(pl, w, nb, psi, hpsi, ld, eps, w.sig_all, opts->n_cg, Ut, lv,
-                                               w.iflags + nb, opts->variant));
-            if (opts->shift_mode != PARO_SHIFT_ADAPTIVE) break;
-            // on negative curvature redo the source problems with sigma_lb
-            double scur = 0.0;
-            PARO_HIP_TRY(hipMemcpyAsync(hflags.data(), w.iflags + nb, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
-            PARO_HIP_TRY(hipMemcpyAsync(&scur, sigma, sizeof(double), hipMemcpyDeviceToHost, st));
-            PARO_HIP_TRY(hipStreamSynchronize(st));
-            bool neg = false;
-            for (int b = 0; b < nb; ++b) neg = neg || (hflags[b] & PARO_F_NEGCURV);
-            if (!neg || scur == opts->sigma_lb || attempt == 1) break;
-            paro_iter_opts fixed = *opts;
-            fixed.shift_mode = PARO_SHIFT_FIXED;
-            fixed.tol_res = 0.0;
-            PARO_CHECK_LAUNCH(launch_bookkeeping(pl, nb, fixed, eps, w.res, w.sig_all, sigma, nullptr, conv));
+            for (CellRun &c : cells) {
+                if (!c.solve) continue;
+                const Plan &pl = *c.pl;
+                Workspace &w = c.w;
+                const int64_t lv = pl.ldv;
+                const bool mparo = c.o.variant != PARO_VARIANT_PARO;
+                double2 *Ut = mparo ? w.U + (size_t)c.nb * lv : w.U;  // u (Algorithm 1) or e (Algorithms 2, 3)
+                if (c.o.precision == PARO_PREC_MIXED)
+                    PARO_CHECK_LAUNCH(source_solve_mixed(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.sig_all, c.o.n_cg,
+                                                         Ut, lv, w.iflags + c.nb, mparo));
+                else
+                    PARO_CHECK_LAUNCH(source_solve(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.sig_all, c.o.n_cg, Ut,
+                                                   lv, w.iflags + c.nb, c.o.variant));
+                if (c.o.shift_mode != PARO_SHIFT_ADAPTIVE) {
+                    c.solve = false;
+                    continue;
+                }
+                PARO_HIP_TRY(hipMemcpyAsync(c.hflags.data(), w.iflags + c.nb, sizeof(int32_t) * c.nb,
+                                            hipMemcpyDeviceToHost, pl.stream));
+                PARO_HIP_TRY(hipMemcpyAsync(&c.scur, c.sigma, sizeof(double), hipMemcpyDeviceToHost, pl.stream));
+            }
+            bool again = false;
+            for (CellRun &c : cells) {
+                if (!c.solve) continue;
+                PARO_HIP_TRY(hipStreamSynchronize(c.pl->stream));
+                bool neg = false;
+                for (int b = 0; b < c.nb; ++b) neg = neg || (c.hflags[b] & PARO_F_NEGCURV);
+                if (!neg || c.scur == c.o.sigma_lb || attempt == 1) {
+                    c.solve = false;
+                    continue;
+                }
+                paro_iter_opts fixed = c.o;
+                fixed.shift_mode = PARO_SHIFT_FIXED;
+                fixed.tol_res = 0.0;
+                PARO_CHECK_LAUNCH(launch_bookkeeping(*c.pl, c.nb, fixed, c.eps, c.w.res, c.w.sig_all, c.sigma,
+                                                     nullptr, c.conv));
+                again = true;
+            }
+            if (!again) break;
         }
-        if (mparo) {
-            // span{psi, e/|e|}, e from the correction equation (Algorithms 2, 3)
-            PARO_CHECK_LAUNCH(launch_normalize_bands(pl, w, nb, Ut, lv));
-            PARO_CHECK_LAUNCH(launch_copy_bands(st, nb, pl.ng, psi, ld, w.U, lv));
-            PARO_CHECK_LAUNCH(launch_copy_bands(st, nb, pl.ng, hpsi, ld, w.W, lv));
-            PARO_CHECK_LAUNCH(apply_full(pl, w, nb, Ut, lv, w.W + (size_t)nb * lv, nullptr));
-            PARO_CHECK_LAUNCH(rayleigh_ritz(pl, w, 2 * nb, nb, w.U, w.W, lv, eps, psi, hpsi, ld));
-        } else {
-            PARO_CHECK_LAUNCH(apply_full(pl, w, nb, w.U, lv, w.W, nullptr));
-            PARO_CHECK_LAUNCH(rayleigh_ritz(pl, w, nb, nb, w.U, w.W, lv, eps, psi, hpsi, ld));
+        // Rayleigh-Ritz, residuals, shift and statistics
+        for (CellRun &c : cells) {
+            if (!c.active) continue;
+            const Plan &pl = *c.pl;
+            Workspace &w = c.w;
+            const int64_t lv = pl.ldv;
+            const int nb = c.nb;
+            if (c.o.variant != PARO_VARIANT_PARO) {
+                // span{psi, e/|e|}, e from the correction equation (Algorithms 2, 3)
+                double2 *Ut = w.U + (size_t)nb * lv;
+                PARO_CHECK_LAUNCH(launch_normalize_bands(pl, w, nb, Ut, lv));
+                PARO_CHECK_LAUNCH(launch_copy_bands(pl.stream, nb, pl.ng, c.psi, c.ld, w.U, lv));
+                PARO_CHECK_LAUNCH(launch_copy_bands(pl.stream, nb, pl.ng, c.hpsi, c.ld, w.W, lv));
+                PARO_CHECK_LAUNCH(apply_full(pl, w, nb, Ut, lv, w.W + (size_t)nb * lv, nullptr));
+                PARO_CHECK_LAUNCH(rayleigh_ritz(pl, w, 2 * nb, nb, w.U, w.W, lv, c.eps, c.psi, c.hpsi, c.ld));
+            } else {
+                PARO_CHECK_LAUNCH(apply_full(pl, w, nb, w.U, lv, w.W, nullptr));
+                PARO_CHECK_LAUNCH(rayleigh_ritz(pl, w, nb, nb, w.U, w.W, lv, c.eps, c.psi, c.hpsi, c.ld));
+            }
+            const int row = 2 * nb + 2;
+            PARO_CHECK_LAUNCH(launch_residuals(pl, w, nb, c.psi, c.hpsi, c.ld, c.eps, w.res));
+            PARO_CHECK_LAUNCH(launch_bookkeeping(pl, nb, c.o, c.eps, w.res, w.sig_all, c.sigma,
+                                                 c.stats ? c.stats + (size_t)(it + 1) * row : nullptr, c.conv));
+            if (c.n_done) *c.n_done = it + 1;
         }
-        PARO_CHECK_LAUNCH(launch_residuals(pl, w, nb, psi, hpsi, ld, eps, w.res));
-        PARO_CHECK_LAUNCH(launch_bookkeeping(pl, nb, *opts, eps, w.res, w.sig_all, sigma,
-                                             stats ? stats + (size_t)(it + 1) * row : nullptr, conv));
-        if (n_done) *n_done = it + 1;
     }
     return PARO_OK;
+}
+
+}  // namespace
+
+int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi, double *hpsi, int64_t ld, double *eps, double *sigma,
+                     const paro_iter_opts *opts, double *stats, void *ws, size_t ws_bytes, int32_t *n_done)
+{
+    std::vector<CellRun> cells(1);
+    int32_t rc = prepare_cell(plan, nb, psi, hpsi, ld, eps, sigma, opts, stats, ws, ws_bytes, n_done, cells[0]);
+    if (rc) return rc;
+    return run_cells(cells);
+}
+
+int32_t paro_iterate_batch(int32_t n_cells, const paro_plan *plans, const int32_t *nb, double *const *psi,
+                           double *const *hpsi, const int64_t *ld, double *const *eps, double *const *sigma,
+                           const paro_iter_opts *opts, double *const *stats, void *const *ws, const size_t *ws_bytes,
+                           int32_t *n_done)
+{
+    if (n_cells <= 0 || !plans || !nb || !psi || !hpsi || !ld || !eps || !sigma || !opts || !ws || !ws_bytes) {
+        set_error("paro_iterate_batch: bad argument");
+        return PARO_EINVAL;
+    }
+    std::vector<CellRun> cells(n_cells);
+    for (int i = 0; i < n_cells; ++i) {
+        for (int k = 0; k < i; ++k)
+            if (ws[k] == ws[i]) {
+                set_error("paro_iterate_batch: cells " + std::to_string(k) + " and " + std::to_string(i) +
+                          " share a workspace");
+                return PARO_EINVAL;
+            }
+        int32_t rc = prepare_cell(plans[i], nb[i], psi[i], hpsi[i], ld[i], eps[i], sigma[i], &opts[i],
+                                  stats ? stats[i] : nullptr, ws[i], ws_bytes[i], n_done ? n_done + i : nullptr,
+                                  cells[i]);
+        if (rc) {
+            set_error("paro_iterate_batch: cell " + std::to_string(i) + ": " + paro_last_error());
+            return rc;
+        }
+    }
+    return run_cells(cells);
 }
 
 int32_t paro_zgemm_hn(paro_stream_t s, int32_t M, int32_t N, int64_t K, const double *A, int64_t lda,

@@ -326,6 +326,69 @@ class Plan:
         return int(f.value)
 
 
+def iterate_batch(plans, psis, n_outer, n_cg, sigma_lbs, variant=L.VARIANT_PARO, shift_mode=L.SHIFT_FIXED,
+                  initial_rr=True, n_conv=None, tol_res=0.0, precision=L.PREC_FP64, streams=None, stats=False):
+    """ParO outer iterations on many independent cells in one library call (paro_iterate_batch).
+
+    plans[i] and psis[i] (its band-major complex128 block, updated in place) form cell i;
+    sigma_lbs[i] its shift bound; n_conv may be a list.  streams: torch streams (default
+    priority) the cells are spread over round-robin (None: one per cell, at most 8); the
+    cells' work is ordered after the current stream's and the current stream waits for all of
+    them at the end.  Returns a list of dict(psi, hpsi, eps, sigma, stats, n_done)."""
+    torch = _torch()
+    n = len(plans)
+    assert n == len(psis) == len(sigma_lbs) and n > 0
+    dev = plans[0].device
+    cur = torch.cuda.current_stream(dev)
+    if streams is None:
+        streams = [torch.cuda.Stream(device=dev) for _ in range(min(n, 8))]
+    out, opts = [], (L.IterOpts * n)()
+    ncv = n_conv if isinstance(n_conv, (list, tuple)) else [n_conv] * n
+    for i, (pl, psi) in enumerate(zip(plans, psis)):
+        pl._check_block(psi)
+        nb = psi.shape[0]
+        out.append(dict(psi=psi, hpsi=torch.zeros_like(psi),
+                        eps=torch.zeros(nb, dtype=torch.float64, device=dev),
+                        sigma=torch.zeros(1, dtype=torch.float64, device=dev),
+                        stats=torch.full((n_outer + 1, 2 * nb + 2), float("nan"), dtype=torch.float64, device=dev)
+                        if stats else None))
+        opts[i] = L.IterOpts(n_outer=int(n_outer), n_cg=int(n_cg), n_conv=int(ncv[i] or nb),
+                             shift_mode=int(shift_mode), variant=int(variant), initial_rr=1 if initial_rr else 0,
+                             sigma_lb=float(sigma_lbs[i]), tol_res=float(tol_res), precision=int(precision))
+    wss = [pl.workspace(psi.shape[0]) for pl, psi in zip(plans, psis)]
+    vp = lambda xs: (C.c_void_p * n)(*[x.value if isinstance(x, C.c_void_p) else x for x in xs])  # noqa: E731
+    hplans = (C.c_void_p * n)(*[pl.h.value for pl in plans])
+    nbs = (C.c_int32 * n)(*[psi.shape[0] for psi in psis])
+    lds = (C.c_int64 * n)(*[psi.stride(0) for psi in psis])
+    ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+    done = (C.c_int32 * n)()
+    ev = torch.cuda.Event()
+    ev.record(cur)
+    for k, pl in enumerate(plans):
+        st = streams[k % len(streams)]
+        st.wait_event(ev)
+        L.check(pl.lib.paro_plan_set_stream(pl.h, C.c_void_p(st.cuda_stream)), "paro_plan_set_stream")
+    lib = plans[0].lib
+    L.check(lib.paro_iterate_batch(n, hplans, nbs, vp([ptr(psi) for psi in psis]),
+                                   vp([ptr(o["hpsi"]) for o in out]), lds, vp([ptr(o["eps"]) for o in out]),
+                                   vp([ptr(o["sigma"]) for o in out]), opts,
+                                   vp([ptr(o["stats"]) for o in out]), vp([w[0] for w in wss]),
+                                   (C.c_size_t * n)(*[w[1] for w in wss]), done), "paro_iterate_batch")
+    for st in streams:
+        e = torch.cuda.Event()
+        e.record(st)
+        cur.wait_event(e)
+    # the tensors were used on the cell streams: keep the allocator from reusing them early
+    for k, o in enumerate(out):
+        st = streams[k % len(streams)]
+        for t in (o["psi"], o["hpsi"], o["eps"], o["sigma"], o["stats"]):
+            if t is not None:
+                t.record_stream(st)
+    for k, o in enumerate(out):
+        o["n_done"] = int(done[k])
+    return out
+
+
 def zgemm_hn(A, B, device=None):
     """C = A^H B for column-major complex A (K x M) and B (K x N) given as torch tensors of
     shape (M, K) and (N, K) (rows = columns of the matrices).  Returns C as (N, M) (rows = columns)."""

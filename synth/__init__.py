@@ -25,7 +25,10 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = ["CellSpec", "WORKLOADS", "make_cell", "vloc_on_grid", "trial_block",
-           "small_cell"]
+           "small_cell", "batch_specs", "FFT_LENGTHS"]
+
+# FFT grid lengths 2^a * {1, 3, 5} from 8 to 96 (the lengths the GPU transforms support)
+FFT_LENGTHS = (8, 16, 24, 32, 40, 48, 64, 80, 96)
 
 
 @dataclass(frozen=True)
@@ -134,3 +137,31 @@ def trial_block(n_g: int, n_bands: int, seed: int) -> np.ndarray:
     x = rng.standard_normal((n_bands, n_g))
     y = rng.standard_normal((n_bands, n_g))
     return (x + 1j * y) / np.sqrt(2.0)
+
+
+def batch_specs(seed: int, n_cells: int = 24, a_range=(8.0, 18.0), ecut_range=(8.0, 20.0),
+                bands_range=(8, 96), atoms_range=(4, 24)) -> list:
+    """Independent cubic cells of uneven size for the batched runs.
+
+    Draw order (``default_rng([seed, 2])``), per cell: lattice constant
+    ``a ~ U(a_range)`` bohr, cutoff ``E_cut ~ U(ecut_range)`` Ha, orbital
+    count ``N ~ U{bands_range}``, atom count ``~ U{atoms_range}``; every atom
+    carries s + p projectors.  The FFT grid of each cell is an input of its
+    problem statement: the smallest length of ``FFT_LENGTHS`` that is at least
+    4 m + 1, with m = floor(sqrt(2 E_cut) a / (2 pi)) the largest Miller index
+    a cubic cell's cutoff admits along an axis.  Cell ``i`` then draws its
+    atoms with ``make_cell(spec, seed * 1000 + i)``.
+    """
+    rng = np.random.default_rng([seed, 2])
+    out = []
+    for i in range(n_cells):
+        a = float(rng.uniform(*a_range))
+        ecut = float(rng.uniform(*ecut_range))
+        nb = int(rng.integers(bands_range[0], bands_range[1] + 1))
+        na = int(rng.integers(atoms_range[0], atoms_range[1] + 1))
+        m = int(np.floor(np.sqrt(2.0 * ecut) * a / (2.0 * np.pi)))
+        grid = next(n for n in FFT_LENGTHS if n >= 4 * m + 1)
+        out.append(CellSpec(name=f"batch{seed}_{i}_a{a:.2f}_ecut{ecut:.2f}_g{grid}_n{nb}", a=a, ecut=ecut,
+                            grid=grid, n_atoms=na, width=0.9, projectors=True, proj_width=0.7,
+                            n_bands=nb, n_buffer=0, n_outer=10, n_cg=10))
+    return out
