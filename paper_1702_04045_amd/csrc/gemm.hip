@@ -289,7 +289,9 @@ hipError_t gemm_hn_t(hipStream_t s, int M, int N, int64_t K, const C2 *A, int64_
     if (M <= 0 || N <= 0) return hipSuccess;
     const int tm = (M + kTile - 1) / kTile, tn = (N + kTile - 1) / kTile;
     int64_t nsplit = (kSplitTarget + tm * tn - 1) / (tm * tn);
-    const int64_t kmax = (K + 255) / 256;  // at least 256 per split
+    // at least one prefetch ring of k per split: small products (few output
+    // tiles, short contraction) still spread over many work-groups
+    const int64_t kmax = (K + 4 * kDepthHN - 1) / (4 * kDepthHN);
     if (nsplit > kmax) nsplit = kmax;
     if (nsplit < 1) nsplit = 1;
     const int64_t cap = (int64_t)(part_elems / ((size_t)M * N));

@@ -224,7 +224,7 @@ size_t workspace_bytes(const Plan &pl, int nb)
     add(sizeof(double2) * m * pl.ldv);                          // U
     add(sizeof(double2) * m * pl.ldv);                          // W
     add(sizeof(double2) * std::max(2 * m * m, np * np));       // gram
-    const size_t part = 32 * std::max(std::max(m * m, np * m), np * np);
+    const size_t part = (size_t)kPartSplits * std::max(std::max(m * m, np * m), np * np);
     add(sizeof(double2) * part);                                // split-K partials
     add(sizeof(double2) * std::max<size_t>(1, np) * m);         // P
     for (int i = 0; i < 5; ++i) add(sizeof(double2) * mm * mm);  // dense
@@ -264,7 +264,7 @@ ProjGradWs proj_grad_workspace(const Plan &pl, int nb, void *ws, size_t *bytes)
     w.gbeta = (double2 *)take(sizeof(double2) * 3 * np * pl.ldv);
     w.P = (double2 *)take(sizeof(double2) * np * nb);
     w.S = (double2 *)take(sizeof(double2) * 3 * np * nb);
-    w.part_elems = 32 * 3 * np * (size_t)nb;
+    w.part_elems = (size_t)kPartSplits * 3 * np * (size_t)nb;
     w.part = (double2 *)take(sizeof(double2) * w.part_elems);
     if (bytes) *bytes = off;
     return w;
@@ -297,7 +297,7 @@ Workspace carve_workspace(const Plan &pl, int nb, void *ws)
     w.q32 = reinterpret_cast<float2 *>(w.q);
     w.d32 = reinterpret_cast<float2 *>(w.W);
     w.gram = (double2 *)take(sizeof(double2) * std::max(2 * m * m, np * np));
-    w.part_elems = 32 * std::max(std::max(m * m, np * m), np * np);
+    w.part_elems = (size_t)kPartSplits * std::max(std::max(m * m, np * m), np * np);
     w.part = (double2 *)take(sizeof(double2) * w.part_elems);
     w.P = (double2 *)take(sizeof(double2) * std::max<size_t>(1, np) * m);
     for (int i = 0; i < 5; ++i) w.dense[i] = (double2 *)take(sizeof(double2) * mm * mm);

@@ -362,9 +362,20 @@ struct CellRun {
     int32_t *conv = nullptr;  // device flag: converged to tol_res
     int32_t *n_done = nullptr;
     bool active = true, solve = false;
-    int32_t hconv = 0;
-    double scur = 0.0;
-    std::vector<int32_t> hflags;
+    // pinned host copies of the device values the loop decides on, so that
+    // the copies are asynchronous and the cells' work is all in flight
+    int32_t *hconv = nullptr;
+    double *scur = nullptr;
+    int32_t *hflags = nullptr;
+};
+
+// Page-locked host memory for the per-cell decision values, freed on scope exit.
+struct PinnedHost {
+    void *p = nullptr;
+    ~PinnedHost()
+    {
+        if (p) (void)hipHostFree(p);
+    }
 };
 
 int32_t prepare_cell(paro_plan plan, int32_t nb, double *psi, double *hpsi, int64_t ld, double *eps, double *sigma,
@@ -403,7 +414,6 @@ int32_t prepare_cell(paro_plan plan, int32_t nb, double *psi, double *hpsi, int6
     c.o = *opts;
     c.conv = reinterpret_cast<int32_t *>(c.w.scal + 1);
     c.n_done = n_done;
-    c.hflags.assign(nb, 0);
     if (n_done) *n_done = 0;
     return PARO_OK;
 }
@@ -415,6 +425,21 @@ int32_t prepare_cell(paro_plan plan, int32_t nb, double *psi, double *hpsi, int6
 // wait for each cell in turn, so that cells on different streams overlap.
 int32_t run_cells(std::vector<CellRun> &cells)
 {
+    // per cell: sigma (double), the convergence flag, the band flags; 8-byte blocks
+    auto block = [](const CellRun &c) { return sizeof(double) + (sizeof(int32_t) * (2 + c.nb) + 7) / 8 * 8; };
+    size_t bytes = 0;
+    for (const CellRun &c : cells) bytes += block(c);
+    PinnedHost host;
+    PARO_HIP_TRY(hipHostMalloc(&host.p, bytes, hipHostMallocDefault));
+    {
+        char *q = static_cast<char *>(host.p);
+        for (CellRun &c : cells) {
+            c.scur = reinterpret_cast<double *>(q);
+            c.hconv = reinterpret_cast<int32_t *>(q + sizeof(double));
+            c.hflags = c.hconv + 2;
+            q += block(c);
+        }
+    }
     for (CellRun &c : cells) {
         const Plan &pl = *c.pl;
         Workspace &w = c.w;
@@ -434,13 +459,13 @@ int32_t run_cells(std::vector<CellRun> &cells)
         for (CellRun &c : cells) {
             if (c.active && it >= c.o.n_outer) c.active = false;
             if (c.active && c.o.tol_res > 0.0)
-                PARO_HIP_TRY(hipMemcpyAsync(&c.hconv, c.conv, sizeof(int32_t), hipMemcpyDeviceToHost, c.pl->stream));
+                PARO_HIP_TRY(hipMemcpyAsync(c.hconv, c.conv, sizeof(int32_t), hipMemcpyDeviceToHost, c.pl->stream));
         }
         bool any = false;
         for (CellRun &c : cells) {
             if (c.active && c.o.tol_res > 0.0) {
                 PARO_HIP_TRY(hipStreamSynchronize(c.pl->stream));
-                if (c.hconv) c.active = false;
+                if (*c.hconv) c.active = false;
             }
             any = any || c.active;
             c.solve = c.active;
@@ -466,9 +491,9 @@ int32_t run_cells(std::vector<CellRun> &cells)
                     c.solve = false;
                     continue;
                 }
-                PARO_HIP_TRY(hipMemcpyAsync(c.hflags.data(), w.iflags + c.nb, sizeof(int32_t) * c.nb,
+                PARO_HIP_TRY(hipMemcpyAsync(c.hflags, w.iflags + c.nb, sizeof(int32_t) * c.nb,
                                             hipMemcpyDeviceToHost, pl.stream));
-                PARO_HIP_TRY(hipMemcpyAsync(&c.scur, c.sigma, sizeof(double), hipMemcpyDeviceToHost, pl.stream));
+                PARO_HIP_TRY(hipMemcpyAsync(c.scur, c.sigma, sizeof(double), hipMemcpyDeviceToHost, pl.stream));
             }
             bool again = false;
             for (CellRun &c : cells) {
@@ -476,7 +501,7 @@ int32_t run_cells(std::vector<CellRun> &cells)
                 PARO_HIP_TRY(hipStreamSynchronize(c.pl->stream));
                 bool neg = false;
                 for (int b = 0; b < c.nb; ++b) neg = neg || (c.hflags[b] & PARO_F_NEGCURV);
-                if (!neg || c.scur == c.o.sigma_lb || attempt == 1) {
+                if (!neg || *c.scur == c.o.sigma_lb || attempt == 1) {
                     c.solve = false;
                     continue;
                 }
