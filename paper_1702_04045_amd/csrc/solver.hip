@@ -418,11 +418,69 @@ int32_t prepare_cell(paro_plan plan, int32_t nb, double *psi, double *hpsi, int6
     return PARO_OK;
 }
 
+// Events, freed on scope exit.
+struct EventSet {
+    std::vector<hipEvent_t> ev;
+    ~EventSet()
+    {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+enum class Phase { Start, WaitConv, WaitSolve, Done };
+
+// Enqueue the source problems of the cell's current iteration (Algorithm 1
+// step 3, or the correction equation of Algorithms 2 and 3).
+hipError_t enqueue_solve(CellRun &c)
+{
+    const Plan &pl = *c.pl;
+    Workspace &w = c.w;
+    const int64_t lv = pl.ldv;
+    const bool mparo = c.o.variant != PARO_VARIANT_PARO;
+    double2 *Ut = mparo ? w.U + (size_t)c.nb * lv : w.U;  // u (Algorithm 1) or e (Algorithms 2, 3)
+    if (c.o.precision == PARO_PREC_MIXED)
+        return source_solve_mixed(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.sig_all, c.o.n_cg, Ut, lv,
+                                  w.iflags + c.nb, mparo);
+    return source_solve(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.sig_all, c.o.n_cg, Ut, lv, w.iflags + c.nb,
+                        c.o.variant);
+}
+
+// Enqueue Rayleigh-Ritz (steps 4), residuals, the next shift and the
+// statistics row of iteration it (step 5).
+hipError_t enqueue_finish(CellRun &c, int it)
+{
+    const Plan &pl = *c.pl;
+    Workspace &w = c.w;
+    const int64_t lv = pl.ldv;
+    const int nb = c.nb;
+    hipError_t e;
+    if (c.o.variant != PARO_VARIANT_PARO) {
+        // span{psi, e/|e|}, e from the correction equation (Algorithms 2, 3)
+        double2 *Ut = w.U + (size_t)nb * lv;
+        if ((e = launch_normalize_bands(pl, w, nb, Ut, lv)) != hipSuccess) return e;
+        if ((e = launch_copy_bands(pl.stream, nb, pl.ng, c.psi, c.ld, w.U, lv)) != hipSuccess) return e;
+        if ((e = launch_copy_bands(pl.stream, nb, pl.ng, c.hpsi, c.ld, w.W, lv)) != hipSuccess) return e;
+        if ((e = apply_full(pl, w, nb, Ut, lv, w.W + (size_t)nb * lv, nullptr)) != hipSuccess) return e;
+        if ((e = rayleigh_ritz(pl, w, 2 * nb, nb, w.U, w.W, lv, c.eps, c.psi, c.hpsi, c.ld)) != hipSuccess) return e;
+    } else {
+        if ((e = apply_full(pl, w, nb, w.U, lv, w.W, nullptr)) != hipSuccess) return e;
+        if ((e = rayleigh_ritz(pl, w, nb, nb, w.U, w.W, lv, c.eps, c.psi, c.hpsi, c.ld)) != hipSuccess) return e;
+    }
+    const int row = 2 * nb + 2;
+    if ((e = launch_residuals(pl, w, nb, c.psi, c.hpsi, c.ld, c.eps, w.res)) != hipSuccess) return e;
+    return launch_bookkeeping(pl, nb, c.o, c.eps, w.res, w.sig_all, c.sigma,
+                              c.stats ? c.stats + (size_t)(it + 1) * row : nullptr, c.conv);
+}
+
 // The outer loop of Algorithm 1 (or 2, 3) for every cell.  Each cell's
-// kernels go to its plan's stream; the host decisions of an iteration (the
-// convergence test, the negative-curvature retry of the adaptive shift)
-// first enqueue every cell's work and its small device-to-host copies, then
-// wait for each cell in turn, so that cells on different streams overlap.
+// kernels go to its plan's stream.  The host decisions of an iteration (the
+// convergence test, the negative-curvature retry of the adaptive shift) read
+// small device values copied into pinned host memory behind an event; the
+// host polls the cells' events and moves each cell on as soon as its own
+// values have arrived, so that no cell waits for another and the GPU always
+// holds the work of every cell that is not waiting.  A cell's sequence of
+// launches is the same as when it runs alone.
 int32_t run_cells(std::vector<CellRun> &cells)
 {
     // per cell: sigma (double), the convergence flag, the band flags; 8-byte blocks
@@ -440,6 +498,10 @@ int32_t run_cells(std::vector<CellRun> &cells)
             q += block(c);
         }
     }
+    const int n = (int)cells.size();
+    EventSet events;
+    events.ev.assign(n, nullptr);
+    for (int i = 0; i < n; ++i) PARO_HIP_TRY(hipEventCreateWithFlags(&events.ev[i], hipEventDisableTiming));
     for (CellRun &c : cells) {
         const Plan &pl = *c.pl;
         Workspace &w = c.w;
@@ -452,93 +514,86 @@ int32_t run_cells(std::vector<CellRun> &cells)
         PARO_CHECK_LAUNCH(launch_residuals(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.res));
         PARO_CHECK_LAUNCH(launch_bookkeeping(pl, c.nb, c.o, c.eps, w.res, w.sig_all, c.sigma, c.stats, c.conv));
     }
-    int max_outer = 0;
-    for (const CellRun &c : cells) max_outer = std::max(max_outer, c.o.n_outer);
-    for (int it = 0; it < max_outer; ++it) {
-        // convergence test (tol_res > 0) on the device flag of the last bookkeeping
-        for (CellRun &c : cells) {
-            if (c.active && it >= c.o.n_outer) c.active = false;
-            if (c.active && c.o.tol_res > 0.0)
-                PARO_HIP_TRY(hipMemcpyAsync(c.hconv, c.conv, sizeof(int32_t), hipMemcpyDeviceToHost, c.pl->stream));
+    std::vector<Phase> phase(n, Phase::Start);
+    std::vector<int> iter(n, 0), attempt(n, 0);
+    // solve, then either wait for the curvature flags or finish the iteration
+    auto solve_step = [&](int i) -> int32_t {
+        CellRun &c = cells[i];
+        PARO_CHECK_LAUNCH(enqueue_solve(c));
+        if (c.o.shift_mode == PARO_SHIFT_ADAPTIVE) {
+            PARO_HIP_TRY(hipMemcpyAsync(c.hflags, c.w.iflags + c.nb, sizeof(int32_t) * c.nb, hipMemcpyDeviceToHost,
+                                        c.pl->stream));
+            PARO_HIP_TRY(hipMemcpyAsync(c.scur, c.sigma, sizeof(double), hipMemcpyDeviceToHost, c.pl->stream));
+            PARO_HIP_TRY(hipEventRecord(events.ev[i], c.pl->stream));
+            phase[i] = Phase::WaitSolve;
+            return PARO_OK;
         }
-        bool any = false;
-        for (CellRun &c : cells) {
-            if (c.active && c.o.tol_res > 0.0) {
-                PARO_HIP_TRY(hipStreamSynchronize(c.pl->stream));
-                if (*c.hconv) c.active = false;
+        PARO_CHECK_LAUNCH(enqueue_finish(c, iter[i]));
+        if (c.n_done) *c.n_done = iter[i] + 1;
+        ++iter[i];
+        phase[i] = Phase::Start;
+        return PARO_OK;
+    };
+    for (;;) {
+        bool left = false;
+        for (int i = 0; i < n; ++i) {
+            CellRun &c = cells[i];
+            if (phase[i] == Phase::Done) continue;
+            left = true;
+            if (phase[i] == Phase::WaitConv || phase[i] == Phase::WaitSolve) {
+                const hipError_t q = hipEventQuery(events.ev[i]);
+                if (q == hipErrorNotReady) continue;
+                PARO_HIP_TRY(q);
             }
-            any = any || c.active;
-            c.solve = c.active;
-        }
-        if (!any) break;
-        // source problems; with the adaptive shift, a cell whose PCG met
-        // negative curvature solves again with sigma_lb
-        for (int attempt = 0; attempt < 2; ++attempt) {
-            for (CellRun &c : cells) {
-                if (!c.solve) continue;
-                const Plan &pl = *c.pl;
-                Workspace &w = c.w;
-                const int64_t lv = pl.ldv;
-                const bool mparo = c.o.variant != PARO_VARIANT_PARO;
-                double2 *Ut = mparo ? w.U + (size_t)c.nb * lv : w.U;  // u (Algorithm 1) or e (Algorithms 2, 3)
-                if (c.o.precision == PARO_PREC_MIXED)
-                    PARO_CHECK_LAUNCH(source_solve_mixed(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.sig_all, c.o.n_cg,
-                                                         Ut, lv, w.iflags + c.nb, mparo));
-                else
-                    PARO_CHECK_LAUNCH(source_solve(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.sig_all, c.o.n_cg, Ut,
-                                                   lv, w.iflags + c.nb, c.o.variant));
-                if (c.o.shift_mode != PARO_SHIFT_ADAPTIVE) {
-                    c.solve = false;
-                    continue;
+            int32_t rc = PARO_OK;
+            switch (phase[i]) {
+            case Phase::Start:
+                if (iter[i] >= c.o.n_outer) {
+                    phase[i] = Phase::Done;
+                } else if (c.o.tol_res > 0.0) {
+                    PARO_HIP_TRY(
+                        hipMemcpyAsync(c.hconv, c.conv, sizeof(int32_t), hipMemcpyDeviceToHost, c.pl->stream));
+                    PARO_HIP_TRY(hipEventRecord(events.ev[i], c.pl->stream));
+                    phase[i] = Phase::WaitConv;
+                } else {
+                    attempt[i] = 0;
+                    rc = solve_step(i);
                 }
-                PARO_HIP_TRY(hipMemcpyAsync(c.hflags, w.iflags + c.nb, sizeof(int32_t) * c.nb,
-                                            hipMemcpyDeviceToHost, pl.stream));
-                PARO_HIP_TRY(hipMemcpyAsync(c.scur, c.sigma, sizeof(double), hipMemcpyDeviceToHost, pl.stream));
-            }
-            bool again = false;
-            for (CellRun &c : cells) {
-                if (!c.solve) continue;
-                PARO_HIP_TRY(hipStreamSynchronize(c.pl->stream));
+                break;
+            case Phase::WaitConv:
+                if (*c.hconv) {
+                    phase[i] = Phase::Done;
+                } else {
+                    attempt[i] = 0;
+                    rc = solve_step(i);
+                }
+                break;
+            case Phase::WaitSolve: {
                 bool neg = false;
                 for (int b = 0; b < c.nb; ++b) neg = neg || (c.hflags[b] & PARO_F_NEGCURV);
-                if (!neg || *c.scur == c.o.sigma_lb || attempt == 1) {
-                    c.solve = false;
-                    continue;
+                if (neg && *c.scur != c.o.sigma_lb && attempt[i] == 0) {
+                    // negative curvature: solve again with sigma_lb
+                    paro_iter_opts fixed = c.o;
+                    fixed.shift_mode = PARO_SHIFT_FIXED;
+                    fixed.tol_res = 0.0;
+                    PARO_CHECK_LAUNCH(launch_bookkeeping(*c.pl, c.nb, fixed, c.eps, c.w.res, c.w.sig_all, c.sigma,
+                                                         nullptr, c.conv));
+                    attempt[i] = 1;
+                    rc = solve_step(i);
+                } else {
+                    PARO_CHECK_LAUNCH(enqueue_finish(c, iter[i]));
+                    if (c.n_done) *c.n_done = iter[i] + 1;
+                    ++iter[i];
+                    phase[i] = Phase::Start;
                 }
-                paro_iter_opts fixed = c.o;
-                fixed.shift_mode = PARO_SHIFT_FIXED;
-                fixed.tol_res = 0.0;
-                PARO_CHECK_LAUNCH(launch_bookkeeping(*c.pl, c.nb, fixed, c.eps, c.w.res, c.w.sig_all, c.sigma,
-                                                     nullptr, c.conv));
-                again = true;
+                break;
             }
-            if (!again) break;
-        }
-        // Rayleigh-Ritz, residuals, shift and statistics
-        for (CellRun &c : cells) {
-            if (!c.active) continue;
-            const Plan &pl = *c.pl;
-            Workspace &w = c.w;
-            const int64_t lv = pl.ldv;
-            const int nb = c.nb;
-            if (c.o.variant != PARO_VARIANT_PARO) {
-                // span{psi, e/|e|}, e from the correction equation (Algorithms 2, 3)
-                double2 *Ut = w.U + (size_t)nb * lv;
-                PARO_CHECK_LAUNCH(launch_normalize_bands(pl, w, nb, Ut, lv));
-                PARO_CHECK_LAUNCH(launch_copy_bands(pl.stream, nb, pl.ng, c.psi, c.ld, w.U, lv));
-                PARO_CHECK_LAUNCH(launch_copy_bands(pl.stream, nb, pl.ng, c.hpsi, c.ld, w.W, lv));
-                PARO_CHECK_LAUNCH(apply_full(pl, w, nb, Ut, lv, w.W + (size_t)nb * lv, nullptr));
-                PARO_CHECK_LAUNCH(rayleigh_ritz(pl, w, 2 * nb, nb, w.U, w.W, lv, c.eps, c.psi, c.hpsi, c.ld));
-            } else {
-                PARO_CHECK_LAUNCH(apply_full(pl, w, nb, w.U, lv, w.W, nullptr));
-                PARO_CHECK_LAUNCH(rayleigh_ritz(pl, w, nb, nb, w.U, w.W, lv, c.eps, c.psi, c.hpsi, c.ld));
+            case Phase::Done:
+                break;
             }
-            const int row = 2 * nb + 2;
-            PARO_CHECK_LAUNCH(launch_residuals(pl, w, nb, c.psi, c.hpsi, c.ld, c.eps, w.res));
-            PARO_CHECK_LAUNCH(launch_bookkeeping(pl, nb, c.o, c.eps, w.res, w.sig_all, c.sigma,
-                                                 c.stats ? c.stats + (size_t)(it + 1) * row : nullptr, c.conv));
-            if (c.n_done) *c.n_done = it + 1;
+            if (rc) return rc;
         }
+        if (!left) break;
     }
     return PARO_OK;
 }
