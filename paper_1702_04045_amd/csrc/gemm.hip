@@ -125,29 +125,51 @@ k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, const C2 *__restrict__ A
             }
 }
 
-// C[i][j] = dscale_i * sum_s part[s][j][i]; quad_j = sum_i dscale_i |sum_s part|^2
+// C[i][j] = dscale_i * sum_s part[s][j][i]; quad_j = sum_i dscale_i |sum_s part|^2.
+// One work-group per column j; 64 rows at a time, the splits dealt to four
+// thread groups (group g sums s = g, g + 4, ... in order) and the four
+// group sums added in group order: a fixed summation order, so the result
+// is bitwise reproducible, with four times the loads in flight of one
+// thread per row.
 template <class CO>
 __global__ void __launch_bounds__(256)
 k_gemm_hn_reduce(int M, int N, int nsplit, const double2 *__restrict__ part, CO *__restrict__ C, int64_t ldc,
                  const double *__restrict__ dscale, double *__restrict__ quad)
 {
     __shared__ double red[4];
+    __shared__ double2 grp[4][64];
     const int j = blockIdx.x;
+    const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
     double q = 0.0;
-    for (int i = threadIdx.x; i < M; i += 256) {
+    for (int i0 = 0; i0 < M; i0 += 64) {
+        const int i = i0 + r;
         double2 s = make_double2(0.0, 0.0);
-        for (int p = 0; p < nsplit; ++p) {
-            const double2 x = part[((size_t)p * N + j) * M + i];
-            s.x += x.x;
-            s.y += x.y;
+        if (i < M) {
+#pragma unroll 4
+            for (int p = g; p < nsplit; p += 4) {
+                const double2 x = part[((size_t)p * N + j) * M + i];
+                s.x += x.x;
+                s.y += x.y;
+            }
         }
-        if (dscale) {
-            const double d = dscale[i];
-            q += d * (s.x * s.x + s.y * s.y);
-            s.x *= d;
-            s.y *= d;
+        grp[g][r] = s;
+        __syncthreads();
+        if (g == 0 && i < M) {
+            double2 t = grp[0][r];
+#pragma unroll
+            for (int k = 1; k < 4; ++k) {
+                t.x += grp[k][r].x;
+                t.y += grp[k][r].y;
+            }
+            if (dscale) {
+                const double d = dscale[i];
+                q += d * (t.x * t.x + t.y * t.y);
+                t.x *= d;
+                t.y *= d;
+            }
+            C[(int64_t)j * ldc + i] = cmk<CO>(t.x, t.y);
         }
-        C[(int64_t)j * ldc + i] = cmk<CO>(s.x, s.y);
+        __syncthreads();
     }
     if (quad) {
         q = block_sum<256>(q, red);
