@@ -145,6 +145,52 @@ def cpu_baseline(spec, cell, v, x_trial, sample_bands=64):
             "seconds_per_outer_iteration": t_outer}
 
 
+def batched_cells(args, P, torch, n_outer=5, n_cg=10, n_streams=8, reps=3):
+    """The uneven 24-cell workload: n_outer ParO outer iterations (adaptive
+    shift, initial Rayleigh-Ritz) of every cell from its trial block, once
+    cell after cell with paro_iterate and once with paro_iterate_batch over
+    n_streams streams; best of reps, wall time between device
+    synchronisations."""
+    specs = synth.batch_specs(args.seed)
+    plans, xs = [], []
+    for i, sp in enumerate(specs):
+        c = synth.make_cell(sp, i)
+        v = synth.vloc_on_grid(c["cell"], c["grid"], c["positions"], c["depths"], c["widths"])
+        pl = P.Plan(c["cell"], c["ecut"], v, c["projectors"])
+        plans.append(pl)
+        xs.append(torch.from_numpy(synth.trial_block(pl.ng, sp.n_bands, i)).cuda())
+    sig = [pl.shift_lower_bound() for pl in plans]
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
+
+    def sequential():
+        for pl, x, s in zip(plans, xs, sig):
+            pl.iterate(x.clone(), n_outer, n_cg, s, shift_mode=P.SHIFT_ADAPTIVE, stats=False)
+
+    def batch():
+        P.iterate_batch(plans, [x.clone() for x in xs], n_outer, n_cg, sig, shift_mode=P.SHIFT_ADAPTIVE,
+                        streams=streams)
+
+    def best(f):
+        f()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return min(ts)
+
+    t_seq, t_bat = best(sequential), best(batch)
+    applies = sum(x.shape[0] for x in xs) * (n_cg + 1) * n_outer
+    return {"cells": len(specs), "grids": sorted({sp.grid for sp in specs}),
+            "bands": [sp.n_bands for sp in specs], "plane_waves": [pl.ng for pl in plans],
+            "projectors": [pl.n_proj for pl in plans], "outer_iterations_per_cell": n_outer, "pcg_steps": n_cg,
+            "streams": n_streams, "seconds": t_bat, "cell_iterations_per_s": len(specs) * n_outer / t_bat,
+            "band_applies_per_s": applies / t_bat, "sequential_seconds": t_seq,
+            "speedup_vs_sequential": t_seq / t_bat, "dtype": "f64"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +200,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-1e-8 run")
     ap.add_argument("--tta-seconds", type=float, default=60.0)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 24-cell batched run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -320,6 +367,8 @@ def main():
                             "launches_timed": int(nld.value), "avg_launch_ms": avg_d,
                             "flops_per_launch": fl_d, "share_of_call": totd.value / 10 / ms_dens}}
 
+    batched = None if args.no_batch else batched_cells(args, P, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(spec, cell, v, x_np)
@@ -332,7 +381,7 @@ def main():
                       "variant": "ParO (Algorithm 1)", "shift": "adaptive", "parallelism": "single GPU"},
            "hpsi_applies_per_s": applies_s, "wall_s_timed": wall, "status_flags": status,
            "roofline": roofline, "time_to_1e-8": tta64, "mixed": mixed, "density": density,
-           "cpu_baseline": cpu}
+           "batched_cells": batched, "cpu_baseline": cpu}
     print(json.dumps(rec))
 
 
