@@ -147,12 +147,15 @@ k_trsm_col(int m, const double2 *__restrict__ L, const double2 *__restrict__ src
 // that H_k^H maps column k below the diagonal to (beta_k, 0, ...), beta_k
 // real.  On exit: d (diagonal), e (off-diagonal, e_k = beta_k), tau, and
 // v_k stored in column k of A below the diagonal.
-__global__ void __launch_bounds__(kBig)
-k_tridiag(int m, double2 *__restrict__ A, double *__restrict__ d, double *__restrict__ e, double2 *__restrict__ tau)
+//
+// One work-group of kBig threads.  A (m x m, column-major, leading
+// dimension m) is either the global matrix or a copy in LDS; sv, sy, sw
+// (m each) and partial (kBig) are LDS scratch.
+__device__ __forceinline__ void tridiag_run(int m, double2 *A, double *__restrict__ d, double *__restrict__ e,
+                                            double2 *__restrict__ tau, double2 *sv, double2 *sy, double2 *sw,
+                                            double2 *partial)
 {
     __shared__ double red[kBig / 64];
-    __shared__ double2 sv[kBig], sy[kBig], sw[kBig];
-    __shared__ double2 partial[kBig];
     __shared__ double2 s_tau, s_scale;
     __shared__ double s_beta;
     const int tid = threadIdx.x;
@@ -253,6 +256,161 @@ k_tridiag(int m, double2 *__restrict__ A, double *__restrict__ d, double *__rest
         e[m - 1] = 0.0;
         tau[m - 1] = make_double2(0.0, 0.0);
     }
+}
+
+__global__ void __launch_bounds__(kBig)
+k_tridiag(int m, double2 *__restrict__ A, double *__restrict__ d, double *__restrict__ e, double2 *__restrict__ tau)
+{
+    __shared__ double2 sv[kBig], sy[kBig], sw[kBig];
+    __shared__ double2 partial[kBig];
+    tridiag_run(m, A, d, e, tau, sv, sy, sw, partial);
+}
+
+// The same reduction with the matrix in LDS for the whole sweep
+// (m <= kTridiagLdsMax), by kTriWaves wavefronts.  Lane l of every
+// wavefront holds rows l and l + 64 of the vectors x, v, y, w; the scalars
+// of each Householder vector and the reductions over rows are computed
+// redundantly and identically by every wavefront (shuffle trees, lane 0
+// broadcasts), so they need no barrier.  The column loops of y = A v and of
+// the rank-2 update are split over the wavefronts (columns j = wave,
+// wave + kTriWaves, ...); the partial y of each wavefront is added in
+// wavefront order.  Four work-group barriers per column.
+// Dynamic LDS: m^2 + (2 + kTriWaves) m complex values.
+constexpr int kTriWaves = 8;
+constexpr int kTridiagLdsMax = 92;
+static size_t tridiag_lds_bytes(int m) { return sizeof(double2) * ((size_t)m * m + (2 + kTriWaves) * (size_t)m); }
+
+// sum over the wavefront (fixed shuffle tree), the same value in every lane
+__device__ __forceinline__ double wave_sum_all(double v) { return __shfl(wave_sum(v), 0, 64); }
+
+__global__ void __launch_bounds__(64 * kTriWaves)
+k_tridiag_lds(int m, double2 *__restrict__ A, double *__restrict__ d, double *__restrict__ e,
+              double2 *__restrict__ tau)
+{
+    extern __shared__ double2 S[];
+    double2 *sv = S + m * m, *sw = sv + m, *yp = sw + m;  // yp: kTriWaves x m partial products
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int NT = 64 * kTriWaves;
+    const int mm = m * m;
+    for (int q = tid; q < mm; q += NT) S[q] = A[q];
+    __syncthreads();
+    // hermitise (upper from the average with the lower triangle)
+    for (int jj = wave; jj < m; jj += kTriWaves) {
+        for (int ii = jj + 1 + lane; ii < m; ii += 64) {
+            const double2 a = S[jj * m + ii], b = S[ii * m + jj];
+            const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+            S[jj * m + ii] = h;
+            S[ii * m + jj] = cconj(h);
+        }
+        if (lane == 0) S[jj * m + jj].y = 0.0;
+    }
+    __syncthreads();
+    const int i0 = lane, i1 = lane + 64;
+    for (int k = 0; k + 1 < m; ++k) {
+        const int n = m - k - 1;
+        double2 *col = S + k * m + k + 1;  // x = A[k+1:, k]
+        const bool h0 = i0 < n, h1 = i1 < n;
+        const double2 x0 = h0 ? col[i0] : make_double2(0.0, 0.0), x1 = h1 ? col[i1] : make_double2(0.0, 0.0);
+        double xn = 0.0;
+        if (h0 && i0 > 0) xn += x0.x * x0.x + x0.y * x0.y;
+        if (h1) xn += x1.x * x1.x + x1.y * x1.y;
+        xn = wave_sum_all(xn);
+        const double2 alpha = col[0];
+        double2 tk, sc;
+        double beta;
+        if (xn == 0.0 && alpha.y == 0.0) {
+            tk = make_double2(0.0, 0.0);
+            beta = alpha.x;
+            sc = make_double2(0.0, 0.0);
+        } else {
+            const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn);
+            beta = alpha.x >= 0.0 ? -nrm : nrm;
+            tk = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+            const double ar = alpha.x - beta, ai = alpha.y, den = ar * ar + ai * ai;
+            sc = make_double2(ar / den, -ai / den);  // 1 / (alpha - beta)
+        }
+        const double dk = S[k * m + k].x;
+        // v = x / (alpha - beta), v_0 = 1, kept in column k below the diagonal
+        const double2 v0 = h0 ? (i0 == 0 ? make_double2(1.0, 0.0) : cmul_(x0, sc)) : make_double2(0.0, 0.0);
+        const double2 v1 = h1 ? cmul_(x1, sc) : make_double2(0.0, 0.0);
+        __syncthreads();  // every wavefront has read column k
+        if (wave == 0) {
+            if (lane == 0) {
+                d[k] = dk;
+                e[k] = beta;
+                tau[k] = tk;
+            }
+            if (h0) col[i0] = sv[i0] = v0;
+            if (h1) col[i1] = sv[i1] = v1;
+        }
+        __syncthreads();
+        if (tk.x == 0.0 && tk.y == 0.0) continue;
+        // partial y = A_trail v over this wavefront's columns, A_trail = A[k+1:, k+1:]
+        double2 *At = S + (k + 1) * m + k + 1;
+        double2 y0 = make_double2(0.0, 0.0), y1 = make_double2(0.0, 0.0);
+#pragma unroll 4
+        for (int jj = wave; jj < n; jj += kTriWaves) {
+            const double2 vj = sv[jj];
+            if (h0) {
+                const double2 t = cmul_(At[jj * m + i0], vj);
+                y0.x += t.x;
+                y0.y += t.y;
+            }
+            if (h1) {
+                const double2 t = cmul_(At[jj * m + i1], vj);
+                y1.x += t.x;
+                y1.y += t.y;
+            }
+        }
+        if (h0) yp[wave * m + i0] = y0;
+        if (h1) yp[wave * m + i1] = y1;
+        __syncthreads();
+        y0 = y1 = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < kTriWaves; ++q) {
+            if (h0) {
+                y0.x += yp[q * m + i0].x;
+                y0.y += yp[q * m + i0].y;
+            }
+            if (h1) {
+                y1.x += yp[q * m + i1].x;
+                y1.y += yp[q * m + i1].y;
+            }
+        }
+        // w = tau y - (|tau|^2 / 2) Re(v^H y) v
+        const double cr = wave_sum_all(cjmul(v0, y0).x + cjmul(v1, y1).x);
+        const double t2 = 0.5 * (tk.x * tk.x + tk.y * tk.y) * cr;
+        const double2 ty0 = cmul_(tk, y0), ty1 = cmul_(tk, y1);
+        const double2 w0 = make_double2(ty0.x - t2 * v0.x, ty0.y - t2 * v0.y);
+        const double2 w1 = make_double2(ty1.x - t2 * v1.x, ty1.y - t2 * v1.y);
+        if (wave == 0) {
+            if (h0) sw[i0] = w0;
+            if (h1) sw[i1] = w1;
+        }
+        __syncthreads();
+        // A_trail -= w v^H + v w^H over this wavefront's columns
+#pragma unroll 4
+        for (int jj = wave; jj < n; jj += kTriWaves) {
+            const double2 vj = sv[jj], wj = sw[jj];
+            if (h0) {
+                const double2 a = cjmul(vj, w0), b = cjmul(wj, v0);  // w_i conj(v_j), v_i conj(w_j)
+                double2 c = At[jj * m + i0];
+                At[jj * m + i0] = make_double2(c.x - (a.x + b.x), c.y - (a.y + b.y));
+            }
+            if (h1) {
+                const double2 a = cjmul(vj, w1), b = cjmul(wj, v1);
+                double2 c = At[jj * m + i1];
+                At[jj * m + i1] = make_double2(c.x - (a.x + b.x), c.y - (a.y + b.y));
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        d[m - 1] = S[(m - 1) * m + m - 1].x;
+        e[m - 1] = 0.0;
+        tau[m - 1] = make_double2(0.0, 0.0);
+    }
+    for (int q = tid; q < mm; q += NT) A[q] = S[q];
 }
 
 // 1 / x: hardware reciprocal refined by one Newton step (about 1 ulp);
@@ -600,7 +758,14 @@ size_t dense_real_elems(int mmax) { return 5 * (size_t)mmax + 2 + (size_t)mmax *
 static hipError_t eig_pipeline(hipStream_t st, int m, double2 *Hh, const DenseScratch &s, double *eps_out,
                                int nout, double2 *Yout, bool vectors)
 {
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kBig), 0, st, m, Hh, s.d, s.e, s.tau);
+    static const hipError_t lds_attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(k_tridiag_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)tridiag_lds_bytes(kTridiagLdsMax));
+    if (m <= kTridiagLdsMax && lds_attr == hipSuccess)
+        hipLaunchKernelGGL(k_tridiag_lds, dim3(1), dim3(64 * kTriWaves), tridiag_lds_bytes(m), st, m, Hh, s.d, s.e,
+                           s.tau);
+    else
+        hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kBig), 0, st, m, Hh, s.d, s.e, s.tau);
     hipLaunchKernelGGL(k_tri_eigvals, dim3(m), dim3(64), 0, st, m, s.d, s.e, s.lam, eps_out, nout);
     if (vectors)
         hipLaunchKernelGGL(k_tri_eigvecs, dim3(m), dim3(64), 8 * (size_t)m * sizeof(double), st, m, s.d, s.e, s.lam,
