@@ -65,6 +65,9 @@ k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, const C2 *__restrict__ A
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i0 = blockIdx.x * kTile + (wave & 1) * 32;
     const int j0 = blockIdx.y * kTile + (wave >> 1) * 32;
+    // a wavefront whose 32 x 32 block lies outside C has nothing to do (the
+    // kernel has no barriers); its SIMD goes to the other resident work-groups
+    if (i0 >= M || j0 >= N) return;
     const int64_t kb = (int64_t)blockIdx.z * kchunk;
     const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
     const int l16 = lane & 15, lk = lane >> 4;
@@ -187,6 +190,7 @@ k_gemm_nn(int64_t M, int N, int K, const C2 *__restrict__ A, int64_t lda, const 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t g0 = (int64_t)blockIdx.x * kTile + (wave & 1) * 32;
     const int n0 = blockIdx.y * kTile + (wave >> 1) * 32;
+    if (g0 >= M || n0 >= N) return;  // block outside C (no barriers in this kernel)
     const int l16 = lane & 15, lk = lane >> 4;
     Acc re[2][2], im[2][2];
 #pragma unroll
@@ -310,7 +314,10 @@ hipError_t gemm_hn_t(hipStream_t s, int M, int N, int64_t K, const C2 *A, int64_
 {
     if (M <= 0 || N <= 0) return hipSuccess;
     const int tm = (M + kTile - 1) / kTile, tn = (N + kTile - 1) / kTile;
-    int64_t nsplit = (kSplitTarget + tm * tn - 1) / (tm * tn);
+    // as many splits as fit in one round of kSplitTarget work-groups (two
+    // resident per compute unit): a last, partly filled round would take
+    // as long as a full one
+    int64_t nsplit = kSplitTarget / (tm * tn);
     // at least one prefetch ring of k per split: small products (few output
     // tiles, short contraction) still spread over many work-groups
     const int64_t kmax = (K + 4 * kDepthHN - 1) / (4 * kDepthHN);
