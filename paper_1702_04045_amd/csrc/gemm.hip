@@ -49,6 +49,18 @@ template <> struct Mma<float2> {
 namespace {
 
 constexpr int kTile = 64;   // work-group tile (4 waves of 32 x 32)
+constexpr int kXcds = 8;    // accelerator complex dies; work-group b runs on die b % kXcds
+
+// Work index of work-group b among total: the work-groups of one die get
+// consecutive work indices in dispatch order, so tiles that share operands
+// (adjacent work indices) run at the same time on the same die and share
+// its L2.  A bijection of [0, total).
+__device__ __forceinline__ int64_t xcd_work_index(int64_t b, int64_t total)
+{
+    const int64_t q = total / kXcds, r = total % kXcds;
+    const int64_t x = b % kXcds, l = b / kXcds;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
+}
 // k-steps of 4 in flight per wave (register prefetch ring), measured best
 // for the long split contraction of gemm_hn and the short one of gemm_nn
 constexpr int kDepthHN = 8;
@@ -58,17 +70,21 @@ constexpr int kDepthNN = 4;
 // (accumulated in the operands' precision, stored in FP64)
 template <class C2>
 __global__ void __launch_bounds__(256)
-k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, const C2 *__restrict__ A, int64_t lda,
-               const C2 *__restrict__ B, int64_t ldb, double2 *__restrict__ part)
+k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, int tm, int tn, int nsplit, const C2 *__restrict__ A,
+               int64_t lda, const C2 *__restrict__ B, int64_t ldb, double2 *__restrict__ part)
 {
     using Acc = typename Mma<C2>::Acc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i0 = blockIdx.x * kTile + (wave & 1) * 32;
-    const int j0 = blockIdx.y * kTile + (wave >> 1) * 32;
+    // work index: the tm x tn tiles of one split are adjacent (they share the
+    // split's slices of A and B)
+    const int64_t w = xcd_work_index(blockIdx.x, (int64_t)tm * tn * nsplit);
+    const int split = (int)(w / (tm * tn)), tile = (int)(w % (tm * tn));
+    const int i0 = (tile % tm) * kTile + (wave & 1) * 32;
+    const int j0 = (tile / tm) * kTile + (wave >> 1) * 32;
     // a wavefront whose 32 x 32 block lies outside C has nothing to do (the
     // kernel has no barriers); its SIMD goes to the other resident work-groups
     if (i0 >= M || j0 >= N) return;
-    const int64_t kb = (int64_t)blockIdx.z * kchunk;
+    const int64_t kb = (int64_t)split * kchunk;
     const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
     const int l16 = lane & 15, lk = lane >> 4;
     Acc re[2][2], im[2][2];
@@ -115,7 +131,7 @@ k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, const C2 *__restrict__ A
             step(d);
         }
     }
-    double2 *P = part + (size_t)blockIdx.z * M * N;
+    double2 *P = part + (size_t)split * M * N;
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -183,13 +199,16 @@ k_gemm_hn_reduce(int M, int N, int nsplit, const double2 *__restrict__ part, CO 
 // C[g][n] (+)= sum_k A[g][k] B[k][n]; matrix-core rows = n, columns = g.
 template <class C2>
 __global__ void __launch_bounds__(256)
-k_gemm_nn(int64_t M, int N, int K, const C2 *__restrict__ A, int64_t lda, const C2 *__restrict__ B, int64_t ldb,
-          C2 *__restrict__ C, int64_t ldc, int accumulate)
+k_gemm_nn(int64_t M, int N, int K, int tn, const C2 *__restrict__ A, int64_t lda, const C2 *__restrict__ B,
+          int64_t ldb, C2 *__restrict__ C, int64_t ldc, int accumulate)
 {
     using Acc = typename Mma<C2>::Acc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t g0 = (int64_t)blockIdx.x * kTile + (wave & 1) * 32;
-    const int n0 = blockIdx.y * kTile + (wave >> 1) * 32;
+    // work index: the tn column tiles of one row tile (which share its rows
+    // of A) are adjacent
+    const int64_t w = xcd_work_index(blockIdx.x, (int64_t)gridDim.x);
+    const int64_t g0 = (w / tn) * kTile + (wave & 1) * 32;
+    const int n0 = (int)(w % tn) * kTile + (wave >> 1) * 32;
     if (g0 >= M || n0 >= N) return;  // block outside C (no barriers in this kernel)
     const int l16 = lane & 15, lk = lane >> 4;
     Acc re[2][2], im[2][2];
@@ -331,8 +350,8 @@ hipError_t gemm_hn_t(hipStream_t s, int M, int N, int64_t K, const C2 *A, int64_
     nsplit = (K + kchunk - 1) / kchunk;
     if (nsplit < 1) nsplit = 1;
     prof_mark(PARO_K_GEMM_HN, s, true);
-    hipLaunchKernelGGL((k_gemm_hn_part<C2>), dim3(tm, tn, nsplit), dim3(256), 0, s, M, N, K, kchunk, A, lda, B, ldb,
-                       part);
+    hipLaunchKernelGGL((k_gemm_hn_part<C2>), dim3((unsigned)(tm * tn * nsplit)), dim3(256), 0, s, M, N, K, kchunk, tm,
+                       tn, (int)nsplit, A, lda, B, ldb, part);
     prof_mark(PARO_K_GEMM_HN, s, false);
     hipLaunchKernelGGL((k_gemm_hn_reduce<C2>), dim3(N), dim3(256), 0, s, M, N, (int)nsplit, part, C, ldc, dscale,
                        quad);
@@ -344,9 +363,11 @@ hipError_t gemm_nn_t(hipStream_t s, int64_t M, int N, int K, const C2 *A, int64_
                      C2 *C, int64_t ldc, bool accumulate)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
-    dim3 grid((unsigned)((M + kTile - 1) / kTile), (N + kTile - 1) / kTile);
+    const int tn = (N + kTile - 1) / kTile;
+    dim3 grid((unsigned)((M + kTile - 1) / kTile * tn));
     prof_mark(PARO_K_GEMM_NN, s, true);
-    hipLaunchKernelGGL((k_gemm_nn<C2>), grid, dim3(256), 0, s, M, N, K, A, lda, B, ldb, C, ldc, accumulate ? 1 : 0);
+    hipLaunchKernelGGL((k_gemm_nn<C2>), grid, dim3(256), 0, s, M, N, K, tn, A, lda, B, ldb, C, ldc,
+                       accumulate ? 1 : 0);
     prof_mark(PARO_K_GEMM_NN, s, false);
     return hipGetLastError();
 }
