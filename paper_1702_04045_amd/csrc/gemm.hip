@@ -15,6 +15,7 @@
 // add q += B (D P) and the Ritz rotations U C, W C).  The matrix-core tile
 // is laid out as (column of C) x (row of C) so that a lane group writes 16
 // consecutive rows of C: stores are coalesced along the sphere.
+#include <algorithm>
 #include <cmath>
 
 #include "fft_device.h"
@@ -48,7 +49,7 @@ template <> struct Mma<float2> {
 
 namespace {
 
-constexpr int kTile = 64;   // work-group tile (4 waves of 32 x 32)
+constexpr int kWaveSlots = 2048;  // wavefronts resident at two per SIMD (256 CUs x 4 SIMDs x 2)
 constexpr int kXcds = 8;    // accelerator complex dies; work-group b runs on die b % kXcds
 
 // Work index of work-group b among total: the work-groups of one die get
@@ -67,81 +68,81 @@ constexpr int kDepthHN = 8;
 constexpr int kDepthNN = 4;
 
 // partial[s][j][i] = sum over k in split s of conj(A[k][i]) B[k][j]
-// (accumulated in the operands' precision, stored in FP64)
+// (accumulated in the operands' precision, stored in FP64).  Work unit =
+// one 32 x 32 block of one split, done by one wavefront; the wavefronts of
+// the grid take the units in turn (unit u, u + waves, ...).  Units of one
+// split are adjacent, so the blocks that share the split's slices of A and
+// B run at the same time on the same die.
 template <class C2>
 __global__ void __launch_bounds__(256)
-k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, int tm, int tn, int nsplit, const C2 *__restrict__ A,
+k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, int bm, int bn, int64_t units, const C2 *__restrict__ A,
                int64_t lda, const C2 *__restrict__ B, int64_t ldb, double2 *__restrict__ part)
 {
     using Acc = typename Mma<C2>::Acc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // work index: the tm x tn tiles of one split are adjacent (they share the
-    // split's slices of A and B)
-    const int64_t w = xcd_work_index(blockIdx.x, (int64_t)tm * tn * nsplit);
-    const int split = (int)(w / (tm * tn)), tile = (int)(w % (tm * tn));
-    const int i0 = (tile % tm) * kTile + (wave & 1) * 32;
-    const int j0 = (tile / tm) * kTile + (wave >> 1) * 32;
-    // a wavefront whose 32 x 32 block lies outside C has nothing to do (the
-    // kernel has no barriers); its SIMD goes to the other resident work-groups
-    if (i0 >= M || j0 >= N) return;
-    const int64_t kb = (int64_t)split * kchunk;
-    const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
-    const int l16 = lane & 15, lk = lane >> 4;
-    Acc re[2][2], im[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            re[a][b] = Acc{0, 0, 0, 0};
-            im[a][b] = Acc{0, 0, 0, 0};
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t unit = xcd_work_index(blockIdx.x, gridDim.x) * 4 + wave; unit < units; unit += nw) {
+        const int split = (int)(unit / (bm * bn)), blk = (int)(unit % (bm * bn));
+        const int i0 = (blk % bm) * 32, j0 = (blk / bm) * 32;
+        const int64_t kb = (int64_t)split * kchunk;
+        const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
+        const int l16 = lane & 15, lk = lane >> 4;
+        Acc re[2][2], im[2][2];
+    #pragma unroll
+        for (int a = 0; a < 2; ++a)
+    #pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                re[a][b] = Acc{0, 0, 0, 0};
+                im[a][b] = Acc{0, 0, 0, 0};
+            }
+        const int ia[2] = {i0 + l16, i0 + 16 + l16};
+        const int jb[2] = {j0 + l16, j0 + 16 + l16};
+        // Register prefetch ring: the operands of k-step s + kDepthHN - 1 are
+        // requested before the products of step s, so that their latency
+        // overlaps kDepthHN - 1 steps of matrix-core work.
+        C2 a[kDepthHN][2], b[kDepthHN][2];
+        auto load = [&](int slot, int64_t k0) {
+            const int64_t kk = k0 + lk;
+            const bool kv = kk < ke;
+    #pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                a[slot][u] = (kv && ia[u] < M) ? A[(int64_t)ia[u] * lda + kk] : C2{0, 0};
+                b[slot][u] = (kv && jb[u] < N) ? B[(int64_t)jb[u] * ldb + kk] : C2{0, 0};
+            }
+        };
+        auto step = [&](int slot) {
+    #pragma unroll
+            for (int u = 0; u < 2; ++u)
+    #pragma unroll
+                for (int w = 0; w < 2; ++w) {
+                    // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
+                    re[u][w] = mfma(a[slot][u].x, b[slot][w].x, re[u][w]);
+                    re[u][w] = mfma(a[slot][u].y, b[slot][w].y, re[u][w]);
+                    im[u][w] = mfma(a[slot][u].x, b[slot][w].y, im[u][w]);
+                    im[u][w] = mfma(-a[slot][u].y, b[slot][w].x, im[u][w]);
+                }
+        };
+    #pragma unroll
+        for (int d = 0; d < kDepthHN - 1; ++d) load(d, kb + 4 * d);
+        for (int64_t k0 = kb; k0 < ke; k0 += 4 * kDepthHN) {
+    #pragma unroll
+            for (int d = 0; d < kDepthHN; ++d) {
+                load((d + kDepthHN - 1) % kDepthHN, k0 + 4 * (d + kDepthHN - 1));
+                step(d);
+            }
         }
-    const int ia[2] = {i0 + l16, i0 + 16 + l16};
-    const int jb[2] = {j0 + l16, j0 + 16 + l16};
-    // Register prefetch ring: the operands of k-step s + kDepthHN - 1 are
-    // requested before the products of step s, so that their latency
-    // overlaps kDepthHN - 1 steps of matrix-core work.
-    C2 a[kDepthHN][2], b[kDepthHN][2];
-    auto load = [&](int slot, int64_t k0) {
-        const int64_t kk = k0 + lk;
-        const bool kv = kk < ke;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            a[slot][u] = (kv && ia[u] < M) ? A[(int64_t)ia[u] * lda + kk] : C2{0, 0};
-            b[slot][u] = (kv && jb[u] < N) ? B[(int64_t)jb[u] * ldb + kk] : C2{0, 0};
-        }
-    };
-    auto step = [&](int slot) {
-#pragma unroll
+        double2 *P = part + (size_t)split * M * N;
+    #pragma unroll
         for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int w = 0; w < 2; ++w) {
-                // conj(a) b = (ar br + ai bi) + i (ar bi - ai br)
-                re[u][w] = mfma(a[slot][u].x, b[slot][w].x, re[u][w]);
-                re[u][w] = mfma(a[slot][u].y, b[slot][w].y, re[u][w]);
-                im[u][w] = mfma(a[slot][u].x, b[slot][w].y, im[u][w]);
-                im[u][w] = mfma(-a[slot][u].y, b[slot][w].x, im[u][w]);
-            }
-    };
-#pragma unroll
-    for (int d = 0; d < kDepthHN - 1; ++d) load(d, kb + 4 * d);
-    for (int64_t k0 = kb; k0 < ke; k0 += 4 * kDepthHN) {
-#pragma unroll
-        for (int d = 0; d < kDepthHN; ++d) {
-            load((d + kDepthHN - 1) % kDepthHN, k0 + 4 * (d + kDepthHN - 1));
-            step(d);
-        }
+    #pragma unroll
+            for (int w = 0; w < 2; ++w)
+    #pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + u * 16 + Mma<C2>::row(lk, v);
+                    const int j = j0 + w * 16 + l16;
+                    if (i < M && j < N) P[(size_t)j * M + i] = make_double2(re[u][w][v], im[u][w][v]);
+                }
     }
-    double2 *P = part + (size_t)split * M * N;
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int w = 0; w < 2; ++w)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = i0 + u * 16 + Mma<C2>::row(lk, v);
-                const int j = j0 + w * 16 + l16;
-                if (i < M && j < N) P[(size_t)j * M + i] = make_double2(re[u][w][v], im[u][w][v]);
-            }
 }
 
 // C[i][j] = dscale_i * sum_s part[s][j][i]; quad_j = sum_i dscale_i |sum_s part|^2.
@@ -199,81 +200,83 @@ k_gemm_hn_reduce(int M, int N, int nsplit, const double2 *__restrict__ part, CO 
 // C[g][n] (+)= sum_k A[g][k] B[k][n]; matrix-core rows = n, columns = g.
 template <class C2>
 __global__ void __launch_bounds__(256)
-k_gemm_nn(int64_t M, int N, int K, int tn, const C2 *__restrict__ A, int64_t lda, const C2 *__restrict__ B,
-          int64_t ldb, C2 *__restrict__ C, int64_t ldc, int accumulate)
+k_gemm_nn(int64_t M, int N, int K, int bn, int64_t units, const C2 *__restrict__ A, int64_t lda,
+          const C2 *__restrict__ B, int64_t ldb, C2 *__restrict__ C, int64_t ldc, int accumulate)
 {
     using Acc = typename Mma<C2>::Acc;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // work index: the tn column tiles of one row tile (which share its rows
-    // of A) are adjacent
-    const int64_t w = xcd_work_index(blockIdx.x, (int64_t)gridDim.x);
-    const int64_t g0 = (w / tn) * kTile + (wave & 1) * 32;
-    const int n0 = (int)(w % tn) * kTile + (wave >> 1) * 32;
-    if (g0 >= M || n0 >= N) return;  // block outside C (no barriers in this kernel)
-    const int l16 = lane & 15, lk = lane >> 4;
-    Acc re[2][2], im[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            re[a][b] = Acc{0, 0, 0, 0};
-            im[a][b] = Acc{0, 0, 0, 0};
-        }
-    const int nb_[2] = {n0 + l16, n0 + 16 + l16};
-    const int64_t gg[2] = {g0 + l16, g0 + 16 + l16};
-    // register prefetch ring, as in k_gemm_hn_part
-    C2 x[kDepthNN][2], y[kDepthNN][2];
-    auto load = [&](int slot, int k0) {
-        const int kk = k0 + lk;
-        const bool kv = kk < K;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            x[slot][u] = (kv && nb_[u] < N) ? B[(int64_t)nb_[u] * ldb + kk] : C2{0, 0};
-            y[slot][u] = (kv && gg[u] < M) ? A[(int64_t)kk * lda + gg[u]] : C2{0, 0};
-        }
-    };
-    auto step = [&](int slot) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int w = 0; w < 2; ++w) {
-                // (x y): re = xr yr - xi yi, im = xr yi + xi yr
-                re[u][w] = mfma(x[slot][u].x, y[slot][w].x, re[u][w]);
-                re[u][w] = mfma(-x[slot][u].y, y[slot][w].y, re[u][w]);
-                im[u][w] = mfma(x[slot][u].x, y[slot][w].y, im[u][w]);
-                im[u][w] = mfma(x[slot][u].y, y[slot][w].x, im[u][w]);
+    // work unit = one 32 x 32 block of C, done by one wavefront; the bn
+    // column blocks of one row block (which share its rows of A) are
+    // adjacent units
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t unit = xcd_work_index(blockIdx.x, gridDim.x) * 4 + wave; unit < units; unit += nw) {
+        const int64_t g0 = (unit / bn) * 32;
+        const int n0 = (int)(unit % bn) * 32;
+        const int l16 = lane & 15, lk = lane >> 4;
+        Acc re[2][2], im[2][2];
+    #pragma unroll
+        for (int a = 0; a < 2; ++a)
+    #pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                re[a][b] = Acc{0, 0, 0, 0};
+                im[a][b] = Acc{0, 0, 0, 0};
             }
-    };
-#pragma unroll
-    for (int d = 0; d < kDepthNN - 1; ++d) load(d, 4 * d);
-    for (int k0 = 0; k0 < K; k0 += 4 * kDepthNN) {
-#pragma unroll
-        for (int d = 0; d < kDepthNN; ++d) {
-            load((d + kDepthNN - 1) % kDepthNN, k0 + 4 * (d + kDepthNN - 1));
-            step(d);
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int w = 0; w < 2; ++w)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int n = n0 + u * 16 + Mma<C2>::row(lk, v);
-                const int64_t g = g0 + w * 16 + l16;
-                if (n < N && g < M) {
-                    C2 *c = C + (int64_t)n * ldc + g;
-                    C2 r;
-                    r.x = re[u][w][v];
-                    r.y = im[u][w][v];
-                    if (accumulate) {
-                        const C2 o = *c;
-                        r.x += o.x;
-                        r.y += o.y;
-                    }
-                    *c = r;
+        const int nb_[2] = {n0 + l16, n0 + 16 + l16};
+        const int64_t gg[2] = {g0 + l16, g0 + 16 + l16};
+        // register prefetch ring, as in k_gemm_hn_part
+        C2 x[kDepthNN][2], y[kDepthNN][2];
+        auto load = [&](int slot, int k0) {
+            const int kk = k0 + lk;
+            const bool kv = kk < K;
+    #pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                x[slot][u] = (kv && nb_[u] < N) ? B[(int64_t)nb_[u] * ldb + kk] : C2{0, 0};
+                y[slot][u] = (kv && gg[u] < M) ? A[(int64_t)kk * lda + gg[u]] : C2{0, 0};
+            }
+        };
+        auto step = [&](int slot) {
+    #pragma unroll
+            for (int u = 0; u < 2; ++u)
+    #pragma unroll
+                for (int w = 0; w < 2; ++w) {
+                    // (x y): re = xr yr - xi yi, im = xr yi + xi yr
+                    re[u][w] = mfma(x[slot][u].x, y[slot][w].x, re[u][w]);
+                    re[u][w] = mfma(-x[slot][u].y, y[slot][w].y, re[u][w]);
+                    im[u][w] = mfma(x[slot][u].x, y[slot][w].y, im[u][w]);
+                    im[u][w] = mfma(x[slot][u].y, y[slot][w].x, im[u][w]);
                 }
+        };
+    #pragma unroll
+        for (int d = 0; d < kDepthNN - 1; ++d) load(d, 4 * d);
+        for (int k0 = 0; k0 < K; k0 += 4 * kDepthNN) {
+    #pragma unroll
+            for (int d = 0; d < kDepthNN; ++d) {
+                load((d + kDepthNN - 1) % kDepthNN, k0 + 4 * (d + kDepthNN - 1));
+                step(d);
             }
+        }
+    #pragma unroll
+        for (int u = 0; u < 2; ++u)
+    #pragma unroll
+            for (int w = 0; w < 2; ++w)
+    #pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int n = n0 + u * 16 + Mma<C2>::row(lk, v);
+                    const int64_t g = g0 + w * 16 + l16;
+                    if (n < N && g < M) {
+                        C2 *c = C + (int64_t)n * ldc + g;
+                        C2 r;
+                        r.x = re[u][w][v];
+                        r.y = im[u][w][v];
+                        if (accumulate) {
+                            const C2 o = *c;
+                            r.x += o.x;
+                            r.y += o.y;
+                        }
+                        *c = r;
+                    }
+                }
+    }
 }
 
 // One work-group per projector: beta_p(G) for every sphere point, then the
@@ -332,13 +335,10 @@ hipError_t gemm_hn_t(hipStream_t s, int M, int N, int64_t K, const C2 *A, int64_
                      C2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale, double *quad)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
-    const int tm = (M + kTile - 1) / kTile, tn = (N + kTile - 1) / kTile;
-    // as many splits as fit in one round of kSplitTarget work-groups (two
-    // resident per compute unit): a last, partly filled round would take
-    // as long as a full one
-    int64_t nsplit = kSplitTarget / (tm * tn);
-    // at least one prefetch ring of k per split: small products (few output
-    // tiles, short contraction) still spread over many work-groups
+    const int bm = (M + 31) / 32, bn = (N + 31) / 32;
+    // about one unit per wavefront slot of the chip, each split at least one
+    // prefetch ring of k long, within the partial buffer
+    int64_t nsplit = kWaveSlots / ((int64_t)bm * bn);
     const int64_t kmax = (K + 4 * kDepthHN - 1) / (4 * kDepthHN);
     if (nsplit > kmax) nsplit = kmax;
     if (nsplit < 1) nsplit = 1;
@@ -349,9 +349,11 @@ hipError_t gemm_hn_t(hipStream_t s, int M, int N, int64_t K, const C2 *A, int64_
     kchunk = (kchunk + 3) / 4 * 4;
     nsplit = (K + kchunk - 1) / kchunk;
     if (nsplit < 1) nsplit = 1;
+    const int64_t units = (int64_t)bm * bn * nsplit;
+    const unsigned wgs = (unsigned)std::min<int64_t>((units + 3) / 4, kWaveSlots / 4);
     prof_mark(PARO_K_GEMM_HN, s, true);
-    hipLaunchKernelGGL((k_gemm_hn_part<C2>), dim3((unsigned)(tm * tn * nsplit)), dim3(256), 0, s, M, N, K, kchunk, tm,
-                       tn, (int)nsplit, A, lda, B, ldb, part);
+    hipLaunchKernelGGL((k_gemm_hn_part<C2>), dim3(wgs), dim3(256), 0, s, M, N, K, kchunk, bm, bn, units, A, lda, B,
+                       ldb, part);
     prof_mark(PARO_K_GEMM_HN, s, false);
     hipLaunchKernelGGL((k_gemm_hn_reduce<C2>), dim3(N), dim3(256), 0, s, M, N, (int)nsplit, part, C, ldc, dscale,
                        quad);
@@ -363,10 +365,11 @@ hipError_t gemm_nn_t(hipStream_t s, int64_t M, int N, int K, const C2 *A, int64_
                      C2 *C, int64_t ldc, bool accumulate)
 {
     if (M <= 0 || N <= 0) return hipSuccess;
-    const int tn = (N + kTile - 1) / kTile;
-    dim3 grid((unsigned)((M + kTile - 1) / kTile * tn));
+    const int bn = (N + 31) / 32;
+    const int64_t units = (M + 31) / 32 * bn;
+    dim3 grid((unsigned)std::min<int64_t>((units + 3) / 4, kWaveSlots / 4));
     prof_mark(PARO_K_GEMM_NN, s, true);
-    hipLaunchKernelGGL((k_gemm_nn<C2>), grid, dim3(256), 0, s, M, N, K, tn, A, lda, B, ldb, C, ldc,
+    hipLaunchKernelGGL((k_gemm_nn<C2>), grid, dim3(256), 0, s, M, N, K, bn, units, A, lda, B, ldb, C, ldc,
                        accumulate ? 1 : 0);
     prof_mark(PARO_K_GEMM_NN, s, false);
     return hipGetLastError();

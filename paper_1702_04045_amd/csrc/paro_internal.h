@@ -11,7 +11,6 @@
 namespace paro {
 
 constexpr int kMaxBandsPerChunk = 64;  // bands per sphere->stick->plane pass (stick buffer size)
-constexpr int kSplitTarget = 512;      // aim for about this many split-K work-groups
 constexpr int kPartSplits = 64;        // split-K partials the workspaces hold per output element
 constexpr int kMaxParts = 512;         // partial sums per band per reduction
 constexpr int kDensityBandsPerGroup = 8;  // bands one work-group of the density kernel sums
