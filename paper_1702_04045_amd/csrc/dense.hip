@@ -266,36 +266,48 @@ k_tridiag(int m, double2 *__restrict__ A, double *__restrict__ d, double *__rest
     tridiag_run(m, A, d, e, tau, sv, sy, sw, partial);
 }
 
-// The same reduction with the matrix in LDS for the whole sweep
-// (m <= kTridiagLdsMax), by kTriWaves wavefronts.  Lane l of every
-// wavefront holds rows l and l + 64 of the vectors x, v, y, w; the scalars
-// of each Householder vector and the reductions over rows are computed
-// redundantly and identically by every wavefront (shuffle trees, lane 0
-// broadcasts), so they need no barrier.  The column loops of y = A v and of
-// the rank-2 update are split over the wavefronts (columns j = wave,
-// wave + kTriWaves, ...); the partial y of each wavefront is added in
-// wavefront order.  Four work-group barriers per column.
-// Dynamic LDS: m^2 + (2 + kTriWaves) m complex values.
-constexpr int kTriWaves = 8;
+// The same reduction by W wavefronts, the matrix either copied to LDS for
+// the whole sweep (LDS, m <= kTridiagLdsMax) or updated in place in global
+// memory (m <= 64 R).  Lane l of every wavefront holds rows l + 64 r
+// (r < R) of the vectors x, v, y, w; the scalars of each Householder vector
+// and the reductions over rows are computed redundantly and identically by
+// every wavefront (shuffle trees, lane 0 broadcasts), so they need no
+// barrier.  The column loops of y = A v and of the rank-2 update are split
+// over the wavefronts (columns j = wave, wave + W, ...); the partial y of
+// each wavefront is added in wavefront order.  Four work-group barriers
+// per column.  In LDS eight wavefronts suffice; in global memory sixteen,
+// with eight columns' loads in flight per wavefront, cover more of the
+// cache latency of the column loops.  Dynamic LDS: (LDS ? m^2 : 0) +
+// (2 + W) m complex values.
+constexpr int kTriWavesLds = 8, kTriWavesGlobal = 16;
 constexpr int kTridiagLdsMax = 92;
-static size_t tridiag_lds_bytes(int m) { return sizeof(double2) * ((size_t)m * m + (2 + kTriWaves) * (size_t)m); }
+constexpr int kTridiagRowsMax = 5;  // rows per lane of the global-memory variant (m <= 320)
+static size_t tridiag_lds_bytes(int m, bool lds)
+{
+    return sizeof(double2) * ((lds ? (size_t)m * m + (2 + kTriWavesLds) * (size_t)m
+                                   : (2 + kTriWavesGlobal) * (size_t)m));
+}
 
 // sum over the wavefront (fixed shuffle tree), the same value in every lane
 __device__ __forceinline__ double wave_sum_all(double v) { return __shfl(wave_sum(v), 0, 64); }
 
-__global__ void __launch_bounds__(64 * kTriWaves)
-k_tridiag_lds(int m, double2 *__restrict__ A, double *__restrict__ d, double *__restrict__ e,
-              double2 *__restrict__ tau)
+template <int R, bool LDS, int W>
+__global__ void __launch_bounds__(64 * W)
+k_tridiag_rows(int m, double2 *__restrict__ A, double *__restrict__ d, double *__restrict__ e,
+               double2 *__restrict__ tau)
 {
-    extern __shared__ double2 S[];
-    double2 *sv = S + m * m, *sw = sv + m, *yp = sw + m;  // yp: kTriWaves x m partial products
+    extern __shared__ double2 dyn[];
+    double2 *S = LDS ? dyn : A;
+    double2 *sv = LDS ? dyn + m * m : dyn, *sw = sv + m, *yp = sw + m;  // yp: W x m partial products
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int NT = 64 * kTriWaves;
+    constexpr int NT = 64 * W;
     const int mm = m * m;
-    for (int q = tid; q < mm; q += NT) S[q] = A[q];
-    __syncthreads();
+    if (LDS) {
+        for (int q = tid; q < mm; q += NT) S[q] = A[q];
+        __syncthreads();
+    }
     // hermitise (upper from the average with the lower triangle)
-    for (int jj = wave; jj < m; jj += kTriWaves) {
+    for (int jj = wave; jj < m; jj += W) {
         for (int ii = jj + 1 + lane; ii < m; ii += 64) {
             const double2 a = S[jj * m + ii], b = S[ii * m + jj];
             const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
@@ -305,15 +317,19 @@ k_tridiag_lds(int m, double2 *__restrict__ A, double *__restrict__ d, double *__
         if (lane == 0) S[jj * m + jj].y = 0.0;
     }
     __syncthreads();
-    const int i0 = lane, i1 = lane + 64;
     for (int k = 0; k + 1 < m; ++k) {
         const int n = m - k - 1;
         double2 *col = S + k * m + k + 1;  // x = A[k+1:, k]
-        const bool h0 = i0 < n, h1 = i1 < n;
-        const double2 x0 = h0 ? col[i0] : make_double2(0.0, 0.0), x1 = h1 ? col[i1] : make_double2(0.0, 0.0);
+        bool h[R];
+        double2 x[R], v[R], y[R], w[R];
         double xn = 0.0;
-        if (h0 && i0 > 0) xn += x0.x * x0.x + x0.y * x0.y;
-        if (h1) xn += x1.x * x1.x + x1.y * x1.y;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = lane + 64 * r;
+            h[r] = i < n;
+            x[r] = h[r] ? col[i] : make_double2(0.0, 0.0);
+            if (h[r] && i > 0) xn += x[r].x * x[r].x + x[r].y * x[r].y;
+        }
         xn = wave_sum_all(xn);
         const double2 alpha = col[0];
         double2 tk, sc;
@@ -331,8 +347,11 @@ k_tridiag_lds(int m, double2 *__restrict__ A, double *__restrict__ d, double *__
         }
         const double dk = S[k * m + k].x;
         // v = x / (alpha - beta), v_0 = 1, kept in column k below the diagonal
-        const double2 v0 = h0 ? (i0 == 0 ? make_double2(1.0, 0.0) : cmul_(x0, sc)) : make_double2(0.0, 0.0);
-        const double2 v1 = h1 ? cmul_(x1, sc) : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = lane + 64 * r;
+            v[r] = h[r] ? (i == 0 ? make_double2(1.0, 0.0) : cmul_(x[r], sc)) : make_double2(0.0, 0.0);
+        }
         __syncthreads();  // every wavefront has read column k
         if (wave == 0) {
             if (lane == 0) {
@@ -340,68 +359,68 @@ k_tridiag_lds(int m, double2 *__restrict__ A, double *__restrict__ d, double *__
                 e[k] = beta;
                 tau[k] = tk;
             }
-            if (h0) col[i0] = sv[i0] = v0;
-            if (h1) col[i1] = sv[i1] = v1;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (h[r]) col[lane + 64 * r] = sv[lane + 64 * r] = v[r];
         }
         __syncthreads();
         if (tk.x == 0.0 && tk.y == 0.0) continue;
         // partial y = A_trail v over this wavefront's columns, A_trail = A[k+1:, k+1:]
         double2 *At = S + (k + 1) * m + k + 1;
-        double2 y0 = make_double2(0.0, 0.0), y1 = make_double2(0.0, 0.0);
-#pragma unroll 4
-        for (int jj = wave; jj < n; jj += kTriWaves) {
-            const double2 vj = sv[jj];
-            if (h0) {
-                const double2 t = cmul_(At[jj * m + i0], vj);
-                y0.x += t.x;
-                y0.y += t.y;
-            }
-            if (h1) {
-                const double2 t = cmul_(At[jj * m + i1], vj);
-                y1.x += t.x;
-                y1.y += t.y;
-            }
-        }
-        if (h0) yp[wave * m + i0] = y0;
-        if (h1) yp[wave * m + i1] = y1;
-        __syncthreads();
-        y0 = y1 = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int q = 0; q < kTriWaves; ++q) {
-            if (h0) {
-                y0.x += yp[q * m + i0].x;
-                y0.y += yp[q * m + i0].y;
-            }
-            if (h1) {
-                y1.x += yp[q * m + i1].x;
-                y1.y += yp[q * m + i1].y;
-            }
+        for (int r = 0; r < R; ++r) y[r] = make_double2(0.0, 0.0);
+#pragma unroll 8
+        for (int jj = wave; jj < n; jj += W) {
+            const double2 vj = sv[jj];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (h[r]) {
+                    const double2 t = cmul_(At[jj * m + lane + 64 * r], vj);
+                    y[r].x += t.x;
+                    y[r].y += t.y;
+                }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (h[r]) yp[wave * m + lane + 64 * r] = y[r];
+        __syncthreads();
+        double crp = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            y[r] = make_double2(0.0, 0.0);
+            if (h[r])
+                for (int q = 0; q < W; ++q) {
+                    y[r].x += yp[q * m + lane + 64 * r].x;
+                    y[r].y += yp[q * m + lane + 64 * r].y;
+                }
+            crp += cjmul(v[r], y[r]).x;
         }
         // w = tau y - (|tau|^2 / 2) Re(v^H y) v
-        const double cr = wave_sum_all(cjmul(v0, y0).x + cjmul(v1, y1).x);
+        const double cr = wave_sum_all(crp);
         const double t2 = 0.5 * (tk.x * tk.x + tk.y * tk.y) * cr;
-        const double2 ty0 = cmul_(tk, y0), ty1 = cmul_(tk, y1);
-        const double2 w0 = make_double2(ty0.x - t2 * v0.x, ty0.y - t2 * v0.y);
-        const double2 w1 = make_double2(ty1.x - t2 * v1.x, ty1.y - t2 * v1.y);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double2 ty = cmul_(tk, y[r]);
+            w[r] = make_double2(ty.x - t2 * v[r].x, ty.y - t2 * v[r].y);
+        }
         if (wave == 0) {
-            if (h0) sw[i0] = w0;
-            if (h1) sw[i1] = w1;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (h[r]) sw[lane + 64 * r] = w[r];
         }
         __syncthreads();
         // A_trail -= w v^H + v w^H over this wavefront's columns
-#pragma unroll 4
-        for (int jj = wave; jj < n; jj += kTriWaves) {
+#pragma unroll 8
+        for (int jj = wave; jj < n; jj += W) {
             const double2 vj = sv[jj], wj = sw[jj];
-            if (h0) {
-                const double2 a = cjmul(vj, w0), b = cjmul(wj, v0);  // w_i conj(v_j), v_i conj(w_j)
-                double2 c = At[jj * m + i0];
-                At[jj * m + i0] = make_double2(c.x - (a.x + b.x), c.y - (a.y + b.y));
-            }
-            if (h1) {
-                const double2 a = cjmul(vj, w1), b = cjmul(wj, v1);
-                double2 c = At[jj * m + i1];
-                At[jj * m + i1] = make_double2(c.x - (a.x + b.x), c.y - (a.y + b.y));
-            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (h[r]) {
+                    const double2 a = cjmul(vj, w[r]), b = cjmul(wj, v[r]);  // w_i conj(v_j), v_i conj(w_j)
+                    double2 *c = At + jj * m + lane + 64 * r;
+                    const double2 o = *c;
+                    *c = make_double2(o.x - (a.x + b.x), o.y - (a.y + b.y));
+                }
         }
         __syncthreads();
     }
@@ -410,7 +429,8 @@ k_tridiag_lds(int m, double2 *__restrict__ A, double *__restrict__ d, double *__
         e[m - 1] = 0.0;
         tau[m - 1] = make_double2(0.0, 0.0);
     }
-    for (int q = tid; q < mm; q += NT) A[q] = S[q];
+    if (LDS)
+        for (int q = tid; q < mm; q += NT) A[q] = S[q];
 }
 
 // 1 / x: hardware reciprocal refined by one Newton step (about 1 ulp);
@@ -759,11 +779,22 @@ static hipError_t eig_pipeline(hipStream_t st, int m, double2 *Hh, const DenseSc
                                int nout, double2 *Yout, bool vectors)
 {
     static const hipError_t lds_attr = hipFuncSetAttribute(
-        reinterpret_cast<const void *>(k_tridiag_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)tridiag_lds_bytes(kTridiagLdsMax));
+        reinterpret_cast<const void *>(k_tridiag_rows<2, true, kTriWavesLds>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)tridiag_lds_bytes(kTridiagLdsMax, true));
+    const dim3 tl(64 * kTriWavesLds), tg(64 * kTriWavesGlobal);
+    const size_t gb = tridiag_lds_bytes(m, false);
     if (m <= kTridiagLdsMax && lds_attr == hipSuccess)
-        hipLaunchKernelGGL(k_tridiag_lds, dim3(1), dim3(64 * kTriWaves), tridiag_lds_bytes(m), st, m, Hh, s.d, s.e,
-                           s.tau);
+        hipLaunchKernelGGL((k_tridiag_rows<2, true, kTriWavesLds>), dim3(1), tl, tridiag_lds_bytes(m, true), st, m,
+                           Hh, s.d, s.e, s.tau);
+    else if (m <= 128)
+        hipLaunchKernelGGL((k_tridiag_rows<2, false, kTriWavesGlobal>), dim3(1), tg, gb, st, m, Hh, s.d, s.e, s.tau);
+    else if (m <= 192)
+        hipLaunchKernelGGL((k_tridiag_rows<3, false, kTriWavesGlobal>), dim3(1), tg, gb, st, m, Hh, s.d, s.e, s.tau);
+    else if (m <= 256)
+        hipLaunchKernelGGL((k_tridiag_rows<4, false, kTriWavesGlobal>), dim3(1), tg, gb, st, m, Hh, s.d, s.e, s.tau);
+    else if (m <= 64 * kTridiagRowsMax)
+        hipLaunchKernelGGL((k_tridiag_rows<kTridiagRowsMax, false, kTriWavesGlobal>), dim3(1), tg, gb, st, m, Hh, s.d,
+                           s.e, s.tau);
     else
         hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(kBig), 0, st, m, Hh, s.d, s.e, s.tau);
     hipLaunchKernelGGL(k_tri_eigvals, dim3(m), dim3(64), 0, st, m, s.d, s.e, s.lam, eps_out, nout);
