@@ -98,6 +98,107 @@ k_rr_chol(int m, const double2 *__restrict__ gram, int hs, double2 *__restrict__
     }
 }
 
+// The same Cholesky by W wavefronts for m <= 64 R: lane l of every
+// wavefront holds rows j + 1 + l + 64 r of the current column j (scaled by
+// 1 / L_jj, computed identically by every wavefront, so no barrier is
+// needed for the pivot); wavefront 0 writes the column back and to LDS; the
+// columns of the trailing update are split over the wavefronts (columns
+// j + 1 + wave, j + 1 + wave + W, ...), rows i >= l of column l.  Two
+// barriers per column.  Dynamic LDS: m complex values.
+template <int R, int W>
+__global__ void __launch_bounds__(64 * W)
+k_rr_chol_rows(int m, const double2 *__restrict__ gram, int hs, double2 *__restrict__ L, double2 *__restrict__ X,
+               int32_t *__restrict__ fail, int32_t *__restrict__ status)
+{
+    __shared__ double red[W];
+    extern __shared__ double2 sa[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int mm = m * m;
+    double dmax = 0.0;
+    for (int jj = wave; jj < m; jj += W)
+        for (int ii = lane; ii < m; ii += 64) {
+            const int q = jj * m + ii;
+            const double2 a = gram[q], b = gram[ii * m + jj];
+            L[q] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+            if (ii == jj) dmax = fmax(dmax, a.x);
+            if (hs) {
+                const double2 c = gram[mm + q], d = gram[mm + ii * m + jj];
+                X[q] = make_double2(0.5 * (c.x + d.x), 0.5 * (c.y - d.y));
+            }
+        }
+    dmax = block_max<64 * W>(dmax, red);  // ends with a barrier: L is complete
+    int failed = 0;
+    for (int j = 0; j < m; ++j) {
+        const double dj = L[j * m + j].x;
+        if (!(dj > 1e-14 * dmax)) {
+            failed = 1;
+            break;
+        }
+        const double ljj = sqrt(dj), inv = 1.0 / ljj;
+        bool h[R];
+        double2 a[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = j + 1 + lane + 64 * r;
+            h[r] = i < m;
+            const double2 v = h[r] ? L[j * m + i] : make_double2(0.0, 0.0);
+            a[r] = make_double2(v.x * inv, v.y * inv);
+        }
+        __syncthreads();  // every wavefront has read column j
+        if (wave == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = j + 1 + lane + 64 * r;
+                if (h[r]) L[j * m + i] = sa[i] = a[r];
+            }
+            if (lane == 0) L[j * m + j] = make_double2(ljj, 0.0);
+        }
+        __syncthreads();
+        // L[i][l] -= L[i][j] conj(L[l][j]) for l > j, i >= l
+#pragma unroll 4
+        for (int l = j + 1 + wave; l < m; l += W) {
+            const double2 b = sa[l];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = j + 1 + lane + 64 * r;
+                if (h[r] && i >= l) {
+                    double2 *c = L + l * m + i;
+                    const double2 o = *c;
+                    *c = make_double2(o.x - (a[r].x * b.x + a[r].y * b.y), o.y - (a[r].y * b.x - a[r].x * b.y));
+                }
+            }
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    for (int jj = wave; jj < m; jj += W)
+        for (int ii = lane; ii < jj; ii += 64) L[jj * m + ii] = make_double2(0.0, 0.0);
+    if (tid == 0) {
+        fail[0] = failed;
+        if (failed) atomicOr(status, PARO_F_CHOL);
+    }
+}
+
+// Cholesky of the hermitised S (and hermitised Hs into X when hs): the
+// row-held variant up to m = 320, the first design beyond.
+static void launch_chol(hipStream_t st, int m, const double2 *gram, int hs, double2 *L, double2 *X, int32_t *fail,
+                        int32_t *status)
+{
+    constexpr int W = 16;
+    const size_t sh = sizeof(double2) * (size_t)m;
+    const dim3 tb(64 * W);
+    if (m <= 128)
+        hipLaunchKernelGGL((k_rr_chol_rows<2, W>), dim3(1), tb, sh, st, m, gram, hs, L, X, fail, status);
+    else if (m <= 192)
+        hipLaunchKernelGGL((k_rr_chol_rows<3, W>), dim3(1), tb, sh, st, m, gram, hs, L, X, fail, status);
+    else if (m <= 256)
+        hipLaunchKernelGGL((k_rr_chol_rows<4, W>), dim3(1), tb, sh, st, m, gram, hs, L, X, fail, status);
+    else if (m <= 320)
+        hipLaunchKernelGGL((k_rr_chol_rows<5, W>), dim3(1), tb, sh, st, m, gram, hs, L, X, fail, status);
+    else
+        hipLaunchKernelGGL(k_rr_chol, dim3(1), dim3(kBig), 0, st, m, gram, hs, L, X, fail, status);
+}
+
 // One column per single-wave work-group.
 // mode 0: out = L^-1 b;  mode 1: out = L^-H b.
 // b = column j of src, or (transb) the conjugate of row j of src.
@@ -814,7 +915,7 @@ hipError_t launch_rr_dense(const Plan &pl, const Workspace &w, int m, int n_keep
     DenseScratch s = dense_scratch(w, m);
     double2 *L = w.dense[0], *X = w.dense[1], *Hh = w.dense[2], *Y = w.dense[3];
     const size_t colshm = (size_t)m * sizeof(double2);
-    hipLaunchKernelGGL(k_rr_chol, dim3(1), dim3(kBig), 0, st, m, w.gram, 1, L, X, s.fail, pl.status);
+    launch_chol(st, m, w.gram, 1, L, X, s.fail, pl.status);
     // X <- L^-1 Hs;  Hh <- L^-1 X^H = L^-1 Hs L^-H
     hipLaunchKernelGGL(k_trsm_col, dim3(m), dim3(64), colshm, st, m, L, X, 0, 0, X);
     hipLaunchKernelGGL(k_trsm_col, dim3(m), dim3(64), colshm, st, m, L, X, 1, 0, Hh);
@@ -848,8 +949,7 @@ hipError_t launch_shift_bound(const Plan &pl, const Workspace &w, double *sigma)
         hipError_t err = gemm_hn(st, np, np, pl.ng, pl.beta, pl.ldv, pl.beta, pl.ldv, w.gram, np, w.part,
                                  w.part_elems, nullptr, nullptr);
         if (err != hipSuccess) return err;
-        hipLaunchKernelGGL(k_rr_chol, dim3(1), dim3(kBig), 0, st, np, w.gram, 0, w.dense[0], w.dense[1], s.fail,
-                           pl.status);
+        launch_chol(st, np, w.gram, 0, w.dense[0], w.dense[1], s.fail, pl.status);
         hipLaunchKernelGGL(k_lhdl, dim3((np + 63) / 64, np), dim3(64), 0, st, np, w.dense[0], pl.dkb, w.dense[2]);
         eig_pipeline(st, np, w.dense[2], s, nullptr, 0, nullptr, false);
     }
