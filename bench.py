@@ -362,7 +362,20 @@ def main():
     fl_d = density_plane_flops(N, ncol) * pl.grid[2] * np.mean(chunks)
     bytes_d = float(np.mean([16.0 * pl.n_sticks * pl.grid[2] * cb + 8.0 * (-(-cb // 8)) * N ** 3
                              for cb in chunks]))
+    # projector gradient of the same block (two matrix-core products with
+    # the 128 projectors and G-weighted projectors, 4 x 8 N_G N_p flops per band)
+    pl.projector_gradient(psi)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        pl.projector_gradient(psi)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_pg = e0.elapsed_time(e1) / 10
+    fl_pg = 4 * 8.0 * pl.ng * pl.n_proj * nb
     density = {"bands": nb, "ms_per_call": ms_dens, "calls_per_s": 1000.0 / ms_dens,
+               "projector_gradient": {"ms_per_call": ms_pg, "tflops": fl_pg / (ms_pg * 1e-3) / 1e12,
+                                      "frac_fp64_matrix_peak": fl_pg / (ms_pg * 1e-3) / PEAK_FP64_VALU},
                "roofline": {"kernel": "k_plane_density<96> (z-plane stage: inverse n2/n1 FFTs, w |psi|^2)",
                             "bound": "alu", "achieved": fl_d / (avg_d * 1e-3) / 1e12,
                             "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
