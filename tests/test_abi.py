@@ -156,3 +156,19 @@ def test_workload_inputs_are_reproducible():
     assert np.array_equal(a["positions"], b["positions"])
     assert len(a["projectors"]) == 128
     assert np.array_equal(synth.trial_block(100, 4, 3), synth.trial_block(100, 4, 3))
+
+
+def test_batched_workload_shapes(P):
+    """The uneven 24-cell workload: draws inside the stated ranges, each grid the
+    smallest supported length >= 4 n_max + 1 of the cell's sphere (the library's
+    own enumeration), reproducible from the seed."""
+    specs = synth.batch_specs(0)
+    assert len(specs) == 24 and specs == synth.batch_specs(0)
+    for sp in specs:
+        assert 8.0 <= sp.a <= 18.0 and 8.0 <= sp.ecut <= 20.0
+        assert 8 <= sp.n_bands <= 96 and 4 <= sp.n_atoms <= 24 and sp.projectors
+        mil, nmax = P.sphere_enumerate(sp.cell, sp.ecut)
+        need = 4 * int(nmax.max()) + 1
+        assert sp.grid >= need and all(g < need for g in synth.FFT_LENGTHS if g < sp.grid)
+        assert len(mil) >= sp.n_bands
+    assert len({sp.grid for sp in specs}) >= 4  # uneven
