@@ -919,7 +919,8 @@ hipError_t launch_rr_dense(const Plan &pl, const Workspace &w, int m, int n_keep
     // X <- L^-1 Hs;  Hh <- L^-1 X^H = L^-1 Hs L^-H
     hipLaunchKernelGGL(k_trsm_col, dim3(m), dim3(64), colshm, st, m, L, X, 0, 0, X);
     hipLaunchKernelGGL(k_trsm_col, dim3(m), dim3(64), colshm, st, m, L, X, 1, 0, Hh);
-    eig_pipeline(st, m, Hh, s, eps_out, n_keep, Y, true);
+    hipError_t e = eig_pipeline(st, m, Hh, s, eps_out, n_keep, Y, true);
+    if (e != hipSuccess) return e;
     // C = L^-H Y
     hipLaunchKernelGGL(k_trsm_col, dim3(m), dim3(64), colshm, st, m, L, Y, 0, 1, C);
     return hipGetLastError();
@@ -951,7 +952,8 @@ hipError_t launch_shift_bound(const Plan &pl, const Workspace &w, double *sigma)
         if (err != hipSuccess) return err;
         launch_chol(st, np, w.gram, 0, w.dense[0], w.dense[1], s.fail, pl.status);
         hipLaunchKernelGGL(k_lhdl, dim3((np + 63) / 64, np), dim3(64), 0, st, np, w.dense[0], pl.dkb, w.dense[2]);
-        eig_pipeline(st, np, w.dense[2], s, nullptr, 0, nullptr, false);
+        err = eig_pipeline(st, np, w.dense[2], s, nullptr, 0, nullptr, false);
+        if (err != hipSuccess) return err;
     }
     hipLaunchKernelGGL(k_shift_final, dim3(1), dim3(1), 0, st, s.vmin, s.lam, np > 0 ? 1 : 0, s.fail, sigma);
     return hipGetLastError();
