@@ -535,16 +535,21 @@ int32_t run_cells(std::vector<CellRun> &cells)
         return PARO_OK;
     };
     for (;;) {
-        bool left = false;
+        bool left = false, moved = false;
+        int waiting = -1;
         for (int i = 0; i < n; ++i) {
             CellRun &c = cells[i];
             if (phase[i] == Phase::Done) continue;
             left = true;
             if (phase[i] == Phase::WaitConv || phase[i] == Phase::WaitSolve) {
                 const hipError_t q = hipEventQuery(events.ev[i]);
-                if (q == hipErrorNotReady) continue;
+                if (q == hipErrorNotReady) {
+                    if (waiting < 0) waiting = i;
+                    continue;
+                }
                 PARO_HIP_TRY(q);
             }
+            moved = true;
             int32_t rc = PARO_OK;
             switch (phase[i]) {
             case Phase::Start:
@@ -594,6 +599,9 @@ int32_t run_cells(std::vector<CellRun> &cells)
             if (rc) return rc;
         }
         if (!left) break;
+        // every cell is waiting for the GPU: block on the first one rather
+        // than spin (the others' work continues meanwhile)
+        if (!moved && waiting >= 0) PARO_HIP_TRY(hipEventSynchronize(events.ev[waiting]));
     }
     return PARO_OK;
 }
