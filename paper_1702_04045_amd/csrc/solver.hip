@@ -483,13 +483,20 @@ hipError_t enqueue_finish(CellRun &c, int it)
 // launches is the same as when it runs alone.
 int32_t run_cells(std::vector<CellRun> &cells)
 {
-    // per cell: sigma (double), the convergence flag, the band flags; 8-byte blocks
-    auto block = [](const CellRun &c) { return sizeof(double) + (sizeof(int32_t) * (2 + c.nb) + 7) / 8 * 8; };
-    size_t bytes = 0;
-    for (const CellRun &c : cells) bytes += block(c);
+    // Host decisions exist only with a tolerance or the adaptive shift;
+    // without them the loop only enqueues kernels (no host memory, events or
+    // waits), so a caller can capture it into a graph.
+    bool decide = false;
+    for (const CellRun &c : cells) decide = decide || c.o.tol_res > 0.0 || c.o.shift_mode == PARO_SHIFT_ADAPTIVE;
+    const int n = (int)cells.size();
     PinnedHost host;
-    PARO_HIP_TRY(hipHostMalloc(&host.p, bytes, hipHostMallocDefault));
-    {
+    EventSet events;
+    if (decide) {
+        // per cell: sigma (double), the convergence flag, the band flags; 8-byte blocks
+        auto block = [](const CellRun &c) { return sizeof(double) + (sizeof(int32_t) * (2 + c.nb) + 7) / 8 * 8; };
+        size_t bytes = 0;
+        for (const CellRun &c : cells) bytes += block(c);
+        PARO_HIP_TRY(hipHostMalloc(&host.p, bytes, hipHostMallocDefault));
         char *q = static_cast<char *>(host.p);
         for (CellRun &c : cells) {
             c.scur = reinterpret_cast<double *>(q);
@@ -497,11 +504,9 @@ int32_t run_cells(std::vector<CellRun> &cells)
             c.hflags = c.hconv + 2;
             q += block(c);
         }
+        events.ev.assign(n, nullptr);
+        for (int i = 0; i < n; ++i) PARO_HIP_TRY(hipEventCreateWithFlags(&events.ev[i], hipEventDisableTiming));
     }
-    const int n = (int)cells.size();
-    EventSet events;
-    events.ev.assign(n, nullptr);
-    for (int i = 0; i < n; ++i) PARO_HIP_TRY(hipEventCreateWithFlags(&events.ev[i], hipEventDisableTiming));
     for (CellRun &c : cells) {
         const Plan &pl = *c.pl;
         Workspace &w = c.w;

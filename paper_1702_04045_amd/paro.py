@@ -318,6 +318,24 @@ class Plan:
                                       C.byref(o), _ptr(st), ws, n, C.byref(done)), "paro_iterate")
         return dict(psi=psi, hpsi=hpsi, eps=eps, sigma=sigma, stats=st, n_done=int(done.value))
 
+    def capture_iterations(self, psi, hpsi, eps, n_outer, n_cg, sigma_lb, variant=L.VARIANT_PARO,
+                           precision=L.PREC_FP64):
+        """Capture n_outer fixed-shift outer iterations on (psi, hpsi, eps), in place and starting
+        from their current contents, into a torch CUDA graph; replaying it continues the
+        iteration.  With the fixed shift and no tolerance the library makes no host decision,
+        so the whole loop is device work.  Returns the torch.cuda.CUDAGraph."""
+        torch = _torch()
+        self._check_block(psi)
+        self.workspace(psi.shape[0])  # allocate outside the capture
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.graph(g, stream=s):
+            self.iterate(psi, n_outer, n_cg, sigma_lb, hpsi=hpsi, eps=eps, variant=variant,
+                         shift_mode=L.SHIFT_FIXED, initial_rr=False, tol_res=0.0, stats=False, precision=precision)
+        torch.cuda.current_stream(self.device).wait_stream(s)
+        return g
+
     def status(self):
         """Read and clear the sticky device status bits (synchronises)."""
         f = C.c_int32()

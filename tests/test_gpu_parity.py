@@ -453,3 +453,32 @@ def test_repeat_runs_are_bitwise_identical():
     b = pl.iterate(to_dev(x), 3, 8, s)
     assert (a["psi"] == b["psi"]).all().item()
     assert (a["eps"] == b["eps"]).all().item()
+
+
+@pytest.mark.parametrize("spec,variant", [(C0, 0), (TINY, 1)], ids=["c0_paro", "tiny_mparo"])
+def test_captured_outer_iterations_replay_like_eager_runs(spec, variant):
+    """Fixed-shift outer iterations captured into a graph: each of three replays,
+    with eager library work and synchronisations in between, equals the eager
+    run of as many iterations bitwise."""
+    torch = _torch()
+    c, v, h, pl = make_case(spec, 5)
+    nb = 8 if spec is C0 else 4
+    sigma = h.shift_bound()
+    x = synth.trial_block(h.ng, nb, 5)
+    st = pl.iterate(to_dev(x), 1, 6, sigma, variant=variant)
+    psi0, hpsi0, eps0 = st["psi"].clone(), st["hpsi"].clone(), st["eps"].clone()
+    psi, hpsi, eps = psi0.clone(), hpsi0.clone(), eps0.clone()
+    g = pl.capture_iterations(psi, hpsi, eps, 1, 6, sigma, variant=variant)
+    torch.cuda.synchronize()
+    psi.copy_(psi0)
+    hpsi.copy_(hpsi0)
+    eps.copy_(eps0)
+    other = to_dev(synth.trial_block(h.ng, 3, 6))
+    for k in range(1, 4):
+        g.replay()
+        torch.cuda.synchronize()
+        ref = pl.iterate(psi0.clone(), k, 6, sigma, hpsi=hpsi0.clone(), eps=eps0.clone(), variant=variant,
+                         initial_rr=False)
+        assert torch.equal(psi, ref["psi"]) and torch.equal(eps, ref["eps"]) and torch.equal(hpsi, ref["hpsi"]), k
+        pl.apply_h(other)  # eager work between replays
+        torch.cuda.synchronize()
