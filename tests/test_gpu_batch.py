@@ -49,9 +49,10 @@ def build(specs, seed0=40):
     return cells
 
 
-@pytest.mark.parametrize("variant,shift_mode,tol", [(0, 1, 0.0), (1, 1, 1e-7), (2, 0, 0.0)],
-                         ids=["paro_adaptive", "mparo_adaptive_tol", "mparo2_fixed"])
-def test_batch_is_bitwise_the_single_cell_runs(variant, shift_mode, tol):
+@pytest.mark.parametrize("variant,shift_mode,tol,precision", [(0, 1, 0.0, 0), (1, 1, 1e-7, 0), (2, 0, 0.0, 0),
+                                                               (1, 1, 0.0, 1)],
+                         ids=["paro_adaptive", "mparo_adaptive_tol", "mparo2_fixed", "mparo_mixed"])
+def test_batch_is_bitwise_the_single_cell_runs(variant, shift_mode, tol, precision):
     import paper_1702_04045_amd as P
     torch = _torch()
     cells = build(small_specs())
@@ -60,11 +61,13 @@ def test_batch_is_bitwise_the_single_cell_runs(variant, shift_mode, tol):
     nconv = [max(1, sp.n_bands // 2) for sp, *_ in cells]
     ref = []
     for (sp, c, v, pl, x), s, k in zip(cells, sig, nconv):
-        r = pl.iterate(to_dev(x), n_outer, 8, s, variant=variant, shift_mode=shift_mode, tol_res=tol, n_conv=k)
+        r = pl.iterate(to_dev(x), n_outer, 8, s, variant=variant, shift_mode=shift_mode, tol_res=tol, n_conv=k,
+                       precision=precision)
         ref.append(r)
     psis = [to_dev(x) for *_, x in cells]
     got = P.iterate_batch([c[3] for c in cells], psis, n_outer, 8, sig, variant=variant, shift_mode=shift_mode,
-                          tol_res=tol, n_conv=nconv, streams=[torch.cuda.Stream() for _ in range(3)], stats=True)
+                          tol_res=tol, n_conv=nconv, precision=precision,
+                          streams=[torch.cuda.Stream() for _ in range(3)], stats=True)
     torch.cuda.synchronize()
     for k, (r, g) in enumerate(zip(ref, got)):
         assert g["n_done"] == r["n_done"], k
