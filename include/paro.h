@@ -60,6 +60,8 @@ extern "C" {
 #define PARO_F_NEGCURV 1   /* PCG met p^H (H - sigma) p <= 0: sigma not below the spectrum */
 #define PARO_F_CHOL 2      /* Rayleigh-Ritz overlap matrix not positive definite */
 #define PARO_F_NAN 4       /* a NaN reached a PCG scalar */
+#define PARO_F_SYNC 8      /* a dense kernel spread over several work-groups waited longer than its
+                              limit for another work-group and stopped: its results are invalid */
 
 /* shift modes of paro_iterate */
 #define PARO_SHIFT_FIXED 0     /* sigma = sigma_lb every outer iteration */

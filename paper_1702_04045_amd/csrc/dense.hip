@@ -179,26 +179,6 @@ k_rr_chol_rows(int m, const double2 *__restrict__ gram, int hs, double2 *__restr
     }
 }
 
-// Cholesky of the hermitised S (and hermitised Hs into X when hs): the
-// row-held variant up to m = 320, the first design beyond.
-static void launch_chol(hipStream_t st, int m, const double2 *gram, int hs, double2 *L, double2 *X, int32_t *fail,
-                        int32_t *status)
-{
-    constexpr int W = 16;
-    const size_t sh = sizeof(double2) * (size_t)m;
-    const dim3 tb(64 * W);
-    if (m <= 128)
-        hipLaunchKernelGGL((k_rr_chol_rows<2, W>), dim3(1), tb, sh, st, m, gram, hs, L, X, fail, status);
-    else if (m <= 192)
-        hipLaunchKernelGGL((k_rr_chol_rows<3, W>), dim3(1), tb, sh, st, m, gram, hs, L, X, fail, status);
-    else if (m <= 256)
-        hipLaunchKernelGGL((k_rr_chol_rows<4, W>), dim3(1), tb, sh, st, m, gram, hs, L, X, fail, status);
-    else if (m <= 320)
-        hipLaunchKernelGGL((k_rr_chol_rows<5, W>), dim3(1), tb, sh, st, m, gram, hs, L, X, fail, status);
-    else
-        hipLaunchKernelGGL(k_rr_chol, dim3(1), dim3(kBig), 0, st, m, gram, hs, L, X, fail, status);
-}
-
 // One column per single-wave work-group.
 // mode 0: out = L^-1 b;  mode 1: out = L^-H b.
 // b = column j of src, or (transb) the conjugate of row j of src.
@@ -381,6 +361,7 @@ k_tridiag(int m, double2 *__restrict__ A, double *__restrict__ d, double *__rest
 // cache latency of the column loops.  Dynamic LDS: (LDS ? m^2 : 0) +
 // (2 + W) m complex values.
 constexpr int kTriWavesLds = 8, kTriWavesGlobal = 16;
+constexpr int kTriDistG = 16;  // work-groups of the multi-work-group tridiagonalisation
 constexpr int kTridiagLdsMax = 92;
 constexpr int kTridiagRowsMax = 5;  // rows per lane of the global-memory variant (m <= 320)
 static size_t tridiag_lds_bytes(int m, bool lds)
@@ -533,6 +514,355 @@ k_tridiag_rows(int m, double2 *__restrict__ A, double *__restrict__ d, double *_
     if (LDS)
         for (int q = tid; q < mm; q += NT) A[q] = S[q];
 }
+
+// The same reduction spread over kTriDistG work-groups (92 < m <= 352),
+// each holding the columns c = g, g + G, ... of the hermitised matrix in
+// its LDS for the whole sweep, so that the trailing updates read and write
+// LDS only.  Per column k: the owner of column k forms the Householder
+// vector and publishes it (with tau) in a global buffer behind a flag;
+// every work-group that owns a trailing column forms the partial
+// y = A v over its own columns and publishes it behind a counter; each then
+// adds the partials in work-group order, forms w and updates its own
+// columns.  The buffers alternate between even and odd columns: a buffer is
+// rewritten two columns later, after every reader has passed the next
+// column's exchange.  Every wait has a time limit; a work-group that
+// reaches it raises a global abort flag that ends every other wait, and
+// sets PARO_F_SYNC.  The launch is cooperative, so the work-groups are
+// resident together.  Dynamic LDS: (ceil(m / G) + 2) m + 1 complex values.
+constexpr int kTriDistThreads = 256;
+constexpr int kTriDistMin = 93, kTriDistMax = 352;
+constexpr long long kTriDistWaitTicks = 20000000;  // 0.2 s of the 100 MHz real-time counter
+
+static size_t tridiag_dist_lds_bytes(int m)
+{
+    return sizeof(double2) * (((size_t)(m + kTriDistG - 1) / kTriDistG + 2) * (size_t)m + 1);
+}
+
+// wait until *p >= target (thread 0 of the work-group); false on abort or time-out
+__device__ bool dist_wait(const int32_t *p, int target, int32_t *abortf, int32_t *status)
+{
+    const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+        if (__hip_atomic_load(abortf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        if ((long long)__builtin_amdgcn_s_memrealtime() - t0 > kTriDistWaitTicks) {
+            __hip_atomic_store(abortf, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (status) atomicOr(status, PARO_F_SYNC);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+__global__ void __launch_bounds__(kTriDistThreads)
+k_tridiag_dist(int m, double2 *__restrict__ A, double *__restrict__ d, double *__restrict__ e,
+               double2 *__restrict__ tau, double2 *__restrict__ vbuf, double2 *__restrict__ ypart,
+               int32_t *__restrict__ flags, int32_t *__restrict__ status)
+{
+    constexpr int G = kTriDistG, NT = kTriDistThreads;
+    extern __shared__ double2 dyn[];
+    __shared__ double red[NT / 64];
+    __shared__ int s_ok;
+    const int g = blockIdx.x, tid = threadIdx.x;
+    const int nl = (m - g + G - 1) / G;  // own columns c = g + G s, s < nl
+    // sv: v (and tau in slot m), sw: w
+    double2 *loc = dyn, *sv = loc + (size_t)((m + G - 1) / G) * m, *sw = sv + m + 1;
+    int32_t *vflag = flags, *ycnt = flags + m, *abortf = flags + 2 * m;
+    // own columns of the hermitised matrix: h_ic = (A_ic + conj(A_ci)) / 2, real diagonal
+    for (int sidx = 0; sidx < nl; ++sidx) {
+        const int c = g + G * sidx;
+        for (int i = tid; i < m; i += NT) {
+            const double2 a = A[(size_t)c * m + i], b = A[(size_t)i * m + c];
+            loc[(size_t)sidx * m + i] =
+                i == c ? make_double2(a.x, 0.0) : make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+        }
+    }
+    __syncthreads();
+    bool ok = true;
+    for (int k = 0; k + 1 < m && ok; ++k) {
+        const int n = m - k - 1;
+        double2 *vb = vbuf + (size_t)(k & 1) * (m + 1);
+        double2 *yb = ypart + (size_t)(k & 1) * G * m;
+        if (g == k % G) {
+            double2 *col = loc + (size_t)(k / G) * m;
+            double xn = 0.0;
+            for (int i = k + 2 + tid; i < m; i += NT) xn += col[i].x * col[i].x + col[i].y * col[i].y;
+            xn = block_sum<NT>(xn, red);
+            const double2 alpha = col[k + 1];
+            double2 tk, sc;
+            double beta;
+            if (xn == 0.0 && alpha.y == 0.0) {
+                tk = make_double2(0.0, 0.0);
+                beta = alpha.x;
+                sc = make_double2(0.0, 0.0);
+            } else {
+                const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn);
+                beta = alpha.x >= 0.0 ? -nrm : nrm;
+                tk = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+                const double ar = alpha.x - beta, ai = alpha.y, den = ar * ar + ai * ai;
+                sc = make_double2(ar / den, -ai / den);  // 1 / (alpha - beta)
+            }
+            for (int i = k + 1 + tid; i < m; i += NT) {
+                const double2 v = i == k + 1 ? make_double2(1.0, 0.0) : cmul_(col[i], sc);
+                col[i] = v;
+                vb[i] = v;
+            }
+            if (tid == 0) {
+                d[k] = col[k].x;
+                e[k] = beta;
+                tau[k] = tk;
+                vb[m] = tk;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                __threadfence();
+                __hip_atomic_store(&vflag[k], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (g + G * (nl - 1) <= k) break;  // no own column after k: this work-group is done
+        if (tid == 0) s_ok = dist_wait(&vflag[k], 1, abortf, status) ? 1 : 0;
+        __syncthreads();
+        if (!s_ok) {
+            ok = false;
+            break;
+        }
+        for (int i = k + 1 + tid; i <= m; i += NT) sv[i] = vb[i];  // v and, in slot m, tau
+        __syncthreads();
+        const double2 tk = sv[m];
+        if (tk.x == 0.0 && tk.y == 0.0) {
+            __syncthreads();
+            continue;
+        }
+        // partial y = sum over own columns c > k of A[:, c] v_c, rows k+1 .. m-1
+        const int i0 = k + 1 + tid, i1 = i0 + NT;
+        double2 y0 = make_double2(0.0, 0.0), y1 = make_double2(0.0, 0.0);
+        for (int sidx = (k + 1 - g + G - 1) / G; sidx < nl; ++sidx) {
+            const int c = g + G * sidx;
+            const double2 vc = sv[c];
+            const double2 *lc = loc + (size_t)sidx * m;
+            if (i0 < m) {
+                const double2 t = cmul_(lc[i0], vc);
+                y0.x += t.x;
+                y0.y += t.y;
+            }
+            if (i1 < m) {
+                const double2 t = cmul_(lc[i1], vc);
+                y1.x += t.x;
+                y1.y += t.y;
+            }
+        }
+        if (i0 < m) yb[(size_t)g * m + i0] = y0;
+        if (i1 < m) yb[(size_t)g * m + i1] = y1;
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence();
+            __hip_atomic_fetch_add(&ycnt[k], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            s_ok = dist_wait(&ycnt[k], n < G ? n : G, abortf, status) ? 1 : 0;
+        }
+        __syncthreads();
+        if (!s_ok) {
+            ok = false;
+            break;
+        }
+        // y: the partials of the work-groups that own a column after k, in work-group order
+        y0 = y1 = make_double2(0.0, 0.0);
+        for (int q = 0; q < G; ++q) {
+            if (n < G && ((q - (k + 1)) % G + G) % G >= n) continue;
+            if (i0 < m) {
+                const double2 t = yb[(size_t)q * m + i0];
+                y0.x += t.x;
+                y0.y += t.y;
+            }
+            if (i1 < m) {
+                const double2 t = yb[(size_t)q * m + i1];
+                y1.x += t.x;
+                y1.y += t.y;
+            }
+        }
+        const double2 v0 = i0 < m ? sv[i0] : make_double2(0.0, 0.0);
+        const double2 v1 = i1 < m ? sv[i1] : make_double2(0.0, 0.0);
+        // w = tau y - (|tau|^2 / 2) Re(v^H y) v
+        const double cr = block_sum<NT>(cjmul(v0, y0).x + cjmul(v1, y1).x, red);
+        const double t2 = 0.5 * (tk.x * tk.x + tk.y * tk.y) * cr;
+        if (i0 < m) {
+            const double2 ty = cmul_(tk, y0);
+            sw[i0] = make_double2(ty.x - t2 * v0.x, ty.y - t2 * v0.y);
+        }
+        if (i1 < m) {
+            const double2 ty = cmul_(tk, y1);
+            sw[i1] = make_double2(ty.x - t2 * v1.x, ty.y - t2 * v1.y);
+        }
+        __syncthreads();
+        // own columns c > k: A[:, c] -= w conj(v_c) + v conj(w_c)
+        for (int sidx = (k + 1 - g + G - 1) / G; sidx < nl; ++sidx) {
+            const int c = g + G * sidx;
+            const double2 vc = sv[c], wc = sw[c];
+            double2 *lc = loc + (size_t)sidx * m;
+            if (i0 < m) {
+                const double2 a = cjmul(vc, sw[i0]), b = cjmul(wc, v0);
+                lc[i0] = make_double2(lc[i0].x - (a.x + b.x), lc[i0].y - (a.y + b.y));
+            }
+            if (i1 < m) {
+                const double2 a = cjmul(vc, sw[i1]), b = cjmul(wc, v1);
+                lc[i1] = make_double2(lc[i1].x - (a.x + b.x), lc[i1].y - (a.y + b.y));
+            }
+        }
+        __syncthreads();
+    }
+    // own columns back to global memory (the Householder vectors below the diagonal)
+    for (int sidx = 0; sidx < nl; ++sidx) {
+        const int c = g + G * sidx;
+        for (int i = tid; i < m; i += NT) A[(size_t)c * m + i] = loc[(size_t)sidx * m + i];
+    }
+    if (g == (m - 1) % G && tid == 0) {
+        d[m - 1] = loc[(size_t)((m - 1) / G) * m + m - 1].x;
+        e[m - 1] = 0.0;
+        tau[m - 1] = make_double2(0.0, 0.0);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_fill_i32(int n, int32_t *__restrict__ p, int32_t v)
+{
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = v;
+}
+
+// The same Cholesky spread over kTriDistG work-groups (92 < m <= 352),
+// each holding the columns c = g, g + G, ... of the hermitised S in its LDS
+// for the whole factorisation.  Per column j the owner checks the pivot,
+// scales its column, writes it (final) to L in global memory and raises
+// the column's flag (2: the pivot failed); every work-group with a column
+// after j waits for the flag, reads column j of L and updates its own
+// columns.  Published columns are final, so no buffer is reused.  Waits
+// are time-limited as in k_tridiag_dist.  Cooperative launch.  Dynamic
+// LDS: (ceil(m / G) + 1) m complex values.
+__global__ void __launch_bounds__(kTriDistThreads)
+k_chol_dist(int m, const double2 *__restrict__ gram, int hs, double2 *__restrict__ L, double2 *__restrict__ X,
+            int32_t *__restrict__ flags, int32_t *__restrict__ fail, int32_t *__restrict__ status)
+{
+    constexpr int G = kTriDistG, NT = kTriDistThreads;
+    extern __shared__ double2 dyn[];
+    __shared__ double red[NT / 64];
+    __shared__ int s_state;
+    const int g = blockIdx.x, tid = threadIdx.x;
+    const int nl = (m - g + G - 1) / G;
+    double2 *loc = dyn, *sa = loc + (size_t)((m + G - 1) / G) * m;
+    int32_t *cflag = flags, *abortf = flags + 2 * m;
+    const size_t mm = (size_t)m * m;
+    double dmax = 0.0;
+    for (int i = tid; i < m; i += NT) dmax = fmax(dmax, gram[(size_t)i * m + i].x);
+    dmax = block_max<NT>(dmax, red);
+    for (int sidx = 0; sidx < nl; ++sidx) {
+        const int c = g + G * sidx;
+        for (int i = tid; i < m; i += NT) {
+            const double2 a = gram[(size_t)c * m + i], b = gram[(size_t)i * m + c];
+            loc[(size_t)sidx * m + i] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+            if (hs) {
+                const double2 x = gram[mm + (size_t)c * m + i], y = gram[mm + (size_t)i * m + c];
+                X[(size_t)c * m + i] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+            }
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < m; ++j) {
+        if (g == j % G) {
+            double2 *col = loc + (size_t)(j / G) * m;
+            const double dj = col[j].x;
+            const bool bad = !(dj > 1e-14 * dmax);
+            if (!bad) {
+                const double ljj = sqrt(dj), inv = 1.0 / ljj;
+                for (int i = j + 1 + tid; i < m; i += NT) {
+                    const double2 v = make_double2(col[i].x * inv, col[i].y * inv);
+                    col[i] = v;
+                    L[(size_t)j * m + i] = v;
+                }
+                if (tid == 0) {
+                    col[j] = make_double2(ljj, 0.0);
+                    L[(size_t)j * m + j] = col[j];
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                __threadfence();
+                __hip_atomic_store(&cflag[j], bad ? 2 : 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                if (bad) {
+                    fail[0] = 1;
+                    atomicOr(status, PARO_F_CHOL);
+                }
+            }
+            if (bad) break;
+        }
+        if (g + G * (nl - 1) <= j) break;  // no own column after j
+        if (tid == 0) {
+            s_state = dist_wait(&cflag[j], 1, abortf, status) ? 1 : 0;
+            if (s_state && __hip_atomic_load(&cflag[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 2)
+                s_state = 0;
+        }
+        __syncthreads();
+        if (!s_state) break;
+        for (int i = j + 1 + tid; i < m; i += NT) sa[i] = L[(size_t)j * m + i];
+        __syncthreads();
+        // own columns l > j, rows i >= l: L_il -= L_ij conj(L_lj)
+        for (int sidx = (j + 1 - g + G - 1) / G; sidx < nl; ++sidx) {
+            const int l = g + G * sidx;
+            const double2 b = sa[l];
+            double2 *lc = loc + (size_t)sidx * m;
+            for (int i = l + tid; i < m; i += NT) {
+                const double2 a = sa[i];
+                lc[i] = make_double2(lc[i].x - (a.x * b.x + a.y * b.y), lc[i].y - (a.y * b.x - a.x * b.y));
+            }
+        }
+        __syncthreads();
+    }
+    // own columns: zero above the diagonal; columns not yet published (after
+    // a stop) are written as they stand
+    for (int sidx = 0; sidx < nl; ++sidx) {
+        const int c = g + G * sidx;
+        for (int i = tid; i < c; i += NT) L[(size_t)c * m + i] = make_double2(0.0, 0.0);
+        if (__hip_atomic_load(&cflag[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 1)
+            for (int i = c + tid; i < m; i += NT) L[(size_t)c * m + i] = loc[(size_t)sidx * m + i];
+    }
+}
+
+// Cholesky of the hermitised S (and hermitised Hs into X when hs): the
+// row-held variant up to m = 320, the first design beyond.
+static void launch_chol(hipStream_t st, int m, const double2 *gram, int hs, double2 *L, double2 *X, int32_t *fail,
+                        int32_t *status, int32_t *flags = nullptr)
+{
+    if (flags && m >= kTriDistMin && m <= kTriDistMax) {
+        static const hipError_t attr = hipFuncSetAttribute(
+            reinterpret_cast<const void *>(k_chol_dist), hipFuncAttributeMaxDynamicSharedMemorySize,
+            (int)(sizeof(double2) * (((size_t)(kTriDistMax + kTriDistG - 1) / kTriDistG + 1) * kTriDistMax)));
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (attr == hipSuccess && hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
+            hipLaunchKernelGGL(k_fill_i32, dim3((2 * m + 1 + 255) / 256), dim3(256), 0, st, 2 * m + 1, flags, 0);
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, 1, fail, 0);
+            int mm = m, h = hs;
+            const double2 *gp = gram;
+            double2 *Lp = L, *Xp = X;
+            int32_t *fl = flags, *fa = fail, *stp = status;
+            void *args[] = {&mm, &gp, &h, &Lp, &Xp, &fl, &fa, &stp};
+            const size_t sh = sizeof(double2) * (((size_t)(m + kTriDistG - 1) / kTriDistG + 1) * (size_t)m);
+            if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_chol_dist), dim3(kTriDistG),
+                                           dim3(kTriDistThreads), args, sh, st) == hipSuccess)
+                return;
+            (void)hipGetLastError();
+        }
+    }
+    constexpr int W = 16;
+    const size_t sh = sizeof(double2) * (size_t)m;
+    const dim3 tb(64 * W);
+    if (m <= 128)
+        hipLaunchKernelGGL((k_rr_chol_rows<2, W>), dim3(1), tb, sh, st, m, gram, hs, L, X, fail, status);
+    else if (m <= 192)
+        hipLaunchKernelGGL((k_rr_chol_rows<3, W>), dim3(1), tb, sh, st, m, gram, hs, L, X, fail, status);
+    else if (m <= 256)
+        hipLaunchKernelGGL((k_rr_chol_rows<4, W>), dim3(1), tb, sh, st, m, gram, hs, L, X, fail, status);
+    else if (m <= 320)
+        hipLaunchKernelGGL((k_rr_chol_rows<5, W>), dim3(1), tb, sh, st, m, gram, hs, L, X, fail, status);
+    else
+        hipLaunchKernelGGL(k_rr_chol, dim3(1), dim3(kBig), 0, st, m, gram, hs, L, X, fail, status);
+}
+
 
 // 1 / x: hardware reciprocal refined by one Newton step (about 1 ulp);
 // used where the result feeds a sign test or an iterative refinement.
@@ -858,6 +1188,10 @@ struct DenseScratch {
     double2 *tau;
     int32_t *fail;
     double *Z;
+    // exchange buffers of the multi-work-group tridiagonalisation:
+    // v (2 x (m + 1)), partial y (2 x kTriDistG x m), flags (2 m + 1 int32)
+    double2 *vbuf, *ypart;
+    int32_t *flags;
 };
 
 static DenseScratch dense_scratch(const Workspace &w, int m)
@@ -871,13 +1205,48 @@ static DenseScratch dense_scratch(const Workspace &w, int m)
     s.vmin = p + 5 * m;
     s.fail = reinterpret_cast<int32_t *>(p + 5 * m + 1);
     s.Z = p + 5 * m + 2;
+    size_t off = 5 * (size_t)m + 2 + (size_t)m * m;
+    off += off & 1;  // 16-byte alignment of the complex buffers
+    s.vbuf = reinterpret_cast<double2 *>(p + off);
+    s.ypart = s.vbuf + 2 * ((size_t)m + 1);
+    s.flags = reinterpret_cast<int32_t *>(s.ypart + 2 * (size_t)kTriDistG * m);
     return s;
 }
 
-size_t dense_real_elems(int mmax) { return 5 * (size_t)mmax + 2 + (size_t)mmax * mmax; }
+size_t dense_real_elems(int mmax)
+{
+    const size_t m = mmax;
+    return 5 * m + 2 + m * m + 1 + 2 * (2 * (m + 1) + 2 * (size_t)kTriDistG * m) + (2 * m + 2) / 2 + 1;
+}
+
+// The distributed tridiagonalisation as a cooperative launch; false when the
+// device cannot run it (the caller then uses a one-work-group variant).
+static bool launch_tridiag_dist(hipStream_t st, int m, double2 *Hh, const DenseScratch &s, int32_t *status)
+{
+    if (m < kTriDistMin || m > kTriDistMax) return false;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return false;
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag_dist),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)tridiag_dist_lds_bytes(kTriDistMax));
+    if (attr != hipSuccess) return false;
+    hipLaunchKernelGGL(k_fill_i32, dim3((2 * m + 1 + 255) / 256), dim3(256), 0, st, 2 * m + 1, s.flags, 0);
+    int mm = m;
+    double2 *A = Hh, *tau = s.tau, *vbuf = s.vbuf, *ypart = s.ypart;
+    double *d = s.d, *e = s.e;
+    int32_t *flags = s.flags, *stat = status;
+    void *args[] = {&mm, &A, &d, &e, &tau, &vbuf, &ypart, &flags, &stat};
+    const hipError_t r = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_tridiag_dist), dim3(kTriDistG),
+                                                    dim3(kTriDistThreads), args, tridiag_dist_lds_bytes(m), st);
+    if (r != hipSuccess) {
+        (void)hipGetLastError();  // clear the launch error; the caller falls back
+        return false;
+    }
+    return true;
+}
 
 static hipError_t eig_pipeline(hipStream_t st, int m, double2 *Hh, const DenseScratch &s, double *eps_out,
-                               int nout, double2 *Yout, bool vectors)
+                               int nout, double2 *Yout, bool vectors, int32_t *status = nullptr)
 {
     static const hipError_t lds_attr = hipFuncSetAttribute(
         reinterpret_cast<const void *>(k_tridiag_rows<2, true, kTriWavesLds>),
@@ -887,7 +1256,8 @@ static hipError_t eig_pipeline(hipStream_t st, int m, double2 *Hh, const DenseSc
     if (m <= kTridiagLdsMax && lds_attr == hipSuccess)
         hipLaunchKernelGGL((k_tridiag_rows<2, true, kTriWavesLds>), dim3(1), tl, tridiag_lds_bytes(m, true), st, m,
                            Hh, s.d, s.e, s.tau);
-    else if (m <= 128)
+    else if (launch_tridiag_dist(st, m, Hh, s, status)) {
+    } else if (m <= 128)
         hipLaunchKernelGGL((k_tridiag_rows<2, false, kTriWavesGlobal>), dim3(1), tg, gb, st, m, Hh, s.d, s.e, s.tau);
     else if (m <= 192)
         hipLaunchKernelGGL((k_tridiag_rows<3, false, kTriWavesGlobal>), dim3(1), tg, gb, st, m, Hh, s.d, s.e, s.tau);
@@ -915,11 +1285,11 @@ hipError_t launch_rr_dense(const Plan &pl, const Workspace &w, int m, int n_keep
     DenseScratch s = dense_scratch(w, m);
     double2 *L = w.dense[0], *X = w.dense[1], *Hh = w.dense[2], *Y = w.dense[3];
     const size_t colshm = (size_t)m * sizeof(double2);
-    launch_chol(st, m, w.gram, 1, L, X, s.fail, pl.status);
+    launch_chol(st, m, w.gram, 1, L, X, s.fail, pl.status, s.flags);
     // X <- L^-1 Hs;  Hh <- L^-1 X^H = L^-1 Hs L^-H
     hipLaunchKernelGGL(k_trsm_col, dim3(m), dim3(64), colshm, st, m, L, X, 0, 0, X);
     hipLaunchKernelGGL(k_trsm_col, dim3(m), dim3(64), colshm, st, m, L, X, 1, 0, Hh);
-    hipError_t e = eig_pipeline(st, m, Hh, s, eps_out, n_keep, Y, true);
+    hipError_t e = eig_pipeline(st, m, Hh, s, eps_out, n_keep, Y, true, pl.status);
     if (e != hipSuccess) return e;
     // C = L^-H Y
     hipLaunchKernelGGL(k_trsm_col, dim3(m), dim3(64), colshm, st, m, L, Y, 0, 1, C);
