@@ -35,6 +35,17 @@ __device__ __forceinline__ f4 mfma(float a, float b, f4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+// c + (-a) b.  The FP64 instruction negates its A operand itself (the
+// blgp field of the FP64 matrix instructions holds the neg:[A,B,C] bits);
+// the FP32 one has no such modifier.
+__device__ __forceinline__ d4 mfma_nega(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 1);
+}
+__device__ __forceinline__ f4 mfma_nega(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(-a, b, c, 0, 0, 0);
+}
 
 // accumulator type and output row of lane group lk, element v
 template <class C2> struct Mma;
@@ -95,21 +106,17 @@ k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, int bm, int bn, int64_t 
                 re[a][b] = Acc{0, 0, 0, 0};
                 im[a][b] = Acc{0, 0, 0, 0};
             }
-        const int ia[2] = {i0 + l16, i0 + 16 + l16};
-        const int jb[2] = {j0 + l16, j0 + 16 + l16};
+        // Rows and columns past M and N read the last valid one: lane l16's
+        // A operand only reaches row i0 + l16 of the block and its B operand
+        // only column j0 + l16, which are not stored.
+        const C2 *pa[2] = {A + (int64_t)min(i0 + l16, M - 1) * lda, A + (int64_t)min(i0 + 16 + l16, M - 1) * lda};
+        const C2 *pb[2] = {B + (int64_t)min(j0 + l16, N - 1) * ldb, B + (int64_t)min(j0 + 16 + l16, N - 1) * ldb};
         // Register prefetch ring: the operands of k-step s + kDepthHN - 1 are
         // requested before the products of step s, so that their latency
-        // overlaps kDepthHN - 1 steps of matrix-core work.
+        // overlaps kDepthHN - 1 steps of matrix-core work.  Operand loads are
+        // never under a branch, so that the compiler counts the loads in
+        // flight instead of waiting for all of them.
         C2 a[kDepthHN][2], b[kDepthHN][2];
-        auto load = [&](int slot, int64_t k0) {
-            const int64_t kk = k0 + lk;
-            const bool kv = kk < ke;
-    #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                a[slot][u] = (kv && ia[u] < M) ? A[(int64_t)ia[u] * lda + kk] : C2{0, 0};
-                b[slot][u] = (kv && jb[u] < N) ? B[(int64_t)jb[u] * ldb + kk] : C2{0, 0};
-            }
-        };
         auto step = [&](int slot) {
     #pragma unroll
             for (int u = 0; u < 2; ++u)
@@ -119,16 +126,73 @@ k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, int bm, int bn, int64_t 
                     re[u][w] = mfma(a[slot][u].x, b[slot][w].x, re[u][w]);
                     re[u][w] = mfma(a[slot][u].y, b[slot][w].y, re[u][w]);
                     im[u][w] = mfma(a[slot][u].x, b[slot][w].y, im[u][w]);
-                    im[u][w] = mfma(-a[slot][u].y, b[slot][w].x, im[u][w]);
+                    im[u][w] = mfma_nega(a[slot][u].y, b[slot][w].x, im[u][w]);
                 }
         };
+        constexpr int ring = 4 * kDepthHN;  // k per pass over the ring
+        if (ke - kb == kchunk && kchunk % ring == 0) {
+            // Full split: every step and every prefetch lies inside the
+            // split, so loads take fixed offsets from four pointers that
+            // advance once per pass, and nothing is masked.
+            const C2 *qa[2] = {pa[0] + kb + lk, pa[1] + kb + lk};
+            const C2 *qb[2] = {pb[0] + kb + lk, pb[1] + kb + lk};
+            auto load = [&](int slot, int off) {
     #pragma unroll
-        for (int d = 0; d < kDepthHN - 1; ++d) load(d, kb + 4 * d);
-        for (int64_t k0 = kb; k0 < ke; k0 += 4 * kDepthHN) {
+                for (int u = 0; u < 2; ++u) {
+                    a[slot][u] = qa[u][off];
+                    b[slot][u] = qb[u][off];
+                }
+            };
     #pragma unroll
-            for (int d = 0; d < kDepthHN; ++d) {
-                load((d + kDepthHN - 1) % kDepthHN, k0 + 4 * (d + kDepthHN - 1));
-                step(d);
+            for (int d = 0; d < kDepthHN - 1; ++d) {
+                // slots issued in ring order, so that the loop's waits count
+                // the same loads on its first pass as on the later ones
+                load(d, 4 * d);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            for (int64_t t = kchunk / ring; t > 1; --t) {
+    #pragma unroll
+                for (int d = 0; d < kDepthHN; ++d) {
+                    load((d + kDepthHN - 1) % kDepthHN, 4 * (d + kDepthHN - 1));
+                    step(d);
+                }
+    #pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    qa[u] += ring;
+                    qb[u] += ring;
+                }
+            }
+            // last pass: only the final step remains to be requested
+            load(kDepthHN - 1, 4 * (kDepthHN - 1));
+    #pragma unroll
+            for (int d = 0; d < kDepthHN; ++d) step(d);
+        } else if (kb < ke) {
+            // Partial split (the last one, or K not a multiple of the ring):
+            // steps past the split's end read the last valid k and their A
+            // operand is zeroed where it is used.
+            auto load = [&](int slot, int64_t k0) {
+                const int64_t kk = k0 + lk < K ? k0 + lk : K - 1;
+    #pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    a[slot][u] = pa[u][kk];
+                    b[slot][u] = pb[u][kk];
+                }
+            };
+    #pragma unroll
+            for (int d = 0; d < kDepthHN - 1; ++d) {
+                load(d, kb + 4 * d);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            for (int64_t k0 = kb; k0 < ke; k0 += ring) {
+    #pragma unroll
+                for (int d = 0; d < kDepthHN; ++d) {
+                    load((d + kDepthHN - 1) % kDepthHN, k0 + 4 * (d + kDepthHN - 1));
+                    const bool kv = k0 + 4 * d + lk < ke;
+    #pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        if (!kv) a[d][u] = C2{0, 0};
+                    step(d);
+                }
             }
         }
         double2 *P = part + (size_t)split * M * N;
@@ -199,7 +263,7 @@ k_gemm_hn_reduce(int M, int N, int nsplit, const double2 *__restrict__ part, CO 
 
 // C[g][n] (+)= sum_k A[g][k] B[k][n]; matrix-core rows = n, columns = g.
 template <class C2>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_gemm_nn(int64_t M, int N, int K, int bn, int64_t units, const C2 *__restrict__ A, int64_t lda,
           const C2 *__restrict__ B, int64_t ldb, C2 *__restrict__ C, int64_t ldc, int accumulate)
 {
@@ -221,19 +285,13 @@ k_gemm_nn(int64_t M, int N, int K, int bn, int64_t units, const C2 *__restrict__
                 re[a][b] = Acc{0, 0, 0, 0};
                 im[a][b] = Acc{0, 0, 0, 0};
             }
-        const int nb_[2] = {n0 + l16, n0 + 16 + l16};
-        const int64_t gg[2] = {g0 + l16, g0 + 16 + l16};
+        // Lane l16's B operand only reaches row n0 + l16 of C and its A
+        // operand only column g0 + l16, so past N and M they read the last
+        // valid one (those rows and columns are not stored).
+        const C2 *px[2] = {B + (int64_t)min(n0 + l16, N - 1) * ldb, B + (int64_t)min(n0 + 16 + l16, N - 1) * ldb};
+        const C2 *py[2] = {A + (g0 + l16 < M ? g0 + l16 : M - 1), A + (g0 + 16 + l16 < M ? g0 + 16 + l16 : M - 1)};
         // register prefetch ring, as in k_gemm_hn_part
         C2 x[kDepthNN][2], y[kDepthNN][2];
-        auto load = [&](int slot, int k0) {
-            const int kk = k0 + lk;
-            const bool kv = kk < K;
-    #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                x[slot][u] = (kv && nb_[u] < N) ? B[(int64_t)nb_[u] * ldb + kk] : C2{0, 0};
-                y[slot][u] = (kv && gg[u] < M) ? A[(int64_t)kk * lda + gg[u]] : C2{0, 0};
-            }
-        };
         auto step = [&](int slot) {
     #pragma unroll
             for (int u = 0; u < 2; ++u)
@@ -241,41 +299,104 @@ k_gemm_nn(int64_t M, int N, int K, int bn, int64_t units, const C2 *__restrict__
                 for (int w = 0; w < 2; ++w) {
                     // (x y): re = xr yr - xi yi, im = xr yi + xi yr
                     re[u][w] = mfma(x[slot][u].x, y[slot][w].x, re[u][w]);
-                    re[u][w] = mfma(-x[slot][u].y, y[slot][w].y, re[u][w]);
+                    re[u][w] = mfma_nega(x[slot][u].y, y[slot][w].y, re[u][w]);
                     im[u][w] = mfma(x[slot][u].x, y[slot][w].y, im[u][w]);
                     im[u][w] = mfma(x[slot][u].y, y[slot][w].x, im[u][w]);
                 }
         };
+        constexpr int ring = 4 * kDepthNN;
+        if (K % ring == 0) {
+            // every step and prefetch inside [0, K): fixed offsets from
+            // pointers that advance once per pass, nothing masked
+            const C2 *qx[2] = {px[0] + lk, px[1] + lk};
+            const C2 *qy[2] = {py[0] + (int64_t)lk * lda, py[1] + (int64_t)lk * lda};
+            const int64_t kstep = 4 * lda;
+            auto load = [&](int slot, int d) {
     #pragma unroll
-        for (int d = 0; d < kDepthNN - 1; ++d) load(d, 4 * d);
-        for (int k0 = 0; k0 < K; k0 += 4 * kDepthNN) {
+                for (int u = 0; u < 2; ++u) {
+                    x[slot][u] = qx[u][4 * d];
+                    y[slot][u] = qy[u][d * kstep];
+                }
+            };
     #pragma unroll
-            for (int d = 0; d < kDepthNN; ++d) {
-                load((d + kDepthNN - 1) % kDepthNN, k0 + 4 * (d + kDepthNN - 1));
-                step(d);
+            for (int d = 0; d < kDepthNN - 1; ++d) {
+                load(d, d);  // in ring order, as in k_gemm_hn_part
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            for (int t = K / ring; t > 1; --t) {
+    #pragma unroll
+                for (int d = 0; d < kDepthNN; ++d) {
+                    load((d + kDepthNN - 1) % kDepthNN, d + kDepthNN - 1);
+                    step(d);
+                }
+    #pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    qx[u] += ring;
+                    qy[u] += kDepthNN * kstep;
+                }
+            }
+            load(kDepthNN - 1, kDepthNN - 1);
+    #pragma unroll
+            for (int d = 0; d < kDepthNN; ++d) step(d);
+        } else if (K > 0) {
+            // steps past K read k = K - 1 and their B operand is zeroed
+            auto load = [&](int slot, int k0) {
+                const int kk = k0 + lk < K ? k0 + lk : K - 1;
+    #pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    x[slot][u] = px[u][kk];
+                    y[slot][u] = py[u][(int64_t)kk * lda];
+                }
+            };
+    #pragma unroll
+            for (int d = 0; d < kDepthNN - 1; ++d) {
+                load(d, 4 * d);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            for (int k0 = 0; k0 < K; k0 += ring) {
+    #pragma unroll
+                for (int d = 0; d < kDepthNN; ++d) {
+                    load((d + kDepthNN - 1) % kDepthNN, k0 + 4 * (d + kDepthNN - 1));
+                    const bool kv = k0 + 4 * d + lk < K;
+    #pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        if (!kv) x[d][u] = C2{0, 0};
+                    step(d);
+                }
             }
         }
+        // Accumulation: the old values of half the block are requested
+        // before the first is used (clamped into C, as the operand loads),
+        // so that their latencies overlap instead of adding up.
     #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int u = 0; u < 2; ++u) {
+            C2 old[2][4];
+            if (accumulate) {
+    #pragma unroll
+                for (int w = 0; w < 2; ++w)
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int n = min(n0 + u * 16 + Mma<C2>::row(lk, v), N - 1);
+                        const int64_t g = g0 + w * 16 + l16 < M ? g0 + w * 16 + l16 : M - 1;
+                        old[w][v] = C[(int64_t)n * ldc + g];
+                    }
+            }
     #pragma unroll
             for (int w = 0; w < 2; ++w)
     #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int n = n0 + u * 16 + Mma<C2>::row(lk, v);
                     const int64_t g = g0 + w * 16 + l16;
-                    if (n < N && g < M) {
-                        C2 *c = C + (int64_t)n * ldc + g;
-                        C2 r;
-                        r.x = re[u][w][v];
-                        r.y = im[u][w][v];
-                        if (accumulate) {
-                            const C2 o = *c;
-                            r.x += o.x;
-                            r.y += o.y;
-                        }
-                        *c = r;
+                    C2 r;
+                    r.x = re[u][w][v];
+                    r.y = im[u][w][v];
+                    if (accumulate) {
+                        r.x += old[w][v].x;
+                        r.y += old[w][v].y;
                     }
+                    if (n < N && g < M) C[(int64_t)n * ldc + g] = r;
                 }
+        }
     }
 }
 
@@ -345,8 +466,11 @@ hipError_t gemm_hn_t(hipStream_t s, int M, int N, int64_t K, const C2 *A, int64_
     const int64_t cap = (int64_t)(part_elems / ((size_t)M * N));
     if (nsplit > cap) nsplit = cap;
     if (nsplit < 1) return hipErrorInvalidValue;
+    // splits a whole number of prefetch-ring passes long (all but the last
+    // then take the kernel's unmasked path)
+    const int64_t ring = 4 * kDepthHN;
     int64_t kchunk = (K + nsplit - 1) / nsplit;
-    kchunk = (kchunk + 3) / 4 * 4;
+    kchunk = (kchunk + ring - 1) / ring * ring;
     nsplit = (K + kchunk - 1) / kchunk;
     if (nsplit < 1) nsplit = 1;
     const int64_t units = (int64_t)bm * bn * nsplit;

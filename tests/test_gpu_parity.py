@@ -85,7 +85,8 @@ C1 = synth.WORKLOADS["c1"]
 
 # ---------------------------------------------------------------- building blocks
 
-@pytest.mark.parametrize("M,N,K", [(16, 16, 4), (37, 21, 1000), (128, 160, 34265), (1, 1, 3)])
+@pytest.mark.parametrize("M,N,K", [(16, 16, 4), (37, 21, 1000), (128, 160, 34265), (1, 1, 3), (33, 65, 4099),
+                                   (160, 160, 1503)])
 def test_zgemm_hn_vs_numpy(M, N, K):
     import paper_1702_04045_amd as P
     rng = np.random.default_rng(M + N + K)
@@ -96,7 +97,8 @@ def test_zgemm_hn_vs_numpy(M, N, K):
     assert rel_err(C, ref) < 1e-13 * np.sqrt(K)
 
 
-@pytest.mark.parametrize("M,N,K", [(16, 16, 4), (1000, 33, 7), (34265, 160, 128), (5, 1, 1)])
+@pytest.mark.parametrize("M,N,K", [(16, 16, 4), (1000, 33, 7), (34265, 160, 128), (5, 1, 1), (70, 17, 130),
+                                   (1503, 160, 160)])
 def test_zgemm_nn_vs_numpy(M, N, K):
     import paper_1702_04045_amd as P
     rng = np.random.default_rng(M + 7 * N + K)
