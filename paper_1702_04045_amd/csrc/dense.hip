@@ -515,7 +515,7 @@ k_tridiag_rows(int m, double2 *__restrict__ A, double *__restrict__ d, double *_
         for (int q = tid; q < mm; q += NT) A[q] = S[q];
 }
 
-// The same reduction spread over kTriDistG work-groups (92 < m <= 352),
+// The same reduction spread over kTriDistG work-groups (208 <= m <= 352),
 // each holding the columns c = g, g + G, ... of the hermitised matrix in
 // its LDS for the whole sweep, so that the trailing updates read and write
 // LDS only.  Per column k: the owner of column k forms the Householder
@@ -531,6 +531,11 @@ k_tridiag_rows(int m, double2 *__restrict__ A, double *__restrict__ d, double *_
 // resident together.  Dynamic LDS: (ceil(m / G) + 2) m + 1 complex values.
 constexpr int kTriDistThreads = 256;
 constexpr int kTriDistMin = 93, kTriDistMax = 352;
+// The tridiagonalisation moves to sixteen work-groups only from m = 208:
+// below that the one-work-group sweep is faster (m = 160: 1.7 against
+// 2.0 ms per eigendecomposition; m = 192: 2.3 against 2.5; m = 256: 4.3
+// against 3.5).  The Cholesky gains from m = 93 on.
+constexpr int kTriDistMinTridiag = 208;
 constexpr long long kTriDistWaitTicks = 20000000;  // 0.2 s of the 100 MHz real-time counter
 
 static size_t tridiag_dist_lds_bytes(int m)
@@ -1223,7 +1228,7 @@ size_t dense_real_elems(int mmax)
 // device cannot run it (the caller then uses a one-work-group variant).
 static bool launch_tridiag_dist(hipStream_t st, int m, double2 *Hh, const DenseScratch &s, int32_t *status)
 {
-    if (m < kTriDistMin || m > kTriDistMax) return false;
+    if (m < kTriDistMinTridiag || m > kTriDistMax) return false;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return false;
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag_dist),

@@ -112,7 +112,7 @@ def test_zgemm_nn_vs_numpy(M, N, K):
     assert rel_err(C2, ref + C0_) < 1e-13 * np.sqrt(K)
 
 
-@pytest.mark.parametrize("m", [1, 2, 7, 64, 160, 333])
+@pytest.mark.parametrize("m", [1, 2, 7, 64, 93, 160, 207, 208, 333, 352, 353])
 def test_device_heev_vs_lapack(m):
     import paper_1702_04045_amd as P
     rng = np.random.default_rng(m)
