@@ -60,7 +60,8 @@ template <> struct Mma<float2> {
 
 namespace {
 
-constexpr int kWaveSlots = 2048;  // wavefronts resident at two per SIMD (256 CUs x 4 SIMDs x 2)
+// Wavefronts gemm_nn spreads over: two per SIMD (256 CUs x 4 SIMDs x 2).
+constexpr int kWaveSlotsNN = 2048;
 constexpr int kXcds = 8;    // accelerator complex dies; work-group b runs on die b % kXcds
 
 // Work index of work-group b among total: the work-groups of one die get
@@ -73,9 +74,21 @@ __device__ __forceinline__ int64_t xcd_work_index(int64_t b, int64_t total)
     const int64_t x = b % kXcds, l = b / kXcds;
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
 }
-// k-steps of 4 in flight per wave (register prefetch ring), measured best
-// for the long split contraction of gemm_hn and the short one of gemm_nn
-constexpr int kDepthHN = 8;
+// gemm_hn schedule per operand precision: wavefronts the split products
+// spread over and k-steps of 4 in flight per wave (register prefetch
+// ring).  FP64: one wave per SIMD with splits twice as long, so that the
+// ring may take most of the registers (for the 128 x 160 x 34265
+// projector product: 2048 slots and 8 steps 122 us; 1024 slots and 8, 12,
+// 16 steps 108, 105, 94 us).  FP32: two waves per SIMD, 8 steps (1024
+// slots and 16 steps: 106 against 96 us).
+template <class C2> struct HnCfg;
+template <> struct HnCfg<double2> {
+    static constexpr int slots = 1024, depth = 16;
+};
+template <> struct HnCfg<float2> {
+    static constexpr int slots = 2048, depth = 8;
+};
+// k-steps in flight per wave for the short contraction of gemm_nn
 constexpr int kDepthNN = 4;
 
 // partial[s][j][i] = sum over k in split s of conj(A[k][i]) B[k][j]
@@ -90,6 +103,7 @@ k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, int bm, int bn, int64_t 
                int64_t lda, const C2 *__restrict__ B, int64_t ldb, double2 *__restrict__ part)
 {
     using Acc = typename Mma<C2>::Acc;
+    constexpr int kDepthHN = HnCfg<C2>::depth;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t nw = (int64_t)gridDim.x * 4;
     for (int64_t unit = xcd_work_index(blockIdx.x, gridDim.x) * 4 + wave; unit < units; unit += nw) {
@@ -459,7 +473,8 @@ hipError_t gemm_hn_t(hipStream_t s, int M, int N, int64_t K, const C2 *A, int64_
     const int bm = (M + 31) / 32, bn = (N + 31) / 32;
     // about one unit per wavefront slot of the chip, each split at least one
     // prefetch ring of k long, within the partial buffer
-    int64_t nsplit = kWaveSlots / ((int64_t)bm * bn);
+    constexpr int kDepthHN = HnCfg<C2>::depth, kWaveSlotsHN = HnCfg<C2>::slots;
+    int64_t nsplit = kWaveSlotsHN / ((int64_t)bm * bn);
     const int64_t kmax = (K + 4 * kDepthHN - 1) / (4 * kDepthHN);
     if (nsplit > kmax) nsplit = kmax;
     if (nsplit < 1) nsplit = 1;
@@ -474,7 +489,7 @@ hipError_t gemm_hn_t(hipStream_t s, int M, int N, int64_t K, const C2 *A, int64_
     nsplit = (K + kchunk - 1) / kchunk;
     if (nsplit < 1) nsplit = 1;
     const int64_t units = (int64_t)bm * bn * nsplit;
-    const unsigned wgs = (unsigned)std::min<int64_t>((units + 3) / 4, kWaveSlots / 4);
+    const unsigned wgs = (unsigned)std::min<int64_t>((units + 3) / 4, kWaveSlotsHN / 4);
     prof_mark(PARO_K_GEMM_HN, s, true);
     hipLaunchKernelGGL((k_gemm_hn_part<C2>), dim3(wgs), dim3(256), 0, s, M, N, K, kchunk, bm, bn, units, A, lda, B,
                        ldb, part);
@@ -491,7 +506,7 @@ hipError_t gemm_nn_t(hipStream_t s, int64_t M, int N, int K, const C2 *A, int64_
     if (M <= 0 || N <= 0) return hipSuccess;
     const int bn = (N + 31) / 32;
     const int64_t units = (M + 31) / 32 * bn;
-    dim3 grid((unsigned)std::min<int64_t>((units + 3) / 4, kWaveSlots / 4));
+    dim3 grid((unsigned)std::min<int64_t>((units + 3) / 4, kWaveSlotsNN / 4));
     prof_mark(PARO_K_GEMM_NN, s, true);
     hipLaunchKernelGGL((k_gemm_nn<C2>), grid, dim3(256), 0, s, M, N, K, bn, units, A, lda, B, ldb, C, ldc,
                        accumulate ? 1 : 0);
