@@ -60,8 +60,6 @@ template <> struct Mma<float2> {
 
 namespace {
 
-// Wavefronts gemm_nn spreads over: two per SIMD (256 CUs x 4 SIMDs x 2).
-constexpr int kWaveSlotsNN = 2048;
 constexpr int kXcds = 8;    // accelerator complex dies; work-group b runs on die b % kXcds
 
 // Work index of work-group b among total: the work-groups of one die get
@@ -88,8 +86,18 @@ template <> struct HnCfg<double2> {
 template <> struct HnCfg<float2> {
     static constexpr int slots = 2048, depth = 8;
 };
-// k-steps in flight per wave for the short contraction of gemm_nn
-constexpr int kDepthNN = 4;
+// gemm_nn schedule per operand precision: wavefronts the persistent grid
+// holds (2048: two per SIMD) and k-steps in flight per wave for its short
+// contraction.  For the 34265 x 160 x 128 nonlocal product (FP64) 2048
+// slots and 4 steps took 120 us; 8 steps 136 us; 1024 slots with 4, 8, 16
+// steps 124, 133, 148 us.
+template <class C2> struct NnCfg;
+template <> struct NnCfg<double2> {
+    static constexpr int slots = 2048, depth = 4;
+};
+template <> struct NnCfg<float2> {
+    static constexpr int slots = 2048, depth = 4;
+};
 
 // partial[s][j][i] = sum over k in split s of conj(A[k][i]) B[k][j]
 // (accumulated in the operands' precision, stored in FP64).  Work unit =
@@ -282,6 +290,7 @@ k_gemm_nn(int64_t M, int N, int K, int bn, int64_t units, const C2 *__restrict__
           const C2 *__restrict__ B, int64_t ldb, C2 *__restrict__ C, int64_t ldc, int accumulate)
 {
     using Acc = typename Mma<C2>::Acc;
+    constexpr int kDepthNN = NnCfg<C2>::depth;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // work unit = one 32 x 32 block of C, done by one wavefront; the bn
     // column blocks of one row block (which share its rows of A) are
@@ -506,7 +515,7 @@ hipError_t gemm_nn_t(hipStream_t s, int64_t M, int N, int K, const C2 *A, int64_
     if (M <= 0 || N <= 0) return hipSuccess;
     const int bn = (N + 31) / 32;
     const int64_t units = (M + 31) / 32 * bn;
-    dim3 grid((unsigned)std::min<int64_t>((units + 3) / 4, kWaveSlotsNN / 4));
+    dim3 grid((unsigned)std::min<int64_t>((units + 3) / 4, NnCfg<C2>::slots / 4));
     prof_mark(PARO_K_GEMM_NN, s, true);
     hipLaunchKernelGGL((k_gemm_nn<C2>), grid, dim3(256), 0, s, M, N, K, bn, units, A, lda, B, ldb, C, ldc,
                        accumulate ? 1 : 0);
