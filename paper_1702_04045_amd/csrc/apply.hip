@@ -45,6 +45,9 @@ template <int T> __device__ __forceinline__ int thread_in_line(int tid) { return
 // threads of the plane kernel: one line slot per row, rounded up to whole wavefronts
 template <int N, class C2> constexpr int plane_threads() { return (N * PlaneCfgP<N, C2>::T + 63) / 64 * 64; }
 constexpr int kBandsPerBlock = 4;  // bands one work-group of the plane kernel takes through its z-plane
+// Row transforms of the plane kernel done across lanes (xlane96_inverse /
+// xlane96_forward) instead of through LDS: the FP64 96-point plane.
+template <int N, class C2> constexpr bool xlane_rows() { return N == 96 && std::is_same<C2, double2>::value; }
 
 // Sphere -> sticks, inverse transform along n3.  Line (stick) threads are
 // consecutive lanes, so the exchanges between passes are wavefront-local.
@@ -195,20 +198,48 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
                 int x = i + sh;
                 return x - (x >= N ? N : 0);
             };
-            VR vr[E];
+            if constexpr (xlane_rows<N, C2>()) {
+                // Thread t reads and writes the row elements t + T m only,
+                // and every exchange is a lane swap: no LDS traffic besides
+                // the populated entries, no wave synchronisation.  All N
+                // line slots are rows here (N T threads), so every lane of
+                // each wavefront takes part in the swaps.
+                static_assert(plane_threads<N, C2>() == N * T && T == 8 && E == 12, "cross-lane rows: 96 x 8 lanes");
+                const C2 *twr = tw;
+                asm volatile("" : "+s"(twr));
 #pragma unroll
-            for (int e = 0; e < E; ++e) vr[e] = vp[e];
-            if (rowact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
-                return (i <= nmax1 || i >= N - nmax1) ? row[at(i)] : cmk<C2>(0.0, 0.0);
-            });
-            stockham_c<C, +1, true>(Inv{}, v, t, rowact, row, 1, tw);
+                for (int m = 0; m < E; ++m) {
+                    const int i = t + T * m;
+                    v[m] = (i <= nmax1 || i >= N - nmax1) ? row[at(i)] : cmk<C2>(0.0, 0.0);
+                }
+                xlane96_inverse(v, t, twr);
 #pragma unroll
-            for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vr[e]);
-            stockham_c<C, -1, true>(Fwd{}, v, t, rowact, row, 1, tw);
-            wave_lds_sync();
-            if (rowact) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
-                if (i <= nmax1 || i >= N - nmax1) row[at(i)] = v[e];
-            });
+                for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vp[e]);
+                // the forward transform reloads the twiddles rather than
+                // keeping the inverse's thirteen live across the multiply
+                asm volatile("" : "+s"(twr));
+                xlane96_forward(v, t, twr);
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int i = t + T * m;
+                    if (i <= nmax1 || i >= N - nmax1) row[at(i)] = v[m];
+                }
+            } else {
+                VR vr[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) vr[e] = vp[e];
+                if (rowact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
+                    return (i <= nmax1 || i >= N - nmax1) ? row[at(i)] : cmk<C2>(0.0, 0.0);
+                });
+                stockham_c<C, +1, true>(Inv{}, v, t, rowact, row, 1, tw);
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vr[e]);
+                stockham_c<C, -1, true>(Fwd{}, v, t, rowact, row, 1, tw);
+                wave_lds_sync();
+                if (rowact) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
+                    if (i <= nmax1 || i >= N - nmax1) row[at(i)] = v[e];
+                });
+            }
         }
         __syncthreads();
     }
@@ -378,19 +409,21 @@ k_density_reduce(const double *__restrict__ part, int ngroups, int N3, int accum
 }
 
 // Potential in the row-thread order of k_plane<N>: out[((z N + y) T + t) E + e]
-// = V(i1 = x(t, e), i2 = y, i3 = z), x(t, e) = t + T (e / RL) + (e % RL)(N / RL),
+// = V(i1 = x(t, e), i2 = y, i3 = z), x(t, e) = t + T (e / RL) + (e % RL)(N / RL)
+// after the Stockham passes, xlane_index(t, e) after the cross-lane rows;
 // from vloc in C order [i1][i2][i3].
 template <int N, class VT>
 void plane_potential(const int32_t *grid, const double *vloc, VT *out)
 {
-    using C = PlaneCfgP<N, typename std::conditional<std::is_same<VT, float>::value, float2, double2>::type>;
+    using C2 = typename std::conditional<std::is_same<VT, float>::value, float2, double2>::type;
+    using C = PlaneCfgP<N, C2>;
     constexpr int T = C::T, E = C::E, RL = ListInfo<typename C::Inv>::last;
     const int N2 = grid[1], N3 = grid[2];
     for (int z = 0; z < N3; ++z)
         for (int y = 0; y < N2; ++y)
             for (int t = 0; t < T; ++t)
                 for (int e = 0; e < E; ++e) {
-                    const int x = t + T * (e / RL) + (e % RL) * (N / RL);
+                    const int x = xlane_rows<N, C2>() ? xlane_index(t, e) : t + T * (e / RL) + (e % RL) * (N / RL);
                     out[(((size_t)z * N + y) * T + t) * E + e] = (VT)vloc[((size_t)x * N2 + y) * N3 + z];
                 }
 }

@@ -381,6 +381,122 @@ __device__ __forceinline__ void stockham(RList<Rs...> l, C2 (&v)[FftCfg<N>::E], 
     stockham_c<FftCfg<N>, SIGN, WL>(l, v, t, act, line, es, tw);
 }
 
+// ---------------------------------------------------------------------------
+// 96-point transform of one line across 8 lanes without LDS (FP64).
+//
+// Thread t of the line (lane bits 3, 4, 5 = bits 0, 1, 2 of t) holds
+// x[t + 8 m], m < 12.  Four-step split 96 = 12 x 8: a 12-point DFT over m in
+// registers, the twiddle w^(t k1), then 8-point DFTs over t across the lanes
+// as three radix-2 decimation-in-frequency stages on thread bits 2, 1, 0
+// (lane distances 32, 16, 8).  Each stage first swaps half of the twelve
+// registers with the partner lane (v_permlane32_swap / v_permlane16_swap,
+// or two DPP row rotations for distance 8), so that each lane then holds
+// both operands of six butterflies.  After the three stages register s of
+// thread t holds X[k] with, for s = j + 3 d + 6 e (j < 3, d, e < 2),
+// k = (j + 3 t1 + 6 t2) + 12 (4 e + 2 d + t0), t = t0 + 2 t1 + 4 t2
+// (xlane_index).  The forward transform applies the conjugate transpose of
+// every step in reverse order, so its outputs are again x[t + 8 m].
+__host__ __device__ constexpr int xlane_index(int t, int s)
+{
+    return (s % 3 + 3 * (t >> 1 & 1) + 6 * (t >> 2 & 1)) + 12 * (4 * (s / 6) + 2 * (s / 3 % 2) + (t & 1));
+}
+
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// Lane swap on thread bit B: the line's lower lane (bit B clear) receives
+// the upper lane's p in q, the upper lane receives the lower lane's q in p.
+template <int B> __device__ __forceinline__ void xswap32(uint32_t &p, uint32_t &q);
+template <> __device__ __forceinline__ void xswap32<2>(uint32_t &p, uint32_t &q)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(p, q, false, false);
+    p = r[0];
+    q = r[1];
+}
+template <> __device__ __forceinline__ void xswap32<1>(uint32_t &p, uint32_t &q)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(p, q, false, false);
+    p = r[0];
+    q = r[1];
+}
+template <> __device__ __forceinline__ void xswap32<0>(uint32_t &p, uint32_t &q)
+{
+    // row_ror:8 pairs lanes l and l ^ 8 of each 16-lane row; banks 0-1 of
+    // a row are its lanes 0-7 (thread bit 0 clear), banks 2-3 lanes 8-15
+    const int p0 = (int)p, q0 = (int)q;
+    q = (uint32_t)__builtin_amdgcn_update_dpp(q0, p0, 0x128, 0xf, 0x3, false);
+    p = (uint32_t)__builtin_amdgcn_update_dpp(p0, q0, 0x128, 0xf, 0xc, false);
+}
+template <int B> __device__ __forceinline__ void xswap(double2 &p, double2 &q)
+{
+    uint32_t a[4], b[4];
+    __builtin_memcpy(a, &p, 16);
+    __builtin_memcpy(b, &q, 16);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) xswap32<B>(a[i], b[i]);
+    __builtin_memcpy(&p, a, 16);
+    __builtin_memcpy(&q, b, 16);
+}
+
+// register pairs of the butterflies of the stage on thread bit B
+template <int B> __device__ __forceinline__ constexpr int xpair_lo(int i)
+{
+    return B == 1 ? (i % 3) + 6 * (i / 3) : i;
+}
+template <int B> __device__ __forceinline__ constexpr int xpair_hi(int i)
+{
+    return B == 1 ? (i % 3) + 3 + 6 * (i / 3) : i + 6;
+}
+
+// inverse-direction stage: swap, then (u, v) -> (u + v, (u - v) w)
+template <int B> __device__ __forceinline__ void xstage_inv(double2 (&v)[12], double2 w)
+{
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double2 &a = v[xpair_lo<B>(i)], &b = v[xpair_hi<B>(i)];
+        xswap<B>(a, b);
+        const double2 u = a, d = csub(a, b);
+        a = cadd(u, b);
+        b = B == 0 ? d : cmul(d, w);
+    }
+}
+// its conjugate transpose: (a, b) -> (a + b w*, a - b w*), then the same swap
+template <int B> __device__ __forceinline__ void xstage_fwd(double2 (&v)[12], double2 wc)
+{
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double2 &a = v[xpair_lo<B>(i)], &b = v[xpair_hi<B>(i)];
+        const double2 c = B == 0 ? b : cmul(b, wc);
+        const double2 u = a;
+        a = cadd(u, c);
+        b = csub(u, c);
+        xswap<B>(a, b);
+    }
+}
+
+// tw[m] = exp(-2 pi i m / 96).  Inverse: v[m] = x[t + 8 m] on entry, v[s] =
+// X[xlane_index(t, s)] (sign +1, unnormalised) on exit.
+__device__ __forceinline__ void xlane96_inverse(double2 (&v)[12], int t, const double2 *__restrict__ tw)
+{
+    Dft<12, +1>::run(v);
+#pragma unroll
+    for (int k = 1; k < 12; ++k) v[k] = cmul(v[k], cconj(tw[t * k]));
+    asm volatile("" : "+s"(tw));  // stage twiddles loaded here, not up front
+    xstage_inv<2>(v, cconj(tw[12 * (t & 3)]));
+    xstage_inv<1>(v, cconj(tw[24 * (t & 1)]));
+    xstage_inv<0>(v, make_double2(1.0, 0.0));
+}
+// Forward (sign -1) from the layout xlane96_inverse leaves: v[m] = y[t + 8 m] on exit.
+__device__ __forceinline__ void xlane96_forward(double2 (&v)[12], int t, const double2 *__restrict__ tw)
+{
+    xstage_fwd<0>(v, make_double2(1.0, 0.0));
+    xstage_fwd<1>(v, tw[24 * (t & 1)]);
+    xstage_fwd<2>(v, tw[12 * (t & 3)]);
+    asm volatile("" : "+s"(tw));
+#pragma unroll
+    for (int k = 1; k < 12; ++k) v[k] = cmul(v[k], tw[t * k]);
+    Dft<12, -1>::run(v);
+}
+
 // Line schedule of the z-plane kernel (defaults to FftCfg).  For 96 points
 // 8 threads per line (12 work-group waves) with passes 4 x 6 x 4 measured
 // fastest among 4 x 24 and 8 x 12 splits of the lines.
