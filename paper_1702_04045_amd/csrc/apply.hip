@@ -170,7 +170,42 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
             xs -= xs >= N ? N : 0;
             C2 *col = plane + (act ? xs : 0);
             C2 *tz = sticks + ((size_t)(b0 + (act ? kb : 0)) * N3 + z) * nst + cst;
-            if (lower) {
+            if constexpr (xlane_rows<N, C2>()) {
+                // Column transforms across lanes too.  The forward column
+                // reads the plane in the register order the cross-lane
+                // inverse leaves (xlane_index) and the inverse column writes
+                // it in that order; the transforms run on every lane of a
+                // wavefront (lines past the populated columns on zeros,
+                // without loads or stores), since a swap only pairs lanes of
+                // one line.
+                if (kb >= 0 && kb < nbk) {
+                    const C2 *twc = tw;
+                    asm volatile("" : "+s"(twc));
+                    if (lower) {
+#pragma unroll
+                        for (int e = 0; e < E; ++e) v[e] = act ? col[xlane_index(t, e) * LDX] : cmk<C2>(0.0, 0.0);
+                        xlane96_forward(v, t, twc);
+                        if (act) {
+#pragma unroll
+                            for (int m = 0; m < E; ++m) {
+                                const int q = stick_of(t + T * m);
+                                if (q >= 0) tz[q] = v[m];
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < E; ++m) {
+                            const int q = act ? stick_of(t + T * m) : -1;
+                            v[m] = q >= 0 ? tz[q] : cmk<C2>(0.0, 0.0);
+                        }
+                        xlane96_inverse(v, t, twc);
+                        if (act) {
+#pragma unroll
+                            for (int e = 0; e < E; ++e) col[xlane_index(t, e) * LDX] = v[e];
+                        }
+                    }
+                }
+            } else if (lower) {
                 if (act) pass_load<N, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return col[i * LDX]; });
                 stockham_c<C, -1, true>(Fwd{}, v, t, act, col, LDX, tw);
                 if (act) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
