@@ -119,6 +119,27 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES, "launches": 3}))
 
 
+def traffic_pass(seed):
+    """Only the FP64 H applies and density calls of the 160-band block on the
+    34,265-plane-wave cell (no Rayleigh-Ritz): the run the plane kernels' HBM
+    counters are read from."""
+    import torch
+    import paper_1702_04045_amd as P
+    dev = torch.device("cuda:0")
+    spec = synth.WORKLOADS["c1"]
+    cell = synth.make_cell(spec, seed)
+    v = synth.vloc_on_grid(cell["cell"], cell["grid"], cell["positions"], cell["depths"], cell["widths"])
+    pl = P.Plan(cell["cell"], cell["ecut"], v, cell["projectors"], device=dev)
+    x = torch.from_numpy(synth.trial_block(pl.ng, spec.n_carried, seed)).to(dev)
+    w = torch.ones(spec.n_carried, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        pl.apply_h(x)
+    for _ in range(3):
+        pl.density(x, w)
+    torch.cuda.synchronize()
+    print(json.dumps({"traffic_pass": {"bands": spec.n_carried, "applies": 3, "density_calls": 3}}))
+
+
 def cpu_baseline(spec, cell, v, x_trial, sample_bands=64):
     """The CPU oracle's outer-iteration time, extrapolated from a bounded sample."""
     import oracle
@@ -205,9 +226,14 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 24-cell batched run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--traffic-pass", action="store_true",
+                    help="only run FP64 H applies and density calls on the benchmark cell (HBM counters) and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.traffic_pass:
+        traffic_pass(args.seed)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the band-sharded multi-GPU "
