@@ -90,12 +90,24 @@ k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const
     __syncthreads();
     C2 v[E];
     C2 *line = tile + sl * LD;
-    if (act) pass_load<N3, T, E, ListInfo<typename C::Inv>::first>(v, t, [&](int i) { return line[i]; });
-    stockham<N3, +1, true>(typename C::Inv{}, v, t, act, line, 1, tw);
     C2 *out = sticks + (size_t)band * N3 * nst;
-    if (act)
-        final_foreach<N3, T, E, ListInfo<typename C::Inv>::last>(
-            v, t, [&](int i, int e) { out[(size_t)i * nst + s] = v[e]; });
+    if constexpr (xlane_rows<N3, C2>()) {
+        // cross-lane transform (every lane takes part; the tile is zero past
+        // the last stick), outputs stored in the schedule's register order
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[m] = line[t + T * m];
+        xlane96_inverse(v, t, tw);
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) out[(size_t)xlane_index(t, e) * nst + s] = v[e];
+        }
+    } else {
+        if (act) pass_load<N3, T, E, ListInfo<typename C::Inv>::first>(v, t, [&](int i) { return line[i]; });
+        stockham<N3, +1, true>(typename C::Inv{}, v, t, act, line, 1, tw);
+        if (act)
+            final_foreach<N3, T, E, ListInfo<typename C::Inv>::last>(
+                v, t, [&](int i, int e) { out[(size_t)i * nst + s] = v[e]; });
+    }
 }
 
 // One z-plane of bands b0 .. b1-1: inverse along n2 (populated n1 columns),
@@ -485,10 +497,20 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
     const C2 *in = sticks + (size_t)band * N3 * nst;
     C2 v[E];
     C2 *line = tile + sl * LD;
-    if (act) pass_load<N3, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return in[(size_t)i * nst + s]; });
-    stockham<N3, -1, true>(Fwd{}, v, t, act, line, 1, tw);
-    wave_lds_sync();
-    if (act) final_foreach<N3, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) { line[i] = v[e]; });
+    if constexpr (xlane_rows<N3, C2>()) {
+        // cross-lane transform: inputs read in the schedule's register order
+        // (zero past the last stick), outputs x[t + T m]
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = act ? in[(size_t)xlane_index(t, e) * nst + s] : cmk<C2>(0.0, 0.0);
+        xlane96_forward(v, t, tw);
+#pragma unroll
+        for (int m = 0; m < E; ++m) line[t + T * m] = v[m];
+    } else {
+        if (act) pass_load<N3, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return in[(size_t)i * nst + s]; });
+        stockham<N3, -1, true>(Fwd{}, v, t, act, line, 1, tw);
+        wave_lds_sync();
+        if (act) final_foreach<N3, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) { line[i] = v[e]; });
+    }
     __syncthreads();
     const int p0 = st_start[s0], p1 = st_start[min(s0 + S, nst)];
     const double sig = shift ? shift[band] : 0.0;
