@@ -304,8 +304,10 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
 // running sums wait in LDS between row stages, in the unpopulated n1 range
 // of the thread's own row (N - 2 nmax1 - 1 >= N / 2 complex slots, which
 // the column stage never writes), so that they take no registers during
-// the column transforms.  The group's partial plane is written in the
-// row-thread order of the potential, part[((z N + y) T + t) E + e].
+// the column transforms.  With the cross-lane 96-point schedule the rows
+// need no exchange space and the sums stay in registers.  The group's
+// partial plane is written in the row threads' register order,
+// part[((z N + y) T + t) E + e].
 template <int N> constexpr bool density_pairs() { return N <= 64; }
 
 template <int N>
@@ -349,7 +351,7 @@ k_plane_density(const double2 *__restrict__ sticks, int nst, int N3, int nb, int
     for (int e = 0; e < E; ++e) acc[e] = 0.0;
     // this thread's E running sums between row stages (without PAIR)
     double *stash = reinterpret_cast<double *>(row + nmax1 + 1) + t * E;
-    if (!PAIR && rowact)
+    if (!PAIR && !xlane_rows<N, double2>() && rowact)
 #pragma unroll
         for (int e = 0; e < E; ++e) stash[e] = 0.0;
     for (int k = b0; k < b1; k += PAIR ? 2 : 1) {
@@ -365,15 +367,50 @@ k_plane_density(const double2 *__restrict__ sticks, int nst, int N3, int nb, int
             double2 *col = plane + (act ? xs : 0);
             const double2 *tz = sticks + ((size_t)(act ? kb : 0) * N3 + z) * nst + cst;
             double2 v[E];
-            if (act) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
-                const int q = stick_of(i);
-                return q >= 0 ? tz[q] : cmk<double2>(0.0, 0.0);
-            });
-            stockham_c<C, +1, true>(Inv{}, v, t, act, col, LDX, tw);
-            wave_lds_sync();
-            if (act) final_foreach<N, T, E, RL>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
+            if constexpr (xlane_rows<N, double2>()) {
+                // cross-lane inverse column (lower slots; the upper ones
+                // have no column without PAIR), written in the register
+                // order the row stage's loads expect
+                if (lower) {
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {
+                        const int q = act ? stick_of(t + T * m) : -1;
+                        v[m] = q >= 0 ? tz[q] : cmk<double2>(0.0, 0.0);
+                    }
+                    xlane96_inverse(v, t, tw);
+                    if (act) {
+#pragma unroll
+                        for (int e = 0; e < E; ++e) col[xlane_index(t, e) * LDX] = v[e];
+                    }
+                }
+            } else {
+                if (act) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
+                    const int q = stick_of(i);
+                    return q >= 0 ? tz[q] : cmk<double2>(0.0, 0.0);
+                });
+                stockham_c<C, +1, true>(Inv{}, v, t, act, col, LDX, tw);
+                wave_lds_sync();
+                if (act) final_foreach<N, T, E, RL>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
+            }
         }
         __syncthreads();
+        if constexpr (xlane_rows<N, double2>()) {
+            // cross-lane inverse rows; the running sums stay in registers,
+            // in the schedule's register order
+            static_assert(!PAIR, "cross-lane density rows: one band per step");
+            double2 v[E];
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int i = t + T * m;
+                v[m] = (i <= nmax1 || i >= N - nmax1) ? row[i] : cmk<double2>(0.0, 0.0);
+            }
+            xlane96_inverse(v, t, tw);
+            const double w0 = weights ? weights[k] : 1.0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] += w0 * (v[e].x * v[e].x + v[e].y * v[e].y);
+            __syncthreads();
+            continue;
+        }
         asm volatile("" : "+v"(t));
         {
             const bool two = PAIR && k + 1 < b1;
@@ -440,7 +477,7 @@ k_density_reduce(const double *__restrict__ part, int ngroups, int N3, int accum
     for (int idx = threadIdx.x; idx < nz * N; idx += 256) {
         const int zz = idx / N, q = idx - zz * N;
         const int t = q / E, e = q - t * E;
-        const int x = t + T * (e / RL) + (e % RL) * (N / RL);
+        const int x = xlane_rows<N, double2>() ? xlane_index(t, e) : t + T * (e / RL) + (e % RL) * (N / RL);
         const double *p = part + ((size_t)(z0 + zz) * N + y) * N + q;
         double s = 0.0;
         for (int gi = 0; gi < ngroups; ++gi) s += p[gi * gstride];
