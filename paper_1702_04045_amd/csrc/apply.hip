@@ -48,6 +48,12 @@ constexpr int kBandsPerBlock = 4;  // bands one work-group of the plane kernel t
 // Row transforms of the plane kernel done across lanes (xlane96_inverse /
 // xlane96_forward) instead of through LDS: the FP64 96-point plane.
 template <int N, class C2> constexpr bool xlane_rows() { return N == 96 && std::is_same<C2, double2>::value; }
+// an opaque copy of the line thread index for one cross-lane call site
+__device__ __forceinline__ int opaque(int t)
+{
+    asm volatile("" : "+v"(t));
+    return t;
+}
 
 // Sphere -> sticks, inverse transform along n3.  Line (stick) threads are
 // consecutive lanes, so the exchanges between passes are wavefront-local.
@@ -64,11 +70,14 @@ k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const
     static_assert(cfg_ok<N3>(), "bad FFT config");
     constexpr int T = C::T, E = C::E, S = kStickThreads / T, LD = N3 + 1;
     __shared__ C2 tile[S * LD];
+    __shared__ C2 twl[xlane_rows<N3, C2>() ? N3 : 1];  // twiddles of the cross-lane transform
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
     const int s0 = blockIdx.x * S, band = blockIdx.y;
     const int s = s0 + sl;
     const bool act = s < nst;
     for (int i = tid; i < S * LD; i += kStickThreads) tile[i] = cmk<C2>(0.0, 0.0);
+    if constexpr (xlane_rows<N3, C2>())
+        for (int i = tid; i < N3; i += kStickThreads) twl[i] = tw[i];
     __syncthreads();
     const int p0 = st_start[s0], p1 = st_start[min(s0 + S, nst)];
     const C2 *x = src + band * ld;
@@ -96,7 +105,7 @@ k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const
         // the last stick), outputs stored in the schedule's register order
 #pragma unroll
         for (int m = 0; m < E; ++m) v[m] = line[t + T * m];
-        xlane96_inverse(v, t, tw);
+        xlane96_inverse(v, opaque(t), twl);
         if (act) {
 #pragma unroll
             for (int e = 0; e < E; ++e) out[(size_t)xlane_index(t, e) * nst + s] = v[e];
@@ -142,8 +151,13 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
     constexpr int T = C::T, E = C::E, LDX = N + 1, HALF = N / 2;
     constexpr int RL = ListInfo<Inv>::last;
     __shared__ C2 plane[N * LDX];
+    __shared__ C2 twl[xlane_rows<N, C2>() ? N : 1];  // twiddles of the cross-lane transforms
     const int tid = threadIdx.x;
     const int z = blockIdx.x;
+    if constexpr (xlane_rows<N, C2>()) {
+        for (int i = tid; i < N; i += plane_threads<N, C2>()) twl[i] = tw[i];
+        __syncthreads();
+    }
     const int b0 = blockIdx.y * kBandsPerBlock, b1 = min(b0 + kBandsPerBlock, nb);
     const int nbk = b1 - b0;
     const int ncol = 2 * nmax1 + 1;
@@ -191,12 +205,10 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
                 // without loads or stores), since a swap only pairs lanes of
                 // one line.
                 if (kb >= 0 && kb < nbk) {
-                    const C2 *twc = tw;
-                    asm volatile("" : "+s"(twc));
                     if (lower) {
 #pragma unroll
                         for (int e = 0; e < E; ++e) v[e] = act ? col[xlane_index(t, e) * LDX] : cmk<C2>(0.0, 0.0);
-                        xlane96_forward(v, t, twc);
+                        xlane96_forward(v, opaque(t), twl);
                         if (act) {
 #pragma unroll
                             for (int m = 0; m < E; ++m) {
@@ -210,7 +222,7 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
                             const int q = act ? stick_of(t + T * m) : -1;
                             v[m] = q >= 0 ? tz[q] : cmk<C2>(0.0, 0.0);
                         }
-                        xlane96_inverse(v, t, twc);
+                        xlane96_inverse(v, opaque(t), twl);
                         if (act) {
 #pragma unroll
                             for (int e = 0; e < E; ++e) col[xlane_index(t, e) * LDX] = v[e];
@@ -252,20 +264,17 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
                 // line slots are rows here (N T threads), so every lane of
                 // each wavefront takes part in the swaps.
                 static_assert(plane_threads<N, C2>() == N * T && T == 8 && E == 12, "cross-lane rows: 96 x 8 lanes");
-                const C2 *twr = tw;
-                asm volatile("" : "+s"(twr));
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int i = t + T * m;
                     v[m] = (i <= nmax1 || i >= N - nmax1) ? row[at(i)] : cmk<C2>(0.0, 0.0);
                 }
-                xlane96_inverse(v, t, twr);
+                xlane96_inverse(v, opaque(t), twl);
 #pragma unroll
                 for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vp[e]);
-                // the forward transform reloads the twiddles rather than
+                // the forward transform rereads the twiddles rather than
                 // keeping the inverse's thirteen live across the multiply
-                asm volatile("" : "+s"(twr));
-                xlane96_forward(v, t, twr);
+                xlane96_forward(v, opaque(t), twl);
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int i = t + T * m;
@@ -322,8 +331,13 @@ k_plane_density(const double2 *__restrict__ sticks, int nst, int N3, int nb, int
     constexpr int T = C::T, E = C::E, LDX = N + 1, HALF = N / 2;
     constexpr int RL = ListInfo<Inv>::last;
     __shared__ double2 plane[N * LDX];
+    __shared__ double2 twl[xlane_rows<N, double2>() ? N : 1];  // twiddles of the cross-lane transforms
     const int tid = threadIdx.x;
     const int z = blockIdx.x, g = blockIdx.y;
+    if constexpr (xlane_rows<N, double2>()) {
+        for (int i = tid; i < N; i += plane_threads<N, double2>()) twl[i] = tw[i];
+        __syncthreads();
+    }
     const int b0 = g * bpg, b1 = min(b0 + bpg, nb);
     const int ncol = 2 * nmax1 + 1;
     const int slot = line_of<T>(tid);
@@ -377,7 +391,7 @@ k_plane_density(const double2 *__restrict__ sticks, int nst, int N3, int nb, int
                         const int q = act ? stick_of(t + T * m) : -1;
                         v[m] = q >= 0 ? tz[q] : cmk<double2>(0.0, 0.0);
                     }
-                    xlane96_inverse(v, t, tw);
+                    xlane96_inverse(v, opaque(t), twl);
                     if (act) {
 #pragma unroll
                         for (int e = 0; e < E; ++e) col[xlane_index(t, e) * LDX] = v[e];
@@ -404,7 +418,7 @@ k_plane_density(const double2 *__restrict__ sticks, int nst, int N3, int nb, int
                 const int i = t + T * m;
                 v[m] = (i <= nmax1 || i >= N - nmax1) ? row[i] : cmk<double2>(0.0, 0.0);
             }
-            xlane96_inverse(v, t, tw);
+            xlane96_inverse(v, opaque(t), twl);
             const double w0 = weights ? weights[k] : 1.0;
 #pragma unroll
             for (int e = 0; e < E; ++e) acc[e] += w0 * (v[e].x * v[e].x + v[e].y * v[e].y);
@@ -527,6 +541,7 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
     constexpr int T = C::T, E = C::E, S = kStickThreads / T, LD = N3 + 1;
     __shared__ C2 tile[S * LD];
     __shared__ double red[kStickThreads / 64];
+    __shared__ C2 twl[xlane_rows<N3, C2>() ? N3 : 1];  // twiddles of the cross-lane transform
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
     const int s0 = blockIdx.x * S, band = blockIdx.y;
     const int s = s0 + sl;
@@ -537,9 +552,11 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
     if constexpr (xlane_rows<N3, C2>()) {
         // cross-lane transform: inputs read in the schedule's register order
         // (zero past the last stick), outputs x[t + T m]
+        for (int i = tid; i < N3; i += kStickThreads) twl[i] = tw[i];
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = act ? in[(size_t)xlane_index(t, e) * nst + s] : cmk<C2>(0.0, 0.0);
-        xlane96_forward(v, t, tw);
+        __syncthreads();
+        xlane96_forward(v, opaque(t), twl);
 #pragma unroll
         for (int m = 0; m < E; ++m) line[t + T * m] = v[m];
     } else {

@@ -473,14 +473,18 @@ template <int B> __device__ __forceinline__ void xstage_fwd(double2 (&v)[12], do
     }
 }
 
-// tw[m] = exp(-2 pi i m / 96).  Inverse: v[m] = x[t + 8 m] on entry, v[s] =
-// X[xlane_index(t, s)] (sign +1, unnormalised) on exit.
+// tw[m] = exp(-2 pi i m / 96), an LDS copy of the plan's table: every
+// transform reads 13 twiddles, and through the vector memory path these
+// loads cost more than the arithmetic around them.  Callers pass t through
+// an opaque copy at each call, so that the compiler does not hoist the
+// twiddle reads of one call site into registers across the others.
+// Inverse: v[m] = x[t + 8 m] on entry, v[s] = X[xlane_index(t, s)] (sign
+// +1, unnormalised) on exit.
 __device__ __forceinline__ void xlane96_inverse(double2 (&v)[12], int t, const double2 *__restrict__ tw)
 {
     Dft<12, +1>::run(v);
 #pragma unroll
     for (int k = 1; k < 12; ++k) v[k] = cmul(v[k], cconj(tw[t * k]));
-    asm volatile("" : "+s"(tw));  // stage twiddles loaded here, not up front
     xstage_inv<2>(v, cconj(tw[12 * (t & 3)]));
     xstage_inv<1>(v, cconj(tw[24 * (t & 1)]));
     xstage_inv<0>(v, make_double2(1.0, 0.0));
@@ -491,7 +495,6 @@ __device__ __forceinline__ void xlane96_forward(double2 (&v)[12], int t, const d
     xstage_fwd<0>(v, make_double2(1.0, 0.0));
     xstage_fwd<1>(v, tw[24 * (t & 1)]);
     xstage_fwd<2>(v, tw[12 * (t & 3)]);
-    asm volatile("" : "+s"(tw));
 #pragma unroll
     for (int k = 1; k < 12; ++k) v[k] = cmul(v[k], tw[t * k]);
     Dft<12, -1>::run(v);
