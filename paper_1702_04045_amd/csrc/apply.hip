@@ -70,14 +70,13 @@ k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const
     static_assert(cfg_ok<N3>(), "bad FFT config");
     constexpr int T = C::T, E = C::E, S = kStickThreads / T, LD = N3 + 1;
     __shared__ C2 tile[S * LD];
-    __shared__ C2 twl[xlane_rows<N3, C2>() ? N3 : 1];  // twiddles of the cross-lane transform
+    __shared__ C2 twl[N3];  // LDS copy of the twiddle table
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
     const int s0 = blockIdx.x * S, band = blockIdx.y;
     const int s = s0 + sl;
     const bool act = s < nst;
     for (int i = tid; i < S * LD; i += kStickThreads) tile[i] = cmk<C2>(0.0, 0.0);
-    if constexpr (xlane_rows<N3, C2>())
-        for (int i = tid; i < N3; i += kStickThreads) twl[i] = tw[i];
+    for (int i = tid; i < N3; i += kStickThreads) twl[i] = tw[i];
     __syncthreads();
     const int p0 = st_start[s0], p1 = st_start[min(s0 + S, nst)];
     const C2 *x = src + band * ld;
@@ -112,7 +111,7 @@ k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const
         }
     } else {
         if (act) pass_load<N3, T, E, ListInfo<typename C::Inv>::first>(v, t, [&](int i) { return line[i]; });
-        stockham<N3, +1, true>(typename C::Inv{}, v, t, act, line, 1, tw);
+        stockham<N3, +1, true>(typename C::Inv{}, v, t, act, line, 1, twl);
         if (act)
             final_foreach<N3, T, E, ListInfo<typename C::Inv>::last>(
                 v, t, [&](int i, int e) { out[(size_t)i * nst + s] = v[e]; });
@@ -151,13 +150,11 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
     constexpr int T = C::T, E = C::E, LDX = N + 1, HALF = N / 2;
     constexpr int RL = ListInfo<Inv>::last;
     __shared__ C2 plane[N * LDX];
-    __shared__ C2 twl[xlane_rows<N, C2>() ? N : 1];  // twiddles of the cross-lane transforms
+    __shared__ C2 twl[N];  // LDS copy of the twiddle table
     const int tid = threadIdx.x;
     const int z = blockIdx.x;
-    if constexpr (xlane_rows<N, C2>()) {
-        for (int i = tid; i < N; i += plane_threads<N, C2>()) twl[i] = tw[i];
-        __syncthreads();
-    }
+    for (int i = tid; i < N; i += plane_threads<N, C2>()) twl[i] = tw[i];
+    __syncthreads();
     const int b0 = blockIdx.y * kBandsPerBlock, b1 = min(b0 + kBandsPerBlock, nb);
     const int nbk = b1 - b0;
     const int ncol = 2 * nmax1 + 1;
@@ -231,7 +228,7 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
                 }
             } else if (lower) {
                 if (act) pass_load<N, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return col[i * LDX]; });
-                stockham_c<C, -1, true>(Fwd{}, v, t, act, col, LDX, tw);
+                stockham_c<C, -1, true>(Fwd{}, v, t, act, col, LDX, twl);
                 if (act) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
                     const int q = stick_of(i);
                     if (q >= 0) tz[q] = v[e];
@@ -241,7 +238,7 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
                     const int q = stick_of(i);
                     return q >= 0 ? tz[q] : cmk<C2>(0.0, 0.0);
                 });
-                stockham_c<C, +1, true>(Inv{}, v, t, act, col, LDX, tw);
+                stockham_c<C, +1, true>(Inv{}, v, t, act, col, LDX, twl);
                 wave_lds_sync();
                 if (act) final_foreach<N, T, E, RL>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
             }
@@ -287,10 +284,10 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
                 if (rowact) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
                     return (i <= nmax1 || i >= N - nmax1) ? row[at(i)] : cmk<C2>(0.0, 0.0);
                 });
-                stockham_c<C, +1, true>(Inv{}, v, t, rowact, row, 1, tw);
+                stockham_c<C, +1, true>(Inv{}, v, t, rowact, row, 1, twl);
 #pragma unroll
                 for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vr[e]);
-                stockham_c<C, -1, true>(Fwd{}, v, t, rowact, row, 1, tw);
+                stockham_c<C, -1, true>(Fwd{}, v, t, rowact, row, 1, twl);
                 wave_lds_sync();
                 if (rowact) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
                     if (i <= nmax1 || i >= N - nmax1) row[at(i)] = v[e];
@@ -331,13 +328,11 @@ k_plane_density(const double2 *__restrict__ sticks, int nst, int N3, int nb, int
     constexpr int T = C::T, E = C::E, LDX = N + 1, HALF = N / 2;
     constexpr int RL = ListInfo<Inv>::last;
     __shared__ double2 plane[N * LDX];
-    __shared__ double2 twl[xlane_rows<N, double2>() ? N : 1];  // twiddles of the cross-lane transforms
+    __shared__ double2 twl[N];  // LDS copy of the twiddle table
     const int tid = threadIdx.x;
     const int z = blockIdx.x, g = blockIdx.y;
-    if constexpr (xlane_rows<N, double2>()) {
-        for (int i = tid; i < N; i += plane_threads<N, double2>()) twl[i] = tw[i];
-        __syncthreads();
-    }
+    for (int i = tid; i < N; i += plane_threads<N, double2>()) twl[i] = tw[i];
+    __syncthreads();
     const int b0 = g * bpg, b1 = min(b0 + bpg, nb);
     const int ncol = 2 * nmax1 + 1;
     const int slot = line_of<T>(tid);
@@ -402,7 +397,7 @@ k_plane_density(const double2 *__restrict__ sticks, int nst, int N3, int nb, int
                     const int q = stick_of(i);
                     return q >= 0 ? tz[q] : cmk<double2>(0.0, 0.0);
                 });
-                stockham_c<C, +1, true>(Inv{}, v, t, act, col, LDX, tw);
+                stockham_c<C, +1, true>(Inv{}, v, t, act, col, LDX, twl);
                 wave_lds_sync();
                 if (act) final_foreach<N, T, E, RL>(v, t, [&](int i, int e) { col[i * LDX] = v[e]; });
             }
@@ -445,7 +440,7 @@ k_plane_density(const double2 *__restrict__ sticks, int nst, int N3, int nb, int
 #pragma unroll
                 for (int e = 0; e < E; ++e) acc[e] = stash[e];
             wave_lds_sync();
-            stockham_c<C, +1, true>(Inv{}, v0, t, rowact, row, 1, tw);
+            stockham_c<C, +1, true>(Inv{}, v0, t, rowact, row, 1, twl);
             const double w0 = weights ? weights[k] : 1.0;
 #pragma unroll
             for (int e = 0; e < E; ++e) acc[e] += w0 * (v0[e].x * v0[e].x + v0[e].y * v0[e].y);
@@ -457,7 +452,7 @@ k_plane_density(const double2 *__restrict__ sticks, int nst, int N3, int nb, int
             }
             if (PAIR && two) {
                 wave_lds_sync();
-                stockham_c<C, +1, true>(Inv{}, v1, t, rowact, row, 1, tw);
+                stockham_c<C, +1, true>(Inv{}, v1, t, rowact, row, 1, twl);
                 const double w1 = weights ? weights[k + 1] : 1.0;
 #pragma unroll
                 for (int e = 0; e < E; ++e) acc[e] += w1 * (v1[e].x * v1[e].x + v1[e].y * v1[e].y);
@@ -541,27 +536,27 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
     constexpr int T = C::T, E = C::E, S = kStickThreads / T, LD = N3 + 1;
     __shared__ C2 tile[S * LD];
     __shared__ double red[kStickThreads / 64];
-    __shared__ C2 twl[xlane_rows<N3, C2>() ? N3 : 1];  // twiddles of the cross-lane transform
+    __shared__ C2 twl[N3];  // LDS copy of the twiddle table
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
     const int s0 = blockIdx.x * S, band = blockIdx.y;
     const int s = s0 + sl;
     const bool act = s < nst;
     const C2 *in = sticks + (size_t)band * N3 * nst;
+    for (int i = tid; i < N3; i += kStickThreads) twl[i] = tw[i];
+    __syncthreads();
     C2 v[E];
     C2 *line = tile + sl * LD;
     if constexpr (xlane_rows<N3, C2>()) {
         // cross-lane transform: inputs read in the schedule's register order
         // (zero past the last stick), outputs x[t + T m]
-        for (int i = tid; i < N3; i += kStickThreads) twl[i] = tw[i];
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = act ? in[(size_t)xlane_index(t, e) * nst + s] : cmk<C2>(0.0, 0.0);
-        __syncthreads();
         xlane96_forward(v, opaque(t), twl);
 #pragma unroll
         for (int m = 0; m < E; ++m) line[t + T * m] = v[m];
     } else {
         if (act) pass_load<N3, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return in[(size_t)i * nst + s]; });
-        stockham<N3, -1, true>(Fwd{}, v, t, act, line, 1, tw);
+        stockham<N3, -1, true>(Fwd{}, v, t, act, line, 1, twl);
         wave_lds_sync();
         if (act) final_foreach<N3, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) { line[i] = v[e]; });
     }

@@ -341,11 +341,17 @@ template <bool WL> __device__ __forceinline__ void line_sync()
 template <int N, int T, int E, int SIGN, bool WL, int NS, int R, int... Rest, class C2>
 __device__ __forceinline__ void stockham_rec(C2 (&v)[E], int t, bool act, C2 *line, int es, const C2 *tw)
 {
-    // A fresh copy of the table pointer per pass keeps the compiler from
-    // loading the twiddles of later passes (or other transforms) up front,
-    // which costs registers; without work-group barriers nothing else
-    // bounds that code motion.
-    if constexpr (NS > 1) asm volatile("" : "+s"(tw));
+    // An opaque zero offset per pass keeps the compiler from loading the
+    // twiddles of later passes (or other transforms) up front, which costs
+    // registers; without work-group barriers nothing else bounds that code
+    // motion.  The offset, not the pointer, is made opaque: the pointer keeps
+    // its address space, so the reads stay global or LDS reads (a flat read
+    // would also hold up every LDS wait of the exchanges).
+    if constexpr (NS > 1) {
+        int zero = 0;
+        asm volatile("" : "+s"(zero));
+        tw += zero;
+    }
     if (act) pass_compute<N, T, E, R, NS, SIGN>(v, t, tw);
     if constexpr (sizeof...(Rest) > 0) {
         constexpr int R2 = FirstOf<Rest...>::value;
@@ -369,9 +375,9 @@ __device__ __forceinline__ void stockham_c(RList<Rs...>, C2 (&v)[Cfg::E], int t,
                                            const C2 *__restrict__ tw)
 {
     static_assert(!WL || 64 % Cfg::T == 0, "wave-local lines need T | 64");
-    const C2 *twl = tw;
-    asm volatile("" : "+s"(twl));
-    stockham_rec<Cfg::N, Cfg::T, Cfg::E, SIGN, WL, 1, Rs...>(v, t, act, line, es, twl);
+    int zero = 0;
+    asm volatile("" : "+s"(zero));
+    stockham_rec<Cfg::N, Cfg::T, Cfg::E, SIGN, WL, 1, Rs...>(v, t, act, line, es, tw + zero);
 }
 
 template <int N, int SIGN, bool WL = false, int... Rs, class C2>
