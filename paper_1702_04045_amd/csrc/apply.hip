@@ -178,12 +178,15 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
         const int k = (i > N / 2 ? i - N : i) - ylo;
         return (unsigned)k < (unsigned)cnt ? k : -1;
     };
-    const VR *vp = vperm + (((size_t)z * N + (rowact ? slot : 0)) * T + t) * E;
+    int64_t vofs = (((int64_t)z * N + (rowact ? slot : 0)) * T + t) * E;  // this thread's potential values
     for (int k = 0; k <= nbk; ++k) {
         // Opaque per band: keeps the compiler from hoisting the potential
         // loads and the per-element stick offsets out of the band loop,
         // which would hold them in registers across all stages.
-        asm volatile("" : "+v"(ylo), "+v"(cnt), "+v"(vp));
+        // (The offset, not a pointer, is made opaque: the loads stay global
+        // loads; a flat load would hold up the LDS waits as well.)
+        asm volatile("" : "+v"(ylo), "+v"(cnt), "+v"(vofs));
+        const VR *vp = vperm + vofs;
         C2 v[E];
         {
             // column phase: forward of band k-1 (lower), inverse of band k (upper)
