@@ -47,7 +47,7 @@ template <int N, class C2> constexpr int plane_threads() { return (N * PlaneCfgP
 constexpr int kBandsPerBlock = 4;  // bands one work-group of the plane kernel takes through its z-plane
 // Row transforms of the plane kernel done across lanes (xlane96_inverse /
 // xlane96_forward) instead of through LDS: the FP64 96-point plane.
-template <int N, class C2> constexpr bool xlane_rows() { return N == 96 && std::is_same<C2, double2>::value; }
+template <int N, class C2> constexpr bool xlane_rows() { return N == 96; }
 // an opaque copy of the line thread index for one cross-lane call site
 __device__ __forceinline__ int opaque(int t)
 {

@@ -408,6 +408,7 @@ __host__ __device__ constexpr int xlane_index(int t, int s)
 }
 
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 
 // Lane swap on thread bit B: the line's lower lane (bit B clear) receives
 // the upper lane's p in q, the upper lane receives the lower lane's q in p.
@@ -432,15 +433,16 @@ template <> __device__ __forceinline__ void xswap32<0>(uint32_t &p, uint32_t &q)
     q = (uint32_t)__builtin_amdgcn_update_dpp(q0, p0, 0x128, 0xf, 0x3, false);
     p = (uint32_t)__builtin_amdgcn_update_dpp(p0, q0, 0x128, 0xf, 0xc, false);
 }
-template <int B> __device__ __forceinline__ void xswap(double2 &p, double2 &q)
+template <int B, class C2> __device__ __forceinline__ void xswap(C2 &p, C2 &q)
 {
-    uint32_t a[4], b[4];
-    __builtin_memcpy(a, &p, 16);
-    __builtin_memcpy(b, &q, 16);
+    constexpr int W = sizeof(C2) / 4;  // 32-bit words per complex value
+    uint32_t a[W], b[W];
+    __builtin_memcpy(a, &p, sizeof(C2));
+    __builtin_memcpy(b, &q, sizeof(C2));
 #pragma unroll
-    for (int i = 0; i < 4; ++i) xswap32<B>(a[i], b[i]);
-    __builtin_memcpy(&p, a, 16);
-    __builtin_memcpy(&q, b, 16);
+    for (int i = 0; i < W; ++i) xswap32<B>(a[i], b[i]);
+    __builtin_memcpy(&p, a, sizeof(C2));
+    __builtin_memcpy(&q, b, sizeof(C2));
 }
 
 // register pairs of the butterflies of the stage on thread bit B
@@ -454,25 +456,25 @@ template <int B> __device__ __forceinline__ constexpr int xpair_hi(int i)
 }
 
 // inverse-direction stage: swap, then (u, v) -> (u + v, (u - v) w)
-template <int B> __device__ __forceinline__ void xstage_inv(double2 (&v)[12], double2 w)
+template <int B, class C2> __device__ __forceinline__ void xstage_inv(C2 (&v)[12], C2 w)
 {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        double2 &a = v[xpair_lo<B>(i)], &b = v[xpair_hi<B>(i)];
+        C2 &a = v[xpair_lo<B>(i)], &b = v[xpair_hi<B>(i)];
         xswap<B>(a, b);
-        const double2 u = a, d = csub(a, b);
+        const C2 u = a, d = csub(a, b);
         a = cadd(u, b);
         b = B == 0 ? d : cmul(d, w);
     }
 }
 // its conjugate transpose: (a, b) -> (a + b w*, a - b w*), then the same swap
-template <int B> __device__ __forceinline__ void xstage_fwd(double2 (&v)[12], double2 wc)
+template <int B, class C2> __device__ __forceinline__ void xstage_fwd(C2 (&v)[12], C2 wc)
 {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-        double2 &a = v[xpair_lo<B>(i)], &b = v[xpair_hi<B>(i)];
-        const double2 c = B == 0 ? b : cmul(b, wc);
-        const double2 u = a;
+        C2 &a = v[xpair_lo<B>(i)], &b = v[xpair_hi<B>(i)];
+        const C2 c = B == 0 ? b : cmul(b, wc);
+        const C2 u = a;
         a = cadd(u, c);
         b = csub(u, c);
         xswap<B>(a, b);
@@ -486,19 +488,19 @@ template <int B> __device__ __forceinline__ void xstage_fwd(double2 (&v)[12], do
 // twiddle reads of one call site into registers across the others.
 // Inverse: v[m] = x[t + 8 m] on entry, v[s] = X[xlane_index(t, s)] (sign
 // +1, unnormalised) on exit.
-__device__ __forceinline__ void xlane96_inverse(double2 (&v)[12], int t, const double2 *__restrict__ tw)
+template <class C2> __device__ __forceinline__ void xlane96_inverse(C2 (&v)[12], int t, const C2 *__restrict__ tw)
 {
     Dft<12, +1>::run(v);
 #pragma unroll
     for (int k = 1; k < 12; ++k) v[k] = cmul(v[k], cconj(tw[t * k]));
     xstage_inv<2>(v, cconj(tw[12 * (t & 3)]));
     xstage_inv<1>(v, cconj(tw[24 * (t & 1)]));
-    xstage_inv<0>(v, make_double2(1.0, 0.0));
+    xstage_inv<0>(v, cmk<C2>(1.0, 0.0));
 }
 // Forward (sign -1) from the layout xlane96_inverse leaves: v[m] = y[t + 8 m] on exit.
-__device__ __forceinline__ void xlane96_forward(double2 (&v)[12], int t, const double2 *__restrict__ tw)
+template <class C2> __device__ __forceinline__ void xlane96_forward(C2 (&v)[12], int t, const C2 *__restrict__ tw)
 {
-    xstage_fwd<0>(v, make_double2(1.0, 0.0));
+    xstage_fwd<0>(v, cmk<C2>(1.0, 0.0));
     xstage_fwd<1>(v, tw[24 * (t & 1)]);
     xstage_fwd<2>(v, tw[12 * (t & 3)]);
 #pragma unroll
@@ -517,15 +519,7 @@ template <> struct PlaneCfg<96> {
     using Inv = RList<4, 6, 4>;
     using Fwd = RList<4, 6, 4>;
 };
-// Per precision: in single precision the 96-point plane uses 4 threads per
-// line and two passes (12 x 8, one LDS exchange); measured faster than 8
-// threads per line, and than capping registers so that two 75 KB
-// work-groups share a compute unit.
+// Per precision (both precisions use the 96-point schedule above).
 template <int N, class C2> struct PlaneCfgP : PlaneCfg<N> {};
-template <> struct PlaneCfgP<96, float2> {
-    static constexpr int N = 96, T = 4, E = 24, min_waves = 1;
-    using Inv = RList<12, 8>;
-    using Fwd = RList<8, 12>;
-};
 
 }  // namespace paro
