@@ -45,8 +45,8 @@ template <int T> __device__ __forceinline__ int thread_in_line(int tid) { return
 // threads of the plane kernel: one line slot per row, rounded up to whole wavefronts
 template <int N, class C2> constexpr int plane_threads() { return (N * PlaneCfgP<N, C2>::T + 63) / 64 * 64; }
 constexpr int kBandsPerBlock = 4;  // bands one work-group of the plane kernel takes through its z-plane
-// Row transforms of the plane kernel done across lanes (xlane96_inverse /
-// xlane96_forward) instead of through LDS: the FP64 96-point plane.
+// Line transforms done across lanes (xlane96_inverse / xlane96_forward)
+// instead of through LDS: the 96-point lines, both precisions.
 template <int N, class C2> constexpr bool xlane_rows() { return N == 96; }
 // an opaque copy of the line thread index for one cross-lane call site
 __device__ __forceinline__ int opaque(int t)

@@ -388,7 +388,7 @@ __device__ __forceinline__ void stockham(RList<Rs...> l, C2 (&v)[FftCfg<N>::E], 
 }
 
 // ---------------------------------------------------------------------------
-// 96-point transform of one line across 8 lanes without LDS (FP64).
+// 96-point transform of one line across 8 lanes without LDS (FP64 or FP32).
 //
 // Thread t of the line (lane bits 3, 4, 5 = bits 0, 1, 2 of t) holds
 // x[t + 8 m], m < 12.  Four-step split 96 = 12 x 8: a 12-point DFT over m in
