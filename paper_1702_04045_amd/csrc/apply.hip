@@ -48,6 +48,13 @@ constexpr int kBandsPerBlock = 4;  // bands one work-group of the plane kernel t
 // Line transforms done across lanes (xlane96_inverse / xlane96_forward)
 // instead of through LDS: the 96-point lines, both precisions.
 template <int N, class C2> constexpr bool xlane_rows() { return N == 96; }
+// Plans need N >= 4 n_max + 1 on every axis, so at N = 96 every populated
+// index has |n| <= 23: a line's inputs x[t + 8 m] with m = 3..8 (indices
+// 24..71) are zero and those outputs are never used.  The cross-lane
+// kernels neither load nor store them and run the pruned 12-point DFTs
+// (xlane_kept, xlane96_inverse<true>, xlane96_forward<true>).
+static_assert(4 * 24 + 1 > 96, "at 96 points every populated |n| is below 24");
+constexpr bool kXlanePrune = true;
 // an opaque copy of the line thread index for one cross-lane call site
 __device__ __forceinline__ int opaque(int t)
 {
@@ -103,8 +110,8 @@ k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const
         // cross-lane transform (every lane takes part; the tile is zero past
         // the last stick), outputs stored in the schedule's register order
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = line[t + T * m];
-        xlane96_inverse(v, opaque(t), twl);
+        for (int m = 0; m < E; ++m) v[m] = xlane_kept(m) ? line[t + T * m] : cmk<C2>(0.0, 0.0);
+        xlane96_inverse<kXlanePrune>(v, opaque(t), twl);
         if (act) {
 #pragma unroll
             for (int e = 0; e < E; ++e) out[(size_t)xlane_index(t, e) * nst + s] = v[e];
@@ -208,10 +215,11 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
                     if (lower) {
 #pragma unroll
                         for (int e = 0; e < E; ++e) v[e] = act ? col[xlane_index(t, e) * LDX] : cmk<C2>(0.0, 0.0);
-                        xlane96_forward(v, opaque(t), twl);
+                        xlane96_forward<kXlanePrune>(v, opaque(t), twl);
                         if (act) {
 #pragma unroll
                             for (int m = 0; m < E; ++m) {
+                                if (!xlane_kept(m)) continue;
                                 const int q = stick_of(t + T * m);
                                 if (q >= 0) tz[q] = v[m];
                             }
@@ -219,10 +227,10 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
                     } else {
 #pragma unroll
                         for (int m = 0; m < E; ++m) {
-                            const int q = act ? stick_of(t + T * m) : -1;
+                            const int q = (act && xlane_kept(m)) ? stick_of(t + T * m) : -1;
                             v[m] = q >= 0 ? tz[q] : cmk<C2>(0.0, 0.0);
                         }
-                        xlane96_inverse(v, opaque(t), twl);
+                        xlane96_inverse<kXlanePrune>(v, opaque(t), twl);
                         if (act) {
 #pragma unroll
                             for (int e = 0; e < E; ++e) col[xlane_index(t, e) * LDX] = v[e];
@@ -267,18 +275,18 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int i = t + T * m;
-                    v[m] = (i <= nmax1 || i >= N - nmax1) ? row[at(i)] : cmk<C2>(0.0, 0.0);
+                    v[m] = (xlane_kept(m) && (i <= nmax1 || i >= N - nmax1)) ? row[at(i)] : cmk<C2>(0.0, 0.0);
                 }
-                xlane96_inverse(v, opaque(t), twl);
+                xlane96_inverse<kXlanePrune>(v, opaque(t), twl);
 #pragma unroll
                 for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vp[e]);
                 // the forward transform rereads the twiddles rather than
                 // keeping the inverse's thirteen live across the multiply
-                xlane96_forward(v, opaque(t), twl);
+                xlane96_forward<kXlanePrune>(v, opaque(t), twl);
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int i = t + T * m;
-                    if (i <= nmax1 || i >= N - nmax1) row[at(i)] = v[m];
+                    if (xlane_kept(m) && (i <= nmax1 || i >= N - nmax1)) row[at(i)] = v[m];
                 }
             } else {
                 VR vr[E];
@@ -386,10 +394,10 @@ k_plane_density(const double2 *__restrict__ sticks, int nst, int N3, int nb, int
                 if (lower) {
 #pragma unroll
                     for (int m = 0; m < E; ++m) {
-                        const int q = act ? stick_of(t + T * m) : -1;
+                        const int q = (act && xlane_kept(m)) ? stick_of(t + T * m) : -1;
                         v[m] = q >= 0 ? tz[q] : cmk<double2>(0.0, 0.0);
                     }
-                    xlane96_inverse(v, opaque(t), twl);
+                    xlane96_inverse<kXlanePrune>(v, opaque(t), twl);
                     if (act) {
 #pragma unroll
                         for (int e = 0; e < E; ++e) col[xlane_index(t, e) * LDX] = v[e];
@@ -414,9 +422,9 @@ k_plane_density(const double2 *__restrict__ sticks, int nst, int N3, int nb, int
 #pragma unroll
             for (int m = 0; m < E; ++m) {
                 const int i = t + T * m;
-                v[m] = (i <= nmax1 || i >= N - nmax1) ? row[i] : cmk<double2>(0.0, 0.0);
+                v[m] = (xlane_kept(m) && (i <= nmax1 || i >= N - nmax1)) ? row[i] : cmk<double2>(0.0, 0.0);
             }
-            xlane96_inverse(v, opaque(t), twl);
+            xlane96_inverse<kXlanePrune>(v, opaque(t), twl);
             const double w0 = weights ? weights[k] : 1.0;
 #pragma unroll
             for (int e = 0; e < E; ++e) acc[e] += w0 * (v[e].x * v[e].x + v[e].y * v[e].y);
@@ -554,9 +562,10 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
         // (zero past the last stick), outputs x[t + T m]
 #pragma unroll
         for (int e = 0; e < E; ++e) v[e] = act ? in[(size_t)xlane_index(t, e) * nst + s] : cmk<C2>(0.0, 0.0);
-        xlane96_forward(v, opaque(t), twl);
+        xlane96_forward<kXlanePrune>(v, opaque(t), twl);
 #pragma unroll
-        for (int m = 0; m < E; ++m) line[t + T * m] = v[m];
+        for (int m = 0; m < E; ++m)
+            if (xlane_kept(m)) line[t + T * m] = v[m];
     } else {
         if (act) pass_load<N3, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return in[(size_t)i * nst + s]; });
         stockham<N3, -1, true>(Fwd{}, v, t, act, line, 1, twl);

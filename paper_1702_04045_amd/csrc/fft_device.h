@@ -488,9 +488,88 @@ template <int B, class C2> __device__ __forceinline__ void xstage_fwd(C2 (&v)[12
 // twiddle reads of one call site into registers across the others.
 // Inverse: v[m] = x[t + 8 m] on entry, v[s] = X[xlane_index(t, s)] (sign
 // +1, unnormalised) on exit.
-template <class C2> __device__ __forceinline__ void xlane96_inverse(C2 (&v)[12], int t, const C2 *__restrict__ tw)
+// Pruned 12-point DFTs (the DftComp<4, 3> order of Dft<12>) for lines whose
+// populated indices all lie within |n| <= 23, so that x[t + 8 m] is zero
+// for m = 3..8 on input and those outputs are never used.  Every output
+// that is computed comes from the same floating-point operations as in
+// Dft<12>, less additions of exact zeros and with a subtraction in place of
+// adding a negation, so the values agree with the full transform's (up to
+// the sign of an exact zero).
+__host__ __device__ constexpr bool xlane_kept(int m) { return m < 3 || m > 8; }
+
+template <int SIGN, class C2> __device__ __forceinline__ void dft12_twiddle(C2 (&b)[3], int ka)
 {
-    Dft<12, +1>::run(v);
+    using S = RealOf<C2>;
+#pragma unroll
+    for (int sb = 1; sb < 3; ++sb) {
+        const int j = sb * ka;
+        if (j != 0) {
+            const S c = (S)TwC<12>::c[j], sn = (S)(SIGN * TwC<12>::s[j]);
+            C2 r;
+            r.x = b[sb].x * c - b[sb].y * sn;
+            r.y = b[sb].x * sn + b[sb].y * c;
+            b[sb] = r;
+        }
+    }
+}
+// inputs 3..8 zero: the 4-point DFTs over s_a see only s_a = 0 and 3
+template <int SIGN, class C2> __device__ __forceinline__ void dft12_in_pruned(C2 (&v)[12])
+{
+    C2 y[12];
+#pragma unroll
+    for (int sb = 0; sb < 3; ++sb) {
+        const C2 a0 = v[sb], a3 = v[9 + sb];
+        const C2 d = mul_si<SIGN>(a3);
+        y[sb * 4 + 0] = cadd(a0, a3);
+        y[sb * 4 + 2] = csub(a0, a3);
+        y[sb * 4 + 1] = csub(a0, d);
+        y[sb * 4 + 3] = cadd(a0, d);
+    }
+#pragma unroll
+    for (int ka = 0; ka < 4; ++ka) {
+        C2 b[3] = {y[ka], y[4 + ka], y[8 + ka]};
+        dft12_twiddle<SIGN>(b, ka);
+        Dft<3, SIGN>::run(b);
+#pragma unroll
+        for (int kb = 0; kb < 3; ++kb) v[ka + 4 * kb] = b[kb];
+    }
+}
+// outputs 3..8 unused: of the 3-point DFTs only the outputs k_a + 4 k_b
+// with k = 0, 1, 2, 9, 10, 11 are formed (outputs 3..8 are left undefined)
+template <int SIGN, class C2> __device__ __forceinline__ void dft12_out_pruned(C2 (&v)[12])
+{
+    using S = RealOf<C2>;
+    C2 y[12];
+#pragma unroll
+    for (int sb = 0; sb < 3; ++sb) {
+        C2 a[4] = {v[sb], v[3 + sb], v[6 + sb], v[9 + sb]};
+        Dft<4, SIGN>::run(a);
+#pragma unroll
+        for (int ka = 0; ka < 4; ++ka) y[sb * 4 + ka] = a[ka];
+    }
+#pragma unroll
+    for (int ka = 0; ka < 4; ++ka) {
+        C2 b[3] = {y[ka], y[4 + ka], y[8 + ka]};
+        dft12_twiddle<SIGN>(b, ka);
+        // the operations of Dft<3> for the outputs that are needed
+        const S h = (S)0.8660254037844386467637;  // sin(2 pi / 3)
+        const C2 t1 = cadd(b[1], b[2]);
+        if (ka < 3) v[ka] = cadd(b[0], t1);  // k_b = 0
+        if (ka > 0) {                          // k_b = 2
+            C2 t2;
+            t2.x = b[0].x - (S)0.5 * t1.x;
+            t2.y = b[0].y - (S)0.5 * t1.y;
+            const C2 it3 = mul_si<SIGN>(cscale(csub(b[1], b[2]), h));
+            v[ka + 8] = csub(t2, it3);
+        }
+    }
+}
+
+template <bool PRUNE = false, class C2>
+__device__ __forceinline__ void xlane96_inverse(C2 (&v)[12], int t, const C2 *__restrict__ tw)
+{
+    if constexpr (PRUNE) dft12_in_pruned<+1>(v);
+    else Dft<12, +1>::run(v);
 #pragma unroll
     for (int k = 1; k < 12; ++k) v[k] = cmul(v[k], cconj(tw[t * k]));
     xstage_inv<2>(v, cconj(tw[12 * (t & 3)]));
@@ -498,14 +577,16 @@ template <class C2> __device__ __forceinline__ void xlane96_inverse(C2 (&v)[12],
     xstage_inv<0>(v, cmk<C2>(1.0, 0.0));
 }
 // Forward (sign -1) from the layout xlane96_inverse leaves: v[m] = y[t + 8 m] on exit.
-template <class C2> __device__ __forceinline__ void xlane96_forward(C2 (&v)[12], int t, const C2 *__restrict__ tw)
+template <bool PRUNE = false, class C2>
+__device__ __forceinline__ void xlane96_forward(C2 (&v)[12], int t, const C2 *__restrict__ tw)
 {
     xstage_fwd<0>(v, cmk<C2>(1.0, 0.0));
     xstage_fwd<1>(v, tw[24 * (t & 1)]);
     xstage_fwd<2>(v, tw[12 * (t & 3)]);
 #pragma unroll
     for (int k = 1; k < 12; ++k) v[k] = cmul(v[k], tw[t * k]);
-    Dft<12, -1>::run(v);
+    if constexpr (PRUNE) dft12_out_pruned<-1>(v);
+    else Dft<12, -1>::run(v);
 }
 
 // Line schedule of the z-plane kernel (defaults to FftCfg).  For 96 points
