@@ -99,3 +99,23 @@ def test_forward_of_multiplied_block_is_the_convolution_step(seed):
     y = forward(R * Vr)
     ref = np.fft.fft(V * (np.fft.ifft(x) * N))
     assert np.abs(y - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_pruned_positions_are_never_populated_on_accepted_grids():
+    """Plans need N >= 4 n_max + 1, so at N = 96 every n_max <= 23, and no
+    populated index i = n mod 96 (|n| <= n_max) sits at a pruned position
+    t + 8 m with m = 3..8 (the kernels neither load nor store those)."""
+    nmax_limit = max(n for n in range(96) if 96 >= 4 * n + 1)
+    assert nmax_limit == 23
+    for nmax in range(nmax_limit + 1):
+        for n in range(-nmax, nmax + 1):
+            i = n % N
+            assert not 3 <= i // T <= 8, (nmax, n)
+    # and a line with only those positions populated transforms like the full one
+    rng = np.random.default_rng(5)
+    x = np.zeros(N, complex)
+    kept = [i for i in range(N) if not 3 <= i // T <= 8]
+    x[kept] = rng.standard_normal(len(kept)) + 1j * rng.standard_normal(len(kept))
+    R = inverse(x)
+    X = np.fft.ifft(x) * N
+    assert max(abs(R[t, s] - X[xlane_index(t, s)]) for t in range(T) for s in range(E)) < 1e-12 * np.abs(X).max()
