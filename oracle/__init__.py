@@ -23,12 +23,17 @@ SRC_PATH = os.path.join(_HERE, "paro_oracle.c")
 F_NEGCURV, F_CHOL, F_NAN = 1, 2, 4
 
 
+# -march=x86-64-v3 (AVX2 + FMA) rather than -march=native: the library is
+# built once and may run on a host with another CPU model.
+CFLAGS = ["-O3", "-march=x86-64-v3", "-fopenmp", "-std=gnu11"]
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (generic x86-64, -O2, OpenMP)."""
+    """Compile the oracle with gcc (CFLAGS, OpenMP)."""
     if force or not os.path.exists(LIB_PATH) or \
             os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
         tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-std=gnu11", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", *CFLAGS, "-shared", "-fPIC",
                                SRC_PATH, "-o", tmp, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -74,6 +79,7 @@ def _load():
         "orc_paro": (C.c_int32, [_vp, C.c_int32, _vp, _vp, _dp, C.c_int32, C.c_int32, C.c_int32,
                                  C.c_int32, C.c_double, _dp, _dp, _dp]),
         "orc_num_threads": (C.c_int32, []),
+        "orc_residual_norms": (None, [C.c_int64, C.c_int32, _vp, _vp, _dp, _dp]),
         "orc_density": (None, [_vp, C.c_int32, _vp, _dp, _dp]),
         "orc_projector_gradient": (None, [_vp, C.c_int32, _vp, _dp, _dp, _dp]),
     }
@@ -165,6 +171,16 @@ def cholesky(A):
 
 def teter(x):
     return _load().orc_teter(float(x))
+
+
+def residual_norms(psi, hpsi, eps):
+    """|hpsi_b - eps_b psi_b| per band (bands x n_g blocks)."""
+    psi, hpsi = _cc(psi), _cc(hpsi)
+    nb, ng = psi.shape
+    eps = _cd(eps)
+    res = np.zeros(nb)
+    _load().orc_residual_norms(ng, nb, _v(psi), _v(hpsi), _d(eps), _d(res))
+    return res
 
 
 def rayleigh_ritz(U, W, nkeep):

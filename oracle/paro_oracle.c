@@ -848,6 +848,12 @@ static void residual_norms(int64_t ng, int nb, const cplx *psi, const cplx *hpsi
     }
 }
 
+void orc_residual_norms(int64_t ng, int32_t nb, const cplx *psi, const cplx *hpsi, const double *eps,
+                        double *res)
+{
+    residual_norms(ng, nb, psi, hpsi, eps, res);
+}
+
 /* ------------------------------------------------------------------ */
 /* ParO at fixed cutoff and potential (Algorithm 1 with steps 1, 3, 4,  */
 /* 5; the cutoff is not raised).  variant 0: Algorithm 1, RR on the      */

@@ -527,8 +527,12 @@ k_tridiag_rows(int m, double2 *__restrict__ A, double *__restrict__ d, double *_
 // rewritten two columns later, after every reader has passed the next
 // column's exchange.  Every wait has a time limit; a work-group that
 // reaches it raises a global abort flag that ends every other wait, and
-// sets PARO_F_SYNC.  The launch is cooperative, so the work-groups are
-// resident together.  Dynamic LDS: (ceil(m / G) + 2) m + 1 complex values.
+// sets PARO_F_SYNC.  The kTriDistG work-groups are launched as an ordinary
+// grid after a check that one fits on a compute unit (dist_grid_fits):
+// with 16 of them on a 256-unit device they start together, and a
+// work-group held back by other kernels' work-groups starts once those
+// end, so every wait either succeeds or reaches its limit.  Dynamic LDS:
+// (ceil(m / G) + 2) m + 1 complex values.
 constexpr int kTriDistThreads = 256;
 constexpr int kTriDistMin = 93, kTriDistMax = 352;
 // The tridiagonalisation moves to sixteen work-groups only from m = 208:
@@ -738,8 +742,8 @@ __global__ void __launch_bounds__(256) k_fill_i32(int n, int32_t *__restrict__ p
 // the column's flag (2: the pivot failed); every work-group with a column
 // after j waits for the flag, reads column j of L and updates its own
 // columns.  Published columns are final, so no buffer is reused.  Waits
-// are time-limited as in k_tridiag_dist.  Cooperative launch.  Dynamic
-// LDS: (ceil(m / G) + 1) m complex values.
+// are time-limited as in k_tridiag_dist, and the launch is the same
+// ordinary grid.  Dynamic LDS: (ceil(m / G) + 1) m complex values.
 __global__ void __launch_bounds__(kTriDistThreads)
 k_chol_dist(int m, const double2 *__restrict__ gram, int hs, double2 *__restrict__ L, double2 *__restrict__ X,
             int32_t *__restrict__ flags, int32_t *__restrict__ fail, int32_t *__restrict__ status)
@@ -828,29 +832,40 @@ k_chol_dist(int m, const double2 *__restrict__ gram, int hs, double2 *__restrict
     }
 }
 
+// Whether the kTriDistG work-groups of a multi-work-group dense kernel can
+// be resident at once: at least one work-group of NT threads and `lds`
+// bytes of dynamic LDS fits on a compute unit, and the device has at least
+// kTriDistG units.  Checked once per kernel and size class.
+static bool dist_grid_fits(const void *kernel, size_t lds)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kTriDistThreads, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return per_cu >= 1 && cus >= kTriDistG;
+}
+
 // Cholesky of the hermitised S (and hermitised Hs into X when hs): the
 // row-held variant up to m = 320, the first design beyond.
 static void launch_chol(hipStream_t st, int m, const double2 *gram, int hs, double2 *L, double2 *X, int32_t *fail,
                         int32_t *status, int32_t *flags = nullptr)
 {
     if (flags && m >= kTriDistMin && m <= kTriDistMax) {
-        static const hipError_t attr = hipFuncSetAttribute(
-            reinterpret_cast<const void *>(k_chol_dist), hipFuncAttributeMaxDynamicSharedMemorySize,
-            (int)(sizeof(double2) * (((size_t)(kTriDistMax + kTriDistG - 1) / kTriDistG + 1) * kTriDistMax)));
-        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        if (attr == hipSuccess && hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
+        const size_t shmax = sizeof(double2) * (((size_t)(kTriDistMax + kTriDistG - 1) / kTriDistG + 1) * kTriDistMax);
+        static const bool ok = hipFuncSetAttribute(reinterpret_cast<const void *>(k_chol_dist),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)shmax) == hipSuccess &&
+                               dist_grid_fits(reinterpret_cast<const void *>(k_chol_dist), shmax);
+        if (ok) {
             hipLaunchKernelGGL(k_fill_i32, dim3((2 * m + 1 + 255) / 256), dim3(256), 0, st, 2 * m + 1, flags, 0);
             hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, 1, fail, 0);
-            int mm = m, h = hs;
-            const double2 *gp = gram;
-            double2 *Lp = L, *Xp = X;
-            int32_t *fl = flags, *fa = fail, *stp = status;
-            void *args[] = {&mm, &gp, &h, &Lp, &Xp, &fl, &fa, &stp};
             const size_t sh = sizeof(double2) * (((size_t)(m + kTriDistG - 1) / kTriDistG + 1) * (size_t)m);
-            if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_chol_dist), dim3(kTriDistG),
-                                           dim3(kTriDistThreads), args, sh, st) == hipSuccess)
-                return;
-            (void)hipGetLastError();
+            hipLaunchKernelGGL(k_chol_dist, dim3(kTriDistG), dim3(kTriDistThreads), sh, st, m, gram, hs, L, X, flags,
+                               fail, status);
+            return;
         }
     }
     constexpr int W = 16;
@@ -1224,29 +1239,21 @@ size_t dense_real_elems(int mmax)
     return 5 * m + 2 + m * m + 1 + 2 * (2 * (m + 1) + 2 * (size_t)kTriDistG * m) + (2 * m + 2) / 2 + 1;
 }
 
-// The distributed tridiagonalisation as a cooperative launch; false when the
-// device cannot run it (the caller then uses a one-work-group variant).
+// The distributed tridiagonalisation (ordinary launch of kTriDistG
+// work-groups); false when the device cannot hold them (the caller then
+// uses a one-work-group variant).
 static bool launch_tridiag_dist(hipStream_t st, int m, double2 *Hh, const DenseScratch &s, int32_t *status)
 {
     if (m < kTriDistMinTridiag || m > kTriDistMax) return false;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return false;
-    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag_dist),
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       (int)tridiag_dist_lds_bytes(kTriDistMax));
-    if (attr != hipSuccess) return false;
+    static const bool ok = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag_dist),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)tridiag_dist_lds_bytes(kTriDistMax)) == hipSuccess &&
+                           dist_grid_fits(reinterpret_cast<const void *>(k_tridiag_dist),
+                                          tridiag_dist_lds_bytes(kTriDistMax));
+    if (!ok) return false;
     hipLaunchKernelGGL(k_fill_i32, dim3((2 * m + 1 + 255) / 256), dim3(256), 0, st, 2 * m + 1, s.flags, 0);
-    int mm = m;
-    double2 *A = Hh, *tau = s.tau, *vbuf = s.vbuf, *ypart = s.ypart;
-    double *d = s.d, *e = s.e;
-    int32_t *flags = s.flags, *stat = status;
-    void *args[] = {&mm, &A, &d, &e, &tau, &vbuf, &ypart, &flags, &stat};
-    const hipError_t r = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_tridiag_dist), dim3(kTriDistG),
-                                                    dim3(kTriDistThreads), args, tridiag_dist_lds_bytes(m), st);
-    if (r != hipSuccess) {
-        (void)hipGetLastError();  // clear the launch error; the caller falls back
-        return false;
-    }
+    hipLaunchKernelGGL(k_tridiag_dist, dim3(kTriDistG), dim3(kTriDistThreads), tridiag_dist_lds_bytes(m), st, m, Hh,
+                       s.d, s.e, s.tau, s.vbuf, s.ypart, s.flags, status);
     return true;
 }
 

@@ -1,0 +1,137 @@
+"""GPU parity at the benchmark's own size: the 34,265-plane-wave cell with 32
+Gaussian atoms and 128 KB projectors (a = 20 bohr, E_cut = 20 Ha, 96^3 grid),
+160 bands, 20 PCG steps per source problem, against the CPU oracle on the same
+seeded inputs.  These reach the code paths that the small cells do not:
+
+- the source problems' reductions over 17 partial sums per band (one at the
+  1503-plane-wave cell);
+- the Rayleigh-Ritz dense part at m = 93 (first size of the multi-work-group
+  Cholesky), 160 (the benchmark's size: multi-work-group Cholesky, one
+  work-group tridiagonalisation from global memory) and 320 (MParO I's size:
+  multi-work-group Cholesky and tridiagonalisation);
+- Algorithm 1 for two outer iterations at the fixed shift, and Algorithm 2
+  (MParO I, m = 320) for one.
+
+Tolerances are those of tests/test_gpu_parity.py.  Subspaces are compared for
+clusters of Ritz values separated from the rest by more than 1e-3 Ha, where
+the sine of the angle is bounded by the vector error over the gap.  The
+oracle takes minutes here, so each test carries its own time limit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from test_gpu_parity import EIG_TOL, SIN_TOL, gapped_clusters, make_case, rel_err, subspace_sin, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+C1 = synth.WORKLOADS["c1"]
+GAP = 1e-3
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return make_case(C1, 0)
+
+
+def _hermitian_diag_err(psi, hpsi, eps):
+    """max |psi^H H psi - diag(eps)| for a (bands x n_g) block."""
+    M = psi.conj() @ hpsi.T
+    return np.abs(M - np.diag(eps)).max()
+
+
+@pytest.mark.timeout(1500)
+def test_paro_c1_two_outer_iterations_match_oracle(c1):
+    """Algorithm 1 from the seeded trial block: the initial Rayleigh-Ritz, then
+    two outer iterations of 160 source problems x 20 PCG steps at the fixed
+    shift sigma_lb, each followed by Rayleigh-Ritz at m = 160."""
+    c, v, h, pl = c1
+    nb = C1.n_carried
+    x = synth.trial_block(h.ng, nb, 0)
+    sigma = h.shift_bound()
+    ref = h.paro(x, 2, C1.n_cg, sigma)
+    out = pl.iterate(to_dev(x), 2, C1.n_cg, sigma)
+    st = to_np(out["stats"])
+    scale = np.maximum(np.abs(ref["eps_hist"]), 1.0)
+    assert np.all(np.abs(st[:, :nb] - ref["eps_hist"]) <= EIG_TOL * scale)
+    assert np.allclose(st[:, nb:2 * nb], ref["res_hist"], rtol=1e-6, atol=1e-10)
+    psi, hpsi = to_np(out["psi"])[:, :h.ng], to_np(out["hpsi"])[:, :h.ng]
+    # the span of all 160 Ritz vectors is span{u_1 .. u_160}: the PCG iterates
+    assert subspace_sin(psi, ref["psi"]) < SIN_TOL
+    clusters = gapped_clusters(ref["eps"], nb, gap=GAP)
+    assert len(clusters) >= nb // 4
+    for i, j in clusters:
+        assert subspace_sin(psi[i:j], ref["psi"][i:j]) < SIN_TOL, (i, j)
+    assert np.abs(psi.conj() @ psi.T - np.eye(nb)).max() < 1e-10
+    assert _hermitian_diag_err(psi, hpsi, to_np(out["eps"])) < 1e-10 * max(1.0, np.abs(ref["eps"]).max())
+    assert pl.status() == 0
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("m,nkeep", [(93, 93), (160, 160), (320, 160)], ids=["m93", "m160", "m320"])
+def test_rayleigh_ritz_c1_matches_oracle(c1, m, nkeep):
+    """Rayleigh-Ritz on m seeded vectors of the 34k-plane-wave cell with W = H U
+    from the oracle's apply: Gram products over K = 34265 on the matrix cores,
+    the multi-work-group Cholesky (m >= 93) and tridiagonalisation (m >= 208)."""
+    c, v, h, pl = c1
+    U = synth.trial_block(h.ng, m, 100 + m)
+    W = h.apply(U)
+    e_ref, p_ref, hp_ref, f = oracle.rayleigh_ritz(U, W, nkeep)
+    assert f == 0
+    eps, psi, hpsi = pl.rayleigh_ritz(to_dev(U), to_dev(W), nkeep)
+    eps, psi, hpsi = to_np(eps), to_np(psi)[:, :h.ng], to_np(hpsi)[:, :h.ng]
+    assert np.abs(eps - e_ref).max() <= EIG_TOL * max(1.0, np.abs(e_ref).max())
+    assert np.abs(psi.conj() @ psi.T - np.eye(nkeep)).max() < 1e-10
+    clusters = gapped_clusters(e_ref, nkeep, gap=GAP)
+    assert len(clusters) >= nkeep // 4
+    for i, j in clusters:
+        assert subspace_sin(psi[i:j], p_ref[i:j]) < SIN_TOL, (i, j)
+    # H psi = W C: the same rotation of W as of U
+    assert subspace_sin(hpsi, hp_ref) < SIN_TOL
+    assert _hermitian_diag_err(psi, hpsi, eps) < 1e-10 * max(1.0, np.abs(e_ref).max())
+    assert pl.status() == 0
+
+
+@pytest.mark.timeout(900)
+def test_source_solve_c1_sampled_bands_match_oracle(c1):
+    """The 160 source problems of one outer iteration in one call (17 partial
+    sums per reduction), four bands (the first and last of each 64-band chunk
+    edge) against the oracle's PCG."""
+    c, v, h, pl = c1
+    nb, ncg = C1.n_carried, C1.n_cg
+    x = synth.trial_block(h.ng, nb, 7)
+    x /= np.linalg.norm(x, axis=1)[:, None]
+    hx = h.apply(x)
+    eps = np.einsum("bg,bg->b", x.conj(), hx).real
+    sh = np.full(nb, h.shift_bound())
+    idx = [0, 63, 64, nb - 1]
+    u_ref, f_ref = h.pcg(x[idx], hx[idx], eps[idx], sh[idx], ncg)
+    u, flags = pl.source_solve(to_dev(x), to_dev(hx), to_dev(eps), to_dev(sh), ncg)
+    u = to_np(u)[:, :h.ng]
+    for k, b in enumerate(idx):
+        assert np.linalg.norm(u[b] - u_ref[k]) <= 1e-9 * np.linalg.norm(u_ref[k]), b
+    assert np.array_equal(to_np(flags)[idx], f_ref)
+    assert pl.status() == 0
+
+
+@pytest.mark.timeout(1200)
+def test_mparo1_c1_one_outer_iteration_matches_oracle(c1):
+    """Algorithm 2 (MParO I) for one outer iteration at the fixed shift: 160
+    correction equations x 20 PCG steps, then Rayleigh-Ritz on span{psi, e} at
+    m = 320.  Every band is compared (one iteration: no band has converged to
+    round-off, so no e_i is noise)."""
+    c, v, h, pl = c1
+    nb = C1.n_carried
+    x = synth.trial_block(h.ng, nb, 3)
+    sigma = h.shift_bound()
+    ref = h.paro(x, 1, C1.n_cg, sigma, variant=1)
+    out = pl.iterate(to_dev(x), 1, C1.n_cg, sigma, variant=1)
+    st = to_np(out["stats"])
+    scale = np.maximum(np.abs(ref["eps_hist"]), 1.0)
+    assert np.all(np.abs(st[:, :nb] - ref["eps_hist"]) <= EIG_TOL * scale)
+    assert np.allclose(st[:, nb:2 * nb], ref["res_hist"], rtol=1e-6, atol=1e-10)
+    psi = to_np(out["psi"])[:, :h.ng]
+    for i, j in gapped_clusters(ref["eps"], nb, gap=GAP):
+        assert subspace_sin(psi[i:j], ref["psi"][i:j]) < SIN_TOL, (i, j)
+    assert pl.status() == 0

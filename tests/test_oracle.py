@@ -287,6 +287,40 @@ def test_teter_limits():
     assert abs(oracle.teter(1e4) * 2e4 - 1) < 1e-3
 
 
+@pytest.mark.parametrize("x,num,den", [(1, 65, 81), (2, 175, 431), (0.5, 40, 41), (3, 405, 1701), (0.25, 518, 519)])
+def test_teter_exact_rationals(x, num, den):
+    """The Teter-Payne-Allan polynomial ratio (PRB 40, 12255) at points where it
+    is a small exact fraction, worked by hand: x = 1 gives 65/81, x = 2 gives
+    175/431, x = 1/2 gives (27 + 9 + 3 + 1)/(40 + 1) = 40/41, x = 3 gives
+    405/1701, x = 1/4 gives 518/519 (numerator 27 + 4.5 + 0.75 + 0.125, the x^4
+    term 16/256, both times 16).  Each coefficient 27, 18, 12, 8, 16 moves at least one of
+    these values."""
+    assert abs(oracle.teter(x) - num / den) <= 2e-16 * (num / den)
+
+
+def test_residual_norms_against_numpy_and_dense_h():
+    """|H psi_b - eps_b psi_b|: the oracle routine against numpy on random
+    blocks (with a non-contiguous shift pattern), and the residual history of
+    a ParO run against a recomputation from the dense matrix of H."""
+    rng = np.random.default_rng(11)
+    psi = rng.standard_normal((7, 513)) + 1j * rng.standard_normal((7, 513))
+    hpsi = rng.standard_normal((7, 513)) + 1j * rng.standard_normal((7, 513))
+    eps = rng.uniform(-2, 2, 7)
+    ref = np.linalg.norm(hpsi - eps[:, None] * psi, axis=1)
+    assert np.allclose(oracle.residual_norms(psi, hpsi, eps), ref, rtol=1e-14, atol=0)
+    # an exact eigenpair of a diagonal operator has zero residual
+    d = rng.uniform(0, 1, 513)
+    e0 = np.zeros((1, 513), complex)
+    e0[0, 17] = 1j
+    assert oracle.residual_norms(e0, d[None, :] * e0, d[17:18])[0] == 0.0
+    spec, c, v, h = tiny(seed=2)
+    H = h.dense()
+    x = synth.trial_block(h.ng, 4, 2)
+    out = h.paro(x, 2, 6, h.shift_bound())
+    r = np.linalg.norm(out["psi"] @ H.T - out["eps"][:, None] * out["psi"], axis=1)
+    assert np.allclose(out["res_hist"][-1], r, rtol=1e-9, atol=1e-13)
+
+
 # ---------------------------------------------------------------- PCG
 
 def test_pcg_converges_to_direct_solve():
