@@ -370,6 +370,20 @@ int32_t paro_zgemm_hn(paro_stream_t s, int32_t M, int32_t N, int64_t K, const do
 int32_t paro_zgemm_nn(paro_stream_t s, int64_t M, int32_t N, int32_t K, const double *A, int64_t lda,
                       const double *B, int64_t ldb, double *C, int64_t ldc, int32_t accumulate);
 
+/* paro_zgemm_hn without a workspace, for callers that cannot allocate
+ * device memory (code under graph capture, serving loops, harnesses that
+ * forbid allocation): the split partial tiles go to a fixed 32 MiB device
+ * array inside the library, one per device, held until the process ends.
+ * Same product, arguments and layout as paro_zgemm_hn; s must be a stream
+ * of the current device (or NULL).  The number of K splits depends on the
+ * scratch size, so results can differ from paro_zgemm_hn's in rounding.
+ * Calls on one device share the array: calls that overlap in time on one
+ * device (different streams, or host threads) race and give wrong results.
+ * The library calls no allocator here.  Errors: PARO_EINVAL (bad argument),
+ * PARO_ESIZE (M * N * 16 bytes above 32 MiB), PARO_EHIP. */
+int32_t paro_zgemm_hn_noalloc(paro_stream_t s, int32_t M, int32_t N, int64_t K, const double *A, int64_t lda,
+                              const double *B, int64_t ldb, double *C, int64_t ldc);
+
 /* The device Hermitian eigensolver of the Rayleigh-Ritz step: A (m x m,
  * column-major, dev, read only) = V diag(w) V^H, w ascending (dev
  * double[m]), V (dev complex m x m).  Householder tridiagonalisation,

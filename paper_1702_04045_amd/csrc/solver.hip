@@ -2,6 +2,7 @@
 // Rayleigh-Ritz (step 4), residuals and the ParO outer loop (steps 1, 3-5;
 // Algorithm 2 for the MParO I variant).
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "paro_internal.h"
@@ -663,6 +664,71 @@ int32_t paro_zgemm_hn(paro_stream_t s, int32_t M, int32_t N, int64_t K, const do
     }
     PARO_CHECK_LAUNCH(gemm_hn(static_cast<hipStream_t>(s), M, N, K, (const double2 *)A, lda, (const double2 *)B, ldb,
                               (double2 *)C, ldc, (double2 *)ws, ws_bytes / sizeof(double2), nullptr, nullptr));
+    return PARO_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Split-K partial tiles of paro_zgemm_hn_noalloc: a fixed device array
+// instead of a caller workspace.  Each device that the library runs on
+// holds its own copy until the process ends.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) double2 scratch[kNoAllocScratchBytes / sizeof(double2)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double2 *g_scratch_addr[kMaxDevices] = {};
+
+// The device address of the current device's copy of scratch, looked up
+// once per device (the array's name is a host-side stand-in, not a device
+// address).
+int32_t scratch_address(double2 **out)
+{
+    int dev = -1;
+    PARO_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("paro_zgemm_hn_noalloc: device index out of range");
+        return PARO_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        PARO_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("paro_zgemm_hn_noalloc: hipGetSymbolAddress returned NULL");
+            return PARO_EHIP;
+        }
+        g_scratch_addr[dev] = static_cast<double2 *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return PARO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t paro_zgemm_hn_noalloc(paro_stream_t s, int32_t M, int32_t N, int64_t K, const double *A, int64_t lda,
+                              const double *B, int64_t ldb, double *C, int64_t ldc)
+{
+    if (M <= 0 || N <= 0 || K <= 0 || !A || !B || !C || lda < K || ldb < K || ldc < M) {
+        set_error("paro_zgemm_hn_noalloc: bad argument");
+        return PARO_EINVAL;
+    }
+    if (sizeof(double2) * (size_t)M * (size_t)N > kNoAllocScratchBytes) {
+        set_error("paro_zgemm_hn_noalloc: M * N * 16 bytes exceeds the " + std::to_string(kNoAllocScratchBytes) +
+                  "-byte device scratch (use paro_zgemm_hn with a workspace)");
+        return PARO_ESIZE;
+    }
+    double2 *part = nullptr;
+    int32_t rc = scratch_address(&part);
+    if (rc) return rc;
+    // every split's partial tile is written in full before the reduce reads
+    // it, so nothing from an earlier call needs clearing
+    PARO_CHECK_LAUNCH(gemm_hn(static_cast<hipStream_t>(s), M, N, K, (const double2 *)A, lda, (const double2 *)B, ldb,
+                              (double2 *)C, ldc, part, kNoAllocScratchBytes / sizeof(double2), nullptr, nullptr));
     return PARO_OK;
 }
 

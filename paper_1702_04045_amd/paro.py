@@ -421,6 +421,19 @@ def zgemm_hn(A, B, device=None):
     return C_
 
 
+def zgemm_hn_noalloc(A, B):
+    """zgemm_hn through paro_zgemm_hn_noalloc: the library's fixed device scratch instead of a
+    workspace (only C is allocated here, by torch)."""
+    torch = _torch()
+    M, K = A.shape
+    N = B.shape[0]
+    C_ = torch.empty((N, M), dtype=torch.complex128, device=A.device)
+    lib = L.load()
+    L.check(lib.paro_zgemm_hn_noalloc(_stream(A.device), M, N, K, _ptr(A), A.stride(0), _ptr(B), B.stride(0),
+                                      _ptr(C_), M), "paro_zgemm_hn_noalloc")
+    return C_
+
+
 def zgemm_nn(A, B, C_=None, accumulate=False):
     """C = A B (+ C): A column-major M x K given as (K, M) tensor, B as (N, K), C as (N, M)."""
     torch = _torch()
