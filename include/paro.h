@@ -54,7 +54,9 @@ extern "C" {
 #define PARO_ESIZE (-3)    /* plan buffer or workspace smaller than queried */
 #define PARO_EHIP (-4)     /* HIP runtime error (text in paro_last_error) */
 #define PARO_EUNSUP (-5)   /* valid input outside what this build supports
-                              (FFT length not in the supported set) */
+                              (FFT length not in the supported set, subspace
+                              above the dense eigensolver's 1024, density on a
+                              grid above 96 points) */
 
 /* sticky device status bits (paro_get_status) */
 #define PARO_F_NEGCURV 1   /* PCG met p^H (H - sigma) p <= 0: sigma not below the spectrum */
@@ -266,7 +268,8 @@ int32_t paro_shift_lower_bound(paro_plan plan, double *sigma_dev, void *ws, size
  * host synchronisation per outer iteration).  In adaptive shift mode a
  * source solve that meets negative curvature is redone with sigma_lb (one
  * host synchronisation per outer iteration).  n_done: host int32 or NULL,
- * the outer iterations run.  ws: paro_workspace_bytes(nb).  nb <= 512. */
+ * the outer iterations run.  ws: paro_workspace_bytes(nb).  nb <= 1024 for
+ * ParO and nb <= 512 for MParO I and II (PARO_EUNSUP beyond). */
 int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi, double *hpsi, int64_t ld,
                      double *eps, double *sigma, const paro_iter_opts *opts, double *stats,
                      void *ws, size_t ws_bytes, int32_t *n_done);

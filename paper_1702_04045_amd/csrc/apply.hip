@@ -29,7 +29,9 @@ template <int N> constexpr bool cfg_ok()
     return C::T * C::E == N && ListInfo<typename C::Inv>::last == ListInfo<typename C::Fwd>::first;
 }
 
-constexpr int kStickThreads = 256;
+// Threads of the stick kernels: 256 (32 sticks of 8 threads at 96 points),
+// 128 for 160-point FP64 sticks so that the LDS tile stays at 41 KB.
+template <int N3, class C2> constexpr int stick_threads() { return N3 > 96 && sizeof(C2) == 16 ? 128 : 256; }
 
 // Thread -> (line, thread-in-line) map: the T threads of a line are in one
 // wavefront, spaced 64/T lanes apart, so that 8 consecutive lanes work on 8
@@ -67,7 +69,7 @@ __device__ __forceinline__ int opaque(int t)
 // pbuf != null: PCG prologue, p <- z + beta p (first step: p <- z), the new p
 // is written back and transformed.  Otherwise src is transformed as is.
 template <int N3, class C2>
-__global__ void __launch_bounds__(kStickThreads)
+__global__ void __launch_bounds__((stick_threads<N3, C2>()))
 k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const double *__restrict__ beta, int first,
             C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ st_start, const int32_t *__restrict__ pt_sz,
             const C2 *__restrict__ tw)
@@ -75,21 +77,22 @@ k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const
     using C = FftCfg<N3>;
     using S2 = RealOf<C2>;
     static_assert(cfg_ok<N3>(), "bad FFT config");
-    constexpr int T = C::T, E = C::E, S = kStickThreads / T, LD = N3 + 1;
+    constexpr int NT = stick_threads<N3, C2>();
+    constexpr int T = C::T, E = C::E, S = NT / T, LD = N3 + 1;
     __shared__ C2 tile[S * LD];
     __shared__ C2 twl[N3];  // LDS copy of the twiddle table
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
     const int s0 = blockIdx.x * S, band = blockIdx.y;
     const int s = s0 + sl;
     const bool act = s < nst;
-    for (int i = tid; i < S * LD; i += kStickThreads) tile[i] = cmk<C2>(0.0, 0.0);
-    for (int i = tid; i < N3; i += kStickThreads) twl[i] = tw[i];
+    for (int i = tid; i < S * LD; i += NT) tile[i] = cmk<C2>(0.0, 0.0);
+    for (int i = tid; i < N3; i += NT) twl[i] = tw[i];
     __syncthreads();
     const int p0 = st_start[s0], p1 = st_start[min(s0 + S, nst)];
     const C2 *x = src + band * ld;
     C2 *pb = pbuf ? pbuf + band * ld : nullptr;
     const S2 bt = (pbuf && !first) ? (S2)beta[band] : (S2)0;
-    for (int idx = p0 + tid; idx < p1; idx += kStickThreads) {
+    for (int idx = p0 + tid; idx < p1; idx += NT) {
         C2 val = x[idx];
         if (pb) {
             if (!first) {
@@ -535,7 +538,7 @@ void plane_potential(const int32_t *grid, const double *vloc, VT *out)
 // Sticks -> sphere, forward transform along n3, then
 // out = scale * local + (kin - shift_b) x; dot_part gets sum Re(conj(x) out).
 template <int N3, class C2>
-__global__ void __launch_bounds__(kStickThreads)
+__global__ void __launch_bounds__((stick_threads<N3, C2>()))
 k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ st_start,
             const int32_t *__restrict__ pt_sz, const C2 *__restrict__ tw, const C2 *__restrict__ xin, int64_t ld,
             C2 *__restrict__ out, const double *__restrict__ kin, const double *__restrict__ shift, double scale,
@@ -544,16 +547,17 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
     using C = FftCfg<N3>;
     using Fwd = typename C::Fwd;
     using S2 = RealOf<C2>;
-    constexpr int T = C::T, E = C::E, S = kStickThreads / T, LD = N3 + 1;
+    constexpr int NT = stick_threads<N3, C2>();
+    constexpr int T = C::T, E = C::E, S = NT / T, LD = N3 + 1;
     __shared__ C2 tile[S * LD];
-    __shared__ double red[kStickThreads / 64];
+    __shared__ double red[NT / 64];
     __shared__ C2 twl[N3];  // LDS copy of the twiddle table
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
     const int s0 = blockIdx.x * S, band = blockIdx.y;
     const int s = s0 + sl;
     const bool act = s < nst;
     const C2 *in = sticks + (size_t)band * N3 * nst;
-    for (int i = tid; i < N3; i += kStickThreads) twl[i] = tw[i];
+    for (int i = tid; i < N3; i += NT) twl[i] = tw[i];
     __syncthreads();
     C2 v[E];
     C2 *line = tile + sl * LD;
@@ -579,7 +583,7 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
     C2 *o = out + band * ld;
     const S2 sc = (S2)scale;
     double dot = 0.0;
-    for (int idx = p0 + tid; idx < p1; idx += kStickThreads) {
+    for (int idx = p0 + tid; idx < p1; idx += NT) {
         const int sz = pt_sz[idx];
         const C2 loc = tile[((sz >> 8) - s0) * LD + (sz & 255)];
         const C2 xv = x[idx];
@@ -591,9 +595,125 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
         dot += (double)xv.x * (double)r.x + (double)xv.y * (double)r.y;
     }
     if (dot_part) {
-        dot = block_sum<kStickThreads>(dot, red);
+        dot = block_sum<NT>(dot, red);
         if (tid == 0) dot_part[(size_t)band * part_stride + blockIdx.x] = dot;
     }
+}
+
+// ---------------------------------------------------------------- split plane stage
+// Grids above 96 points: a z-plane of populated columns, ncol x N complex,
+// no longer fits LDS with room to pipeline (160 points: 67 columns, 86 KB in
+// FP32, 172 KB in FP64), so the plane stage runs as three batches of
+// independent line transforms through a compressed plane in HBM,
+// Q[band][z][y][c] (c = n1 + nmax1 the populated column, y = n2 mod N):
+//   k_col_inv   columns: sticks -> inverse along n2 -> Q (all N rows),
+//   k_row       rows: Q -> inverse along n1, x V, forward along n1 -> Q
+//               (populated columns only),
+//   k_col_fwd   columns: Q -> forward along n2 -> sticks (the column's sticks).
+// Each line is T consecutive-by-line lanes of one wavefront (line_of), so
+// its Stockham exchanges need only wavefront ordering; the tile holds one
+// line slot per line.  The eight lanes at one element index take eight
+// consecutive lines, i.e. eight consecutive columns c of Q (row kernel:
+// eight consecutive rows), so their stores and loads are runs of eight.
+template <int N, class C2> constexpr int split_threads() { return sizeof(C2) == 16 ? 128 : 256; }
+
+template <int N, class C2>
+__global__ void __launch_bounds__((split_threads<N, C2>()))
+k_col_inv(const C2 *__restrict__ sticks, int nst, int N3, const int32_t *__restrict__ cols, int ncol,
+          C2 *__restrict__ Q, const C2 *__restrict__ tw)
+{
+    using C = FftCfg<N>;
+    constexpr int NT = split_threads<N, C2>(), T = C::T, E = C::E, S = NT / T, LD = N + 1;
+    constexpr int RL = ListInfo<typename C::Inv>::last;
+    __shared__ C2 tile[S * LD];
+    __shared__ C2 twl[N];
+    const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
+    for (int i = tid; i < N; i += NT) twl[i] = tw[i];
+    __syncthreads();
+    const int c = blockIdx.x * S + sl, z = blockIdx.y, band = blockIdx.z;
+    const bool act = c < ncol;
+    int cst = 0, ylo = 0, cnt = 0;
+    if (act) {
+        cst = cols[3 * c];
+        ylo = cols[3 * c + 1];
+        cnt = cols[3 * c + 2];
+    }
+    const C2 *tz = sticks + ((size_t)band * N3 + z) * nst + cst;
+    C2 v[E];
+    if (act) pass_load<N, T, E, ListInfo<typename C::Inv>::first>(v, t, [&](int i) {
+        const int k = (i > N / 2 ? i - N : i) - ylo;
+        return (unsigned)k < (unsigned)cnt ? tz[k] : cmk<C2>(0.0, 0.0);
+    });
+    stockham<N, +1, true>(typename C::Inv{}, v, t, act, tile + sl * LD, 1, twl);
+    C2 *q = Q + ((size_t)band * N3 + z) * N * ncol + c;
+    if (act) final_foreach<N, T, E, RL>(v, t, [&](int i, int e) { q[(size_t)i * ncol] = v[e]; });
+}
+
+template <int N, class C2>
+__global__ void __launch_bounds__((split_threads<N, C2>()))
+k_row(C2 *__restrict__ Q, int N3, int ncol, int nmax1, const RealOf<C2> *__restrict__ vperm,
+      const C2 *__restrict__ tw)
+{
+    using C = FftCfg<N>;
+    using Inv = typename C::Inv;
+    using Fwd = typename C::Fwd;
+    static_assert(ListInfo<Inv>::last == ListInfo<Fwd>::first, "the forward starts where the inverse ends");
+    constexpr int NT = split_threads<N, C2>(), T = C::T, E = C::E, S = NT / T, LD = N + 1;
+    __shared__ C2 tile[S * LD];
+    __shared__ C2 twl[N];
+    const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
+    for (int i = tid; i < N; i += NT) twl[i] = tw[i];
+    __syncthreads();
+    const int y = blockIdx.x * S + sl, z = blockIdx.y, band = blockIdx.z;
+    const bool act = y < N;
+    C2 *row = Q + (((size_t)band * N3 + z) * N + (act ? y : 0)) * ncol;
+    auto populated = [&](int i) { return i <= nmax1 || i >= N - nmax1; };
+    auto col_of = [&](int i) { return i <= nmax1 ? i + nmax1 : i - N + nmax1; };
+    C2 v[E];
+    if (act) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
+        return populated(i) ? row[col_of(i)] : cmk<C2>(0.0, 0.0);
+    });
+    C2 *line = tile + sl * LD;
+    stockham<N, +1, true>(Inv{}, v, t, act, line, 1, twl);
+    const RealOf<C2> *vp = vperm + (((size_t)z * N + (act ? y : 0)) * T + t) * E;
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vp[e]);
+    stockham<N, -1, true>(Fwd{}, v, t, act, line, 1, twl);
+    if (act) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
+        if (populated(i)) row[col_of(i)] = v[e];
+    });
+}
+
+template <int N, class C2>
+__global__ void __launch_bounds__((split_threads<N, C2>()))
+k_col_fwd(const C2 *__restrict__ Q, int N3, int ncol, const int32_t *__restrict__ cols, C2 *__restrict__ sticks,
+          int nst, const C2 *__restrict__ tw)
+{
+    using C = FftCfg<N>;
+    using Fwd = typename C::Fwd;
+    constexpr int NT = split_threads<N, C2>(), T = C::T, E = C::E, S = NT / T, LD = N + 1;
+    __shared__ C2 tile[S * LD];
+    __shared__ C2 twl[N];
+    const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
+    for (int i = tid; i < N; i += NT) twl[i] = tw[i];
+    __syncthreads();
+    const int c = blockIdx.x * S + sl, z = blockIdx.y, band = blockIdx.z;
+    const bool act = c < ncol;
+    int cst = 0, ylo = 0, cnt = 0;
+    if (act) {
+        cst = cols[3 * c];
+        ylo = cols[3 * c + 1];
+        cnt = cols[3 * c + 2];
+    }
+    const C2 *q = Q + ((size_t)band * N3 + z) * N * ncol + (act ? c : 0);
+    C2 v[E];
+    if (act) pass_load<N, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return q[(size_t)i * ncol]; });
+    stockham<N, -1, true>(Fwd{}, v, t, act, tile + sl * LD, 1, twl);
+    C2 *tz = sticks + ((size_t)band * N3 + z) * nst + cst;
+    if (act) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
+        const int k = (i > N / 2 ? i - N : i) - ylo;
+        if ((unsigned)k < (unsigned)cnt) tz[k] = v[e];
+    });
 }
 
 // Precision-specific plan tables.
@@ -612,7 +732,8 @@ hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const C2 *src, 
                      const double *shift, C2 *pbuf, const double *beta, bool first, double *dot_part,
                      int *nparts_out)
 {
-    constexpr int S = kStickThreads / FftCfg<N>::T;
+    constexpr int NT = stick_threads<N, C2>();
+    constexpr int S = NT / FftCfg<N>::T;
     const int N3 = pl.grid[2];
     const int ntiles = (pl.nst + S - 1) / S;
     if (nparts_out) *nparts_out = ntiles;
@@ -621,7 +742,7 @@ hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const C2 *src, 
     for (int c0 = 0; c0 < nb; c0 += kMaxBandsPerChunk) {
         const int cb = min(kMaxBandsPerChunk, nb - c0);
         prof_mark(PARO_K_STICK_INV, pl.stream, true);
-        hipLaunchKernelGGL((k_stick_inv<N, C2>), dim3(ntiles, cb), dim3(kStickThreads), 0, pl.stream,
+        hipLaunchKernelGGL((k_stick_inv<N, C2>), dim3(ntiles, cb), dim3(NT), 0, pl.stream,
                            src + c0 * ld, ld, pbuf ? pbuf + c0 * ld : nullptr, beta ? beta + c0 : nullptr,
                            first ? 1 : 0, sticks, pl.nst, pl.st_start, pl.pt_sz, PlanTabs<C2>::tw(pl, 2));
         prof_mark(PARO_K_STICK_INV, pl.stream, false);
@@ -632,9 +753,53 @@ hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const C2 *src, 
         prof_mark(PARO_K_PLANE, pl.stream, false);
         const C2 *x = pbuf ? pbuf : src;
         prof_mark(PARO_K_STICK_FWD, pl.stream, true);
-        hipLaunchKernelGGL((k_stick_fwd<N, C2>), dim3(ntiles, cb), dim3(kStickThreads), 0, pl.stream, sticks,
+        hipLaunchKernelGGL((k_stick_fwd<N, C2>), dim3(ntiles, cb), dim3(NT), 0, pl.stream, sticks,
                            pl.nst, pl.st_start, pl.pt_sz, PlanTabs<C2>::tw(pl, 2), x + c0 * ld, ld, out + c0 * ld,
                            pl.kin, shift ? shift + c0 : nullptr, scale,
+                           dot_part ? dot_part + (size_t)c0 * kMaxParts : nullptr, kMaxParts);
+        prof_mark(PARO_K_STICK_FWD, pl.stream, false);
+    }
+    return hipGetLastError();
+}
+
+// The local part at grids above 96 points: sticks, then the three line
+// batches of the split plane stage through Q, then the forward sticks.
+template <int N, class C2>
+hipError_t run_local_split(const Plan &pl, const Workspace &w, int nb, const C2 *src, int64_t ld, C2 *out,
+                           const double *shift, C2 *pbuf, const double *beta, bool first, double *dot_part,
+                           int *nparts_out)
+{
+    constexpr int NT = stick_threads<N, C2>();
+    constexpr int S = NT / FftCfg<N>::T;
+    constexpr int NTS = split_threads<N, C2>(), SL = NTS / FftCfg<N>::T;
+    static_assert(N % SL == 0, "rows split evenly into work-groups");
+    const int N3 = pl.grid[2];
+    const int ntiles = (pl.nst + S - 1) / S;
+    if (nparts_out) *nparts_out = ntiles;
+    const double scale = 1.0 / ((double)pl.grid[0] * pl.grid[1] * pl.grid[2]);
+    C2 *sticks = reinterpret_cast<C2 *>(w.sticks);
+    C2 *Q = reinterpret_cast<C2 *>(w.qplane);
+    const int ncol = pl.ncol;
+    for (int c0 = 0; c0 < nb; c0 += kMaxBandsPerChunk) {
+        const int cb = min(kMaxBandsPerChunk, nb - c0);
+        prof_mark(PARO_K_STICK_INV, pl.stream, true);
+        hipLaunchKernelGGL((k_stick_inv<N, C2>), dim3(ntiles, cb), dim3(NT), 0, pl.stream, src + c0 * ld, ld,
+                           pbuf ? pbuf + c0 * ld : nullptr, beta ? beta + c0 : nullptr, first ? 1 : 0, sticks, pl.nst,
+                           pl.st_start, pl.pt_sz, PlanTabs<C2>::tw(pl, 2));
+        prof_mark(PARO_K_STICK_INV, pl.stream, false);
+        prof_mark(PARO_K_PLANE, pl.stream, true);
+        hipLaunchKernelGGL((k_col_inv<N, C2>), dim3((ncol + SL - 1) / SL, N3, cb), dim3(NTS), 0, pl.stream, sticks,
+                           pl.nst, N3, pl.cols, ncol, Q, PlanTabs<C2>::tw(pl, 1));
+        hipLaunchKernelGGL((k_row<N, C2>), dim3(N / SL, N3, cb), dim3(NTS), 0, pl.stream, Q, N3, ncol, pl.nmax[0],
+                           PlanTabs<C2>::v(pl), PlanTabs<C2>::tw(pl, 0));
+        hipLaunchKernelGGL((k_col_fwd<N, C2>), dim3((ncol + SL - 1) / SL, N3, cb), dim3(NTS), 0, pl.stream, Q, N3,
+                           ncol, pl.cols, sticks, pl.nst, PlanTabs<C2>::tw(pl, 1));
+        prof_mark(PARO_K_PLANE, pl.stream, false);
+        const C2 *x = pbuf ? pbuf : src;
+        prof_mark(PARO_K_STICK_FWD, pl.stream, true);
+        hipLaunchKernelGGL((k_stick_fwd<N, C2>), dim3(ntiles, cb), dim3(NT), 0, pl.stream, sticks, pl.nst,
+                           pl.st_start, pl.pt_sz, PlanTabs<C2>::tw(pl, 2), x + c0 * ld, ld, out + c0 * ld, pl.kin,
+                           shift ? shift + c0 : nullptr, scale,
                            dot_part ? dot_part + (size_t)c0 * kMaxParts : nullptr, kMaxParts);
         prof_mark(PARO_K_STICK_FWD, pl.stream, false);
     }
@@ -645,13 +810,14 @@ template <int N>
 hipError_t run_density(const Plan &pl, double2 *sticks, double *part, int nb, const double2 *psi, int64_t ld,
                        const double *weights, double *rho)
 {
-    constexpr int S = kStickThreads / FftCfg<N>::T;
+    constexpr int NT = stick_threads<N, double2>();
+    constexpr int S = NT / FftCfg<N>::T;
     const int N3 = pl.grid[2];
     const int ntiles = (pl.nst + S - 1) / S;
     for (int c0 = 0; c0 < nb; c0 += kMaxBandsPerChunk) {
         const int cb = min(kMaxBandsPerChunk, nb - c0);
         const int ng = (cb + kDensityBandsPerGroup - 1) / kDensityBandsPerGroup;
-        hipLaunchKernelGGL((k_stick_inv<N, double2>), dim3(ntiles, cb), dim3(kStickThreads), 0, pl.stream,
+        hipLaunchKernelGGL((k_stick_inv<N, double2>), dim3(ntiles, cb), dim3(NT), 0, pl.stream,
                            psi + c0 * ld, ld, nullptr, nullptr, 0, sticks, pl.nst, pl.st_start, pl.pt_sz, pl.tw[2]);
         prof_mark(PARO_K_DENSITY, pl.stream, true);
         hipLaunchKernelGGL((k_plane_density<N>), dim3(N3, ng), dim3(plane_threads<N, double2>()), 0, pl.stream,
@@ -676,6 +842,7 @@ hipError_t local_apply(const Plan &pl, const Workspace &w, int nb, const C2 *src
     PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
     PARO_CASE(80) PARO_CASE(96)
 #undef PARO_CASE
+    case 160: return run_local_split<160, C2>(pl, w, nb, src, ld, out, shift, pbuf, beta, first, dot_part, nparts_out);
     default: return hipErrorInvalidValue;
     }
 }
@@ -685,10 +852,12 @@ hipError_t local_apply(const Plan &pl, const Workspace &w, int nb, const C2 *src
 bool fft_supported(int n)
 {
     switch (n) {
-    case 8: case 16: case 24: case 32: case 40: case 48: case 64: case 80: case 96: return true;
+    case 8: case 16: case 24: case 32: case 40: case 48: case 64: case 80: case 96: case 160: return true;
     default: return false;
     }
 }
+
+bool split_plane(int n) { return n > 96; }
 
 hipError_t launch_density(const Plan &pl, double2 *sticks, double *part, int nb, const double2 *psi, int64_t ld,
                           const double *weights, double *rho)
@@ -709,7 +878,7 @@ template <class VT> static void build_plane_potential_t(int n, const int32_t *gr
 #define PARO_CASE(k) \
     case k: plane_potential<k, VT>(grid, vloc, out); break;
     PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
-    PARO_CASE(80) PARO_CASE(96)
+    PARO_CASE(80) PARO_CASE(96) PARO_CASE(160)
 #undef PARO_CASE
     default: break;
     }

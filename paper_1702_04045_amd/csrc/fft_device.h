@@ -259,6 +259,7 @@ template <> struct FftCfg<48> { static constexpr int N = 48, T = 4, E = 12; usin
 template <> struct FftCfg<64> { static constexpr int N = 64, T = 8, E = 8; using Inv = RList<8, 8>; using Fwd = RList<8, 8>; };
 template <> struct FftCfg<80> { static constexpr int N = 80, T = 4, E = 20; using Inv = RList<5, 4, 4>; using Fwd = RList<4, 4, 5>; };
 template <> struct FftCfg<96> { static constexpr int N = 96, T = 8, E = 12; using Inv = RList<6, 4, 4>; using Fwd = RList<4, 4, 6>; };
+template <> struct FftCfg<160> { static constexpr int N = 160, T = 8, E = 20; using Inv = RList<10, 4, 4>; using Fwd = RList<4, 4, 10>; };
 
 template <class L> struct ListInfo;
 template <int... Rs> struct ListInfo<RList<Rs...>> {

@@ -182,7 +182,7 @@ static int32_t validate(const paro_problem *p, HostGeom *g)
         if (!std::isfinite(p->vloc[i])) return fail(PARO_EINVAL, "vloc has a non-finite value");
     if (p->grid[0] != p->grid[1] || p->grid[1] != p->grid[2] || !fft_supported(p->grid[0]) ||
         !good_size(p->grid[0]))
-        return fail(PARO_EUNSUP, "this build supports cubic FFT grids of 8, 16, 24, 32, 40, 48, 64, 80 or 96 points");
+        return fail(PARO_EUNSUP, "this build supports cubic FFT grids of 8, 16, 24, 32, 40, 48, 64, 80, 96 or 160 points");
     g->ng = n;
     // Sticks are numbered column by column (n1 ascending), n2 ascending
     // within a column, and every n2 between a column's lowest and highest
@@ -220,6 +220,7 @@ size_t workspace_bytes(const Plan &pl, int nb)
     size_t tot = 0;
     auto add = [&](size_t bytes) { tot = align256(tot + bytes); };
     add(sizeof(double2) * cb * pl.grid[2] * pl.nst);          // sticks
+    if (split_plane(pl.grid[0])) add(sizeof(double2) * cb * pl.grid[2] * pl.grid[1] * pl.ncol);  // qplane
     for (int i = 0; i < 4; ++i) add(sizeof(double2) * nb * pl.ldv);  // r z p q
     add(sizeof(double2) * m * pl.ldv);                          // U
     add(sizeof(double2) * m * pl.ldv);                          // W
@@ -285,6 +286,8 @@ Workspace carve_workspace(const Plan &pl, int nb, void *ws)
         return p;
     };
     w.sticks = (double2 *)take(sizeof(double2) * cb * pl.grid[2] * pl.nst);
+    w.qplane = split_plane(pl.grid[0]) ? (double2 *)take(sizeof(double2) * cb * pl.grid[2] * pl.grid[1] * pl.ncol)
+                                       : nullptr;
     w.r = (double2 *)take(sizeof(double2) * nb * pl.ldv);
     w.z = (double2 *)take(sizeof(double2) * nb * pl.ldv);
     w.p = (double2 *)take(sizeof(double2) * nb * pl.ldv);

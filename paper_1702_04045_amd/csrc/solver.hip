@@ -119,6 +119,9 @@ using namespace paro;
         }                                                                        \
     } while (0)
 
+// Largest Rayleigh-Ritz subspace of the device dense path (m x m eigensolve).
+constexpr int kMaxIterBands = 1024;
+
 static int32_t check_ws(const Plan &pl, int nb, void *ws, size_t ws_bytes)
 {
     if (!ws) {
@@ -183,6 +186,10 @@ int32_t paro_density(paro_plan plan, int32_t nb, const double *psi, int64_t ld, 
     if (ld < pl.ng) {
         set_error("paro_density: ld < n_g");
         return PARO_EINVAL;
+    }
+    if (split_plane(pl.grid[0])) {
+        set_error("paro_density: grids above 96 points are not supported");
+        return PARO_EUNSUP;
     }
     size_t off = 0;
     if (ws_bytes < density_workspace_bytes(pl, nb, &off)) {
@@ -305,6 +312,10 @@ int32_t paro_rayleigh_ritz(paro_plan plan, int32_t m, int32_t n_keep, const doub
         set_error("paro_rayleigh_ritz: ld < n_g");
         return PARO_EINVAL;
     }
+    if (m > kMaxIterBands) {
+        set_error("paro_rayleigh_ritz: m above " + std::to_string(kMaxIterBands));
+        return PARO_EUNSUP;
+    }
     const int nbw = (m + 1) / 2;
     int32_t rc = check_ws(pl, nbw, ws, ws_bytes);
     if (rc) return rc;
@@ -384,7 +395,7 @@ int32_t prepare_cell(paro_plan plan, int32_t nb, double *psi, double *hpsi, int6
                      CellRun &c)
 {
     if (!plan || nb <= 0 || !psi || !hpsi || !eps || !sigma || !opts || opts->n_outer < 0 || opts->n_cg < 0 ||
-        nb > 512 ||
+        nb > kMaxIterBands ||
         (opts->variant != PARO_VARIANT_PARO && opts->variant != PARO_VARIANT_MPARO1 &&
          opts->variant != PARO_VARIANT_MPARO2) ||
         (opts->shift_mode != PARO_SHIFT_FIXED && opts->shift_mode != PARO_SHIFT_ADAPTIVE) ||
@@ -396,6 +407,11 @@ int32_t prepare_cell(paro_plan plan, int32_t nb, double *psi, double *hpsi, int6
     if (ld < pl.ng) {
         set_error("paro_iterate: ld < n_g");
         return PARO_EINVAL;
+    }
+    if (opts->variant != PARO_VARIANT_PARO && 2 * nb > kMaxIterBands) {
+        set_error("paro_iterate: MParO runs Rayleigh-Ritz on 2 nb vectors, at most " +
+                  std::to_string(kMaxIterBands));
+        return PARO_EUNSUP;
     }
     if (opts->variant == PARO_VARIANT_MPARO2 && opts->precision != PARO_PREC_FP64) {
         set_error("paro_iterate: MParO II runs in FP64 only");

@@ -27,8 +27,8 @@ import numpy as np
 __all__ = ["CellSpec", "WORKLOADS", "make_cell", "vloc_on_grid", "trial_block",
            "small_cell", "batch_specs", "FFT_LENGTHS"]
 
-# FFT grid lengths 2^a * {1, 3, 5} from 8 to 96 (the lengths the GPU transforms support)
-FFT_LENGTHS = (8, 16, 24, 32, 40, 48, 64, 80, 96)
+# FFT grid lengths 2^a * {1, 3, 5} the GPU transforms support
+FFT_LENGTHS = (8, 16, 24, 32, 40, 48, 64, 80, 96, 160)
 
 
 @dataclass(frozen=True)
@@ -58,8 +58,9 @@ class CellSpec:
         return self.n_bands + self.n_buffer
 
 
-# The workloads: a 1.5k-plane-wave cell without nonlocal part, and a
-# 34k-plane-wave cell with 32 atoms carrying s + p KB projectors (128 in all).
+# The workloads: a 1.5k-plane-wave cell without nonlocal part, a
+# 34k-plane-wave cell with 32 atoms carrying s + p KB projectors (128 in all),
+# and a 161k-plane-wave cell with 128 such atoms (512 projectors).
 WORKLOADS = {
     "c0": CellSpec(name="c0_a10_ecut10_g32_n8", a=10.0, ecut=10.0, grid=32,
                    n_atoms=4, width=1.0, projectors=False,
@@ -67,6 +68,12 @@ WORKLOADS = {
     "c1": CellSpec(name="c1_a20_ecut20_g96_n128_p128", a=20.0, ecut=20.0,
                    grid=96, n_atoms=32, width=0.8, projectors=True,
                    proj_width=0.8, n_bands=128, n_buffer=32, n_outer=10,
+                   n_cg=20),
+    # mixed precision at scale: 161k plane waves, 128 atoms (512 projectors),
+    # 512 orbitals plus 128 buffer orbitals
+    "c3": CellSpec(name="c3_a30_ecut25_g160_n512_p512", a=30.0, ecut=25.0,
+                   grid=160, n_atoms=128, width=0.8, projectors=True,
+                   proj_width=0.8, n_bands=512, n_buffer=128, n_outer=10,
                    n_cg=20),
 }
 

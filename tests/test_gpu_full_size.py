@@ -135,3 +135,24 @@ def test_mparo1_c1_one_outer_iteration_matches_oracle(c1):
     for i, j in gapped_clusters(ref["eps"], nb, gap=GAP):
         assert subspace_sin(psi[i:j], ref["psi"][i:j]) < SIN_TOL, (i, j)
     assert pl.status() == 0
+
+
+@pytest.mark.timeout(900)
+def test_rayleigh_ritz_m640_matches_oracle():
+    """Rayleigh-Ritz at m = 640 (the 640-band block of the 161k-plane-wave cell)
+    on the 1503-plane-wave cell: the one-work-group Cholesky and
+    tridiagonalisation beyond the multi-work-group range."""
+    c, v, h, pl = make_case(synth.WORKLOADS["c0"], 3)
+    m = 640
+    U = synth.trial_block(h.ng, m, 640)
+    W = h.apply(U)
+    e_ref, p_ref, hp_ref, f = oracle.rayleigh_ritz(U, W, m)
+    assert f == 0
+    eps, psi, hpsi = pl.rayleigh_ritz(to_dev(U), to_dev(W), m)
+    eps, psi, hpsi = to_np(eps), to_np(psi)[:, :h.ng], to_np(hpsi)[:, :h.ng]
+    assert np.abs(eps - e_ref).max() <= EIG_TOL * max(1.0, np.abs(e_ref).max())
+    assert np.abs(psi.conj() @ psi.T - np.eye(m)).max() < 1e-10
+    for i, j in gapped_clusters(e_ref, m, gap=GAP):
+        assert subspace_sin(psi[i:j], p_ref[i:j]) < SIN_TOL, (i, j)
+    assert _hermitian_diag_err(psi, hpsi, eps) < 1e-10 * max(1.0, np.abs(e_ref).max())
+    assert pl.status() == 0

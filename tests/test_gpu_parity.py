@@ -113,7 +113,7 @@ def test_zgemm_nn_vs_numpy(M, N, K):
     assert rel_err(C2, ref + C0_) < 1e-13 * np.sqrt(K)
 
 
-@pytest.mark.parametrize("m", [1, 2, 7, 64, 93, 160, 207, 208, 333, 352, 353])
+@pytest.mark.parametrize("m", [1, 2, 7, 64, 93, 160, 207, 208, 333, 352, 353, 640])
 def test_device_heev_vs_lapack(m):
     import paper_1702_04045_amd as P
     rng = np.random.default_rng(m)
@@ -165,7 +165,7 @@ def test_apply_h_matches_oracle(spec, nb):
     assert rel_err(got0, ref0) < 1e-12
 
 
-@pytest.mark.parametrize("grid", [8, 24, 40, 48, 64, 80, 96])
+@pytest.mark.parametrize("grid", [8, 24, 40, 48, 64, 80, 96, 160])
 def test_apply_h_every_supported_grid(grid):
     """Every instantiated FFT length (including blocks that are not whole
     wavefronts) against the oracle; grids larger than 4 n_max + 1 are valid."""
@@ -174,6 +174,16 @@ def test_apply_h_every_supported_grid(grid):
     c, v, h, pl = make_case(spec, 9)
     x = synth.trial_block(h.ng, 5, 9)
     assert rel_err(to_np(pl.apply_h(to_dev(x))), h.apply(x)) < 1e-12
+
+
+@pytest.mark.parametrize("grid", [96, 160])
+def test_apply_h_f32_large_grids(grid):
+    """The FP32 transforms at the two largest lengths (cross-lane 96-point
+    lines; 160-point split plane stage) against the oracle."""
+    spec = synth.small_cell(a=6.0, ecut=4.0, grid=grid, n_atoms=2)
+    c, v, h, pl = make_case(spec, 9)
+    x = synth.trial_block(h.ng, 5, 9).astype(np.complex64)
+    assert rel_err(to_np(pl.apply_h_f32(to_dev(x))), h.apply(x.astype(np.complex128))) < 2e-6
 
 
 def test_apply_h_padded_leading_dimension():
