@@ -257,6 +257,85 @@ def batched_cells(args, P, torch, n_outer=5, n_cg=10, n_streams=8, reps=3):
             "speedup_vs_sequential": t_seq / t_bat, "dtype": "f64"}
 
 
+def at_scale(args, P, torch, steps=3, tta=False, tta_seconds=600.0):
+    """The 161k-plane-wave cell (a = 30 bohr, E_cut = 25 Ha, 160^3 grid, 128
+    atoms with 512 projectors, 512 + 128 bands, 20 PCG steps, adaptive shift):
+    outer iterations per second in FP64 and in mixed precision, timed with
+    events after one warm-up iteration from the initial Rayleigh-Ritz; the
+    timed paro_apply_h / paro_apply_h_f32 on the 640-band block.  With tta,
+    both precisions run from the trial block until the certified bound on the
+    512 lowest eigenvalues is 1e-8 Ha, and the two sets of eigenvalues are
+    compared band by band."""
+    spec = synth.WORKLOADS["c3"]
+    dev = torch.device("cuda:0")
+    cell = synth.make_cell(spec, args.seed)
+    v = synth.vloc_on_grid(cell["cell"], cell["grid"], cell["positions"], cell["depths"], cell["widths"])
+    pl = P.Plan(cell["cell"], cell["ecut"], v, cell["projectors"], device=dev)
+    nb, nconv, ncg = spec.n_carried, spec.n_bands, spec.n_cg
+    x0 = torch.from_numpy(synth.trial_block(pl.ng, nb, args.seed)).to(dev)
+    sig = pl.shift_lower_bound()
+    kw = dict(shift_mode=P.SHIFT_ADAPTIVE, n_conv=nconv)
+    out = {"workload": spec.name, "n_g": pl.ng, "grid": list(pl.grid), "bands": nb, "bands_converged": nconv,
+           "projectors": pl.n_proj, "pcg_steps": ncg}
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
+        psi = x0.clone()
+        st = pl.iterate(psi, 1, ncg, sig, initial_rr=True, stats=False, precision=prec, **kw)
+        h, e = st["hpsi"], st["eps"]
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        pl.iterate(psi, steps, ncg, sig, hpsi=h, eps=e, initial_rr=False, stats=False, precision=prec, **kw)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[name] = {"outer_iterations_per_s": 1000.0 / ms, "ms_per_step": ms, "status_flags": pl.status()}
+    for name, f, blk in (("fp64", pl.apply_h, x0), ("mixed", pl.apply_h_f32, x0.to(torch.complex64))):
+        o = f(blk)
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(3):
+            f(blk, out=o)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / 3 * 1e3 / nb
+        local, nlf, byts = hpsi_work(pl.grid[0], pl.n_sticks, 2 * pl.nmax[0] + 1, pl.ng, pl.n_proj, 64)
+        peak = PEAK_FP64_VALU if name == "fp64" else PEAK_FP32_VALU
+        t_roof = max(byts / (2 if name == "mixed" else 1) / PEAK_HBM, local / peak) * 1e6 + nlf / peak * 1e6
+        out[name]["hpsi_us_per_band_apply"] = us
+        out[name]["hpsi_roofline_frac"] = t_roof / us
+        out[name]["hpsi_t_roof_us"] = t_roof
+    out["mixed"]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    if tta:
+        final = {}
+        for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
+            psi = x0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = pl.iterate(psi, 0, ncg, sig, initial_rr=True, stats=True, precision=prec, **kw)
+            h, e = r["hpsi"], r["eps"]
+            its, bound, row = 0, np.inf, None
+            while time.perf_counter() - t0 < tta_seconds:
+                r = pl.iterate(psi, 10, ncg, sig, hpsi=h, eps=e, initial_rr=False, stats=True, precision=prec, **kw)
+                its += r["n_done"]
+                row = r["stats"][-1].cpu().numpy()
+                bound = kato_temple_bound(row[:nb], row[nb:2 * nb], nconv)
+                print(json.dumps({"c3_tta_progress": name, "outer_iterations": its, "bound": bound}), flush=True)
+                if bound <= 1e-8:
+                    break
+            torch.cuda.synchronize()
+            out[name]["time_to_1e-8"] = {"outer_iterations": its, "seconds": time.perf_counter() - t0,
+                                         "eig_err_bound": bound, "reached": bool(bound <= 1e-8)}
+            final[name] = row
+        de = np.abs(final["mixed"][:nconv] - final["fp64"][:nconv])
+        out["mixed_vs_fp64_eigenvalues"] = {
+            "max_abs_diff_ha": float(de.max()), "median_abs_diff_ha": float(np.median(de)),
+            "per_band_bound_ha": "Kato-Temple bound of each run <= 1e-8 (time_to_1e-8.eig_err_bound); "
+                                 "|diff| <= sum of the two bounds"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +346,9 @@ def main():
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-1e-8 run")
     ap.add_argument("--tta-seconds", type=float, default=60.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the 24-cell batched run")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 161k-plane-wave (160^3) leg")
+    ap.add_argument("--c3-tta", action="store_true",
+                    help="only run the 161k-plane-wave leg with the time to 1e-8 Ha in both precisions and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--traffic-pass", action="store_true",
@@ -286,6 +368,9 @@ def main():
     import torch
     import paper_1702_04045_amd as P
     from paper_1702_04045_amd import _lib as L
+    if args.c3_tta:
+        print(json.dumps({"at_scale": at_scale(args, P, torch, tta=True, tta_seconds=args.tta_seconds)}))
+        return
 
     dev = torch.device("cuda:0")
     spec = synth.WORKLOADS["c1"]
@@ -494,6 +579,7 @@ def main():
         "fp64": tta(P.PREC_FP64, P.VARIANT_MPARO1, 10), "mixed": tta(P.PREC_MIXED, P.VARIANT_MPARO1, 10)}
 
     batched = None if args.no_batch else batched_cells(args, P, torch)
+    scale = None if args.no_c3 else at_scale(args, P, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -509,7 +595,8 @@ def main():
            "applies (20 PCG + H U); hpsi_timed is paro_apply_h alone", "hpsi_timed": hpsi,
            "wall_s_timed": wall, "status_flags": status,
            "roofline": roofline, "time_to_1e-8": tta64, "mixed": mixed,
-           "time_to_1e-8_mparo1_10pcg": fastest, "density": density, "batched_cells": batched, "cpu_baseline": cpu}
+           "time_to_1e-8_mparo1_10pcg": fastest, "density": density, "batched_cells": batched,
+           "mixed_at_scale": scale, "cpu_baseline": cpu}
     print(json.dumps(rec))
 
 

@@ -358,6 +358,34 @@ int32_t paro_projector_gradient_workspace_bytes(paro_plan plan, int32_t nb, size
 int32_t paro_projector_gradient(paro_plan plan, int32_t nb, const double *psi, int64_t ld, const double *weights,
                                 double *dd, double *dR, void *ws, size_t ws_bytes);
 
+/* Reverse-mode gradient of the band energy after K truncated outer
+ * iterations of Algorithm 1 (Section 3) at a fixed shift:
+ *   (eps^0, psi^0) = Rayleigh-Ritz of the trial block (step 1), then K outer
+ *   iterations of n_cg PCG steps per source problem and Rayleigh-Ritz
+ *   (steps 3 and 4), exactly as paro_iterate with PARO_SHIFT_FIXED and no
+ *   tolerance, and E = sum_b w_b eps_b^K.
+ * Writes E and its derivatives with respect to the local potential on the
+ * grid (dvloc[j] = dE/dvloc[j], C order like paro_problem.vloc) and to the
+ * projector centres (dR[3p + a] = dE/dR_p,a), differentiating the truncated
+ * map itself (not its converged limit): one checkpoint per outer
+ * iteration, each outer iteration recomputed in the backward pass with its
+ * PCG iterates kept, then the Rayleigh-Ritz, H U and PCG steps reversed on
+ * the device.  The trial block and sigma are constants.
+ * trial: dev complex nb bands, leading dimension ld >= n_g; weights: dev
+ * double[nb]; energy: dev double[1]; dvloc: dev double[N1 N2 N3]; dR: dev
+ * double[3 n_proj] (may be NULL when n_proj = 0); all outputs overwritten.
+ * ws: dev, 256-byte aligned, paro_truncated_gradient_workspace_bytes(nb,
+ * n_outer, n_cg) bytes (about (n_outer + 4 n_cg + 20) nb n_g 16 bytes).
+ * A source problem that stopped early (PCG's stopping rules) is
+ * differentiated along that branch: its later steps are the identity.
+ * Synchronises the plan's stream.  Errors: PARO_EINVAL, PARO_ESIZE,
+ * PARO_EUNSUP (grid above 96 points). */
+int32_t paro_truncated_gradient_workspace_bytes(paro_plan plan, int32_t nb, int32_t n_outer, int32_t n_cg,
+                                                size_t *bytes);
+int32_t paro_truncated_gradient(paro_plan plan, int32_t nb, const double *trial, int64_t ld, double sigma,
+                                int32_t n_outer, int32_t n_cg, const double *weights, double *energy, double *dvloc,
+                                double *dR, void *ws, size_t ws_bytes);
+
 /* ---------------------------------------------------------------- building blocks */
 
 /* Complex double GEMMs on the FP64 matrix cores, the products the hot

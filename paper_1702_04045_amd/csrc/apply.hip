@@ -49,7 +49,7 @@ template <int N, class C2> constexpr int plane_threads() { return (N * PlaneCfgP
 constexpr int kBandsPerBlock = 4;  // bands one work-group of the plane kernel takes through its z-plane
 // Line transforms done across lanes (xlane96_inverse / xlane96_forward)
 // instead of through LDS: the 96-point lines, both precisions.
-template <int N, class C2> constexpr bool xlane_rows() { return N == 96; }
+template <int N, class C2> constexpr bool xlane_rows() { return N == 96 || N == 160; }
 // Plans need N >= 4 n_max + 1 on every axis, so at N = 96 every populated
 // index has |n| <= 23: a line's inputs x[t + 8 m] with m = 3..8 (indices
 // 24..71) are zero and those outputs are never used.  The cross-lane
@@ -62,6 +62,23 @@ __device__ __forceinline__ int opaque(int t)
 {
     asm volatile("" : "+v"(t));
     return t;
+}
+// Cross-lane transforms by length: the pruned 96-point functions, or the
+// general N = 8 E schedule (160 points, every position kept).
+template <int N> __host__ __device__ constexpr int xl_index(int t, int s)
+{
+    return N == 96 ? xlane_index(t, s) : xlane_index_e<N / 8>(t, s);
+}
+template <int N> __device__ __forceinline__ constexpr bool xl_kept(int m) { return N == 96 ? xlane_kept(m) : true; }
+template <int N, class C2> __device__ __forceinline__ void xl_inverse(C2 (&v)[N / 8], int t, const C2 *tw)
+{
+    if constexpr (N == 96) xlane96_inverse<kXlanePrune>(v, t, tw);
+    else xlane_inverse_n<N>(v, t, tw);
+}
+template <int N, class C2> __device__ __forceinline__ void xl_forward(C2 (&v)[N / 8], int t, const C2 *tw)
+{
+    if constexpr (N == 96) xlane96_forward<kXlanePrune>(v, t, tw);
+    else xlane_forward_n<N>(v, t, tw);
 }
 
 // Sphere -> sticks, inverse transform along n3.  Line (stick) threads are
@@ -113,11 +130,11 @@ k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const
         // cross-lane transform (every lane takes part; the tile is zero past
         // the last stick), outputs stored in the schedule's register order
 #pragma unroll
-        for (int m = 0; m < E; ++m) v[m] = xlane_kept(m) ? line[t + T * m] : cmk<C2>(0.0, 0.0);
-        xlane96_inverse<kXlanePrune>(v, opaque(t), twl);
+        for (int m = 0; m < E; ++m) v[m] = xl_kept<N3>(m) ? line[t + T * m] : cmk<C2>(0.0, 0.0);
+        xl_inverse<N3>(v, opaque(t), twl);
         if (act) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) out[(size_t)xlane_index(t, e) * nst + s] = v[e];
+            for (int e = 0; e < E; ++e) out[(size_t)xl_index<N3>(t, e) * nst + s] = v[e];
         }
     } else {
         if (act) pass_load<N3, T, E, ListInfo<typename C::Inv>::first>(v, t, [&](int i) { return line[i]; });
@@ -500,7 +517,7 @@ k_density_reduce(const double *__restrict__ part, int ngroups, int N3, int accum
     for (int idx = threadIdx.x; idx < nz * N; idx += 256) {
         const int zz = idx / N, q = idx - zz * N;
         const int t = q / E, e = q - t * E;
-        const int x = xlane_rows<N, double2>() ? xlane_index(t, e) : t + T * (e / RL) + (e % RL) * (N / RL);
+        const int x = xlane_rows<N, double2>() ? xl_index<N>(t, e) : t + T * (e / RL) + (e % RL) * (N / RL);
         const double *p = part + ((size_t)(z0 + zz) * N + y) * N + q;
         double s = 0.0;
         for (int gi = 0; gi < ngroups; ++gi) s += p[gi * gstride];
@@ -530,7 +547,7 @@ void plane_potential(const int32_t *grid, const double *vloc, VT *out)
         for (int y = 0; y < N2; ++y)
             for (int t = 0; t < T; ++t)
                 for (int e = 0; e < E; ++e) {
-                    const int x = xlane_rows<N, C2>() ? xlane_index(t, e) : t + T * (e / RL) + (e % RL) * (N / RL);
+                    const int x = xlane_rows<N, C2>() ? xl_index<N>(t, e) : t + T * (e / RL) + (e % RL) * (N / RL);
                     out[(((size_t)z * N + y) * T + t) * E + e] = (VT)vloc[((size_t)x * N2 + y) * N3 + z];
                 }
 }
@@ -565,11 +582,11 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
         // cross-lane transform: inputs read in the schedule's register order
         // (zero past the last stick), outputs x[t + T m]
 #pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = act ? in[(size_t)xlane_index(t, e) * nst + s] : cmk<C2>(0.0, 0.0);
-        xlane96_forward<kXlanePrune>(v, opaque(t), twl);
+        for (int e = 0; e < E; ++e) v[e] = act ? in[(size_t)xl_index<N3>(t, e) * nst + s] : cmk<C2>(0.0, 0.0);
+        xl_forward<N3>(v, opaque(t), twl);
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            if (xlane_kept(m)) line[t + T * m] = v[m];
+            if (xl_kept<N3>(m)) line[t + T * m] = v[m];
     } else {
         if (act) pass_load<N3, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return in[(size_t)i * nst + s]; });
         stockham<N3, -1, true>(Fwd{}, v, t, act, line, 1, twl);
@@ -610,27 +627,29 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
 //   k_row       rows: Q -> inverse along n1, x V, forward along n1 -> Q
 //               (populated columns only),
 //   k_col_fwd   columns: Q -> forward along n2 -> sticks (the column's sticks).
-// Each line is T consecutive-by-line lanes of one wavefront (line_of), so
-// its Stockham exchanges need only wavefront ordering; the tile holds one
-// line slot per line.  The eight lanes at one element index take eight
-// consecutive lines, i.e. eight consecutive columns c of Q (row kernel:
-// eight consecutive rows), so their stores and loads are runs of eight.
-template <int N, class C2> constexpr int split_threads() { return sizeof(C2) == 16 ? 128 : 256; }
+// Every line is a cross-lane transform on 8 lanes (thread t holds the
+// elements t + 8 m in registers), so the kernels use no LDS but the
+// twiddle table's copy.  The eight lanes at one element index belong to
+// eight consecutive lines, i.e. eight consecutive columns c of Q (row
+// kernel: eight consecutive rows), so their stores and loads are runs of
+// eight.  Lines past the last column transform zeros on every lane (a swap
+// pairs lanes of one line) without loads or stores.
+constexpr int kSplitThreads = 256;
+// the fused LDS plane stage (k_plane_cc) instead of the three batches
+constexpr bool kFusedPlaneAbove96 = true;
 
 template <int N, class C2>
-__global__ void __launch_bounds__((split_threads<N, C2>()))
+__global__ void __launch_bounds__(kSplitThreads)
 k_col_inv(const C2 *__restrict__ sticks, int nst, int N3, const int32_t *__restrict__ cols, int ncol,
           C2 *__restrict__ Q, const C2 *__restrict__ tw)
 {
-    using C = FftCfg<N>;
-    constexpr int NT = split_threads<N, C2>(), T = C::T, E = C::E, S = NT / T, LD = N + 1;
-    constexpr int RL = ListInfo<typename C::Inv>::last;
-    __shared__ C2 tile[S * LD];
+    static_assert(xlane_rows<N, C2>(), "cross-lane lines");
+    constexpr int T = 8, E = N / 8;
     __shared__ C2 twl[N];
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
-    for (int i = tid; i < N; i += NT) twl[i] = tw[i];
+    for (int i = tid; i < N; i += kSplitThreads) twl[i] = tw[i];
     __syncthreads();
-    const int c = blockIdx.x * S + sl, z = blockIdx.y, band = blockIdx.z;
+    const int c = blockIdx.x * (kSplitThreads / T) + sl, z = blockIdx.y, band = blockIdx.z;
     const bool act = c < ncol;
     int cst = 0, ylo = 0, cnt = 0;
     if (act) {
@@ -640,64 +659,68 @@ k_col_inv(const C2 *__restrict__ sticks, int nst, int N3, const int32_t *__restr
     }
     const C2 *tz = sticks + ((size_t)band * N3 + z) * nst + cst;
     C2 v[E];
-    if (act) pass_load<N, T, E, ListInfo<typename C::Inv>::first>(v, t, [&](int i) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i = t + T * m;
         const int k = (i > N / 2 ? i - N : i) - ylo;
-        return (unsigned)k < (unsigned)cnt ? tz[k] : cmk<C2>(0.0, 0.0);
-    });
-    stockham<N, +1, true>(typename C::Inv{}, v, t, act, tile + sl * LD, 1, twl);
+        v[m] = (act && (unsigned)k < (unsigned)cnt) ? tz[k] : cmk<C2>(0.0, 0.0);
+    }
+    xl_inverse<N>(v, opaque(t), twl);
     C2 *q = Q + ((size_t)band * N3 + z) * N * ncol + c;
-    if (act) final_foreach<N, T, E, RL>(v, t, [&](int i, int e) { q[(size_t)i * ncol] = v[e]; });
+    if (act) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) q[(size_t)xl_index<N>(t, e) * ncol] = v[e];
+    }
 }
 
 template <int N, class C2>
-__global__ void __launch_bounds__((split_threads<N, C2>()))
+__global__ void __launch_bounds__(kSplitThreads)
 k_row(C2 *__restrict__ Q, int N3, int ncol, int nmax1, const RealOf<C2> *__restrict__ vperm,
       const C2 *__restrict__ tw)
 {
-    using C = FftCfg<N>;
-    using Inv = typename C::Inv;
-    using Fwd = typename C::Fwd;
-    static_assert(ListInfo<Inv>::last == ListInfo<Fwd>::first, "the forward starts where the inverse ends");
-    constexpr int NT = split_threads<N, C2>(), T = C::T, E = C::E, S = NT / T, LD = N + 1;
-    __shared__ C2 tile[S * LD];
+    static_assert(xlane_rows<N, C2>(), "cross-lane lines");
+    constexpr int T = 8, E = N / 8;
     __shared__ C2 twl[N];
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
-    for (int i = tid; i < N; i += NT) twl[i] = tw[i];
+    for (int i = tid; i < N; i += kSplitThreads) twl[i] = tw[i];
     __syncthreads();
-    const int y = blockIdx.x * S + sl, z = blockIdx.y, band = blockIdx.z;
+    const int y = blockIdx.x * (kSplitThreads / T) + sl, z = blockIdx.y, band = blockIdx.z;
     const bool act = y < N;
     C2 *row = Q + (((size_t)band * N3 + z) * N + (act ? y : 0)) * ncol;
-    auto populated = [&](int i) { return i <= nmax1 || i >= N - nmax1; };
-    auto col_of = [&](int i) { return i <= nmax1 ? i + nmax1 : i - N + nmax1; };
     C2 v[E];
-    if (act) pass_load<N, T, E, ListInfo<Inv>::first>(v, t, [&](int i) {
-        return populated(i) ? row[col_of(i)] : cmk<C2>(0.0, 0.0);
-    });
-    C2 *line = tile + sl * LD;
-    stockham<N, +1, true>(Inv{}, v, t, act, line, 1, twl);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i = t + T * m;
+        const bool pop = i <= nmax1 || i >= N - nmax1;
+        v[m] = (act && pop) ? row[i <= nmax1 ? i + nmax1 : i - N + nmax1] : cmk<C2>(0.0, 0.0);
+    }
+    xl_inverse<N>(v, opaque(t), twl);
+    // the potential in the register order of the cross-lane inverse
     const RealOf<C2> *vp = vperm + (((size_t)z * N + (act ? y : 0)) * T + t) * E;
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vp[e]);
-    stockham<N, -1, true>(Fwd{}, v, t, act, line, 1, twl);
-    if (act) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
-        if (populated(i)) row[col_of(i)] = v[e];
-    });
+    xl_forward<N>(v, opaque(t), twl);
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int i = t + T * m;
+            if (i <= nmax1 || i >= N - nmax1) row[i <= nmax1 ? i + nmax1 : i - N + nmax1] = v[m];
+        }
+    }
 }
 
 template <int N, class C2>
-__global__ void __launch_bounds__((split_threads<N, C2>()))
+__global__ void __launch_bounds__(kSplitThreads)
 k_col_fwd(const C2 *__restrict__ Q, int N3, int ncol, const int32_t *__restrict__ cols, C2 *__restrict__ sticks,
           int nst, const C2 *__restrict__ tw)
 {
-    using C = FftCfg<N>;
-    using Fwd = typename C::Fwd;
-    constexpr int NT = split_threads<N, C2>(), T = C::T, E = C::E, S = NT / T, LD = N + 1;
-    __shared__ C2 tile[S * LD];
+    static_assert(xlane_rows<N, C2>(), "cross-lane lines");
+    constexpr int T = 8, E = N / 8;
     __shared__ C2 twl[N];
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
-    for (int i = tid; i < N; i += NT) twl[i] = tw[i];
+    for (int i = tid; i < N; i += kSplitThreads) twl[i] = tw[i];
     __syncthreads();
-    const int c = blockIdx.x * S + sl, z = blockIdx.y, band = blockIdx.z;
+    const int c = blockIdx.x * (kSplitThreads / T) + sl, z = blockIdx.y, band = blockIdx.z;
     const bool act = c < ncol;
     int cst = 0, ylo = 0, cnt = 0;
     if (act) {
@@ -707,13 +730,147 @@ k_col_fwd(const C2 *__restrict__ Q, int N3, int ncol, const int32_t *__restrict_
     }
     const C2 *q = Q + ((size_t)band * N3 + z) * N * ncol + (act ? c : 0);
     C2 v[E];
-    if (act) pass_load<N, T, E, ListInfo<Fwd>::first>(v, t, [&](int i) { return q[(size_t)i * ncol]; });
-    stockham<N, -1, true>(Fwd{}, v, t, act, tile + sl * LD, 1, twl);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = act ? q[(size_t)xl_index<N>(t, e) * ncol] : cmk<C2>(0.0, 0.0);
+    xl_forward<N>(v, opaque(t), twl);
     C2 *tz = sticks + ((size_t)band * N3 + z) * nst + cst;
-    if (act) final_foreach<N, T, E, ListInfo<Fwd>::last>(v, t, [&](int i, int e) {
-        const int k = (i > N / 2 ? i - N : i) - ylo;
-        if ((unsigned)k < (unsigned)cnt) tz[k] = v[e];
-    });
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int i = t + T * m;
+            const int k = (i > N / 2 ? i - N : i) - ylo;
+            if ((unsigned)k < (unsigned)cnt) tz[k] = v[m];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- fused plane stage above 96 points
+// One z-plane of up to kCcBands bands per work-group, with the plane held
+// in LDS in compressed-column form: plane[c][y] for the populated columns
+// c = n1 + nmax1 only (ncol <= kCcMaxCols), y = n2 mod N.  Per band: the
+// inverse column transforms (sticks -> plane), the row transforms (inverse,
+// x V, forward; populated entries read and written back), the forward
+// column transforms (plane -> sticks).  All lines are cross-lane transforms
+// (8 lanes, no exchange space), so LDS holds only the plane.  FP32: the
+// whole plane, 79 x 161 x 8 B = 102 KB at most.  FP64 would need twice that,
+// so the rows go in two passes of N/2 (y < N/2, then y >= N/2): each pass
+// stores half of every inverse column's outputs, and the forward columns,
+// linear in their input, add the second pass's transform of the other half
+// to the stick values the first pass wrote.  The outputs go to a second
+// stick buffer (sout): the second pass reads its inputs again from sin.
+constexpr int kCcMaxCols = 79;   // 2 nmax + 1 with 160 >= 4 nmax + 1
+constexpr int kCcThreads = 640;  // 80 line slots of 8 lanes
+constexpr int kCcBands = 4;      // bands per work-group
+template <class C2> constexpr int cc_passes() { return sizeof(C2) == 16 ? 2 : 1; }
+
+template <int N, class C2>
+__global__ void __launch_bounds__(kCcThreads)
+k_plane_cc(const C2 *__restrict__ sin, C2 *__restrict__ sout, int nst, int N3, int nb, const int32_t *__restrict__ cols,
+           int ncol, int nmax1, const RealOf<C2> *__restrict__ vperm, const C2 *__restrict__ tw)
+{
+    static_assert(xlane_rows<N, C2>(), "cross-lane lines");
+    constexpr int T = 8, E = N / 8, NP = cc_passes<C2>(), NR = N / NP, LDY = NR + 1;
+    constexpr int SLOTS = kCcThreads / T;
+    static_assert(NR % SLOTS == 0 && SLOTS >= kCcMaxCols, "whole row rounds; one line slot per column");
+    __shared__ C2 plane[kCcMaxCols * LDY];
+    __shared__ C2 twl[N];
+    const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
+    for (int i = tid; i < N; i += kCcThreads) twl[i] = tw[i];
+    __syncthreads();
+    const int z = blockIdx.x;
+    const int b0 = blockIdx.y * kCcBands, b1 = min(b0 + kCcBands, nb);
+    const int c = sl;
+    const bool colact = c < ncol;
+    int cst = 0, ylo = 0, cnt = 0;
+    if (colact) {
+        cst = cols[3 * c];
+        ylo = cols[3 * c + 1];
+        cnt = cols[3 * c + 2];
+    }
+    for (int k = b0; k < b1; ++k) {
+#pragma unroll 1
+        for (int p = 0; p < NP; ++p) {
+            C2 v[E];
+            {
+                // inverse along n2 of column c; keep the outputs of this pass's rows.
+                // (The index values of each stage are made opaque, so that the
+                // compiler recomputes them per stage instead of holding every
+                // stage's offsets in registers across the band loop.)
+                int tt = t, lo = ylo, n = cnt;
+                asm volatile("" : "+v"(tt), "+v"(lo), "+v"(n));
+                const C2 *tz = sin + ((size_t)k * N3 + z) * nst + cst;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int i = tt + T * m;
+                    const int q = (i > N / 2 ? i - N : i) - lo;
+                    v[m] = (colact && (unsigned)q < (unsigned)n) ? tz[q] : cmk<C2>(0.0, 0.0);
+                }
+                xl_inverse<N>(v, opaque(t), twl);
+                if (colact) {
+                    C2 *pc = plane + c * LDY;
+                    const int ts = opaque(t);
+#pragma unroll
+                    for (int s = 0; s < E; ++s) {
+                        const int y = xl_index<N>(ts, s);
+                        if (NP == 1 || y / NR == p) pc[y - p * NR] = v[s];
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int r = sl; r < NR; r += SLOTS) {
+                // row y = p NR + r along n1: inverse, x V, forward (populated columns only)
+                const int y = p * NR + r;
+                int tt = t, nm = nmax1;
+                asm volatile("" : "+v"(tt), "+v"(nm));
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int i = tt + T * m;
+                    const bool pop = i <= nm || i >= N - nm;
+                    v[m] = pop ? plane[(i <= nm ? i + nm : i - N + nm) * LDY + r] : cmk<C2>(0.0, 0.0);
+                }
+                xl_inverse<N>(v, opaque(t), twl);
+                const RealOf<C2> *vp = vperm + (((size_t)z * N + y) * T + opaque(t)) * E;
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vp[e]);
+                xl_forward<N>(v, opaque(t), twl);
+                int tw2 = t, nm2 = nmax1;
+                asm volatile("" : "+v"(tw2), "+v"(nm2));
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int i = tw2 + T * m;
+                    if (i <= nm2 || i >= N - nm2) plane[(i <= nm2 ? i + nm2 : i - N + nm2) * LDY + r] = v[m];
+                }
+            }
+            __syncthreads();
+            {
+                // forward along n2 of column c from this pass's rows; back to the sticks
+                const int ts = opaque(t);
+                const C2 *pc = plane + (colact ? c : 0) * LDY;
+#pragma unroll
+                for (int s = 0; s < E; ++s) {
+                    const int y = xl_index<N>(ts, s);
+                    v[s] = (colact && (NP == 1 || y / NR == p)) ? pc[y - p * NR] : cmk<C2>(0.0, 0.0);
+                }
+                xl_forward<N>(v, opaque(t), twl);
+                if (colact) {
+                    int tt = t, lo = ylo, n = cnt;
+                    asm volatile("" : "+v"(tt), "+v"(lo), "+v"(n));
+                    C2 *tz = sout + ((size_t)k * N3 + z) * nst + cst;
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {
+                        const int i = tt + T * m;
+                        const int q = (i > N / 2 ? i - N : i) - lo;
+                        if ((unsigned)q < (unsigned)n) {
+                            if (p == 0) tz[q] = v[m];
+                            else tz[q] = cadd(tz[q], v[m]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
 }
 
 // Precision-specific plan tables.
@@ -771,7 +928,7 @@ hipError_t run_local_split(const Plan &pl, const Workspace &w, int nb, const C2 
 {
     constexpr int NT = stick_threads<N, C2>();
     constexpr int S = NT / FftCfg<N>::T;
-    constexpr int NTS = split_threads<N, C2>(), SL = NTS / FftCfg<N>::T;
+    constexpr int NTS = kSplitThreads, SL = NTS / 8;
     static_assert(N % SL == 0, "rows split evenly into work-groups");
     const int N3 = pl.grid[2];
     const int ntiles = (pl.nst + S - 1) / S;
@@ -788,16 +945,24 @@ hipError_t run_local_split(const Plan &pl, const Workspace &w, int nb, const C2 
                            pl.st_start, pl.pt_sz, PlanTabs<C2>::tw(pl, 2));
         prof_mark(PARO_K_STICK_INV, pl.stream, false);
         prof_mark(PARO_K_PLANE, pl.stream, true);
-        hipLaunchKernelGGL((k_col_inv<N, C2>), dim3((ncol + SL - 1) / SL, N3, cb), dim3(NTS), 0, pl.stream, sticks,
-                           pl.nst, N3, pl.cols, ncol, Q, PlanTabs<C2>::tw(pl, 1));
-        hipLaunchKernelGGL((k_row<N, C2>), dim3(N / SL, N3, cb), dim3(NTS), 0, pl.stream, Q, N3, ncol, pl.nmax[0],
-                           PlanTabs<C2>::v(pl), PlanTabs<C2>::tw(pl, 0));
-        hipLaunchKernelGGL((k_col_fwd<N, C2>), dim3((ncol + SL - 1) / SL, N3, cb), dim3(NTS), 0, pl.stream, Q, N3,
-                           ncol, pl.cols, sticks, pl.nst, PlanTabs<C2>::tw(pl, 1));
+        const bool fused = kFusedPlaneAbove96 && ncol <= kCcMaxCols;
+        if (fused) {
+            // out of place: the forward sticks go to Q, which is at least as large
+            hipLaunchKernelGGL((k_plane_cc<N, C2>), dim3(N3, (cb + kCcBands - 1) / kCcBands), dim3(kCcThreads), 0,
+                               pl.stream, sticks, Q, pl.nst, N3, cb, pl.cols, ncol, pl.nmax[0], PlanTabs<C2>::v(pl),
+                               PlanTabs<C2>::tw(pl, 0));
+        } else {
+            hipLaunchKernelGGL((k_col_inv<N, C2>), dim3((ncol + SL - 1) / SL, N3, cb), dim3(NTS), 0, pl.stream,
+                               sticks, pl.nst, N3, pl.cols, ncol, Q, PlanTabs<C2>::tw(pl, 1));
+            hipLaunchKernelGGL((k_row<N, C2>), dim3(N / SL, N3, cb), dim3(NTS), 0, pl.stream, Q, N3, ncol,
+                               pl.nmax[0], PlanTabs<C2>::v(pl), PlanTabs<C2>::tw(pl, 0));
+            hipLaunchKernelGGL((k_col_fwd<N, C2>), dim3((ncol + SL - 1) / SL, N3, cb), dim3(NTS), 0, pl.stream, Q,
+                               N3, ncol, pl.cols, sticks, pl.nst, PlanTabs<C2>::tw(pl, 1));
+        }
         prof_mark(PARO_K_PLANE, pl.stream, false);
         const C2 *x = pbuf ? pbuf : src;
         prof_mark(PARO_K_STICK_FWD, pl.stream, true);
-        hipLaunchKernelGGL((k_stick_fwd<N, C2>), dim3(ntiles, cb), dim3(NT), 0, pl.stream, sticks, pl.nst,
+        hipLaunchKernelGGL((k_stick_fwd<N, C2>), dim3(ntiles, cb), dim3(NT), 0, pl.stream, fused ? Q : sticks, pl.nst,
                            pl.st_start, pl.pt_sz, PlanTabs<C2>::tw(pl, 2), x + c0 * ld, ld, out + c0 * ld, pl.kin,
                            shift ? shift + c0 : nullptr, scale,
                            dot_part ? dot_part + (size_t)c0 * kMaxParts : nullptr, kMaxParts);
@@ -808,7 +973,7 @@ hipError_t run_local_split(const Plan &pl, const Workspace &w, int nb, const C2 
 
 template <int N>
 hipError_t run_density(const Plan &pl, double2 *sticks, double *part, int nb, const double2 *psi, int64_t ld,
-                       const double *weights, double *rho)
+                       const double *weights, double *rho, bool accumulate)
 {
     constexpr int NT = stick_threads<N, double2>();
     constexpr int S = NT / FftCfg<N>::T;
@@ -825,7 +990,7 @@ hipError_t run_density(const Plan &pl, double2 *sticks, double *part, int nb, co
                            weights ? weights + c0 : nullptr, pl.tw[0], part);
         prof_mark(PARO_K_DENSITY, pl.stream, false);
         hipLaunchKernelGGL((k_density_reduce<N>), dim3(N, (N3 + kRedZ - 1) / kRedZ), dim3(256), 0, pl.stream, part,
-                           ng, N3, c0 > 0 ? 1 : 0, rho);
+                           ng, N3, (accumulate || c0 > 0) ? 1 : 0, rho);
     }
     return hipGetLastError();
 }
@@ -860,11 +1025,11 @@ bool fft_supported(int n)
 bool split_plane(int n) { return n > 96; }
 
 hipError_t launch_density(const Plan &pl, double2 *sticks, double *part, int nb, const double2 *psi, int64_t ld,
-                          const double *weights, double *rho)
+                          const double *weights, double *rho, bool accumulate)
 {
     switch (pl.grid[0]) {
 #define PARO_CASE(n) \
-    case n: return run_density<n>(pl, sticks, part, nb, psi, ld, weights, rho);
+    case n: return run_density<n>(pl, sticks, part, nb, psi, ld, weights, rho, accumulate);
     PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
     PARO_CASE(80) PARO_CASE(96)
 #undef PARO_CASE

@@ -515,7 +515,8 @@ k_tridiag_rows(int m, double2 *__restrict__ A, double *__restrict__ d, double *_
         for (int q = tid; q < mm; q += NT) A[q] = S[q];
 }
 
-// The same reduction spread over kTriDistG work-groups (208 <= m <= 352),
+// The same reduction spread over G work-groups (G = 16 for 208 <= m <= 352,
+// G = 64 for 352 < m <= 704),
 // each holding the columns c = g, g + G, ... of the hermitised matrix in
 // its LDS for the whole sweep, so that the trailing updates read and write
 // LDS only.  Per column k: the owner of column k forms the Householder
@@ -527,14 +528,19 @@ k_tridiag_rows(int m, double2 *__restrict__ A, double *__restrict__ d, double *_
 // rewritten two columns later, after every reader has passed the next
 // column's exchange.  Every wait has a time limit; a work-group that
 // reaches it raises a global abort flag that ends every other wait, and
-// sets PARO_F_SYNC.  The kTriDistG work-groups are launched as an ordinary
+// sets PARO_F_SYNC.  The G work-groups are launched as an ordinary
 // grid after a check that one fits on a compute unit (dist_grid_fits):
-// with 16 of them on a 256-unit device they start together, and a
+// with 16 or 64 of them on a 256-unit device they start together, and a
 // work-group held back by other kernels' work-groups starts once those
 // end, so every wait either succeeds or reaches its limit.  Dynamic LDS:
 // (ceil(m / G) + 2) m + 1 complex values.
 constexpr int kTriDistThreads = 256;
 constexpr int kTriDistMin = 93, kTriDistMax = 352;
+// The second size class: 64 work-groups of 512 threads for 352 < m <= 704
+// (m = 704: 11 columns per work-group, (11 + 2) 704 complex = 146 KB of LDS;
+// 512 threads cover the 2 x 512 rows the tridiagonalisation's y and w
+// loops take per thread).
+constexpr int kTriDistG2 = 64, kTriDistThreads2 = 512, kTriDistMax2 = 704;
 // The tridiagonalisation moves to sixteen work-groups only from m = 208:
 // below that the one-work-group sweep is faster (m = 160: 1.7 against
 // 2.0 ms per eigendecomposition; m = 192: 2.3 against 2.5; m = 256: 4.3
@@ -542,9 +548,13 @@ constexpr int kTriDistMin = 93, kTriDistMax = 352;
 constexpr int kTriDistMinTridiag = 208;
 constexpr long long kTriDistWaitTicks = 20000000;  // 0.2 s of the 100 MHz real-time counter
 
-static size_t tridiag_dist_lds_bytes(int m)
+template <int G> static size_t tridiag_dist_lds_bytes(int m)
 {
-    return sizeof(double2) * (((size_t)(m + kTriDistG - 1) / kTriDistG + 2) * (size_t)m + 1);
+    return sizeof(double2) * (((size_t)(m + G - 1) / G + 2) * (size_t)m + 1);
+}
+template <int G> static size_t chol_dist_lds_bytes(int m)
+{
+    return sizeof(double2) * (((size_t)(m + G - 1) / G + 1) * (size_t)m);
 }
 
 // wait until *p >= target (thread 0 of the work-group); false on abort or time-out
@@ -563,12 +573,12 @@ __device__ bool dist_wait(const int32_t *p, int target, int32_t *abortf, int32_t
     }
 }
 
-__global__ void __launch_bounds__(kTriDistThreads)
+template <int G, int NT>
+__global__ void __launch_bounds__(NT)
 k_tridiag_dist(int m, double2 *__restrict__ A, double *__restrict__ d, double *__restrict__ e,
                double2 *__restrict__ tau, double2 *__restrict__ vbuf, double2 *__restrict__ ypart,
                int32_t *__restrict__ flags, int32_t *__restrict__ status)
 {
-    constexpr int G = kTriDistG, NT = kTriDistThreads;
     extern __shared__ double2 dyn[];
     __shared__ double red[NT / 64];
     __shared__ int s_ok;
@@ -735,7 +745,8 @@ __global__ void __launch_bounds__(256) k_fill_i32(int n, int32_t *__restrict__ p
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = v;
 }
 
-// The same Cholesky spread over kTriDistG work-groups (92 < m <= 352),
+// The same Cholesky spread over G work-groups (G = 16 for 92 < m <= 352,
+// G = 64 for 352 < m <= 704),
 // each holding the columns c = g, g + G, ... of the hermitised S in its LDS
 // for the whole factorisation.  Per column j the owner checks the pivot,
 // scales its column, writes it (final) to L in global memory and raises
@@ -744,11 +755,11 @@ __global__ void __launch_bounds__(256) k_fill_i32(int n, int32_t *__restrict__ p
 // columns.  Published columns are final, so no buffer is reused.  Waits
 // are time-limited as in k_tridiag_dist, and the launch is the same
 // ordinary grid.  Dynamic LDS: (ceil(m / G) + 1) m complex values.
-__global__ void __launch_bounds__(kTriDistThreads)
+template <int G, int NT>
+__global__ void __launch_bounds__(NT)
 k_chol_dist(int m, const double2 *__restrict__ gram, int hs, double2 *__restrict__ L, double2 *__restrict__ X,
             int32_t *__restrict__ flags, int32_t *__restrict__ fail, int32_t *__restrict__ status)
 {
-    constexpr int G = kTriDistG, NT = kTriDistThreads;
     extern __shared__ double2 dyn[];
     __shared__ double red[NT / 64];
     __shared__ int s_state;
@@ -832,20 +843,38 @@ k_chol_dist(int m, const double2 *__restrict__ gram, int hs, double2 *__restrict
     }
 }
 
-// Whether the kTriDistG work-groups of a multi-work-group dense kernel can
-// be resident at once: at least one work-group of NT threads and `lds`
-// bytes of dynamic LDS fits on a compute unit, and the device has at least
-// kTriDistG units.  Checked once per kernel and size class.
-static bool dist_grid_fits(const void *kernel, size_t lds)
+// Whether the G work-groups of NT threads of a multi-work-group dense kernel
+// can be resident at once: at least one work-group with `lds` bytes of
+// dynamic LDS fits on a compute unit, and the device has at least G units.
+// Checked once per kernel and size class.
+static bool dist_grid_fits(const void *kernel, int G, int NT, size_t lds)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kTriDistThreads, lds) != hipSuccess) {
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, NT, lds) != hipSuccess) {
         (void)hipGetLastError();
         return false;
     }
-    return per_cu >= 1 && cus >= kTriDistG;
+    return per_cu >= 1 && cus >= G;
+}
+
+// One size class of the multi-work-group Cholesky: set up once, then
+// launched for kTriDistMin <= m <= MMAX.
+template <int G, int NT, int MMAX>
+static bool launch_chol_dist(hipStream_t st, int m, const double2 *gram, int hs, double2 *L, double2 *X,
+                             int32_t *fail, int32_t *status, int32_t *flags)
+{
+    const void *k = reinterpret_cast<const void *>(k_chol_dist<G, NT>);
+    static const bool ok = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)chol_dist_lds_bytes<G>(MMAX)) == hipSuccess &&
+                           dist_grid_fits(k, G, NT, chol_dist_lds_bytes<G>(MMAX));
+    if (!ok) return false;
+    hipLaunchKernelGGL(k_fill_i32, dim3((2 * m + 1 + 255) / 256), dim3(256), 0, st, 2 * m + 1, flags, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, 1, fail, 0);
+    hipLaunchKernelGGL((k_chol_dist<G, NT>), dim3(G), dim3(NT), chol_dist_lds_bytes<G>(m), st, m, gram, hs, L, X,
+                       flags, fail, status);
+    return true;
 }
 
 // Cholesky of the hermitised S (and hermitised Hs into X when hs): the
@@ -853,21 +882,12 @@ static bool dist_grid_fits(const void *kernel, size_t lds)
 static void launch_chol(hipStream_t st, int m, const double2 *gram, int hs, double2 *L, double2 *X, int32_t *fail,
                         int32_t *status, int32_t *flags = nullptr)
 {
-    if (flags && m >= kTriDistMin && m <= kTriDistMax) {
-        const size_t shmax = sizeof(double2) * (((size_t)(kTriDistMax + kTriDistG - 1) / kTriDistG + 1) * kTriDistMax);
-        static const bool ok = hipFuncSetAttribute(reinterpret_cast<const void *>(k_chol_dist),
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   (int)shmax) == hipSuccess &&
-                               dist_grid_fits(reinterpret_cast<const void *>(k_chol_dist), shmax);
-        if (ok) {
-            hipLaunchKernelGGL(k_fill_i32, dim3((2 * m + 1 + 255) / 256), dim3(256), 0, st, 2 * m + 1, flags, 0);
-            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, 1, fail, 0);
-            const size_t sh = sizeof(double2) * (((size_t)(m + kTriDistG - 1) / kTriDistG + 1) * (size_t)m);
-            hipLaunchKernelGGL(k_chol_dist, dim3(kTriDistG), dim3(kTriDistThreads), sh, st, m, gram, hs, L, X, flags,
-                               fail, status);
-            return;
-        }
-    }
+    if (flags && m >= kTriDistMin && m <= kTriDistMax &&
+        launch_chol_dist<kTriDistG, kTriDistThreads, kTriDistMax>(st, m, gram, hs, L, X, fail, status, flags))
+        return;
+    if (flags && m > kTriDistMax && m <= kTriDistMax2 &&
+        launch_chol_dist<kTriDistG2, kTriDistThreads2, kTriDistMax2>(st, m, gram, hs, L, X, fail, status, flags))
+        return;
     constexpr int W = 16;
     const size_t sh = sizeof(double2) * (size_t)m;
     const dim3 tb(64 * W);
@@ -1209,7 +1229,7 @@ struct DenseScratch {
     int32_t *fail;
     double *Z;
     // exchange buffers of the multi-work-group tridiagonalisation:
-    // v (2 x (m + 1)), partial y (2 x kTriDistG x m), flags (2 m + 1 int32)
+    // v (2 x (m + 1)), partial y (2 x G x m, G up to kTriDistG2), flags (2 m + 1 int32)
     double2 *vbuf, *ypart;
     int32_t *flags;
 };
@@ -1229,32 +1249,40 @@ static DenseScratch dense_scratch(const Workspace &w, int m)
     off += off & 1;  // 16-byte alignment of the complex buffers
     s.vbuf = reinterpret_cast<double2 *>(p + off);
     s.ypart = s.vbuf + 2 * ((size_t)m + 1);
-    s.flags = reinterpret_cast<int32_t *>(s.ypart + 2 * (size_t)kTriDistG * m);
+    s.flags = reinterpret_cast<int32_t *>(s.ypart + 2 * (size_t)kTriDistG2 * m);
     return s;
 }
 
 size_t dense_real_elems(int mmax)
 {
     const size_t m = mmax;
-    return 5 * m + 2 + m * m + 1 + 2 * (2 * (m + 1) + 2 * (size_t)kTriDistG * m) + (2 * m + 2) / 2 + 1;
+    return 5 * m + 2 + m * m + 1 + 2 * (2 * (m + 1) + 2 * (size_t)kTriDistG2 * m) + (2 * m + 2) / 2 + 1;
 }
 
-// The distributed tridiagonalisation (ordinary launch of kTriDistG
-// work-groups); false when the device cannot hold them (the caller then
+// The distributed tridiagonalisation (ordinary launch of G work-groups),
+// one size class; false when the device cannot hold them (the caller then
 // uses a one-work-group variant).
-static bool launch_tridiag_dist(hipStream_t st, int m, double2 *Hh, const DenseScratch &s, int32_t *status)
+template <int G, int NT, int MMAX>
+static bool launch_tridiag_dist_g(hipStream_t st, int m, double2 *Hh, const DenseScratch &s, int32_t *status)
 {
-    if (m < kTriDistMinTridiag || m > kTriDistMax) return false;
-    static const bool ok = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag_dist),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)tridiag_dist_lds_bytes(kTriDistMax)) == hipSuccess &&
-                           dist_grid_fits(reinterpret_cast<const void *>(k_tridiag_dist),
-                                          tridiag_dist_lds_bytes(kTriDistMax));
+    const void *k = reinterpret_cast<const void *>(k_tridiag_dist<G, NT>);
+    static const bool ok = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)tridiag_dist_lds_bytes<G>(MMAX)) == hipSuccess &&
+                           dist_grid_fits(k, G, NT, tridiag_dist_lds_bytes<G>(MMAX));
     if (!ok) return false;
     hipLaunchKernelGGL(k_fill_i32, dim3((2 * m + 1 + 255) / 256), dim3(256), 0, st, 2 * m + 1, s.flags, 0);
-    hipLaunchKernelGGL(k_tridiag_dist, dim3(kTriDistG), dim3(kTriDistThreads), tridiag_dist_lds_bytes(m), st, m, Hh,
-                       s.d, s.e, s.tau, s.vbuf, s.ypart, s.flags, status);
+    hipLaunchKernelGGL((k_tridiag_dist<G, NT>), dim3(G), dim3(NT), tridiag_dist_lds_bytes<G>(m), st, m, Hh, s.d,
+                       s.e, s.tau, s.vbuf, s.ypart, s.flags, status);
     return true;
+}
+
+static bool launch_tridiag_dist(hipStream_t st, int m, double2 *Hh, const DenseScratch &s, int32_t *status)
+{
+    if (m >= kTriDistMinTridiag && m <= kTriDistMax)
+        return launch_tridiag_dist_g<kTriDistG, kTriDistThreads, kTriDistMax>(st, m, Hh, s, status);
+    if (m > kTriDistMax && m <= kTriDistMax2)
+        return launch_tridiag_dist_g<kTriDistG2, kTriDistThreads2, kTriDistMax2>(st, m, Hh, s, status);
+    return false;
 }
 
 static hipError_t eig_pipeline(hipStream_t st, int m, double2 *Hh, const DenseScratch &s, double *eps_out,

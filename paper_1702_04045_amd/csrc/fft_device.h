@@ -590,6 +590,78 @@ __device__ __forceinline__ void xlane96_forward(C2 (&v)[12], int t, const C2 *__
     else Dft<12, -1>::run(v);
 }
 
+// The same schedule for any N = 8 E with E = 4 J (160 points: E = 20, a
+// 20-point DFT in registers).  Register s = j + J d + 2 J e (j < J, d, e <
+// 2); the stages pair registers (i, i + 2 J) on thread bits 2 and 0 and
+// (j + 2 J c, j + J + 2 J c) on bit 1, and after the three stages register s
+// of thread t holds X[k] with
+// k = (j + J t1 + 2 J t2) + E (4 e + 2 d + t0) (xlane_index_e); for E = 12
+// these are the pairs and the order of the 96-point functions above.
+template <int E> __host__ __device__ constexpr int xlane_index_e(int t, int s)
+{
+    constexpr int J = E / 4;
+    return (s % J + J * (t >> 1 & 1) + 2 * J * (t >> 2 & 1)) + E * (4 * (s / (2 * J)) + 2 * (s / J % 2) + (t & 1));
+}
+template <int B, int E> __device__ __forceinline__ constexpr int xpair_lo_e(int i)
+{
+    constexpr int J = E / 4;
+    return B == 1 ? (i % J) + 2 * J * (i / J) : i;
+}
+template <int B, int E> __device__ __forceinline__ constexpr int xpair_hi_e(int i)
+{
+    constexpr int J = E / 4;
+    return B == 1 ? (i % J) + J + 2 * J * (i / J) : i + 2 * J;
+}
+template <int B, int E, class C2> __device__ __forceinline__ void xstage_inv_e(C2 (&v)[E], C2 w)
+{
+#pragma unroll
+    for (int i = 0; i < E / 2; ++i) {
+        C2 &a = v[xpair_lo_e<B, E>(i)], &b = v[xpair_hi_e<B, E>(i)];
+        xswap<B>(a, b);
+        const C2 u = a, d = csub(a, b);
+        a = cadd(u, b);
+        b = B == 0 ? d : cmul(d, w);
+    }
+}
+template <int B, int E, class C2> __device__ __forceinline__ void xstage_fwd_e(C2 (&v)[E], C2 wc)
+{
+#pragma unroll
+    for (int i = 0; i < E / 2; ++i) {
+        C2 &a = v[xpair_lo_e<B, E>(i)], &b = v[xpair_hi_e<B, E>(i)];
+        const C2 c = B == 0 ? b : cmul(b, wc);
+        const C2 u = a;
+        a = cadd(u, c);
+        b = csub(u, c);
+        xswap<B>(a, b);
+    }
+}
+// tw[m] = exp(-2 pi i m / N).  Inverse: v[m] = x[t + 8 m] on entry,
+// v[s] = X[xlane_index_e<N / 8>(t, s)] (sign +1, unnormalised) on exit.
+template <int N, class C2>
+__device__ __forceinline__ void xlane_inverse_n(C2 (&v)[N / 8], int t, const C2 *__restrict__ tw)
+{
+    constexpr int E = N / 8;
+    static_assert(E % 4 == 0, "N = 8 E with E a multiple of 4");
+    Dft<E, +1>::run(v);
+#pragma unroll
+    for (int k = 1; k < E; ++k) v[k] = cmul(v[k], cconj(tw[t * k]));
+    xstage_inv_e<2, E>(v, cconj(tw[(N / 8) * (t & 3)]));
+    xstage_inv_e<1, E>(v, cconj(tw[(N / 4) * (t & 1)]));
+    xstage_inv_e<0, E>(v, cmk<C2>(1.0, 0.0));
+}
+// Forward (sign -1) from the layout xlane_inverse_n leaves: v[m] = y[t + 8 m] on exit.
+template <int N, class C2>
+__device__ __forceinline__ void xlane_forward_n(C2 (&v)[N / 8], int t, const C2 *__restrict__ tw)
+{
+    constexpr int E = N / 8;
+    xstage_fwd_e<0, E>(v, cmk<C2>(1.0, 0.0));
+    xstage_fwd_e<1, E>(v, tw[(N / 4) * (t & 1)]);
+    xstage_fwd_e<2, E>(v, tw[(N / 8) * (t & 3)]);
+#pragma unroll
+    for (int k = 1; k < E; ++k) v[k] = cmul(v[k], tw[t * k]);
+    Dft<E, -1>::run(v);
+}
+
 // Line schedule of the z-plane kernel (defaults to FftCfg).  For 96 points
 // 8 threads per line (12 work-group waves) with passes 4 x 6 x 4 measured
 // fastest among 4 x 24 and 8 x 12 splits of the lines.

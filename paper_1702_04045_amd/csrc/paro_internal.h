@@ -114,7 +114,7 @@ hipError_t launch_local_apply(const Plan &pl, const Workspace &w, int nb, const 
 // rho (C order [i1][i2][i3]) = sum_b w_b |psi_b(r)|^2 on the FFT grid, weights
 // null = 1; sticks: min(64, nb) x N3 x nst, part: ceil(min(64, nb) / 8) grids
 hipError_t launch_density(const Plan &pl, double2 *sticks, double *part, int nb, const double2 *psi, int64_t ld,
-                          const double *weights, double *rho);
+                          const double *weights, double *rho, bool accumulate = false);
 // gemm.hip
 hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const double2 *A, int64_t lda, const double2 *B,
                    int64_t ldb, double2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale,
@@ -159,6 +159,19 @@ hipError_t launch_residuals(const Plan &pl, const Workspace &w, int nb, const do
 hipError_t launch_normalize_bands(const Plan &pl, const Workspace &w, int nb, double2 *e, int64_t lde);
 hipError_t launch_copy_bands(hipStream_t s, int nb, int64_t ng, const double2 *src, int64_t lds, double2 *dst,
                              int64_t ldd);
+// solver.hip
+// out_b = (H - shift_b) x_b (shift null: H), local and nonlocal parts
+hipError_t apply_full(const Plan &pl, const Workspace &w, int nb, const double2 *x, int64_t ld, double2 *out,
+                      const double *shift);
+// n_cg PCG steps of the source problems (mode 0: Algorithm 1, from u = psi;
+// 1: the correction equation of Algorithm 2; 2: the projected one of Algorithm 3)
+hipError_t source_solve(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
+                        int64_t ld, const double *eps, const double *shift, int ncg, double2 *u, int64_t ldu,
+                        int32_t *band_flags, int mode = 0);
+// Rayleigh-Ritz on span{U} with W = H U (m vectors, ld); the eigenvector
+// coefficients C (m x n_keep, column-major) are left in w.dense[4]
+hipError_t rayleigh_ritz(const Plan &pl, const Workspace &w, int m, int nkeep, const double2 *U, const double2 *W,
+                         int64_t ld, double *eps, double2 *psi, double2 *hpsi, int64_t ldo);
 // dense.hip
 hipError_t launch_rr_dense(const Plan &pl, const Workspace &w, int m, int n_keep, double *eps_out, double2 *C);
 hipError_t launch_heev(hipStream_t st, const Workspace &w, int m, const double2 *A, double *wout, double2 *V);

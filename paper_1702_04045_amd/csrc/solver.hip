@@ -9,8 +9,8 @@
 
 namespace paro {
 
-static hipError_t apply_full(const Plan &pl, const Workspace &w, int nb, const double2 *x, int64_t ld, double2 *out,
-                             const double *shift)
+hipError_t apply_full(const Plan &pl, const Workspace &w, int nb, const double2 *x, int64_t ld, double2 *out,
+                      const double *shift)
 {
     hipError_t e = launch_local_apply(pl, w, nb, x, ld, out, shift, nullptr, nullptr, false, nullptr, nullptr);
     if (e != hipSuccess || pl.nproj == 0) return e;
@@ -25,9 +25,9 @@ static hipError_t apply_full(const Plan &pl, const Workspace &w, int nb, const d
 // correction equation of Algorithm 2 (from e = 0); 2: the projected
 // correction equation of Algorithm 3 (from e = 0 in the complement of psi;
 // r0, every z and every (H - sigma) p projected).
-static hipError_t source_solve(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
-                               int64_t ld, const double *eps, const double *shift, int ncg, double2 *u, int64_t ldu,
-                               int32_t *band_flags, int mode = 0)
+hipError_t source_solve(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
+                        int64_t ld, const double *eps, const double *shift, int ncg, double2 *u, int64_t ldu,
+                        int32_t *band_flags, int mode)
 {
     const double2 *proj = mode == 2 ? psi : nullptr;
     hipError_t e = launch_pcg_init(pl, w, nb, psi, hpsi, ld, eps, u, ldu, band_flags, mode >= 1, proj);
@@ -93,8 +93,8 @@ static hipError_t source_solve_mixed(const Plan &pl, const Workspace &w, int nb,
     return e;
 }
 
-static hipError_t rayleigh_ritz(const Plan &pl, const Workspace &w, int m, int nkeep, const double2 *U,
-                                const double2 *W, int64_t ld, double *eps, double2 *psi, double2 *hpsi, int64_t ldo)
+hipError_t rayleigh_ritz(const Plan &pl, const Workspace &w, int m, int nkeep, const double2 *U, const double2 *W,
+                         int64_t ld, double *eps, double2 *psi, double2 *hpsi, int64_t ldo)
 {
     hipError_t e = gemm_hn(pl.stream, m, m, pl.ng, U, ld, U, ld, w.gram, m, w.part, w.part_elems, nullptr, nullptr);
     if (e == hipSuccess)

@@ -17,6 +17,12 @@ expectation of dH/d(parameter) (Hellmann-Feynman):
 The error of these gradients is first order in the eigenvector error, i.e.
 of the order of the residual tolerance over the gap to the next band.
 
+truncated_band_energy differentiates instead the map of a fixed number K of
+ParO outer iterations from a fixed trial block, by reverse mode through
+those iterations (paro_truncated_gradient): its gradient is exact for the
+truncated map at any K, and tends to the Hellmann-Feynman one as the
+iterations converge.
+
 Every numerical step runs in libparo's kernels; this module marshals
 arguments and wires the results into torch.autograd.
 """
@@ -137,3 +143,71 @@ def potential_gradient(problem: BandEnergyProblem, psi: torch.Tensor, plan: Plan
     """d E / d vloc for a converged block psi of plan: rho / (N1 N2 N3) on the device."""
     rho = plan.density(psi[: problem.n_occ], problem.weights)
     return rho / float(np.prod(plan.grid))
+
+
+class TruncatedProblem:
+    """The band energy after a fixed number of ParO outer iterations (Algorithm 1,
+    fixed shift) from a fixed trial block: E(V, R) = sum_b w_b eps_b^K with
+    (eps^0, psi^0) the Rayleigh-Ritz pairs of the trial block and K outer
+    iterations of n_cg PCG steps each.  The trial block, the shift and the
+    KB energies are constants; the local potential on the grid and the
+    projector centres are the variables."""
+
+    def __init__(self, cell, ecut, projectors, trial, n_outer, n_cg, sigma, weights=None, device="cuda:0"):
+        self.cell = np.asarray(cell, np.float64)
+        self.ecut = float(ecut)
+        self.projectors = list(projectors)
+        self.device = torch.device(device)
+        self.trial = torch.as_tensor(np.ascontiguousarray(trial), dtype=torch.complex128).to(self.device)
+        self.n_outer, self.n_cg, self.sigma = int(n_outer), int(n_cg), float(sigma)
+        nb = self.trial.shape[0]
+        w = np.ones(nb) if weights is None else np.asarray(weights, np.float64)
+        assert w.shape == (nb,)
+        self.weights = torch.as_tensor(w, dtype=torch.float64, device=self.device)
+
+    def plan(self, vloc, centers=None):
+        v = np.ascontiguousarray(vloc.detach().to("cpu", torch.float64).numpy())
+        projs = [dict(p) for p in self.projectors]
+        if centers is not None:
+            c = centers.detach().to("cpu", torch.float64).numpy().reshape(len(projs), 3)
+            for p, r in zip(projs, c):
+                p["center"] = [float(x) for x in r]
+        return Plan(self.cell, self.ecut, v, projs, device=self.device)
+
+    def energy(self, vloc, centers=None):
+        """E alone, through paro_iterate (the forward map, for finite differences)."""
+        pl = self.plan(vloc, centers)
+        out = pl.iterate(self.trial.clone(), self.n_outer, self.n_cg, self.sigma, stats=False)
+        return float((self.weights * out["eps"]).sum().item())
+
+
+class _TruncatedBandEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, vloc, centers, problem):
+        pl = problem.plan(vloc, centers)
+        e, dv, dr = pl.truncated_gradient(problem.trial, problem.n_outer, problem.n_cg, problem.sigma,
+                                          problem.weights)
+        ctx.save_for_backward(dv, dr)
+        ctx.devices = (vloc.device, centers.device)
+        return torch.tensor(e, dtype=torch.float64, device=vloc.device)
+
+    @staticmethod
+    def backward(ctx, grad):
+        dv, dr = ctx.saved_tensors
+        g = grad.to(dv.device)
+        gv = (dv * g).to(ctx.devices[0]) if ctx.needs_input_grad[0] else None
+        gr = (dr * g).to(ctx.devices[1]) if ctx.needs_input_grad[1] else None
+        return gv, gr, None
+
+
+def truncated_band_energy(vloc: torch.Tensor, problem: TruncatedProblem, centers: torch.Tensor = None) -> torch.Tensor:
+    """sum_b w_b eps_b after problem.n_outer truncated ParO outer iterations for the local
+    potential vloc (N1 x N2 x N3, float64, C order) and projector centres (n_proj x 3, bohr;
+    default the problem's).  Differentiable with respect to both by the device reverse-mode
+    adjoint of the truncated iterations (paro_truncated_gradient)."""
+    assert vloc.dtype == torch.float64 and vloc.dim() == 3
+    n = len(problem.projectors)
+    if centers is None:
+        centers = torch.tensor([list(p["center"]) for p in problem.projectors], dtype=torch.float64).reshape(n, 3)
+    assert centers.shape == (n, 3)
+    return _TruncatedBandEnergy.apply(vloc, centers, problem)

@@ -336,6 +336,31 @@ class Plan:
         torch.cuda.current_stream(self.device).wait_stream(s)
         return g
 
+    def truncated_gradient(self, trial, n_outer, n_cg, sigma, weights=None):
+        """Band energy E = sum_b w_b eps_b after the initial Rayleigh-Ritz of the trial block and
+        n_outer fixed-shift ParO outer iterations (as iterate() computes them), and its derivatives
+        dE/dvloc (grid-shaped) and dE/dR (n_proj x 3) through the truncated iterations.
+        Returns (E, dvloc, dR)."""
+        torch = _torch()
+        self._check_block(trial)
+        nb = trial.shape[0]
+        w = torch.ones(nb, dtype=torch.float64, device=self.device) if weights is None else \
+            torch.as_tensor(weights, dtype=torch.float64, device=self.device).contiguous()
+        assert w.shape == (nb,)
+        e = torch.empty(1, dtype=torch.float64, device=self.device)
+        dv = torch.empty(self.grid, dtype=torch.float64, device=self.device)
+        dr = torch.empty((max(self.n_proj, 1), 3), dtype=torch.float64, device=self.device)
+        n = C.c_size_t()
+        L.check(self.lib.paro_truncated_gradient_workspace_bytes(self.h, nb, int(n_outer), int(n_cg), C.byref(n)),
+                "paro_truncated_gradient_workspace_bytes")
+        raw = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._sync_stream()
+        L.check(self.lib.paro_truncated_gradient(self.h, nb, _ptr(trial), trial.stride(0), float(sigma), int(n_outer),
+                                                 int(n_cg), _ptr(w), _ptr(e), _ptr(dv), _ptr(dr),
+                                                 C.c_void_p(raw.data_ptr() + off), n.value), "paro_truncated_gradient")
+        return float(e.item()), dv, dr[: self.n_proj]
+
     def status(self):
         """Read and clear the sticky device status bits (synchronises)."""
         f = C.c_int32()

@@ -11,66 +11,114 @@ references are numpy's FFTs."""
 import numpy as np
 import pytest
 
-N, T, E = 96, 8, 12
-PAIRS = {2: [(j, j + 6) for j in range(6)],
-         1: [(j + 6 * c, j + 3 + 6 * c) for c in range(2) for j in range(3)],
-         0: [(j, j + 6) for j in range(6)]}
+T = 8
 
 
-def w(sign, m):
-    return np.exp(sign * 2j * np.pi * m / N)
+class Sched:
+    """The schedule for N = 8 E points (E = 4 J registers: s = j + J d + 2 J e)."""
+
+    def __init__(self, N):
+        self.N, self.E = N, N // T
+        J = self.J = self.E // 4
+        self.pairs = {2: [(j, j + 2 * J) for j in range(2 * J)],
+                      1: [(j + 2 * J * c, j + J + 2 * J * c) for c in range(2) for j in range(J)],
+                      0: [(j, j + 2 * J) for j in range(2 * J)]}
+
+    def w(self, sign, m):
+        return np.exp(sign * 2j * np.pi * m / self.N)
+
+    def stage_twiddle_exponent(self, b, t):
+        return self.N // 8 * (t & 3) if b == 2 else (self.N // 4 * (t & 1) if b == 1 else 0)
+
+    def xlane_index(self, t, s):
+        J, E = self.J, self.E
+        return (s % J + J * (t >> 1 & 1) + 2 * J * (t >> 2 & 1)) + E * (4 * (s // (2 * J)) + 2 * (s // J % 2) + (t & 1))
+
+    def swap(self, R, b):
+        """The lower lane (thread bit b clear) receives the upper lane's register s
+        in s2; the upper lane receives the lower lane's s2 in s."""
+        R = R.copy()
+        for t in range(T):
+            if t >> b & 1:
+                continue
+            u = t | (1 << b)
+            for s, s2 in self.pairs[b]:
+                R[t, s2], R[u, s] = R[u, s], R[t, s2]
+        return R
+
+    def inverse(self, x):
+        E = self.E
+        R = np.array([[x[t + T * m] for m in range(E)] for t in range(T)], dtype=complex)
+        R = np.fft.ifft(R, axis=1) * E  # E-point DFT with sign +1
+        R = R * self.w(+1, np.outer(np.arange(T), np.arange(E)))
+        for b in (2, 1, 0):
+            R = self.swap(R, b)
+            for t in range(T):
+                tw = self.w(+1, self.stage_twiddle_exponent(b, t))
+                for s, s2 in self.pairs[b]:
+                    u, v = R[t, s], R[t, s2]
+                    R[t, s], R[t, s2] = u + v, (u - v) * tw
+        return R
+
+    def forward(self, R):
+        E = self.E
+        R = R.copy()
+        for b in (0, 1, 2):
+            for t in range(T):
+                twc = self.w(-1, self.stage_twiddle_exponent(b, t))
+                for s, s2 in self.pairs[b]:
+                    a, c = R[t, s], R[t, s2] * twc
+                    R[t, s], R[t, s2] = a + c, a - c
+            R = self.swap(R, b)
+        R = R * self.w(-1, np.outer(np.arange(T), np.arange(E)))
+        R = np.fft.fft(R, axis=1)  # E-point DFT with sign -1
+        out = np.empty(self.N, complex)
+        for t in range(T):
+            out[t + T * np.arange(E)] = R[t]
+        return out
 
 
-def stage_twiddle_exponent(b, t):
-    return 12 * (t & 3) if b == 2 else (24 * (t & 1) if b == 1 else 0)
+S96, S160 = Sched(96), Sched(160)
+N, E = 96, 12
 
 
 def xlane_index(t, s):
-    return (s % 3 + 3 * (t >> 1 & 1) + 6 * (t >> 2 & 1)) + 12 * (4 * (s // 6) + 2 * (s // 3 % 2) + (t & 1))
-
-
-def swap(R, b):
-    """The lower lane (thread bit b clear) receives the upper lane's register s
-    in s2; the upper lane receives the lower lane's s2 in s."""
-    R = R.copy()
-    for t in range(T):
-        if t >> b & 1:
-            continue
-        u = t | (1 << b)
-        for s, s2 in PAIRS[b]:
-            R[t, s2], R[u, s] = R[u, s], R[t, s2]
-    return R
+    return S96.xlane_index(t, s)
 
 
 def inverse(x):
-    R = np.array([[x[t + T * m] for m in range(E)] for t in range(T)], dtype=complex)
-    R = np.fft.ifft(R, axis=1) * E  # 12-point DFT with sign +1
-    R = R * w(+1, np.outer(np.arange(T), np.arange(E)))
-    for b in (2, 1, 0):
-        R = swap(R, b)
-        for t in range(T):
-            tw = w(+1, stage_twiddle_exponent(b, t))
-            for s, s2 in PAIRS[b]:
-                u, v = R[t, s], R[t, s2]
-                R[t, s], R[t, s2] = u + v, (u - v) * tw
-    return R
+    return S96.inverse(x)
 
 
 def forward(R):
-    R = R.copy()
-    for b in (0, 1, 2):
+    return S96.forward(R)
+
+
+@pytest.mark.parametrize("n", [96, 160])
+def test_register_order_is_a_bijection_both_lengths(n):
+    S = Sched(n)
+    assert sorted(S.xlane_index(t, s) for t in range(T) for s in range(S.E)) == list(range(n))
+    if n == 96:  # the closed form the 96-point kernels use
         for t in range(T):
-            twc = w(-1, stage_twiddle_exponent(b, t))
-            for s, s2 in PAIRS[b]:
-                a, c = R[t, s], R[t, s2] * twc
-                R[t, s], R[t, s2] = a + c, a - c
-        R = swap(R, b)
-    R = R * w(-1, np.outer(np.arange(T), np.arange(E)))
-    R = np.fft.fft(R, axis=1)  # 12-point DFT with sign -1
-    out = np.empty(N, complex)
-    for t in range(T):
-        out[t + T * np.arange(E)] = R[t]
-    return out
+            for s in range(S.E):
+                assert S.xlane_index(t, s) == (s % 3 + 3 * (t >> 1 & 1) + 6 * (t >> 2 & 1)) + 12 * (
+                    4 * (s // 6) + 2 * (s // 3 % 2) + (t & 1))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_160_point_schedule_inverse_and_convolution_step(seed):
+    """The same four-step schedule with a 20-point DFT in registers (160 = 20 x 8)."""
+    S = S160
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(160) + 1j * rng.standard_normal(160)
+    X = np.fft.ifft(x) * 160
+    R = S.inverse(x)
+    assert max(abs(R[t, s] - X[S.xlane_index(t, s)]) for t in range(T) for s in range(S.E)) < 1e-12 * np.abs(X).max()
+    V = rng.standard_normal(160)
+    Vr = np.array([[V[S.xlane_index(t, s)] for s in range(S.E)] for t in range(T)])
+    y = S.forward(R * Vr)
+    ref = np.fft.fft(V * X)
+    assert np.abs(y - ref).max() < 1e-11 * np.abs(ref).max()
 
 
 def test_register_order_is_a_bijection():
