@@ -336,6 +336,33 @@ def at_scale(args, P, torch, steps=3, tta=False, tta_seconds=600.0):
     return out
 
 
+def adjoint_leg(args, P, torch, K=8):
+    """The gradient of the band energy after K truncated outer iterations
+    (N = 128 bands of the 34k-plane-wave cell, 20 PCG steps, fixed shift):
+    the time of paro_truncated_gradient (forward with checkpoints, backward)
+    against the forward alone (paro_iterate)."""
+    spec = synth.WORKLOADS["c1"]
+    cell = synth.make_cell(spec, args.seed)
+    v = synth.vloc_on_grid(cell["cell"], cell["grid"], cell["positions"], cell["depths"], cell["widths"])
+    pl = P.Plan(cell["cell"], cell["ecut"], v, cell["projectors"])
+    nb = spec.n_bands
+    x = torch.from_numpy(synth.trial_block(pl.ng, nb, args.seed)).cuda()
+    sig = pl.shift_lower_bound()
+    pl.truncated_gradient(x, 1, spec.n_cg, sig)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e, dv, dr = pl.truncated_gradient(x, K, spec.n_cg, sig)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pl.iterate(x.clone(), K, spec.n_cg, sig, stats=False)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    return {"workload": spec.name, "bands": nb, "outer_iterations": K, "pcg_steps": spec.n_cg,
+            "seconds_per_gradient": t_grad, "seconds_forward_only": t_fwd, "gradient_over_forward": t_grad / t_fwd,
+            "outputs": "dE/dV on the 96^3 grid, dE/dR for 128 projector centres"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,6 +374,7 @@ def main():
     ap.add_argument("--tta-seconds", type=float, default=60.0)
     ap.add_argument("--no-batch", action="store_true", help="skip the 24-cell batched run")
     ap.add_argument("--no-c3", action="store_true", help="skip the 161k-plane-wave (160^3) leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the truncated-iteration gradient timing")
     ap.add_argument("--c3-tta", action="store_true",
                     help="only run the 161k-plane-wave leg with the time to 1e-8 Ha in both precisions and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -580,6 +608,7 @@ def main():
 
     batched = None if args.no_batch else batched_cells(args, P, torch)
     scale = None if args.no_c3 else at_scale(args, P, torch)
+    adjoint = None if args.no_adjoint else adjoint_leg(args, P, torch)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -596,7 +625,7 @@ def main():
            "wall_s_timed": wall, "status_flags": status,
            "roofline": roofline, "time_to_1e-8": tta64, "mixed": mixed,
            "time_to_1e-8_mparo1_10pcg": fastest, "density": density, "batched_cells": batched,
-           "mixed_at_scale": scale, "cpu_baseline": cpu}
+           "mixed_at_scale": scale, "truncated_gradient": adjoint, "cpu_baseline": cpu}
     print(json.dumps(rec))
 
 

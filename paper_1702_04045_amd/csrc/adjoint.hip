@@ -756,7 +756,7 @@ int32_t paro_truncated_gradient(paro_plan plan, int32_t nb, const double *trial,
         set_error("paro_truncated_gradient: dR is NULL");
         return PARO_EINVAL;
     }
-    if (split_plane(pl.grid[0])) {
+    if (big_grid(pl.grid[0])) {
         set_error("paro_truncated_gradient: grids above 96 points are not supported");
         return PARO_EUNSUP;
     }

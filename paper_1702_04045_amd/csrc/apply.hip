@@ -617,133 +617,6 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
     }
 }
 
-// ---------------------------------------------------------------- split plane stage
-// Grids above 96 points: a z-plane of populated columns, ncol x N complex,
-// no longer fits LDS with room to pipeline (160 points: 67 columns, 86 KB in
-// FP32, 172 KB in FP64), so the plane stage runs as three batches of
-// independent line transforms through a compressed plane in HBM,
-// Q[band][z][y][c] (c = n1 + nmax1 the populated column, y = n2 mod N):
-//   k_col_inv   columns: sticks -> inverse along n2 -> Q (all N rows),
-//   k_row       rows: Q -> inverse along n1, x V, forward along n1 -> Q
-//               (populated columns only),
-//   k_col_fwd   columns: Q -> forward along n2 -> sticks (the column's sticks).
-// Every line is a cross-lane transform on 8 lanes (thread t holds the
-// elements t + 8 m in registers), so the kernels use no LDS but the
-// twiddle table's copy.  The eight lanes at one element index belong to
-// eight consecutive lines, i.e. eight consecutive columns c of Q (row
-// kernel: eight consecutive rows), so their stores and loads are runs of
-// eight.  Lines past the last column transform zeros on every lane (a swap
-// pairs lanes of one line) without loads or stores.
-constexpr int kSplitThreads = 256;
-// the fused LDS plane stage (k_plane_cc) instead of the three batches
-constexpr bool kFusedPlaneAbove96 = true;
-
-template <int N, class C2>
-__global__ void __launch_bounds__(kSplitThreads)
-k_col_inv(const C2 *__restrict__ sticks, int nst, int N3, const int32_t *__restrict__ cols, int ncol,
-          C2 *__restrict__ Q, const C2 *__restrict__ tw)
-{
-    static_assert(xlane_rows<N, C2>(), "cross-lane lines");
-    constexpr int T = 8, E = N / 8;
-    __shared__ C2 twl[N];
-    const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
-    for (int i = tid; i < N; i += kSplitThreads) twl[i] = tw[i];
-    __syncthreads();
-    const int c = blockIdx.x * (kSplitThreads / T) + sl, z = blockIdx.y, band = blockIdx.z;
-    const bool act = c < ncol;
-    int cst = 0, ylo = 0, cnt = 0;
-    if (act) {
-        cst = cols[3 * c];
-        ylo = cols[3 * c + 1];
-        cnt = cols[3 * c + 2];
-    }
-    const C2 *tz = sticks + ((size_t)band * N3 + z) * nst + cst;
-    C2 v[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int i = t + T * m;
-        const int k = (i > N / 2 ? i - N : i) - ylo;
-        v[m] = (act && (unsigned)k < (unsigned)cnt) ? tz[k] : cmk<C2>(0.0, 0.0);
-    }
-    xl_inverse<N>(v, opaque(t), twl);
-    C2 *q = Q + ((size_t)band * N3 + z) * N * ncol + c;
-    if (act) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) q[(size_t)xl_index<N>(t, e) * ncol] = v[e];
-    }
-}
-
-template <int N, class C2>
-__global__ void __launch_bounds__(kSplitThreads)
-k_row(C2 *__restrict__ Q, int N3, int ncol, int nmax1, const RealOf<C2> *__restrict__ vperm,
-      const C2 *__restrict__ tw)
-{
-    static_assert(xlane_rows<N, C2>(), "cross-lane lines");
-    constexpr int T = 8, E = N / 8;
-    __shared__ C2 twl[N];
-    const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
-    for (int i = tid; i < N; i += kSplitThreads) twl[i] = tw[i];
-    __syncthreads();
-    const int y = blockIdx.x * (kSplitThreads / T) + sl, z = blockIdx.y, band = blockIdx.z;
-    const bool act = y < N;
-    C2 *row = Q + (((size_t)band * N3 + z) * N + (act ? y : 0)) * ncol;
-    C2 v[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int i = t + T * m;
-        const bool pop = i <= nmax1 || i >= N - nmax1;
-        v[m] = (act && pop) ? row[i <= nmax1 ? i + nmax1 : i - N + nmax1] : cmk<C2>(0.0, 0.0);
-    }
-    xl_inverse<N>(v, opaque(t), twl);
-    // the potential in the register order of the cross-lane inverse
-    const RealOf<C2> *vp = vperm + (((size_t)z * N + (act ? y : 0)) * T + t) * E;
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vp[e]);
-    xl_forward<N>(v, opaque(t), twl);
-    if (act) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int i = t + T * m;
-            if (i <= nmax1 || i >= N - nmax1) row[i <= nmax1 ? i + nmax1 : i - N + nmax1] = v[m];
-        }
-    }
-}
-
-template <int N, class C2>
-__global__ void __launch_bounds__(kSplitThreads)
-k_col_fwd(const C2 *__restrict__ Q, int N3, int ncol, const int32_t *__restrict__ cols, C2 *__restrict__ sticks,
-          int nst, const C2 *__restrict__ tw)
-{
-    static_assert(xlane_rows<N, C2>(), "cross-lane lines");
-    constexpr int T = 8, E = N / 8;
-    __shared__ C2 twl[N];
-    const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
-    for (int i = tid; i < N; i += kSplitThreads) twl[i] = tw[i];
-    __syncthreads();
-    const int c = blockIdx.x * (kSplitThreads / T) + sl, z = blockIdx.y, band = blockIdx.z;
-    const bool act = c < ncol;
-    int cst = 0, ylo = 0, cnt = 0;
-    if (act) {
-        cst = cols[3 * c];
-        ylo = cols[3 * c + 1];
-        cnt = cols[3 * c + 2];
-    }
-    const C2 *q = Q + ((size_t)band * N3 + z) * N * ncol + (act ? c : 0);
-    C2 v[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = act ? q[(size_t)xl_index<N>(t, e) * ncol] : cmk<C2>(0.0, 0.0);
-    xl_forward<N>(v, opaque(t), twl);
-    C2 *tz = sticks + ((size_t)band * N3 + z) * nst + cst;
-    if (act) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-            const int i = t + T * m;
-            const int k = (i > N / 2 ? i - N : i) - ylo;
-            if ((unsigned)k < (unsigned)cnt) tz[k] = v[m];
-        }
-    }
-}
-
 // ---------------------------------------------------------------- fused plane stage above 96 points
 // One z-plane of up to kCcBands bands per work-group, with the plane held
 // in LDS in compressed-column form: plane[c][y] for the populated columns
@@ -919,24 +792,23 @@ hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const C2 *src, 
     return hipGetLastError();
 }
 
-// The local part at grids above 96 points: sticks, then the three line
-// batches of the split plane stage through Q, then the forward sticks.
+// The local part at grids above 96 points: sticks, the plane stage with the
+// compressed plane in LDS (k_plane_cc, writing the forward sticks to a
+// second stick buffer), the forward sticks.
 template <int N, class C2>
-hipError_t run_local_split(const Plan &pl, const Workspace &w, int nb, const C2 *src, int64_t ld, C2 *out,
-                           const double *shift, C2 *pbuf, const double *beta, bool first, double *dot_part,
-                           int *nparts_out)
+hipError_t run_local_big(const Plan &pl, const Workspace &w, int nb, const C2 *src, int64_t ld, C2 *out,
+                         const double *shift, C2 *pbuf, const double *beta, bool first, double *dot_part,
+                         int *nparts_out)
 {
     constexpr int NT = stick_threads<N, C2>();
     constexpr int S = NT / FftCfg<N>::T;
-    constexpr int NTS = kSplitThreads, SL = NTS / 8;
-    static_assert(N % SL == 0, "rows split evenly into work-groups");
     const int N3 = pl.grid[2];
     const int ntiles = (pl.nst + S - 1) / S;
     if (nparts_out) *nparts_out = ntiles;
+    if (pl.ncol > kCcMaxCols) return hipErrorInvalidValue;
     const double scale = 1.0 / ((double)pl.grid[0] * pl.grid[1] * pl.grid[2]);
     C2 *sticks = reinterpret_cast<C2 *>(w.sticks);
-    C2 *Q = reinterpret_cast<C2 *>(w.qplane);
-    const int ncol = pl.ncol;
+    C2 *sticks2 = reinterpret_cast<C2 *>(w.sticks2);
     for (int c0 = 0; c0 < nb; c0 += kMaxBandsPerChunk) {
         const int cb = min(kMaxBandsPerChunk, nb - c0);
         prof_mark(PARO_K_STICK_INV, pl.stream, true);
@@ -945,24 +817,13 @@ hipError_t run_local_split(const Plan &pl, const Workspace &w, int nb, const C2 
                            pl.st_start, pl.pt_sz, PlanTabs<C2>::tw(pl, 2));
         prof_mark(PARO_K_STICK_INV, pl.stream, false);
         prof_mark(PARO_K_PLANE, pl.stream, true);
-        const bool fused = kFusedPlaneAbove96 && ncol <= kCcMaxCols;
-        if (fused) {
-            // out of place: the forward sticks go to Q, which is at least as large
-            hipLaunchKernelGGL((k_plane_cc<N, C2>), dim3(N3, (cb + kCcBands - 1) / kCcBands), dim3(kCcThreads), 0,
-                               pl.stream, sticks, Q, pl.nst, N3, cb, pl.cols, ncol, pl.nmax[0], PlanTabs<C2>::v(pl),
-                               PlanTabs<C2>::tw(pl, 0));
-        } else {
-            hipLaunchKernelGGL((k_col_inv<N, C2>), dim3((ncol + SL - 1) / SL, N3, cb), dim3(NTS), 0, pl.stream,
-                               sticks, pl.nst, N3, pl.cols, ncol, Q, PlanTabs<C2>::tw(pl, 1));
-            hipLaunchKernelGGL((k_row<N, C2>), dim3(N / SL, N3, cb), dim3(NTS), 0, pl.stream, Q, N3, ncol,
-                               pl.nmax[0], PlanTabs<C2>::v(pl), PlanTabs<C2>::tw(pl, 0));
-            hipLaunchKernelGGL((k_col_fwd<N, C2>), dim3((ncol + SL - 1) / SL, N3, cb), dim3(NTS), 0, pl.stream, Q,
-                               N3, ncol, pl.cols, sticks, pl.nst, PlanTabs<C2>::tw(pl, 1));
-        }
+        hipLaunchKernelGGL((k_plane_cc<N, C2>), dim3(N3, (cb + kCcBands - 1) / kCcBands), dim3(kCcThreads), 0,
+                           pl.stream, sticks, sticks2, pl.nst, N3, cb, pl.cols, pl.ncol, pl.nmax[0],
+                           PlanTabs<C2>::v(pl), PlanTabs<C2>::tw(pl, 0));
         prof_mark(PARO_K_PLANE, pl.stream, false);
         const C2 *x = pbuf ? pbuf : src;
         prof_mark(PARO_K_STICK_FWD, pl.stream, true);
-        hipLaunchKernelGGL((k_stick_fwd<N, C2>), dim3(ntiles, cb), dim3(NT), 0, pl.stream, fused ? Q : sticks, pl.nst,
+        hipLaunchKernelGGL((k_stick_fwd<N, C2>), dim3(ntiles, cb), dim3(NT), 0, pl.stream, sticks2, pl.nst,
                            pl.st_start, pl.pt_sz, PlanTabs<C2>::tw(pl, 2), x + c0 * ld, ld, out + c0 * ld, pl.kin,
                            shift ? shift + c0 : nullptr, scale,
                            dot_part ? dot_part + (size_t)c0 * kMaxParts : nullptr, kMaxParts);
@@ -1007,7 +868,7 @@ hipError_t local_apply(const Plan &pl, const Workspace &w, int nb, const C2 *src
     PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
     PARO_CASE(80) PARO_CASE(96)
 #undef PARO_CASE
-    case 160: return run_local_split<160, C2>(pl, w, nb, src, ld, out, shift, pbuf, beta, first, dot_part, nparts_out);
+    case 160: return run_local_big<160, C2>(pl, w, nb, src, ld, out, shift, pbuf, beta, first, dot_part, nparts_out);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1022,7 +883,7 @@ bool fft_supported(int n)
     }
 }
 
-bool split_plane(int n) { return n > 96; }
+bool big_grid(int n) { return n > 96; }
 
 hipError_t launch_density(const Plan &pl, double2 *sticks, double *part, int nb, const double2 *psi, int64_t ld,
                           const double *weights, double *rho, bool accumulate)

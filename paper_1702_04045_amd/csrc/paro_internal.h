@@ -46,7 +46,7 @@ struct Plan {
 // Workspace carve-up for calls on up to nb bands (m <= 2 nb for Rayleigh-Ritz).
 struct Workspace {
     double2 *sticks;          // min(64, 2 nb) x N3 x nst
-    double2 *qplane;          // grids above 96 points: min(64, 2 nb) x N3 x N2 x ncol (else null)
+    double2 *sticks2;         // grids above 96 points: a second stick buffer (else null)
     double2 *r, *z, *p, *q;   // PCG vectors, nb x ldv each
     double2 *U, *W;           // 2 nb x ldv each: Rayleigh-Ritz basis and its H image
     double2 *gram;            // [S Hs], m x 2m
@@ -95,9 +95,9 @@ void prof_mark(int kernel, hipStream_t s, bool begin);
 // ---- launchers (return the hipError_t of the launches) ----
 // apply.hip
 bool fft_supported(int n);
-// whether the plane stage of an n-point cubic grid runs as split line batches
-// through a compressed plane in the workspace (n > 96)
-bool split_plane(int n);
+// grids above 96 points: the plane stage keeps only the populated columns
+// in LDS and writes the forward sticks to a second stick buffer
+bool big_grid(int n);
 // the local potential re-laid in the order the plane kernel's row threads use it
 void build_plane_potential(int n, const int32_t *grid, const double *vloc, double *out);
 void build_plane_potential(int n, const int32_t *grid, const double *vloc, float *out);

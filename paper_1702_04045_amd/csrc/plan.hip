@@ -220,7 +220,7 @@ size_t workspace_bytes(const Plan &pl, int nb)
     size_t tot = 0;
     auto add = [&](size_t bytes) { tot = align256(tot + bytes); };
     add(sizeof(double2) * cb * pl.grid[2] * pl.nst);          // sticks
-    if (split_plane(pl.grid[0])) add(sizeof(double2) * cb * pl.grid[2] * pl.grid[1] * pl.ncol);  // qplane
+    if (big_grid(pl.grid[0])) add(sizeof(double2) * cb * pl.grid[2] * pl.nst);  // sticks2
     for (int i = 0; i < 4; ++i) add(sizeof(double2) * nb * pl.ldv);  // r z p q
     add(sizeof(double2) * m * pl.ldv);                          // U
     add(sizeof(double2) * m * pl.ldv);                          // W
@@ -286,8 +286,7 @@ Workspace carve_workspace(const Plan &pl, int nb, void *ws)
         return p;
     };
     w.sticks = (double2 *)take(sizeof(double2) * cb * pl.grid[2] * pl.nst);
-    w.qplane = split_plane(pl.grid[0]) ? (double2 *)take(sizeof(double2) * cb * pl.grid[2] * pl.grid[1] * pl.ncol)
-                                       : nullptr;
+    w.sticks2 = big_grid(pl.grid[0]) ? (double2 *)take(sizeof(double2) * cb * pl.grid[2] * pl.nst) : nullptr;
     w.r = (double2 *)take(sizeof(double2) * nb * pl.ldv);
     w.z = (double2 *)take(sizeof(double2) * nb * pl.ldv);
     w.p = (double2 *)take(sizeof(double2) * nb * pl.ldv);

@@ -187,7 +187,7 @@ int32_t paro_density(paro_plan plan, int32_t nb, const double *psi, int64_t ld, 
         set_error("paro_density: ld < n_g");
         return PARO_EINVAL;
     }
-    if (split_plane(pl.grid[0])) {
+    if (big_grid(pl.grid[0])) {
         set_error("paro_density: grids above 96 points are not supported");
         return PARO_EUNSUP;
     }
