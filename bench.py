@@ -40,12 +40,14 @@ METRIC = "ParO iters/s & Hψ applies/s, plain FP64 vs batched mixed, at 1e-8 Ha 
 # counts only while the kernel sources hash to the value recorded there.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_plane_96_c1_hbm_traffic.txt")
 DENSITY_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_plane_density_96_c1_hbm_traffic.txt")
-PLANE_SOURCES = ["paper_1702_04045_amd/csrc/apply.hip", "paper_1702_04045_amd/csrc/fft_device.h",
-                 "paper_1702_04045_amd/csrc/paro_internal.h"]
+# the sources of the 96-point plane and density kernels (the traffic summaries
+# hold their SHA-256; a summary taken on other sources reads as null)
+PLANE_SOURCES = ["paper_1702_04045_amd/csrc/apply.hip", "paper_1702_04045_amd/csrc/fft_device.h"]
 COPY_BYTES = 1 << 30         # bytes read (and written) by the calibration copy
 PEAK_FP64_VALU = 78.6e12     # MI355X FP64 vector, flop/s
 PEAK_FP32_VALU = 157.3e12    # MI355X FP32 vector, flop/s
 PEAK_HBM = 8.0e12            # bytes/s
+PEAK_BF16_MFMA = 2.5e15      # MI355X dense BF16 matrix cores, flop/s
 
 
 def fft_flops(n):
@@ -278,7 +280,8 @@ def at_scale(args, P, torch, steps=3, tta=False, tta_seconds=600.0):
     out = {"workload": spec.name, "n_g": pl.ng, "grid": list(pl.grid), "bands": nb, "bands_converged": nconv,
            "projectors": pl.n_proj, "pcg_steps": ncg}
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
+    precs = (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED), ("mixed_bf16", P.PREC_MIXED_BF16))
+    for name, prec in precs:
         psi = x0.clone()
         st = pl.iterate(psi, 1, ncg, sig, initial_rr=True, stats=False, precision=prec, **kw)
         h, e = st["hpsi"], st["eps"]
@@ -290,7 +293,9 @@ def at_scale(args, P, torch, steps=3, tta=False, tta_seconds=600.0):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         out[name] = {"outer_iterations_per_s": 1000.0 / ms, "ms_per_step": ms, "status_flags": pl.status()}
-    for name, f, blk in (("fp64", pl.apply_h, x0), ("mixed", pl.apply_h_f32, x0.to(torch.complex64))):
+    x32 = x0.to(torch.complex64)
+    bf = lambda blk, out=None: pl.apply_h_f32(blk, out=out, bf16=True)  # noqa: E731
+    for name, f, blk in (("fp64", pl.apply_h, x0), ("mixed", pl.apply_h_f32, x32), ("mixed_bf16", bf, x32)):
         o = f(blk)
         torch.cuda.synchronize()
         e0, e1 = ev(), ev()
@@ -302,14 +307,17 @@ def at_scale(args, P, torch, steps=3, tta=False, tta_seconds=600.0):
         us = e0.elapsed_time(e1) / 3 * 1e3 / nb
         local, nlf, byts = hpsi_work(pl.grid[0], pl.n_sticks, 2 * pl.nmax[0] + 1, pl.ng, pl.n_proj, 64)
         peak = PEAK_FP64_VALU if name == "fp64" else PEAK_FP32_VALU
-        t_roof = max(byts / (2 if name == "mixed" else 1) / PEAK_HBM, local / peak) * 1e6 + nlf / peak * 1e6
+        # split-BF16: three BF16 matrix-core products per product
+        t_nl = 3 * nlf / PEAK_BF16_MFMA if name == "mixed_bf16" else nlf / peak
+        t_roof = max(byts / (1 if name == "fp64" else 2) / PEAK_HBM, local / peak) * 1e6 + t_nl * 1e6
         out[name]["hpsi_us_per_band_apply"] = us
         out[name]["hpsi_roofline_frac"] = t_roof / us
         out[name]["hpsi_t_roof_us"] = t_roof
-    out["mixed"]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"]
+    for name in ("mixed", "mixed_bf16"):
+        out[name]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out[name]["ms_per_step"]
     if tta:
         final = {}
-        for name, prec in (("fp64", P.PREC_FP64), ("mixed", P.PREC_MIXED)):
+        for name, prec in precs:
             psi = x0.clone()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -328,11 +336,12 @@ def at_scale(args, P, torch, steps=3, tta=False, tta_seconds=600.0):
             out[name]["time_to_1e-8"] = {"outer_iterations": its, "seconds": time.perf_counter() - t0,
                                          "eig_err_bound": bound, "reached": bool(bound <= 1e-8)}
             final[name] = row
-        de = np.abs(final["mixed"][:nconv] - final["fp64"][:nconv])
-        out["mixed_vs_fp64_eigenvalues"] = {
-            "max_abs_diff_ha": float(de.max()), "median_abs_diff_ha": float(np.median(de)),
-            "per_band_bound_ha": "Kato-Temple bound of each run <= 1e-8 (time_to_1e-8.eig_err_bound); "
-                                 "|diff| <= sum of the two bounds"}
+        for name in ("mixed", "mixed_bf16"):
+            de = np.abs(final[name][:nconv] - final["fp64"][:nconv])
+            out[name + "_vs_fp64_eigenvalues"] = {
+                "max_abs_diff_ha": float(de.max()), "median_abs_diff_ha": float(np.median(de)),
+                "per_band_bound_ha": "Kato-Temple bound of each run <= 1e-8 (time_to_1e-8.eig_err_bound); "
+                                     "|diff| <= sum of the two bounds"}
     return out
 
 
@@ -377,6 +386,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the truncated-iteration gradient timing")
     ap.add_argument("--c3-tta", action="store_true",
                     help="only run the 161k-plane-wave leg with the time to 1e-8 Ha in both precisions and exit")
+    ap.add_argument("--c3-only", action="store_true",
+                    help="only run the 161k-plane-wave leg (3 timed outer iterations per precision) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--traffic-pass", action="store_true",
@@ -396,8 +407,8 @@ def main():
     import torch
     import paper_1702_04045_amd as P
     from paper_1702_04045_amd import _lib as L
-    if args.c3_tta:
-        print(json.dumps({"at_scale": at_scale(args, P, torch, tta=True, tta_seconds=args.tta_seconds)}))
+    if args.c3_tta or args.c3_only:
+        print(json.dumps({"at_scale": at_scale(args, P, torch, tta=args.c3_tta, tta_seconds=args.tta_seconds)}))
         return
 
     dev = torch.device("cuda:0")
@@ -430,7 +441,7 @@ def main():
         """K outer iterations from the warmed-up state; HIP events around every plane-stage launch."""
         import ctypes as C
         p, h, e = (t.clone() for t in start)
-        if precision == P.PREC_MIXED and args.warmup:
+        if precision != P.PREC_FP64 and args.warmup:
             pl.iterate(p.clone(), 1, ncg, sigma_lb, hpsi=h.clone(), eps=e.clone(), initial_rr=False, stats=False,
                        precision=precision, **kw)
         torch.cuda.synchronize()
@@ -449,7 +460,7 @@ def main():
         L.check(lib.paro_profile_stop(C.byref(nl), C.byref(tot)), "paro_profile_stop")
         ms_step = e0.elapsed_time(e1) / max(args.steps, 1)
         # plane launches per step: n_cg + 1 applies in FP64, or n_cg in FP32 and one in FP64
-        n_prec = launches_per_apply * (ncg if precision == P.PREC_MIXED else ncg + 1) * args.steps
+        n_prec = launches_per_apply * (ncg if precision != P.PREC_FP64 else ncg + 1) * args.steps
         return ms_step, wall, nl.value, tot.value, n_prec
 
     def tta(precision, variant=P.VARIANT_PARO, n_cg=None):
@@ -553,6 +564,13 @@ def main():
     L.check(lib.paro_profile_stop(C.byref(nlf), C.byref(totf)), "paro_profile_stop")
     mixed["roofline"] = roofline_of(ms_m, nlf.value, totf.value, P.PREC_MIXED)
     mixed["roofline"]["share_of_step"] = (totf.value / nlf.value) * n32 / max(args.steps, 1) / ms_m
+    # the same with split-BF16 projector products in the FP32 source problems
+    ms_b, wall_b, _, _, _ = timed(P.PREC_MIXED_BF16)
+    mixed["bf16_projector_products"] = {
+        "value": 1000.0 / ms_b, "unit": "ParO outer iterations/s", "ms_per_step": ms_b, "wall_s_timed": wall_b,
+        "speedup_vs_fp64": ms_step / ms_b, "status_flags": pl.status(),
+        "dtype": "f32 source problems with bf16x3 projector products, f64 H U and RR",
+        "time_to_1e-8": tta(P.PREC_MIXED_BF16)}
 
     # density of the whole block (the Hellmann-Feynman gradient of the band
     # energy): the full call timed with events on the plan's stream, its

@@ -74,6 +74,9 @@ extern "C" {
 #define PARO_PREC_MIXED 1  /* source problems in FP32 (correction form, see
                               paro_source_solve_mixed); H U, Rayleigh-Ritz,
                               residuals and shifts in FP64 */
+#define PARO_PREC_MIXED_BF16 2  /* as PARO_PREC_MIXED, with the projector
+                              products of the FP32 applies as split-BF16
+                              products (paro_apply_h_f32_bf16) */
 
 /* solver variants of paro_iterate */
 #define PARO_VARIANT_PARO 0    /* Algorithm 1: Rayleigh-Ritz on span{u_i} (m = nb) */
@@ -135,7 +138,7 @@ typedef struct {
     double sigma_lb;         /* lower bound of the spectrum (paro_shift_lower_bound) */
     double tol_res;          /* stop once max_{b < n_conv} |H psi_b - eps_b psi_b| <= tol_res
                                 (checked on the device after each outer iteration; 0 = never) */
-    int32_t precision;       /* PARO_PREC_FP64 or PARO_PREC_MIXED */
+    int32_t precision;       /* PARO_PREC_FP64, PARO_PREC_MIXED or PARO_PREC_MIXED_BF16 */
 } paro_iter_opts;
 
 /* ---------------------------------------------------------------- ABI */
@@ -203,6 +206,17 @@ int32_t paro_apply_h(paro_plan plan, int32_t nb, const double *psi, int64_t ld,
  * block of the mixed-precision source solve; shift and ws as paro_apply_h. */
 int32_t paro_apply_h_f32(paro_plan plan, int32_t nb, const float *psi, int64_t ld,
                          const double *shift, float *hpsi, void *ws, size_t ws_bytes);
+
+/* paro_apply_h_f32 with the projector products V_NL psi = B D (B^H psi) of
+ * Section 2.2 on the BF16 matrix cores: every FP32 operand x is split into
+ * hi = bf16(x) and lo = bf16(x - hi), and a product x y is taken as
+ * hi hi + hi lo + lo hi, accumulated in FP32 (the split-K partial sums of
+ * B^H psi added in FP64).  Each product is within about 3 x 2^-16 of x y,
+ * so the nonlocal part carries a relative error of about 5e-5 (FP32
+ * operands: 6e-8); the local part is that of paro_apply_h_f32.  Arguments,
+ * layout and errors as paro_apply_h_f32. */
+int32_t paro_apply_h_f32_bf16(paro_plan plan, int32_t nb, const float *psi, int64_t ld,
+                              const double *shift, float *hpsi, void *ws, size_t ws_bytes);
 
 /* The N independent source problems of Algorithm 1, step 3, read with a
  * shift sigma_b below the spectrum:

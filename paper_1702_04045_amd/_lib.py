@@ -15,7 +15,7 @@ PARO_OK, PARO_EINVAL, PARO_EALIAS, PARO_ESIZE, PARO_EHIP, PARO_EUNSUP = 0, -1, -
 F_NEGCURV, F_CHOL, F_NAN = 1, 2, 4
 SHIFT_FIXED, SHIFT_ADAPTIVE = 0, 1
 VARIANT_PARO, VARIANT_MPARO1, VARIANT_MPARO2 = 0, 1, 2
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_MIXED_BF16 = 0, 1, 2
 K_STICK_INV, K_PLANE, K_STICK_FWD, K_GEMM_HN, K_GEMM_NN, K_PCG_UPDATE, K_DENSITY = 1, 2, 3, 4, 5, 6, 7
 
 ERRORS = {PARO_EINVAL: "EINVAL", PARO_EALIAS: "EALIAS", PARO_ESIZE: "ESIZE", PARO_EHIP: "EHIP",
@@ -68,6 +68,7 @@ SIGNATURES = {
     "paro_get_projectors": (C.c_int32, [_vp, _vp]),
     "paro_apply_h": (C.c_int32, [_vp, C.c_int32, _vp, C.c_int64, _vp, _vp, _vp, _sz]),
     "paro_apply_h_f32": (C.c_int32, [_vp, C.c_int32, _vp, C.c_int64, _vp, _vp, _vp, _sz]),
+    "paro_apply_h_f32_bf16": (C.c_int32, [_vp, C.c_int32, _vp, C.c_int64, _vp, _vp, _vp, _sz]),
     "paro_iterate_batch": (C.c_int32, [C.c_int32, C.POINTER(_vp), C.POINTER(C.c_int32), C.POINTER(_vp),
                                        C.POINTER(_vp), C.POINTER(C.c_int64), C.POINTER(_vp), C.POINTER(_vp),
                                        C.POINTER(IterOpts), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_sz),

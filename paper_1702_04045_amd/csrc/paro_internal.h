@@ -38,6 +38,11 @@ struct Plan {
     float *vplane32 = nullptr;
     float2 *tw32[3] = {nullptr, nullptr, nullptr};
     float2 *beta32 = nullptr;
+    // the projectors as BF16 hi / lo pairs for the split-BF16 products:
+    // nproj x bf_ldk (projector-major) and ng x bf_ldp (transposed), zero padded
+    uint32_t *bs_hi = nullptr, *bs_lo = nullptr, *bt_hi = nullptr, *bt_lo = nullptr;
+    int64_t bf_ldk = 0;
+    int32_t bf_ldp = 0;
     double *dkb = nullptr;        // KB energies
     int32_t *status = nullptr;    // sticky status bits
     int32_t *miller = nullptr;    // Miller indices of the sphere, ng x 3
@@ -129,6 +134,13 @@ hipError_t gemm_hn(hipStream_t s, int M, int N, int64_t K, const float2 *A, int6
 hipError_t gemm_nn(hipStream_t s, int64_t M, int N, int K, const float2 *A, int64_t lda, const float2 *B,
                    int64_t ldb, float2 *C, int64_t ldc, bool accumulate);
 hipError_t launch_to_single(hipStream_t s, int64_t n, const double2 *src, float2 *dst);
+// split-BF16 projector products (gemm_bf16.hip)
+int64_t bf16_ldk(int64_t ng);
+int bf16_ldp(int nproj);
+hipError_t launch_split_beta(const Plan &pl);
+size_t bf16_apply_scratch_bytes(const Plan &pl, int nb);
+hipError_t apply_nl_bf16(const Plan &pl, const Workspace &w, int nb, const float2 *x, int64_t ld, float2 *out,
+                         int64_t ldo, void *scratch, double *quad);
 // dd[p] = sum_b w_b |P_pb|^2, dR[3p + a] = sum_b w_b d_p 2 Re(conj(P_pb) Q_pb^a)
 // with P = beta^H psi and Q^a = (-i G_a beta)^H psi (weights null = 1)
 hipError_t launch_projector_gradient(const Plan &pl, const ProjGradWs &w, int nb, const double2 *psi, int64_t ld,

@@ -105,7 +105,7 @@ static bool good_size(int n)
 // Layout of the device plan buffer.
 struct PlanLayout {
     size_t kin, pt_sz, st_start, cols, vplane, tw[3], beta, dkb, miller, pcen, plm, pwid, status;
-    size_t vplane32, tw32[3], beta32, total;
+    size_t vplane32, tw32[3], beta32, bs_hi, bs_lo, bt_hi, bt_lo, total;
 };
 
 struct HostGeom {
@@ -142,6 +142,13 @@ static PlanLayout layout(const paro_problem &p, const HostGeom &g)
     L.vplane32 = take(sizeof(float) * nv);
     for (int d = 0; d < 3; ++d) L.tw32[d] = take(sizeof(float2) * p.grid[d]);
     L.beta32 = take(sizeof(float2) * (size_t)p.n_proj * g.ldv);
+    // BF16 hi / lo pairs of the projectors (split-BF16 products)
+    const size_t nbs = p.n_proj > 0 ? (size_t)p.n_proj * bf16_ldk(g.ng) : 0;
+    const size_t nbt = p.n_proj > 0 ? (size_t)g.ng * bf16_ldp(p.n_proj) : 0;
+    L.bs_hi = take(sizeof(uint32_t) * nbs);
+    L.bs_lo = take(sizeof(uint32_t) * nbs);
+    L.bt_hi = take(sizeof(uint32_t) * nbt);
+    L.bt_lo = take(sizeof(uint32_t) * nbt);
     L.total = off;
     return L;
 }
@@ -407,6 +414,12 @@ int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes, 
     pl.vplane32 = (float *)(base + L.vplane32);
     for (int d = 0; d < 3; ++d) pl.tw32[d] = (float2 *)(base + L.tw32[d]);
     pl.beta32 = (float2 *)(base + L.beta32);
+    pl.bf_ldk = bf16_ldk(g.ng);
+    pl.bf_ldp = bf16_ldp(pl.nproj);
+    pl.bs_hi = (uint32_t *)(base + L.bs_hi);
+    pl.bs_lo = (uint32_t *)(base + L.bs_lo);
+    pl.bt_hi = (uint32_t *)(base + L.bt_hi);
+    pl.bt_lo = (uint32_t *)(base + L.bt_lo);
     pl.status = (int32_t *)(base + L.status);
     int32_t *miller_dev = (int32_t *)(base + L.miller);
     pl.miller = miller_dev;
@@ -481,6 +494,7 @@ int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes, 
     if (e == hipSuccess) e = hipMemsetAsync(pl.status, 0, sizeof(int32_t) * 64, pl.stream);
     if (e == hipSuccess) e = launch_build_projectors(pl, miller_dev, pcen, plm, pwid);
     if (e == hipSuccess) e = launch_to_single(pl.stream, (int64_t)pl.nproj * pl.ldv, pl.beta, pl.beta32);
+    if (e == hipSuccess) e = launch_split_beta(pl);
     if (e == hipSuccess) e = hipStreamSynchronize(pl.stream);
     if (e != hipSuccess) {
         delete h;

@@ -49,17 +49,33 @@ hipError_t source_solve(const Plan &pl, const Workspace &w, int nb, const double
     return e;
 }
 
-// H x in single precision (FP32 plan tables, FP32 matrix cores).
-static hipError_t apply_full(const Plan &pl, const Workspace &w, int nb, const float2 *x, int64_t ld, float2 *out,
-                             const double *shift)
+// The nonlocal part of a single-precision apply, out += V_NL x: FP32
+// matrix-core products, or split-BF16 ones (bf16 true) with their operand
+// pairs in scratch (cap bytes).
+static hipError_t apply_nl_f32(const Plan &pl, const Workspace &w, int nb, const float2 *x, int64_t ld, float2 *out,
+                               int64_t ldo, double *quad, bool bf16, void *scratch, size_t cap)
+{
+    if (pl.nproj == 0) return hipSuccess;
+    if (bf16) {
+        if (bf16_apply_scratch_bytes(pl, nb) > cap) return hipErrorInvalidValue;
+        return apply_nl_bf16(pl, w, nb, x, ld, out, ldo, scratch, quad);
+    }
+    float2 *P = reinterpret_cast<float2 *>(w.P);
+    hipError_t e = gemm_hn(pl.stream, pl.nproj, nb, pl.ng, pl.beta32, pl.ldv, x, ld, P, pl.nproj, w.part,
+                           w.part_elems, pl.dkb, quad);
+    if (e != hipSuccess) return e;
+    return gemm_nn(pl.stream, pl.ng, nb, pl.nproj, pl.beta32, pl.ldv, P, pl.nproj, out, ldo, true);
+}
+
+// H x in single precision (FP32 plan tables; FP32 or split-BF16 matrix
+// cores).  The split-BF16 operand pairs go to the W block of the
+// workspace, which the single-precision apply does not use.
+static hipError_t apply_full(const Plan &pl, const Workspace &w, int nb, int nbw, const float2 *x, int64_t ld,
+                             float2 *out, const double *shift, bool bf16)
 {
     hipError_t e = launch_local_apply(pl, w, nb, x, ld, out, shift, nullptr, nullptr, false, nullptr, nullptr);
-    if (e != hipSuccess || pl.nproj == 0) return e;
-    float2 *P = reinterpret_cast<float2 *>(w.P);
-    e = gemm_hn(pl.stream, pl.nproj, nb, pl.ng, pl.beta32, pl.ldv, x, ld, P, pl.nproj, w.part, w.part_elems, pl.dkb,
-                nullptr);
     if (e != hipSuccess) return e;
-    return gemm_nn(pl.stream, pl.ng, nb, pl.nproj, pl.beta32, pl.ldv, P, pl.nproj, out, ld, true);
+    return apply_nl_f32(pl, w, nb, x, ld, out, ld, nullptr, bf16, w.W, sizeof(double2) * 2 * (size_t)nbw * pl.ldv);
 }
 
 // Mixed-precision source problems: the correction d = u - psi solves
@@ -70,23 +86,23 @@ static hipError_t apply_full(const Plan &pl, const Workspace &w, int nb, const f
 // written in FP64.  The FP64 Rayleigh-Ritz that follows acts as the
 // refinement: the FP32 error is relative to d, which vanishes as the bands
 // converge.
+// With bf16 the projector products run as split-BF16 products, their
+// operand pairs in the W block past d (the correction, in its first
+// quarter).
 static hipError_t source_solve_mixed(const Plan &pl, const Workspace &w, int nb, const double2 *psi,
                                      const double2 *hpsi, int64_t ld, const double *eps, const double *shift, int ncg,
-                                     double2 *u, int64_t ldu, int32_t *band_flags, bool correction)
+                                     double2 *u, int64_t ldu, int32_t *band_flags, bool correction, bool bf16)
 {
     hipError_t e = launch_pcg_init_mixed(pl, w, nb, psi, hpsi, ld, eps, band_flags);
     double *pq_parts = w.dots + (size_t)DOT_PQ * nb * kMaxParts;
-    float2 *P = reinterpret_cast<float2 *>(w.P);
+    void *scratch = reinterpret_cast<char *>(w.W) + sizeof(float2) * (size_t)nb * pl.ldv;
+    const size_t cap = sizeof(float2) * 3 * (size_t)nb * pl.ldv;
     for (int k = 1; k <= ncg && e == hipSuccess; ++k) {
         int npq = 0;
         e = launch_local_apply(pl, w, nb, w.z32, pl.ldv, w.q32, shift, w.p32, w.sc + SC_BETA * nb, k == 1, pq_parts,
                                &npq);
-        if (e == hipSuccess && pl.nproj > 0) {
-            e = gemm_hn(pl.stream, pl.nproj, nb, pl.ng, pl.beta32, pl.ldv, w.p32, pl.ldv, P, pl.nproj, w.part,
-                        w.part_elems, pl.dkb, w.sc + SC_NLQ * nb);
-            if (e == hipSuccess)
-                e = gemm_nn(pl.stream, pl.ng, nb, pl.nproj, pl.beta32, pl.ldv, P, pl.nproj, w.q32, pl.ldv, true);
-        }
+        if (e == hipSuccess)
+            e = apply_nl_f32(pl, w, nb, w.p32, pl.ldv, w.q32, pl.ldv, w.sc + SC_NLQ * nb, bf16, scratch, cap);
         if (e == hipSuccess) e = launch_pcg_update_mixed(pl, w, nb, npq, band_flags);
     }
     if (e == hipSuccess) e = launch_finish_correction(pl, w, nb, correction ? nullptr : psi, ld, u, ldu);
@@ -238,24 +254,36 @@ int32_t paro_projector_gradient(paro_plan plan, int32_t nb, const double *psi, i
     return PARO_OK;
 }
 
-int32_t paro_apply_h_f32(paro_plan plan, int32_t nb, const float *psi, int64_t ld, const double *shift, float *hpsi,
-                         void *ws, size_t ws_bytes)
+static int32_t apply_f32_entry(const char *name, paro_plan plan, int32_t nb, const float *psi, int64_t ld,
+                               const double *shift, float *hpsi, void *ws, size_t ws_bytes, bool bf16)
 {
     if (!plan || nb <= 0 || !psi || !hpsi) {
-        set_error("paro_apply_h_f32: bad argument");
+        set_error(std::string(name) + ": bad argument");
         return PARO_EINVAL;
     }
     const Plan &pl = plan->pl;
     if (ld < pl.ng) {
-        set_error("paro_apply_h_f32: ld < n_g");
+        set_error(std::string(name) + ": ld < n_g");
         return PARO_EINVAL;
     }
     const int nbw = (nb + 1) / 2;
     int32_t rc = check_ws(pl, nbw, ws, ws_bytes);
     if (rc) return rc;
     Workspace w = carve_workspace(pl, nbw, ws);
-    PARO_CHECK_LAUNCH(apply_full(pl, w, nb, (const float2 *)psi, ld, (float2 *)hpsi, shift));
+    PARO_CHECK_LAUNCH(apply_full(pl, w, nb, nbw, (const float2 *)psi, ld, (float2 *)hpsi, shift, bf16));
     return PARO_OK;
+}
+
+int32_t paro_apply_h_f32(paro_plan plan, int32_t nb, const float *psi, int64_t ld, const double *shift, float *hpsi,
+                         void *ws, size_t ws_bytes)
+{
+    return apply_f32_entry("paro_apply_h_f32", plan, nb, psi, ld, shift, hpsi, ws, ws_bytes, false);
+}
+
+int32_t paro_apply_h_f32_bf16(paro_plan plan, int32_t nb, const float *psi, int64_t ld, const double *shift,
+                              float *hpsi, void *ws, size_t ws_bytes)
+{
+    return apply_f32_entry("paro_apply_h_f32_bf16", plan, nb, psi, ld, shift, hpsi, ws, ws_bytes, true);
 }
 
 int32_t paro_source_solve_mixed(paro_plan plan, int32_t nb, const double *psi, const double *hpsi, int64_t ld,
@@ -275,7 +303,7 @@ int32_t paro_source_solve_mixed(paro_plan plan, int32_t nb, const double *psi, c
     if (rc) return rc;
     Workspace w = carve_workspace(pl, nb, ws);
     PARO_CHECK_LAUNCH(source_solve_mixed(pl, w, nb, (const double2 *)psi, (const double2 *)hpsi, ld, eps, shift,
-                                         n_cg, (double2 *)u, ld, band_flags, false));
+                                         n_cg, (double2 *)u, ld, band_flags, false, false));
     return PARO_OK;
 }
 
@@ -399,7 +427,8 @@ int32_t prepare_cell(paro_plan plan, int32_t nb, double *psi, double *hpsi, int6
         (opts->variant != PARO_VARIANT_PARO && opts->variant != PARO_VARIANT_MPARO1 &&
          opts->variant != PARO_VARIANT_MPARO2) ||
         (opts->shift_mode != PARO_SHIFT_FIXED && opts->shift_mode != PARO_SHIFT_ADAPTIVE) ||
-        (opts->precision != PARO_PREC_FP64 && opts->precision != PARO_PREC_MIXED)) {
+        (opts->precision != PARO_PREC_FP64 && opts->precision != PARO_PREC_MIXED &&
+         opts->precision != PARO_PREC_MIXED_BF16)) {
         set_error("paro_iterate: bad argument");
         return PARO_EINVAL;
     }
@@ -456,9 +485,9 @@ hipError_t enqueue_solve(CellRun &c)
     const int64_t lv = pl.ldv;
     const bool mparo = c.o.variant != PARO_VARIANT_PARO;
     double2 *Ut = mparo ? w.U + (size_t)c.nb * lv : w.U;  // u (Algorithm 1) or e (Algorithms 2, 3)
-    if (c.o.precision == PARO_PREC_MIXED)
+    if (c.o.precision != PARO_PREC_FP64)
         return source_solve_mixed(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.sig_all, c.o.n_cg, Ut, lv,
-                                  w.iflags + c.nb, mparo);
+                                  w.iflags + c.nb, mparo, c.o.precision == PARO_PREC_MIXED_BF16);
     return source_solve(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.sig_all, c.o.n_cg, Ut, lv, w.iflags + c.nb,
                         c.o.variant);
 }

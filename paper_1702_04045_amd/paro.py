@@ -171,8 +171,9 @@ class Plan:
                 "paro_apply_h")
         return out
 
-    def apply_h_f32(self, psi, shift=None, out=None):
-        """(H - shift_b) psi_b in single precision; psi: band-major complex64 block."""
+    def apply_h_f32(self, psi, shift=None, out=None, bf16=False):
+        """(H - shift_b) psi_b in single precision; psi: band-major complex64 block.  bf16:
+        the projector products as split-BF16 products (paro_apply_h_f32_bf16)."""
         torch = _torch()
         assert psi.dtype == torch.complex64 and psi.device == self.device and psi.dim() == 2
         assert psi.stride(1) == 1 and psi.stride(0) >= self.ng
@@ -180,8 +181,8 @@ class Plan:
         out = out if out is not None else torch.empty_like(psi)
         ws, n = self.workspace((nb + 1) // 2)
         self._sync_stream()
-        L.check(self.lib.paro_apply_h_f32(self.h, nb, _ptr(psi), psi.stride(0), _ptr(shift), _ptr(out), ws, n),
-                "paro_apply_h_f32")
+        name = "paro_apply_h_f32_bf16" if bf16 else "paro_apply_h_f32"
+        L.check(getattr(self.lib, name)(self.h, nb, _ptr(psi), psi.stride(0), _ptr(shift), _ptr(out), ws, n), name)
         return out
 
     def density(self, psi, weights=None, out=None):
@@ -297,7 +298,8 @@ class Plan:
                 shift_mode=L.SHIFT_FIXED, initial_rr=True, n_conv=None, tol_res=0.0, stats=True,
                 precision=L.PREC_FP64):
         """ParO / MParO I / MParO II outer iterations; psi is updated in place.  precision:
-        PREC_FP64, or PREC_MIXED (FP32 source problems, FP64 Rayleigh-Ritz).
+        PREC_FP64, PREC_MIXED (FP32 source problems, FP64 Rayleigh-Ritz), or PREC_MIXED_BF16
+        (PREC_MIXED with split-BF16 projector products in the source problems).
 
         Returns dict(psi, hpsi, eps, sigma, stats (rows x (2 nb + 2)) or None, n_done)."""
         torch = _torch()

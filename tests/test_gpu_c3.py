@@ -16,6 +16,7 @@ import pytest
 
 import oracle
 import synth
+from test_gpu_bf16 import nl_bound
 from test_gpu_parity import make_case, rel_err, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
@@ -52,6 +53,11 @@ def test_apply_h_c3_sampled_bands(c3, block):
     g32 = to_np(pl.apply_h_f32(to_dev(x.astype(np.complex64))))[:, :h.ng]
     ref32 = h.apply(x[idx].astype(np.complex64).astype(np.complex128))
     assert rel_err(g32[idx], ref32) < 2e-6
+    # split-BF16 projector products (512 projectors, 640 bands): the bound of tests/test_gpu_bf16.py
+    gbf = to_np(pl.apply_h_f32(to_dev(x.astype(np.complex64)), bf16=True))[:, :h.ng]
+    xs = x[idx].astype(np.complex64).astype(np.complex128)
+    bound = 2e-6 * np.abs(ref32).max() + nl_bound(c, h, xs)
+    assert np.all(np.abs(gbf[idx] - ref32) <= bound)
 
 
 @pytest.mark.timeout(600)
