@@ -386,6 +386,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the truncated-iteration gradient timing")
     ap.add_argument("--c3-tta", action="store_true",
                     help="only run the 161k-plane-wave leg with the time to 1e-8 Ha in both precisions and exit")
+    ap.add_argument("--batch-only", action="store_true", help="only run the 24-cell batched leg and exit")
     ap.add_argument("--c3-only", action="store_true",
                     help="only run the 161k-plane-wave leg (3 timed outer iterations per precision) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -407,6 +408,9 @@ def main():
     import torch
     import paper_1702_04045_amd as P
     from paper_1702_04045_amd import _lib as L
+    if args.batch_only:
+        print(json.dumps({"batched_cells": batched_cells(args, P, torch)}))
+        return
     if args.c3_tta or args.c3_only:
         print(json.dumps({"at_scale": at_scale(args, P, torch, tta=args.c3_tta, tta_seconds=args.tta_seconds)}))
         return

@@ -16,6 +16,7 @@
 #include <type_traits>
 
 #include "fft_device.h"
+#include "group.h"
 #include "paro_internal.h"
 #include "reduce_device.h"
 
@@ -86,10 +87,10 @@ template <int N, class C2> __device__ __forceinline__ void xl_forward(C2 (&v)[N 
 // pbuf != null: PCG prologue, p <- z + beta p (first step: p <- z), the new p
 // is written back and transformed.  Otherwise src is transformed as is.
 template <int N3, class C2>
-__global__ void __launch_bounds__((stick_threads<N3, C2>()))
-k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const double *__restrict__ beta, int first,
-            C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ st_start, const int32_t *__restrict__ pt_sz,
-            const C2 *__restrict__ tw)
+__device__ __forceinline__ void stick_inv_body(int bx, int by, const C2 *__restrict__ src, int64_t ld,
+                                               C2 *__restrict__ pbuf, const double *__restrict__ beta, int first,
+                                               C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ st_start,
+                                               const int32_t *__restrict__ pt_sz, const C2 *__restrict__ tw)
 {
     using C = FftCfg<N3>;
     using S2 = RealOf<C2>;
@@ -99,7 +100,7 @@ k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const
     __shared__ C2 tile[S * LD];
     __shared__ C2 twl[N3];  // LDS copy of the twiddle table
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
-    const int s0 = blockIdx.x * S, band = blockIdx.y;
+    const int s0 = bx * S, band = by;
     const int s = s0 + sl;
     const bool act = s < nst;
     for (int i = tid; i < S * LD; i += NT) tile[i] = cmk<C2>(0.0, 0.0);
@@ -144,6 +145,23 @@ k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const
                 v, t, [&](int i, int e) { out[(size_t)i * nst + s] = v[e]; });
     }
 }
+template <int N3, class C2>
+__global__ void __launch_bounds__((stick_threads<N3, C2>()))
+k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const double *__restrict__ beta, int first,
+            C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ st_start, const int32_t *__restrict__ pt_sz,
+            const C2 *__restrict__ tw)
+{
+    stick_inv_body<N3, C2>(blockIdx.x, blockIdx.y, src, ld, pbuf, beta, first, sticks, nst, st_start, pt_sz, tw);
+}
+template <int N3, class C2>
+__global__ void __launch_bounds__((stick_threads<N3, C2>())) k_stick_inv_grp(GroupTab t, int first)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const StickInvArgs<C2> &a = *static_cast<const StickInvArgs<C2> *>(t.args[e]);
+    stick_inv_body<N3, C2>(bx, by, a.src, a.ld, a.pbuf, a.beta, first, a.sticks, a.nst, a.st_start, a.pt_sz, a.tw);
+}
+
 
 // One z-plane of bands b0 .. b1-1: inverse along n2 (populated n1 columns),
 // along n1 (all rows), times V, forward along n1, forward along n2; in place
@@ -163,10 +181,9 @@ k_stick_inv(const C2 *__restrict__ src, int64_t ld, C2 *__restrict__ pbuf, const
 // reads E consecutive doubles, which the bands of the work-group share
 // through the cache.
 template <int N, class C2>
-__global__ void __launch_bounds__((plane_threads<N, C2>()))
-__attribute__((amdgpu_waves_per_eu(PlaneCfgP<N, C2>::min_waves)))
-k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restrict__ cols,
-        const RealOf<C2> *__restrict__ vperm, int nmax1, const C2 *__restrict__ tw)
+__device__ __forceinline__ void plane_body(int bx, int by, C2 *__restrict__ sticks, int nst, int N3, int nb,
+                                           const int32_t *__restrict__ cols, const RealOf<C2> *__restrict__ vperm,
+                                           int nmax1, const C2 *__restrict__ tw)
 {
     using VR = RealOf<C2>;
     using C = PlaneCfgP<N, C2>;
@@ -179,10 +196,10 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
     __shared__ C2 plane[N * LDX];
     __shared__ C2 twl[N];  // LDS copy of the twiddle table
     const int tid = threadIdx.x;
-    const int z = blockIdx.x;
+    const int z = bx;
     for (int i = tid; i < N; i += plane_threads<N, C2>()) twl[i] = tw[i];
     __syncthreads();
-    const int b0 = blockIdx.y * kBandsPerBlock, b1 = min(b0 + kBandsPerBlock, nb);
+    const int b0 = by * kBandsPerBlock, b1 = min(b0 + kBandsPerBlock, nb);
     const int nbk = b1 - b0;
     const int ncol = 2 * nmax1 + 1;
     const int slot = line_of<T>(tid), t = thread_in_line<T>(tid);
@@ -328,6 +345,25 @@ k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restr
         __syncthreads();
     }
 }
+template <int N, class C2>
+__global__ void __launch_bounds__((plane_threads<N, C2>()))
+__attribute__((amdgpu_waves_per_eu(PlaneCfgP<N, C2>::min_waves)))
+k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restrict__ cols,
+        const RealOf<C2> *__restrict__ vperm, int nmax1, const C2 *__restrict__ tw)
+{
+    plane_body<N, C2>(blockIdx.x, blockIdx.y, sticks, nst, N3, nb, cols, vperm, nmax1, tw);
+}
+template <int N, class C2>
+__global__ void __launch_bounds__((plane_threads<N, C2>()))
+__attribute__((amdgpu_waves_per_eu(PlaneCfgP<N, C2>::min_waves)))
+k_plane_grp(GroupTab t)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const PlaneArgs<C2> &a = *static_cast<const PlaneArgs<C2> *>(t.args[e]);
+    plane_body<N, C2>(bx, by, a.sticks, a.nst, a.N3, a.nb, a.cols, a.vperm, a.nmax1, a.tw);
+}
+
 
 // Density of bands b0 .. b1-1 (b1 - b0 <= bands per group) on one
 // z-plane: inverse along n2 and n1 as in k_plane, then w_b |psi_b(r)|^2
@@ -555,11 +591,12 @@ void plane_potential(const int32_t *grid, const double *vloc, VT *out)
 // Sticks -> sphere, forward transform along n3, then
 // out = scale * local + (kin - shift_b) x; dot_part gets sum Re(conj(x) out).
 template <int N3, class C2>
-__global__ void __launch_bounds__((stick_threads<N3, C2>()))
-k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ st_start,
-            const int32_t *__restrict__ pt_sz, const C2 *__restrict__ tw, const C2 *__restrict__ xin, int64_t ld,
-            C2 *__restrict__ out, const double *__restrict__ kin, const double *__restrict__ shift, double scale,
-            double *__restrict__ dot_part, int part_stride)
+__device__ __forceinline__ void stick_fwd_body(int bx, int by, const C2 *__restrict__ sticks, int nst,
+                                               const int32_t *__restrict__ st_start,
+                                               const int32_t *__restrict__ pt_sz, const C2 *__restrict__ tw,
+                                               const C2 *__restrict__ xin, int64_t ld, C2 *__restrict__ out,
+                                               const double *__restrict__ kin, const double *__restrict__ shift,
+                                               double scale, double *__restrict__ dot_part, int part_stride)
 {
     using C = FftCfg<N3>;
     using Fwd = typename C::Fwd;
@@ -570,7 +607,7 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
     __shared__ double red[NT / 64];
     __shared__ C2 twl[N3];  // LDS copy of the twiddle table
     const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
-    const int s0 = blockIdx.x * S, band = blockIdx.y;
+    const int s0 = bx * S, band = by;
     const int s = s0 + sl;
     const bool act = s < nst;
     const C2 *in = sticks + (size_t)band * N3 * nst;
@@ -613,9 +650,29 @@ k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ 
     }
     if (dot_part) {
         dot = block_sum<NT>(dot, red);
-        if (tid == 0) dot_part[(size_t)band * part_stride + blockIdx.x] = dot;
+        if (tid == 0) dot_part[(size_t)band * part_stride + bx] = dot;
     }
 }
+template <int N3, class C2>
+__global__ void __launch_bounds__((stick_threads<N3, C2>()))
+k_stick_fwd(const C2 *__restrict__ sticks, int nst, const int32_t *__restrict__ st_start,
+            const int32_t *__restrict__ pt_sz, const C2 *__restrict__ tw, const C2 *__restrict__ xin, int64_t ld,
+            C2 *__restrict__ out, const double *__restrict__ kin, const double *__restrict__ shift, double scale,
+            double *__restrict__ dot_part, int part_stride)
+{
+    stick_fwd_body<N3, C2>(blockIdx.x, blockIdx.y, sticks, nst, st_start, pt_sz, tw, xin, ld, out, kin, shift, scale,
+                           dot_part, part_stride);
+}
+template <int N3, class C2>
+__global__ void __launch_bounds__((stick_threads<N3, C2>())) k_stick_fwd_grp(GroupTab t)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const StickFwdArgs<C2> &a = *static_cast<const StickFwdArgs<C2> *>(t.args[e]);
+    stick_fwd_body<N3, C2>(bx, by, a.sticks, a.nst, a.st_start, a.pt_sz, a.tw, a.xin, a.ld, a.out, a.kin, a.shift,
+                           a.scale, a.dot_part, a.part_stride);
+}
+
 
 // ---------------------------------------------------------------- fused plane stage above 96 points
 // One z-plane of up to kCcBands bands per work-group, with the plane held
@@ -932,6 +989,99 @@ hipError_t launch_local_apply(const Plan &pl, const Workspace &w, int nb, const 
                               int *nparts_out)
 {
     return local_apply<float2>(pl, w, nb, src, ld, out, shift, pbuf, beta, first, dot_part, nparts_out);
+}
+
+}  // namespace paro
+
+namespace paro {
+
+// ---------------------------------------------------------------- grouped launches
+// The local part of the source solve's (H - sigma) p for many cells: per
+// 64-band chunk the arguments run_local gives k_stick_inv, k_plane and
+// k_stick_fwd, with src = z, out = q, pbuf = p, beta = the PCG beta.
+int describe_local_apply(const Plan &pl, const Workspace &w, int nb, const double *shift, GroupCellDesc &d)
+{
+    const int N3 = pl.grid[2];
+    int ntiles = 0;
+    const double scale = 1.0 / ((double)pl.grid[0] * pl.grid[1] * pl.grid[2]);
+    const double *beta = w.sc + SC_BETA * nb;
+    double *pq_parts = w.dots + (size_t)DOT_PQ * nb * kMaxParts;
+    for (int c = 0, c0 = 0; c0 < nb; ++c, c0 += kMaxBandsPerChunk) {
+        const int cb = std::min(kMaxBandsPerChunk, nb - c0);
+        d.sinv[c] = StickInvArgs<double2>{w.z + c0 * pl.ldv, pl.ldv, w.p + c0 * pl.ldv, beta + c0, w.sticks,
+                                          pl.st_start, pl.pt_sz, pl.tw[2], pl.nst};
+        d.plane[c] = PlaneArgs<double2>{w.sticks, pl.cols, pl.vplane, pl.tw[0], pl.nst, N3, cb, pl.nmax[0]};
+        d.sfwd[c] = StickFwdArgs<double2>{w.sticks, pl.st_start, pl.pt_sz, pl.tw[2], w.p + c0 * pl.ldv, pl.ldv,
+                                          w.q + c0 * pl.ldv, pl.kin, shift ? shift + c0 : nullptr, scale,
+                                          pq_parts + (size_t)c0 * kMaxParts, pl.nst, kMaxParts};
+    }
+    switch (pl.grid[0]) {
+#define PARO_CASE(n) \
+    case n: ntiles = (pl.nst + stick_threads<n, double2>() / FftCfg<n>::T - 1) / (stick_threads<n, double2>() / FftCfg<n>::T); break;
+    PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
+    PARO_CASE(80) PARO_CASE(96)
+#undef PARO_CASE
+    default: break;
+    }
+    return ntiles;
+}
+
+bool grouped_grid(int n) { return fft_supported(n) && !big_grid(n); }
+
+namespace {
+
+template <int N>
+hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool first)
+{
+    constexpr int NT = stick_threads<N, double2>();
+    constexpr int S = NT / FftCfg<N>::T;
+    int rounds = 0;
+    for (int i = 0; i < n; ++i)
+        if (cells[i].pl->grid[0] == N) rounds = std::max(rounds, cells[i].nchunk);
+    for (int r = 0; r < rounds; ++r) {
+        // the three kernels in turn, every entry of the round in each
+        for (int k = 0; k < 3; ++k) {
+            GroupBuilder g;
+            auto flush = [&]() {
+                if (g.t.n == 0) return;
+                const dim3 grid((unsigned)g.total);
+                if (k == 0)
+                    hipLaunchKernelGGL((k_stick_inv_grp<N, double2>), grid, dim3(NT), 0, s, g.t, first ? 1 : 0);
+                else if (k == 1)
+                    hipLaunchKernelGGL((k_plane_grp<N, double2>), grid, dim3(plane_threads<N, double2>()), 0, s,
+                                       g.t);
+                else
+                    hipLaunchKernelGGL((k_stick_fwd_grp<N, double2>), grid, dim3(NT), 0, s, g.t);
+                g = GroupBuilder();
+            };
+            for (int i = 0; i < n; ++i) {
+                const GroupCell &c = cells[i];
+                if (c.pl->grid[0] != N || c.nchunk <= r) continue;
+                const int cb = std::min(kMaxBandsPerChunk, c.nb - r * kMaxBandsPerChunk);
+                const int ntiles = (c.pl->nst + S - 1) / S;
+                if (k == 0) g.add(&c.dev->sinv[r], (int64_t)ntiles * cb, ntiles);
+                else if (k == 1) g.add(&c.dev->plane[r], (int64_t)c.pl->grid[2] * ((cb + kBandsPerBlock - 1) / kBandsPerBlock),
+                                       c.pl->grid[2]);
+                else g.add(&c.dev->sfwd[r], (int64_t)ntiles * cb, ntiles);
+                if (g.full()) flush();
+            }
+            flush();
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_local_apply_grouped(hipStream_t s, const GroupCell *cells, int n, bool first)
+{
+    hipError_t e = hipSuccess;
+#define PARO_CASE(k) \
+    if (e == hipSuccess) e = grouped_local_n<k>(s, cells, n, first);
+    PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
+    PARO_CASE(80) PARO_CASE(96)
+#undef PARO_CASE
+    return e;
 }
 
 }  // namespace paro

@@ -19,6 +19,7 @@
 #include <cmath>
 
 #include "fft_device.h"
+#include "group.h"
 #include "paro_internal.h"
 #include "reduce_device.h"
 
@@ -106,15 +107,13 @@ template <> struct NnCfg<float2> {
 // split are adjacent, so the blocks that share the split's slices of A and
 // B run at the same time on the same die.
 template <class C2>
-__global__ void __launch_bounds__(256)
-k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, int bm, int bn, int64_t units, const C2 *__restrict__ A,
-               int64_t lda, const C2 *__restrict__ B, int64_t ldb, double2 *__restrict__ part)
+__device__ __forceinline__ void hn_unit(int64_t unit, int lane, int M, int N, int64_t K, int64_t kchunk, int bm,
+                                        int bn, const C2 *__restrict__ A, int64_t lda, const C2 *__restrict__ B,
+                                        int64_t ldb, double2 *__restrict__ part)
 {
     using Acc = typename Mma<C2>::Acc;
     constexpr int kDepthHN = HnCfg<C2>::depth;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t nw = (int64_t)gridDim.x * 4;
-    for (int64_t unit = xcd_work_index(blockIdx.x, gridDim.x) * 4 + wave; unit < units; unit += nw) {
+    {
         const int split = (int)(unit / (bm * bn)), blk = (int)(unit % (bm * bn));
         const int i0 = (blk % bm) * 32, j0 = (blk / bm) * 32;
         const int64_t kb = (int64_t)split * kchunk;
@@ -230,6 +229,27 @@ k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, int bm, int bn, int64_t 
                 }
     }
 }
+template <class C2>
+__global__ void __launch_bounds__(256)
+k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, int bm, int bn, int64_t units, const C2 *__restrict__ A,
+               int64_t lda, const C2 *__restrict__ B, int64_t ldb, double2 *__restrict__ part)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t unit = xcd_work_index(blockIdx.x, gridDim.x) * 4 + wave; unit < units; unit += nw)
+        hn_unit<C2>(unit, lane, M, N, K, kchunk, bm, bn, A, lda, B, ldb, part);
+}
+// the units of every entry, in one range (start[] counts units)
+template <class C2> __global__ void __launch_bounds__(256) k_gemm_hn_part_grp(GroupTab t)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t nw = (int64_t)gridDim.x * 4, total = t.start[t.n];
+    for (int64_t g = xcd_work_index(blockIdx.x, gridDim.x) * 4 + wave; g < total; g += nw) {
+        const int e = group_entry(t, g);
+        const GemmHnArgs<C2> &a = *static_cast<const GemmHnArgs<C2> *>(t.args[e]);
+        hn_unit<C2>(g - t.start[e], lane, a.M, a.N, a.K, a.kchunk, a.bm, a.bn, a.A, a.lda, a.B, a.ldb, a.part);
+    }
+}
 
 // C[i][j] = dscale_i * sum_s part[s][j][i]; quad_j = sum_i dscale_i |sum_s part|^2.
 // One work-group per column j; 64 rows at a time, the splits dealt to four
@@ -238,13 +258,12 @@ k_gemm_hn_part(int M, int N, int64_t K, int64_t kchunk, int bm, int bn, int64_t 
 // is bitwise reproducible, with four times the loads in flight of one
 // thread per row.
 template <class CO>
-__global__ void __launch_bounds__(256)
-k_gemm_hn_reduce(int M, int N, int nsplit, const double2 *__restrict__ part, CO *__restrict__ C, int64_t ldc,
-                 const double *__restrict__ dscale, double *__restrict__ quad)
+__device__ __forceinline__ void hn_reduce_body(int j, int M, int N, int nsplit, const double2 *__restrict__ part,
+                                               CO *__restrict__ C, int64_t ldc, const double *__restrict__ dscale,
+                                               double *__restrict__ quad)
 {
     __shared__ double red[4];
     __shared__ double2 grp[4][64];
-    const int j = blockIdx.x;
     const int r = threadIdx.x & 63, g = threadIdx.x >> 6;
     double q = 0.0;
     for (int i0 = 0; i0 < M; i0 += 64) {
@@ -282,21 +301,30 @@ k_gemm_hn_reduce(int M, int N, int nsplit, const double2 *__restrict__ part, CO 
         if (threadIdx.x == 0) quad[j] = q;
     }
 }
+template <class CO>
+__global__ void __launch_bounds__(256)
+k_gemm_hn_reduce(int M, int N, int nsplit, const double2 *__restrict__ part, CO *__restrict__ C, int64_t ldc,
+                 const double *__restrict__ dscale, double *__restrict__ quad)
+{
+    hn_reduce_body<CO>(blockIdx.x, M, N, nsplit, part, C, ldc, dscale, quad);
+}
+template <class CO> __global__ void __launch_bounds__(256) k_gemm_hn_reduce_grp(GroupTab t)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const GemmHnRedArgs<CO> &a = *static_cast<const GemmHnRedArgs<CO> *>(t.args[e]);
+    hn_reduce_body<CO>(bx, a.M, a.N, a.nsplit, a.part, a.C, a.ldc, a.dscale, a.quad);
+}
 
 // C[g][n] (+)= sum_k A[g][k] B[k][n]; matrix-core rows = n, columns = g.
 template <class C2>
-__global__ void __launch_bounds__(256, 2)
-k_gemm_nn(int64_t M, int N, int K, int bn, int64_t units, const C2 *__restrict__ A, int64_t lda,
-          const C2 *__restrict__ B, int64_t ldb, C2 *__restrict__ C, int64_t ldc, int accumulate)
+__device__ __forceinline__ void nn_unit(int64_t unit, int lane, int64_t M, int N, int K, int bn,
+                                        const C2 *__restrict__ A, int64_t lda, const C2 *__restrict__ B, int64_t ldb,
+                                        C2 *__restrict__ C, int64_t ldc, int accumulate)
 {
     using Acc = typename Mma<C2>::Acc;
     constexpr int kDepthNN = NnCfg<C2>::depth;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // work unit = one 32 x 32 block of C, done by one wavefront; the bn
-    // column blocks of one row block (which share its rows of A) are
-    // adjacent units
-    const int64_t nw = (int64_t)gridDim.x * 4;
-    for (int64_t unit = xcd_work_index(blockIdx.x, gridDim.x) * 4 + wave; unit < units; unit += nw) {
+    {
         const int64_t g0 = (unit / bn) * 32;
         const int n0 = (int)(unit % bn) * 32;
         const int l16 = lane & 15, lk = lane >> 4;
@@ -422,6 +450,29 @@ k_gemm_nn(int64_t M, int N, int K, int bn, int64_t units, const C2 *__restrict__
         }
     }
 }
+template <class C2>
+__global__ void __launch_bounds__(256, 2)
+k_gemm_nn(int64_t M, int N, int K, int bn, int64_t units, const C2 *__restrict__ A, int64_t lda,
+          const C2 *__restrict__ B, int64_t ldb, C2 *__restrict__ C, int64_t ldc, int accumulate)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // work unit = one 32 x 32 block of C, done by one wavefront; the bn
+    // column blocks of one row block (which share its rows of A) are
+    // adjacent units
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t unit = xcd_work_index(blockIdx.x, gridDim.x) * 4 + wave; unit < units; unit += nw)
+        nn_unit<C2>(unit, lane, M, N, K, bn, A, lda, B, ldb, C, ldc, accumulate);
+}
+template <class C2> __global__ void __launch_bounds__(256, 2) k_gemm_nn_grp(GroupTab t)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t nw = (int64_t)gridDim.x * 4, total = t.start[t.n];
+    for (int64_t g = xcd_work_index(blockIdx.x, gridDim.x) * 4 + wave; g < total; g += nw) {
+        const int e = group_entry(t, g);
+        const GemmNnArgs<C2> &a = *static_cast<const GemmNnArgs<C2> *>(t.args[e]);
+        nn_unit<C2>(g - t.start[e], lane, a.M, a.N, a.K, a.bn, a.A, a.lda, a.B, a.ldb, a.C, a.ldc, a.accumulate);
+    }
+}
 
 // One work-group per projector: beta_p(G) for every sphere point, then the
 // normalisation sum_G |beta_p(G)|^2 = 1 (two passes over the sphere).
@@ -474,14 +525,15 @@ __global__ void __launch_bounds__(256) k_to_single(int64_t n, const double2 *__r
     }
 }
 
+// The split of A^H B over K: about one unit per wavefront slot of the
+// chip, each split at least one prefetch ring of k long, within the
+// partial buffer, and a whole number of ring passes long (all but the last
+// then take the kernel's unmasked path).  False if the buffer is too small.
 template <class C2>
-hipError_t gemm_hn_t(hipStream_t s, int M, int N, int64_t K, const C2 *A, int64_t lda, const C2 *B, int64_t ldb,
-                     C2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale, double *quad)
+bool hn_split(int M, int N, int64_t K, size_t part_elems, int64_t *nsplit_out, int64_t *kchunk_out,
+              int64_t *units_out)
 {
-    if (M <= 0 || N <= 0) return hipSuccess;
     const int bm = (M + 31) / 32, bn = (N + 31) / 32;
-    // about one unit per wavefront slot of the chip, each split at least one
-    // prefetch ring of k long, within the partial buffer
     constexpr int kDepthHN = HnCfg<C2>::depth, kWaveSlotsHN = HnCfg<C2>::slots;
     int64_t nsplit = kWaveSlotsHN / ((int64_t)bm * bn);
     const int64_t kmax = (K + 4 * kDepthHN - 1) / (4 * kDepthHN);
@@ -489,15 +541,27 @@ hipError_t gemm_hn_t(hipStream_t s, int M, int N, int64_t K, const C2 *A, int64_
     if (nsplit < 1) nsplit = 1;
     const int64_t cap = (int64_t)(part_elems / ((size_t)M * N));
     if (nsplit > cap) nsplit = cap;
-    if (nsplit < 1) return hipErrorInvalidValue;
-    // splits a whole number of prefetch-ring passes long (all but the last
-    // then take the kernel's unmasked path)
+    if (nsplit < 1) return false;
     const int64_t ring = 4 * kDepthHN;
     int64_t kchunk = (K + nsplit - 1) / nsplit;
     kchunk = (kchunk + ring - 1) / ring * ring;
     nsplit = (K + kchunk - 1) / kchunk;
     if (nsplit < 1) nsplit = 1;
-    const int64_t units = (int64_t)bm * bn * nsplit;
+    *nsplit_out = nsplit;
+    *kchunk_out = kchunk;
+    *units_out = (int64_t)bm * bn * nsplit;
+    return true;
+}
+
+template <class C2>
+hipError_t gemm_hn_t(hipStream_t s, int M, int N, int64_t K, const C2 *A, int64_t lda, const C2 *B, int64_t ldb,
+                     C2 *C, int64_t ldc, double2 *part, size_t part_elems, const double *dscale, double *quad)
+{
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int bm = (M + 31) / 32, bn = (N + 31) / 32;
+    constexpr int kWaveSlotsHN = HnCfg<C2>::slots;
+    int64_t nsplit, kchunk, units;
+    if (!hn_split<C2>(M, N, K, part_elems, &nsplit, &kchunk, &units)) return hipErrorInvalidValue;
     const unsigned wgs = (unsigned)std::min<int64_t>((units + 3) / 4, kWaveSlotsHN / 4);
     prof_mark(PARO_K_GEMM_HN, s, true);
     hipLaunchKernelGGL((k_gemm_hn_part<C2>), dim3(wgs), dim3(256), 0, s, M, N, K, kchunk, bm, bn, units, A, lda, B,
@@ -642,6 +706,50 @@ hipError_t launch_build_projectors(const Plan &pl, const int32_t *miller_dev, co
     const double *b = pl.bvec;
     hipLaunchKernelGGL(k_build_projectors, dim3(pl.nproj), dim3(256), 0, pl.stream, pl.ng, miller_dev, b[0], b[1],
                        b[2], b[3], b[4], b[5], b[6], b[7], b[8], centers, lm, widths, pl.beta, pl.ldv);
+    return hipGetLastError();
+}
+
+}  // namespace paro
+
+namespace paro {
+
+// ---------------------------------------------------------------- grouped launches
+// The nonlocal part of the source solve's (H - sigma) p for many cells: the
+// arguments gemm_hn (P = B^H p, times the KB energies, p^H V_NL p into the
+// PCG scalars) and gemm_nn (q += B P) give their kernels.
+void describe_nonlocal(const Plan &pl, const Workspace &w, int nb, GroupCellDesc &d)
+{
+    const int M = pl.nproj, N = nb;
+    int64_t nsplit = 0, kchunk = 0, units = 0;
+    if (M > 0) hn_split<double2>(M, N, pl.ng, w.part_elems, &nsplit, &kchunk, &units);
+    d.hn = GemmHnArgs<double2>{pl.beta, pl.ldv, w.p, pl.ldv, w.part, pl.ng, kchunk, units, M, N, (M + 31) / 32,
+                               (N + 31) / 32};
+    d.hred = GemmHnRedArgs<double2>{w.part, w.P, M, pl.dkb, w.sc + SC_NLQ * nb, M, N, (int)nsplit};
+    const int bn = (N + 31) / 32;
+    d.nn = GemmNnArgs<double2>{pl.beta, pl.ldv, w.P, M, w.q, pl.ldv, pl.ng, (pl.ng + 31) / 32 * bn, N, M, bn, 1};
+}
+
+hipError_t launch_nonlocal_grouped(hipStream_t s, const GroupCell *cells, int n)
+{
+    // cells with projectors, in groups of kGroupMax
+    for (int i0 = 0; i0 < n;) {
+        GroupBuilder hn, red, nn;
+        int i = i0;
+        for (; i < n && !hn.full(); ++i) {
+            const GroupCell &c = cells[i];
+            if (c.pl->nproj == 0) continue;
+            hn.add(&c.dev->hn, c.host->hn.units, 1);
+            red.add(&c.dev->hred, c.nb, c.nb);
+            nn.add(&c.dev->nn, c.host->nn.units, 1);
+        }
+        i0 = i;
+        if (hn.t.n == 0) continue;
+        const unsigned whn = (unsigned)std::min<int64_t>((hn.total + 3) / 4, HnCfg<double2>::slots / 4);
+        const unsigned wnn = (unsigned)std::min<int64_t>((nn.total + 3) / 4, NnCfg<double2>::slots / 4);
+        hipLaunchKernelGGL((k_gemm_hn_part_grp<double2>), dim3(whn), dim3(256), 0, s, hn.t);
+        hipLaunchKernelGGL((k_gemm_hn_reduce_grp<double2>), dim3((unsigned)red.total), dim3(256), 0, s, red.t);
+        hipLaunchKernelGGL((k_gemm_nn_grp<double2>), dim3(wnn), dim3(256), 0, s, nn.t);
+    }
     return hipGetLastError();
 }
 

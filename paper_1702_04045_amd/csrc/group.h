@@ -1,0 +1,178 @@
+// Grouped launches: one kernel launch that runs the work of many cells.
+//
+// A grouped launch covers up to kGroupMax entries (a cell, or one 64-band
+// chunk of a cell).  Entry e owns the virtual blocks start[e] .. start[e+1]-1
+// of a one-dimensional grid, laid out as a gx[e]-wide two-dimensional grid
+// (or, for the matrix-core products, as a range of work units); args[e]
+// points at the entry's kernel arguments in device memory.  The table is
+// passed by value, so a launch needs no copy to the device.  Each entry's
+// blocks compute exactly what the cell's own launch computes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace paro {
+
+constexpr int kGroupMax = 64;
+
+struct GroupTab {
+    const void *args[kGroupMax];
+    int32_t start[kGroupMax + 1];
+    int32_t gx[kGroupMax];
+    int32_t n;
+};
+
+// entry and two-dimensional block coordinates of virtual block b
+__device__ __forceinline__ int group_entry(const GroupTab &t, int64_t b)
+{
+    int lo = 0, hi = t.n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (t.start[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ void group_block(const GroupTab &t, int &e, int &bx, int &by)
+{
+    e = group_entry(t, blockIdx.x);
+    const int l = (int)blockIdx.x - t.start[e];
+    bx = l % t.gx[e];
+    by = l / t.gx[e];
+}
+
+// Host side: entries are appended with their block (or unit) counts.
+struct GroupBuilder {
+    GroupTab t{};
+    int64_t total = 0;
+    GroupBuilder() { t.start[0] = 0; }
+    bool full() const { return t.n == kGroupMax; }
+    void add(const void *dev_args, int64_t blocks, int gx)
+    {
+        t.args[t.n] = dev_args;
+        t.gx[t.n] = gx;
+        total += blocks;
+        t.start[t.n + 1] = (int32_t)total;
+        ++t.n;
+    }
+};
+
+// Kernel arguments of the grouped source solve, one set per cell (the
+// stick and plane kernels one per 64-band chunk).
+template <class C2> struct GReal;
+template <> struct GReal<double2> { using T = double; };
+template <> struct GReal<float2> { using T = float; };
+
+template <class C2> struct StickInvArgs {
+    const C2 *src;
+    int64_t ld;
+    C2 *pbuf;
+    const double *beta;
+    C2 *sticks;
+    const int32_t *st_start, *pt_sz;
+    const C2 *tw;
+    int nst;
+};
+template <class C2> struct PlaneArgs {
+    C2 *sticks;
+    const int32_t *cols;
+    const typename GReal<C2>::T *vperm;
+    const C2 *tw;
+    int nst, N3, nb, nmax1;
+};
+template <class C2> struct StickFwdArgs {
+    const C2 *sticks;
+    const int32_t *st_start, *pt_sz;
+    const C2 *tw, *xin;
+    int64_t ld;
+    C2 *out;
+    const double *kin, *shift;
+    double scale;
+    double *dot_part;
+    int nst, part_stride;
+};
+struct PcgInitPartsArgs {
+    const double2 *psi;
+    int64_t ld;
+    const double *kin;
+    double *dots;
+    int64_t ng;
+    int nb;
+};
+template <class CV, class CU> struct PcgInitArgs {
+    const double2 *psi, *hpsi;
+    int64_t ld;
+    const double *eps, *kin;
+    CU *u;
+    int64_t ldu;
+    CV *r, *z;
+    int64_t ldv;
+    double *dots, *sc;
+    int64_t ng;
+    int nparts, nb, correction;
+};
+struct PcgScalarsArgs {
+    const double *dots_pq, *dots_rz;
+    double *sc;
+    int32_t *active, *bflags, *band_flags_out, *status;
+    int nb, nparts_rz, npq;
+};
+template <class CV, class CU> struct PcgUpdateArgs {
+    const CV *p, *q;
+    int64_t ldv;
+    CU *u;
+    int64_t ldu;
+    CV *r, *z;
+    const double *kin, *dots_pq;
+    double *dots_rz;
+    const double *sc;
+    const int32_t *active;
+    int64_t ng;
+    int npq, nb;
+};
+template <class C2> struct GemmHnArgs {
+    const C2 *A;
+    int64_t lda;
+    const C2 *B;
+    int64_t ldb;
+    double2 *part;
+    int64_t K, kchunk, units;
+    int M, N, bm, bn;
+};
+template <class CO> struct GemmHnRedArgs {
+    const double2 *part;
+    CO *C;
+    int64_t ldc;
+    const double *dscale;
+    double *quad;
+    int M, N, nsplit;
+};
+template <class C2> struct GemmNnArgs {
+    const C2 *A;
+    int64_t lda;
+    const C2 *B;
+    int64_t ldb;
+    C2 *C;
+    int64_t ldc, M, units;
+    int N, K, bn, accumulate;
+};
+
+constexpr int kGroupChunks = 16;  // 64-band chunks of up to 1024 bands
+
+// Everything one cell's FP64 source solve needs, in the cell's workspace.
+struct GroupCellDesc {
+    StickInvArgs<double2> sinv[kGroupChunks];
+    PlaneArgs<double2> plane[kGroupChunks];
+    StickFwdArgs<double2> sfwd[kGroupChunks];
+    GemmHnArgs<double2> hn;
+    GemmHnRedArgs<double2> hred;
+    GemmNnArgs<double2> nn;
+    PcgInitPartsArgs iparts;
+    PcgInitArgs<double2, double2> init;
+    PcgScalarsArgs sc0, sc1;
+    PcgUpdateArgs<double2, double2> upd;
+};
+
+}  // namespace paro

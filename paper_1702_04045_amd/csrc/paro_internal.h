@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <string>
 
+#include "group.h"
 #include "paro.h"
 
 namespace paro {
@@ -69,6 +70,8 @@ struct Workspace {
     // single-precision PCG vectors of the mixed-precision source solve,
     // aliased onto r, z, p, q and W (unused while it runs): nb x ldv each
     float2 *r32, *z32, *p32, *q32, *d32;
+    // kernel arguments of this cell's grouped source-solve launches
+    GroupCellDesc *desc;
 };
 
 size_t workspace_bytes(const Plan &pl, int nb);
@@ -190,6 +193,29 @@ hipError_t launch_heev(hipStream_t st, const Workspace &w, int m, const double2 
 hipError_t launch_shift_bound(const Plan &pl, const Workspace &w, double *sigma);
 hipError_t launch_bookkeeping(const Plan &pl, int nb, const paro_iter_opts &o, const double *eps, const double *res,
                               double *sig_all, double *sig_out, double *stats_row, int32_t *conv);
+
+// Grouped FP64 source solve over many cells (one launch per kernel and
+// FFT length): the cells, each with its descriptor in device memory.
+struct GroupCell {
+    const Plan *pl;
+    const Workspace *w;
+    int nb, nchunk;
+    const GroupCellDesc *dev;   // in the cell's workspace
+    const GroupCellDesc *host;  // the host copy it was written from
+};
+void describe_pcg(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi, int64_t ld,
+                  const double *eps, double2 *u, int64_t ldu, int32_t *band_flags, bool correction, int npq,
+                  GroupCellDesc &d);
+hipError_t launch_pcg_init_grouped(hipStream_t s, const GroupCell *cells, int n);
+hipError_t launch_pcg_update_grouped(hipStream_t s, const GroupCell *cells, int n);
+// the stick and plane launches of (H - sigma) p with the PCG prologue, as
+// launch_local_apply(w.z, w.q, shift, w.p, beta = w.sc + SC_BETA nb); returns
+// the number of partial sums of p^H q per band
+int describe_local_apply(const Plan &pl, const Workspace &w, int nb, const double *shift, GroupCellDesc &d);
+bool grouped_grid(int n);  // FFT lengths with grouped kernels
+hipError_t launch_local_apply_grouped(hipStream_t s, const GroupCell *cells, int n, bool first);
+void describe_nonlocal(const Plan &pl, const Workspace &w, int nb, GroupCellDesc &d);
+hipError_t launch_nonlocal_grouped(hipStream_t s, const GroupCell *cells, int n);
 
 }  // namespace paro
 

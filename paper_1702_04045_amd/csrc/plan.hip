@@ -241,6 +241,7 @@ size_t workspace_bytes(const Plan &pl, int nb)
     add(sizeof(double) * kDotSlots * nb * kMaxParts);          // dots
     add(sizeof(int32_t) * 2 * nb);                              // iflags
     add(sizeof(double) * (3 * m + 8));                          // misc: sig_all, res, eps_all, scalars
+    add(sizeof(GroupCellDesc));                                 // grouped-launch arguments
     return tot;
 }
 
@@ -320,6 +321,7 @@ Workspace carve_workspace(const Plan &pl, int nb, void *ws)
     w.res = misc + m;
     w.eps_all = misc + 2 * m;
     w.scal = misc + 3 * m;
+    w.desc = (GroupCellDesc *)take(sizeof(GroupCellDesc));
     return w;
 }
 

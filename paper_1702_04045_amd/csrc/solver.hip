@@ -1,7 +1,9 @@
 // Drivers of the hot path: H psi, the source problems (Algorithm 1, step 3),
 // Rayleigh-Ritz (step 4), residuals and the ParO outer loop (steps 1, 3-5;
 // Algorithm 2 for the MParO I variant).
+#include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 #include <vector>
 
@@ -657,6 +659,172 @@ int32_t run_cells(std::vector<CellRun> &cells)
     return PARO_OK;
 }
 
+// Whether a batch can run its source problems as grouped launches: FP64
+// Algorithm 1 or 2 on grids with grouped kernels, more than one cell.
+bool groupable(const std::vector<CellRun> &cells)
+{
+    if (cells.size() < 2) return false;
+    for (const CellRun &c : cells)
+        if (c.o.precision != PARO_PREC_FP64 || c.o.variant == PARO_VARIANT_MPARO2 || !grouped_grid(c.pl->grid[0]) ||
+            c.nb > kGroupChunks * kMaxBandsPerChunk)
+            return false;
+    return true;
+}
+
+// The source problems of the given cells (Algorithm 1 step 3, or the
+// correction equation of Algorithm 2) as grouped launches on stream s: per
+// PCG step one launch per kernel and FFT length for all cells, each cell's
+// work exactly that of its own source_solve.
+hipError_t source_solve_grouped(hipStream_t s, const std::vector<GroupCell> &gc, const std::vector<int> &ncg)
+{
+    const int n = (int)gc.size();
+    hipError_t e = launch_pcg_init_grouped(s, gc.data(), n);
+    int kmax = 0;
+    for (int k : ncg) kmax = std::max(kmax, k);
+    std::vector<GroupCell> sub;
+    for (int k = 1; k <= kmax && e == hipSuccess; ++k) {
+        sub.clear();
+        for (int i = 0; i < n; ++i)
+            if (ncg[i] >= k) sub.push_back(gc[i]);
+        const int m = (int)sub.size();
+        e = launch_local_apply_grouped(s, sub.data(), m, k == 1);
+        if (e == hipSuccess) e = launch_nonlocal_grouped(s, sub.data(), m);
+        if (e == hipSuccess) e = launch_pcg_update_grouped(s, sub.data(), m);
+    }
+    return e;
+}
+
+// The outer loop of run_cells with the cells in lockstep: every outer
+// iteration, the source problems of all cells still iterating run as
+// grouped launches on the first such cell's stream (ordered against each
+// cell's own stream by events), then each cell's Rayleigh-Ritz, residuals
+// and shift run on its own stream as before, side by side.  The host takes
+// the same decisions as run_cells, from the same device values, for all
+// cells at once; each cell's device work is exactly that of its lone run.
+int32_t run_cells_grouped(std::vector<CellRun> &cells)
+{
+    const int n = (int)cells.size();
+    // host copies of the descriptors, then per cell: sigma, conv, band flags
+    auto block = [](const CellRun &c) { return sizeof(double) + (sizeof(int32_t) * (2 + c.nb) + 7) / 8 * 8; };
+    size_t bytes = sizeof(GroupCellDesc) * n;
+    for (const CellRun &c : cells) bytes += block(c);
+    PinnedHost host;
+    PARO_HIP_TRY(hipHostMalloc(&host.p, bytes, hipHostMallocDefault));
+    GroupCellDesc *hdesc = static_cast<GroupCellDesc *>(host.p);
+    char *q = static_cast<char *>(host.p) + sizeof(GroupCellDesc) * n;
+    for (CellRun &c : cells) {
+        c.scur = reinterpret_cast<double *>(q);
+        c.hconv = reinterpret_cast<int32_t *>(q + sizeof(double));
+        c.hflags = c.hconv + 2;
+        q += block(c);
+    }
+    EventSet events;
+    events.ev.assign(n + 1, nullptr);
+    for (int i = 0; i <= n; ++i) PARO_HIP_TRY(hipEventCreateWithFlags(&events.ev[i], hipEventDisableTiming));
+    hipEvent_t gev = events.ev[n];
+    std::vector<GroupCell> gc(n);
+    std::vector<int> ncg(n);
+    for (int i = 0; i < n; ++i) {
+        CellRun &c = cells[i];
+        const Plan &pl = *c.pl;
+        Workspace &w = c.w;
+        const int64_t lv = pl.ldv;
+        const bool mparo = c.o.variant != PARO_VARIANT_PARO;
+        double2 *Ut = mparo ? w.U + (size_t)c.nb * lv : w.U;
+        GroupCellDesc &d = hdesc[i];
+        std::memset(&d, 0, sizeof(d));
+        const int npq = describe_local_apply(pl, w, c.nb, w.sig_all, d);
+        describe_nonlocal(pl, w, c.nb, d);
+        describe_pcg(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, Ut, lv, w.iflags + c.nb, mparo, npq, d);
+        PARO_HIP_TRY(hipMemcpyAsync(w.desc, &d, sizeof(d), hipMemcpyHostToDevice, pl.stream));
+        gc[i] = GroupCell{&pl, &w, c.nb, (c.nb + kMaxBandsPerChunk - 1) / kMaxBandsPerChunk, w.desc, &d};
+        ncg[i] = c.o.n_cg;
+        if (c.o.initial_rr) {
+            PARO_CHECK_LAUNCH(launch_copy_bands(pl.stream, c.nb, pl.ng, c.psi, c.ld, w.U, lv));
+            PARO_CHECK_LAUNCH(apply_full(pl, w, c.nb, w.U, lv, w.W, nullptr));
+            PARO_CHECK_LAUNCH(rayleigh_ritz(pl, w, c.nb, c.nb, w.U, w.W, lv, c.eps, c.psi, c.hpsi, c.ld));
+        }
+        PARO_CHECK_LAUNCH(launch_residuals(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.res));
+        PARO_CHECK_LAUNCH(launch_bookkeeping(pl, c.nb, c.o, c.eps, w.res, w.sig_all, c.sigma, c.stats, c.conv));
+    }
+    std::vector<int> iter(n, 0);
+    std::vector<char> done(n, 0);
+    std::vector<GroupCell> agc;
+    std::vector<int> ancg, act;
+    for (;;) {
+        // step 5 of the previous iteration: which cells go on
+        bool wait = false;
+        for (int i = 0; i < n; ++i) {
+            CellRun &c = cells[i];
+            if (done[i]) continue;
+            if (iter[i] >= c.o.n_outer) {
+                done[i] = 1;
+            } else if (c.o.tol_res > 0.0) {
+                PARO_HIP_TRY(hipMemcpyAsync(c.hconv, c.conv, sizeof(int32_t), hipMemcpyDeviceToHost, c.pl->stream));
+                PARO_HIP_TRY(hipEventRecord(events.ev[i], c.pl->stream));
+                wait = true;
+            }
+        }
+        if (wait)
+            for (int i = 0; i < n; ++i)
+                if (!done[i] && cells[i].o.tol_res > 0.0) {
+                    PARO_HIP_TRY(hipEventSynchronize(events.ev[i]));
+                    if (*cells[i].hconv) done[i] = 1;
+                }
+        act.clear();
+        for (int i = 0; i < n; ++i)
+            if (!done[i]) act.push_back(i);
+        if (act.empty()) break;
+        // the grouped source problems, after each cell's own work so far
+        hipStream_t gs = cells[act[0]].pl->stream;
+        agc.clear();
+        ancg.clear();
+        for (int i : act) {
+            PARO_HIP_TRY(hipEventRecord(events.ev[i], cells[i].pl->stream));
+            PARO_HIP_TRY(hipStreamWaitEvent(gs, events.ev[i], 0));
+            agc.push_back(gc[i]);
+            ancg.push_back(ncg[i]);
+        }
+        PARO_CHECK_LAUNCH(source_solve_grouped(gs, agc, ancg));
+        PARO_HIP_TRY(hipEventRecord(gev, gs));
+        bool adaptive = false;
+        for (int i : act) {
+            CellRun &c = cells[i];
+            PARO_HIP_TRY(hipStreamWaitEvent(c.pl->stream, gev, 0));
+            if (c.o.shift_mode == PARO_SHIFT_ADAPTIVE) {
+                PARO_HIP_TRY(hipMemcpyAsync(c.hflags, c.w.iflags + c.nb, sizeof(int32_t) * c.nb,
+                                            hipMemcpyDeviceToHost, c.pl->stream));
+                PARO_HIP_TRY(hipMemcpyAsync(c.scur, c.sigma, sizeof(double), hipMemcpyDeviceToHost, c.pl->stream));
+                PARO_HIP_TRY(hipEventRecord(events.ev[i], c.pl->stream));
+                adaptive = true;
+            }
+        }
+        for (int i : act) {
+            CellRun &c = cells[i];
+            if (adaptive && c.o.shift_mode == PARO_SHIFT_ADAPTIVE) {
+                PARO_HIP_TRY(hipEventSynchronize(events.ev[i]));
+                bool neg = false;
+                for (int b = 0; b < c.nb; ++b) neg = neg || (c.hflags[b] & PARO_F_NEGCURV);
+                if (neg && *c.scur != c.o.sigma_lb) {
+                    // negative curvature: the cell solves again alone with sigma_lb, as in run_cells
+                    paro_iter_opts fixed = c.o;
+                    fixed.shift_mode = PARO_SHIFT_FIXED;
+                    fixed.tol_res = 0.0;
+                    PARO_CHECK_LAUNCH(launch_bookkeeping(*c.pl, c.nb, fixed, c.eps, c.w.res, c.w.sig_all, c.sigma,
+                                                         nullptr, c.conv));
+                    PARO_CHECK_LAUNCH(enqueue_solve(c));
+                }
+            }
+            PARO_CHECK_LAUNCH(enqueue_finish(c, iter[i]));
+            if (c.n_done) *c.n_done = iter[i] + 1;
+            ++iter[i];
+        }
+    }
+    // the pinned descriptors may still be read by copies in flight
+    for (const CellRun &c : cells) PARO_HIP_TRY(hipStreamSynchronize(c.pl->stream));
+    return PARO_OK;
+}
+
 }  // namespace
 
 int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi, double *hpsi, int64_t ld, double *eps, double *sigma,
@@ -693,7 +861,7 @@ int32_t paro_iterate_batch(int32_t n_cells, const paro_plan *plans, const int32_
             return rc;
         }
     }
-    return run_cells(cells);
+    return groupable(cells) ? run_cells_grouped(cells) : run_cells(cells);
 }
 
 int32_t paro_zgemm_hn(paro_stream_t s, int32_t M, int32_t N, int64_t K, const double *A, int64_t lda,

@@ -3,6 +3,7 @@
 // of Algorithm 2.  Every reduction goes through per-work-group partial sums
 // that the consumer adds in a fixed order, so runs are bitwise reproducible.
 #include "fft_device.h"
+#include "group.h"
 #include "paro_internal.h"
 #include "reduce_device.h"
 
@@ -28,15 +29,15 @@ __device__ __forceinline__ double teter(double x)
 }
 
 // partial sums of <psi|T|psi> and <psi|psi>
-__global__ void __launch_bounds__(kVecThreads)
-k_pcg_init_parts(int64_t ng, const double2 *__restrict__ psi, int64_t ld, const double *__restrict__ kin,
-                 double *__restrict__ dots, int nb)
+__device__ __forceinline__ void pcg_init_parts_body(int bx, int by, int64_t ng, const double2 *__restrict__ psi,
+                                                    int64_t ld, const double *__restrict__ kin,
+                                                    double *__restrict__ dots, int nb)
 {
     __shared__ double red[kVecThreads / 64];
-    const int band = blockIdx.y;
+    const int band = by;
     const double2 *x = psi + band * ld;
     double tk = 0.0, nr = 0.0;
-    const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t g0 = (int64_t)bx * kVecChunk;
     const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
     for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
         const double2 v = x[g];
@@ -47,9 +48,22 @@ k_pcg_init_parts(int64_t ng, const double2 *__restrict__ psi, int64_t ld, const 
     tk = block_sum<kVecThreads>(tk, red);
     nr = block_sum<kVecThreads>(nr, red);
     if (threadIdx.x == 0) {
-        dots[((size_t)DOT_TKIN * nb + band) * kMaxParts + blockIdx.x] = tk;
-        dots[((size_t)DOT_NRM * nb + band) * kMaxParts + blockIdx.x] = nr;
+        dots[((size_t)DOT_TKIN * nb + band) * kMaxParts + bx] = tk;
+        dots[((size_t)DOT_NRM * nb + band) * kMaxParts + bx] = nr;
     }
+}
+__global__ void __launch_bounds__(kVecThreads)
+k_pcg_init_parts(int64_t ng, const double2 *__restrict__ psi, int64_t ld, const double *__restrict__ kin,
+                 double *__restrict__ dots, int nb)
+{
+    pcg_init_parts_body(blockIdx.x, blockIdx.y, ng, psi, ld, kin, dots, nb);
+}
+__global__ void __launch_bounds__(kVecThreads) k_pcg_init_parts_grp(GroupTab t)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const PcgInitPartsArgs &a = *static_cast<const PcgInitPartsArgs *>(t.args[e]);
+    pcg_init_parts_body(bx, by, a.ng, a.psi, a.ld, a.kin, a.dots, a.nb);
 }
 
 // u = psi (correction: u = 0, the iterate is then e = u - psi of the
@@ -58,24 +72,25 @@ k_pcg_init_parts(int64_t ng, const double2 *__restrict__ psi, int64_t ld, const 
 // vectors are stored as CV (double2, or float2 in the mixed-precision
 // solve) and u as CU.
 template <class CV, class CU>
-__global__ void __launch_bounds__(kVecThreads)
-k_pcg_init(int64_t ng, int nparts, const double2 *__restrict__ psi, const double2 *__restrict__ hpsi, int64_t ld,
-           const double *__restrict__ eps, const double *__restrict__ kin, CU *__restrict__ u, int64_t ldu,
-           CV *__restrict__ r, CV *__restrict__ z, int64_t ldv, double *__restrict__ dots,
-           double *__restrict__ sc, int nb, int correction)
+__device__ __forceinline__ void pcg_init_body(int bx, int by, int64_t ng, int nparts, const double2 *__restrict__ psi,
+                                              const double2 *__restrict__ hpsi, int64_t ld,
+                                              const double *__restrict__ eps, const double *__restrict__ kin,
+                                              CU *__restrict__ u, int64_t ldu, CV *__restrict__ r,
+                                              CV *__restrict__ z, int64_t ldv, double *__restrict__ dots,
+                                              double *__restrict__ sc, int nb, int correction)
 {
     __shared__ double red[kVecThreads / 64];
-    const int band = blockIdx.y;
+    const int band = by;
     const double tk = sum_parts(dots + ((size_t)DOT_TKIN * nb + band) * kMaxParts, nparts);
     const double nr = sum_parts(dots + ((size_t)DOT_NRM * nb + band) * kMaxParts, nparts);
     const double tau = tk / nr;
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc[SC_TAU * nb + band] = tau;
+    if (bx == 0 && threadIdx.x == 0) sc[SC_TAU * nb + band] = tau;
     const double e = eps[band];
     const double2 *x = psi + band * ld, *hx = hpsi + band * ld;
     CU *uu = u + band * ldu;
     CV *rr = r + band * ldv, *zz = z + band * ldv;
     double rz = 0.0;
-    const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t g0 = (int64_t)bx * kVecChunk;
     const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
     for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
         const double2 v = x[g], hv = hx[g];
@@ -88,20 +103,39 @@ k_pcg_init(int64_t ng, int nparts, const double2 *__restrict__ psi, const double
         rz += (double)rv.x * (double)zv.x + (double)rv.y * (double)zv.y;
     }
     rz = block_sum<kVecThreads>(rz, red);
-    if (threadIdx.x == 0) dots[((size_t)DOT_RZ * nb + band) * kMaxParts + blockIdx.x] = rz;
+    if (threadIdx.x == 0) dots[((size_t)DOT_RZ * nb + band) * kMaxParts + bx] = rz;
+}
+template <class CV, class CU>
+__global__ void __launch_bounds__(kVecThreads)
+k_pcg_init(int64_t ng, int nparts, const double2 *__restrict__ psi, const double2 *__restrict__ hpsi, int64_t ld,
+           const double *__restrict__ eps, const double *__restrict__ kin, CU *__restrict__ u, int64_t ldu,
+           CV *__restrict__ r, CV *__restrict__ z, int64_t ldv, double *__restrict__ dots,
+           double *__restrict__ sc, int nb, int correction)
+{
+    pcg_init_body<CV, CU>(blockIdx.x, blockIdx.y, ng, nparts, psi, hpsi, ld, eps, kin, u, ldu, r, z, ldv, dots, sc,
+                          nb, correction);
+}
+template <class CV, class CU> __global__ void __launch_bounds__(kVecThreads) k_pcg_init_grp(GroupTab t)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const PcgInitArgs<CV, CU> &a = *static_cast<const PcgInitArgs<CV, CU> *>(t.args[e]);
+    pcg_init_body<CV, CU>(bx, by, a.ng, a.nparts, a.psi, a.hpsi, a.ld, a.eps, a.kin, a.u, a.ldu, a.r, a.z, a.ldv,
+                          a.dots, a.sc, a.nb, a.correction);
 }
 
 // alpha = gamma / p^H q; u += alpha p; r -= alpha q; z = K r; partial r^H z
 // (FP64 arithmetic on CV / CU storage).
 template <class CV, class CU>
-__global__ void __launch_bounds__(kVecThreads)
-k_pcg_update(int64_t ng, int npq, const CV *__restrict__ p, const CV *__restrict__ q, int64_t ldv,
-             CU *__restrict__ u, int64_t ldu, CV *__restrict__ r, CV *__restrict__ z,
-             const double *__restrict__ kin, const double *__restrict__ dots_pq, double *__restrict__ dots_rz,
-             const double *__restrict__ sc, const int32_t *__restrict__ active, int nb)
+__device__ __forceinline__ void pcg_update_body(int bx, int by, int64_t ng, int npq, const CV *__restrict__ p,
+                                                const CV *__restrict__ q, int64_t ldv, CU *__restrict__ u,
+                                                int64_t ldu, CV *__restrict__ r, CV *__restrict__ z,
+                                                const double *__restrict__ kin, const double *__restrict__ dots_pq,
+                                                double *__restrict__ dots_rz, const double *__restrict__ sc,
+                                                const int32_t *__restrict__ active, int nb)
 {
     __shared__ double red[kVecThreads / 64];
-    const int band = blockIdx.y;
+    const int band = by;
     const double pq = sum_parts(dots_pq + (size_t)band * kMaxParts, npq) + sc[SC_NLQ * nb + band];
     const bool go = active[band] && pq > 0.0;
     double rz = 0.0;
@@ -111,7 +145,7 @@ k_pcg_update(int64_t ng, int npq, const CV *__restrict__ p, const CV *__restrict
         const CV *pp = p + band * ldv, *qq = q + band * ldv;
         CU *uu = u + band * ldu;
         CV *rr = r + band * ldv, *zz = z + band * ldv;
-        const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+        const int64_t g0 = (int64_t)bx * kVecChunk;
         const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
         for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
             const CV pv = pp[g], qv = qq[g];
@@ -128,7 +162,25 @@ k_pcg_update(int64_t ng, int npq, const CV *__restrict__ p, const CV *__restrict
         }
     }
     rz = block_sum<kVecThreads>(rz, red);
-    if (threadIdx.x == 0) dots_rz[(size_t)band * kMaxParts + blockIdx.x] = rz;
+    if (threadIdx.x == 0) dots_rz[(size_t)band * kMaxParts + bx] = rz;
+}
+template <class CV, class CU>
+__global__ void __launch_bounds__(kVecThreads)
+k_pcg_update(int64_t ng, int npq, const CV *__restrict__ p, const CV *__restrict__ q, int64_t ldv,
+             CU *__restrict__ u, int64_t ldu, CV *__restrict__ r, CV *__restrict__ z,
+             const double *__restrict__ kin, const double *__restrict__ dots_pq, double *__restrict__ dots_rz,
+             const double *__restrict__ sc, const int32_t *__restrict__ active, int nb)
+{
+    pcg_update_body<CV, CU>(blockIdx.x, blockIdx.y, ng, npq, p, q, ldv, u, ldu, r, z, kin, dots_pq, dots_rz, sc,
+                            active, nb);
+}
+template <class CV, class CU> __global__ void __launch_bounds__(kVecThreads) k_pcg_update_grp(GroupTab t)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const PcgUpdateArgs<CV, CU> &a = *static_cast<const PcgUpdateArgs<CV, CU> *>(t.args[e]);
+    pcg_update_body<CV, CU>(bx, by, a.ng, a.npq, a.p, a.q, a.ldv, a.u, a.ldu, a.r, a.z, a.kin, a.dots_pq,
+                            a.dots_rz, a.sc, a.active, a.nb);
 }
 
 // u_b = base_b + d_b (base != null) or u_b = d_b, in FP64
@@ -228,10 +280,11 @@ k_proj_sub(int64_t ng, int nparts, const double2 *__restrict__ psi, int64_t ld, 
 // stage 0 (after init): gamma = gamma0 = r^H z; active = gamma0 > 0.
 // stage 1 (after an update): stop on p^H q <= 0 (flag NEGCURV, or NAN), else
 //   gamma' = r^H z; stop when gamma' <= 1e-26 gamma0, else beta = gamma'/gamma.
-__global__ void __launch_bounds__(kVecThreads)
-k_pcg_scalars(int nb, int stage, int nparts_rz, int npq, const double *__restrict__ dots_pq,
-              const double *__restrict__ dots_rz, double *__restrict__ sc, int32_t *__restrict__ active,
-              int32_t *__restrict__ bflags, int32_t *__restrict__ band_flags_out, int32_t *__restrict__ status)
+__device__ __forceinline__ void pcg_scalars_body(int nb, int stage, int nparts_rz, int npq,
+                                                 const double *__restrict__ dots_pq,
+                                                 const double *__restrict__ dots_rz, double *__restrict__ sc,
+                                                 int32_t *__restrict__ active, int32_t *__restrict__ bflags,
+                                                 int32_t *__restrict__ band_flags_out, int32_t *__restrict__ status)
 {
     for (int b = threadIdx.x; b < nb; b += kVecThreads) {
         const double rz = sum_parts(dots_rz + (size_t)b * kMaxParts, nparts_rz);
@@ -265,6 +318,20 @@ k_pcg_scalars(int nb, int stage, int nparts_rz, int npq, const double *__restric
         }
         if (band_flags_out) band_flags_out[b] = bflags[b];
     }
+}
+__global__ void __launch_bounds__(kVecThreads)
+k_pcg_scalars(int nb, int stage, int nparts_rz, int npq, const double *__restrict__ dots_pq,
+              const double *__restrict__ dots_rz, double *__restrict__ sc, int32_t *__restrict__ active,
+              int32_t *__restrict__ bflags, int32_t *__restrict__ band_flags_out, int32_t *__restrict__ status)
+{
+    pcg_scalars_body(nb, stage, nparts_rz, npq, dots_pq, dots_rz, sc, active, bflags, band_flags_out, status);
+}
+// one work-group per entry
+__global__ void __launch_bounds__(kVecThreads) k_pcg_scalars_grp(GroupTab t, int stage)
+{
+    const PcgScalarsArgs &a = *static_cast<const PcgScalarsArgs *>(t.args[blockIdx.x]);
+    pcg_scalars_body(a.nb, stage, a.nparts_rz, a.npq, a.dots_pq, a.dots_rz, a.sc, a.active, a.bflags,
+                     a.band_flags_out, a.status);
 }
 
 // partial sums of |hpsi - eps psi|^2
@@ -462,6 +529,95 @@ hipError_t launch_copy_bands(hipStream_t s, int nb, int64_t ng, const double2 *s
 {
     if (nb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy_bands, dim3(nchunks(ng), nb), dim3(kVecThreads), 0, s, ng, src, lds, dst, ldd);
+    return hipGetLastError();
+}
+
+}  // namespace paro
+
+namespace paro {
+
+// ---------------------------------------------------------------- grouped launches
+// The PCG kernels of the FP64 source solve for many cells at once: the
+// arguments each cell's own launches take (launch_pcg_init and
+// launch_pcg_update without projection), in its descriptor.
+void describe_pcg(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi, int64_t ld,
+                  const double *eps, double2 *u, int64_t ldu, int32_t *band_flags, bool correction, int npq,
+                  GroupCellDesc &d)
+{
+    const int nc = (int)nchunks(pl.ng);
+    d.iparts = PcgInitPartsArgs{psi, ld, pl.kin, w.dots, pl.ng, nb};
+    d.init = PcgInitArgs<double2, double2>{psi, hpsi, ld, eps, pl.kin, u, ldu, w.r, w.z, pl.ldv, w.dots, w.sc,
+                                           pl.ng, nc, nb, correction ? 1 : 0};
+    d.sc0 = PcgScalarsArgs{nullptr, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags, w.iflags + nb,
+                           band_flags, pl.status, nb, nc, 0};
+    d.sc1 = PcgScalarsArgs{w.dots + (size_t)DOT_PQ * nb * kMaxParts, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc,
+                           w.iflags, w.iflags + nb, band_flags, pl.status, nb, nc, npq};
+    d.upd = PcgUpdateArgs<double2, double2>{w.p, w.q, pl.ldv, u, ldu, w.r, w.z, pl.kin,
+                                            w.dots + (size_t)DOT_PQ * nb * kMaxParts,
+                                            w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags, pl.ng, npq, nb};
+}
+
+namespace {
+
+// entries of a (chunk x band) vector kernel; launches every kGroupMax entries
+template <class F, class G>
+hipError_t group_vec(hipStream_t s, const GroupCell *cells, int n, F args_of, G launch)
+{
+    GroupBuilder g;
+    for (int i = 0; i < n; ++i) {
+        const int nc = (int)nchunks(cells[i].pl->ng);
+        g.add(args_of(cells[i].dev), (int64_t)nc * cells[i].nb, nc);
+        if (g.full() || i == n - 1) {
+            launch(g);
+            g = GroupBuilder();
+        }
+    }
+    return hipGetLastError();
+}
+template <class F>
+void group_scalars(hipStream_t s, const GroupCell *cells, int n, F args_of, int stage)
+{
+    GroupBuilder g;
+    for (int i = 0; i < n; ++i) {
+        g.add(args_of(cells[i].dev), 1, 1);
+        if (g.full() || i == n - 1) {
+            hipLaunchKernelGGL(k_pcg_scalars_grp, dim3(g.t.n), dim3(kVecThreads), 0, s, g.t, stage);
+            g = GroupBuilder();
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_pcg_init_grouped(hipStream_t s, const GroupCell *cells, int n)
+{
+    if (n <= 0) return hipSuccess;
+    hipError_t e = group_vec(s, cells, n, [](const GroupCellDesc *d) { return (const void *)&d->iparts; },
+                             [&](const GroupBuilder &g) {
+                                 hipLaunchKernelGGL(k_pcg_init_parts_grp, dim3((unsigned)g.total), dim3(kVecThreads),
+                                                    0, s, g.t);
+                             });
+    if (e != hipSuccess) return e;
+    e = group_vec(s, cells, n, [](const GroupCellDesc *d) { return (const void *)&d->init; },
+                  [&](const GroupBuilder &g) {
+                      hipLaunchKernelGGL((k_pcg_init_grp<double2, double2>), dim3((unsigned)g.total),
+                                         dim3(kVecThreads), 0, s, g.t);
+                  });
+    if (e != hipSuccess) return e;
+    group_scalars(s, cells, n, [](const GroupCellDesc *d) { return (const void *)&d->sc0; }, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_pcg_update_grouped(hipStream_t s, const GroupCell *cells, int n)
+{
+    if (n <= 0) return hipSuccess;
+    hipError_t e = group_vec(s, cells, n, [](const GroupCellDesc *d) { return (const void *)&d->upd; },
+                             [&](const GroupBuilder &g) {
+                                 hipLaunchKernelGGL((k_pcg_update_grp<double2, double2>), dim3((unsigned)g.total),
+                                                    dim3(kVecThreads), 0, s, g.t);
+                             });
+    if (e != hipSuccess) return e;
+    group_scalars(s, cells, n, [](const GroupCellDesc *d) { return (const void *)&d->sc1; }, 1);
     return hipGetLastError();
 }
 

@@ -376,7 +376,7 @@ def iterate_batch(plans, psis, n_outer, n_cg, sigma_lbs, variant=L.VARIANT_PARO,
     """ParO outer iterations on many independent cells in one library call (paro_iterate_batch).
 
     plans[i] and psis[i] (its band-major complex128 block, updated in place) form cell i;
-    sigma_lbs[i] its shift bound; n_conv may be a list.  streams: torch streams (default
+    sigma_lbs[i] its shift bound; n_conv and n_cg may be lists.  streams: torch streams (default
     priority) the cells are spread over round-robin (None: one per cell, at most 8); the
     cells' work is ordered after the current stream's and the current stream waits for all of
     them at the end.  Returns a list of dict(psi, hpsi, eps, sigma, stats, n_done)."""
@@ -389,6 +389,7 @@ def iterate_batch(plans, psis, n_outer, n_cg, sigma_lbs, variant=L.VARIANT_PARO,
         streams = [torch.cuda.Stream(device=dev) for _ in range(min(n, 8))]
     out, opts = [], (L.IterOpts * n)()
     ncv = n_conv if isinstance(n_conv, (list, tuple)) else [n_conv] * n
+    ncgs = n_cg if isinstance(n_cg, (list, tuple)) else [n_cg] * n
     for i, (pl, psi) in enumerate(zip(plans, psis)):
         pl._check_block(psi)
         nb = psi.shape[0]
@@ -397,7 +398,7 @@ def iterate_batch(plans, psis, n_outer, n_cg, sigma_lbs, variant=L.VARIANT_PARO,
                         sigma=torch.zeros(1, dtype=torch.float64, device=dev),
                         stats=torch.full((n_outer + 1, 2 * nb + 2), float("nan"), dtype=torch.float64, device=dev)
                         if stats else None))
-        opts[i] = L.IterOpts(n_outer=int(n_outer), n_cg=int(n_cg), n_conv=int(ncv[i] or nb),
+        opts[i] = L.IterOpts(n_outer=int(n_outer), n_cg=int(ncgs[i]), n_conv=int(ncv[i] or nb),
                              shift_mode=int(shift_mode), variant=int(variant), initial_rr=1 if initial_rr else 0,
                              sigma_lb=float(sigma_lbs[i]), tol_res=float(tol_res), precision=int(precision))
     wss = [pl.workspace(psi.shape[0]) for pl, psi in zip(plans, psis)]

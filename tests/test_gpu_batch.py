@@ -1,7 +1,10 @@
 """Batched ParO (paro_iterate_batch) on cells of uneven grid, sphere and band
 count: every cell's result is bitwise the one paro_iterate gives for that
-cell alone (the same kernels in the same order on the cell's stream), and
-one cell is checked against the oracle's ParO histories.
+cell alone, and one cell is checked against the oracle's ParO histories.
+FP64 batches of Algorithm 1 or 2 run their source problems as grouped
+launches (one launch per kernel and FFT length for all cells, each cell's
+blocks computing exactly what its own launch computes); MParO II and mixed
+precision run cell by cell on the cells' streams.  Both paths are covered.
 """
 import numpy as np
 import pytest
@@ -79,6 +82,31 @@ def test_batch_is_bitwise_the_single_cell_runs(variant, shift_mode, tol, precisi
         assert torch.equal(g["stats"][:rows], r["stats"][:rows]), k
     if tol > 0:
         assert len({g["n_done"] for g in got}) > 1  # cells stopped at their own iteration
+    for _, _, _, pl, _ in cells:
+        assert pl.status() == 0
+
+
+def test_grouped_batch_many_cells_two_chunks_uneven_pcg_steps():
+    """More entries than one grouped launch takes (70 cells, so the tables
+    are split), a cell of 80 bands (two 64-band chunks of the stick and plane
+    stages), cells with and without projectors, and three PCG step counts:
+    every cell bitwise equal to its lone run."""
+    import paper_1702_04045_amd as P
+    torch = _torch()
+    specs = [synth.small_cell(a=6.0, ecut=4.0, grid=16, n_atoms=2, n_bands=3 + i % 4,
+                              projectors=(i % 3 != 0)) for i in range(69)]
+    specs.append(synth.small_cell(a=10.0, ecut=8.0, grid=32, n_atoms=3, n_bands=80))
+    cells = build(specs, seed0=70)
+    sig = [pl.shift_lower_bound() for _, _, _, pl, _ in cells]
+    ncg = [4 + i % 3 for i in range(len(cells))]
+    ref = [pl.iterate(to_dev(x), 3, k, s, shift_mode=P.SHIFT_ADAPTIVE)
+           for (sp, c, v, pl, x), s, k in zip(cells, sig, ncg)]
+    got = P.iterate_batch([c[3] for c in cells], [to_dev(c[4]) for c in cells], 3, ncg, sig,
+                          shift_mode=P.SHIFT_ADAPTIVE, streams=[torch.cuda.Stream() for _ in range(4)])
+    torch.cuda.synchronize()
+    for k, (r, g) in enumerate(zip(ref, got)):
+        assert torch.equal(g["psi"], r["psi"]) and torch.equal(g["eps"], r["eps"]), k
+        assert torch.equal(g["hpsi"], r["hpsi"]) and torch.equal(g["sigma"], r["sigma"]), k
     for _, _, _, pl, _ in cells:
         assert pl.status() == 0
 
