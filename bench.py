@@ -217,8 +217,8 @@ def batched_cells(args, P, torch, n_outer=5, n_cg=10, n_streams=8, reps=3):
     """The uneven 24-cell workload: n_outer ParO outer iterations (adaptive
     shift, initial Rayleigh-Ritz) of every cell from its trial block, once
     cell after cell with paro_iterate and once with paro_iterate_batch over
-    n_streams streams; best of reps, wall time between device
-    synchronisations."""
+    n_streams streams, in FP64 and in mixed precision; best of reps, wall
+    time between device synchronisations."""
     specs = synth.batch_specs(args.seed)
     plans, xs = [], []
     for i, sp in enumerate(specs):
@@ -230,13 +230,15 @@ def batched_cells(args, P, torch, n_outer=5, n_cg=10, n_streams=8, reps=3):
     sig = [pl.shift_lower_bound() for pl in plans]
     streams = [torch.cuda.Stream() for _ in range(n_streams)]
 
+    prec = [P.PREC_FP64]
+
     def sequential():
         for pl, x, s in zip(plans, xs, sig):
-            pl.iterate(x.clone(), n_outer, n_cg, s, shift_mode=P.SHIFT_ADAPTIVE, stats=False)
+            pl.iterate(x.clone(), n_outer, n_cg, s, shift_mode=P.SHIFT_ADAPTIVE, stats=False, precision=prec[0])
 
     def batch():
         P.iterate_batch(plans, [x.clone() for x in xs], n_outer, n_cg, sig, shift_mode=P.SHIFT_ADAPTIVE,
-                        streams=streams)
+                        streams=streams, precision=prec[0])
 
     def best(f):
         f()
@@ -250,13 +252,19 @@ def batched_cells(args, P, torch, n_outer=5, n_cg=10, n_streams=8, reps=3):
         return min(ts)
 
     t_seq, t_bat = best(sequential), best(batch)
+    prec[0] = P.PREC_MIXED
+    m_seq, m_bat = best(sequential), best(batch)
     applies = sum(x.shape[0] for x in xs) * (n_cg + 1) * n_outer
     return {"cells": len(specs), "grids": sorted({sp.grid for sp in specs}),
             "bands": [sp.n_bands for sp in specs], "plane_waves": [pl.ng for pl in plans],
             "projectors": [pl.n_proj for pl in plans], "outer_iterations_per_cell": n_outer, "pcg_steps": n_cg,
             "streams": n_streams, "seconds": t_bat, "cell_iterations_per_s": len(specs) * n_outer / t_bat,
             "band_applies_per_s": applies / t_bat, "sequential_seconds": t_seq,
-            "speedup_vs_sequential": t_seq / t_bat, "dtype": "f64"}
+            "speedup_vs_sequential": t_seq / t_bat, "dtype": "f64",
+            "mixed": {"seconds": m_bat, "cell_iterations_per_s": len(specs) * n_outer / m_bat,
+                      "sequential_seconds": m_seq, "speedup_vs_sequential": m_seq / m_bat,
+                      "speedup_vs_fp64_batch": t_bat / m_bat,
+                      "dtype": "f32 source problems, f64 H U and Rayleigh-Ritz"}}
 
 
 def at_scale(args, P, torch, steps=3, tta=False, tta_seconds=600.0):

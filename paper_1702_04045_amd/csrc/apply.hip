@@ -1006,14 +1006,22 @@ int describe_local_apply(const Plan &pl, const Workspace &w, int nb, const doubl
     const double scale = 1.0 / ((double)pl.grid[0] * pl.grid[1] * pl.grid[2]);
     const double *beta = w.sc + SC_BETA * nb;
     double *pq_parts = w.dots + (size_t)DOT_PQ * nb * kMaxParts;
+    float2 *sticks32 = reinterpret_cast<float2 *>(w.sticks);
     for (int c = 0, c0 = 0; c0 < nb; ++c, c0 += kMaxBandsPerChunk) {
         const int cb = std::min(kMaxBandsPerChunk, nb - c0);
-        d.sinv[c] = StickInvArgs<double2>{w.z + c0 * pl.ldv, pl.ldv, w.p + c0 * pl.ldv, beta + c0, w.sticks,
-                                          pl.st_start, pl.pt_sz, pl.tw[2], pl.nst};
-        d.plane[c] = PlaneArgs<double2>{w.sticks, pl.cols, pl.vplane, pl.tw[0], pl.nst, N3, cb, pl.nmax[0]};
-        d.sfwd[c] = StickFwdArgs<double2>{w.sticks, pl.st_start, pl.pt_sz, pl.tw[2], w.p + c0 * pl.ldv, pl.ldv,
-                                          w.q + c0 * pl.ldv, pl.kin, shift ? shift + c0 : nullptr, scale,
-                                          pq_parts + (size_t)c0 * kMaxParts, pl.nst, kMaxParts};
+        const int64_t o = (int64_t)c0 * pl.ldv;
+        const double *sh = shift ? shift + c0 : nullptr;
+        double *dp = pq_parts + (size_t)c0 * kMaxParts;
+        d.f64.sinv[c] = StickInvArgs<double2>{w.z + o, pl.ldv, w.p + o, beta + c0, w.sticks, pl.st_start, pl.pt_sz,
+                                              pl.tw[2], pl.nst};
+        d.f64.plane[c] = PlaneArgs<double2>{w.sticks, pl.cols, pl.vplane, pl.tw[0], pl.nst, N3, cb, pl.nmax[0]};
+        d.f64.sfwd[c] = StickFwdArgs<double2>{w.sticks, pl.st_start, pl.pt_sz, pl.tw[2], w.p + o, pl.ldv, w.q + o,
+                                              pl.kin, sh, scale, dp, pl.nst, kMaxParts};
+        d.f32.sinv[c] = StickInvArgs<float2>{w.z32 + o, pl.ldv, w.p32 + o, beta + c0, sticks32, pl.st_start,
+                                             pl.pt_sz, pl.tw32[2], pl.nst};
+        d.f32.plane[c] = PlaneArgs<float2>{sticks32, pl.cols, pl.vplane32, pl.tw32[0], pl.nst, N3, cb, pl.nmax[0]};
+        d.f32.sfwd[c] = StickFwdArgs<float2>{sticks32, pl.st_start, pl.pt_sz, pl.tw32[2], w.p32 + o, pl.ldv,
+                                             w.q32 + o, pl.kin, sh, scale, dp, pl.nst, kMaxParts};
     }
     switch (pl.grid[0]) {
 #define PARO_CASE(n) \
@@ -1030,10 +1038,10 @@ bool grouped_grid(int n) { return fft_supported(n) && !big_grid(n); }
 
 namespace {
 
-template <int N>
+template <int N, class C2>
 hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool first)
 {
-    constexpr int NT = stick_threads<N, double2>();
+    constexpr int NT = stick_threads<N, C2>();
     constexpr int S = NT / FftCfg<N>::T;
     int rounds = 0;
     for (int i = 0; i < n; ++i)
@@ -1046,12 +1054,11 @@ hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool fi
                 if (g.t.n == 0) return;
                 const dim3 grid((unsigned)g.total);
                 if (k == 0)
-                    hipLaunchKernelGGL((k_stick_inv_grp<N, double2>), grid, dim3(NT), 0, s, g.t, first ? 1 : 0);
+                    hipLaunchKernelGGL((k_stick_inv_grp<N, C2>), grid, dim3(NT), 0, s, g.t, first ? 1 : 0);
                 else if (k == 1)
-                    hipLaunchKernelGGL((k_plane_grp<N, double2>), grid, dim3(plane_threads<N, double2>()), 0, s,
-                                       g.t);
+                    hipLaunchKernelGGL((k_plane_grp<N, C2>), grid, dim3(plane_threads<N, C2>()), 0, s, g.t);
                 else
-                    hipLaunchKernelGGL((k_stick_fwd_grp<N, double2>), grid, dim3(NT), 0, s, g.t);
+                    hipLaunchKernelGGL((k_stick_fwd_grp<N, C2>), grid, dim3(NT), 0, s, g.t);
                 g = GroupBuilder();
             };
             for (int i = 0; i < n; ++i) {
@@ -1059,10 +1066,12 @@ hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool fi
                 if (c.pl->grid[0] != N || c.nchunk <= r) continue;
                 const int cb = std::min(kMaxBandsPerChunk, c.nb - r * kMaxBandsPerChunk);
                 const int ntiles = (c.pl->nst + S - 1) / S;
-                if (k == 0) g.add(&c.dev->sinv[r], (int64_t)ntiles * cb, ntiles);
-                else if (k == 1) g.add(&c.dev->plane[r], (int64_t)c.pl->grid[2] * ((cb + kBandsPerBlock - 1) / kBandsPerBlock),
-                                       c.pl->grid[2]);
-                else g.add(&c.dev->sfwd[r], (int64_t)ntiles * cb, ntiles);
+                const GroupSolveArgs<C2> *a = group_solve_args<C2>(c.dev);
+                if (k == 0) g.add(&a->sinv[r], (int64_t)ntiles * cb, ntiles);
+                else if (k == 1)
+                    g.add(&a->plane[r], (int64_t)c.pl->grid[2] * ((cb + kBandsPerBlock - 1) / kBandsPerBlock),
+                          c.pl->grid[2]);
+                else g.add(&a->sfwd[r], (int64_t)ntiles * cb, ntiles);
                 if (g.full()) flush();
             }
             flush();
@@ -1073,15 +1082,17 @@ hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool fi
 
 }  // namespace
 
-hipError_t launch_local_apply_grouped(hipStream_t s, const GroupCell *cells, int n, bool first)
+template <class C2> hipError_t launch_local_apply_grouped(hipStream_t s, const GroupCell *cells, int n, bool first)
 {
     hipError_t e = hipSuccess;
 #define PARO_CASE(k) \
-    if (e == hipSuccess) e = grouped_local_n<k>(s, cells, n, first);
+    if (e == hipSuccess) e = grouped_local_n<k, C2>(s, cells, n, first);
     PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
     PARO_CASE(80) PARO_CASE(96)
 #undef PARO_CASE
     return e;
 }
+template hipError_t launch_local_apply_grouped<double2>(hipStream_t, const GroupCell *, int, bool);
+template hipError_t launch_local_apply_grouped<float2>(hipStream_t, const GroupCell *, int, bool);
 
 }  // namespace paro

@@ -717,19 +717,27 @@ namespace paro {
 // The nonlocal part of the source solve's (H - sigma) p for many cells: the
 // arguments gemm_hn (P = B^H p, times the KB energies, p^H V_NL p into the
 // PCG scalars) and gemm_nn (q += B P) give their kernels.
-void describe_nonlocal(const Plan &pl, const Workspace &w, int nb, GroupCellDesc &d)
+template <class C2>
+static void describe_nonlocal_t(const Plan &pl, const Workspace &w, int nb, const C2 *beta, const C2 *p, C2 *q,
+                                GroupSolveArgs<C2> &d)
 {
     const int M = pl.nproj, N = nb;
     int64_t nsplit = 0, kchunk = 0, units = 0;
-    if (M > 0) hn_split<double2>(M, N, pl.ng, w.part_elems, &nsplit, &kchunk, &units);
-    d.hn = GemmHnArgs<double2>{pl.beta, pl.ldv, w.p, pl.ldv, w.part, pl.ng, kchunk, units, M, N, (M + 31) / 32,
-                               (N + 31) / 32};
-    d.hred = GemmHnRedArgs<double2>{w.part, w.P, M, pl.dkb, w.sc + SC_NLQ * nb, M, N, (int)nsplit};
+    if (M > 0) hn_split<C2>(M, N, pl.ng, w.part_elems, &nsplit, &kchunk, &units);
+    C2 *P = reinterpret_cast<C2 *>(w.P);
+    d.hn = GemmHnArgs<C2>{beta, pl.ldv, p, pl.ldv, w.part, pl.ng, kchunk, units, M, N, (M + 31) / 32, (N + 31) / 32};
+    d.hred = GemmHnRedArgs<C2>{w.part, P, M, pl.dkb, w.sc + SC_NLQ * nb, M, N, (int)nsplit};
     const int bn = (N + 31) / 32;
-    d.nn = GemmNnArgs<double2>{pl.beta, pl.ldv, w.P, M, w.q, pl.ldv, pl.ng, (pl.ng + 31) / 32 * bn, N, M, bn, 1};
+    d.nn = GemmNnArgs<C2>{beta, pl.ldv, P, M, q, pl.ldv, pl.ng, (pl.ng + 31) / 32 * bn, N, M, bn, 1};
 }
 
-hipError_t launch_nonlocal_grouped(hipStream_t s, const GroupCell *cells, int n)
+void describe_nonlocal(const Plan &pl, const Workspace &w, int nb, GroupCellDesc &d)
+{
+    describe_nonlocal_t<double2>(pl, w, nb, pl.beta, w.p, w.q, d.f64);
+    describe_nonlocal_t<float2>(pl, w, nb, pl.beta32, w.p32, w.q32, d.f32);
+}
+
+template <class C2> hipError_t launch_nonlocal_grouped(hipStream_t s, const GroupCell *cells, int n)
 {
     // cells with projectors, in groups of kGroupMax
     for (int i0 = 0; i0 < n;) {
@@ -738,19 +746,22 @@ hipError_t launch_nonlocal_grouped(hipStream_t s, const GroupCell *cells, int n)
         for (; i < n && !hn.full(); ++i) {
             const GroupCell &c = cells[i];
             if (c.pl->nproj == 0) continue;
-            hn.add(&c.dev->hn, c.host->hn.units, 1);
-            red.add(&c.dev->hred, c.nb, c.nb);
-            nn.add(&c.dev->nn, c.host->nn.units, 1);
+            const GroupSolveArgs<C2> *a = group_solve_args<C2>(c.dev), *h = group_solve_args<C2>(c.host);
+            hn.add(&a->hn, h->hn.units, 1);
+            red.add(&a->hred, c.nb, c.nb);
+            nn.add(&a->nn, h->nn.units, 1);
         }
         i0 = i;
         if (hn.t.n == 0) continue;
-        const unsigned whn = (unsigned)std::min<int64_t>((hn.total + 3) / 4, HnCfg<double2>::slots / 4);
-        const unsigned wnn = (unsigned)std::min<int64_t>((nn.total + 3) / 4, NnCfg<double2>::slots / 4);
-        hipLaunchKernelGGL((k_gemm_hn_part_grp<double2>), dim3(whn), dim3(256), 0, s, hn.t);
-        hipLaunchKernelGGL((k_gemm_hn_reduce_grp<double2>), dim3((unsigned)red.total), dim3(256), 0, s, red.t);
-        hipLaunchKernelGGL((k_gemm_nn_grp<double2>), dim3(wnn), dim3(256), 0, s, nn.t);
+        const unsigned whn = (unsigned)std::min<int64_t>((hn.total + 3) / 4, HnCfg<C2>::slots / 4);
+        const unsigned wnn = (unsigned)std::min<int64_t>((nn.total + 3) / 4, NnCfg<C2>::slots / 4);
+        hipLaunchKernelGGL((k_gemm_hn_part_grp<C2>), dim3(whn), dim3(256), 0, s, hn.t);
+        hipLaunchKernelGGL((k_gemm_hn_reduce_grp<C2>), dim3((unsigned)red.total), dim3(256), 0, s, red.t);
+        hipLaunchKernelGGL((k_gemm_nn_grp<C2>), dim3(wnn), dim3(256), 0, s, nn.t);
     }
     return hipGetLastError();
 }
+template hipError_t launch_nonlocal_grouped<double2>(hipStream_t, const GroupCell *, int);
+template hipError_t launch_nonlocal_grouped<float2>(hipStream_t, const GroupCell *, int);
 
 }  // namespace paro

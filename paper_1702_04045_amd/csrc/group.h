@@ -11,6 +11,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 
 namespace paro {
@@ -161,18 +162,32 @@ template <class C2> struct GemmNnArgs {
 
 constexpr int kGroupChunks = 16;  // 64-band chunks of up to 1024 bands
 
-// Everything one cell's FP64 source solve needs, in the cell's workspace.
-struct GroupCellDesc {
-    StickInvArgs<double2> sinv[kGroupChunks];
-    PlaneArgs<double2> plane[kGroupChunks];
-    StickFwdArgs<double2> sfwd[kGroupChunks];
-    GemmHnArgs<double2> hn;
-    GemmHnRedArgs<double2> hred;
-    GemmNnArgs<double2> nn;
-    PcgInitPartsArgs iparts;
-    PcgInitArgs<double2, double2> init;
-    PcgScalarsArgs sc0, sc1;
-    PcgUpdateArgs<double2, double2> upd;
+// The kernels of one cell's source solve in one precision of its vectors
+// (FP64, or FP32 for the mixed-precision solve of the correction).
+template <class C2> struct GroupSolveArgs {
+    StickInvArgs<C2> sinv[kGroupChunks];
+    PlaneArgs<C2> plane[kGroupChunks];
+    StickFwdArgs<C2> sfwd[kGroupChunks];
+    GemmHnArgs<C2> hn;
+    GemmHnRedArgs<C2> hred;
+    GemmNnArgs<C2> nn;
+    PcgInitArgs<C2, C2> init;
+    PcgUpdateArgs<C2, C2> upd;
 };
+
+// Everything one cell's source solve needs, in the cell's workspace.
+struct GroupCellDesc {
+    GroupSolveArgs<double2> f64;
+    GroupSolveArgs<float2> f32;
+    PcgInitPartsArgs iparts;
+    PcgScalarsArgs sc0, sc1;
+};
+// device address of a cell descriptor's arguments for vectors of type C2
+template <class C2> inline const GroupSolveArgs<C2> *group_solve_args(const GroupCellDesc *d)
+{
+    const char *b = reinterpret_cast<const char *>(d);
+    if constexpr (sizeof(C2) == 16) return reinterpret_cast<const GroupSolveArgs<C2> *>(b + offsetof(GroupCellDesc, f64));
+    else return reinterpret_cast<const GroupSolveArgs<C2> *>(b + offsetof(GroupCellDesc, f32));
+}
 
 }  // namespace paro

@@ -206,16 +206,22 @@ struct GroupCell {
 void describe_pcg(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi, int64_t ld,
                   const double *eps, double2 *u, int64_t ldu, int32_t *band_flags, bool correction, int npq,
                   GroupCellDesc &d);
-hipError_t launch_pcg_init_grouped(hipStream_t s, const GroupCell *cells, int n);
-hipError_t launch_pcg_update_grouped(hipStream_t s, const GroupCell *cells, int n);
+// the mixed-precision solve's PCG (launch_pcg_init_mixed, launch_pcg_update_mixed)
+void describe_pcg_mixed(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
+                        int64_t ld, const double *eps, int32_t *band_flags, int npq, GroupCellDesc &d);
+// C2 = double2: the FP64 solve; float2: the mixed-precision solve
+template <class C2> hipError_t launch_pcg_init_grouped(hipStream_t s, const GroupCell *cells, int n);
+template <class C2> hipError_t launch_pcg_update_grouped(hipStream_t s, const GroupCell *cells, int n);
 // the stick and plane launches of (H - sigma) p with the PCG prologue, as
-// launch_local_apply(w.z, w.q, shift, w.p, beta = w.sc + SC_BETA nb); returns
-// the number of partial sums of p^H q per band
+// launch_local_apply(z, q, shift, p, beta = w.sc + SC_BETA nb) with the FP64
+// vectors (and the FP32 ones of the mixed solve); returns the number of
+// partial sums of p^H q per band
 int describe_local_apply(const Plan &pl, const Workspace &w, int nb, const double *shift, GroupCellDesc &d);
 bool grouped_grid(int n);  // FFT lengths with grouped kernels
-hipError_t launch_local_apply_grouped(hipStream_t s, const GroupCell *cells, int n, bool first);
+template <class C2> hipError_t launch_local_apply_grouped(hipStream_t s, const GroupCell *cells, int n, bool first);
+// the projector products of the solve (FP64, and FP32 matrix cores)
 void describe_nonlocal(const Plan &pl, const Workspace &w, int nb, GroupCellDesc &d);
-hipError_t launch_nonlocal_grouped(hipStream_t s, const GroupCell *cells, int n);
+template <class C2> hipError_t launch_nonlocal_grouped(hipStream_t s, const GroupCell *cells, int n);
 
 }  // namespace paro
 

@@ -665,8 +665,9 @@ bool groupable(const std::vector<CellRun> &cells)
 {
     if (cells.size() < 2) return false;
     for (const CellRun &c : cells)
-        if (c.o.precision != PARO_PREC_FP64 || c.o.variant == PARO_VARIANT_MPARO2 || !grouped_grid(c.pl->grid[0]) ||
-            c.nb > kGroupChunks * kMaxBandsPerChunk)
+        if ((c.o.precision != PARO_PREC_FP64 && c.o.precision != PARO_PREC_MIXED) ||
+            c.o.precision != cells[0].o.precision || c.o.variant == PARO_VARIANT_MPARO2 ||
+            !grouped_grid(c.pl->grid[0]) || c.nb > kGroupChunks * kMaxBandsPerChunk)
             return false;
     return true;
 }
@@ -675,10 +676,15 @@ bool groupable(const std::vector<CellRun> &cells)
 // correction equation of Algorithm 2) as grouped launches on stream s: per
 // PCG step one launch per kernel and FFT length for all cells, each cell's
 // work exactly that of its own source_solve.
-hipError_t source_solve_grouped(hipStream_t s, const std::vector<GroupCell> &gc, const std::vector<int> &ncg)
+extern "C++" {
+// C2 = float2: the mixed-precision solve of the correction (FP32 vectors,
+// FP32 matrix-core products), ending with u = psi + d (or d) per cell.
+template <class C2>
+hipError_t source_solve_grouped(hipStream_t s, const std::vector<GroupCell> &gc, const std::vector<int> &ncg,
+                                const std::vector<const CellRun *> &cr)
 {
     const int n = (int)gc.size();
-    hipError_t e = launch_pcg_init_grouped(s, gc.data(), n);
+    hipError_t e = launch_pcg_init_grouped<C2>(s, gc.data(), n);
     int kmax = 0;
     for (int k : ncg) kmax = std::max(kmax, k);
     std::vector<GroupCell> sub;
@@ -687,12 +693,24 @@ hipError_t source_solve_grouped(hipStream_t s, const std::vector<GroupCell> &gc,
         for (int i = 0; i < n; ++i)
             if (ncg[i] >= k) sub.push_back(gc[i]);
         const int m = (int)sub.size();
-        e = launch_local_apply_grouped(s, sub.data(), m, k == 1);
-        if (e == hipSuccess) e = launch_nonlocal_grouped(s, sub.data(), m);
-        if (e == hipSuccess) e = launch_pcg_update_grouped(s, sub.data(), m);
+        e = launch_local_apply_grouped<C2>(s, sub.data(), m, k == 1);
+        if (e == hipSuccess) e = launch_nonlocal_grouped<C2>(s, sub.data(), m);
+        if (e == hipSuccess) e = launch_pcg_update_grouped<C2>(s, sub.data(), m);
+    }
+    if constexpr (sizeof(C2) == 8) {
+        for (int i = 0; i < n && e == hipSuccess; ++i) {
+            const CellRun &c = *cr[i];
+            const bool mparo = c.o.variant != PARO_VARIANT_PARO;
+            double2 *Ut = mparo ? c.w.U + (size_t)c.nb * c.pl->ldv : c.w.U;
+            Plan pl = *c.pl;
+            pl.stream = s;
+            e = launch_finish_correction(pl, c.w, c.nb, mparo ? nullptr : c.psi, c.ld, Ut, c.pl->ldv);
+        }
     }
     return e;
 }
+
+}  // extern "C++"
 
 // The outer loop of run_cells with the cells in lockstep: every outer
 // iteration, the source problems of all cells still iterating run as
@@ -719,9 +737,9 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
         q += block(c);
     }
     EventSet events;
-    events.ev.assign(n + 1, nullptr);
-    for (int i = 0; i <= n; ++i) PARO_HIP_TRY(hipEventCreateWithFlags(&events.ev[i], hipEventDisableTiming));
-    hipEvent_t gev = events.ev[n];
+    events.ev.assign(2 * n + 1, nullptr);
+    for (int i = 0; i <= 2 * n; ++i) PARO_HIP_TRY(hipEventCreateWithFlags(&events.ev[i], hipEventDisableTiming));
+    hipEvent_t gev = events.ev[2 * n];
     std::vector<GroupCell> gc(n);
     std::vector<int> ncg(n);
     for (int i = 0; i < n; ++i) {
@@ -735,8 +753,12 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
         std::memset(&d, 0, sizeof(d));
         const int npq = describe_local_apply(pl, w, c.nb, w.sig_all, d);
         describe_nonlocal(pl, w, c.nb, d);
-        describe_pcg(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, Ut, lv, w.iflags + c.nb, mparo, npq, d);
+        if (c.o.precision == PARO_PREC_MIXED)
+            describe_pcg_mixed(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.iflags + c.nb, npq, d);
+        else
+            describe_pcg(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, Ut, lv, w.iflags + c.nb, mparo, npq, d);
         PARO_HIP_TRY(hipMemcpyAsync(w.desc, &d, sizeof(d), hipMemcpyHostToDevice, pl.stream));
+        PARO_HIP_TRY(hipEventRecord(events.ev[n + i], pl.stream));
         gc[i] = GroupCell{&pl, &w, c.nb, (c.nb + kMaxBandsPerChunk - 1) / kMaxBandsPerChunk, w.desc, &d};
         ncg[i] = c.o.n_cg;
         if (c.o.initial_rr) {
@@ -751,6 +773,8 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
     std::vector<char> done(n, 0);
     std::vector<GroupCell> agc;
     std::vector<int> ancg, act;
+    std::vector<const CellRun *> acr;
+    const bool mixed = cells[0].o.precision == PARO_PREC_MIXED;
     for (;;) {
         // step 5 of the previous iteration: which cells go on
         bool wait = false;
@@ -779,13 +803,16 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
         hipStream_t gs = cells[act[0]].pl->stream;
         agc.clear();
         ancg.clear();
+        acr.clear();
         for (int i : act) {
             PARO_HIP_TRY(hipEventRecord(events.ev[i], cells[i].pl->stream));
             PARO_HIP_TRY(hipStreamWaitEvent(gs, events.ev[i], 0));
             agc.push_back(gc[i]);
             ancg.push_back(ncg[i]);
+            acr.push_back(&cells[i]);
         }
-        PARO_CHECK_LAUNCH(source_solve_grouped(gs, agc, ancg));
+        if (mixed) PARO_CHECK_LAUNCH(source_solve_grouped<float2>(gs, agc, ancg, acr));
+        else PARO_CHECK_LAUNCH(source_solve_grouped<double2>(gs, agc, ancg, acr));
         PARO_HIP_TRY(hipEventRecord(gev, gs));
         bool adaptive = false;
         for (int i : act) {
@@ -820,8 +847,9 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
             ++iter[i];
         }
     }
-    // the pinned descriptors may still be read by copies in flight
-    for (const CellRun &c : cells) PARO_HIP_TRY(hipStreamSynchronize(c.pl->stream));
+    // the pinned host copies of the descriptors are freed on return: wait
+    // for the copies (long done by now), not for the cells' work
+    for (int i = 0; i < n; ++i) PARO_HIP_TRY(hipEventSynchronize(events.ev[n + i]));
     return PARO_OK;
 }
 

@@ -537,31 +537,53 @@ hipError_t launch_copy_bands(hipStream_t s, int nb, int64_t ng, const double2 *s
 namespace paro {
 
 // ---------------------------------------------------------------- grouped launches
-// The PCG kernels of the FP64 source solve for many cells at once: the
+// The PCG kernels of the source solve for many cells at once: the
 // arguments each cell's own launches take (launch_pcg_init and
-// launch_pcg_update without projection), in its descriptor.
+// launch_pcg_update without projection, or their mixed-precision forms),
+// in its descriptor.
+static void describe_pcg_common(const Plan &pl, const Workspace &w, int nb, const double2 *psi, int64_t ld,
+                                int32_t *band_flags, int npq, GroupCellDesc &d)
+{
+    const int nc = (int)nchunks(pl.ng);
+    d.iparts = PcgInitPartsArgs{psi, ld, pl.kin, w.dots, pl.ng, nb};
+    d.sc0 = PcgScalarsArgs{nullptr, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags, w.iflags + nb,
+                           band_flags, pl.status, nb, nc, 0};
+    d.sc1 = PcgScalarsArgs{w.dots + (size_t)DOT_PQ * nb * kMaxParts, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc,
+                           w.iflags, w.iflags + nb, band_flags, pl.status, nb, nc, npq};
+}
+
 void describe_pcg(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi, int64_t ld,
                   const double *eps, double2 *u, int64_t ldu, int32_t *band_flags, bool correction, int npq,
                   GroupCellDesc &d)
 {
     const int nc = (int)nchunks(pl.ng);
-    d.iparts = PcgInitPartsArgs{psi, ld, pl.kin, w.dots, pl.ng, nb};
-    d.init = PcgInitArgs<double2, double2>{psi, hpsi, ld, eps, pl.kin, u, ldu, w.r, w.z, pl.ldv, w.dots, w.sc,
-                                           pl.ng, nc, nb, correction ? 1 : 0};
-    d.sc0 = PcgScalarsArgs{nullptr, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags, w.iflags + nb,
-                           band_flags, pl.status, nb, nc, 0};
-    d.sc1 = PcgScalarsArgs{w.dots + (size_t)DOT_PQ * nb * kMaxParts, w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc,
-                           w.iflags, w.iflags + nb, band_flags, pl.status, nb, nc, npq};
-    d.upd = PcgUpdateArgs<double2, double2>{w.p, w.q, pl.ldv, u, ldu, w.r, w.z, pl.kin,
-                                            w.dots + (size_t)DOT_PQ * nb * kMaxParts,
-                                            w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags, pl.ng, npq, nb};
+    describe_pcg_common(pl, w, nb, psi, ld, band_flags, npq, d);
+    d.f64.init = PcgInitArgs<double2, double2>{psi, hpsi, ld, eps, pl.kin, u, ldu, w.r, w.z, pl.ldv, w.dots, w.sc,
+                                               pl.ng, nc, nb, correction ? 1 : 0};
+    d.f64.upd = PcgUpdateArgs<double2, double2>{w.p, w.q, pl.ldv, u, ldu, w.r, w.z, pl.kin,
+                                                w.dots + (size_t)DOT_PQ * nb * kMaxParts,
+                                                w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags, pl.ng, npq,
+                                                nb};
+}
+
+void describe_pcg_mixed(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
+                        int64_t ld, const double *eps, int32_t *band_flags, int npq, GroupCellDesc &d)
+{
+    const int nc = (int)nchunks(pl.ng);
+    describe_pcg_common(pl, w, nb, psi, ld, band_flags, npq, d);
+    d.f32.init = PcgInitArgs<float2, float2>{psi, hpsi, ld, eps, pl.kin, w.d32, pl.ldv, w.r32, w.z32, pl.ldv, w.dots,
+                                             w.sc, pl.ng, nc, nb, 1};
+    d.f32.upd = PcgUpdateArgs<float2, float2>{w.p32, w.q32, pl.ldv, w.d32, pl.ldv, w.r32, w.z32, pl.kin,
+                                              w.dots + (size_t)DOT_PQ * nb * kMaxParts,
+                                              w.dots + (size_t)DOT_RZ * nb * kMaxParts, w.sc, w.iflags, pl.ng, npq,
+                                              nb};
 }
 
 namespace {
 
 // entries of a (chunk x band) vector kernel; launches every kGroupMax entries
 template <class F, class G>
-hipError_t group_vec(hipStream_t s, const GroupCell *cells, int n, F args_of, G launch)
+hipError_t group_vec(const GroupCell *cells, int n, F args_of, G launch)
 {
     GroupBuilder g;
     for (int i = 0; i < n; ++i) {
@@ -589,36 +611,41 @@ void group_scalars(hipStream_t s, const GroupCell *cells, int n, F args_of, int 
 
 }  // namespace
 
-hipError_t launch_pcg_init_grouped(hipStream_t s, const GroupCell *cells, int n)
+template <class C2> hipError_t launch_pcg_init_grouped(hipStream_t s, const GroupCell *cells, int n)
 {
     if (n <= 0) return hipSuccess;
-    hipError_t e = group_vec(s, cells, n, [](const GroupCellDesc *d) { return (const void *)&d->iparts; },
+    hipError_t e = group_vec(cells, n, [](const GroupCellDesc *d) { return (const void *)&d->iparts; },
                              [&](const GroupBuilder &g) {
                                  hipLaunchKernelGGL(k_pcg_init_parts_grp, dim3((unsigned)g.total), dim3(kVecThreads),
                                                     0, s, g.t);
                              });
     if (e != hipSuccess) return e;
-    e = group_vec(s, cells, n, [](const GroupCellDesc *d) { return (const void *)&d->init; },
+    e = group_vec(cells, n, [](const GroupCellDesc *d) { return (const void *)&group_solve_args<C2>(d)->init; },
                   [&](const GroupBuilder &g) {
-                      hipLaunchKernelGGL((k_pcg_init_grp<double2, double2>), dim3((unsigned)g.total),
-                                         dim3(kVecThreads), 0, s, g.t);
+                      hipLaunchKernelGGL((k_pcg_init_grp<C2, C2>), dim3((unsigned)g.total), dim3(kVecThreads), 0, s,
+                                         g.t);
                   });
     if (e != hipSuccess) return e;
     group_scalars(s, cells, n, [](const GroupCellDesc *d) { return (const void *)&d->sc0; }, 0);
     return hipGetLastError();
 }
 
-hipError_t launch_pcg_update_grouped(hipStream_t s, const GroupCell *cells, int n)
+template <class C2> hipError_t launch_pcg_update_grouped(hipStream_t s, const GroupCell *cells, int n)
 {
     if (n <= 0) return hipSuccess;
-    hipError_t e = group_vec(s, cells, n, [](const GroupCellDesc *d) { return (const void *)&d->upd; },
+    hipError_t e = group_vec(cells, n, [](const GroupCellDesc *d) { return (const void *)&group_solve_args<C2>(d)->upd; },
                              [&](const GroupBuilder &g) {
-                                 hipLaunchKernelGGL((k_pcg_update_grp<double2, double2>), dim3((unsigned)g.total),
+                                 hipLaunchKernelGGL((k_pcg_update_grp<C2, C2>), dim3((unsigned)g.total),
                                                     dim3(kVecThreads), 0, s, g.t);
                              });
     if (e != hipSuccess) return e;
     group_scalars(s, cells, n, [](const GroupCellDesc *d) { return (const void *)&d->sc1; }, 1);
     return hipGetLastError();
 }
+
+template hipError_t launch_pcg_init_grouped<double2>(hipStream_t, const GroupCell *, int);
+template hipError_t launch_pcg_init_grouped<float2>(hipStream_t, const GroupCell *, int);
+template hipError_t launch_pcg_update_grouped<double2>(hipStream_t, const GroupCell *, int);
+template hipError_t launch_pcg_update_grouped<float2>(hipStream_t, const GroupCell *, int);
 
 }  // namespace paro

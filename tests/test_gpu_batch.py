@@ -1,10 +1,12 @@
 """Batched ParO (paro_iterate_batch) on cells of uneven grid, sphere and band
 count: every cell's result is bitwise the one paro_iterate gives for that
 cell alone, and one cell is checked against the oracle's ParO histories.
-FP64 batches of Algorithm 1 or 2 run their source problems as grouped
-launches (one launch per kernel and FFT length for all cells, each cell's
-blocks computing exactly what its own launch computes); MParO II and mixed
-precision run cell by cell on the cells' streams.  Both paths are covered.
+Batches of Algorithm 1 or 2 in FP64 or in mixed precision with FP32
+projector products run their source problems as grouped launches (one
+launch per kernel and FFT length for all cells, each cell's blocks
+computing exactly what its own launch computes); MParO II and the split-BF16
+mixed precision run cell by cell on the cells' streams.  Both paths are
+covered.
 """
 import numpy as np
 import pytest
@@ -53,8 +55,9 @@ def build(specs, seed0=40):
 
 
 @pytest.mark.parametrize("variant,shift_mode,tol,precision", [(0, 1, 0.0, 0), (1, 1, 1e-7, 0), (2, 0, 0.0, 0),
-                                                               (1, 1, 0.0, 1)],
-                         ids=["paro_adaptive", "mparo_adaptive_tol", "mparo2_fixed", "mparo_mixed"])
+                                                               (1, 1, 0.0, 1), (0, 1, 1e-7, 1), (0, 1, 0.0, 2)],
+                         ids=["paro_adaptive", "mparo_adaptive_tol", "mparo2_fixed", "mparo_mixed",
+                              "paro_mixed_tol", "paro_mixed_bf16"])
 def test_batch_is_bitwise_the_single_cell_runs(variant, shift_mode, tol, precision):
     import paper_1702_04045_amd as P
     torch = _torch()
