@@ -819,6 +819,9 @@ hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const C2 *src, 
                      const double *shift, C2 *pbuf, const double *beta, bool first, double *dot_part,
                      int *nparts_out)
 {
+    // the pruned 96-point transforms leave out the line entries |n| > 23
+    if (N == 96 && kXlanePrune && (pl.nmax[0] > 23 || pl.nmax[1] > 23 || pl.nmax[2] > 23))
+        return hipErrorInvalidValue;
     constexpr int NT = stick_threads<N, C2>();
     constexpr int S = NT / FftCfg<N>::T;
     const int N3 = pl.grid[2];
@@ -1046,6 +1049,10 @@ hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool fi
     int rounds = 0;
     for (int i = 0; i < n; ++i)
         if (cells[i].pl->grid[0] == N) rounds = std::max(rounds, cells[i].nchunk);
+    for (int i = 0; i < n; ++i)
+        if (N == 96 && kXlanePrune && cells[i].pl->grid[0] == N &&
+            (cells[i].pl->nmax[0] > 23 || cells[i].pl->nmax[1] > 23 || cells[i].pl->nmax[2] > 23))
+            return hipErrorInvalidValue;
     for (int r = 0; r < rounds; ++r) {
         // the three kernels in turn, every entry of the round in each
         for (int k = 0; k < 3; ++k) {

@@ -186,6 +186,22 @@ def test_apply_h_f32_large_grids(grid):
     assert rel_err(to_np(pl.apply_h_f32(to_dev(x))), h.apply(x.astype(np.complex128))) < 2e-6
 
 
+def test_apply_h_96_at_the_pruning_limit():
+    """a = 20 bohr, E_cut = 27 Ha: n_max = 23, the largest the 96-point grid
+    accepts (96 >= 4 n_max + 1), so the populated line entries reach the
+    edge of the set the pruned 12-point DFTs keep (|n| <= 23).  FP64 and FP32
+    applies of two bands against the oracle, and the density."""
+    spec = synth.small_cell(a=20.0, ecut=27.0, grid=96, n_atoms=2)
+    c, v, h, pl = make_case(spec, 12)
+    assert int(h.nmax.max()) == 23
+    x = synth.trial_block(h.ng, 2, 12)
+    ref = h.apply(x)
+    assert rel_err(to_np(pl.apply_h(to_dev(x))), ref) < 1e-12
+    x32 = x.astype(np.complex64)
+    assert rel_err(to_np(pl.apply_h_f32(to_dev(x32))), h.apply(x32.astype(np.complex128))) < 2e-6
+    assert rel_err(to_np(pl.density(to_dev(x))), h.density(x)) < 1e-12
+
+
 def test_apply_h_padded_leading_dimension():
     torch = _torch()
     c, v, h, pl = make_case(TINY, 3)

@@ -167,3 +167,71 @@ def test_pruned_positions_are_never_populated_on_accepted_grids():
     R = inverse(x)
     X = np.fft.ifft(x) * N
     assert max(abs(R[t, s] - X[xlane_index(t, s)]) for t in range(T) for s in range(E)) < 1e-12 * np.abs(X).max()
+
+
+# ---------------------------------------------------------------- pruned 12-point DFTs
+# The 96-point kernels take the 12-point DFT in registers as 12 = 4 x 3:
+# input m = s_b + 3 q (q < 4), a 4-point DFT over q, the twiddle
+# w12^(s_b k_a), a 3-point DFT over s_b, output k = k_a + 4 k_b.  With
+# inputs 3..8 zero (q = 1, 2) the 4-point DFTs see only q = 0 and 3
+# (dft12_in_pruned); of the outputs only k = 0, 1, 2, 9, 10, 11 are kept
+# (k_b = 0 for k_a < 3, k_b = 2 for k_a > 0: dft12_out_pruned).  The model
+# restates those two steps and checks them against numpy.
+
+def _dft(x, sign):
+    n = len(x)
+    k = np.arange(n)
+    return np.exp(sign * 2j * np.pi * np.outer(k, k) / n) @ x
+
+
+def dft12_in_pruned_model(v, sign):
+    y = np.zeros(12, complex)
+    for sb in range(3):
+        a0, a3 = v[sb], v[9 + sb]
+        d = sign * 1j * a3
+        y[sb * 4 + 0], y[sb * 4 + 2] = a0 + a3, a0 - a3
+        y[sb * 4 + 1], y[sb * 4 + 3] = a0 - d, a0 + d
+    out = np.zeros(12, complex)
+    for ka in range(4):
+        b = np.array([y[ka], y[4 + ka], y[8 + ka]]) * np.exp(sign * 2j * np.pi * np.arange(3) * ka / 12)
+        out[ka + 4 * np.arange(3)] = _dft(b, sign)
+    return out
+
+
+def dft12_out_pruned_model(v, sign):
+    y = np.zeros(12, complex)
+    for sb in range(3):
+        y[sb * 4:sb * 4 + 4] = _dft(np.array([v[sb], v[3 + sb], v[6 + sb], v[9 + sb]]), sign)
+    out = np.full(12, np.nan + 0j)
+    h = np.sin(2 * np.pi / 3)
+    for ka in range(4):
+        b = np.array([y[ka], y[4 + ka], y[8 + ka]]) * np.exp(sign * 2j * np.pi * np.arange(3) * ka / 12)
+        t1 = b[1] + b[2]
+        if ka < 3:
+            out[ka] = b[0] + t1
+        if ka > 0:
+            out[ka + 8] = (b[0] - 0.5 * t1) - sign * 1j * h * (b[1] - b[2])
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_pruned_dft12_inverse_on_zero_inputs(seed):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(12) + 1j * rng.standard_normal(12)
+    v[3:9] = 0.0
+    assert np.abs(dft12_in_pruned_model(v, +1) - np.fft.ifft(v) * 12).max() < 1e-13
+    # the pruning really assumes those inputs zero: a nonzero one is dropped
+    w = v.copy()
+    w[5] = 1.0
+    assert np.abs(dft12_in_pruned_model(w, +1) - np.fft.ifft(w) * 12).max() > 0.1
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_pruned_dft12_forward_kept_outputs(seed):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(12) + 1j * rng.standard_normal(12)
+    got = dft12_out_pruned_model(v, -1)
+    kept = [0, 1, 2, 9, 10, 11]
+    assert np.abs(got[kept] - np.fft.fft(v)[kept]).max() < 1e-13
+    assert np.all(np.isnan(got[3:9]))
+    assert [m for m in range(12) if not 3 <= m <= 8] == kept
