@@ -712,15 +712,13 @@ hipError_t source_solve_grouped(hipStream_t s, const std::vector<GroupCell> &gc,
 
 }  // extern "C++"
 
-// The outer loop of run_cells with the cells in lockstep, in two groups:
-// every outer iteration, the source problems of a group's cells still
-// iterating run as grouped launches on the stream of the group's first such
-// cell (ordered against each cell's own stream by events), then each cell's
-// Rayleigh-Ritz, residuals and shift run on its own stream as before, side
-// by side.  The groups run half an iteration apart, so one group's
-// Rayleigh-Ritz phase overlaps the other's source problems.  The host takes
-// the same decisions as run_cells, from the same device values; each cell's
-// device work is exactly that of its lone run.
+// The outer loop of run_cells with the cells in lockstep: every outer
+// iteration, the source problems of all cells still iterating run as
+// grouped launches on the first such cell's stream (ordered against each
+// cell's own stream by events), then each cell's Rayleigh-Ritz, residuals
+// and shift run on its own stream as before, side by side.  The host takes
+// the same decisions as run_cells, from the same device values, for all
+// cells at once; each cell's device work is exactly that of its lone run.
 int32_t run_cells_grouped(std::vector<CellRun> &cells)
 {
     const int n = (int)cells.size();
@@ -739,8 +737,9 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
         q += block(c);
     }
     EventSet events;
-    events.ev.assign(2 * n + 2, nullptr);
-    for (int i = 0; i < 2 * n + 2; ++i) PARO_HIP_TRY(hipEventCreateWithFlags(&events.ev[i], hipEventDisableTiming));
+    events.ev.assign(2 * n + 1, nullptr);
+    for (int i = 0; i <= 2 * n; ++i) PARO_HIP_TRY(hipEventCreateWithFlags(&events.ev[i], hipEventDisableTiming));
+    hipEvent_t gev = events.ev[2 * n];
     std::vector<GroupCell> gc(n);
     std::vector<int> ncg(n);
     for (int i = 0; i < n; ++i) {
@@ -770,56 +769,18 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
         PARO_CHECK_LAUNCH(launch_residuals(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.res));
         PARO_CHECK_LAUNCH(launch_bookkeeping(pl, c.nb, c.o, c.eps, w.res, w.sig_all, c.sigma, c.stats, c.conv));
     }
-    // Two groups of cells, split by stream and balanced by work, run a
-    // half iteration apart: while one group's grouped source problems run,
-    // the other group's Rayleigh-Ritz phase runs on its cells' streams.
-    std::vector<hipStream_t> streams;
-    std::vector<double> work;
-    std::vector<int> sidx(n);
-    for (int i = 0; i < n; ++i) {
-        const hipStream_t st = cells[i].pl->stream;
-        int k = 0;
-        while (k < (int)streams.size() && streams[k] != st) ++k;
-        if (k == (int)streams.size()) {
-            streams.push_back(st);
-            work.push_back(0.0);
-        }
-        sidx[i] = k;
-        work[k] += (double)cells[i].nb * (double)cells[i].pl->ng * cells[i].o.n_cg;
-    }
-    const int ngroups = streams.size() > 1 ? 2 : 1;
-    std::vector<int> sgroup(streams.size(), 0);
-    {
-        std::vector<int> order(streams.size());
-        for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
-        std::sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
-        double load[2] = {0.0, 0.0};
-        for (int k : order) {
-            const int g = ngroups > 1 && load[1] < load[0] ? 1 : 0;
-            sgroup[k] = g;
-            load[g] += work[k];
-        }
-    }
     std::vector<int> iter(n, 0);
     std::vector<char> done(n, 0);
-    const bool mixed = cells[0].o.precision == PARO_PREC_MIXED;
-    struct GroupState {
-        std::vector<int> act;  // cells whose source problems are in flight
-        bool live = true;
-    };
-    GroupState gst[2];
     std::vector<GroupCell> agc;
-    std::vector<int> ancg;
+    std::vector<int> ancg, act;
     std::vector<const CellRun *> acr;
-    // decide which of group g's cells go on (step 5 of their previous
-    // iteration) and enqueue their grouped source problems
-    auto start_solve = [&](int g) -> int32_t {
-        GroupState &G = gst[g];
-        G.act.clear();
+    const bool mixed = cells[0].o.precision == PARO_PREC_MIXED;
+    for (;;) {
+        // step 5 of the previous iteration: which cells go on
         bool wait = false;
         for (int i = 0; i < n; ++i) {
             CellRun &c = cells[i];
-            if (done[i] || sgroup[sidx[i]] != g) continue;
+            if (done[i]) continue;
             if (iter[i] >= c.o.n_outer) {
                 done[i] = 1;
             } else if (c.o.tol_res > 0.0) {
@@ -830,22 +791,20 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
         }
         if (wait)
             for (int i = 0; i < n; ++i)
-                if (!done[i] && sgroup[sidx[i]] == g && cells[i].o.tol_res > 0.0) {
+                if (!done[i] && cells[i].o.tol_res > 0.0) {
                     PARO_HIP_TRY(hipEventSynchronize(events.ev[i]));
                     if (*cells[i].hconv) done[i] = 1;
                 }
+        act.clear();
         for (int i = 0; i < n; ++i)
-            if (!done[i] && sgroup[sidx[i]] == g) G.act.push_back(i);
-        if (G.act.empty()) {
-            G.live = false;
-            return PARO_OK;
-        }
+            if (!done[i]) act.push_back(i);
+        if (act.empty()) break;
         // the grouped source problems, after each cell's own work so far
-        hipStream_t gs = cells[G.act[0]].pl->stream;
+        hipStream_t gs = cells[act[0]].pl->stream;
         agc.clear();
         ancg.clear();
         acr.clear();
-        for (int i : G.act) {
+        for (int i : act) {
             PARO_HIP_TRY(hipEventRecord(events.ev[i], cells[i].pl->stream));
             PARO_HIP_TRY(hipStreamWaitEvent(gs, events.ev[i], 0));
             agc.push_back(gc[i]);
@@ -854,9 +813,9 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
         }
         if (mixed) PARO_CHECK_LAUNCH(source_solve_grouped<float2>(gs, agc, ancg, acr));
         else PARO_CHECK_LAUNCH(source_solve_grouped<double2>(gs, agc, ancg, acr));
-        hipEvent_t gev = events.ev[2 * n + g];
         PARO_HIP_TRY(hipEventRecord(gev, gs));
-        for (int i : G.act) {
+        bool adaptive = false;
+        for (int i : act) {
             CellRun &c = cells[i];
             PARO_HIP_TRY(hipStreamWaitEvent(c.pl->stream, gev, 0));
             if (c.o.shift_mode == PARO_SHIFT_ADAPTIVE) {
@@ -864,15 +823,12 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
                                             hipMemcpyDeviceToHost, c.pl->stream));
                 PARO_HIP_TRY(hipMemcpyAsync(c.scur, c.sigma, sizeof(double), hipMemcpyDeviceToHost, c.pl->stream));
                 PARO_HIP_TRY(hipEventRecord(events.ev[i], c.pl->stream));
+                adaptive = true;
             }
         }
-        return PARO_OK;
-    };
-    // the negative-curvature retries and steps 4-5 of group g's cells
-    auto finish = [&](int g) -> int32_t {
-        for (int i : gst[g].act) {
+        for (int i : act) {
             CellRun &c = cells[i];
-            if (c.o.shift_mode == PARO_SHIFT_ADAPTIVE) {
+            if (adaptive && c.o.shift_mode == PARO_SHIFT_ADAPTIVE) {
                 PARO_HIP_TRY(hipEventSynchronize(events.ev[i]));
                 bool neg = false;
                 for (int b = 0; b < c.nb; ++b) neg = neg || (c.hflags[b] & PARO_F_NEGCURV);
@@ -890,23 +846,6 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
             if (c.n_done) *c.n_done = iter[i] + 1;
             ++iter[i];
         }
-        gst[g].act.clear();
-        return PARO_OK;
-    };
-    for (int g = 0; g < ngroups; ++g) {
-        int32_t rc = start_solve(g);
-        if (rc) return rc;
-    }
-    for (;;) {
-        bool any = false;
-        for (int g = 0; g < ngroups; ++g) {
-            if (!gst[g].live) continue;
-            any = true;
-            int32_t rc = finish(g);
-            if (rc == PARO_OK) rc = start_solve(g);
-            if (rc) return rc;
-        }
-        if (!any) break;
     }
     // the pinned host copies of the descriptors are freed on return: wait
     // for the copies (long done by now), not for the cells' work
