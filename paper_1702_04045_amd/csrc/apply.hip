@@ -1041,7 +1041,9 @@ bool grouped_grid(int n) { return fft_supported(n) && !big_grid(n); }
 
 namespace {
 
-template <int N, class C2>
+// FIN: the arguments of W = H U at the end of an outer iteration (FP64)
+// instead of those of the source solve
+template <int N, class C2, bool FIN>
 hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool first)
 {
     constexpr int NT = stick_threads<N, C2>();
@@ -1073,12 +1075,21 @@ hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool fi
                 if (c.pl->grid[0] != N || c.nchunk <= r) continue;
                 const int cb = std::min(kMaxBandsPerChunk, c.nb - r * kMaxBandsPerChunk);
                 const int ntiles = (c.pl->nst + S - 1) / S;
-                const GroupSolveArgs<C2> *a = group_solve_args<C2>(c.dev);
-                if (k == 0) g.add(&a->sinv[r], (int64_t)ntiles * cb, ntiles);
+                const void *ai, *ap, *af;
+                if constexpr (FIN) {
+                    ai = &c.dev->fin.sinv[r];
+                    ap = &c.dev->fin.plane[r];
+                    af = &c.dev->fin.sfwd[r];
+                } else {
+                    const GroupSolveArgs<C2> *a = group_solve_args<C2>(c.dev);
+                    ai = &a->sinv[r];
+                    ap = &a->plane[r];
+                    af = &a->sfwd[r];
+                }
+                if (k == 0) g.add(ai, (int64_t)ntiles * cb, ntiles);
                 else if (k == 1)
-                    g.add(&a->plane[r], (int64_t)c.pl->grid[2] * ((cb + kBandsPerBlock - 1) / kBandsPerBlock),
-                          c.pl->grid[2]);
-                else g.add(&a->sfwd[r], (int64_t)ntiles * cb, ntiles);
+                    g.add(ap, (int64_t)c.pl->grid[2] * ((cb + kBandsPerBlock - 1) / kBandsPerBlock), c.pl->grid[2]);
+                else g.add(af, (int64_t)ntiles * cb, ntiles);
                 if (g.full()) flush();
             }
             flush();
@@ -1093,13 +1104,41 @@ template <class C2> hipError_t launch_local_apply_grouped(hipStream_t s, const G
 {
     hipError_t e = hipSuccess;
 #define PARO_CASE(k) \
-    if (e == hipSuccess) e = grouped_local_n<k, C2>(s, cells, n, first);
+    if (e == hipSuccess) e = grouped_local_n<k, C2, false>(s, cells, n, first);
     PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
     PARO_CASE(80) PARO_CASE(96)
 #undef PARO_CASE
     return e;
 }
 template hipError_t launch_local_apply_grouped<double2>(hipStream_t, const GroupCell *, int, bool);
+
+// W = H U, local part (launch_local_apply(U, W) without PCG prologue, shift or dot products)
+void describe_finish_local(const Plan &pl, const Workspace &w, int nb, const double2 *U, double2 *W, int64_t ld,
+                           GroupFinishArgs &f)
+{
+    const int N3 = pl.grid[2];
+    const double scale = 1.0 / ((double)pl.grid[0] * pl.grid[1] * pl.grid[2]);
+    for (int c = 0, c0 = 0; c0 < nb; ++c, c0 += kMaxBandsPerChunk) {
+        const int cb = std::min(kMaxBandsPerChunk, nb - c0);
+        const int64_t o = (int64_t)c0 * ld;
+        f.sinv[c] = StickInvArgs<double2>{U + o, ld, nullptr, nullptr, w.sticks, pl.st_start, pl.pt_sz, pl.tw[2],
+                                          pl.nst};
+        f.plane[c] = PlaneArgs<double2>{w.sticks, pl.cols, pl.vplane, pl.tw[0], pl.nst, N3, cb, pl.nmax[0]};
+        f.sfwd[c] = StickFwdArgs<double2>{w.sticks, pl.st_start, pl.pt_sz, pl.tw[2], U + o, ld, W + o, pl.kin,
+                                          nullptr, scale, nullptr, pl.nst, kMaxParts};
+    }
+}
+
+hipError_t launch_finish_local_grouped(hipStream_t s, const GroupCell *cells, int n)
+{
+    hipError_t e = hipSuccess;
+#define PARO_CASE(k) \
+    if (e == hipSuccess) e = grouped_local_n<k, double2, true>(s, cells, n, false);
+    PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
+    PARO_CASE(80) PARO_CASE(96)
+#undef PARO_CASE
+    return e;
+}
 template hipError_t launch_local_apply_grouped<float2>(hipStream_t, const GroupCell *, int, bool);
 
 }  // namespace paro

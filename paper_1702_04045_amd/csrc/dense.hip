@@ -9,6 +9,7 @@
 #include <cfloat>
 #include <cmath>
 
+#include "group.h"
 #include "paro_internal.h"
 #include "reduce_device.h"
 
@@ -106,9 +107,9 @@ k_rr_chol(int m, const double2 *__restrict__ gram, int hs, double2 *__restrict__
 // j + 1 + wave, j + 1 + wave + W, ...), rows i >= l of column l.  Two
 // barriers per column.  Dynamic LDS: m complex values.
 template <int R, int W>
-__global__ void __launch_bounds__(64 * W)
-k_rr_chol_rows(int m, const double2 *__restrict__ gram, int hs, double2 *__restrict__ L, double2 *__restrict__ X,
-               int32_t *__restrict__ fail, int32_t *__restrict__ status)
+__device__ __forceinline__ void rr_chol_rows_body(int m, const double2 *__restrict__ gram, int hs,
+                                                  double2 *__restrict__ L, double2 *__restrict__ X,
+                                                  int32_t *__restrict__ fail, int32_t *__restrict__ status)
 {
     __shared__ double red[W];
     extern __shared__ double2 sa[];
@@ -178,16 +179,30 @@ k_rr_chol_rows(int m, const double2 *__restrict__ gram, int hs, double2 *__restr
         if (failed) atomicOr(status, PARO_F_CHOL);
     }
 }
+template <int R, int W>
+__global__ void __launch_bounds__(64 * W)
+k_rr_chol_rows(int m, const double2 *__restrict__ gram, int hs, double2 *__restrict__ L, double2 *__restrict__ X,
+               int32_t *__restrict__ fail, int32_t *__restrict__ status)
+{
+    rr_chol_rows_body<R, W>(m, gram, hs, L, X, fail, status);
+}
+// one work-group per entry
+template <int R, int W> __global__ void __launch_bounds__(64 * W) k_rr_chol_rows_grp(GroupTab t)
+{
+    const CholArgs &a = *static_cast<const CholArgs *>(t.args[blockIdx.x]);
+    rr_chol_rows_body<R, W>(a.m, a.gram, a.hs, a.L, a.X, a.fail, a.status);
+}
+
 
 // One column per single-wave work-group.
 // mode 0: out = L^-1 b;  mode 1: out = L^-H b.
 // b = column j of src, or (transb) the conjugate of row j of src.
-__global__ void __launch_bounds__(64)
-k_trsm_col(int m, const double2 *__restrict__ L, const double2 *__restrict__ src, int transb, int mode,
-           double2 *__restrict__ out)
+__device__ __forceinline__ void trsm_col_body(int bx, int m, const double2 *__restrict__ L,
+                                              const double2 *__restrict__ src, int transb, int mode,
+                                              double2 *__restrict__ out)
 {
     extern __shared__ double2 x[];
-    const int j = blockIdx.x, lane = threadIdx.x;
+    const int j = bx, lane = threadIdx.x;
     for (int i = lane; i < m; i += 64)
         x[i] = transb ? cconj(src[(int64_t)i * m + j]) : src[(int64_t)j * m + i];
     __syncthreads();
@@ -221,6 +236,20 @@ k_trsm_col(int m, const double2 *__restrict__ L, const double2 *__restrict__ src
     }
     for (int i = lane; i < m; i += 64) out[(int64_t)j * m + i] = x[i];
 }
+__global__ void __launch_bounds__(64)
+k_trsm_col(int m, const double2 *__restrict__ L, const double2 *__restrict__ src, int transb, int mode,
+           double2 *__restrict__ out)
+{
+    trsm_col_body(blockIdx.x, m, L, src, transb, mode, out);
+}
+__global__ void __launch_bounds__(64) k_trsm_col_grp(GroupTab t)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const TrsmArgs &a = *static_cast<const TrsmArgs *>(t.args[e]);
+    trsm_col_body(bx, a.m, a.L, a.src, a.transb, a.mode, a.out);
+}
+
 
 // Householder reduction of the Hermitian matrix A (hermitised first) to a
 // real symmetric tridiagonal T = Q^H A Q, Q = H_0 ... H_{m-2},
@@ -374,9 +403,8 @@ static size_t tridiag_lds_bytes(int m, bool lds)
 __device__ __forceinline__ double wave_sum_all(double v) { return __shfl(wave_sum(v), 0, 64); }
 
 template <int R, bool LDS, int W>
-__global__ void __launch_bounds__(64 * W)
-k_tridiag_rows(int m, double2 *__restrict__ A, double *__restrict__ d, double *__restrict__ e,
-               double2 *__restrict__ tau)
+__device__ __forceinline__ void tridiag_rows_body(int m, double2 *__restrict__ A, double *__restrict__ d,
+                                                  double *__restrict__ e, double2 *__restrict__ tau)
 {
     extern __shared__ double2 dyn[];
     double2 *S = LDS ? dyn : A;
@@ -514,6 +542,20 @@ k_tridiag_rows(int m, double2 *__restrict__ A, double *__restrict__ d, double *_
     if (LDS)
         for (int q = tid; q < mm; q += NT) A[q] = S[q];
 }
+template <int R, bool LDS, int W>
+__global__ void __launch_bounds__(64 * W)
+k_tridiag_rows(int m, double2 *__restrict__ A, double *__restrict__ d, double *__restrict__ e,
+               double2 *__restrict__ tau)
+{
+    tridiag_rows_body<R, LDS, W>(m, A, d, e, tau);
+}
+// one work-group per entry
+template <int R, bool LDS, int W> __global__ void __launch_bounds__(64 * W) k_tridiag_rows_grp(GroupTab t)
+{
+    const TridiagArgs &a = *static_cast<const TridiagArgs *>(t.args[blockIdx.x]);
+    tridiag_rows_body<R, LDS, W>(a.m, a.A, a.d, a.e, a.tau);
+}
+
 
 // The same reduction spread over G work-groups (G = 16 for 208 <= m <= 352,
 // G = 64 for 352 < m <= 704),
@@ -960,12 +1002,12 @@ constexpr int kTriMax = 1024;  // largest tridiagonal order of the eigen kernels
 // single-wave work-group per eigenvalue: 64-point multisection of Sturm
 // counts, each round shrinking the interval 65-fold, down to an absolute
 // width of 2 eps |T| (the accuracy of the eigenvalues of T).
-__global__ void __launch_bounds__(64)
-k_tri_eigvals(int m, const double *__restrict__ d_in, const double *__restrict__ e_in, double *__restrict__ lam,
-              double *__restrict__ lam2, int nout)
+__device__ __forceinline__ void tri_eigvals_body(int bx, int m, const double *__restrict__ d_in,
+                                                 const double *__restrict__ e_in, double *__restrict__ lam,
+                                                 double *__restrict__ lam2, int nout)
 {
     __shared__ double sd[kTriMax], se[kTriMax], se2[kTriMax];
-    const int lane = threadIdx.x, j = blockIdx.x;
+    const int lane = threadIdx.x, j = bx;
     for (int i = lane; i < m; i += 64) {
         sd[i] = d_in[i];
         se[i] = i + 1 < m ? e_in[i] : 0.0;
@@ -992,6 +1034,20 @@ k_tri_eigvals(int m, const double *__restrict__ d_in, const double *__restrict__
         if (lam2 && j < nout) lam2[j] = v;
     }
 }
+__global__ void __launch_bounds__(64)
+k_tri_eigvals(int m, const double *__restrict__ d_in, const double *__restrict__ e_in, double *__restrict__ lam,
+              double *__restrict__ lam2, int nout)
+{
+    tri_eigvals_body(blockIdx.x, m, d_in, e_in, lam, lam2, nout);
+}
+__global__ void __launch_bounds__(64) k_tri_eigvals_grp(GroupTab t)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const EigvalsArgs &a = *static_cast<const EigvalsArgs *>(t.args[e]);
+    tri_eigvals_body(bx, a.m, a.d, a.e, a.lam, a.lam2, a.nout);
+}
+
 
 // Eigenvectors of T by inverse iteration, one single-wave work-group per
 // cluster of eigenvalues (gaps below 1e-5 |T|; most clusters have one
@@ -1002,16 +1058,16 @@ k_tri_eigvals(int m, const double *__restrict__ d_in, const double *__restrict__
 // after every solve.  The LU factors and the iterate live in LDS; lane 0
 // runs the serial recurrences, the wavefront the vector operations.
 // Z: column j (m doubles) of eigenvector j.
-__global__ void __launch_bounds__(64)
-k_tri_eigvecs(int m, const double *__restrict__ d_in, const double *__restrict__ e_in, const double *__restrict__ lam,
-              double *__restrict__ Z)
+__device__ __forceinline__ void tri_eigvecs_body(int bx, int m, const double *__restrict__ d_in,
+                                                 const double *__restrict__ e_in, const double *__restrict__ lam,
+                                                 double *__restrict__ Z)
 {
     extern __shared__ double lds[];
     double *sd = lds, *se = lds + m;
     double *S0 = lds + 2 * m, *S1 = lds + 3 * m, *S2 = lds + 4 * m, *S3 = lds + 5 * m, *PV = lds + 6 * m;
     double *zw = lds + 7 * m;
     __shared__ double s_scale;
-    const int lane = threadIdx.x, j0 = blockIdx.x;
+    const int lane = threadIdx.x, j0 = bx;
     for (int i = lane; i < m; i += 64) {
         sd[i] = d_in[i];
         se[i] = i + 1 < m ? e_in[i] : 0.0;
@@ -1121,15 +1177,29 @@ k_tri_eigvecs(int m, const double *__restrict__ d_in, const double *__restrict__
         __syncthreads();
     }
 }
+__global__ void __launch_bounds__(64)
+k_tri_eigvecs(int m, const double *__restrict__ d_in, const double *__restrict__ e_in, const double *__restrict__ lam,
+              double *__restrict__ Z)
+{
+    tri_eigvecs_body(blockIdx.x, m, d_in, e_in, lam, Z);
+}
+__global__ void __launch_bounds__(64) k_tri_eigvecs_grp(GroupTab t)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const EigvecsArgs &a = *static_cast<const EigvecsArgs *>(t.args[e]);
+    tri_eigvecs_body(bx, a.m, a.d, a.e, a.lam, a.Z);
+}
+
 
 // Y = Q Z (complex m x m from real Z), one column per single-wave block:
 // y <- H_k y = y - tau_k v_k (v_k^H y), k = m-2 .. 0.
-__global__ void __launch_bounds__(64)
-k_backtransform(int m, const double2 *__restrict__ A, const double2 *__restrict__ tau, const double *__restrict__ Z,
-                double2 *__restrict__ Y)
+__device__ __forceinline__ void backtransform_body(int bx, int m, const double2 *__restrict__ A,
+                                                   const double2 *__restrict__ tau, const double *__restrict__ Z,
+                                                   double2 *__restrict__ Y)
 {
     extern __shared__ double2 y[];
-    const int j = blockIdx.x, lane = threadIdx.x;
+    const int j = bx, lane = threadIdx.x;
     for (int i = lane; i < m; i += 64) y[i] = make_double2(Z[(int64_t)j * m + i], 0.0);
     __syncthreads();
     for (int k = m - 2; k >= 0; --k) {
@@ -1157,6 +1227,20 @@ k_backtransform(int m, const double2 *__restrict__ A, const double2 *__restrict_
     }
     for (int i = lane; i < m; i += 64) Y[(int64_t)j * m + i] = y[i];
 }
+__global__ void __launch_bounds__(64)
+k_backtransform(int m, const double2 *__restrict__ A, const double2 *__restrict__ tau, const double *__restrict__ Z,
+                double2 *__restrict__ Y)
+{
+    backtransform_body(blockIdx.x, m, A, tau, Z, Y);
+}
+__global__ void __launch_bounds__(64) k_backtransform_grp(GroupTab t)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const BacktArgs &a = *static_cast<const BacktArgs *>(t.args[e]);
+    backtransform_body(bx, a.m, a.A, a.tau, a.Z, a.Y);
+}
+
 
 // M = L^H diag(dk) L (projector part of the shift bound)
 __global__ void k_lhdl(int m, const double2 *__restrict__ L, const double *__restrict__ dk, double2 *__restrict__ M)
@@ -1191,9 +1275,10 @@ __global__ void k_shift_final(const double *__restrict__ vmin, const double *__r
 }
 
 // After an outer iteration: stats row, next shift, convergence flag.
-__global__ void k_bookkeep(int nb, int n_conv, int shift_mode, double sigma_lb, double tol_res,
-                           const double *__restrict__ eps, const double *__restrict__ res, double *__restrict__ sig_all,
-                           double *__restrict__ sig_out, double *__restrict__ stats_row, int32_t *__restrict__ conv)
+__device__ __forceinline__ void bookkeep_body(int nb, int n_conv, int shift_mode, double sigma_lb, double tol_res,
+                                              const double *__restrict__ eps, const double *__restrict__ res,
+                                              double *__restrict__ sig_all, double *__restrict__ sig_out,
+                                              double *__restrict__ stats_row, int32_t *__restrict__ conv)
 {
     double sigma = sigma_lb;
     if (shift_mode == PARO_SHIFT_ADAPTIVE && res[0] < 0.1) {
@@ -1219,6 +1304,20 @@ __global__ void k_bookkeep(int nb, int n_conv, int shift_mode, double sigma_lb, 
         }
     }
 }
+__global__ void k_bookkeep(int nb, int n_conv, int shift_mode, double sigma_lb, double tol_res,
+                           const double *__restrict__ eps, const double *__restrict__ res, double *__restrict__ sig_all,
+                           double *__restrict__ sig_out, double *__restrict__ stats_row, int32_t *__restrict__ conv)
+{
+    bookkeep_body(nb, n_conv, shift_mode, sigma_lb, tol_res, eps, res, sig_all, sig_out, stats_row, conv);
+}
+// one work-group per entry; it: the outer iteration whose statistics row is written
+__global__ void k_bookkeep_grp(GroupTab t, int it)
+{
+    const BookArgs &a = *static_cast<const BookArgs *>(t.args[blockIdx.x]);
+    bookkeep_body(a.nb, a.n_conv, a.shift_mode, a.sigma_lb, a.tol_res, a.eps, a.res, a.sig_all, a.sig_out,
+                  a.stats ? a.stats + (size_t)(it + 1) * a.row : nullptr, a.conv);
+}
+
 
 }  // namespace
 
@@ -1375,6 +1474,125 @@ hipError_t launch_bookkeeping(const Plan &pl, int nb, const paro_iter_opts &o, c
     const int nconv = o.n_conv > 0 && o.n_conv <= nb ? o.n_conv : nb;
     hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(256), 0, pl.stream, nb, nconv, o.shift_mode, o.sigma_lb, o.tol_res,
                        eps, res, sig_all, sig_out, stats_row, conv);
+    return hipGetLastError();
+}
+
+}  // namespace paro
+
+namespace paro {
+
+// ---------------------------------------------------------------- grouped launches
+// The dense part of Rayleigh-Ritz (launch_rr_dense) for many cells at once,
+// for m <= 92: the one-work-group Cholesky, the three triangular solves,
+// the LDS-resident tridiagonalisation, eigenvalues, eigenvectors and the
+// back-transformation, each one launch for all cells.
+bool rr_dense_groupable(int m) { return m >= 1 && m <= kTridiagLdsMax; }
+
+void describe_rr_dense(const Plan &pl, const Workspace &w, int m, int n_keep, double *eps_out, double2 *C,
+                       GroupFinishArgs &f)
+{
+    DenseScratch s = dense_scratch(w, m);
+    double2 *L = w.dense[0], *X = w.dense[1], *Hh = w.dense[2], *Y = w.dense[3];
+    f.chol = CholArgs{w.gram, L, X, s.fail, pl.status, m, 1};
+    f.trsm[0] = TrsmArgs{L, X, X, m, 0, 0};
+    f.trsm[1] = TrsmArgs{L, X, Hh, m, 1, 0};
+    f.trsm[2] = TrsmArgs{L, Y, C, m, 0, 1};
+    f.tri = TridiagArgs{Hh, s.d, s.e, s.tau, m};
+    f.evals = EigvalsArgs{s.d, s.e, s.lam, eps_out, m, n_keep};
+    f.evecs = EigvecsArgs{s.d, s.e, s.lam, s.Z, m};
+    f.back = BacktArgs{Hh, s.tau, s.Z, Y, m};
+}
+
+void describe_bookkeeping(const Plan &pl, int nb, const paro_iter_opts &o, const double *eps, const double *res,
+                          double *sig_all, double *sig_out, double *stats, int32_t *conv, GroupFinishArgs &f)
+{
+    (void)pl;
+    const int nconv = o.n_conv > 0 && o.n_conv <= nb ? o.n_conv : nb;
+    f.book = BookArgs{eps, res, sig_all, sig_out, stats, conv, o.sigma_lb, o.tol_res, nb, nconv, o.shift_mode,
+                      2 * nb + 2};
+}
+
+namespace {
+
+// one entry per cell, blocks per entry from blocks_of(cell); launches every kGroupMax entries
+template <class A, class B, class L>
+void group_dense(const GroupCell *cells, int n, A args_of, B blocks_of, L launch)
+{
+    GroupBuilder g;
+    int mmax = 0;
+    for (int i = 0; i < n; ++i) {
+        const int m = cells[i].host->fin.chol.m;
+        const int64_t nbk = blocks_of(m);
+        g.add(args_of(cells[i].dev), nbk, (int)nbk);
+        mmax = std::max(mmax, m);
+        if (g.full() || i == n - 1) {
+            launch(g, mmax);
+            g = GroupBuilder();
+            mmax = 0;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_rr_dense_grouped(hipStream_t s, const GroupCell *cells, int n)
+{
+    if (n <= 0) return hipSuccess;
+    static const hipError_t lds_attr = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(k_tridiag_rows_grp<2, true, kTriWavesLds>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)tridiag_lds_bytes(kTridiagLdsMax, true));
+    if (lds_attr != hipSuccess) return lds_attr;
+    constexpr int W = 16;
+    auto one = [](int) { return (int64_t)1; };
+    auto cols = [](int m) { return (int64_t)m; };
+    group_dense(cells, n, [](const GroupCellDesc *d) { return (const void *)&d->fin.chol; }, one,
+                [&](const GroupBuilder &g, int mmax) {
+                    hipLaunchKernelGGL((k_rr_chol_rows_grp<2, W>), dim3(g.t.n), dim3(64 * W),
+                                       sizeof(double2) * (size_t)mmax, s, g.t);
+                });
+    for (int k = 0; k < 2; ++k)
+        group_dense(cells, n, [k](const GroupCellDesc *d) { return (const void *)&d->fin.trsm[k]; }, cols,
+                    [&](const GroupBuilder &g, int mmax) {
+                        hipLaunchKernelGGL(k_trsm_col_grp, dim3((unsigned)g.total), dim3(64),
+                                           sizeof(double2) * (size_t)mmax, s, g.t);
+                    });
+    group_dense(cells, n, [](const GroupCellDesc *d) { return (const void *)&d->fin.tri; }, one,
+                [&](const GroupBuilder &g, int mmax) {
+                    hipLaunchKernelGGL((k_tridiag_rows_grp<2, true, kTriWavesLds>), dim3(g.t.n),
+                                       dim3(64 * kTriWavesLds), tridiag_lds_bytes(mmax, true), s, g.t);
+                });
+    group_dense(cells, n, [](const GroupCellDesc *d) { return (const void *)&d->fin.evals; }, cols,
+                [&](const GroupBuilder &g, int) {
+                    hipLaunchKernelGGL(k_tri_eigvals_grp, dim3((unsigned)g.total), dim3(64), 0, s, g.t);
+                });
+    group_dense(cells, n, [](const GroupCellDesc *d) { return (const void *)&d->fin.evecs; }, cols,
+                [&](const GroupBuilder &g, int mmax) {
+                    hipLaunchKernelGGL(k_tri_eigvecs_grp, dim3((unsigned)g.total), dim3(64),
+                                       8 * (size_t)mmax * sizeof(double), s, g.t);
+                });
+    group_dense(cells, n, [](const GroupCellDesc *d) { return (const void *)&d->fin.back; }, cols,
+                [&](const GroupBuilder &g, int mmax) {
+                    hipLaunchKernelGGL(k_backtransform_grp, dim3((unsigned)g.total), dim3(64),
+                                       sizeof(double2) * (size_t)mmax, s, g.t);
+                });
+    group_dense(cells, n, [](const GroupCellDesc *d) { return (const void *)&d->fin.trsm[2]; }, cols,
+                [&](const GroupBuilder &g, int mmax) {
+                    hipLaunchKernelGGL(k_trsm_col_grp, dim3((unsigned)g.total), dim3(64),
+                                       sizeof(double2) * (size_t)mmax, s, g.t);
+                });
+    return hipGetLastError();
+}
+
+hipError_t launch_bookkeeping_grouped(hipStream_t s, const GroupCell *cells, int n, int it)
+{
+    GroupBuilder g;
+    for (int i = 0; i < n; ++i) {
+        g.add(&cells[i].dev->fin.book, 1, 1);
+        if (g.full() || i == n - 1) {
+            hipLaunchKernelGGL(k_bookkeep_grp, dim3(g.t.n), dim3(256), 0, s, g.t, it);
+            g = GroupBuilder();
+        }
+    }
     return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@
 // consecutive rows of C: stores are coalesced along the sphere.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "fft_device.h"
 #include "group.h"
@@ -737,31 +738,80 @@ void describe_nonlocal(const Plan &pl, const Workspace &w, int nb, GroupCellDesc
     describe_nonlocal_t<float2>(pl, w, nb, pl.beta32, w.p32, w.q32, d.f32);
 }
 
-template <class C2> hipError_t launch_nonlocal_grouped(hipStream_t s, const GroupCell *cells, int n)
+template <class C2> hipError_t launch_hn_grouped(hipStream_t s, const HnRef<C2> *v, int n)
 {
-    // cells with projectors, in groups of kGroupMax
     for (int i0 = 0; i0 < n;) {
-        GroupBuilder hn, red, nn;
+        GroupBuilder hn, red;
         int i = i0;
         for (; i < n && !hn.full(); ++i) {
-            const GroupCell &c = cells[i];
-            if (c.pl->nproj == 0) continue;
-            const GroupSolveArgs<C2> *a = group_solve_args<C2>(c.dev), *h = group_solve_args<C2>(c.host);
-            hn.add(&a->hn, h->hn.units, 1);
-            red.add(&a->hred, c.nb, c.nb);
-            nn.add(&a->nn, h->nn.units, 1);
+            hn.add(v[i].dev, v[i].host->units, 1);
+            red.add(v[i].dred, v[i].host->N, v[i].host->N);
         }
         i0 = i;
-        if (hn.t.n == 0) continue;
-        const unsigned whn = (unsigned)std::min<int64_t>((hn.total + 3) / 4, HnCfg<C2>::slots / 4);
-        const unsigned wnn = (unsigned)std::min<int64_t>((nn.total + 3) / 4, NnCfg<C2>::slots / 4);
-        hipLaunchKernelGGL((k_gemm_hn_part_grp<C2>), dim3(whn), dim3(256), 0, s, hn.t);
+        const unsigned w = (unsigned)std::min<int64_t>((hn.total + 3) / 4, HnCfg<C2>::slots / 4);
+        hipLaunchKernelGGL((k_gemm_hn_part_grp<C2>), dim3(w), dim3(256), 0, s, hn.t);
         hipLaunchKernelGGL((k_gemm_hn_reduce_grp<C2>), dim3((unsigned)red.total), dim3(256), 0, s, red.t);
-        hipLaunchKernelGGL((k_gemm_nn_grp<C2>), dim3(wnn), dim3(256), 0, s, nn.t);
     }
     return hipGetLastError();
 }
+
+template <class C2> hipError_t launch_nn_grouped(hipStream_t s, const NnRef<C2> *v, int n)
+{
+    for (int i0 = 0; i0 < n;) {
+        GroupBuilder nn;
+        int i = i0;
+        for (; i < n && !nn.full(); ++i) nn.add(v[i].dev, v[i].host->units, 1);
+        i0 = i;
+        const unsigned w = (unsigned)std::min<int64_t>((nn.total + 3) / 4, NnCfg<C2>::slots / 4);
+        hipLaunchKernelGGL((k_gemm_nn_grp<C2>), dim3(w), dim3(256), 0, s, nn.t);
+    }
+    return hipGetLastError();
+}
+
+template <class C2> hipError_t launch_nonlocal_grouped(hipStream_t s, const GroupCell *cells, int n)
+{
+    // cells with projectors
+    std::vector<HnRef<C2>> hv;
+    std::vector<NnRef<C2>> nv;
+    for (int i = 0; i < n; ++i) {
+        const GroupCell &c = cells[i];
+        if (c.pl->nproj == 0) continue;
+        const GroupSolveArgs<C2> *a = group_solve_args<C2>(c.dev), *h = group_solve_args<C2>(c.host);
+        hv.push_back(HnRef<C2>{&a->hn, &h->hn, &a->hred});
+        nv.push_back(NnRef<C2>{&a->nn, &h->nn});
+    }
+    hipError_t e = launch_hn_grouped<C2>(s, hv.data(), (int)hv.size());
+    if (e == hipSuccess) e = launch_nn_grouped<C2>(s, nv.data(), (int)nv.size());
+    return e;
+}
+
+// The products of W = H U (nonlocal part) and of Rayleigh-Ritz for the
+// grouped finish of an outer iteration: as apply_full's gemm_hn / gemm_nn
+// on U and rayleigh_ritz's Gram and rotation products.
+void describe_finish_products(const Plan &pl, const Workspace &w, int m, int nkeep, const double2 *U,
+                              const double2 *W, int64_t ld, double2 *psi, double2 *hpsi, int64_t ldo,
+                              GroupFinishArgs &f)
+{
+    const int np = pl.nproj, bm = (m + 31) / 32;
+    int64_t nsplit = 0, kchunk = 0, units = 0;
+    if (np > 0) hn_split<double2>(np, m, pl.ng, w.part_elems, &nsplit, &kchunk, &units);
+    f.nl_hn = GemmHnArgs<double2>{pl.beta, pl.ldv, U, ld, w.part, pl.ng, kchunk, units, np, m, (np + 31) / 32, bm};
+    f.nl_red = GemmHnRedArgs<double2>{w.part, w.P, np, pl.dkb, nullptr, np, m, (int)nsplit};
+    f.nl_nn = GemmNnArgs<double2>{pl.beta, pl.ldv, w.P, np, const_cast<double2 *>(W), ld, pl.ng,
+                                  (pl.ng + 31) / 32 * bm, m, np, bm, 1};
+    hn_split<double2>(m, m, pl.ng, w.part_elems, &nsplit, &kchunk, &units);
+    f.s_hn = GemmHnArgs<double2>{U, ld, U, ld, w.part, pl.ng, kchunk, units, m, m, bm, bm};
+    f.h_hn = GemmHnArgs<double2>{U, ld, W, ld, w.part, pl.ng, kchunk, units, m, m, bm, bm};
+    f.s_red = GemmHnRedArgs<double2>{w.part, w.gram, m, nullptr, nullptr, m, m, (int)nsplit};
+    f.h_red = GemmHnRedArgs<double2>{w.part, w.gram + (size_t)m * m, m, nullptr, nullptr, m, m, (int)nsplit};
+    const int bk = (nkeep + 31) / 32;
+    f.rot_psi = GemmNnArgs<double2>{U, ld, w.dense[4], m, psi, ldo, pl.ng, (pl.ng + 31) / 32 * bk, nkeep, m, bk, 0};
+    f.rot_hpsi = GemmNnArgs<double2>{W, ld, w.dense[4], m, hpsi, ldo, pl.ng, (pl.ng + 31) / 32 * bk, nkeep, m, bk, 0};
+}
+
 template hipError_t launch_nonlocal_grouped<double2>(hipStream_t, const GroupCell *, int);
 template hipError_t launch_nonlocal_grouped<float2>(hipStream_t, const GroupCell *, int);
+template hipError_t launch_hn_grouped<double2>(hipStream_t, const HnRef<double2> *, int);
+template hipError_t launch_nn_grouped<double2>(hipStream_t, const NnRef<double2> *, int);
 
 }  // namespace paro

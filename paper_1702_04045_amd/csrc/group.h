@@ -175,12 +175,90 @@ template <class C2> struct GroupSolveArgs {
     PcgUpdateArgs<C2, C2> upd;
 };
 
-// Everything one cell's source solve needs, in the cell's workspace.
+// Rayleigh-Ritz, residuals and shift of Algorithm 1 (steps 4-5)
+struct CholArgs {
+    const double2 *gram;
+    double2 *L, *X;
+    int32_t *fail, *status;
+    int m, hs;
+};
+struct TrsmArgs {
+    const double2 *L, *src;
+    double2 *out;
+    int m, transb, mode;
+};
+struct TridiagArgs {
+    double2 *A;
+    double *d, *e;
+    double2 *tau;
+    int m;
+};
+struct EigvalsArgs {
+    const double *d, *e;
+    double *lam, *lam2;
+    int m, nout;
+};
+struct EigvecsArgs {
+    const double *d, *e, *lam;
+    double *Z;
+    int m;
+};
+struct BacktArgs {
+    const double2 *A, *tau;
+    const double *Z;
+    double2 *Y;
+    int m;
+};
+struct ResPartsArgs {
+    const double2 *psi, *hpsi;
+    int64_t ld;
+    const double *eps;
+    double *dots;
+    int64_t ng;
+};
+struct ResFinalArgs {
+    const double *dots;
+    double *res;
+    int nb, nparts;
+};
+struct BookArgs {
+    const double *eps, *res;
+    double *sig_all, *sig_out, *stats;  // stats: the statistics table (row it + 1 is written)
+    int32_t *conv;
+    double sigma_lb, tol_res;
+    int nb, n_conv, shift_mode, row;
+};
+struct GroupFinishArgs {
+    // W = H U
+    StickInvArgs<double2> sinv[kGroupChunks];
+    PlaneArgs<double2> plane[kGroupChunks];
+    StickFwdArgs<double2> sfwd[kGroupChunks];
+    GemmHnArgs<double2> nl_hn;
+    GemmHnRedArgs<double2> nl_red;
+    GemmNnArgs<double2> nl_nn;
+    // S = U^H U, H_s = U^H W, the dense eigenproblem, psi = U C, H psi = W C
+    GemmHnArgs<double2> s_hn, h_hn;
+    GemmHnRedArgs<double2> s_red, h_red;
+    CholArgs chol;
+    TrsmArgs trsm[3];
+    TridiagArgs tri;
+    EigvalsArgs evals;
+    EigvecsArgs evecs;
+    BacktArgs back;
+    GemmNnArgs<double2> rot_psi, rot_hpsi;
+    ResPartsArgs rparts;
+    ResFinalArgs rfinal;
+    BookArgs book;
+};
+
+// Everything one cell's source solve and Rayleigh-Ritz need, in the
+// cell's workspace.
 struct GroupCellDesc {
     GroupSolveArgs<double2> f64;
     GroupSolveArgs<float2> f32;
     PcgInitPartsArgs iparts;
     PcgScalarsArgs sc0, sc1;
+    GroupFinishArgs fin;
 };
 // device address of a cell descriptor's arguments for vectors of type C2
 template <class C2> inline const GroupSolveArgs<C2> *group_solve_args(const GroupCellDesc *d)

@@ -222,6 +222,34 @@ template <class C2> hipError_t launch_local_apply_grouped(hipStream_t s, const G
 // the projector products of the solve (FP64, and FP32 matrix cores)
 void describe_nonlocal(const Plan &pl, const Workspace &w, int nb, GroupCellDesc &d);
 template <class C2> hipError_t launch_nonlocal_grouped(hipStream_t s, const GroupCell *cells, int n);
+// matrix-core products of many cells (device arguments, and the host copy for the work counts)
+template <class C2> struct HnRef {
+    const GemmHnArgs<C2> *dev, *host;
+    const GemmHnRedArgs<C2> *dred;
+};
+template <class C2> struct NnRef {
+    const GemmNnArgs<C2> *dev, *host;
+};
+template <class C2> hipError_t launch_hn_grouped(hipStream_t s, const HnRef<C2> *v, int n);
+template <class C2> hipError_t launch_nn_grouped(hipStream_t s, const NnRef<C2> *v, int n);
+// The grouped end of an outer iteration of Algorithm 1 (W = H U,
+// Rayleigh-Ritz at m = nb <= 92, residuals, next shift)
+void describe_finish_local(const Plan &pl, const Workspace &w, int nb, const double2 *U, double2 *W, int64_t ld,
+                           GroupFinishArgs &f);
+hipError_t launch_finish_local_grouped(hipStream_t s, const GroupCell *cells, int n);
+void describe_finish_products(const Plan &pl, const Workspace &w, int m, int nkeep, const double2 *U,
+                              const double2 *W, int64_t ld, double2 *psi, double2 *hpsi, int64_t ldo,
+                              GroupFinishArgs &f);
+bool rr_dense_groupable(int m);
+void describe_rr_dense(const Plan &pl, const Workspace &w, int m, int n_keep, double *eps_out, double2 *C,
+                       GroupFinishArgs &f);
+hipError_t launch_rr_dense_grouped(hipStream_t s, const GroupCell *cells, int n);
+void describe_residuals(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
+                        int64_t ld, const double *eps, double *res, GroupFinishArgs &f);
+hipError_t launch_residuals_grouped(hipStream_t s, const GroupCell *cells, int n);
+void describe_bookkeeping(const Plan &pl, int nb, const paro_iter_opts &o, const double *eps, const double *res,
+                          double *sig_all, double *sig_out, double *stats, int32_t *conv, GroupFinishArgs &f);
+hipError_t launch_bookkeeping_grouped(hipStream_t s, const GroupCell *cells, int n, int it);
 
 }  // namespace paro
 

@@ -712,6 +712,44 @@ hipError_t source_solve_grouped(hipStream_t s, const std::vector<GroupCell> &gc,
 
 }  // extern "C++"
 
+// Steps 4-5 of Algorithm 1 for the given cells as grouped launches, each
+// cell's work that of its enqueue_finish: W = H U, Rayleigh-Ritz at m = nb
+// (Gram products, the dense eigenproblem, the rotations), residuals, the
+// next shift and the statistics row of iteration it.
+hipError_t finish_grouped(hipStream_t s, const std::vector<GroupCell> &gc, int it)
+{
+    const int n = (int)gc.size();
+    hipError_t e = launch_finish_local_grouped(s, gc.data(), n);
+    std::vector<HnRef<double2>> hv;
+    std::vector<NnRef<double2>> nv;
+    for (const GroupCell &c : gc)
+        if (c.pl->nproj > 0) {
+            hv.push_back(HnRef<double2>{&c.dev->fin.nl_hn, &c.host->fin.nl_hn, &c.dev->fin.nl_red});
+            nv.push_back(NnRef<double2>{&c.dev->fin.nl_nn, &c.host->fin.nl_nn});
+        }
+    if (e == hipSuccess) e = launch_hn_grouped<double2>(s, hv.data(), (int)hv.size());
+    if (e == hipSuccess) e = launch_nn_grouped<double2>(s, nv.data(), (int)nv.size());
+    // S = U^H U, then H_s = U^H W (each cell's split partials are reused)
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        hv.clear();
+        for (const GroupCell &c : gc)
+            hv.push_back(k == 0 ? HnRef<double2>{&c.dev->fin.s_hn, &c.host->fin.s_hn, &c.dev->fin.s_red}
+                                : HnRef<double2>{&c.dev->fin.h_hn, &c.host->fin.h_hn, &c.dev->fin.h_red});
+        e = launch_hn_grouped<double2>(s, hv.data(), n);
+    }
+    if (e == hipSuccess) e = launch_rr_dense_grouped(s, gc.data(), n);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        nv.clear();
+        for (const GroupCell &c : gc)
+            nv.push_back(k == 0 ? NnRef<double2>{&c.dev->fin.rot_psi, &c.host->fin.rot_psi}
+                                : NnRef<double2>{&c.dev->fin.rot_hpsi, &c.host->fin.rot_hpsi});
+        e = launch_nn_grouped<double2>(s, nv.data(), n);
+    }
+    if (e == hipSuccess) e = launch_residuals_grouped(s, gc.data(), n);
+    if (e == hipSuccess) e = launch_bookkeeping_grouped(s, gc.data(), n, it);
+    return e;
+}
+
 // The outer loop of run_cells with the cells in lockstep: every outer
 // iteration, the source problems of all cells still iterating run as
 // grouped launches on the first such cell's stream (ordered against each
@@ -742,6 +780,10 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
     hipEvent_t gev = events.ev[2 * n];
     std::vector<GroupCell> gc(n);
     std::vector<int> ncg(n);
+    // steps 4-5 grouped too: Algorithm 1 with Rayleigh-Ritz at m = nb <= 92
+    bool group_finish = true;
+    for (const CellRun &c : cells)
+        group_finish = group_finish && c.o.variant == PARO_VARIANT_PARO && rr_dense_groupable(c.nb);
     for (int i = 0; i < n; ++i) {
         CellRun &c = cells[i];
         const Plan &pl = *c.pl;
@@ -757,6 +799,13 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
             describe_pcg_mixed(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.iflags + c.nb, npq, d);
         else
             describe_pcg(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, Ut, lv, w.iflags + c.nb, mparo, npq, d);
+        if (group_finish) {
+            describe_finish_local(pl, w, c.nb, w.U, w.W, lv, d.fin);
+            describe_finish_products(pl, w, c.nb, c.nb, w.U, w.W, lv, c.psi, c.hpsi, c.ld, d.fin);
+            describe_rr_dense(pl, w, c.nb, c.nb, c.eps, w.dense[4], d.fin);
+            describe_residuals(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.res, d.fin);
+            describe_bookkeeping(pl, c.nb, c.o, c.eps, w.res, w.sig_all, c.sigma, c.stats, c.conv, d.fin);
+        }
         PARO_HIP_TRY(hipMemcpyAsync(w.desc, &d, sizeof(d), hipMemcpyHostToDevice, pl.stream));
         PARO_HIP_TRY(hipEventRecord(events.ev[n + i], pl.stream));
         gc[i] = GroupCell{&pl, &w, c.nb, (c.nb + kMaxBandsPerChunk - 1) / kMaxBandsPerChunk, w.desc, &d};
@@ -840,9 +889,23 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
                     PARO_CHECK_LAUNCH(launch_bookkeeping(*c.pl, c.nb, fixed, c.eps, c.w.res, c.w.sig_all, c.sigma,
                                                          nullptr, c.conv));
                     PARO_CHECK_LAUNCH(enqueue_solve(c));
+                    if (group_finish) {
+                        PARO_HIP_TRY(hipEventRecord(events.ev[i], c.pl->stream));
+                        PARO_HIP_TRY(hipStreamWaitEvent(gs, events.ev[i], 0));
+                    }
                 }
             }
-            PARO_CHECK_LAUNCH(enqueue_finish(c, iter[i]));
+            if (!group_finish) PARO_CHECK_LAUNCH(enqueue_finish(c, iter[i]));
+        }
+        if (group_finish) {
+            // steps 4-5 of every cell as grouped launches on the same stream, then
+            // each cell's stream waits for them
+            PARO_CHECK_LAUNCH(finish_grouped(gs, agc, iter[act[0]]));
+            PARO_HIP_TRY(hipEventRecord(gev, gs));
+            for (int i : act) PARO_HIP_TRY(hipStreamWaitEvent(cells[i].pl->stream, gev, 0));
+        }
+        for (int i : act) {
+            CellRun &c = cells[i];
             if (c.n_done) *c.n_done = iter[i] + 1;
             ++iter[i];
         }

@@ -335,16 +335,16 @@ __global__ void __launch_bounds__(kVecThreads) k_pcg_scalars_grp(GroupTab t, int
 }
 
 // partial sums of |hpsi - eps psi|^2
-__global__ void __launch_bounds__(kVecThreads)
-k_res_parts(int64_t ng, const double2 *__restrict__ psi, const double2 *__restrict__ hpsi, int64_t ld,
-            const double *__restrict__ eps, double *__restrict__ dots)
+__device__ __forceinline__ void res_parts_body(int bx, int by, int64_t ng, const double2 *__restrict__ psi,
+                                               const double2 *__restrict__ hpsi, int64_t ld,
+                                               const double *__restrict__ eps, double *__restrict__ dots)
 {
     __shared__ double red[kVecThreads / 64];
-    const int band = blockIdx.y;
+    const int band = by;
     const double e = eps[band];
     const double2 *x = psi + band * ld, *hx = hpsi + band * ld;
     double s = 0.0;
-    const int64_t g0 = (int64_t)blockIdx.x * kVecChunk;
+    const int64_t g0 = (int64_t)bx * kVecChunk;
     const int64_t g1 = g0 + kVecChunk < ng ? g0 + kVecChunk : ng;
     for (int64_t g = g0 + threadIdx.x; g < g1; g += kVecThreads) {
         const double2 v = x[g], hv = hx[g];
@@ -352,13 +352,35 @@ k_res_parts(int64_t ng, const double2 *__restrict__ psi, const double2 *__restri
         s += dx * dx + dy * dy;
     }
     s = block_sum<kVecThreads>(s, red);
-    if (threadIdx.x == 0) dots[(size_t)band * kMaxParts + blockIdx.x] = s;
+    if (threadIdx.x == 0) dots[(size_t)band * kMaxParts + bx] = s;
+}
+__global__ void __launch_bounds__(kVecThreads)
+k_res_parts(int64_t ng, const double2 *__restrict__ psi, const double2 *__restrict__ hpsi, int64_t ld,
+            const double *__restrict__ eps, double *__restrict__ dots)
+{
+    res_parts_body(blockIdx.x, blockIdx.y, ng, psi, hpsi, ld, eps, dots);
+}
+__global__ void __launch_bounds__(kVecThreads) k_res_parts_grp(GroupTab t)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const ResPartsArgs &a = *static_cast<const ResPartsArgs *>(t.args[e]);
+    res_parts_body(bx, by, a.ng, a.psi, a.hpsi, a.ld, a.eps, a.dots);
 }
 
 __global__ void k_res_final(int nb, int nparts, const double *__restrict__ dots, double *__restrict__ res)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < nb) res[b] = sqrt(sum_parts(dots + (size_t)b * kMaxParts, nparts));
+}
+// 256 threads per work-group, bands b = 256 bx + thread
+__global__ void __launch_bounds__(256) k_res_final_grp(GroupTab t)
+{
+    int e, bx, by;
+    group_block(t, e, bx, by);
+    const ResFinalArgs &a = *static_cast<const ResFinalArgs *>(t.args[e]);
+    const int b = bx * 256 + threadIdx.x;
+    if (b < a.nb) a.res[b] = sqrt(sum_parts(a.dots + (size_t)b * kMaxParts, a.nparts));
 }
 
 // partial sums of |e|^2
@@ -640,6 +662,35 @@ template <class C2> hipError_t launch_pcg_update_grouped(hipStream_t s, const Gr
                              });
     if (e != hipSuccess) return e;
     group_scalars(s, cells, n, [](const GroupCellDesc *d) { return (const void *)&d->sc1; }, 1);
+    return hipGetLastError();
+}
+
+void describe_residuals(const Plan &pl, const Workspace &w, int nb, const double2 *psi, const double2 *hpsi,
+                        int64_t ld, const double *eps, double *res, GroupFinishArgs &f)
+{
+    double *dots = w.dots + (size_t)DOT_RES * nb * kMaxParts;
+    f.rparts = ResPartsArgs{psi, hpsi, ld, eps, dots, pl.ng};
+    f.rfinal = ResFinalArgs{dots, res, nb, (int)nchunks(pl.ng)};
+}
+
+hipError_t launch_residuals_grouped(hipStream_t s, const GroupCell *cells, int n)
+{
+    if (n <= 0) return hipSuccess;
+    hipError_t e = group_vec(cells, n, [](const GroupCellDesc *d) { return (const void *)&d->fin.rparts; },
+                             [&](const GroupBuilder &g) {
+                                 hipLaunchKernelGGL(k_res_parts_grp, dim3((unsigned)g.total), dim3(kVecThreads), 0,
+                                                    s, g.t);
+                             });
+    if (e != hipSuccess) return e;
+    GroupBuilder g;
+    for (int i = 0; i < n; ++i) {
+        const int nbk = (cells[i].nb + 255) / 256;
+        g.add(&cells[i].dev->fin.rfinal, nbk, nbk);
+        if (g.full() || i == n - 1) {
+            hipLaunchKernelGGL(k_res_final_grp, dim3((unsigned)g.total), dim3(256), 0, s, g.t);
+            g = GroupBuilder();
+        }
+    }
     return hipGetLastError();
 }
 
