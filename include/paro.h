@@ -293,10 +293,17 @@ int32_t paro_iterate(paro_plan plan, int32_t nb, double *psi, double *hpsi, int6
  * paro_iterate(plans[i], nb[i], psi[i], hpsi[i], ld[i], eps[i], sigma[i],
  * &opts[i], stats ? stats[i] : NULL, ws[i], ws_bytes[i], n_done + i), with
  * bitwise the same results.  Each cell's kernels are enqueued on its plan's
- * stream: plans on different streams run concurrently on the GPU.  Every
- * outer iteration first enqueues the work of all cells and then waits for
- * them once (convergence test, negative-curvature retry) instead of once
- * per cell.  A cell stops at its own n_outer or tolerance.  Each cell needs
+ * stream: plans on different streams run concurrently on the GPU.  Two or
+ * more cells of one precision (FP64 or PARO_PREC_MIXED, not MParO II) share
+ * grouped launches instead: one launch of each kernel of the source
+ * problems (and, for ParO with nb <= 92, of the Rayleigh-Ritz step) covers
+ * all cells; these run on the first active cell's stream, ordered against
+ * the other cells' streams by events.  Every outer iteration first enqueues
+ * the work of all cells and then waits for them once (convergence test,
+ * negative-curvature retry) instead of once per cell.  With tol_res = 0 and
+ * the fixed shift in every cell and one stream for all plans, the call
+ * enqueues kernels only (no event, wait or host memory) and can be
+ * captured into a HIP graph.  A cell stops at its own n_outer or tolerance.  Each cell needs
  * its own workspace (paro_workspace_bytes(nb[i]) of its plan); cells that
  * share a plan share its stream and run one after the other.  stats may be
  * NULL, or hold NULL entries; n_done may be NULL.  Errors: as

@@ -232,6 +232,8 @@ template <class C2> struct NnRef {
 };
 template <class C2> hipError_t launch_hn_grouped(hipStream_t s, const HnRef<C2> *v, int n);
 template <class C2> hipError_t launch_nn_grouped(hipStream_t s, const NnRef<C2> *v, int n);
+// host bytes to device memory through kernel arguments (capturable)
+hipError_t upload_bytes(hipStream_t s, void *dst, const void *src, size_t bytes);
 // The grouped end of an outer iteration of Algorithm 1 (W = H U,
 // Rayleigh-Ritz at m = nb <= 92, residuals, next shift)
 void describe_finish_local(const Plan &pl, const Workspace &w, int nb, const double2 *U, double2 *W, int64_t ld,

@@ -760,24 +760,38 @@ hipError_t finish_grouped(hipStream_t s, const std::vector<GroupCell> &gc, int i
 int32_t run_cells_grouped(std::vector<CellRun> &cells)
 {
     const int n = (int)cells.size();
-    // host copies of the descriptors, then per cell: sigma, conv, band flags
-    auto block = [](const CellRun &c) { return sizeof(double) + (sizeof(int32_t) * (2 + c.nb) + 7) / 8 * 8; };
-    size_t bytes = sizeof(GroupCellDesc) * n;
-    for (const CellRun &c : cells) bytes += block(c);
+    // Host decisions exist only with a tolerance or the adaptive shift.
+    // They need, per cell, sigma, conv and the band flags in pinned host
+    // memory.
+    bool decide = false;
+    for (const CellRun &c : cells) decide = decide || c.o.tol_res > 0.0 || c.o.shift_mode == PARO_SHIFT_ADAPTIVE;
     PinnedHost host;
-    PARO_HIP_TRY(hipHostMalloc(&host.p, bytes, hipHostMallocDefault));
-    GroupCellDesc *hdesc = static_cast<GroupCellDesc *>(host.p);
-    char *q = static_cast<char *>(host.p) + sizeof(GroupCellDesc) * n;
-    for (CellRun &c : cells) {
-        c.scur = reinterpret_cast<double *>(q);
-        c.hconv = reinterpret_cast<int32_t *>(q + sizeof(double));
-        c.hflags = c.hconv + 2;
-        q += block(c);
+    if (decide) {
+        auto block = [](const CellRun &c) { return sizeof(double) + (sizeof(int32_t) * (2 + c.nb) + 7) / 8 * 8; };
+        size_t bytes = 0;
+        for (const CellRun &c : cells) bytes += block(c);
+        PARO_HIP_TRY(hipHostMalloc(&host.p, bytes, hipHostMallocDefault));
+        char *q = static_cast<char *>(host.p);
+        for (CellRun &c : cells) {
+            c.scur = reinterpret_cast<double *>(q);
+            c.hconv = reinterpret_cast<int32_t *>(q + sizeof(double));
+            c.hflags = c.hconv + 2;
+            q += block(c);
+        }
     }
+    // host copies of the descriptors (uploaded through kernel arguments)
+    std::vector<GroupCellDesc> hdesc(n);
+    // Cells on one stream need no events to order the grouped launches
+    // against their own work; with no host decision either, the call then
+    // enqueues kernels only and can be captured into a graph.
+    bool one_stream = true;
+    for (const CellRun &c : cells) one_stream = one_stream && c.pl->stream == cells[0].pl->stream;
     EventSet events;
-    events.ev.assign(2 * n + 1, nullptr);
-    for (int i = 0; i <= 2 * n; ++i) PARO_HIP_TRY(hipEventCreateWithFlags(&events.ev[i], hipEventDisableTiming));
-    hipEvent_t gev = events.ev[2 * n];
+    if (decide || !one_stream) {
+        events.ev.assign(n + 1, nullptr);
+        for (int i = 0; i <= n; ++i) PARO_HIP_TRY(hipEventCreateWithFlags(&events.ev[i], hipEventDisableTiming));
+    }
+    hipEvent_t gev = events.ev.empty() ? nullptr : events.ev[n];
     std::vector<GroupCell> gc(n);
     std::vector<int> ncg(n);
     // steps 4-5 grouped too: Algorithm 1 with Rayleigh-Ritz at m = nb <= 92
@@ -806,8 +820,7 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
             describe_residuals(pl, w, c.nb, c.psi, c.hpsi, c.ld, c.eps, w.res, d.fin);
             describe_bookkeeping(pl, c.nb, c.o, c.eps, w.res, w.sig_all, c.sigma, c.stats, c.conv, d.fin);
         }
-        PARO_HIP_TRY(hipMemcpyAsync(w.desc, &d, sizeof(d), hipMemcpyHostToDevice, pl.stream));
-        PARO_HIP_TRY(hipEventRecord(events.ev[n + i], pl.stream));
+        PARO_CHECK_LAUNCH(upload_bytes(pl.stream, w.desc, &d, sizeof(d)));
         gc[i] = GroupCell{&pl, &w, c.nb, (c.nb + kMaxBandsPerChunk - 1) / kMaxBandsPerChunk, w.desc, &d};
         ncg[i] = c.o.n_cg;
         if (c.o.initial_rr) {
@@ -854,19 +867,21 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
         ancg.clear();
         acr.clear();
         for (int i : act) {
-            PARO_HIP_TRY(hipEventRecord(events.ev[i], cells[i].pl->stream));
-            PARO_HIP_TRY(hipStreamWaitEvent(gs, events.ev[i], 0));
+            if (!one_stream) {
+                PARO_HIP_TRY(hipEventRecord(events.ev[i], cells[i].pl->stream));
+                PARO_HIP_TRY(hipStreamWaitEvent(gs, events.ev[i], 0));
+            }
             agc.push_back(gc[i]);
             ancg.push_back(ncg[i]);
             acr.push_back(&cells[i]);
         }
         if (mixed) PARO_CHECK_LAUNCH(source_solve_grouped<float2>(gs, agc, ancg, acr));
         else PARO_CHECK_LAUNCH(source_solve_grouped<double2>(gs, agc, ancg, acr));
-        PARO_HIP_TRY(hipEventRecord(gev, gs));
+        if (!one_stream) PARO_HIP_TRY(hipEventRecord(gev, gs));
         bool adaptive = false;
         for (int i : act) {
             CellRun &c = cells[i];
-            PARO_HIP_TRY(hipStreamWaitEvent(c.pl->stream, gev, 0));
+            if (!one_stream) PARO_HIP_TRY(hipStreamWaitEvent(c.pl->stream, gev, 0));
             if (c.o.shift_mode == PARO_SHIFT_ADAPTIVE) {
                 PARO_HIP_TRY(hipMemcpyAsync(c.hflags, c.w.iflags + c.nb, sizeof(int32_t) * c.nb,
                                             hipMemcpyDeviceToHost, c.pl->stream));
@@ -901,8 +916,10 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
             // steps 4-5 of every cell as grouped launches on the same stream, then
             // each cell's stream waits for them
             PARO_CHECK_LAUNCH(finish_grouped(gs, agc, iter[act[0]]));
-            PARO_HIP_TRY(hipEventRecord(gev, gs));
-            for (int i : act) PARO_HIP_TRY(hipStreamWaitEvent(cells[i].pl->stream, gev, 0));
+            if (!one_stream) {
+                PARO_HIP_TRY(hipEventRecord(gev, gs));
+                for (int i : act) PARO_HIP_TRY(hipStreamWaitEvent(cells[i].pl->stream, gev, 0));
+            }
         }
         for (int i : act) {
             CellRun &c = cells[i];
@@ -910,9 +927,6 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
             ++iter[i];
         }
     }
-    // the pinned host copies of the descriptors are freed on return: wait
-    // for the copies (long done by now), not for the cells' work
-    for (int i = 0; i < n; ++i) PARO_HIP_TRY(hipEventSynchronize(events.ev[n + i]));
     return PARO_OK;
 }
 

@@ -2,6 +2,9 @@
 // (Algorithm 1, step 3), residual norms (step 5) and the correction vectors
 // of Algorithm 2.  Every reduction goes through per-work-group partial sums
 // that the consumer adds in a fixed order, so runs are bitwise reproducible.
+#include <algorithm>
+#include <cstring>
+
 #include "fft_device.h"
 #include "group.h"
 #include "paro_internal.h"
@@ -662,6 +665,33 @@ template <class C2> hipError_t launch_pcg_update_grouped(hipStream_t s, const Gr
                              });
     if (e != hipSuccess) return e;
     group_scalars(s, cells, n, [](const GroupCellDesc *d) { return (const void *)&d->sc1; }, 1);
+    return hipGetLastError();
+}
+
+namespace {
+constexpr int kUploadWords = 240;  // 1920 bytes of kernel arguments per launch
+struct UploadChunk {
+    uint64_t w[kUploadWords];
+};
+__global__ void __launch_bounds__(256) k_store_words(uint64_t *__restrict__ dst, UploadChunk c, int nwords)
+{
+    for (int i = threadIdx.x; i < nwords; i += 256) dst[i] = c.w[i];
+}
+}  // namespace
+
+// Host bytes to device memory through kernel arguments: no host buffer has
+// to outlive the call, and the upload can be captured into a graph.
+hipError_t upload_bytes(hipStream_t s, void *dst, const void *src, size_t bytes)
+{
+    const size_t nw = (bytes + 7) / 8;
+    const uint64_t *w = static_cast<const uint64_t *>(src);
+    uint64_t *d = static_cast<uint64_t *>(dst);
+    for (size_t o = 0; o < nw; o += kUploadWords) {
+        UploadChunk c{};
+        const int k = (int)std::min<size_t>(kUploadWords, nw - o);
+        std::memcpy(c.w, w + o, (bytes - o * 8 < (size_t)k * 8) ? bytes - o * 8 : (size_t)k * 8);
+        hipLaunchKernelGGL(k_store_words, dim3(1), dim3(256), 0, s, d + o, c, k);
+    }
     return hipGetLastError();
 }
 

@@ -372,14 +372,17 @@ class Plan:
 
 
 def iterate_batch(plans, psis, n_outer, n_cg, sigma_lbs, variant=L.VARIANT_PARO, shift_mode=L.SHIFT_FIXED,
-                  initial_rr=True, n_conv=None, tol_res=0.0, precision=L.PREC_FP64, streams=None, stats=False):
+                  initial_rr=True, n_conv=None, tol_res=0.0, precision=L.PREC_FP64, streams=None, stats=False,
+                  hpsis=None, epss=None):
     """ParO outer iterations on many independent cells in one library call (paro_iterate_batch).
 
     plans[i] and psis[i] (its band-major complex128 block, updated in place) form cell i;
     sigma_lbs[i] its shift bound; n_conv and n_cg may be lists.  streams: torch streams (default
     priority) the cells are spread over round-robin (None: one per cell, at most 8); the
     cells' work is ordered after the current stream's and the current stream waits for all of
-    them at the end.  Returns a list of dict(psi, hpsi, eps, sigma, stats, n_done)."""
+    them at the end.  hpsis / epss: each cell's H psi and eps to continue from (with
+    initial_rr=False), updated in place.  Returns a list of dict(psi, hpsi, eps, sigma, stats,
+    n_done)."""
     torch = _torch()
     n = len(plans)
     assert n == len(psis) == len(sigma_lbs) and n > 0
@@ -393,8 +396,8 @@ def iterate_batch(plans, psis, n_outer, n_cg, sigma_lbs, variant=L.VARIANT_PARO,
     for i, (pl, psi) in enumerate(zip(plans, psis)):
         pl._check_block(psi)
         nb = psi.shape[0]
-        out.append(dict(psi=psi, hpsi=torch.zeros_like(psi),
-                        eps=torch.zeros(nb, dtype=torch.float64, device=dev),
+        out.append(dict(psi=psi, hpsi=hpsis[i] if hpsis is not None else torch.zeros_like(psi),
+                        eps=epss[i] if epss is not None else torch.zeros(nb, dtype=torch.float64, device=dev),
                         sigma=torch.zeros(1, dtype=torch.float64, device=dev),
                         stats=torch.full((n_outer + 1, 2 * nb + 2), float("nan"), dtype=torch.float64, device=dev)
                         if stats else None))
@@ -433,6 +436,28 @@ def iterate_batch(plans, psis, n_outer, n_cg, sigma_lbs, variant=L.VARIANT_PARO,
     for k, o in enumerate(out):
         o["n_done"] = int(done[k])
     return out
+
+
+def capture_batch(plans, psis, hpsis, epss, n_outer, n_cg, sigma_lbs, variant=L.VARIANT_PARO,
+                  precision=L.PREC_FP64):
+    """Capture n_outer fixed-shift outer iterations of a batch of cells on (psis, hpsis, epss),
+    in place and from their current contents, into a torch CUDA graph; replaying it continues
+    the iterations.  With the fixed shift, no tolerance and all cells on the capturing stream
+    the batch enqueues kernels only.  Workspaces are allocated before the capture.  Returns
+    the torch.cuda.CUDAGraph."""
+    torch = _torch()
+    dev = plans[0].device
+    for pl, psi in zip(plans, psis):
+        pl.workspace(psi.shape[0])
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.graph(g, stream=s):
+        iterate_batch(plans, psis, n_outer, n_cg, sigma_lbs, variant=variant, shift_mode=L.SHIFT_FIXED,
+                      initial_rr=False, tol_res=0.0, precision=precision, streams=[s], hpsis=hpsis,
+                      epss=epss)
+    torch.cuda.current_stream(dev).wait_stream(s)
+    return g
 
 
 def zgemm_hn(A, B, device=None):

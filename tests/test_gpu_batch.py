@@ -114,6 +114,33 @@ def test_grouped_batch_many_cells_two_chunks_uneven_pcg_steps():
         assert pl.status() == 0
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_captured_batch_replays_like_eager_runs(precision):
+    """Fixed-shift outer iterations of a grouped batch captured into a graph
+    (no host decisions): two replays, with other eager work between them,
+    equal two eager batch calls from the same state bitwise."""
+    import paper_1702_04045_amd as P
+    torch = _torch()
+    cells = build(small_specs(), seed0=90)
+    plans = [c[3] for c in cells]
+    sig = [pl.shift_lower_bound() for pl in plans]
+    first = P.iterate_batch(plans, [to_dev(c[4]) for c in cells], 0, 8, sig, initial_rr=True)
+    clone = lambda key: [o[key].clone() for o in first]  # noqa: E731
+    ge, he, ee = clone("psi"), clone("hpsi"), clone("eps")
+    gg, hg, eg = clone("psi"), clone("hpsi"), clone("eps")
+    g = P.capture_batch(plans, gg, hg, eg, 3, 8, sig, precision=precision)
+    for rep in range(2):
+        g.replay()
+        P.iterate_batch(plans, ge, 3, 8, sig, initial_rr=False, hpsis=he, epss=ee, precision=precision)
+        torch.cuda.synchronize()
+        for k in range(len(cells)):
+            assert torch.equal(gg[k], ge[k]) and torch.equal(hg[k], he[k]) and torch.equal(eg[k], ee[k]), (rep, k)
+        # unrelated eager work between the replays
+        plans[0].iterate(to_dev(cells[0][4]), 2, 4, sig[0])
+    for pl in plans:
+        assert pl.status() == 0
+
+
 def test_batch_cell_matches_oracle():
     """A cell with projectors inside a batch against the oracle's fixed-shift ParO histories."""
     import paper_1702_04045_amd as P
