@@ -265,6 +265,19 @@ def batched_cells(args, P, torch, n_outer=5, n_cg=10, n_streams=8, reps=3):
 
     graph = P.capture_batch(plans, st_g[0], st_g[1], st_g[2], n_outer, n_cg, sig)
     f_eager, f_graph = best(eager_fixed), best(graph.replay)
+    del graph
+    # the plane stage's schedule and bands per work-group tuned per cell, then the same runs
+    t0 = time.perf_counter()
+    tuned = [pl.autotune(x.shape[0], force=True) for pl, x in zip(plans, xs)]
+    t_tune = time.perf_counter() - t0
+    prec[0] = P.PREC_FP64
+    a_seq, a_bat = best(sequential), best(batch)
+    prec[0] = P.PREC_MIXED
+    am_seq, am_bat = best(sequential), best(batch)
+    choices = {}
+    for sp, r in zip(specs, tuned):
+        key = f"{sp.grid}: schedule {r['schedule'][0]}/{r['schedule'][1]}, bands {r['bands'][0]}/{r['bands'][1]}"
+        choices[key] = choices.get(key, 0) + 1
     applies = sum(x.shape[0] for x in xs) * (n_cg + 1) * n_outer
     return {"cells": len(specs), "grids": sorted({sp.grid for sp in specs}),
             "bands": [sp.n_bands for sp in specs], "plane_waves": [pl.ng for pl in plans],
@@ -278,7 +291,14 @@ def batched_cells(args, P, torch, n_outer=5, n_cg=10, n_streams=8, reps=3):
                       "dtype": "f32 source problems, f64 H U and Rayleigh-Ritz"},
             "fixed_shift_graph": {"eager_seconds": f_eager, "graph_replay_seconds": f_graph,
                                   "speedup": f_eager / f_graph,
-                                  "note": "fixed shift, no initial Rayleigh-Ritz: the batch captured once and replayed"}}
+                                  "note": "fixed shift, no initial Rayleigh-Ritz: the batch captured once and replayed"},
+            "autotuned": {"tune_seconds": t_tune, "seconds": a_bat, "sequential_seconds": a_seq,
+                          "speedup_vs_sequential": a_seq / a_bat, "speedup_vs_untuned_batch": t_bat / a_bat,
+                          "mixed_seconds": am_bat, "mixed_sequential_seconds": am_seq,
+                          "mixed_speedup_vs_untuned_batch": m_bat / am_bat,
+                          "cell_iterations_per_s": len(specs) * n_outer / a_bat,
+                          "choices (grid: FP64/FP32)": choices,
+                          "note": "paro_plan_autotune per cell: plane-stage line schedule and bands per work-group"}}
 
 
 def at_scale(args, P, torch, steps=3, tta=False, tta_seconds=600.0):

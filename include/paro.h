@@ -187,6 +187,50 @@ int32_t paro_workspace_bytes(paro_plan plan, int32_t nb, size_t *bytes);
 int32_t paro_get_kinetic(paro_plan plan, double *kin_dev);
 int32_t paro_get_projectors(paro_plan plan, double *beta_dev);
 
+/* ------------------------------------------------------------ autotuning */
+
+/* Launch choices of the z-plane stage of the local part of H (the n2 / n1
+ * transforms and the multiply by vloc, eq. (e5)), per plan and per
+ * precision (PARO_PREC_FP64; PARO_PREC_MIXED and PARO_PREC_MIXED_BF16 share
+ * the FP32 choice):
+ *   schedule  the line schedule of the transforms, 0 <= schedule <
+ *             n_schedules: threads per line and radix order.  Grids of 24
+ *             to 80 points have 3; the others 1.  Another schedule changes
+ *             the rounding of the transforms (their radix order), not what
+ *             they compute.
+ *   bands     bands one work-group takes through its z-plane (1 .. 64;
+ *             default 4).  Results are bitwise the same for every value.
+ * A new plan starts at schedule 0 and 4 bands.  set_schedule re-lays the
+ * plan's potential tables for the new schedule on the plan's stream and
+ * waits for it: call it while no work that uses the plan is in flight.
+ * Errors: PARO_EINVAL (NULL plan, unknown precision, values out of range). */
+int32_t paro_plan_set_schedule(paro_plan plan, int32_t precision, int32_t schedule, int32_t bands);
+int32_t paro_plan_get_schedule(paro_plan plan, int32_t precision, int32_t *schedule, int32_t *bands,
+                               int32_t *n_schedules);
+
+#define PARO_TUNE_FORCE 1  /* time again even if a plan of this shape was tuned before */
+
+typedef struct {
+    int32_t schedule[2];   /* chosen schedule: [0] FP64, [1] FP32 */
+    int32_t bands[2];      /* chosen bands per work-group */
+    double ms[2];          /* plane-stage time on nb bands with the choice, ms */
+    double ms_default[2];  /* the same with schedule 0 and 4 bands */
+    int32_t candidates;    /* configurations timed per precision */
+    int32_t cached;        /* 1: both choices came from an earlier tuning of this shape */
+} paro_tune_result;
+
+/* Time every (schedule, bands) pair of the plane stage on this plan's own
+ * shape with nb bands (in the 64-band chunks the solver uses), for both
+ * precisions, and select the fastest (the default unless another is more
+ * than 1 % faster).  The choice of a shape (grid, sticks, columns, nb) is
+ * kept for the process: a later plan of the same shape takes it without
+ * timing unless flags has PARO_TUNE_FORCE.  ws: a workspace of
+ * paro_workspace_bytes(nb); its contents are overwritten.  Synchronises the
+ * plan's stream; not capturable.  result may be NULL.  Errors: PARO_EINVAL,
+ * PARO_ESIZE, PARO_EHIP. */
+int32_t paro_plan_autotune(paro_plan plan, int32_t nb, void *ws, size_t ws_bytes, int32_t flags,
+                           paro_tune_result *result);
+
 /* ---------------------------------------------------------------- hot path */
 
 /* hpsi_b = (H - shift_b) psi_b for b < nb.  The matrix elements are

@@ -16,6 +16,7 @@ F_NEGCURV, F_CHOL, F_NAN = 1, 2, 4
 SHIFT_FIXED, SHIFT_ADAPTIVE = 0, 1
 VARIANT_PARO, VARIANT_MPARO1, VARIANT_MPARO2 = 0, 1, 2
 PREC_FP64, PREC_MIXED, PREC_MIXED_BF16 = 0, 1, 2
+TUNE_FORCE = 1
 K_STICK_INV, K_PLANE, K_STICK_FWD, K_GEMM_HN, K_GEMM_NN, K_PCG_UPDATE, K_DENSITY = 1, 2, 3, 4, 5, 6, 7
 
 ERRORS = {PARO_EINVAL: "EINVAL", PARO_EALIAS: "EALIAS", PARO_ESIZE: "ESIZE", PARO_EHIP: "EHIP",
@@ -44,6 +45,11 @@ class PlanInfo(C.Structure):
                 ("n_proj", C.c_int32), ("omega", C.c_double)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("schedule", C.c_int32 * 2), ("bands", C.c_int32 * 2), ("ms", C.c_double * 2),
+                ("ms_default", C.c_double * 2), ("candidates", C.c_int32), ("cached", C.c_int32)]
+
+
 class IterOpts(C.Structure):
     _fields_ = [("n_outer", C.c_int32), ("n_cg", C.c_int32), ("n_conv", C.c_int32), ("shift_mode", C.c_int32),
                 ("variant", C.c_int32), ("initial_rr", C.c_int32), ("sigma_lb", C.c_double),
@@ -63,6 +69,10 @@ SIGNATURES = {
     "paro_plan_destroy": (C.c_int32, [_vp]),
     "paro_plan_set_stream": (C.c_int32, [_vp, _vp]),
     "paro_plan_get_info": (C.c_int32, [_vp, C.POINTER(PlanInfo)]),
+    "paro_plan_set_schedule": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.c_int32]),
+    "paro_plan_get_schedule": (C.c_int32, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_int32)]),
+    "paro_plan_autotune": (C.c_int32, [_vp, C.c_int32, _vp, C.c_size_t, C.c_int32, C.POINTER(TuneResult)]),
     "paro_workspace_bytes": (C.c_int32, [_vp, C.c_int32, C.POINTER(_sz)]),
     "paro_get_kinetic": (C.c_int32, [_vp, _vp]),
     "paro_get_projectors": (C.c_int32, [_vp, _vp]),

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libparo.so")
 
-SOURCES = ["plan.hip", "apply.hip", "gemm.hip", "gemm_bf16.hip", "vec.hip", "dense.hip", "solver.hip", "adjoint.hip"]
+SOURCES = ["plan.hip", "apply.hip", "gemm.hip", "gemm_bf16.hip", "vec.hip", "dense.hip", "solver.hip", "adjoint.hip", "tune.hip"]
 ARCH = os.environ.get("PARO_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: no packed FP32 instructions anywhere in this library.

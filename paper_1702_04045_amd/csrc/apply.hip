@@ -14,6 +14,7 @@
 // is contiguous for the plane kernel and the stick kernels write rows of
 // consecutive sticks.
 #include <type_traits>
+#include <vector>
 
 #include "fft_device.h"
 #include "group.h"
@@ -46,8 +47,10 @@ template <int T> __device__ __forceinline__ int line_of(int tid)
 template <int T> __device__ __forceinline__ int thread_in_line(int tid) { return (tid & 63) / (64 / T); }
 
 // threads of the plane kernel: one line slot per row, rounded up to whole wavefronts
-template <int N, class C2> constexpr int plane_threads() { return (N * PlaneCfgP<N, C2>::T + 63) / 64 * 64; }
-constexpr int kBandsPerBlock = 4;  // bands one work-group of the plane kernel takes through its z-plane
+template <int N, class C2, int V = 0> constexpr int plane_threads()
+{
+    return (N * PlaneSched<N, C2, V>::T + 63) / 64 * 64;
+}
 // Line transforms done across lanes (xlane96_inverse / xlane96_forward)
 // instead of through LDS: the 96-point lines, both precisions.
 template <int N, class C2> constexpr bool xlane_rows() { return N == 96 || N == 160; }
@@ -180,13 +183,13 @@ __global__ void __launch_bounds__((stick_threads<N3, C2>())) k_stick_inv_grp(Gro
 // stored in the order the row threads hold their values, so each thread
 // reads E consecutive doubles, which the bands of the work-group share
 // through the cache.
-template <int N, class C2>
+template <int N, class C2, int V>
 __device__ __forceinline__ void plane_body(int bx, int by, C2 *__restrict__ sticks, int nst, int N3, int nb,
                                            const int32_t *__restrict__ cols, const RealOf<C2> *__restrict__ vperm,
-                                           int nmax1, const C2 *__restrict__ tw)
+                                           int nmax1, const C2 *__restrict__ tw, int bpb)
 {
     using VR = RealOf<C2>;
-    using C = PlaneCfgP<N, C2>;
+    using C = PlaneSched<N, C2, V>;
     static_assert(C::T * C::E == N && ListInfo<typename C::Inv>::last == ListInfo<typename C::Fwd>::first,
                   "bad plane FFT config");
     using Inv = typename C::Inv;
@@ -197,9 +200,9 @@ __device__ __forceinline__ void plane_body(int bx, int by, C2 *__restrict__ stic
     __shared__ C2 twl[N];  // LDS copy of the twiddle table
     const int tid = threadIdx.x;
     const int z = bx;
-    for (int i = tid; i < N; i += plane_threads<N, C2>()) twl[i] = tw[i];
+    for (int i = tid; i < N; i += plane_threads<N, C2, V>()) twl[i] = tw[i];
     __syncthreads();
-    const int b0 = by * kBandsPerBlock, b1 = min(b0 + kBandsPerBlock, nb);
+    const int b0 = by * bpb, b1 = min(b0 + bpb, nb);
     const int nbk = b1 - b0;
     const int ncol = 2 * nmax1 + 1;
     const int slot = line_of<T>(tid), t = thread_in_line<T>(tid);
@@ -308,7 +311,7 @@ __device__ __forceinline__ void plane_body(int bx, int by, C2 *__restrict__ stic
                 // the populated entries, no wave synchronisation.  All N
                 // line slots are rows here (N T threads), so every lane of
                 // each wavefront takes part in the swaps.
-                static_assert(plane_threads<N, C2>() == N * T && T == 8 && E == 12, "cross-lane rows: 96 x 8 lanes");
+                static_assert(plane_threads<N, C2, V>() == N * T && T == 8 && E == 12, "cross-lane rows: 96 x 8 lanes");
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int i = t + T * m;
@@ -345,23 +348,23 @@ __device__ __forceinline__ void plane_body(int bx, int by, C2 *__restrict__ stic
         __syncthreads();
     }
 }
-template <int N, class C2>
-__global__ void __launch_bounds__((plane_threads<N, C2>()))
-__attribute__((amdgpu_waves_per_eu(PlaneCfgP<N, C2>::min_waves)))
+template <int N, class C2, int V>
+__global__ void __launch_bounds__((plane_threads<N, C2, V>()))
+__attribute__((amdgpu_waves_per_eu(PlaneSched<N, C2, V>::min_waves)))
 k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restrict__ cols,
-        const RealOf<C2> *__restrict__ vperm, int nmax1, const C2 *__restrict__ tw)
+        const RealOf<C2> *__restrict__ vperm, int nmax1, const C2 *__restrict__ tw, int bpb)
 {
-    plane_body<N, C2>(blockIdx.x, blockIdx.y, sticks, nst, N3, nb, cols, vperm, nmax1, tw);
+    plane_body<N, C2, V>(blockIdx.x, blockIdx.y, sticks, nst, N3, nb, cols, vperm, nmax1, tw, bpb);
 }
-template <int N, class C2>
-__global__ void __launch_bounds__((plane_threads<N, C2>()))
-__attribute__((amdgpu_waves_per_eu(PlaneCfgP<N, C2>::min_waves)))
+template <int N, class C2, int V>
+__global__ void __launch_bounds__((plane_threads<N, C2, V>()))
+__attribute__((amdgpu_waves_per_eu(PlaneSched<N, C2, V>::min_waves)))
 k_plane_grp(GroupTab t)
 {
     int e, bx, by;
     group_block(t, e, bx, by);
     const PlaneArgs<C2> &a = *static_cast<const PlaneArgs<C2> *>(t.args[e]);
-    plane_body<N, C2>(bx, by, a.sticks, a.nst, a.N3, a.nb, a.cols, a.vperm, a.nmax1, a.tw);
+    plane_body<N, C2, V>(bx, by, a.sticks, a.nst, a.N3, a.nb, a.cols, a.vperm, a.nmax1, a.tw, a.bpb);
 }
 
 
@@ -568,24 +571,48 @@ k_density_reduce(const double *__restrict__ part, int ngroups, int N3, int accum
     }
 }
 
-// Potential in the row-thread order of k_plane<N>: out[((z N + y) T + t) E + e]
+// Potential in the row-thread order of k_plane<N, C2, V>: out[((z N + y) T + t) E + e]
 // = V(i1 = x(t, e), i2 = y, i3 = z), x(t, e) = t + T (e / RL) + (e % RL)(N / RL)
 // after the Stockham passes, xlane_index(t, e) after the cross-lane rows;
 // from vloc in C order [i1][i2][i3].
+template <int N, class C2, int V> int plane_x(int t, int e)
+{
+    using C = PlaneSched<N, C2, V>;
+    constexpr int T = C::T, RL = ListInfo<typename C::Inv>::last;
+    if constexpr (xlane_rows<N, C2>()) return xl_index<N>(t, e);
+    else return t + T * (e / RL) + (e % RL) * (N / RL);
+}
 template <int N, class VT>
 void plane_potential(const int32_t *grid, const double *vloc, VT *out)
 {
     using C2 = typename std::conditional<std::is_same<VT, float>::value, float2, double2>::type;
-    using C = PlaneCfgP<N, C2>;
-    constexpr int T = C::T, E = C::E, RL = ListInfo<typename C::Inv>::last;
+    using C = PlaneSched<N, C2, 0>;
+    constexpr int T = C::T, E = C::E;
     const int N2 = grid[1], N3 = grid[2];
     for (int z = 0; z < N3; ++z)
         for (int y = 0; y < N2; ++y)
             for (int t = 0; t < T; ++t)
                 for (int e = 0; e < E; ++e) {
-                    const int x = xlane_rows<N, C2>() ? xl_index<N>(t, e) : t + T * (e / RL) + (e % RL) * (N / RL);
+                    const int x = plane_x<N, C2, 0>(t, e);
                     out[(((size_t)z * N + y) * T + t) * E + e] = (VT)vloc[((size_t)x * N2 + y) * N3 + z];
                 }
+}
+// n1 index of every row position p = t E + e of schedule V
+template <int N, class C2> bool row_order(int V, int32_t *x)
+{
+    auto fill = [&](auto vc) {
+        constexpr int VV = decltype(vc)::value;
+        using C = PlaneSched<N, C2, VV>;
+        for (int t = 0; t < C::T; ++t)
+            for (int e = 0; e < C::E; ++e) x[t * C::E + e] = plane_x<N, C2, VV>(t, e);
+    };
+    if (V == 0) fill(std::integral_constant<int, 0>());
+    else if constexpr (plane_nsched(N) > 1) {
+        if (V == 1) fill(std::integral_constant<int, 1>());
+        else if (V == 2) fill(std::integral_constant<int, 2>());
+        else return false;
+    } else return false;
+    return true;
 }
 
 // Sticks -> sphere, forward transform along n3, then
@@ -813,6 +840,27 @@ template <> struct PlanTabs<float2> {
     static const float2 *tw(const Plan &pl, int d) { return pl.tw32[d]; }
     static const float *v(const Plan &pl) { return pl.vplane32; }
 };
+template <class C2> constexpr int prec_index() { return sizeof(C2) == 8 ? 1 : 0; }
+
+// The plane kernel on cb bands of the stick buffer with the plan's line
+// schedule and bands per work-group for this precision.
+template <int N, class C2>
+void launch_plane(const Plan &pl, C2 *sticks, int cb)
+{
+    const int V = pl.plane_sched[prec_index<C2>()], bpb = pl.plane_bands[prec_index<C2>()];
+    const int N3 = pl.grid[2];
+    const dim3 grid(N3, (cb + bpb - 1) / bpb);
+    auto go = [&](auto vc) {
+        constexpr int VV = decltype(vc)::value;
+        hipLaunchKernelGGL((k_plane<N, C2, VV>), grid, dim3(plane_threads<N, C2, VV>()), 0, pl.stream, sticks, pl.nst,
+                           N3, cb, pl.cols, PlanTabs<C2>::v(pl), pl.nmax[0], PlanTabs<C2>::tw(pl, 0), bpb);
+    };
+    if constexpr (plane_nsched(N) > 1) {
+        if (V == 1) return go(std::integral_constant<int, 1>());
+        if (V == 2) return go(std::integral_constant<int, 2>());
+    }
+    go(std::integral_constant<int, 0>());
+}
 
 template <int N, class C2>
 hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const C2 *src, int64_t ld, C2 *out,
@@ -837,9 +885,7 @@ hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const C2 *src, 
                            first ? 1 : 0, sticks, pl.nst, pl.st_start, pl.pt_sz, PlanTabs<C2>::tw(pl, 2));
         prof_mark(PARO_K_STICK_INV, pl.stream, false);
         prof_mark(PARO_K_PLANE, pl.stream, true);
-        hipLaunchKernelGGL((k_plane<N, C2>), dim3(N3, (cb + kBandsPerBlock - 1) / kBandsPerBlock),
-                           dim3(plane_threads<N, C2>()), 0, pl.stream, sticks, pl.nst, N3, cb, pl.cols,
-                           PlanTabs<C2>::v(pl), pl.nmax[0], PlanTabs<C2>::tw(pl, 0));
+        launch_plane<N, C2>(pl, sticks, cb);
         prof_mark(PARO_K_PLANE, pl.stream, false);
         const C2 *x = pbuf ? pbuf : src;
         prof_mark(PARO_K_STICK_FWD, pl.stream, true);
@@ -933,7 +979,61 @@ hipError_t local_apply(const Plan &pl, const Workspace &w, int nb, const C2 *src
     }
 }
 
+template <class C2> hipError_t plane_only(const Plan &pl, const Workspace &w, int nb)
+{
+    C2 *sticks = reinterpret_cast<C2 *>(w.sticks);
+    for (int c0 = 0; c0 < nb; c0 += kMaxBandsPerChunk) {
+        const int cb = min(kMaxBandsPerChunk, nb - c0);
+        switch (pl.grid[0]) {
+#define PARO_CASE(n) \
+    case n: launch_plane<n, C2>(pl, sticks, cb); break;
+            PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
+            PARO_CASE(80) PARO_CASE(96)
+#undef PARO_CASE
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+template <class C2> bool row_order_rt(int n, int V, int32_t *x)
+{
+    switch (n) {
+#define PARO_CASE(k) \
+    case k: return row_order<k, C2>(V, x);
+    PARO_CASE(8) PARO_CASE(16) PARO_CASE(24) PARO_CASE(32) PARO_CASE(40) PARO_CASE(48) PARO_CASE(64)
+    PARO_CASE(80) PARO_CASE(96)
+#undef PARO_CASE
+    default: return false;
+    }
+}
+
 }  // namespace
+
+int plane_schedules(int n) { return fft_supported(n) && !big_grid(n) ? plane_nsched(n) : 1; }
+
+bool plane_row_map(int n, bool fp32, int from, int to, int32_t *map)
+{
+    std::vector<int32_t> xf(n), xt(n), pos(n, -1);
+    const bool ok = fp32 ? row_order_rt<float2>(n, from, xf.data()) && row_order_rt<float2>(n, to, xt.data())
+                         : row_order_rt<double2>(n, from, xf.data()) && row_order_rt<double2>(n, to, xt.data());
+    if (!ok) return false;
+    for (int p = 0; p < n; ++p) {
+        if (xf[p] < 0 || xf[p] >= n || pos[xf[p]] >= 0) return false;
+        pos[xf[p]] = p;
+    }
+    for (int p = 0; p < n; ++p) {
+        if (xt[p] < 0 || xt[p] >= n || pos[xt[p]] < 0) return false;
+        map[p] = pos[xt[p]];
+    }
+    return true;
+}
+
+hipError_t launch_plane_only(const Plan &pl, const Workspace &w, int nb, bool fp32)
+{
+    if (big_grid(pl.grid[0])) return hipErrorInvalidValue;
+    return fp32 ? plane_only<float2>(pl, w, nb) : plane_only<double2>(pl, w, nb);
+}
 
 bool fft_supported(int n)
 {
@@ -1017,12 +1117,14 @@ int describe_local_apply(const Plan &pl, const Workspace &w, int nb, const doubl
         double *dp = pq_parts + (size_t)c0 * kMaxParts;
         d.f64.sinv[c] = StickInvArgs<double2>{w.z + o, pl.ldv, w.p + o, beta + c0, w.sticks, pl.st_start, pl.pt_sz,
                                               pl.tw[2], pl.nst};
-        d.f64.plane[c] = PlaneArgs<double2>{w.sticks, pl.cols, pl.vplane, pl.tw[0], pl.nst, N3, cb, pl.nmax[0]};
+        d.f64.plane[c] = PlaneArgs<double2>{w.sticks, pl.cols, pl.vplane, pl.tw[0], pl.nst, N3, cb, pl.nmax[0],
+                                            pl.plane_bands[0]};
         d.f64.sfwd[c] = StickFwdArgs<double2>{w.sticks, pl.st_start, pl.pt_sz, pl.tw[2], w.p + o, pl.ldv, w.q + o,
                                               pl.kin, sh, scale, dp, pl.nst, kMaxParts};
         d.f32.sinv[c] = StickInvArgs<float2>{w.z32 + o, pl.ldv, w.p32 + o, beta + c0, sticks32, pl.st_start,
                                              pl.pt_sz, pl.tw32[2], pl.nst};
-        d.f32.plane[c] = PlaneArgs<float2>{sticks32, pl.cols, pl.vplane32, pl.tw32[0], pl.nst, N3, cb, pl.nmax[0]};
+        d.f32.plane[c] = PlaneArgs<float2>{sticks32, pl.cols, pl.vplane32, pl.tw32[0], pl.nst, N3, cb, pl.nmax[0],
+                                           pl.plane_bands[1]};
         d.f32.sfwd[c] = StickFwdArgs<float2>{sticks32, pl.st_start, pl.pt_sz, pl.tw32[2], w.p32 + o, pl.ldv,
                                              w.q32 + o, pl.kin, sh, scale, dp, pl.nst, kMaxParts};
     }
@@ -1055,24 +1157,38 @@ hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool fi
         if (N == 96 && kXlanePrune && cells[i].pl->grid[0] == N &&
             (cells[i].pl->nmax[0] > 23 || cells[i].pl->nmax[1] > 23 || cells[i].pl->nmax[2] > 23))
             return hipErrorInvalidValue;
+    constexpr int pi = prec_index<C2>();
     for (int r = 0; r < rounds; ++r) {
-        // the three kernels in turn, every entry of the round in each
-        for (int k = 0; k < 3; ++k) {
+        // the three kernels in turn, every entry of the round in each (the
+        // plane kernel once per line schedule the cells use)
+        constexpr int nv = plane_nsched(N);
+        for (int step = 0; step < nv + 2; ++step) {
+            const int k = step == 0 ? 0 : (step <= nv ? 1 : 2), V = k == 1 ? step - 1 : 0;
             GroupBuilder g;
             auto flush = [&]() {
                 if (g.t.n == 0) return;
                 const dim3 grid((unsigned)g.total);
                 if (k == 0)
                     hipLaunchKernelGGL((k_stick_inv_grp<N, C2>), grid, dim3(NT), 0, s, g.t, first ? 1 : 0);
-                else if (k == 1)
-                    hipLaunchKernelGGL((k_plane_grp<N, C2>), grid, dim3(plane_threads<N, C2>()), 0, s, g.t);
-                else
+                else if (k == 1) {
+                    auto go = [&](auto vc) {
+                        constexpr int VV = decltype(vc)::value;
+                        hipLaunchKernelGGL((k_plane_grp<N, C2, VV>), grid, dim3(plane_threads<N, C2, VV>()), 0, s,
+                                           g.t);
+                    };
+                    if constexpr (plane_nsched(N) > 1) {
+                        if (V == 1) go(std::integral_constant<int, 1>());
+                        else if (V == 2) go(std::integral_constant<int, 2>());
+                        else go(std::integral_constant<int, 0>());
+                    } else go(std::integral_constant<int, 0>());
+                } else
                     hipLaunchKernelGGL((k_stick_fwd_grp<N, C2>), grid, dim3(NT), 0, s, g.t);
                 g = GroupBuilder();
             };
             for (int i = 0; i < n; ++i) {
                 const GroupCell &c = cells[i];
                 if (c.pl->grid[0] != N || c.nchunk <= r) continue;
+                if (k == 1 && c.pl->plane_sched[pi] != V) continue;
                 const int cb = std::min(kMaxBandsPerChunk, c.nb - r * kMaxBandsPerChunk);
                 const int ntiles = (c.pl->nst + S - 1) / S;
                 const void *ai, *ap, *af;
@@ -1087,8 +1203,10 @@ hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool fi
                     af = &a->sfwd[r];
                 }
                 if (k == 0) g.add(ai, (int64_t)ntiles * cb, ntiles);
-                else if (k == 1)
-                    g.add(ap, (int64_t)c.pl->grid[2] * ((cb + kBandsPerBlock - 1) / kBandsPerBlock), c.pl->grid[2]);
+                else if (k == 1) {
+                    const int bpb = c.pl->plane_bands[pi];
+                    g.add(ap, (int64_t)c.pl->grid[2] * ((cb + bpb - 1) / bpb), c.pl->grid[2]);
+                }
                 else g.add(af, (int64_t)ntiles * cb, ntiles);
                 if (g.full()) flush();
             }
@@ -1123,7 +1241,8 @@ void describe_finish_local(const Plan &pl, const Workspace &w, int nb, const dou
         const int64_t o = (int64_t)c0 * ld;
         f.sinv[c] = StickInvArgs<double2>{U + o, ld, nullptr, nullptr, w.sticks, pl.st_start, pl.pt_sz, pl.tw[2],
                                           pl.nst};
-        f.plane[c] = PlaneArgs<double2>{w.sticks, pl.cols, pl.vplane, pl.tw[0], pl.nst, N3, cb, pl.nmax[0]};
+        f.plane[c] = PlaneArgs<double2>{w.sticks, pl.cols, pl.vplane, pl.tw[0], pl.nst, N3, cb, pl.nmax[0],
+                                        pl.plane_bands[0]};
         f.sfwd[c] = StickFwdArgs<double2>{w.sticks, pl.st_start, pl.pt_sz, pl.tw[2], U + o, ld, W + o, pl.kin,
                                           nullptr, scale, nullptr, pl.nst, kMaxParts};
     }

@@ -682,4 +682,33 @@ template <> struct PlaneCfgP<96, float2> : PlaneCfg<96> {
     static constexpr int min_waves = 6;  // two 12-wave work-groups per compute unit
 };
 
+// Line schedules of the z-plane kernel that a plan can select (the
+// autotuner times them on the plan's own shape).  Variant 0 is PlaneCfgP;
+// the grids that run the Stockham passes (24 to 80 points) have two more,
+// with other threads per line and radix orders.  Every list multiplies to
+// N, each radix divides E = N / T, and the inverse list ends on the radix
+// the forward list starts with, so the potential multiply stays in
+// registers between them.
+template <int N_, int T_, class Inv_, class Fwd_> struct SchedDef {
+    static constexpr int N = N_, T = T_, E = N_ / T_, min_waves = 1;
+    using Inv = Inv_;
+    using Fwd = Fwd_;
+};
+template <int N, class C2, int V> struct PlaneSched : PlaneCfgP<N, C2> {};
+template <class C2> struct PlaneSched<24, C2, 1> : SchedDef<24, 4, RList<6, 2, 2>, RList<2, 2, 6>> {};
+template <class C2> struct PlaneSched<24, C2, 2> : SchedDef<24, 2, RList<4, 6>, RList<6, 4>> {};
+template <class C2> struct PlaneSched<32, C2, 1> : SchedDef<32, 8, RList<4, 4, 2>, RList<2, 4, 4>> {};
+template <class C2> struct PlaneSched<32, C2, 2> : SchedDef<32, 2, RList<16, 2>, RList<2, 16>> {};
+template <class C2> struct PlaneSched<40, C2, 1> : SchedDef<40, 4, RList<10, 2, 2>, RList<2, 2, 10>> {};
+template <class C2> struct PlaneSched<40, C2, 2> : SchedDef<40, 2, RList<20, 2>, RList<2, 20>> {};
+template <class C2> struct PlaneSched<48, C2, 1> : SchedDef<48, 8, RList<6, 2, 2, 2>, RList<2, 2, 2, 6>> {};
+template <class C2> struct PlaneSched<48, C2, 2> : SchedDef<48, 2, RList<12, 4>, RList<4, 12>> {};
+template <class C2> struct PlaneSched<64, C2, 1> : SchedDef<64, 4, RList<16, 4>, RList<4, 16>> {};
+template <class C2> struct PlaneSched<64, C2, 2> : SchedDef<64, 16, RList<4, 4, 4>, RList<4, 4, 4>> {};
+template <class C2> struct PlaneSched<80, C2, 1> : SchedDef<80, 8, RList<10, 2, 2, 2>, RList<2, 2, 2, 10>> {};
+template <class C2> struct PlaneSched<80, C2, 2> : SchedDef<80, 4, RList<4, 4, 5>, RList<5, 4, 4>> {};
+// number of selectable schedules at N points
+__host__ __device__ constexpr int plane_nsched(int n) { return n >= 24 && n <= 80 ? 3 : 1; }
+constexpr int kPlaneSchedMax = 3;
+
 }  // namespace paro

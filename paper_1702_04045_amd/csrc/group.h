@@ -81,7 +81,7 @@ template <class C2> struct PlaneArgs {
     const int32_t *cols;
     const typename GReal<C2>::T *vperm;
     const C2 *tw;
-    int nst, N3, nb, nmax1;
+    int nst, N3, nb, nmax1, bpb;  // bpb: bands per work-group
 };
 template <class C2> struct StickFwdArgs {
     const C2 *sticks;

@@ -15,6 +15,8 @@ constexpr int kMaxBandsPerChunk = 64;  // bands per sphere->stick->plane pass (s
 constexpr int kPartSplits = 64;        // split-K partials the workspaces hold per output element
 constexpr int kMaxParts = 512;         // partial sums per band per reduction
 constexpr int kDensityBandsPerGroup = 8;  // bands one work-group of the density kernel sums
+constexpr int kPlaneBandsDefault = 4;     // bands per work-group of the plane kernel unless tuned
+constexpr int kPlaneBandsMax = 64;
 
 // per-band scalar slots (Workspace::sc, each nb long)
 enum { SC_GAMMA = 0, SC_GAMMA0, SC_TAU, SC_BETA, SC_NLQ, kScalars };
@@ -47,6 +49,11 @@ struct Plan {
     double *dkb = nullptr;        // KB energies
     int32_t *status = nullptr;    // sticky status bits
     int32_t *miller = nullptr;    // Miller indices of the sphere, ng x 3
+    // plane-stage launch choices per precision (0: FP64, 1: FP32): the line
+    // schedule (PlaneSched variant; vplane / vplane32 are laid out for it)
+    // and the bands one work-group takes through its z-plane
+    int32_t plane_sched[2] = {0, 0};
+    int32_t plane_bands[2] = {kPlaneBandsDefault, kPlaneBandsDefault};
 };
 
 // Workspace carve-up for calls on up to nb bands (m <= 2 nb for Rayleigh-Ritz).
@@ -109,6 +116,13 @@ bool big_grid(int n);
 // the local potential re-laid in the order the plane kernel's row threads use it
 void build_plane_potential(int n, const int32_t *grid, const double *vloc, double *out);
 void build_plane_potential(int n, const int32_t *grid, const double *vloc, float *out);
+// selectable line schedules of the plane stage at n points
+int plane_schedules(int n);
+// map[p'] = p: row position p of line schedule `from` that holds the entry
+// row position p' of schedule `to` holds (n entries; Stockham grids only)
+bool plane_row_map(int n, bool fp32, int from, int to, int32_t *map);
+// only the plane kernel of a local apply (the sticks as they are), for the autotuner
+hipError_t launch_plane_only(const Plan &pl, const Workspace &w, int nb, bool fp32);
 // Local part on nb bands: out_b = FFT^-1 (V FFT(x_b)) / N + (kin - shift_b) x_b,
 // x = src, or in PCG mode (pbuf != null) x = p with p <- z + beta_b p first
 // (first: p <- z) and src = z; dot_part then gets partial Re(x^H out).

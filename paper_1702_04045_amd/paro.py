@@ -144,6 +144,31 @@ class Plan:
         if nb is not None:
             assert x.shape[0] >= nb
 
+    # -------------------------------------------------------------- tuning
+    def set_schedule(self, precision, schedule, bands):
+        """Line schedule and bands per work-group of the plane stage for one precision
+        (paro_plan_set_schedule)."""
+        self._sync_stream()
+        L.check(self.lib.paro_plan_set_schedule(self.h, int(precision), int(schedule), int(bands)),
+                "paro_plan_set_schedule")
+
+    def get_schedule(self, precision):
+        s, b, n = C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(self.lib.paro_plan_get_schedule(self.h, int(precision), C.byref(s), C.byref(b), C.byref(n)),
+                "paro_plan_get_schedule")
+        return dict(schedule=s.value, bands=b.value, n_schedules=n.value)
+
+    def autotune(self, nb, force=False):
+        """Time the plane stage's schedules and bands per work-group on nb bands and keep the
+        fastest for both precisions (paro_plan_autotune)."""
+        ws, n = self.workspace(nb)
+        self._sync_stream()
+        r = L.TuneResult()
+        L.check(self.lib.paro_plan_autotune(self.h, int(nb), ws, n, L.TUNE_FORCE if force else 0, C.byref(r)),
+                "paro_plan_autotune")
+        return dict(schedule=list(r.schedule), bands=list(r.bands), ms=list(r.ms), ms_default=list(r.ms_default),
+                    candidates=int(r.candidates), cached=bool(r.cached))
+
     # -------------------------------------------------------------- data
     def kinetic(self):
         torch = _torch()
