@@ -73,17 +73,24 @@ template <int N> __host__ __device__ constexpr int xl_index(int t, int s)
 {
     return N == 96 ? xlane_index(t, s) : xlane_index_e<N / 8>(t, s);
 }
-template <int N> __device__ __forceinline__ constexpr bool xl_kept(int m) { return N == 96 ? xlane_kept(m) : true; }
+// At 160 points every populated |n| is at most 39 (160 >= 4 n_max + 1), so
+// x[t + 8 m] is zero for m = 5..14: the pruned 20-point DFTs.
+template <int N> __device__ __forceinline__ constexpr bool xl_kept(int m)
+{
+    return !kXlanePrune || (N == 96 ? xlane_kept(m) : xlane_kept_e<N / 8>(m));
+}
 template <int N, class C2> __device__ __forceinline__ void xl_inverse(C2 (&v)[N / 8], int t, const C2 *tw)
 {
     if constexpr (N == 96) xlane96_inverse<kXlanePrune>(v, t, tw);
-    else xlane_inverse_n<N>(v, t, tw);
+    else xlane_inverse_n<N, kXlanePrune>(v, t, tw);
 }
 template <int N, class C2> __device__ __forceinline__ void xl_forward(C2 (&v)[N / 8], int t, const C2 *tw)
 {
     if constexpr (N == 96) xlane96_forward<kXlanePrune>(v, t, tw);
-    else xlane_forward_n<N>(v, t, tw);
+    else xlane_forward_n<N, kXlanePrune>(v, t, tw);
 }
+// largest populated |n| the pruned lines of N points allow
+constexpr int xl_nmax_limit(int n) { return n == 96 ? 23 : n == 160 ? 39 : 1 << 30; }
 
 // Sphere -> sticks, inverse transform along n3.  Line (stick) threads are
 // consecutive lanes, so the exchanges between passes are wavefront-local.
@@ -760,7 +767,7 @@ k_plane_cc(const C2 *__restrict__ sin, C2 *__restrict__ sout, int nst, int N3, i
                 for (int m = 0; m < E; ++m) {
                     const int i = tt + T * m;
                     const int q = (i > N / 2 ? i - N : i) - lo;
-                    v[m] = (colact && (unsigned)q < (unsigned)n) ? tz[q] : cmk<C2>(0.0, 0.0);
+                    v[m] = (xl_kept<N>(m) && colact && (unsigned)q < (unsigned)n) ? tz[q] : cmk<C2>(0.0, 0.0);
                 }
                 xl_inverse<N>(v, opaque(t), twl);
                 if (colact) {
@@ -783,7 +790,7 @@ k_plane_cc(const C2 *__restrict__ sin, C2 *__restrict__ sout, int nst, int N3, i
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int i = tt + T * m;
-                    const bool pop = i <= nm || i >= N - nm;
+                    const bool pop = xl_kept<N>(m) && (i <= nm || i >= N - nm);
                     v[m] = pop ? plane[(i <= nm ? i + nm : i - N + nm) * LDY + r] : cmk<C2>(0.0, 0.0);
                 }
                 xl_inverse<N>(v, opaque(t), twl);
@@ -796,7 +803,8 @@ k_plane_cc(const C2 *__restrict__ sin, C2 *__restrict__ sout, int nst, int N3, i
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const int i = tw2 + T * m;
-                    if (i <= nm2 || i >= N - nm2) plane[(i <= nm2 ? i + nm2 : i - N + nm2) * LDY + r] = v[m];
+                    if (xl_kept<N>(m) && (i <= nm2 || i >= N - nm2))
+                        plane[(i <= nm2 ? i + nm2 : i - N + nm2) * LDY + r] = v[m];
                 }
             }
             __syncthreads();
@@ -818,7 +826,7 @@ k_plane_cc(const C2 *__restrict__ sin, C2 *__restrict__ sout, int nst, int N3, i
                     for (int m = 0; m < E; ++m) {
                         const int i = tt + T * m;
                         const int q = (i > N / 2 ? i - N : i) - lo;
-                        if ((unsigned)q < (unsigned)n) {
+                        if (xl_kept<N>(m) && (unsigned)q < (unsigned)n) {
                             if (p == 0) tz[q] = v[m];
                             else tz[q] = cadd(tz[q], v[m]);
                         }
@@ -912,6 +920,10 @@ hipError_t run_local_big(const Plan &pl, const Workspace &w, int nb, const C2 *s
     const int ntiles = (pl.nst + S - 1) / S;
     if (nparts_out) *nparts_out = ntiles;
     if (pl.ncol > kCcMaxCols) return hipErrorInvalidValue;
+    // the pruned lines leave out the entries |n| > 39
+    if (kXlanePrune && (pl.nmax[0] > xl_nmax_limit(N) || pl.nmax[1] > xl_nmax_limit(N) ||
+                        pl.nmax[2] > xl_nmax_limit(N)))
+        return hipErrorInvalidValue;
     const double scale = 1.0 / ((double)pl.grid[0] * pl.grid[1] * pl.grid[2]);
     C2 *sticks = reinterpret_cast<C2 *>(w.sticks);
     C2 *sticks2 = reinterpret_cast<C2 *>(w.sticks2);

@@ -635,14 +635,88 @@ template <int B, int E, class C2> __device__ __forceinline__ void xstage_fwd_e(C
         xswap<B>(a, b);
     }
 }
+// Pruned E-point DFTs for E = 4 B (the DftComp<4, B> order of Dft<E>), the
+// generalisation of the 12-point ones above.  A line whose populated
+// indices satisfy |n| < 2 E (|n| <= 39 at 160 points, which every plan
+// with N >= 4 n_max + 1 meets) holds zeros in x[t + 8 m] for
+// E / 4 <= m < 3 E / 4: the inputs B .. 3 B - 1, i.e. s_a = 1 and 2 of the
+// 4-point DFTs over x[B s_a + s_b].  Those outputs are never used either.
+template <int E> __host__ __device__ constexpr bool xlane_kept_e(int m) { return m < E / 4 || m >= 3 * E / 4; }
+
+template <int B, int SIGN, class C2> __device__ __forceinline__ void dft4b_twiddle(C2 (&b)[B], int ka)
+{
+    using S = RealOf<C2>;
+#pragma unroll
+    for (int sb = 1; sb < B; ++sb) {
+        const int j = sb * ka;
+        if (j != 0) {
+            const S c = (S)TwC<4 * B>::c[j], sn = (S)(SIGN * TwC<4 * B>::s[j]);
+            C2 r;
+            r.x = b[sb].x * c - b[sb].y * sn;
+            r.y = b[sb].x * sn + b[sb].y * c;
+            b[sb] = r;
+        }
+    }
+}
+// inputs B .. 3 B - 1 zero: each 4-point DFT sees only s_a = 0 and 3
+template <int B, int SIGN, class C2> __device__ __forceinline__ void dft4b_in_pruned(C2 (&v)[4 * B])
+{
+    C2 y[4 * B];
+#pragma unroll
+    for (int sb = 0; sb < B; ++sb) {
+        const C2 a0 = v[sb], a3 = v[3 * B + sb];
+        const C2 d = mul_si<SIGN>(a3);
+        y[sb * 4 + 0] = cadd(a0, a3);
+        y[sb * 4 + 2] = csub(a0, a3);
+        y[sb * 4 + 1] = csub(a0, d);
+        y[sb * 4 + 3] = cadd(a0, d);
+    }
+#pragma unroll
+    for (int ka = 0; ka < 4; ++ka) {
+        C2 b[B];
+#pragma unroll
+        for (int sb = 0; sb < B; ++sb) b[sb] = y[sb * 4 + ka];
+        dft4b_twiddle<B, SIGN>(b, ka);
+        Dft<B, SIGN>::run(b);
+#pragma unroll
+        for (int kb = 0; kb < B; ++kb) v[ka + 4 * kb] = b[kb];
+    }
+}
+// outputs B .. 3 B - 1 unused: only the kept outputs are stored (the
+// B-point DFTs' other outputs are dead code; the unkept v[k] keep stale values)
+template <int B, int SIGN, class C2> __device__ __forceinline__ void dft4b_out_pruned(C2 (&v)[4 * B])
+{
+    C2 y[4 * B];
+#pragma unroll
+    for (int sb = 0; sb < B; ++sb) {
+        C2 a[4] = {v[sb], v[B + sb], v[2 * B + sb], v[3 * B + sb]};
+        Dft<4, SIGN>::run(a);
+#pragma unroll
+        for (int ka = 0; ka < 4; ++ka) y[sb * 4 + ka] = a[ka];
+    }
+#pragma unroll
+    for (int ka = 0; ka < 4; ++ka) {
+        C2 b[B];
+#pragma unroll
+        for (int sb = 0; sb < B; ++sb) b[sb] = y[sb * 4 + ka];
+        dft4b_twiddle<B, SIGN>(b, ka);
+        Dft<B, SIGN>::run(b);
+#pragma unroll
+        for (int kb = 0; kb < B; ++kb)
+            if (xlane_kept_e<4 * B>(ka + 4 * kb)) v[ka + 4 * kb] = b[kb];
+    }
+}
+
 // tw[m] = exp(-2 pi i m / N).  Inverse: v[m] = x[t + 8 m] on entry,
 // v[s] = X[xlane_index_e<N / 8>(t, s)] (sign +1, unnormalised) on exit.
-template <int N, class C2>
+// PRUNE: inputs x[t + 8 m] with m not xlane_kept_e are zero (not read).
+template <int N, bool PRUNE = false, class C2>
 __device__ __forceinline__ void xlane_inverse_n(C2 (&v)[N / 8], int t, const C2 *__restrict__ tw)
 {
     constexpr int E = N / 8;
     static_assert(E % 4 == 0, "N = 8 E with E a multiple of 4");
-    Dft<E, +1>::run(v);
+    if constexpr (PRUNE) dft4b_in_pruned<E / 4, +1>(v);
+    else Dft<E, +1>::run(v);
 #pragma unroll
     for (int k = 1; k < E; ++k) v[k] = cmul(v[k], cconj(tw[t * k]));
     xstage_inv_e<2, E>(v, cconj(tw[(N / 8) * (t & 3)]));
@@ -650,7 +724,8 @@ __device__ __forceinline__ void xlane_inverse_n(C2 (&v)[N / 8], int t, const C2 
     xstage_inv_e<0, E>(v, cmk<C2>(1.0, 0.0));
 }
 // Forward (sign -1) from the layout xlane_inverse_n leaves: v[m] = y[t + 8 m] on exit.
-template <int N, class C2>
+// PRUNE: only the outputs with xlane_kept_e(m) are formed.
+template <int N, bool PRUNE = false, class C2>
 __device__ __forceinline__ void xlane_forward_n(C2 (&v)[N / 8], int t, const C2 *__restrict__ tw)
 {
     constexpr int E = N / 8;
@@ -659,7 +734,8 @@ __device__ __forceinline__ void xlane_forward_n(C2 (&v)[N / 8], int t, const C2 
     xstage_fwd_e<2, E>(v, tw[(N / 8) * (t & 3)]);
 #pragma unroll
     for (int k = 1; k < E; ++k) v[k] = cmul(v[k], tw[t * k]);
-    Dft<E, -1>::run(v);
+    if constexpr (PRUNE) dft4b_out_pruned<E / 4, -1>(v);
+    else Dft<E, -1>::run(v);
 }
 
 // Line schedule of the z-plane kernel (defaults to FftCfg).  For 96 points

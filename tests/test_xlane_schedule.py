@@ -235,3 +235,82 @@ def test_pruned_dft12_forward_kept_outputs(seed):
     assert np.abs(got[kept] - np.fft.fft(v)[kept]).max() < 1e-13
     assert np.all(np.isnan(got[3:9]))
     assert [m for m in range(12) if not 3 <= m <= 8] == kept
+
+
+# The same pruning for the 160-point lines (E = 20 = 4 x 5, dft4b_in_pruned /
+# dft4b_out_pruned with B = 5): every populated |n| <= 39, so x[t + 8 m] is
+# zero for m = 5..14 (s_a = 1, 2 of the 4-point DFTs over x[5 s_a + s_b]) and
+# only the outputs m < 5 or m >= 15 are kept.  The model restates the
+# generic steps for B = 3 and 5 and checks them against numpy.
+
+def kept_e(E, m):
+    return m < E // 4 or m >= 3 * E // 4
+
+
+def dft4b_in_pruned_model(v, sign, B):
+    E = 4 * B
+    y = np.zeros(E, complex)
+    for sb in range(B):
+        a0, a3 = v[sb], v[3 * B + sb]
+        d = sign * 1j * a3
+        y[sb * 4 + 0], y[sb * 4 + 2] = a0 + a3, a0 - a3
+        y[sb * 4 + 1], y[sb * 4 + 3] = a0 - d, a0 + d
+    out = np.zeros(E, complex)
+    for ka in range(4):
+        b = np.array([y[sb * 4 + ka] for sb in range(B)]) * np.exp(sign * 2j * np.pi * np.arange(B) * ka / E)
+        out[ka + 4 * np.arange(B)] = _dft(b, sign)
+    return out
+
+
+def dft4b_out_pruned_model(v, sign, B):
+    E = 4 * B
+    y = np.zeros(E, complex)
+    for sb in range(B):
+        y[sb * 4:sb * 4 + 4] = _dft(np.array([v[sb], v[B + sb], v[2 * B + sb], v[3 * B + sb]]), sign)
+    out = np.full(E, np.nan + 0j)
+    for ka in range(4):
+        b = np.array([y[sb * 4 + ka] for sb in range(B)]) * np.exp(sign * 2j * np.pi * np.arange(B) * ka / E)
+        full = _dft(b, sign)
+        for kb in range(B):
+            if kept_e(E, ka + 4 * kb):
+                out[ka + 4 * kb] = full[kb]
+    return out
+
+
+@pytest.mark.parametrize("B,seed", [(3, 5), (5, 6), (5, 7)])
+def test_pruned_dft4b_inverse_on_zero_inputs(B, seed):
+    E = 4 * B
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(E) + 1j * rng.standard_normal(E)
+    v[B:3 * B] = 0.0
+    assert np.abs(dft4b_in_pruned_model(v, +1, B) - np.fft.ifft(v) * E).max() < 1e-13
+    if B == 3:
+        assert np.abs(dft4b_in_pruned_model(v, +1, B) - dft12_in_pruned_model(v, +1)).max() < 1e-14
+    w = v.copy()
+    w[B + 1] = 1.0
+    assert np.abs(dft4b_in_pruned_model(w, +1, B) - np.fft.ifft(w) * E).max() > 0.1
+
+
+@pytest.mark.parametrize("B,seed", [(3, 8), (5, 9)])
+def test_pruned_dft4b_forward_kept_outputs(B, seed):
+    E = 4 * B
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(E) + 1j * rng.standard_normal(E)
+    got = dft4b_out_pruned_model(v, -1, B)
+    kept = [m for m in range(E) if kept_e(E, m)]
+    assert len(kept) == E // 2
+    assert np.abs(got[kept] - np.fft.fft(v)[kept]).max() < 1e-13
+    assert np.all(np.isnan(np.delete(got, kept)))
+
+
+def test_pruned_160_positions_cover_every_populated_index():
+    """x[t + 8 m] of a 160-point line with m kept covers every |n| <= 39, the
+    largest n_max a 160-point plan accepts (160 >= 4 n_max + 1)."""
+    nmax = (160 - 1) // 4
+    assert nmax == 39
+    for t in range(8):
+        for m in range(20):
+            i = t + 8 * m
+            n = i if i < 80 else i - 160
+            if abs(n) <= nmax:
+                assert kept_e(20, m), (t, m)
