@@ -557,6 +557,418 @@ template <int R, bool LDS, int W> __global__ void __launch_bounds__(64 * W) k_tr
 }
 
 
+// The same reduction with the matrix in registers (93 <= m <= 160): the
+// matrix (409 KB at m = 160) fits neither LDS nor one compute unit's cache
+// share, but it fits a 512-thread work-group's registers and LDS.  Thread
+// (r, c) = (lane & 31, 2 wave + (lane >> 5)) holds A(i, j) for i = r + 32 a
+// (a < 5) and j = c + 16 b (b < 10).  Rows 32 .. 159 (a >= 1) sit in
+// registers (40 complex values, 160 registers per thread, indexed only
+// with compile-time slots); rows 0 .. 31 (a = 0), which leave the trailing
+// block after 31 columns, sit in LDS.  Per column k, three work-group
+// barriers:
+//   - the half-wavefront that holds column k forms the Householder vector
+//     v (its norm summed over the half-wavefront) and publishes it in LDS
+//     (two buffers, alternating with k) with tau;
+//   - every thread sums y = A v over its columns for its rows; the two
+//     halves of each wavefront are added, and each wavefront publishes its
+//     partial y and its share of Re(v^H y);
+//   - 160 threads add the partials in wavefront order and publish
+//     w = tau y - (|tau|^2 / 2) Re(v^H y) v;
+//   - every thread updates its own elements, A -= w v^H + v w^H.
+// Entries outside the trailing block see v = w = 0 and stay unchanged.  The
+// reflectors, d, e and tau go to global memory after the first barrier, so
+// no barrier waits for a global store.  Dynamic LDS: kTriRegLds bytes.
+constexpr int kTriRegMin = 93, kTriRegMax = 160, kTriRegWaves = 8;
+constexpr int kTriRegA = 5, kTriRegB = 10;  // row and column slots per thread
+static_assert(32 * kTriRegA >= kTriRegMax && 16 * kTriRegB >= kTriRegMax && 2 * kTriRegWaves == 16, "slots");
+constexpr size_t kTriRegLds = sizeof(double2) * ((3 + kTriRegWaves) * kTriRegMax + 32 * kTriRegMax + 16);
+
+// Cross-lane moves of a double without LDS: a DPP pattern inside each
+// 16-lane row (two 32-bit moves), and the value of the lane 16 or 32 away
+// (v_permlane16_swap / v_permlane32_swap with both operands the same: a
+// lane with the distance bit clear finds its partner's value in the second
+// result, the other lane in the first).
+template <int CTRL> __device__ __forceinline__ double dpp_d(double v)
+{
+    uint32_t w[2];
+    __builtin_memcpy(w, &v, sizeof(v));
+#pragma unroll
+    for (int h = 0; h < 2; ++h) w[h] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w[h], CTRL, 0xf, 0xf, false);
+    __builtin_memcpy(&v, w, sizeof(v));
+    return v;
+}
+template <int D> __device__ __forceinline__ double lane_partner(double v)
+{
+    uint32_t w[2];
+    __builtin_memcpy(w, &v, sizeof(v));
+    const bool hi = threadIdx.x & D;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if constexpr (D == 16) {
+            const auto r = __builtin_amdgcn_permlane16_swap(w[h], w[h], false, false);
+            w[h] = hi ? r[0] : r[1];
+        } else {
+            const auto r = __builtin_amdgcn_permlane32_swap(w[h], w[h], false, false);
+            w[h] = hi ? r[0] : r[1];
+        }
+    }
+    __builtin_memcpy(&v, w, sizeof(v));
+    return v;
+}
+// sum over the 32 lanes of each half-wavefront, the same value in each of
+// them: lane pairs, quads (quad_perm), eights (row_half_mirror), rows
+// (row_mirror), then the two rows of the half
+__device__ __forceinline__ double half_sum(double v)
+{
+    v += dpp_d<0xb1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4e>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x141>(v);  // row_half_mirror
+    v += dpp_d<0x140>(v);  // row_mirror
+    return v + lane_partner<16>(v);
+}
+// Work-group barrier that waits for this wavefront's LDS accesses only,
+// not for its global stores (a __syncthreads would hold every wavefront
+// until the reflector stores of the column owner reached memory).  For
+// data shared through LDS only; the compiler may not move memory accesses
+// across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+// a double of one lane of the wavefront (uniform lane index)
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    uint32_t w[2];
+    __builtin_memcpy(w, &v, sizeof(v));
+#pragma unroll
+    for (int h = 0; h < 2; ++h) w[h] = (uint32_t)__builtin_amdgcn_readlane((int)w[h], l);
+    __builtin_memcpy(&v, w, sizeof(v));
+    return v;
+}
+
+__global__ void __launch_bounds__(64 * kTriRegWaves)
+k_tridiag_reg(int m, double2 *__restrict__ A, double *__restrict__ d, double *__restrict__ e, double2 *__restrict__ tau)
+{
+    extern __shared__ double2 dyn[];
+    double2 *vbuf = dyn;                            // v, two buffers of kTriRegMax
+    double2 *ws = vbuf + 2 * kTriRegMax;
+    double2 *part = ws + kTriRegMax;                // [wave][row]
+    double2 *A0 = part + kTriRegWaves * kTriRegMax;  // rows 0 .. 31: A0[j * 32 + i]
+    double2 *scal = A0 + 32 * kTriRegMax;           // tau (two buffers), Re(v^H y) per wavefront
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 31, c = 2 * wave + (lane >> 5);
+    constexpr int NT = 64 * kTriRegWaves;
+    // load, hermitised: A(i, j) <- (A(i, j) + conj(A(j, i))) / 2, real diagonal
+    double2 a_[kTriRegA][kTriRegB];
+#pragma unroll
+    for (int a = 0; a < kTriRegA; ++a)
+#pragma unroll
+        for (int b = 0; b < kTriRegB; ++b) {
+            const int i = r + 32 * a, j = c + 16 * b;
+            double2 h = make_double2(0.0, 0.0);
+            if (i < m && j < m) {
+                const double2 x = A[(int64_t)j * m + i], y = A[(int64_t)i * m + j];
+                h = i == j ? make_double2(x.x, 0.0) : make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+            }
+            if (a == 0) A0[j * 32 + r] = h;
+            else a_[a][b] = h;
+        }
+    __syncthreads();
+    for (int k = 0; k + 1 < m; ++k) {
+        const int n = m - k - 1;
+        double2 *vs = vbuf + (k & 1) * kTriRegMax;
+        // the half-wavefront holding column k: Householder vector and scalars
+        double beta = 0.0, dk = 0.0;
+        const bool owner = c == (k & 15);
+        if (wave == ((k & 15) >> 1)) {
+            double2 x[kTriRegA];
+#pragma unroll
+            for (int a = 0; a < kTriRegA; ++a) x[a] = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int b = 0; b < kTriRegB; ++b)
+                if (b == (k >> 4))
+#pragma unroll
+                    for (int a = 0; a < kTriRegA; ++a) x[a] = a == 0 ? A0[k * 32 + r] : a_[a][b];
+            double xn = 0.0;
+            double2 al = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int a = 0; a < kTriRegA; ++a) {
+                const int i = r + 32 * a;
+                if (i > k + 1 && i < m) xn += x[a].x * x[a].x + x[a].y * x[a].y;
+                if (a == ((k + 1) >> 5)) al = x[a];
+                if (i == k) dk = x[a].x;
+            }
+            xn = half_sum(xn);
+            // alpha = A(k + 1, k), from the owner lane of row k + 1
+            const int la = ((k & 1) << 5) | ((k + 1) & 31);
+            const double ar = lane_value(al.x, la), ai = lane_value(al.y, la);
+            double2 tk, sc;
+            if (xn == 0.0 && ai == 0.0) {
+                tk = make_double2(0.0, 0.0);
+                beta = ar;
+                sc = make_double2(0.0, 0.0);
+            } else {
+                const double nrm = sqrt(ar * ar + ai * ai + xn);
+                beta = ar >= 0.0 ? -nrm : nrm;
+                tk = make_double2((beta - ar) / beta, -ai / beta);
+                const double br = ar - beta, den = br * br + ai * ai;
+                sc = make_double2(br / den, -ai / den);  // 1 / (alpha - beta)
+            }
+#pragma unroll
+            for (int a = 0; a < kTriRegA; ++a) {
+                const int i = r + 32 * a;
+                const double2 v = i == k + 1 ? make_double2(1.0, 0.0)
+                                             : (i > k + 1 && i < m ? cmul_(x[a], sc) : make_double2(0.0, 0.0));
+                if (owner) vs[i] = v;
+            }
+            if (owner && r == 0) scal[k & 1] = tk;
+        }
+        lds_barrier();
+        const double2 tk = scal[k & 1];
+        if (owner && wave == ((k & 15) >> 1)) {
+            // the reflector (below the diagonal of column k) and the scalars
+#pragma unroll
+            for (int a = 0; a < kTriRegA; ++a) {
+                const int i = r + 32 * a;
+                if (i > k && i < m) A[(int64_t)k * m + i] = vs[i];
+                if (i == k) d[k] = dk;
+            }
+            if (r == 0) {
+                e[k] = beta;
+                tau[k] = tk;
+            }
+        }
+        if (tk.x == 0.0 && tk.y == 0.0) continue;
+        // partial y over this thread's columns (column slots outer: each v_j
+        // is read once), then over the two half-waves; this wavefront's share
+        // of Re(v^H y)
+        double2 acc[kTriRegA];
+#pragma unroll
+        for (int a = 0; a < kTriRegA; ++a) acc[a] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int b = 0; b < kTriRegB; ++b) {
+            if (16 * b + 15 <= k || 16 * b >= m) continue;
+            const int j = c + 16 * b;
+            const double2 vj = vs[j];
+#pragma unroll
+            for (int a = 0; a < kTriRegA; ++a) {
+                if (32 * a + 31 <= k || 32 * a >= m) continue;
+                const double2 t = cmul_(a == 0 ? A0[j * 32 + r] : a_[a][b], vj);
+                acc[a].x += t.x;
+                acc[a].y += t.y;
+            }
+        }
+        double crp = 0.0;
+#pragma unroll
+        for (int a = 0; a < kTriRegA; ++a) {
+            if (32 * a + 31 <= k || 32 * a >= m) continue;
+            acc[a].x += lane_partner<32>(acc[a].x);
+            acc[a].y += lane_partner<32>(acc[a].y);
+            const int i = r + 32 * a;
+            if (i > k && i < m) {
+                if (lane < 32) part[wave * kTriRegMax + i] = acc[a];
+                crp += cjmul(vs[i], acc[a]).x;
+            }
+        }
+        crp = half_sum(crp);
+        if (lane == 0) scal[2 + wave].x = crp;
+        lds_barrier();
+        // y over the wavefronts, in wavefront order, and w = tau y - (|tau|^2 / 2) Re(v^H y) v
+        double cr = 0.0;
+#pragma unroll
+        for (int q = 0; q < kTriRegWaves; ++q) cr += scal[2 + q].x;
+        const double t2 = 0.5 * (tk.x * tk.x + tk.y * tk.y) * cr;
+        for (int i = tid; i < kTriRegMax; i += NT) {
+            double2 y = make_double2(0.0, 0.0);
+            if (i > k && i < m)
+#pragma unroll
+                for (int q = 0; q < kTriRegWaves; ++q) {
+                    y.x += part[q * kTriRegMax + i].x;
+                    y.y += part[q * kTriRegMax + i].y;
+                }
+            const double2 ty = cmul_(tk, y), v = vs[i];
+            ws[i] = make_double2(ty.x - t2 * v.x, ty.y - t2 * v.y);
+        }
+        lds_barrier();
+        // A -= w v^H + v w^H on this thread's elements (column slots outer:
+        // v_j, w_j read once; v_i, w_i of the five row slots held throughout)
+        double2 vi[kTriRegA], wi[kTriRegA];
+#pragma unroll
+        for (int a = 0; a < kTriRegA; ++a) {
+            vi[a] = vs[r + 32 * a];
+            wi[a] = ws[r + 32 * a];
+        }
+#pragma unroll
+        for (int b = 0; b < kTriRegB; ++b) {
+            if (16 * b + 15 <= k || 16 * b >= m) continue;
+            const int j = c + 16 * b;
+            const double2 vj = vs[j], wj = ws[j];
+#pragma unroll
+            for (int a = 0; a < kTriRegA; ++a) {
+                if (32 * a + 31 <= k || 32 * a >= m) continue;
+                const double2 p = cjmul(vj, wi[a]), q = cjmul(wj, vi[a]);  // w_i conj(v_j), v_i conj(w_j)
+                if (a == 0) {
+                    double2 &o = A0[j * 32 + r];
+                    o = make_double2(o.x - (p.x + q.x), o.y - (p.y + q.y));
+                } else {
+                    a_[a][b].x -= p.x + q.x;
+                    a_[a][b].y -= p.y + q.y;
+                }
+            }
+        }
+    }
+    // last diagonal element (row m - 1 >= 92 lies in the register rows)
+#pragma unroll
+    for (int a = 1; a < kTriRegA; ++a)
+#pragma unroll
+        for (int b = 0; b < kTriRegB; ++b)
+            if (r + 32 * a == m - 1 && c + 16 * b == m - 1) {
+                d[m - 1] = a_[a][b].x;
+                e[m - 1] = 0.0;
+                tau[m - 1] = make_double2(0.0, 0.0);
+            }
+}
+
+// Cholesky of the hermitised S (and hermitised Hs into X when hs) with the
+// matrix in registers, 93 <= m <= 160, in the layout of k_tridiag_reg:
+// thread (r, c) holds S(r + 32 a, c + 16 b), rows 32 .. 159 in registers,
+// rows 0 .. 31 in LDS.  One work-group barrier per column: the half-
+// wavefront that holds column j checks the pivot, forms the column of L
+// (l_i = S(i, j) / sqrt(S(j, j)), i > j), publishes it in LDS (two buffers,
+// alternating with j) and writes column j of L (zero above the diagonal);
+// after the barrier every thread updates its trailing elements on or below
+// the diagonal, S(i, l) -= l_i conj(l_l), and the holder of column j + 1
+// goes on at once.
+// A pivot at or below 1e-14 max_i S(i, i) stops the factorisation and sets
+// fail and PARO_F_CHOL, as the other Cholesky kernels do.
+constexpr size_t kCholRegLds = sizeof(double2) * (2 * kTriRegMax + 32 * kTriRegMax) + sizeof(double) * (kTriRegWaves + 1);
+
+__global__ void __launch_bounds__(64 * kTriRegWaves)
+k_chol_reg(int m, const double2 *__restrict__ gram, int hs, double2 *__restrict__ L, double2 *__restrict__ X,
+           int32_t *__restrict__ fail, int32_t *__restrict__ status)
+{
+    extern __shared__ double2 dyn[];
+    double2 *lbuf = dyn;                   // the current column of L, two buffers
+    double2 *A0 = lbuf + 2 * kTriRegMax;   // rows 0 .. 31: A0[j * 32 + i]
+    double *red = reinterpret_cast<double *>(A0 + 32 * kTriRegMax);  // kTriRegWaves maxima, then the stop flag
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 31, c = 2 * wave + (lane >> 5);
+    constexpr int NT = 64 * kTriRegWaves;
+    const int64_t mm = (int64_t)m * m;
+    // the hermitised Hs to X (rows in lanes: coalesced stores)
+    if (hs)
+        for (int64_t q = tid; q < mm; q += NT) {
+            const int jj = (int)(q / m), ii = (int)(q - (int64_t)jj * m);
+            const double2 a = gram[mm + q], b = gram[mm + (int64_t)ii * m + jj];
+            X[q] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+        }
+    // the hermitised S, and the largest diagonal element
+    double2 a_[kTriRegA][kTriRegB];
+    double dmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < kTriRegA; ++a)
+#pragma unroll
+        for (int b = 0; b < kTriRegB; ++b) {
+            const int i = r + 32 * a, j = c + 16 * b;
+            double2 h = make_double2(0.0, 0.0);
+            if (i < m && j < m) {
+                const double2 x = gram[(int64_t)j * m + i], y = gram[(int64_t)i * m + j];
+                h = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+                if (i == j) dmax = fmax(dmax, x.x);
+            }
+            if (a == 0) A0[j * 32 + r] = h;
+            else a_[a][b] = h;
+        }
+    dmax = wave_max(dmax);
+    if (lane == 0) red[wave] = dmax;
+    if (tid == 0) red[kTriRegWaves] = 0.0;
+    __syncthreads();
+    dmax = red[0];
+#pragma unroll
+    for (int q = 1; q < kTriRegWaves; ++q) dmax = fmax(dmax, red[q]);
+    int failed = 0, jf = m;
+    for (int j = 0; j < m; ++j) {
+        double2 *ls = lbuf + (j & 1) * kTriRegMax;
+        if (c == (j & 15)) {
+            // the half-wavefront holding column j
+            double2 x[kTriRegA];
+#pragma unroll
+            for (int a = 0; a < kTriRegA; ++a) x[a] = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int b = 0; b < kTriRegB; ++b)
+                if (b == (j >> 4))
+#pragma unroll
+                    for (int a = 0; a < kTriRegA; ++a) x[a] = a == 0 ? A0[j * 32 + r] : a_[a][b];
+            double dl = 0.0;
+#pragma unroll
+            for (int a = 0; a < kTriRegA; ++a)
+                if (a == (j >> 5)) dl = x[a].x;
+            const double dj = lane_value(dl, ((j & 1) << 5) | (j & 31));
+            if (!(dj > 1e-14 * dmax)) {
+                if (r == 0) red[kTriRegWaves] = 1.0;
+            } else {
+                const double ljj = sqrt(dj), inv = 1.0 / ljj;
+#pragma unroll
+                for (int a = 0; a < kTriRegA; ++a) {
+                    const int i = r + 32 * a;
+                    const double2 l = i > j && i < m ? make_double2(x[a].x * inv, x[a].y * inv)
+                                                     : make_double2(0.0, 0.0);
+                    ls[i] = l;
+                    if (i < m) L[(int64_t)j * m + i] = i == j ? make_double2(ljj, 0.0) : l;
+                }
+            }
+        }
+        lds_barrier();
+        if (red[kTriRegWaves] != 0.0) {
+            failed = 1;
+            jf = j;
+            break;
+        }
+        // S(i, l) -= l_i conj(l_l) on the trailing elements
+        double2 li[kTriRegA];
+#pragma unroll
+        for (int a = 0; a < kTriRegA; ++a) li[a] = ls[r + 32 * a];
+#pragma unroll
+        for (int b = 0; b < kTriRegB; ++b) {
+            if (16 * b + 15 <= j || 16 * b >= m) continue;
+            const double2 ll = ls[c + 16 * b];
+#pragma unroll
+            for (int a = 0; a < kTriRegA; ++a) {
+                // trailing slots on or below the diagonal only (the upper triangle is never read)
+                if (32 * a + 31 <= j || 32 * a >= m || 16 * b > 32 * a + 31) continue;
+                const double2 p = cjmul(ll, li[a]);  // l_i conj(l_l)
+                if (a == 0) {
+                    double2 &o = A0[(c + 16 * b) * 32 + r];
+                    o = make_double2(o.x - p.x, o.y - p.y);
+                } else {
+                    a_[a][b].x -= p.x;
+                    a_[a][b].y -= p.y;
+                }
+            }
+        }
+    }
+    if (failed) {
+        // the columns not factorised keep the partly updated lower triangle
+#pragma unroll
+        for (int a = 0; a < kTriRegA; ++a)
+#pragma unroll
+            for (int b = 0; b < kTriRegB; ++b) {
+                const int i = r + 32 * a, l = c + 16 * b;
+                if (i < m && l < m && l >= jf) {
+                    const double2 v = a == 0 ? A0[l * 32 + r] : a_[a][b];
+                    L[(int64_t)l * m + i] = i >= l ? v : make_double2(0.0, 0.0);
+                }
+            }
+    }
+    if (tid == 0) {
+        fail[0] = failed;
+        if (failed) atomicOr(status, PARO_F_CHOL);
+    }
+}
+
 // The same reduction spread over G work-groups (G = 16 for 208 <= m <= 352,
 // G = 64 for 352 < m <= 704),
 // each holding the columns c = g, g + G, ... of the hermitised matrix in
@@ -924,6 +1336,13 @@ static bool launch_chol_dist(hipStream_t st, int m, const double2 *gram, int hs,
 static void launch_chol(hipStream_t st, int m, const double2 *gram, int hs, double2 *L, double2 *X, int32_t *fail,
                         int32_t *status, int32_t *flags = nullptr)
 {
+    static const hipError_t reg_attr = hipFuncSetAttribute(reinterpret_cast<const void *>(k_chol_reg),
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCholRegLds);
+    if (m >= kTriRegMin && m <= kTriRegMax && reg_attr == hipSuccess) {
+        hipLaunchKernelGGL(k_chol_reg, dim3(1), dim3(64 * kTriRegWaves), kCholRegLds, st, m, gram, hs, L, X, fail,
+                           status);
+        return;
+    }
     if (flags && m >= kTriDistMin && m <= kTriDistMax &&
         launch_chol_dist<kTriDistG, kTriDistThreads, kTriDistMax>(st, m, gram, hs, L, X, fail, status, flags))
         return;
@@ -1390,11 +1809,15 @@ static hipError_t eig_pipeline(hipStream_t st, int m, double2 *Hh, const DenseSc
     static const hipError_t lds_attr = hipFuncSetAttribute(
         reinterpret_cast<const void *>(k_tridiag_rows<2, true, kTriWavesLds>),
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)tridiag_lds_bytes(kTridiagLdsMax, true));
+    static const hipError_t reg_attr = hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag_reg),
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTriRegLds);
     const dim3 tl(64 * kTriWavesLds), tg(64 * kTriWavesGlobal);
     const size_t gb = tridiag_lds_bytes(m, false);
     if (m <= kTridiagLdsMax && lds_attr == hipSuccess)
         hipLaunchKernelGGL((k_tridiag_rows<2, true, kTriWavesLds>), dim3(1), tl, tridiag_lds_bytes(m, true), st, m,
                            Hh, s.d, s.e, s.tau);
+    else if (m >= kTriRegMin && m <= kTriRegMax && reg_attr == hipSuccess)
+        hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(64 * kTriRegWaves), kTriRegLds, st, m, Hh, s.d, s.e, s.tau);
     else if (launch_tridiag_dist(st, m, Hh, s, status)) {
     } else if (m <= 128)
         hipLaunchKernelGGL((k_tridiag_rows<2, false, kTriWavesGlobal>), dim3(1), tg, gb, st, m, Hh, s.d, s.e, s.tau);

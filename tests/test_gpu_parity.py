@@ -113,7 +113,7 @@ def test_zgemm_nn_vs_numpy(M, N, K):
     assert rel_err(C2, ref + C0_) < 1e-13 * np.sqrt(K)
 
 
-@pytest.mark.parametrize("m", [1, 2, 7, 64, 93, 160, 207, 208, 333, 352, 353, 640])
+@pytest.mark.parametrize("m", [1, 2, 7, 64, 92, 93, 100, 128, 150, 160, 161, 207, 208, 333, 352, 353, 640])
 def test_device_heev_vs_lapack(m):
     import paper_1702_04045_amd as P
     rng = np.random.default_rng(m)
@@ -126,6 +126,46 @@ def test_device_heev_vs_lapack(m):
     assert np.abs(w - wr).max() < 1e-13 * nrm * max(1, np.sqrt(m) / 4)
     assert np.abs(A @ V - V * w).max() < 1e-11 * nrm
     assert np.abs(V.conj().T @ V - np.eye(m)).max() < 1e-10
+
+
+@pytest.mark.parametrize("m", [40, 150, 200])
+def test_device_heev_hermitian_part(m):
+    """The eigensolver takes the Hermitian part (A + A^H) / 2 of a slightly
+    non-Hermitian input (as the Rayleigh-Ritz matrix L^-1 H L^-H is, up to
+    rounding), in the LDS, register and global-memory tridiagonalisations."""
+    import paper_1702_04045_amd as P
+    rng = np.random.default_rng(m + 1)
+    H = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    H = H + H.conj().T
+    K = 1e-3 * (rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m)))
+    K = K - K.conj().T + 1e-3j * np.diag(rng.standard_normal(m))  # anti-Hermitian, imaginary diagonal
+    w, V = P.heev(to_dev(H + K))
+    w, V = to_np(w), to_np(V)
+    wr = np.linalg.eigvalsh(H)
+    nrm = np.abs(wr).max()
+    assert np.abs(w - wr).max() < 1e-13 * nrm * max(1, np.sqrt(m) / 4)
+    assert np.abs(H @ V - V * w).max() < 1e-11 * nrm
+
+
+@pytest.mark.parametrize("m", [40, 100, 160, 200])
+def test_rayleigh_ritz_rank_deficient_basis_flags_cholesky(m):
+    """A basis with a repeated vector: the overlap is singular, every
+    Cholesky kernel (rows, register-resident, multi-work-group) stops at
+    the zero pivot and raises PARO_F_CHOL; the call returns normally."""
+    import paper_1702_04045_amd as P
+    c, v, h, pl = make_case(C0, 1)
+    U = synth.trial_block(h.ng, m, 1)
+    U[m // 2] = U[3]
+    Ud = to_dev(U)
+    W = pl.apply_h(Ud)
+    pl.rayleigh_ritz(Ud, W, 4)
+    assert pl.status() & P.F_CHOL
+    # a good basis afterwards is unaffected
+    U[m // 2] = synth.trial_block(h.ng, 1, 2)[0]
+    Ud = to_dev(U)
+    eps, _, _ = pl.rayleigh_ritz(Ud, pl.apply_h(Ud), 4)
+    assert np.all(np.isfinite(to_np(eps)))
+    assert pl.status() == 0
 
 
 def test_device_heev_degenerate():
