@@ -885,8 +885,8 @@ hipError_t run_local(const Plan &pl, const Workspace &w, int nb, const C2 *src, 
     if (nparts_out) *nparts_out = ntiles;
     const double scale = 1.0 / ((double)pl.grid[0] * pl.grid[1] * pl.grid[2]);
     C2 *sticks = reinterpret_cast<C2 *>(w.sticks);
-    for (int c0 = 0; c0 < nb; c0 += kMaxBandsPerChunk) {
-        const int cb = min(kMaxBandsPerChunk, nb - c0);
+    for (int c0 = 0; c0 < nb; c0 += chunk_bands<C2>()) {
+        const int cb = min(chunk_bands<C2>(), nb - c0);
         prof_mark(PARO_K_STICK_INV, pl.stream, true);
         hipLaunchKernelGGL((k_stick_inv<N, C2>), dim3(ntiles, cb), dim3(NT), 0, pl.stream,
                            src + c0 * ld, ld, pbuf ? pbuf + c0 * ld : nullptr, beta ? beta + c0 : nullptr,
@@ -927,8 +927,8 @@ hipError_t run_local_big(const Plan &pl, const Workspace &w, int nb, const C2 *s
     const double scale = 1.0 / ((double)pl.grid[0] * pl.grid[1] * pl.grid[2]);
     C2 *sticks = reinterpret_cast<C2 *>(w.sticks);
     C2 *sticks2 = reinterpret_cast<C2 *>(w.sticks2);
-    for (int c0 = 0; c0 < nb; c0 += kMaxBandsPerChunk) {
-        const int cb = min(kMaxBandsPerChunk, nb - c0);
+    for (int c0 = 0; c0 < nb; c0 += chunk_bands<C2>()) {
+        const int cb = min(chunk_bands<C2>(), nb - c0);
         prof_mark(PARO_K_STICK_INV, pl.stream, true);
         hipLaunchKernelGGL((k_stick_inv<N, C2>), dim3(ntiles, cb), dim3(NT), 0, pl.stream, src + c0 * ld, ld,
                            pbuf ? pbuf + c0 * ld : nullptr, beta ? beta + c0 : nullptr, first ? 1 : 0, sticks, pl.nst,
@@ -994,8 +994,8 @@ hipError_t local_apply(const Plan &pl, const Workspace &w, int nb, const C2 *src
 template <class C2> hipError_t plane_only(const Plan &pl, const Workspace &w, int nb)
 {
     C2 *sticks = reinterpret_cast<C2 *>(w.sticks);
-    for (int c0 = 0; c0 < nb; c0 += kMaxBandsPerChunk) {
-        const int cb = min(kMaxBandsPerChunk, nb - c0);
+    for (int c0 = 0; c0 < nb; c0 += chunk_bands<C2>()) {
+        const int cb = min(chunk_bands<C2>(), nb - c0);
         switch (pl.grid[0]) {
 #define PARO_CASE(n) \
     case n: launch_plane<n, C2>(pl, sticks, cb); break;
@@ -1122,8 +1122,8 @@ int describe_local_apply(const Plan &pl, const Workspace &w, int nb, const doubl
     const double *beta = w.sc + SC_BETA * nb;
     double *pq_parts = w.dots + (size_t)DOT_PQ * nb * kMaxParts;
     float2 *sticks32 = reinterpret_cast<float2 *>(w.sticks);
-    for (int c = 0, c0 = 0; c0 < nb; ++c, c0 += kMaxBandsPerChunk) {
-        const int cb = std::min(kMaxBandsPerChunk, nb - c0);
+    for (int c = 0, c0 = 0; c0 < nb; ++c, c0 += chunk_bands<double2>()) {
+        const int cb = std::min(chunk_bands<double2>(), nb - c0);
         const int64_t o = (int64_t)c0 * pl.ldv;
         const double *sh = shift ? shift + c0 : nullptr;
         double *dp = pq_parts + (size_t)c0 * kMaxParts;
@@ -1133,6 +1133,12 @@ int describe_local_apply(const Plan &pl, const Workspace &w, int nb, const doubl
                                             pl.plane_bands[0]};
         d.f64.sfwd[c] = StickFwdArgs<double2>{w.sticks, pl.st_start, pl.pt_sz, pl.tw[2], w.p + o, pl.ldv, w.q + o,
                                               pl.kin, sh, scale, dp, pl.nst, kMaxParts};
+    }
+    for (int c = 0, c0 = 0; c0 < nb; ++c, c0 += chunk_bands<float2>()) {
+        const int cb = std::min(chunk_bands<float2>(), nb - c0);
+        const int64_t o = (int64_t)c0 * pl.ldv;
+        const double *sh = shift ? shift + c0 : nullptr;
+        double *dp = pq_parts + (size_t)c0 * kMaxParts;
         d.f32.sinv[c] = StickInvArgs<float2>{w.z32 + o, pl.ldv, w.p32 + o, beta + c0, sticks32, pl.st_start,
                                              pl.pt_sz, pl.tw32[2], pl.nst};
         d.f32.plane[c] = PlaneArgs<float2>{sticks32, pl.cols, pl.vplane32, pl.tw32[0], pl.nst, N3, cb, pl.nmax[0],
@@ -1162,9 +1168,12 @@ hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool fi
 {
     constexpr int NT = stick_threads<N, C2>();
     constexpr int S = NT / FftCfg<N>::T;
+    // chunks of this precision's size (FP64 and FP32 passes take different numbers of bands)
+    constexpr int CB = chunk_bands<C2>();
+    auto nchunk = [](const GroupCell &c) { return (c.nb + CB - 1) / CB; };
     int rounds = 0;
     for (int i = 0; i < n; ++i)
-        if (cells[i].pl->grid[0] == N) rounds = std::max(rounds, cells[i].nchunk);
+        if (cells[i].pl->grid[0] == N) rounds = std::max(rounds, nchunk(cells[i]));
     for (int i = 0; i < n; ++i)
         if (N == 96 && kXlanePrune && cells[i].pl->grid[0] == N &&
             (cells[i].pl->nmax[0] > 23 || cells[i].pl->nmax[1] > 23 || cells[i].pl->nmax[2] > 23))
@@ -1199,9 +1208,9 @@ hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool fi
             };
             for (int i = 0; i < n; ++i) {
                 const GroupCell &c = cells[i];
-                if (c.pl->grid[0] != N || c.nchunk <= r) continue;
+                if (c.pl->grid[0] != N || nchunk(c) <= r) continue;
                 if (k == 1 && c.pl->plane_sched[pi] != V) continue;
-                const int cb = std::min(kMaxBandsPerChunk, c.nb - r * kMaxBandsPerChunk);
+                const int cb = std::min(CB, c.nb - r * CB);
                 const int ntiles = (c.pl->nst + S - 1) / S;
                 const void *ai, *ap, *af;
                 if constexpr (FIN) {
@@ -1248,8 +1257,8 @@ void describe_finish_local(const Plan &pl, const Workspace &w, int nb, const dou
 {
     const int N3 = pl.grid[2];
     const double scale = 1.0 / ((double)pl.grid[0] * pl.grid[1] * pl.grid[2]);
-    for (int c = 0, c0 = 0; c0 < nb; ++c, c0 += kMaxBandsPerChunk) {
-        const int cb = std::min(kMaxBandsPerChunk, nb - c0);
+    for (int c = 0, c0 = 0; c0 < nb; ++c, c0 += chunk_bands<double2>()) {
+        const int cb = std::min(chunk_bands<double2>(), nb - c0);
         const int64_t o = (int64_t)c0 * ld;
         f.sinv[c] = StickInvArgs<double2>{U + o, ld, nullptr, nullptr, w.sticks, pl.st_start, pl.pt_sz, pl.tw[2],
                                           pl.nst};

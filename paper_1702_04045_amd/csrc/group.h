@@ -160,7 +160,7 @@ template <class C2> struct GemmNnArgs {
     int N, K, bn, accumulate;
 };
 
-constexpr int kGroupChunks = 16;  // 64-band chunks of up to 1024 bands
+constexpr int kGroupChunks = 16;  // band chunks of up to 1024 bands (FP64: 64 bands each; FP32: 160)
 
 // The kernels of one cell's source solve in one precision of its vectors
 // (FP64, or FP32 for the mixed-precision solve of the correction).

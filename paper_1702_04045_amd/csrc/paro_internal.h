@@ -11,7 +11,11 @@
 
 namespace paro {
 
-constexpr int kMaxBandsPerChunk = 64;  // bands per sphere->stick->plane pass (stick buffer size)
+constexpr int kMaxBandsPerChunk = 64;     // FP64 bands per sphere->stick->plane pass
+constexpr int kMaxBandsPerChunk32 = 160;  // FP32 bands per pass (the same stick buffer holds either)
+template <class C2> constexpr int chunk_bands() { return sizeof(C2) == 16 ? kMaxBandsPerChunk : kMaxBandsPerChunk32; }
+static_assert(kGroupChunks * kMaxBandsPerChunk >= 1024 && kGroupChunks * kMaxBandsPerChunk32 >= 1024,
+              "grouped descriptors cover every chunk of a 1024-band cell");
 constexpr int kPartSplits = 64;        // split-K partials the workspaces hold per output element
 constexpr int kMaxParts = 512;         // partial sums per band per reduction
 constexpr int kDensityBandsPerGroup = 8;  // bands one work-group of the density kernel sums
@@ -208,12 +212,12 @@ hipError_t launch_shift_bound(const Plan &pl, const Workspace &w, double *sigma)
 hipError_t launch_bookkeeping(const Plan &pl, int nb, const paro_iter_opts &o, const double *eps, const double *res,
                               double *sig_all, double *sig_out, double *stats_row, int32_t *conv);
 
-// Grouped FP64 source solve over many cells (one launch per kernel and
-// FFT length): the cells, each with its descriptor in device memory.
+// Grouped source solve over many cells (one launch per kernel and FFT
+// length): the cells, each with its descriptor in device memory.
 struct GroupCell {
     const Plan *pl;
     const Workspace *w;
-    int nb, nchunk;
+    int nb;
     const GroupCellDesc *dev;   // in the cell's workspace
     const GroupCellDesc *host;  // the host copy it was written from
 };

@@ -218,16 +218,24 @@ static int32_t validate(const paro_problem *p, HostGeom *g)
     return PARO_OK;
 }
 
+// bytes of a stick buffer for passes on up to m bands: a chunk of FP64
+// bands or a (larger) chunk of FP32 bands
+static size_t stick_buffer_bytes(const Plan &pl, size_t m)
+{
+    const size_t per = std::max(sizeof(double2) * std::min<size_t>(kMaxBandsPerChunk, m),
+                                sizeof(float2) * std::min<size_t>(kMaxBandsPerChunk32, m));
+    return per * pl.grid[2] * pl.nst;
+}
+
 size_t workspace_bytes(const Plan &pl, int nb)
 {
     const size_t m = 2 * (size_t)nb;
     const size_t np = pl.nproj;
     const size_t mm = std::max(m, np);
-    const size_t cb = std::min<size_t>(kMaxBandsPerChunk, m);
     size_t tot = 0;
     auto add = [&](size_t bytes) { tot = align256(tot + bytes); };
-    add(sizeof(double2) * cb * pl.grid[2] * pl.nst);          // sticks
-    if (big_grid(pl.grid[0])) add(sizeof(double2) * cb * pl.grid[2] * pl.nst);  // sticks2
+    add(stick_buffer_bytes(pl, m));                            // sticks
+    if (big_grid(pl.grid[0])) add(stick_buffer_bytes(pl, m));  // sticks2
     for (int i = 0; i < 4; ++i) add(sizeof(double2) * nb * pl.ldv);  // r z p q
     add(sizeof(double2) * m * pl.ldv);                          // U
     add(sizeof(double2) * m * pl.ldv);                          // W
@@ -285,7 +293,6 @@ Workspace carve_workspace(const Plan &pl, int nb, void *ws)
     const size_t m = 2 * (size_t)nb;
     const size_t np = pl.nproj;
     const size_t mm = std::max(m, np);
-    const size_t cb = std::min<size_t>(kMaxBandsPerChunk, m);
     char *base = static_cast<char *>(ws);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -293,8 +300,8 @@ Workspace carve_workspace(const Plan &pl, int nb, void *ws)
         off = align256(off + bytes);
         return p;
     };
-    w.sticks = (double2 *)take(sizeof(double2) * cb * pl.grid[2] * pl.nst);
-    w.sticks2 = big_grid(pl.grid[0]) ? (double2 *)take(sizeof(double2) * cb * pl.grid[2] * pl.nst) : nullptr;
+    w.sticks = (double2 *)take(stick_buffer_bytes(pl, m));
+    w.sticks2 = big_grid(pl.grid[0]) ? (double2 *)take(stick_buffer_bytes(pl, m)) : nullptr;
     w.r = (double2 *)take(sizeof(double2) * nb * pl.ldv);
     w.z = (double2 *)take(sizeof(double2) * nb * pl.ldv);
     w.p = (double2 *)take(sizeof(double2) * nb * pl.ldv);

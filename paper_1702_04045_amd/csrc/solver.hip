@@ -821,7 +821,7 @@ int32_t run_cells_grouped(std::vector<CellRun> &cells)
             describe_bookkeeping(pl, c.nb, c.o, c.eps, w.res, w.sig_all, c.sigma, c.stats, c.conv, d.fin);
         }
         PARO_CHECK_LAUNCH(upload_bytes(pl.stream, w.desc, &d, sizeof(d)));
-        gc[i] = GroupCell{&pl, &w, c.nb, (c.nb + kMaxBandsPerChunk - 1) / kMaxBandsPerChunk, w.desc, &d};
+        gc[i] = GroupCell{&pl, &w, c.nb, w.desc, &d};
         ncg[i] = c.o.n_cg;
         if (c.o.initial_rr) {
             PARO_CHECK_LAUNCH(launch_copy_bands(pl.stream, c.nb, pl.ng, c.psi, c.ld, w.U, lv));

@@ -133,7 +133,7 @@ struct Events {
 int32_t tune_slot(Plan &pl, const Workspace &w, int nb, int pi, Events &ev, Choice *out)
 {
     const int n = pl.grid[0];
-    const int cbmax = std::min(nb, kMaxBandsPerChunk);
+    const int cbmax = std::min(nb, pi == 1 ? kMaxBandsPerChunk32 : kMaxBandsPerChunk);
     const int sched0 = pl.plane_sched[pi], bands0 = pl.plane_bands[pi];
     Choice best{0, kPlaneBandsDefault, 1e300, 0.0, 0};
     // one untimed stage, then the repetitions that make about a millisecond
@@ -233,7 +233,9 @@ int32_t paro_plan_autotune(paro_plan plan, int32_t nb, void *ws, size_t ws_bytes
     }
     const Workspace w = carve_workspace(pl, nb, ws);
     const size_t stick_bytes =
-        sizeof(double2) * (size_t)std::min(nb, kMaxBandsPerChunk) * (size_t)pl.grid[2] * (size_t)pl.nst;
+        std::max(sizeof(double2) * (size_t)std::min(nb, kMaxBandsPerChunk),
+                 sizeof(float2) * (size_t)std::min(nb, kMaxBandsPerChunk32)) *
+        (size_t)pl.grid[2] * (size_t)pl.nst;
     PARO_HIP_TRY(hipMemsetAsync(w.sticks, 0, stick_bytes, pl.stream));
     Events ev;
     PARO_HIP_TRY(hipEventCreate(&ev.e0));
