@@ -48,6 +48,10 @@ PEAK_FP64_VALU = 78.6e12     # MI355X FP64 vector, flop/s
 PEAK_FP32_VALU = 157.3e12    # MI355X FP32 vector, flop/s
 PEAK_HBM = 8.0e12            # bytes/s
 PEAK_BF16_MFMA = 2.5e15      # MI355X dense BF16 matrix cores, flop/s
+# stride of the event-timed plane launches in the timed outer iterations:
+# each event pair orders the stream (about 5.6 us of idle per pair), so only
+# every fourth launch is bracketed
+PLANE_SAMPLE = 4
 
 
 def fft_flops(n):
@@ -468,6 +472,11 @@ def main():
     sigma_lb = pl.shift_lower_bound()
     kw = dict(shift_mode=P.SHIFT_ADAPTIVE, n_conv=nconv)
 
+    # the timing events, created before the warm-up: the library keeps them
+    # for every later profile, so starting one leaves the GPU no idle time
+    lib = P.load()
+    L.check(lib.paro_profile_start_sampled(L.K_PLANE, 1 << 12, 1), "paro_profile_start_sampled")
+    L.check(lib.paro_profile_stop(None, None), "paro_profile_stop")
     # initial Rayleigh-Ritz (Algorithm 1, step 1) and warm-up iterations (untimed)
     psi = x0.clone()
     st = pl.iterate(psi, 0, ncg, sigma_lb, initial_rr=True, stats=False, **kw)
@@ -476,22 +485,30 @@ def main():
         pl.iterate(psi, args.warmup, ncg, sigma_lb, hpsi=hpsi, eps=eps, initial_rr=False, stats=False, **kw)
     torch.cuda.synchronize()
     start = (psi.clone(), hpsi.clone(), eps.clone())
-    lib = P.load()
     N = pl.grid[0]
     ncol = 2 * pl.nmax[0] + 1
-    launches_per_apply = (nb + 63) // 64
-    planes_per_launch = (nb * pl.grid[2]) / launches_per_apply
-    flops_launch = plane_flops(N, ncol) * planes_per_launch
+
+    def launches_per_apply(precision):
+        """Plane-stage launches of one apply: the bands go in chunks of 64
+        (FP64 sticks) or 160 (FP32 sticks)."""
+        chunk = 64 if precision == P.PREC_FP64 else 160
+        return (nb + chunk - 1) // chunk
+
+    def flops_launch(precision):
+        return plane_flops(N, ncol) * (nb * pl.grid[2]) / launches_per_apply(precision)
 
     def timed(precision):
-        """K outer iterations from the warmed-up state; HIP events around every plane-stage launch."""
+        """K outer iterations from the warmed-up state; HIP events around every
+        PLANE_SAMPLE-th plane-stage launch."""
         import ctypes as C
         p, h, e = (t.clone() for t in start)
         if precision != P.PREC_FP64 and args.warmup:
             pl.iterate(p.clone(), 1, ncg, sigma_lb, hpsi=h.clone(), eps=e.clone(), initial_rr=False, stats=False,
                        precision=precision, **kw)
         torch.cuda.synchronize()
-        L.check(lib.paro_profile_start(L.K_PLANE, 1 << 16), "paro_profile_start")
+        # every PLANE_SAMPLE-th plane launch bracketed by events (coprime to the
+        # three launches of an apply, so every chunk size is sampled)
+        L.check(lib.paro_profile_start_sampled(L.K_PLANE, 1 << 12, PLANE_SAMPLE), "paro_profile_start_sampled")
         stream = torch.cuda.current_stream(dev)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -506,7 +523,7 @@ def main():
         L.check(lib.paro_profile_stop(C.byref(nl), C.byref(tot)), "paro_profile_stop")
         ms_step = e0.elapsed_time(e1) / max(args.steps, 1)
         # plane launches per step: n_cg + 1 applies in FP64, or n_cg in FP32 and one in FP64
-        n_prec = launches_per_apply * (ncg if precision != P.PREC_FP64 else ncg + 1) * args.steps
+        n_prec = launches_per_apply(precision) * (ncg if precision != P.PREC_FP64 else ncg + 1) * args.steps
         return ms_step, wall, nl.value, tot.value, n_prec
 
     def tta(precision, variant=P.VARIANT_PARO, n_cg=None):
@@ -536,20 +553,25 @@ def main():
                 "reached": bool(bound <= 1e-8), "checked_every": chunk, "pcg_steps": n_cg,
                 "variant": names[variant] + ", adaptive shift"}
 
-    def roofline_of(ms_step, nl, tot, precision):
+    def roofline_of(ms_step, nl, tot, precision, n_launches, every):
+        """nl of the n_launches plane launches (one in every `every`) timed,
+        tot ms in all."""
         avg_ms = tot / max(nl, 1)
         peak = PEAK_FP32_VALU if precision == P.PREC_MIXED else PEAK_FP64_VALU
-        achieved = flops_launch / (avg_ms * 1e-3)
+        fl = flops_launch(precision)
+        achieved = fl / (avg_ms * 1e-3)
         esize = 8 if precision == P.PREC_MIXED else 16
-        bytes_launch = 2 * float(esize) * pl.n_sticks * pl.grid[2] * (nb / launches_per_apply) + esize / 2 * N ** 3
+        bytes_launch = (2 * float(esize) * pl.n_sticks * pl.grid[2] * (nb / launches_per_apply(precision))
+                        + esize / 2 * N ** 3)
         name = "k_plane<96, float2>" if precision == P.PREC_MIXED else "k_plane<96, double2>"
         return {"kernel": name + " (z-plane stage: n2/n1 FFTs, V multiply)", "bound": "alu",
                 "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic() if precision == P.PREC_FP64 else None,
                 "algorithmic_bytes_per_launch": bytes_launch,
                 "hbm_frac_algorithmic": bytes_launch / (avg_ms * 1e-3) / PEAK_HBM,
-                "launches_timed": int(nl), "avg_launch_ms": avg_ms, "flops_per_launch": flops_launch,
-                "share_of_step": (tot / max(args.steps, 1)) / ms_step}
+                "launches_timed": int(nl), "launches_sampled_every": every, "avg_launch_ms": avg_ms,
+                "flops_per_launch": fl, "bands_per_launch": nb / launches_per_apply(precision),
+                "share_of_step": avg_ms * n_launches / max(args.steps, 1) / ms_step}
 
     def hpsi_timed(block, reps=10):
         """paro_apply_h on the whole 160-band block, HIP events on the plan's
@@ -566,7 +588,7 @@ def main():
         torch.cuda.synchronize()
         ms_call = e0.elapsed_time(e1) / reps
         us_band = ms_call * 1e3 / nb
-        local, nlf, byts = hpsi_work(N, pl.n_sticks, ncol, pl.ng, pl.n_proj, nb / launches_per_apply)
+        local, nlf, byts = hpsi_work(N, pl.n_sticks, ncol, pl.ng, pl.n_proj, nb / launches_per_apply(P.PREC_FP64))
         t_hbm = byts / PEAK_HBM * 1e6
         t_local = local / PEAK_FP64_VALU * 1e6
         t_nl = nlf / PEAK_FP64_VALU * 1e6
@@ -583,11 +605,11 @@ def main():
                              "frac": t_roof / us_band}}
 
     # FP64: every plane launch is the FP64 kernel
-    ms_step, wall, nl, tot, _ = timed(P.PREC_FP64)
+    ms_step, wall, nl, tot, n64 = timed(P.PREC_FP64)
     iters_s = 1000.0 / ms_step
     applies_s = iters_s * nb * (ncg + 1)
     status = pl.status()
-    roofline = roofline_of(ms_step, nl, tot, P.PREC_FP64)
+    roofline = roofline_of(ms_step, nl, tot, P.PREC_FP64, n64, PLANE_SAMPLE)
     hpsi = hpsi_timed(psi)
     tta64 = tta(P.PREC_FP64)
 
@@ -601,15 +623,15 @@ def main():
     # FP32 plane kernel alone (the mixed step's dominant kernel), HIP events over 10 FP32 applies
     import ctypes as C
     x32 = x0.to(torch.complex64)
-    pl.apply_h_f32(x32)
-    torch.cuda.synchronize()
+    # untimed applies first: the GPU clocks back up after the host-side pause
+    for _ in range(10):
+        pl.apply_h_f32(x32)
     L.check(lib.paro_profile_start(L.K_PLANE, 1 << 12), "paro_profile_start")
     for _ in range(10):
         pl.apply_h_f32(x32)
     nlf, totf = C.c_int32(), C.c_double()
     L.check(lib.paro_profile_stop(C.byref(nlf), C.byref(totf)), "paro_profile_stop")
-    mixed["roofline"] = roofline_of(ms_m, nlf.value, totf.value, P.PREC_MIXED)
-    mixed["roofline"]["share_of_step"] = (totf.value / nlf.value) * n32 / max(args.steps, 1) / ms_m
+    mixed["roofline"] = roofline_of(ms_m, nlf.value, totf.value, P.PREC_MIXED, n32, 1)
     # the same with split-BF16 projector products in the FP32 source problems
     ms_b, wall_b, _, _, _ = timed(P.PREC_MIXED_BF16)
     mixed["bf16_projector_products"] = {

@@ -376,8 +376,16 @@ int32_t paro_get_status(paro_plan plan, int32_t *flags);
  * stream it is launched on, for up to max_launches launches, until
  * paro_profile_stop.  Process-wide (one class at a time); not thread-safe.
  * paro_profile_stop synchronises the recorded events and returns the number
- * of timed launches and their summed duration in milliseconds. */
+ * of timed launches and their summed duration in milliseconds.  The events
+ * are kept per device for the next profile (created on the current device
+ * at the start, as many as 2 max_launches).
+ * paro_profile_start_sampled times only launches 0, every, 2 every, ... of
+ * the class (every >= 1; paro_profile_start is every = 1): each event pair
+ * orders the stream around its launch, so sampling keeps that cost off the
+ * timed work.  Errors: PARO_EINVAL (bad class, count or stride, a profile
+ * already running), PARO_EHIP. */
 int32_t paro_profile_start(int32_t kernel, int32_t max_launches);
+int32_t paro_profile_start_sampled(int32_t kernel, int32_t max_launches, int32_t every);
 int32_t paro_profile_stop(int32_t *launches, double *total_ms);
 
 /* ---------------------------------------------------------------- density */

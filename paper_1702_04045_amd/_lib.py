@@ -107,6 +107,7 @@ SIGNATURES = {
     "paro_truncated_gradient": (C.c_int32, [_vp, C.c_int32, _vp, C.c_int64, C.c_double, C.c_int32, C.c_int32, _vp,
                                             _vp, _vp, _vp, _vp, _sz]),
     "paro_profile_start": (C.c_int32, [C.c_int32, C.c_int32]),
+    "paro_profile_start_sampled": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
     "paro_profile_stop": (C.c_int32, [_ip, C.POINTER(C.c_double)]),
     "paro_heev_workspace_bytes": (C.c_int32, [C.c_int32, C.POINTER(_sz)]),
     "paro_heev": (C.c_int32, [_vp, C.c_int32, _vp, _vp, _vp, _vp, _sz]),

@@ -54,6 +54,17 @@ template <int N, class C2, int V = 0> constexpr int plane_threads()
 // Line transforms done across lanes (xlane96_inverse / xlane96_forward)
 // instead of through LDS: the 96-point lines, both precisions.
 template <int N, class C2> constexpr bool xlane_rows() { return N == 96 || N == 160; }
+// plane schedule 1 at 96 points: the cross-lane lines with two threads per lane
+template <int N, class C2, int V> constexpr bool xlane_pair() { return N == 96 && V == 1; }
+// go(std::integral_constant<int, V>) for plane schedule V of N points (V < plane_nsched(N))
+template <int N, class F> void with_sched(int V, F &&go)
+{
+    if constexpr (plane_nsched(N) > 2)
+        if (V == 2) return go(std::integral_constant<int, 2>());
+    if constexpr (plane_nsched(N) > 1)
+        if (V == 1) return go(std::integral_constant<int, 1>());
+    go(std::integral_constant<int, 0>());
+}
 // Plans need N >= 4 n_max + 1 on every axis, so at N = 96 every populated
 // index has |n| <= 23: a line's inputs x[t + 8 m] with m = 3..8 (indices
 // 24..71) are zero and those outputs are never used.  The cross-lane
@@ -250,7 +261,47 @@ __device__ __forceinline__ void plane_body(int bx, int by, C2 *__restrict__ stic
             xs -= xs >= N ? N : 0;
             C2 *col = plane + (act ? xs : 0);
             C2 *tz = sticks + ((size_t)(b0 + (act ? kb : 0)) * N3 + z) * nst + cst;
-            if constexpr (xlane_rows<N, C2>()) {
+            if constexpr (xlane_pair<N, C2, V>()) {
+                // as below, with the eight-lane threads 2 t and 2 t + 1 in
+                // this lane (register sets a and b)
+                const int ta = 2 * t, tb = ta + 1;
+                if (kb >= 0 && kb < nbk) {
+                    C2 va[12], vb[12];
+                    if (lower) {
+#pragma unroll
+                        for (int e = 0; e < 12; ++e) {
+                            va[e] = act ? col[xlane_index(ta, e) * LDX] : cmk<C2>(0.0, 0.0);
+                            vb[e] = act ? col[xlane_index(tb, e) * LDX] : cmk<C2>(0.0, 0.0);
+                        }
+                        xlane96x2_forward<kXlanePrune>(va, vb, opaque(t), twl);
+                        if (act) {
+#pragma unroll
+                            for (int m = 0; m < 12; ++m) {
+                                if (!xlane_kept(m)) continue;
+                                const int qa = stick_of(ta + 8 * m), qb = stick_of(tb + 8 * m);
+                                if (qa >= 0) tz[qa] = va[m];
+                                if (qb >= 0) tz[qb] = vb[m];
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int m = 0; m < 12; ++m) {
+                            const int qa = (act && xlane_kept(m)) ? stick_of(ta + 8 * m) : -1;
+                            const int qb = (act && xlane_kept(m)) ? stick_of(tb + 8 * m) : -1;
+                            va[m] = qa >= 0 ? tz[qa] : cmk<C2>(0.0, 0.0);
+                            vb[m] = qb >= 0 ? tz[qb] : cmk<C2>(0.0, 0.0);
+                        }
+                        xlane96x2_inverse<kXlanePrune>(va, vb, opaque(t), twl);
+                        if (act) {
+#pragma unroll
+                            for (int e = 0; e < 12; ++e) {
+                                col[xlane_index(ta, e) * LDX] = va[e];
+                                col[xlane_index(tb, e) * LDX] = vb[e];
+                            }
+                        }
+                    }
+                }
+            } else if constexpr (xlane_rows<N, C2>()) {
                 // Column transforms across lanes too.  The forward column
                 // reads the plane in the register order the cross-lane
                 // inverse leaves (xlane_index) and the inverse column writes
@@ -312,7 +363,33 @@ __device__ __forceinline__ void plane_body(int bx, int by, C2 *__restrict__ stic
                 int x = i + sh;
                 return x - (x >= N ? N : 0);
             };
-            if constexpr (xlane_rows<N, C2>()) {
+            if constexpr (xlane_pair<N, C2, V>()) {
+                // as below, with the eight-lane threads 2 t and 2 t + 1 in
+                // this lane; their potential values are this lane's 24
+                static_assert(plane_threads<N, C2, V>() == N * T && T == 4 && E == 24,
+                              "paired cross-lane rows: 96 x 4 lanes");
+                const int ta = 2 * t, tb = ta + 1;
+                C2 va[12], vb[12];
+#pragma unroll
+                for (int m = 0; m < 12; ++m) {
+                    const int ia = ta + 8 * m, ib = tb + 8 * m;
+                    va[m] = (xlane_kept(m) && (ia <= nmax1 || ia >= N - nmax1)) ? row[at(ia)] : cmk<C2>(0.0, 0.0);
+                    vb[m] = (xlane_kept(m) && (ib <= nmax1 || ib >= N - nmax1)) ? row[at(ib)] : cmk<C2>(0.0, 0.0);
+                }
+                xlane96x2_inverse<kXlanePrune>(va, vb, opaque(t), twl);
+#pragma unroll
+                for (int e = 0; e < 12; ++e) {
+                    va[e] = cscale(va[e], vp[e]);
+                    vb[e] = cscale(vb[e], vp[12 + e]);
+                }
+                xlane96x2_forward<kXlanePrune>(va, vb, opaque(t), twl);
+#pragma unroll
+                for (int m = 0; m < 12; ++m) {
+                    const int ia = ta + 8 * m, ib = tb + 8 * m;
+                    if (xlane_kept(m) && (ia <= nmax1 || ia >= N - nmax1)) row[at(ia)] = va[m];
+                    if (xlane_kept(m) && (ib <= nmax1 || ib >= N - nmax1)) row[at(ib)] = vb[m];
+                }
+            } else if constexpr (xlane_rows<N, C2>()) {
                 // Thread t reads and writes the row elements t + T m only,
                 // and every exchange is a lane swap: no LDS traffic besides
                 // the populated entries, no wave synchronisation.  All N
@@ -586,7 +663,8 @@ template <int N, class C2, int V> int plane_x(int t, int e)
 {
     using C = PlaneSched<N, C2, V>;
     constexpr int T = C::T, RL = ListInfo<typename C::Inv>::last;
-    if constexpr (xlane_rows<N, C2>()) return xl_index<N>(t, e);
+    if constexpr (xlane_pair<N, C2, V>()) return xlane_index(2 * t + e / 12, e % 12);
+    else if constexpr (xlane_rows<N, C2>()) return xl_index<N>(t, e);
     else return t + T * (e / RL) + (e % RL) * (N / RL);
 }
 template <int N, class VT>
@@ -613,12 +691,8 @@ template <int N, class C2> bool row_order(int V, int32_t *x)
         for (int t = 0; t < C::T; ++t)
             for (int e = 0; e < C::E; ++e) x[t * C::E + e] = plane_x<N, C2, VV>(t, e);
     };
-    if (V == 0) fill(std::integral_constant<int, 0>());
-    else if constexpr (plane_nsched(N) > 1) {
-        if (V == 1) fill(std::integral_constant<int, 1>());
-        else if (V == 2) fill(std::integral_constant<int, 2>());
-        else return false;
-    } else return false;
+    if (V < 0 || V >= plane_nsched(N)) return false;
+    with_sched<N>(V, fill);
     return true;
 }
 
@@ -863,11 +937,7 @@ void launch_plane(const Plan &pl, C2 *sticks, int cb)
         hipLaunchKernelGGL((k_plane<N, C2, VV>), grid, dim3(plane_threads<N, C2, VV>()), 0, pl.stream, sticks, pl.nst,
                            N3, cb, pl.cols, PlanTabs<C2>::v(pl), pl.nmax[0], PlanTabs<C2>::tw(pl, 0), bpb);
     };
-    if constexpr (plane_nsched(N) > 1) {
-        if (V == 1) return go(std::integral_constant<int, 1>());
-        if (V == 2) return go(std::integral_constant<int, 2>());
-    }
-    go(std::integral_constant<int, 0>());
+    with_sched<N>(V, go);
 }
 
 template <int N, class C2>
@@ -1197,11 +1267,7 @@ hipError_t grouped_local_n(hipStream_t s, const GroupCell *cells, int n, bool fi
                         hipLaunchKernelGGL((k_plane_grp<N, C2, VV>), grid, dim3(plane_threads<N, C2, VV>()), 0, s,
                                            g.t);
                     };
-                    if constexpr (plane_nsched(N) > 1) {
-                        if (V == 1) go(std::integral_constant<int, 1>());
-                        else if (V == 2) go(std::integral_constant<int, 2>());
-                        else go(std::integral_constant<int, 0>());
-                    } else go(std::integral_constant<int, 0>());
+                    with_sched<N>(V, go);
                 } else
                     hipLaunchKernelGGL((k_stick_fwd_grp<N, C2>), grid, dim3(NT), 0, s, g.t);
                 g = GroupBuilder();

@@ -457,7 +457,8 @@ template <int B> __device__ __forceinline__ constexpr int xpair_hi(int i)
 }
 
 // inverse-direction stage: swap, then (u, v) -> (u + v, (u - v) w)
-template <int B, class C2> __device__ __forceinline__ void xstage_inv(C2 (&v)[12], C2 w)
+// (W false: w is 1 and the multiply is left out)
+template <int B, bool W = true, class C2> __device__ __forceinline__ void xstage_inv(C2 (&v)[12], C2 w)
 {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
@@ -465,16 +466,16 @@ template <int B, class C2> __device__ __forceinline__ void xstage_inv(C2 (&v)[12
         xswap<B>(a, b);
         const C2 u = a, d = csub(a, b);
         a = cadd(u, b);
-        b = B == 0 ? d : cmul(d, w);
+        b = (B == 0 || !W) ? d : cmul(d, w);
     }
 }
 // its conjugate transpose: (a, b) -> (a + b w*, a - b w*), then the same swap
-template <int B, class C2> __device__ __forceinline__ void xstage_fwd(C2 (&v)[12], C2 wc)
+template <int B, bool W = true, class C2> __device__ __forceinline__ void xstage_fwd(C2 (&v)[12], C2 wc)
 {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         C2 &a = v[xpair_lo<B>(i)], &b = v[xpair_hi<B>(i)];
-        const C2 c = B == 0 ? b : cmul(b, wc);
+        const C2 c = (B == 0 || !W) ? b : cmul(b, wc);
         const C2 u = a;
         a = cadd(u, c);
         b = csub(u, c);
@@ -588,6 +589,90 @@ __device__ __forceinline__ void xlane96_forward(C2 (&v)[12], int t, const C2 *__
     for (int k = 1; k < 12; ++k) v[k] = cmul(v[k], tw[t * k]);
     if constexpr (PRUNE) dft12_out_pruned<-1>(v);
     else Dft<12, -1>::run(v);
+}
+
+// The same 96-point schedule with two of its threads in each lane: a line
+// takes four lanes u = 0..3 (lane distances 16 and 32, the swaps of thread
+// bits 1 and 2), and lane u holds the registers of threads 2 u (set a) and
+// 2 u + 1 (set b).  The 12-point DFTs, the twiddles and the stages on
+// thread bits 2 and 1 are those of xlane96_inverse, once per set; the stage
+// on thread bit 0 pairs the two sets inside the lane, where the swap
+// becomes a renaming of registers (no exchange at all).  Thread 2 u has
+// the stage-1 twiddle 1, so that multiply is left out.  On exit register
+// s of set j holds X[xlane_index(2 u + j, s)], as thread 2 u + j of the
+// eight-lane schedule would.
+template <class C2> __device__ __forceinline__ void xstage_inv_bit0(C2 (&a)[12], C2 (&b)[12])
+{
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        // after the eight-lane swap thread 2 u would hold (a[i], b[i]) and
+        // thread 2 u + 1 (a[i + 6], b[i + 6]) in its registers i and i + 6
+        const C2 pa = a[i], qa = b[i], pb = a[i + 6], qb = b[i + 6];
+        a[i] = cadd(pa, qa);
+        a[i + 6] = csub(pa, qa);
+        b[i] = cadd(pb, qb);
+        b[i + 6] = csub(pb, qb);
+    }
+}
+template <class C2> __device__ __forceinline__ void xstage_fwd_bit0(C2 (&a)[12], C2 (&b)[12])
+{
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const C2 sa = cadd(a[i], a[i + 6]), da = csub(a[i], a[i + 6]);
+        const C2 sb = cadd(b[i], b[i + 6]), db = csub(b[i], b[i + 6]);
+        // the swap: thread 2 u keeps its sum and receives the other's; the
+        // differences go to thread 2 u + 1
+        a[i] = sa;
+        a[i + 6] = sb;
+        b[i] = da;
+        b[i + 6] = db;
+    }
+}
+template <bool PRUNE = false, class C2>
+__device__ __forceinline__ void xlane96x2_inverse(C2 (&a)[12], C2 (&b)[12], int u, const C2 *__restrict__ tw)
+{
+    const int ta = 2 * u, tb = ta + 1;
+    if constexpr (PRUNE) {
+        dft12_in_pruned<+1>(a);
+        dft12_in_pruned<+1>(b);
+    } else {
+        Dft<12, +1>::run(a);
+        Dft<12, +1>::run(b);
+    }
+#pragma unroll
+    for (int k = 1; k < 12; ++k) {
+        a[k] = cmul(a[k], cconj(tw[ta * k]));
+        b[k] = cmul(b[k], cconj(tw[tb * k]));
+    }
+    xstage_inv<2>(a, cconj(tw[12 * (ta & 3)]));
+    xstage_inv<2>(b, cconj(tw[12 * (tb & 3)]));
+    xstage_inv<1, false>(a, cmk<C2>(1.0, 0.0));
+    xstage_inv<1>(b, cconj(tw[24]));
+    xstage_inv_bit0(a, b);
+}
+// Forward (sign -1) from the layout xlane96x2_inverse leaves: a[m] =
+// y[2 u + 8 m], b[m] = y[2 u + 1 + 8 m] on exit.
+template <bool PRUNE = false, class C2>
+__device__ __forceinline__ void xlane96x2_forward(C2 (&a)[12], C2 (&b)[12], int u, const C2 *__restrict__ tw)
+{
+    const int ta = 2 * u, tb = ta + 1;
+    xstage_fwd_bit0(a, b);
+    xstage_fwd<1, false>(a, cmk<C2>(1.0, 0.0));
+    xstage_fwd<1>(b, tw[24]);
+    xstage_fwd<2>(a, tw[12 * (ta & 3)]);
+    xstage_fwd<2>(b, tw[12 * (tb & 3)]);
+#pragma unroll
+    for (int k = 1; k < 12; ++k) {
+        a[k] = cmul(a[k], tw[ta * k]);
+        b[k] = cmul(b[k], tw[tb * k]);
+    }
+    if constexpr (PRUNE) {
+        dft12_out_pruned<-1>(a);
+        dft12_out_pruned<-1>(b);
+    } else {
+        Dft<12, -1>::run(a);
+        Dft<12, -1>::run(b);
+    }
 }
 
 // The same schedule for any N = 8 E with E = 4 J (160 points: E = 20, a
@@ -783,8 +868,17 @@ template <class C2> struct PlaneSched<64, C2, 1> : SchedDef<64, 4, RList<16, 4>,
 template <class C2> struct PlaneSched<64, C2, 2> : SchedDef<64, 16, RList<4, 4, 4>, RList<4, 4, 4>> {};
 template <class C2> struct PlaneSched<80, C2, 1> : SchedDef<80, 8, RList<10, 2, 2, 2>, RList<2, 2, 2, 10>> {};
 template <class C2> struct PlaneSched<80, C2, 2> : SchedDef<80, 4, RList<4, 4, 5>, RList<5, 4, 4>> {};
+// 96 points with four lanes per line, two threads of the cross-lane
+// schedule in each (xlane96x2_inverse / xlane96x2_forward): 6 work-group
+// waves, the potential in the same order as variant 0.  (The lists only
+// satisfy the generic checks; the lines are cross-lane.)
+template <class C2> struct PlaneSched<96, C2, 1> {
+    static constexpr int N = 96, T = 4, E = 24, min_waves = sizeof(C2) == 8 ? 3 : 1;
+    using Inv = RList<4, 6, 4>;
+    using Fwd = RList<4, 6, 4>;
+};
 // number of selectable schedules at N points
-__host__ __device__ constexpr int plane_nsched(int n) { return n >= 24 && n <= 80 ? 3 : 1; }
+__host__ __device__ constexpr int plane_nsched(int n) { return n >= 24 && n <= 80 ? 3 : n == 96 ? 2 : 1; }
 constexpr int kPlaneSchedMax = 3;
 
 }  // namespace paro

@@ -4,6 +4,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -15,18 +16,23 @@ static thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 
 struct Profiler {
-    int kernel = 0, cap = 0, used = 0;
+    int kernel = 0, cap = 0, used = 0, every = 1, device = 0;
+    int64_t seen = 0;  // launches of the class since the start
     bool skip = false;
     std::vector<hipEvent_t> ev;
 };
 static Profiler *g_prof = nullptr;
+// Timing events kept per device between profiles: creating thousands of
+// events takes long enough on the host for the GPU to idle and drop its
+// clocks before the timed work starts.
+static std::map<int, std::vector<hipEvent_t>> g_event_pool;
 
 void prof_mark(int kernel, hipStream_t s, bool begin)
 {
     Profiler *p = g_prof;
     if (!p || p->kernel != kernel) return;
     if (begin) {
-        p->skip = p->used >= p->cap;
+        p->skip = p->used >= p->cap || (p->seen++ % p->every) != 0;
         if (!p->skip) (void)hipEventRecord(p->ev[2 * p->used], s);
     } else if (!p->skip) {
         (void)hipEventRecord(p->ev[2 * p->used + 1], s);
@@ -566,26 +572,42 @@ int32_t paro_get_projectors(paro_plan plan, double *beta_dev)
     return PARO_OK;
 }
 
-int32_t paro_profile_start(int32_t kernel, int32_t max_launches)
+int32_t paro_profile_start_sampled(int32_t kernel, int32_t max_launches, int32_t every)
 {
-    if (kernel < PARO_K_STICK_INV || kernel > PARO_K_DENSITY || max_launches <= 0 || max_launches > (1 << 20))
-        return fail(PARO_EINVAL, "paro_profile_start: bad kernel class or launch count");
+    if (kernel < PARO_K_STICK_INV || kernel > PARO_K_DENSITY || max_launches <= 0 || max_launches > (1 << 20) ||
+        every <= 0)
+        return fail(PARO_EINVAL, "paro_profile_start: bad kernel class, launch count or sampling stride");
     if (g_prof) return fail(PARO_EINVAL, "paro_profile_start: a profile is already running");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(PARO_EHIP, "paro_profile_start: hipGetDevice failed");
     Profiler *p = new (std::nothrow) Profiler();
     if (!p) return fail(PARO_EINVAL, "out of host memory");
     p->kernel = kernel;
     p->cap = max_launches;
-    p->ev.resize(2 * (size_t)max_launches);
-    for (auto &e : p->ev) {
+    p->every = every;
+    p->device = dev;
+    std::vector<hipEvent_t> &pool = g_event_pool[dev];
+    const size_t need = 2 * (size_t)max_launches;
+    while (p->ev.size() < need && !pool.empty()) {
+        p->ev.push_back(pool.back());
+        pool.pop_back();
+    }
+    while (p->ev.size() < need) {
+        hipEvent_t e = nullptr;
         if (hipEventCreate(&e) != hipSuccess) {
-            for (auto &f : p->ev)
-                if (f) (void)hipEventDestroy(f);
+            pool.insert(pool.end(), p->ev.begin(), p->ev.end());
             delete p;
             return fail(PARO_EHIP, "paro_profile_start: hipEventCreate failed");
         }
+        p->ev.push_back(e);
     }
     g_prof = p;
     return PARO_OK;
+}
+
+int32_t paro_profile_start(int32_t kernel, int32_t max_launches)
+{
+    return paro_profile_start_sampled(kernel, max_launches, 1);
 }
 
 int32_t paro_profile_stop(int32_t *launches, double *total_ms)
@@ -606,7 +628,8 @@ int32_t paro_profile_stop(int32_t *launches, double *total_ms)
     }
     if (launches) *launches = p->used;
     if (total_ms) *total_ms = tot;
-    for (auto &e : p->ev) (void)hipEventDestroy(e);
+    std::vector<hipEvent_t> &pool = g_event_pool[p->device];
+    pool.insert(pool.end(), p->ev.begin(), p->ev.end());
     delete p;
     return rc;
 }

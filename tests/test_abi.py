@@ -172,3 +172,15 @@ def test_batched_workload_shapes(P):
         assert sp.grid >= need and all(g < need for g in synth.FFT_LENGTHS if g < sp.grid)
         assert len(mil) >= sp.n_bands
     assert len({sp.grid for sp in specs}) >= 4  # uneven
+
+
+def test_profile_argument_errors(P):
+    """The kernel-timing calls reject a bad class, count or sampling stride,
+    and a stop without a start, before touching the GPU."""
+    from paper_1702_04045_amd import _lib as L
+    lib = P.load()
+    assert lib.paro_profile_start_sampled(L.K_PLANE, 16, 0) == L.PARO_EINVAL
+    assert lib.paro_profile_start_sampled(L.K_PLANE, 0, 1) == L.PARO_EINVAL
+    assert lib.paro_profile_start_sampled(0, 16, 1) == L.PARO_EINVAL
+    assert lib.paro_profile_start(99, 16) == L.PARO_EINVAL
+    assert lib.paro_profile_stop(None, None) == L.PARO_EINVAL

@@ -314,3 +314,107 @@ def test_pruned_160_positions_cover_every_populated_index():
             n = i if i < 80 else i - 160
             if abs(n) <= nmax:
                 assert kept_e(20, m), (t, m)
+
+
+# ---------------------------------------------------------------- two threads per lane
+# Plane schedule 1 at 96 points runs the same schedule with threads 2 u
+# (set a) and 2 u + 1 (set b) in one lane: the stages on thread bits 2 and 1
+# are the swaps above, once per set; the stage on thread bit 0 becomes a
+# renaming of registers inside the lane (xstage_inv_bit0 / xstage_fwd_bit0
+# in fft_device.h, restated here).
+
+def pair_bit0_inverse(a, b):
+    a2, b2 = a.copy(), b.copy()
+    for i in range(6):
+        pa, qa, pb, qb = a[i], b[i], a[i + 6], b[i + 6]
+        a2[i], a2[i + 6] = pa + qa, pa - qa
+        b2[i], b2[i + 6] = pb + qb, pb - qb
+    return a2, b2
+
+
+def pair_bit0_forward(a, b):
+    a2, b2 = a.copy(), b.copy()
+    for i in range(6):
+        a2[i], a2[i + 6] = a[i] + a[i + 6], b[i] + b[i + 6]
+        b2[i], b2[i + 6] = a[i] - a[i + 6], b[i] - b[i + 6]
+    return a2, b2
+
+
+def _bit0_stage_inverse(R):
+    R = S96.swap(R, 0)
+    for t in range(T):
+        for s, s2 in S96.pairs[0]:
+            u, v = R[t, s], R[t, s2]
+            R[t, s], R[t, s2] = u + v, u - v
+    return R
+
+
+def _bit0_stage_forward(R):
+    R = R.copy()
+    for t in range(T):
+        for s, s2 in S96.pairs[0]:
+            a, c = R[t, s], R[t, s2]
+            R[t, s], R[t, s2] = a + c, a - c
+    return S96.swap(R, 0)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_paired_bit0_stage_is_the_swap_stage(seed):
+    """On any register state the in-lane stage of each direction gives lane u's
+    sets exactly the registers threads 2 u and 2 u + 1 hold after the
+    eight-lane swap stage."""
+    rng = np.random.default_rng(seed)
+    R = rng.standard_normal((T, E)) + 1j * rng.standard_normal((T, E))
+    for stage8, stage2 in ((_bit0_stage_inverse, pair_bit0_inverse), (_bit0_stage_forward, pair_bit0_forward)):
+        ref = stage8(R)
+        for u in range(4):
+            a, b = stage2(R[2 * u], R[2 * u + 1])
+            assert np.array_equal(a, ref[2 * u]) and np.array_equal(b, ref[2 * u + 1])
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_paired_schedule_convolution_step(seed):
+    """The whole paired row step, inverse, x V in the lane's 24-value order
+    (set a then set b), forward, against numpy."""
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    V = rng.standard_normal(N)
+    # inverse: per-thread DFT, twiddle and the bit-2 and bit-1 stages, then the in-lane bit-0 stage
+    R = np.array([[x[t + T * m] for m in range(E)] for t in range(T)], dtype=complex)
+    R = np.fft.ifft(R, axis=1) * E
+    R = R * S96.w(+1, np.outer(np.arange(T), np.arange(E)))
+    for b in (2, 1):
+        R = S96.swap(R, b)
+        for t in range(T):
+            tw = S96.w(+1, S96.stage_twiddle_exponent(b, t))
+            for s, s2 in S96.pairs[b]:
+                u, v = R[t, s], R[t, s2]
+                R[t, s], R[t, s2] = u + v, (u - v) * tw
+    lanes = [pair_bit0_inverse(R[2 * u], R[2 * u + 1]) for u in range(4)]
+    X = np.fft.ifft(x) * N
+    for u, (a, b) in enumerate(lanes):
+        for s in range(E):
+            assert abs(a[s] - X[xlane_index(2 * u, s)]) < 1e-12 * np.abs(X).max()
+            assert abs(b[s] - X[xlane_index(2 * u + 1, s)]) < 1e-12 * np.abs(X).max()
+    # lane u's potential: 24 values, position p = 24 u + e of the row (the same
+    # memory order as eight threads of 12)
+    Vl = np.array([V[xlane_index(2 * u + e // 12, e % 12)] for u in range(4) for e in range(24)]).reshape(4, 24)
+    lanes = [(a * Vl[u, :12], b * Vl[u, 12:]) for u, (a, b) in enumerate(lanes)]
+    # forward: in-lane bit-0 stage, then the eight-lane bit-1 and bit-2 stages and the rest
+    R = np.zeros((T, E), complex)
+    for u, (a, b) in enumerate(lanes):
+        R[2 * u], R[2 * u + 1] = pair_bit0_forward(a, b)
+    for b in (1, 2):
+        for t in range(T):
+            twc = S96.w(-1, S96.stage_twiddle_exponent(b, t))
+            for s, s2 in S96.pairs[b]:
+                a_, c = R[t, s], R[t, s2] * twc
+                R[t, s], R[t, s2] = a_ + c, a_ - c
+        R = S96.swap(R, b)
+    R = R * S96.w(-1, np.outer(np.arange(T), np.arange(E)))
+    R = np.fft.fft(R, axis=1)
+    y = np.empty(N, complex)
+    for t in range(T):
+        y[t + T * np.arange(E)] = R[t]
+    ref = np.fft.fft(V * X)
+    assert np.abs(y - ref).max() < 1e-11 * np.abs(ref).max()
