@@ -103,6 +103,9 @@ template <int N, class C2> __device__ __forceinline__ void xl_forward(C2 (&v)[N 
 // largest populated |n| the pruned lines of N points allow
 constexpr int xl_nmax_limit(int n) { return n == 96 ? 23 : n == 160 ? 39 : 1 << 30; }
 
+// sphere points per thread whose loads the stick kernels issue together
+constexpr int kGatherPts = 4;
+
 // Sphere -> sticks, inverse transform along n3.  Line (stick) threads are
 // consecutive lanes, so the exchanges between passes are wavefront-local.
 // pbuf != null: PCG prologue, p <- z + beta p (first step: p <- z), the new p
@@ -131,18 +134,33 @@ __device__ __forceinline__ void stick_inv_body(int bx, int by, const C2 *__restr
     const C2 *x = src + band * ld;
     C2 *pb = pbuf ? pbuf + band * ld : nullptr;
     const S2 bt = (pbuf && !first) ? (S2)beta[band] : (S2)0;
-    for (int idx = p0 + tid; idx < p1; idx += NT) {
-        C2 val = x[idx];
-        if (pb) {
-            if (!first) {
-                const C2 po = pb[idx];
-                val.x += bt * po.x;
-                val.y += bt * po.y;
-            }
-            pb[idx] = val;
+    // all loads of kGatherPts points per thread first, then the arithmetic
+    // and the stores, so that one memory latency covers them (a lane past
+    // the range loads point p0 and stores nothing)
+    for (int base = p0 + tid; base < p1; base += kGatherPts * NT) {
+        C2 xv[kGatherPts], po[kGatherPts];
+        int sz[kGatherPts];
+#pragma unroll
+        for (int u = 0; u < kGatherPts; ++u) {
+            const int idx = base + u * NT, i = idx < p1 ? idx : p0;
+            xv[u] = x[i];
+            sz[u] = pt_sz[i];
+            if (pb && !first) po[u] = pb[i];
         }
-        const int sz = pt_sz[idx];
-        tile[((sz >> 8) - s0) * LD + (sz & 255)] = val;
+#pragma unroll
+        for (int u = 0; u < kGatherPts; ++u) {
+            const int idx = base + u * NT;
+            if (idx >= p1) break;
+            C2 val = xv[u];
+            if (pb) {
+                if (!first) {
+                    val.x += bt * po[u].x;
+                    val.y += bt * po[u].y;
+                }
+                pb[idx] = val;
+            }
+            tile[((sz[u] >> 8) - s0) * LD + (sz[u] & 255)] = val;
+        }
     }
     __syncthreads();
     C2 v[E];
@@ -745,16 +763,32 @@ __device__ __forceinline__ void stick_fwd_body(int bx, int by, const C2 *__restr
     C2 *o = out + band * ld;
     const S2 sc = (S2)scale;
     double dot = 0.0;
-    for (int idx = p0 + tid; idx < p1; idx += NT) {
-        const int sz = pt_sz[idx];
-        const C2 loc = tile[((sz >> 8) - s0) * LD + (sz & 255)];
-        const C2 xv = x[idx];
-        const S2 k = (S2)(kin[idx] - sig);
-        C2 r;
-        r.x = loc.x * sc + k * xv.x;
-        r.y = loc.y * sc + k * xv.y;
-        o[idx] = r;
-        dot += (double)xv.x * (double)r.x + (double)xv.y * (double)r.y;
+    // loads of kGatherPts points per thread first, as in the sphere scatter;
+    // the points are taken, and summed into dot, in the same order as one
+    // at a time
+    for (int base = p0 + tid; base < p1; base += kGatherPts * NT) {
+        int sz[kGatherPts];
+        C2 xv[kGatherPts];
+        double kv[kGatherPts];
+#pragma unroll
+        for (int u = 0; u < kGatherPts; ++u) {
+            const int idx = base + u * NT, i = idx < p1 ? idx : p0;
+            sz[u] = pt_sz[i];
+            xv[u] = x[i];
+            kv[u] = kin[i];
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherPts; ++u) {
+            const int idx = base + u * NT;
+            if (idx >= p1) break;
+            const C2 loc = tile[((sz[u] >> 8) - s0) * LD + (sz[u] & 255)];
+            const S2 k = (S2)(kv[u] - sig);
+            C2 r;
+            r.x = loc.x * sc + k * xv[u].x;
+            r.y = loc.y * sc + k * xv[u].y;
+            o[idx] = r;
+            dot += (double)xv[u].x * (double)r.x + (double)xv[u].y * (double)r.y;
+        }
     }
     if (dot_part) {
         dot = block_sum<NT>(dot, red);
