@@ -342,6 +342,23 @@ __device__ __forceinline__ void nn_unit(int64_t unit, int lane, int64_t M, int N
         // valid one (those rows and columns are not stored).
         const C2 *px[2] = {B + (int64_t)min(n0 + l16, N - 1) * ldb, B + (int64_t)min(n0 + 16 + l16, N - 1) * ldb};
         const C2 *py[2] = {A + (g0 + l16 < M ? g0 + l16 : M - 1), A + (g0 + 16 + l16 < M ? g0 + 16 + l16 : M - 1)};
+        // Accumulation: the old values of the whole block (clamped into C,
+        // as the operand loads) are requested before the last pass of the
+        // contraction, so that their latency overlaps its k-steps.
+        C2 old[2][2][4];
+        auto load_old = [&]() {
+            if (!accumulate) return;
+    #pragma unroll
+            for (int u = 0; u < 2; ++u)
+    #pragma unroll
+                for (int w = 0; w < 2; ++w)
+    #pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int n = min(n0 + u * 16 + Mma<C2>::row(lk, v), N - 1);
+                        const int64_t g = g0 + w * 16 + l16 < M ? g0 + w * 16 + l16 : M - 1;
+                        old[u][w][v] = C[(int64_t)n * ldc + g];
+                    }
+        };
         // register prefetch ring, as in k_gemm_hn_part
         C2 x[kDepthNN][2], y[kDepthNN][2];
         auto step = [&](int slot) {
@@ -388,6 +405,7 @@ __device__ __forceinline__ void nn_unit(int64_t unit, int lane, int64_t M, int N
                 }
             }
             load(kDepthNN - 1, kDepthNN - 1);
+            load_old();
     #pragma unroll
             for (int d = 0; d < kDepthNN; ++d) step(d);
         } else if (K > 0) {
@@ -416,23 +434,12 @@ __device__ __forceinline__ void nn_unit(int64_t unit, int lane, int64_t M, int N
                     step(d);
                 }
             }
+            load_old();
+        } else {
+            load_old();
         }
-        // Accumulation: the old values of half the block are requested
-        // before the first is used (clamped into C, as the operand loads),
-        // so that their latencies overlap instead of adding up.
     #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            C2 old[2][4];
-            if (accumulate) {
-    #pragma unroll
-                for (int w = 0; w < 2; ++w)
-    #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int n = min(n0 + u * 16 + Mma<C2>::row(lk, v), N - 1);
-                        const int64_t g = g0 + w * 16 + l16 < M ? g0 + w * 16 + l16 : M - 1;
-                        old[w][v] = C[(int64_t)n * ldc + g];
-                    }
-            }
     #pragma unroll
             for (int w = 0; w < 2; ++w)
     #pragma unroll
@@ -443,8 +450,8 @@ __device__ __forceinline__ void nn_unit(int64_t unit, int lane, int64_t M, int N
                     r.x = re[u][w][v];
                     r.y = im[u][w][v];
                     if (accumulate) {
-                        r.x += old[w][v].x;
-                        r.y += old[w][v].y;
+                        r.x += old[u][w][v].x;
+                        r.y += old[u][w][v].y;
                     }
                     if (n < N && g < M) C[(int64_t)n * ldc + g] = r;
                 }
