@@ -52,6 +52,9 @@ PEAK_BF16_MFMA = 2.5e15      # MI355X dense BF16 matrix cores, flop/s
 # each event pair orders the stream (about 5.6 us of idle per pair), so only
 # every fourth launch is bracketed
 PLANE_SAMPLE = 4
+# the plane-stage schedules at 96 points (paro_plan_set_schedule)
+PLANE_SCHEDULES = {0: "two bands' columns in LDS", 1: "four lanes per line",
+                   2: "compressed columns, two work-groups per CU"}
 
 
 def fft_flops(n):
@@ -563,8 +566,11 @@ def main():
         esize = 8 if precision == P.PREC_MIXED else 16
         bytes_launch = (2 * float(esize) * pl.n_sticks * pl.grid[2] * (nb / launches_per_apply(precision))
                         + esize / 2 * N ** 3)
-        name = "k_plane<96, float2>" if precision == P.PREC_MIXED else "k_plane<96, double2>"
-        return {"kernel": name + " (z-plane stage: n2/n1 FFTs, V multiply)", "bound": "alu",
+        sch = pl.get_schedule(precision)
+        name = (f"k_plane<96, {'float2' if precision == P.PREC_MIXED else 'double2'}, {sch['schedule']}>"
+                f" (z-plane stage: n2/n1 FFTs, V multiply; {PLANE_SCHEDULES[sch['schedule']]},"
+                f" {sch['bands']} bands per work-group)")
+        return {"kernel": name, "bound": "alu",
                 "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic() if precision == P.PREC_FP64 else None,
                 "algorithmic_bytes_per_launch": bytes_launch,

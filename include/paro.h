@@ -195,12 +195,16 @@ int32_t paro_get_projectors(paro_plan plan, double *beta_dev);
  * the FP32 choice):
  *   schedule  the line schedule of the transforms, 0 <= schedule <
  *             n_schedules: threads per line and radix order.  Grids of 24
- *             to 80 points have 3; the others 1.  Another schedule changes
- *             the rounding of the transforms (their radix order), not what
- *             they compute.
- *   bands     bands one work-group takes through its z-plane (1 .. 64;
- *             default 4).  Results are bitwise the same for every value.
- * A new plan starts at schedule 0 and 4 bands.  set_schedule re-lays the
+ *             to 80 points have 3 (radix orders); 96 points has 3 (0: the
+ *             cross-lane lines with two bands' columns in LDS, 1: the same
+ *             lines on four lanes each, 2: the same lines with one band's
+ *             populated columns in LDS, two work-groups per compute unit);
+ *             the others 1.  Another radix order changes the rounding of
+ *             the transforms, not what they compute.
+ *   bands     bands one work-group takes through its z-plane (1 .. 64).
+ *             Results are bitwise the same for every value.
+ * A new plan starts at schedule 0 and 4 bands, except FP64 on 96 points:
+ * schedule 2 and 2 bands (the fastest measured there).  set_schedule re-lays the
  * plan's potential tables for the new schedule on the plan's stream and
  * waits for it: call it while no work that uses the plan is in flight.
  * Errors: PARO_EINVAL (NULL plan, unknown precision, values out of range). */
@@ -214,7 +218,7 @@ typedef struct {
     int32_t schedule[2];   /* chosen schedule: [0] FP64, [1] FP32 */
     int32_t bands[2];      /* chosen bands per work-group */
     double ms[2];          /* plane-stage time on nb bands with the choice, ms */
-    double ms_default[2];  /* the same with schedule 0 and 4 bands */
+    double ms_default[2];  /* the same with a new plan's choice */
     int32_t candidates;    /* configurations timed per precision */
     int32_t cached;        /* 1: both choices came from an earlier tuning of this shape */
 } paro_tune_result;

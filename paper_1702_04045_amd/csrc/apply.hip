@@ -46,10 +46,25 @@ template <int T> __device__ __forceinline__ int line_of(int tid)
 }
 template <int T> __device__ __forceinline__ int thread_in_line(int tid) { return (tid & 63) / (64 / T); }
 
-// threads of the plane kernel: one line slot per row, rounded up to whole wavefronts
+// Shape of the compressed-column plane stage (plane_cc_body): threads per
+// work-group, the most populated columns its LDS plane holds, row passes.
+template <int N, class C2> struct CcCfg {
+    static constexpr int threads = 640, maxcols = 79, passes = sizeof(C2) == 16 ? 2 : 1;  // 160 points
+};
+template <class C2> struct CcCfg<96, C2> {
+    static constexpr int threads = 512, maxcols = 47, passes = 1;
+};
+constexpr int kCcMaxCols = CcCfg<160, double2>::maxcols;  // 2 nmax + 1 with 160 >= 4 nmax + 1
+constexpr int kCcBands = 4;                               // bands per work-group above 96 points
+// plane schedule 2 at 96 points: the compressed-column stage
+template <int N, class C2, int V> constexpr bool plane_cc() { return N == 96 && V == 2; }
+
+// threads of the plane kernel: one line slot per row, rounded up to whole
+// wavefronts (the compressed-column schedule: its own work-group size)
 template <int N, class C2, int V = 0> constexpr int plane_threads()
 {
-    return (N * PlaneSched<N, C2, V>::T + 63) / 64 * 64;
+    if constexpr (plane_cc<N, C2, V>()) return CcCfg<N, C2>::threads;
+    else return (N * PlaneSched<N, C2, V>::T + 63) / 64 * 64;
 }
 // Line transforms done across lanes (xlane96_inverse / xlane96_forward)
 // instead of through LDS: the 96-point lines, both precisions.
@@ -199,6 +214,150 @@ __global__ void __launch_bounds__((stick_threads<N3, C2>())) k_stick_inv_grp(Gro
     group_block(t, e, bx, by);
     const StickInvArgs<C2> &a = *static_cast<const StickInvArgs<C2> *>(t.args[e]);
     stick_inv_body<N3, C2>(bx, by, a.src, a.ld, a.pbuf, a.beta, first, a.sticks, a.nst, a.st_start, a.pt_sz, a.tw);
+}
+
+
+// ---------------------------------------------------------------- compressed-column plane stage
+// One z-plane of up to bpg bands per work-group, with the plane held in LDS
+// in compressed-column form: plane[c][y] for the populated columns
+// c = n1 + nmax1 only (ncol <= CcCfg::maxcols), y = n2 mod N.  Per band:
+// the inverse column transforms (sticks -> plane), the row transforms
+// (inverse, x V, forward; populated entries read and written back), the
+// forward column transforms (plane -> sticks).  All lines are cross-lane
+// transforms (8 lanes, no exchange space), so LDS holds only the plane.
+// Above 96 points (k_plane_cc): FP32 holds the whole plane, 79 x 161 x 8 B
+// = 102 KB at most.  FP64 would need twice that, so the rows go in two
+// passes of N/2 (y < N/2, then y >= N/2): each pass stores half of every
+// inverse column's outputs, and the forward columns, linear in their
+// input, add the second pass's transform of the other half to the stick
+// values the first pass wrote.  The outputs go to a second stick buffer
+// (sout): the second pass reads its inputs again from sin.  At 96 points
+// (plane schedule 2): one pass, 47 x 97 x 16 B = 73 KB in FP64, so two
+// 512-thread work-groups share a compute unit, and the outputs go back in
+// place (sout = sin: every stick entry is read and written by the same
+// line slot, the writes after a barrier that follows the reads).
+// Wavefronts whose line slots hold no populated column skip the column
+// transforms; the swaps inside a transform pair lanes of one line, and
+// every skip is uniform over a wavefront.
+
+template <int N, class C2>
+__device__ __forceinline__ void plane_cc_body(int z, int by, int bpg, const C2 *sin, C2 *sout, int nst, int N3, int nb,
+                                              const int32_t *__restrict__ cols, int ncol, int nmax1,
+                                              const RealOf<C2> *__restrict__ vperm, const C2 *__restrict__ tw)
+{
+    static_assert(xlane_rows<N, C2>(), "cross-lane lines");
+    using CC = CcCfg<N, C2>;
+    constexpr int T = 8, E = N / 8, NP = CC::passes, NR = N / NP, LDY = NR + 1;
+    constexpr int SLOTS = CC::threads / T, WS = 64 / T;  // line slots per work-group and per wavefront
+    // one line slot per column; the last row round ends on a wavefront boundary
+    static_assert(SLOTS >= CC::maxcols && (NR % SLOTS) % WS == 0, "cc plane shape");
+    __shared__ C2 plane[CC::maxcols * LDY];
+    __shared__ C2 twl[N];
+    const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
+    for (int i = tid; i < N; i += CC::threads) twl[i] = tw[i];
+    __syncthreads();
+    const int b0 = by * bpg, b1 = min(b0 + bpg, nb);
+    const int c = sl;
+    const bool colact = c < ncol;
+    const bool wave_cols = (tid >> 6) * WS < ncol;  // this wavefront holds a populated column
+    int cst = 0, ylo = 0, cnt = 0;
+    if (colact) {
+        cst = cols[3 * c];
+        ylo = cols[3 * c + 1];
+        cnt = cols[3 * c + 2];
+    }
+    for (int k = b0; k < b1; ++k) {
+#pragma unroll 1
+        for (int p = 0; p < NP; ++p) {
+            C2 v[E];
+            if (wave_cols) {
+                // inverse along n2 of column c; keep the outputs of this pass's rows.
+                // (The index values of each stage are made opaque, so that the
+                // compiler recomputes them per stage instead of holding every
+                // stage's offsets in registers across the band loop.)
+                int tt = t, lo = ylo, n = cnt;
+                asm volatile("" : "+v"(tt), "+v"(lo), "+v"(n));
+                const C2 *tz = sin + ((size_t)k * N3 + z) * nst + cst;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int i = tt + T * m;
+                    const int q = (i > N / 2 ? i - N : i) - lo;
+                    v[m] = (xl_kept<N>(m) && colact && (unsigned)q < (unsigned)n) ? tz[q] : cmk<C2>(0.0, 0.0);
+                }
+                xl_inverse<N>(v, opaque(t), twl);
+                if (colact) {
+                    C2 *pc = plane + c * LDY;
+                    const int ts = opaque(t);
+#pragma unroll
+                    for (int s = 0; s < E; ++s) {
+                        const int y = xl_index<N>(ts, s);
+                        if (NP == 1 || y / NR == p) pc[y - p * NR] = v[s];
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int r = sl; r < NR; r += SLOTS) {
+                // row y = p NR + r along n1: inverse, x V, forward (populated columns only)
+                const int y = p * NR + r;
+                int tt = t, nm = nmax1;
+                asm volatile("" : "+v"(tt), "+v"(nm));
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int i = tt + T * m;
+                    const bool pop = xl_kept<N>(m) && (i <= nm || i >= N - nm);
+                    v[m] = pop ? plane[(i <= nm ? i + nm : i - N + nm) * LDY + r] : cmk<C2>(0.0, 0.0);
+                }
+                xl_inverse<N>(v, opaque(t), twl);
+                const RealOf<C2> *vp = vperm + (((size_t)z * N + y) * T + opaque(t)) * E;
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vp[e]);
+                xl_forward<N>(v, opaque(t), twl);
+                int tw2 = t, nm2 = nmax1;
+                asm volatile("" : "+v"(tw2), "+v"(nm2));
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int i = tw2 + T * m;
+                    if (xl_kept<N>(m) && (i <= nm2 || i >= N - nm2))
+                        plane[(i <= nm2 ? i + nm2 : i - N + nm2) * LDY + r] = v[m];
+                }
+            }
+            __syncthreads();
+            if (wave_cols) {
+                // forward along n2 of column c from this pass's rows; back to the sticks
+                const int ts = opaque(t);
+                const C2 *pc = plane + (colact ? c : 0) * LDY;
+#pragma unroll
+                for (int s = 0; s < E; ++s) {
+                    const int y = xl_index<N>(ts, s);
+                    v[s] = (colact && (NP == 1 || y / NR == p)) ? pc[y - p * NR] : cmk<C2>(0.0, 0.0);
+                }
+                xl_forward<N>(v, opaque(t), twl);
+                if (colact) {
+                    int tt = t, lo = ylo, n = cnt;
+                    asm volatile("" : "+v"(tt), "+v"(lo), "+v"(n));
+                    C2 *tz = sout + ((size_t)k * N3 + z) * nst + cst;
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {
+                        const int i = tt + T * m;
+                        const int q = (i > N / 2 ? i - N : i) - lo;
+                        if (xl_kept<N>(m) && (unsigned)q < (unsigned)n) {
+                            if (p == 0) tz[q] = v[m];
+                            else tz[q] = cadd(tz[q], v[m]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+template <int N, class C2>
+__global__ void __launch_bounds__((CcCfg<N, C2>::threads))
+k_plane_cc(const C2 *__restrict__ sin, C2 *__restrict__ sout, int nst, int N3, int nb, const int32_t *__restrict__ cols,
+           int ncol, int nmax1, const RealOf<C2> *__restrict__ vperm, const C2 *__restrict__ tw)
+{
+    plane_cc_body<N, C2>(blockIdx.x, blockIdx.y, kCcBands, sin, sout, nst, N3, nb, cols, ncol, nmax1, vperm, tw);
 }
 
 
@@ -456,7 +615,10 @@ __attribute__((amdgpu_waves_per_eu(PlaneSched<N, C2, V>::min_waves)))
 k_plane(C2 *__restrict__ sticks, int nst, int N3, int nb, const int32_t *__restrict__ cols,
         const RealOf<C2> *__restrict__ vperm, int nmax1, const C2 *__restrict__ tw, int bpb)
 {
-    plane_body<N, C2, V>(blockIdx.x, blockIdx.y, sticks, nst, N3, nb, cols, vperm, nmax1, tw, bpb);
+    if constexpr (plane_cc<N, C2, V>())
+        plane_cc_body<N, C2>(blockIdx.x, blockIdx.y, bpb, sticks, sticks, nst, N3, nb, cols, 2 * nmax1 + 1, nmax1,
+                             vperm, tw);
+    else plane_body<N, C2, V>(blockIdx.x, blockIdx.y, sticks, nst, N3, nb, cols, vperm, nmax1, tw, bpb);
 }
 template <int N, class C2, int V>
 __global__ void __launch_bounds__((plane_threads<N, C2, V>()))
@@ -466,7 +628,10 @@ k_plane_grp(GroupTab t)
     int e, bx, by;
     group_block(t, e, bx, by);
     const PlaneArgs<C2> &a = *static_cast<const PlaneArgs<C2> *>(t.args[e]);
-    plane_body<N, C2, V>(bx, by, a.sticks, a.nst, a.N3, a.nb, a.cols, a.vperm, a.nmax1, a.tw, a.bpb);
+    if constexpr (plane_cc<N, C2, V>())
+        plane_cc_body<N, C2>(bx, by, a.bpb, a.sticks, a.sticks, a.nst, a.N3, a.nb, a.cols, 2 * a.nmax1 + 1, a.nmax1,
+                             a.vperm, a.tw);
+    else plane_body<N, C2, V>(bx, by, a.sticks, a.nst, a.N3, a.nb, a.cols, a.vperm, a.nmax1, a.tw, a.bpb);
 }
 
 
@@ -816,136 +981,6 @@ __global__ void __launch_bounds__((stick_threads<N3, C2>())) k_stick_fwd_grp(Gro
 }
 
 
-// ---------------------------------------------------------------- fused plane stage above 96 points
-// One z-plane of up to kCcBands bands per work-group, with the plane held
-// in LDS in compressed-column form: plane[c][y] for the populated columns
-// c = n1 + nmax1 only (ncol <= kCcMaxCols), y = n2 mod N.  Per band: the
-// inverse column transforms (sticks -> plane), the row transforms (inverse,
-// x V, forward; populated entries read and written back), the forward
-// column transforms (plane -> sticks).  All lines are cross-lane transforms
-// (8 lanes, no exchange space), so LDS holds only the plane.  FP32: the
-// whole plane, 79 x 161 x 8 B = 102 KB at most.  FP64 would need twice that,
-// so the rows go in two passes of N/2 (y < N/2, then y >= N/2): each pass
-// stores half of every inverse column's outputs, and the forward columns,
-// linear in their input, add the second pass's transform of the other half
-// to the stick values the first pass wrote.  The outputs go to a second
-// stick buffer (sout): the second pass reads its inputs again from sin.
-constexpr int kCcMaxCols = 79;   // 2 nmax + 1 with 160 >= 4 nmax + 1
-constexpr int kCcThreads = 640;  // 80 line slots of 8 lanes
-constexpr int kCcBands = 4;      // bands per work-group
-template <class C2> constexpr int cc_passes() { return sizeof(C2) == 16 ? 2 : 1; }
-
-template <int N, class C2>
-__global__ void __launch_bounds__(kCcThreads)
-k_plane_cc(const C2 *__restrict__ sin, C2 *__restrict__ sout, int nst, int N3, int nb, const int32_t *__restrict__ cols,
-           int ncol, int nmax1, const RealOf<C2> *__restrict__ vperm, const C2 *__restrict__ tw)
-{
-    static_assert(xlane_rows<N, C2>(), "cross-lane lines");
-    constexpr int T = 8, E = N / 8, NP = cc_passes<C2>(), NR = N / NP, LDY = NR + 1;
-    constexpr int SLOTS = kCcThreads / T;
-    static_assert(NR % SLOTS == 0 && SLOTS >= kCcMaxCols, "whole row rounds; one line slot per column");
-    __shared__ C2 plane[kCcMaxCols * LDY];
-    __shared__ C2 twl[N];
-    const int tid = threadIdx.x, sl = line_of<T>(tid), t = thread_in_line<T>(tid);
-    for (int i = tid; i < N; i += kCcThreads) twl[i] = tw[i];
-    __syncthreads();
-    const int z = blockIdx.x;
-    const int b0 = blockIdx.y * kCcBands, b1 = min(b0 + kCcBands, nb);
-    const int c = sl;
-    const bool colact = c < ncol;
-    int cst = 0, ylo = 0, cnt = 0;
-    if (colact) {
-        cst = cols[3 * c];
-        ylo = cols[3 * c + 1];
-        cnt = cols[3 * c + 2];
-    }
-    for (int k = b0; k < b1; ++k) {
-#pragma unroll 1
-        for (int p = 0; p < NP; ++p) {
-            C2 v[E];
-            {
-                // inverse along n2 of column c; keep the outputs of this pass's rows.
-                // (The index values of each stage are made opaque, so that the
-                // compiler recomputes them per stage instead of holding every
-                // stage's offsets in registers across the band loop.)
-                int tt = t, lo = ylo, n = cnt;
-                asm volatile("" : "+v"(tt), "+v"(lo), "+v"(n));
-                const C2 *tz = sin + ((size_t)k * N3 + z) * nst + cst;
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const int i = tt + T * m;
-                    const int q = (i > N / 2 ? i - N : i) - lo;
-                    v[m] = (xl_kept<N>(m) && colact && (unsigned)q < (unsigned)n) ? tz[q] : cmk<C2>(0.0, 0.0);
-                }
-                xl_inverse<N>(v, opaque(t), twl);
-                if (colact) {
-                    C2 *pc = plane + c * LDY;
-                    const int ts = opaque(t);
-#pragma unroll
-                    for (int s = 0; s < E; ++s) {
-                        const int y = xl_index<N>(ts, s);
-                        if (NP == 1 || y / NR == p) pc[y - p * NR] = v[s];
-                    }
-                }
-            }
-            __syncthreads();
-#pragma unroll 1
-            for (int r = sl; r < NR; r += SLOTS) {
-                // row y = p NR + r along n1: inverse, x V, forward (populated columns only)
-                const int y = p * NR + r;
-                int tt = t, nm = nmax1;
-                asm volatile("" : "+v"(tt), "+v"(nm));
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const int i = tt + T * m;
-                    const bool pop = xl_kept<N>(m) && (i <= nm || i >= N - nm);
-                    v[m] = pop ? plane[(i <= nm ? i + nm : i - N + nm) * LDY + r] : cmk<C2>(0.0, 0.0);
-                }
-                xl_inverse<N>(v, opaque(t), twl);
-                const RealOf<C2> *vp = vperm + (((size_t)z * N + y) * T + opaque(t)) * E;
-#pragma unroll
-                for (int e = 0; e < E; ++e) v[e] = cscale(v[e], vp[e]);
-                xl_forward<N>(v, opaque(t), twl);
-                int tw2 = t, nm2 = nmax1;
-                asm volatile("" : "+v"(tw2), "+v"(nm2));
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const int i = tw2 + T * m;
-                    if (xl_kept<N>(m) && (i <= nm2 || i >= N - nm2))
-                        plane[(i <= nm2 ? i + nm2 : i - N + nm2) * LDY + r] = v[m];
-                }
-            }
-            __syncthreads();
-            {
-                // forward along n2 of column c from this pass's rows; back to the sticks
-                const int ts = opaque(t);
-                const C2 *pc = plane + (colact ? c : 0) * LDY;
-#pragma unroll
-                for (int s = 0; s < E; ++s) {
-                    const int y = xl_index<N>(ts, s);
-                    v[s] = (colact && (NP == 1 || y / NR == p)) ? pc[y - p * NR] : cmk<C2>(0.0, 0.0);
-                }
-                xl_forward<N>(v, opaque(t), twl);
-                if (colact) {
-                    int tt = t, lo = ylo, n = cnt;
-                    asm volatile("" : "+v"(tt), "+v"(lo), "+v"(n));
-                    C2 *tz = sout + ((size_t)k * N3 + z) * nst + cst;
-#pragma unroll
-                    for (int m = 0; m < E; ++m) {
-                        const int i = tt + T * m;
-                        const int q = (i > N / 2 ? i - N : i) - lo;
-                        if (xl_kept<N>(m) && (unsigned)q < (unsigned)n) {
-                            if (p == 0) tz[q] = v[m];
-                            else tz[q] = cadd(tz[q], v[m]);
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
 // Precision-specific plan tables.
 template <class C2> struct PlanTabs;
 template <> struct PlanTabs<double2> {
@@ -1039,7 +1074,7 @@ hipError_t run_local_big(const Plan &pl, const Workspace &w, int nb, const C2 *s
                            pl.st_start, pl.pt_sz, PlanTabs<C2>::tw(pl, 2));
         prof_mark(PARO_K_STICK_INV, pl.stream, false);
         prof_mark(PARO_K_PLANE, pl.stream, true);
-        hipLaunchKernelGGL((k_plane_cc<N, C2>), dim3(N3, (cb + kCcBands - 1) / kCcBands), dim3(kCcThreads), 0,
+        hipLaunchKernelGGL((k_plane_cc<N, C2>), dim3(N3, (cb + kCcBands - 1) / kCcBands), dim3(CcCfg<N, C2>::threads), 0,
                            pl.stream, sticks, sticks2, pl.nst, N3, cb, pl.cols, pl.ncol, pl.nmax[0],
                            PlanTabs<C2>::v(pl), PlanTabs<C2>::tw(pl, 0));
         prof_mark(PARO_K_PLANE, pl.stream, false);

@@ -877,8 +877,14 @@ template <class C2> struct PlaneSched<96, C2, 1> {
     using Inv = RList<4, 6, 4>;
     using Fwd = RList<4, 6, 4>;
 };
+// 96 points, the compressed-column plane stage (plane_cc_body in apply.hip):
+// the cross-lane lines of variant 0 and its potential order, the populated
+// columns of one band at a time in LDS, two work-groups per compute unit
+template <class C2> struct PlaneSched<96, C2, 2> : PlaneCfg<96> {
+    static constexpr int min_waves = 4;  // two 8-wave work-groups per compute unit
+};
 // number of selectable schedules at N points
-__host__ __device__ constexpr int plane_nsched(int n) { return n >= 24 && n <= 80 ? 3 : n == 96 ? 2 : 1; }
+__host__ __device__ constexpr int plane_nsched(int n) { return n >= 24 && n <= 80 ? 3 : n == 96 ? 3 : 1; }
 constexpr int kPlaneSchedMax = 3;
 
 }  // namespace paro

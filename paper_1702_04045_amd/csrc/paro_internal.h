@@ -20,6 +20,18 @@ constexpr int kPartSplits = 64;        // split-K partials the workspaces hold p
 constexpr int kMaxParts = 512;         // partial sums per band per reduction
 constexpr int kDensityBandsPerGroup = 8;  // bands one work-group of the density kernel sums
 constexpr int kPlaneBandsDefault = 4;     // bands per work-group of the plane kernel unless tuned
+// Plane-stage launch choice a new plan takes for grid n and precision slot
+// pi (0: FP64, 1: FP32): schedule 0 with kPlaneBandsDefault bands per
+// work-group, except FP64 at 96 points: the compressed-column schedule 2
+// with 2 bands per work-group, the fastest choice measured at that grid.
+// A plan builds its potential in schedule 0's order, which schedule 2
+// shares, so the default needs no re-layout.
+inline void plane_default(int n, int pi, int32_t *sched, int32_t *bands)
+{
+    const bool cc = n == 96 && pi == 0;
+    *sched = cc ? 2 : 0;
+    *bands = cc ? 2 : kPlaneBandsDefault;
+}
 constexpr int kPlaneBandsMax = 64;
 
 // per-band scalar slots (Workspace::sc, each nb long)

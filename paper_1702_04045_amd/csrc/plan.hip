@@ -412,6 +412,7 @@ int32_t paro_plan_create(const paro_problem *prob, void *dev_buf, size_t bytes, 
     pl.ecut = prob->ecut;
     std::memcpy(pl.grid, prob->grid, sizeof(pl.grid));
     std::memcpy(pl.nmax, g.nmax, sizeof(pl.nmax));
+    for (int pi = 0; pi < 2; ++pi) plane_default(pl.grid[0], pi, &pl.plane_sched[pi], &pl.plane_bands[pi]);
     pl.ng = g.ng;
     pl.ldv = g.ldv;
     pl.nst = g.nst;

@@ -135,10 +135,12 @@ int32_t tune_slot(Plan &pl, const Workspace &w, int nb, int pi, Events &ev, Choi
     const int n = pl.grid[0];
     const int cbmax = std::min(nb, pi == 1 ? kMaxBandsPerChunk32 : kMaxBandsPerChunk);
     const int sched0 = pl.plane_sched[pi], bands0 = pl.plane_bands[pi];
-    Choice best{0, kPlaneBandsDefault, 1e300, 0.0, 0};
+    int32_t dsched = 0, dbands = kPlaneBandsDefault;  // a new plan's choice
+    plane_default(n, pi, &dsched, &dbands);
+    Choice best{dsched, dbands, 1e300, 0.0, 0};
     // one untimed stage, then the repetitions that make about a millisecond
-    pl.plane_sched[pi] = 0;
-    pl.plane_bands[pi] = kPlaneBandsDefault;
+    pl.plane_sched[pi] = dsched;
+    pl.plane_bands[pi] = dbands;
     PARO_HIP_TRY(launch_plane_only(pl, w, nb, pi == 1));
     double t1 = 0.0;
     int32_t rc = time_plane(pl, w, nb, pi == 1, ev.e0, ev.e1, 1, &t1);
@@ -156,7 +158,7 @@ int32_t tune_slot(Plan &pl, const Workspace &w, int nb, int pi, Events &ev, Choi
             rc = time_plane(pl, w, nb, pi == 1, ev.e0, ev.e1, reps, &ms);
             if (rc) return rc;
             ++best.candidates;
-            if (v == 0 && b == kPlaneBandsDefault) best.ms_default = ms;
+            if (v == dsched && b == dbands) best.ms_default = ms;
             if (ms < best.ms) {
                 best.sched = v;
                 best.bands = b;
@@ -166,8 +168,8 @@ int32_t tune_slot(Plan &pl, const Workspace &w, int nb, int pi, Events &ev, Choi
     }
     // keep the default unless a candidate is more than 1 % faster
     if (best.ms_default > 0.0 && best.ms_default <= 1.01 * best.ms) {
-        best.sched = 0;
-        best.bands = kPlaneBandsDefault;
+        best.sched = dsched;
+        best.bands = dbands;
         best.ms = best.ms_default;
     }
     pl.plane_sched[pi] = sched0;

@@ -1,7 +1,7 @@
 """The plane stage's selectable launch choices and the autotuner.
 
-Every line schedule of every Stockham grid (24 to 80 points) and both of
-the 96-point grid, with several bands per work-group, against the oracle in
+Every line schedule of every Stockham grid (24 to 80 points) and the three
+of the 96-point grid, with several bands per work-group, against the oracle in
 FP64 (1e-12) and FP32 (2e-6);
 bands per work-group leave results bitwise unchanged; a schedule switch
 re-lays the potential exactly (switching back restores bitwise results);
@@ -64,20 +64,25 @@ def test_every_schedule_matches_oracle(n):
     assert pl.status() == 0
 
 
+@pytest.mark.parametrize("sched", [1, 2], ids=["paired", "cc"])
 @pytest.mark.parametrize("nmax_edge", [False, True], ids=["c1like", "nmax23"])
-def test_paired_96_point_schedule(nmax_edge):
-    """Schedule 1 at 96 points (four lanes per line, two threads of the
-    cross-lane schedule in each) against the oracle and against schedule 0,
-    on a cell with the largest Miller index the pruned lines allow (23) and on
-    a smaller one; bands per work-group change nothing; back to schedule 0
-    the potential is unchanged."""
+def test_96_point_schedules(nmax_edge, sched):
+    """Schedules 1 (four lanes per line, two threads of the cross-lane
+    schedule in each) and 2 (the compressed-column plane, one band's
+    populated columns in LDS) at 96 points against the oracle and against
+    schedule 0, on a cell with the largest Miller index the pruned lines
+    allow (23) and on a smaller one; bands per work-group change nothing;
+    back to schedule 0 the potential is unchanged."""
     import paper_1702_04045_amd as P
     spec = (synth.small_cell(a=20.0, ecut=27.0, grid=96, n_atoms=3) if nmax_edge
             else synth.small_cell(a=20.0, ecut=20.0, grid=96, n_atoms=3))
     c, v, h, pl = make_case(spec, 9)
     if nmax_edge:
         assert int(h.nmax.max()) == 23
-    assert pl.get_schedule(P.PREC_FP64) == dict(schedule=0, bands=4, n_schedules=2)
+    # a new 96-point plan: FP64 on schedule 2 with 2 bands per work-group
+    assert pl.get_schedule(P.PREC_FP64) == dict(schedule=2, bands=2, n_schedules=3)
+    assert pl.get_schedule(P.PREC_MIXED) == dict(schedule=0, bands=4, n_schedules=3)
+    pl.set_schedule(P.PREC_FP64, 0, 4)
     x = synth.trial_block(h.ng, 37, 9)
     x32 = x.astype(np.complex64)
     ref = h.apply(x)
@@ -86,8 +91,8 @@ def test_paired_96_point_schedule(nmax_edge):
     base32 = to_np(pl.apply_h_f32(to_dev(x32)))
     got = {}
     for b in (4, 1, 16):
-        pl.set_schedule(P.PREC_FP64, 1, b)
-        pl.set_schedule(P.PREC_MIXED, 1, b)
+        pl.set_schedule(P.PREC_FP64, sched, b)
+        pl.set_schedule(P.PREC_MIXED, sched, b)
         g = to_np(pl.apply_h(to_dev(x)))
         g32 = to_np(pl.apply_h_f32(to_dev(x32)))
         assert rel_err(g, ref) < 1e-12, b
@@ -110,11 +115,11 @@ def test_schedule_errors():
     _, _, _, p32 = make_case(edge_spec(32), 0)
     _, _, _, p96 = make_case(synth.small_cell(a=6.0, ecut=4.0, grid=96, n_atoms=2), 0)
     for pl, s, b, prec in ((p32, 3, 4, 0), (p32, -1, 4, 0), (p32, 0, 0, 0), (p32, 0, 65, 1), (p32, 0, 4, 7),
-                           (p96, 2, 4, 0)):
+                           (p96, 3, 4, 0)):
         with pytest.raises(P.ParoError) as e:
             pl.set_schedule(prec, s, b)
         assert e.value.code == -1
-    assert p96.get_schedule(P.PREC_MIXED) == dict(schedule=0, bands=4, n_schedules=2)
+    assert p96.get_schedule(P.PREC_MIXED) == dict(schedule=0, bands=4, n_schedules=3)
     # nothing changed by the refused calls
     assert p32.get_schedule(P.PREC_FP64) == dict(schedule=0, bands=4, n_schedules=3)
 
@@ -124,14 +129,15 @@ def test_autotune_picks_a_timed_candidate(n, nb):
     import paper_1702_04045_amd as P
     spec = edge_spec(n) if n in EDGE else synth.small_cell(a=20.0, ecut=20.0, grid=96, n_atoms=3)
     c, v, h, pl = make_case(spec, 5)
+    default = [pl.get_schedule(p) for p in (P.PREC_FP64, P.PREC_MIXED)]
     r = pl.autotune(nb, force=True)
-    nsched = 3 if n in EDGE else 2
+    nsched = 3
     assert not r["cached"]
     assert r["candidates"] == nsched * 4
     for k in range(2):
         assert 0 <= r["schedule"][k] < nsched and r["bands"][k] in (2, 4, 8, 16)
         assert 0 < r["ms"][k] <= r["ms_default"][k]
-        if (r["schedule"][k], r["bands"][k]) != (0, 4):
+        if (r["schedule"][k], r["bands"][k]) != (default[k]["schedule"], default[k]["bands"]):
             assert r["ms"][k] * 1.01 < r["ms_default"][k]
     assert pl.get_schedule(P.PREC_FP64)["schedule"] == r["schedule"][0]
     assert pl.get_schedule(P.PREC_MIXED)["bands"] == r["bands"][1]
@@ -150,7 +156,7 @@ def test_autotune_picks_a_timed_candidate(n, nb):
 def test_batch_with_mixed_schedules_is_bitwise_the_lone_runs(precision):
     """Three cells on the 32-point grid with schedules 0, 1, 2 (and different
     bands per work-group), a 48-point cell with schedule 2 and two 96-point
-    cells with schedules 1 and 0, in one grouped batch, against each cell's
+    cells with schedules 1 and 2, in one grouped batch, against each cell's
     lone run."""
     import torch
 
@@ -162,7 +168,7 @@ def test_batch_with_mixed_schedules_is_bitwise_the_lone_runs(precision):
              synth.small_cell(a=12.0, ecut=12.0, grid=96, n_atoms=2, n_bands=9),
              synth.small_cell(a=11.0, ecut=12.0, grid=96, n_atoms=2, n_bands=13)]
     cells = []
-    for i, (sp, (s, b)) in enumerate(zip(specs, [(0, 4), (1, 2), (2, 16), (2, 8), (1, 4), (0, 2)])):
+    for i, (sp, (s, b)) in enumerate(zip(specs, [(0, 4), (1, 2), (2, 16), (2, 8), (1, 4), (2, 2)])):
         c = synth.make_cell(sp, 70 + i)
         v = synth.vloc_on_grid(c["cell"], c["grid"], c["positions"], c["depths"], c["widths"])
         pl = P.Plan(c["cell"], c["ecut"], v, c["projectors"])
