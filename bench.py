@@ -40,6 +40,7 @@ METRIC = "ParO iters/s & Hψ applies/s, plain FP64 vs batched mixed, at 1e-8 Ha 
 # counts only while the kernel sources hash to the value recorded there.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_plane_96_c1_hbm_traffic.txt")
 DENSITY_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_plane_density_96_c1_hbm_traffic.txt")
+F32_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_plane_96_f32_c1_hbm_traffic.txt")
 # the sources of the 96-point plane and density kernels (the traffic summaries
 # hold their SHA-256; a summary taken on other sources reads as null)
 PLANE_SOURCES = ["paper_1702_04045_amd/csrc/apply.hip", "paper_1702_04045_amd/csrc/fft_device.h"]
@@ -171,9 +172,9 @@ def copy_calibration():
 
 
 def traffic_pass(seed):
-    """Only the FP64 H applies and density calls of the 160-band block on the
-    34,265-plane-wave cell (no Rayleigh-Ritz): the run the plane kernels' HBM
-    counters are read from."""
+    """Only the FP64 and FP32 H applies and the density calls of the 160-band
+    block on the 34,265-plane-wave cell (no Rayleigh-Ritz): the run the plane
+    kernels' HBM counters are read from."""
     import torch
     import paper_1702_04045_amd as P
     dev = torch.device("cuda:0")
@@ -183,12 +184,15 @@ def traffic_pass(seed):
     pl = P.Plan(cell["cell"], cell["ecut"], v, cell["projectors"], device=dev)
     x = torch.from_numpy(synth.trial_block(pl.ng, spec.n_carried, seed)).to(dev)
     w = torch.ones(spec.n_carried, dtype=torch.float64, device=dev)
+    x32 = x.to(torch.complex64)
     for _ in range(3):
         pl.apply_h(x)
     for _ in range(3):
+        pl.apply_h_f32(x32)
+    for _ in range(3):
         pl.density(x, w)
     torch.cuda.synchronize()
-    print(json.dumps({"traffic_pass": {"bands": spec.n_carried, "applies": 3, "density_calls": 3}}))
+    print(json.dumps({"traffic_pass": {"bands": spec.n_carried, "applies": 3, "fp32_applies": 3, "density_calls": 3}}))
 
 
 def cpu_baseline(spec, cell, v, x_trial, sample_bands=64):
@@ -441,7 +445,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--traffic-pass", action="store_true",
-                    help="only run FP64 H applies and density calls on the benchmark cell (HBM counters) and exit")
+                    help="only run FP64 and FP32 H applies and density calls on the benchmark cell (HBM counters) "
+                         "and exit")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -572,7 +577,7 @@ def main():
                 f" {sch['bands']} bands per work-group)")
         return {"kernel": name, "bound": "alu",
                 "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": measured_traffic() if precision == P.PREC_FP64 else None,
+                "traffic": measured_traffic(TRAFFIC_FILE if precision == P.PREC_FP64 else F32_TRAFFIC_FILE),
                 "algorithmic_bytes_per_launch": bytes_launch,
                 "hbm_frac_algorithmic": bytes_launch / (avg_ms * 1e-3) / PEAK_HBM,
                 "launches_timed": int(nl), "launches_sampled_every": every, "avg_launch_ms": avg_ms,
